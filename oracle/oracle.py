@@ -1,0 +1,277 @@
+"""ctypes access to the reference oracle (TEST INFRASTRUCTURE ONLY).
+
+The oracle is a plain FP64 CPU implementation of one ADER-WENO-AO
+divergence-free MHD step written from the paper (Sections II-VI).  Only the
+test-suite, the smoke check and the CPU-baseline leg of the benchmark may use
+it; the GPU library never imports or links it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "init.c", "oracle.c"]
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-shared", "-fPIC",
+               *[os.path.join(_HERE, s) for s in _SOURCES], "-o", _LIB_PATH + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        L.rgo_create.restype = C.c_void_p
+        L.rgo_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
+        L.rgo_destroy.argtypes = [C.c_void_p]
+        L.rgo_sizes.argtypes = [C.c_void_p, _lp]
+        L.rgo_zone_data.argtypes = [C.c_void_p, _dp, _dp, _ip, _ip]
+        L.rgo_zone_faces.argtypes = [C.c_void_p, _ip, _ip]
+        L.rgo_face_data.argtypes = [C.c_void_p, _dp, _dp, _dp, _ip]
+        L.rgo_face_quad.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.rgo_edge_data.argtypes = [C.c_void_p, _dp, _dp, _ip]
+        L.rgo_face_edges.argtypes = [C.c_void_p, _ip, _ip]
+        L.rgo_cubature.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.rgo_ncub.restype = C.c_int
+        L.rgo_ncub.argtypes = [C.c_void_p]
+        L.rgo_node_data.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.rgo_sphericity.restype = C.c_double
+        L.rgo_sphericity.argtypes = [C.c_void_p, C.c_int]
+        L.rgo_step.restype = C.c_int
+        L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
+                               C.c_void_p, C.c_void_p]
+        L.rgo_recon.restype = C.c_int
+        L.rgo_recon.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.rgo_divfree.restype = C.c_int
+        L.rgo_divfree.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, _dp, _ip, _dp]
+        L.rgo_cfl_dt.restype = C.c_double
+        L.rgo_cfl_dt.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp]
+        L.rgo_init_harmonic.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
+        L.rgo_init_alfven.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.rgo_refel_query.restype = C.c_int
+        L.rgo_refel_query.argtypes = [C.c_int, _ip, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rgo_refel_eval.restype = C.c_int
+        L.rgo_refel_eval.argtypes = [C.c_int, C.c_int, _dp, _dp]
+        L.rgo_lagrange.restype = C.c_int
+        L.rgo_lagrange.argtypes = [C.c_int, _dp, _ip, _dp]
+        L.rgo_gauss01.argtypes = [C.c_int, _dp, _dp]
+        L.rgo_predict.restype = C.c_int
+        L.rgo_predict.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.rgo_hll.argtypes = [_dp, _dp, _dp, C.c_double, _dp]
+        L.rgo_flux.argtypes = [_dp, C.c_double, _dp]
+        L.rgo_emf.restype = C.c_double
+        L.rgo_emf.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
+        _lib = L
+    return _lib
+
+
+NVAR = 8
+FLAG_LINEAR_WEIGHTS = 1
+
+
+class OracleMesh:
+    """Cube-based geodesic shell mesh with per-zone geometry (oracle side)."""
+
+    def __init__(self, n_ang, n_rad, r_in=1.0, r_out=2.0, n_ghost=3, map_order=None, order=3):
+        if map_order is None:
+            map_order = order - 1
+        self.order = order
+        self.n_ang, self.n_rad, self.r_in, self.r_out = n_ang, n_rad, r_in, r_out
+        self._h = lib().rgo_create(n_ang, n_rad, r_in, r_out, n_ghost, map_order, order)
+        if not self._h:
+            raise ValueError("oracle mesh construction failed")
+        s = np.zeros(8, np.int64)
+        lib().rgo_sizes(self._h, s)
+        self.nz, self.nf, self.ne, self.ktot, self.n_ghost, self.nquad, self.nv, self.nnodes = map(int, s)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rgo_destroy(h)
+            self._h = None
+
+    # geometry ---------------------------------------------------------
+    def zones(self):
+        cen = np.zeros((self.nz, 3)); vol = np.zeros(self.nz)
+        shell = np.zeros(self.nz, np.int32); stn = np.zeros(self.nz, np.int32)
+        lib().rgo_zone_data(self._h, cen, vol, shell, stn)
+        return cen, vol, shell, stn
+
+    def zone_faces(self):
+        f = np.zeros((self.nz, 6), np.int32); n = np.zeros((self.nz, 6), np.int32)
+        lib().rgo_zone_faces(self._h, f, n)
+        return f, n
+
+    def faces(self):
+        cen = np.zeros((self.nf, 3)); nrm = np.zeros((self.nf, 3)); area = np.zeros(self.nf)
+        zones = np.zeros((self.nf, 2), np.int32)
+        lib().rgo_face_data(self._h, cen, nrm, area, zones)
+        return cen, nrm, area, zones
+
+    def face_quad(self):
+        Q = (self.order - 1) ** 2
+        x = np.zeros((self.nf, Q, 3)); n = np.zeros((self.nf, Q, 3)); dA = np.zeros((self.nf, Q))
+        lib().rgo_face_quad(self._h, x, n, dA)
+        return x, n, dA
+
+    def edges(self):
+        mid = np.zeros((self.ne, 3)); tan = np.zeros((self.ne, 3)); nzs = np.zeros(self.ne, np.int32)
+        lib().rgo_edge_data(self._h, mid, tan, nzs)
+        return mid, tan, nzs
+
+    def face_edges(self):
+        e = np.zeros((self.nf, 4), np.int32); s = np.zeros((self.nf, 4), np.int32)
+        lib().rgo_face_edges(self._h, e, s)
+        return e, s
+
+    def cubature(self, z):
+        n = lib().rgo_ncub(self._h)
+        x = np.zeros((n, 3)); w = np.zeros(n)
+        lib().rgo_cubature(self._h, int(z), x, w)
+        return x, w
+
+    def node_data(self, z):
+        N = self.nnodes
+        x = np.zeros((N, 3)); J = np.zeros(N); met = np.zeros((N, 3, 3))
+        lib().rgo_node_data(self._h, int(z), x, J, met)
+        return x, J, met
+
+    def sphericity(self, samples=16):
+        return lib().rgo_sphericity(self._h, samples)
+
+    # initial data -------------------------------------------------------
+    def init_harmonic(self, prob):
+        U = np.zeros((NVAR, self.nz)); Bf = np.zeros(self.nf)
+        lib().rgo_init_harmonic(self._h, np.ascontiguousarray(prob["rho"], np.float64),
+                                np.ascontiguousarray(prob["v"], np.float64),
+                                np.ascontiguousarray(prob["A"], np.float64),
+                                float(prob["p"]), float(prob["gamma"]), U, Bf)
+        return U, Bf
+
+    def init_alfven(self, prob, t=0.0):
+        U = np.zeros((NVAR, self.nz)); Bf = np.zeros(self.nf)
+        lib().rgo_init_alfven(self._h, np.ascontiguousarray(prob["frame"], np.float64).ravel(),
+                              prob["rho"], prob["p"], prob["B0"], prob["dB"], prob["wavelength"],
+                              prob["gamma"], float(t), U, Bf)
+        return U, Bf
+
+    # the method -----------------------------------------------------------
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False):
+        U = np.ascontiguousarray(U, np.float64); Bf = np.ascontiguousarray(Bf, np.float64)
+        Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
+        phi = np.zeros((self.nf, NVAR)) if debug else None
+        gam = np.zeros(self.ne) if debug else None
+        rc = lib().rgo_step(self._h, gamma, dt, bc, flags, U, Bf, Uo, Bo,
+                            phi.ctypes.data if debug else None, gam.ctypes.data if debug else None)
+        if rc != 0:
+            raise RuntimeError("oracle step failed")
+        if debug:
+            return Uo, Bo, phi, gam
+        return Uo, Bo
+
+    def recon(self, U, Bf, z, pts, flags=0):
+        pts = np.ascontiguousarray(pts, np.float64)
+        w = np.zeros((len(pts), NVAR)); b = np.zeros((len(pts), 3))
+        rc = lib().rgo_recon(self._h, flags, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
+                             len(pts), pts, w, b)
+        if rc != 0:
+            raise RuntimeError("oracle reconstruction failed")
+        return w, b
+
+    def divfree(self, U, Bf, z, flags=0):
+        nb = 16 if self.order == 3 else 30
+        Q = (self.order - 1) ** 2
+        c = np.zeros(3 * nb); e = np.zeros((3 * nb, 3), np.int32); fn = np.zeros((6, Q))
+        rc = lib().rgo_divfree(self._h, flags, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
+                               c, e, fn)
+        if rc != nb:
+            raise RuntimeError("oracle divergence-free reconstruction failed")
+        return c.reshape(3, nb), e.reshape(3, nb, 3), fn
+
+    def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
+        return lib().rgo_cfl_dt(self._h, gamma, cfl, np.ascontiguousarray(U))
+
+
+def refel(order):
+    NM = np.zeros(2, np.int32)
+    lib().rgo_refel_query(order, NM, None, None, None, None, None, None, None)
+    N, M = map(int, NM)
+    E = (M - 1) * N
+    tau = np.zeros(M); wt = np.zeros(M); nodes = np.zeros((N, 3)); D = np.zeros((3, N, N))
+    Kd = np.zeros((3, E, E)); Kd0 = np.zeros((3, E, N)); Kt0 = np.zeros((E, N))
+    lib().rgo_refel_query(order, NM, tau.ctypes.data, wt.ctypes.data, nodes.ctypes.data, D.ctypes.data,
+                          Kd.ctypes.data, Kd0.ctypes.data, Kt0.ctypes.data)
+    return dict(N=N, M=M, tau=tau, wt=wt, nodes=nodes, D=D, Kd=Kd, Kd0=Kd0, Kt0=Kt0)
+
+
+def refel_eval(order, xi):
+    xi = np.ascontiguousarray(xi, np.float64)
+    N = 20 if order == 3 else 32
+    out = np.zeros((len(xi), N))
+    lib().rgo_refel_eval(order, len(xi), xi, out)
+    return out
+
+
+def lagrange(nodes, exps):
+    nodes = np.ascontiguousarray(nodes, np.float64)
+    exps = np.ascontiguousarray(exps, np.int32)
+    n = len(nodes)
+    coef = np.zeros((n, n))
+    if lib().rgo_lagrange(n, nodes, exps, coef) != 0:
+        raise RuntimeError("singular Vandermonde")
+    return coef  # psi_l = sum_k coef[k, l] * mono_k
+
+
+def gauss01(n):
+    x = np.zeros(n); w = np.zeros(n)
+    lib().rgo_gauss01(n, x, w)
+    return x, w
+
+
+def predict(order, dt, J, met, Ua, gamma=5.0 / 3.0):
+    N = len(J)
+    M = order
+    Ulev = np.zeros((M * N, NVAR)); aU = np.zeros((N, NVAR)); aF = np.zeros((N, 3, NVAR))
+    lib().rgo_predict(order, gamma, dt, np.ascontiguousarray(J, np.float64),
+                      np.ascontiguousarray(met, np.float64), np.ascontiguousarray(Ua, np.float64), Ulev, aU, aF)
+    return Ulev.reshape(M, N, NVAR), aU, aF
+
+
+def hll(UL, UR, n, gamma=5.0 / 3.0):
+    out = np.zeros(NVAR)
+    lib().rgo_hll(np.ascontiguousarray(UL, np.float64), np.ascontiguousarray(UR, np.float64),
+                  np.ascontiguousarray(n, np.float64), gamma, out)
+    return out
+
+
+def flux(U, gamma=5.0 / 3.0):
+    out = np.zeros((3, NVAR))
+    lib().rgo_flux(np.ascontiguousarray(U, np.float64), gamma, out)
+    return out
+
+
+def emf4(U4, E4, cen4, t, gamma=5.0 / 3.0):
+    return lib().rgo_emf(np.ascontiguousarray(U4, np.float64), np.ascontiguousarray(E4, np.float64),
+                         np.ascontiguousarray(cen4, np.float64), np.ascontiguousarray(t, np.float64), gamma)

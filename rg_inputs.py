@@ -1,0 +1,158 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU library.
+
+This module holds no arithmetic of the numerical method.  It only turns seeds
+into problem-definition parameters:
+
+* scalar fields on the sphere, sum_{l<=4, m} c_lm Y_lm(x/|x|) with real
+  orthonormal spherical harmonics (no Condon-Shortley phase, (l, m) in
+  lexicographic order, m = -l..l) and coefficients c_lm ~ N(0, 1) / (l+1)^2,
+  re-expressed as homogeneous polynomials: f(x) = sum_k a_k x^e_k / |x|^deg_k
+  over the 35 monomials of degree <= 4 listed by MONOMIALS;
+* the propagation axis and transverse frame of a circularly polarised wave;
+* per-zone white-noise arrays.
+
+The two consumers (the oracle under oracle/ and the library's field
+initialiser) each evaluate these definitions with their own code.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+LMAX = 4
+
+# monomials x^a y^b z^c of degree <= 4: by degree, then a descending, b descending
+MONOMIALS = [(a, b, d - a - b) for d in range(LMAX + 1)
+             for a in range(d, -1, -1) for b in range(d - a, -1, -1)]
+N_MONO = len(MONOMIALS)  # 35
+
+SEED_RHO = 101
+SEED_V = (102, 103, 104)
+SEED_A = (105, 106, 107)
+SEED_AXIS = 108
+SEED_NOISE = 109
+SEED_TARGET = (110, 111)
+
+
+def _assoc_legendre(l: int, m: int, x: np.ndarray) -> np.ndarray:
+    """P_l^m(x) without the Condon-Shortley phase, m >= 0."""
+    pmm = np.ones_like(x)
+    if m > 0:
+        s = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+        fact = 1.0
+        for _ in range(m):
+            pmm = pmm * fact * s
+            fact += 2.0
+    if l == m:
+        return pmm
+    pmmp1 = x * (2 * m + 1) * pmm
+    if l == m + 1:
+        return pmmp1
+    pll = pmmp1
+    for ll in range(m + 2, l + 1):
+        pll = (x * (2 * ll - 1) * pmmp1 - (ll + m - 1) * pmm) / (ll - m)
+        pmm, pmmp1 = pmmp1, pll
+    return pll
+
+
+def real_ylm(l: int, m: int, n: np.ndarray) -> np.ndarray:
+    """Real orthonormal spherical harmonic at unit vectors n (..., 3)."""
+    ct = n[..., 2]
+    phi = np.arctan2(n[..., 1], n[..., 0])
+    am = abs(m)
+    norm = math.sqrt((2 * l + 1) / (4 * math.pi)
+                     * math.factorial(l - am) / math.factorial(l + am))
+    p = _assoc_legendre(l, am, ct)
+    if m == 0:
+        return norm * p
+    if m > 0:
+        return math.sqrt(2.0) * norm * p * np.cos(am * phi)
+    return math.sqrt(2.0) * norm * p * np.sin(am * phi)
+
+
+def _ylm_as_monomials() -> dict:
+    """Exact homogeneous-polynomial form of each Y_lm (degree l)."""
+    rng = np.random.default_rng(12345)
+    pts = rng.normal(size=(200, 3))
+    pts /= np.linalg.norm(pts, axis=1, keepdims=True)
+    out = {}
+    for l in range(LMAX + 1):
+        idx = [k for k, e in enumerate(MONOMIALS) if sum(e) == l]
+        V = np.stack([pts[:, 0] ** MONOMIALS[k][0] * pts[:, 1] ** MONOMIALS[k][1]
+                      * pts[:, 2] ** MONOMIALS[k][2] for k in idx], axis=1)
+        for m in range(-l, l + 1):
+            y = real_ylm(l, m, pts)
+            c, *_ = np.linalg.lstsq(V, y, rcond=None)
+            if np.max(np.abs(V @ c - y)) > 1e-12:
+                raise RuntimeError("Y_lm is not a homogeneous polynomial fit")
+            full = np.zeros(N_MONO)
+            full[idx] = c
+            out[(l, m)] = full
+    return out
+
+
+_YLM_MONO = None
+
+
+def harmonic_field(seed: int) -> np.ndarray:
+    """Monomial coefficients (35,) of sum_lm c_lm Y_lm, c_lm ~ N(0,1)/(l+1)^2."""
+    global _YLM_MONO
+    if _YLM_MONO is None:
+        _YLM_MONO = _ylm_as_monomials()
+    rng = np.random.default_rng(seed)
+    out = np.zeros(N_MONO)
+    for l in range(LMAX + 1):
+        for m in range(-l, l + 1):
+            out += rng.normal() / (l + 1) ** 2 * _YLM_MONO[(l, m)]
+    return out
+
+
+def eval_field(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Evaluate a field given by monomial coefficients at points x (..., 3)."""
+    r = np.linalg.norm(x, axis=-1)
+    val = np.zeros(x.shape[:-1])
+    for k, (a, b, c) in enumerate(MONOMIALS):
+        val = val + coef[k] * x[..., 0] ** a * x[..., 1] ** b * x[..., 2] ** c / r ** (a + b + c)
+    return val
+
+
+def harmonic_problem() -> dict:
+    """Smooth multi-harmonic state: rho = 1 + 0.1 f, p = 1, v = 0.1 f, A = 0.1 f.
+
+    Returns monomial-coefficient arrays of shape (35,) for rho (including the
+    constant 1), vx, vy, vz and the vector potential Ax, Ay, Az.
+    """
+    rho = 0.1 * harmonic_field(SEED_RHO)
+    rho[0] += 1.0
+    return {
+        "rho": rho,
+        "v": np.stack([0.1 * harmonic_field(s) for s in SEED_V]),
+        "A": np.stack([0.1 * harmonic_field(s) for s in SEED_A]),
+        "p": 1.0,
+        "gamma": 5.0 / 3.0,
+    }
+
+
+def wave_frame(seed: int = SEED_AXIS) -> np.ndarray:
+    """Seeded unit axis a and transverse e1, e2 with e1 x e2 = a; rows (e1, e2, a)."""
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    helper = np.eye(3)[int(np.argmin(np.abs(a)))]
+    e1 = np.cross(a, helper)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(a, e1)
+    return np.stack([e1, e2, a])
+
+
+def alfven_problem() -> dict:
+    """Circularly polarised Alfven wave: B0 = 1 along a, dB = 0.1, rho = 1, p = 0.1."""
+    return {"frame": wave_frame(), "rho": 1.0, "p": 0.1, "B0": 1.0, "dB": 0.1,
+            "wavelength": 1.0, "gamma": 5.0 / 3.0}
+
+
+def white_noise(n: int, seed: int = SEED_NOISE, count: int = 2) -> np.ndarray:
+    """Uniform(-1, 1) noise, shape (count, n)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=(count, n))

@@ -1,0 +1,395 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle (oracle/) against something other than itself:
+values printed in the paper (tests/golden/), closed forms, exactness
+properties of polynomial reconstructions, and exact special solutions.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import rg_inputs as RI
+from oracle import oracle as O
+from tests import golden_io as G
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+# ---------------------------------------------------------------- reference element
+@pytest.mark.parametrize("order", [3, 4])
+def test_time_galerkin_matches_printed_R(order):
+    """The oracle's full space-time Galerkin reduction (eqs. 5.24-5.29) equals
+    R (x) D with R as printed in (C.18)/(D.28) and D the nodal derivative
+    matrix, i.e. the compact update (C.34)-(C.36), (D.29)-(D.32)."""
+    R = np.array(G.time_R()[order])
+    r = O.refel(order)
+    N, M = r["N"], r["M"]
+    for d in range(3):
+        np.testing.assert_allclose(r["Kd"][d], np.kron(R[1:, 1:], r["D"][d]), atol=1e-12)
+        np.testing.assert_allclose(r["Kd0"][d], np.kron(R[1:, :1], r["D"][d]), atol=1e-12)
+    np.testing.assert_allclose(r["Kt0"], np.kron(np.ones((M - 1, 1)), np.eye(N)), atol=1e-12)
+
+
+def test_time_nodes_and_printed_R_second_order():
+    """(5.15)-(5.17): tau = 0 plus Gauss points; R rows sum to tau (B.9/C.18/D.28)."""
+    for order, R in G.time_R().items():
+        R = np.array(R)
+        if order >= 3:
+            r = O.refel(order)
+            np.testing.assert_allclose(R.sum(1), r["tau"], atol=1e-14)
+    r3 = O.refel(3)
+    np.testing.assert_allclose(r3["tau"], [0, 0.5 - 0.5 / math.sqrt(3), 0.5 + 0.5 / math.sqrt(3)], atol=1e-15)
+    r4 = O.refel(4)
+    np.testing.assert_allclose(r4["tau"], [0, 0.5 - 0.5 * math.sqrt(0.6), 0.5, 0.5 + 0.5 * math.sqrt(0.6)],
+                               atol=1e-15)
+    np.testing.assert_allclose(r4["wt"][1:], [5 / 18, 8 / 18, 5 / 18], atol=1e-15)
+
+
+def test_lagrange_generator_reproduces_printed_prism_basis():
+    """Generic Lagrange generator on the printed prism nodes (C.2-C.16) and
+    monomials (5.13) reproduces the printed basis functions (C.19, C.21, C.25,
+    C.28, C.29)."""
+    nodes, monos, basis = G.prism_basis()
+    coef = O.lagrange(np.array(nodes), np.array(monos))
+    for idx, printed in basis.items():
+        l = idx - 1
+        for k, e in enumerate(monos):
+            assert abs(coef[k, l] - printed.get(e, 0.0)) < 1e-12, (idx, e)
+
+
+def test_square_rules_match_printed_appendix_A():
+    """Tensor Gauss rules equal the printed (A.4) and (A.6) square rules."""
+    rules = G.square_rules()
+    x2, w2 = O.gauss01(2)
+    x3, w3 = O.gauss01(3)
+    a4 = sorted((a, b, wa * wb) for a, wa in zip(x2, w2) for b, wb in zip(x2, w2))
+    np.testing.assert_allclose(np.array(a4), np.array(sorted(map(tuple, rules["A4"]))), atol=1e-15)
+    a6 = sorted((a, b, wa * wb) for a, wa in zip(x2, w2) for b, wb in zip(x3, w3))
+    np.testing.assert_allclose(np.array(a6), np.array(sorted(map(tuple, rules["A6"]))), atol=1e-15)
+    for n in range(1, 11):
+        x, w = O.gauss01(n)
+        for k in range(2 * n):
+            assert abs(np.sum(w * x ** k) - 1.0 / (k + 1)) < 1e-14
+
+
+@pytest.mark.parametrize("order,nn", [(3, 20), (4, 32)])
+def test_hex_serendipity_element(order, nn):
+    """Serendipity basis: nodal, reproduces every polynomial of total degree
+    <= p-1 exactly, derivative matrices exact and commuting (closure)."""
+    r = O.refel(order)
+    assert r["N"] == nn
+    nodes = r["nodes"]
+    psi = O.refel_eval(order, nodes)
+    np.testing.assert_allclose(psi, np.eye(nn), atol=1e-12)
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-0.5, 0.5, size=(40, 3))
+    P = O.refel_eval(order, pts)
+    np.testing.assert_allclose(P.sum(1), 1.0, atol=1e-12)
+    for a in range(order):
+        for b in range(order - a):
+            for c in range(order - a - b):
+                f = lambda x: x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c
+                np.testing.assert_allclose(P @ f(nodes), f(pts), atol=1e-12)
+                df = a * nodes[:, 0] ** max(a - 1, 0) * nodes[:, 1] ** b * nodes[:, 2] ** c
+                np.testing.assert_allclose(r["D"][0] @ f(nodes), df, atol=1e-12)
+    D = r["D"]
+    for i in range(3):
+        for j in range(3):
+            np.testing.assert_allclose(D[i] @ D[j], D[j] @ D[i], atol=1e-10)
+    # entries of D are multiples of 1/2
+    np.testing.assert_allclose(np.round(2 * D), 2 * D, atol=1e-9)
+
+
+# ---------------------------------------------------------------- mesh and geometry
+@pytest.fixture(scope="module")
+def mesh3():
+    return O.OracleMesh(8, 4, order=3, n_ghost=2)
+
+
+@pytest.fixture(scope="module")
+def mesh4():
+    return O.OracleMesh(4, 4, order=4, n_ghost=3)
+
+
+def test_mesh_counts(mesh3):
+    m = mesh3
+    N, K = 8, m.ktot
+    assert m.nv == 6 * N * N + 2
+    assert m.nz == 6 * N * N * K
+    assert m.nf == 6 * N * N * (K + 1) + 12 * N * N * K
+    assert m.ne == (6 * N * N + 2) * K + 12 * N * N * (K + 1)
+
+
+def test_stencil_sizes(mesh3, mesh4):
+    for m, full, corner in [(mesh3, 26, 23), (mesh4, 32, 29)]:
+        cen, vol, shell, stn = m.zones()
+        g = m.n_ghost
+        act = (shell >= g - 1) & (shell <= g + m.n_rad)
+        vals, cnt = np.unique(stn[act], return_counts=True)
+        assert set(vals) == {full, corner}
+        # three columns touch each of the 8 cube corners
+        assert cnt[list(vals).index(corner)] == 24 * (m.n_rad + 2)
+
+
+def test_sphericity_of_isoparametric_maps():
+    """Quadratic and cubic maps reproduce the sphere to about one part in 1e6
+    and 1e7 for ~5 degree elements (Section II.b)."""
+    q2 = O.OracleMesh(16, 1, order=3, n_ghost=2, map_order=2).sphericity(12)
+    q3 = O.OracleMesh(16, 1, order=4, n_ghost=3, map_order=3).sphericity(12)
+    assert q2 < 1e-6 and q3 < 1e-7 and q3 < q2 / 3
+
+
+def test_volume_and_second_moment_closed_forms():
+    m = O.OracleMesh(16, 2, order=4, n_ghost=3, map_order=3)
+    cen, vol, shell, _ = m.zones()
+    g = m.n_ghost
+    act = (shell >= g) & (shell < g + m.n_rad)
+    V = (4 * math.pi / 3) * (2.0 ** 3 - 1.0)
+    assert abs(vol[act].sum() / V - 1) < 1e-6
+    # int |x|^2 dV over the shell from centroids + zone moments (parallel axis)
+    z0 = np.where(act)[0]
+    I = 0.0
+    for z in z0:
+        x, w = m.cubature(z)
+        I += np.sum(w * np.sum(x * x, 1))
+    assert abs(I / ((4 * math.pi / 5) * (2.0 ** 5 - 1.0)) - 1) < 1e-6
+
+
+def test_face_closure(mesh4):
+    m = mesh4
+    zf, _ = m.zone_faces()
+    _, _, area, fz = m.faces()
+    x, n, dA = m.face_quad()
+    worst = 0.0
+    for z in range(0, m.nz, 7):
+        s = np.zeros(3)
+        for lf in range(6):
+            f = zf[z, lf]
+            s += (1 if fz[f, 0] == z else -1) * (n[f] * dA[f][:, None]).sum(0)
+        worst = max(worst, np.abs(s).max() / area[zf[z]].max())
+    assert worst < 1e-13
+
+
+@pytest.mark.parametrize("which", ["mesh3", "mesh4"])
+def test_curl_metrics_have_zero_discrete_divergence(which, request):
+    m = request.getfixturevalue(which)
+    r = O.refel(m.order)
+    for z in range(0, m.nz, 97):
+        x, J, met = m.node_data(z)
+        div = sum(r["D"][d] @ met[:, d, :] for d in range(3))
+        assert np.abs(div).max() < 1e-14 * max(1.0, np.abs(met).max() * 100)
+        assert (J > 0).all()
+
+
+# ---------------------------------------------------------------- reconstruction
+def _zone_average(m, z, f):
+    x, w = m.cubature(z)
+    return np.sum(w * f(x)) / np.sum(w)
+
+
+@pytest.mark.parametrize("which", ["mesh3", "mesh4"])
+def test_lsq_reproduces_polynomials(which, request):
+    """Linear-weight WENO-AO (the large-stencil least squares of eq. 3.4)
+    reproduces any polynomial of degree <= p-1 on curved zones; the nonlinear
+    reconstruction reproduces linear functions."""
+    m = request.getfixturevalue(which)
+    p = m.order
+    rng = np.random.default_rng(7)
+    cen, vol, shell, _ = m.zones()
+    z = int(np.where(shell == m.n_ghost + 1)[0][13])
+    pts = cen[z] + 0.3 * vol[z] ** (1 / 3) * rng.uniform(-1, 1, size=(6, 3))
+    exps = [(a, b, c) for a in range(p) for b in range(p - a) for c in range(p - a - b)]
+    coef = rng.normal(size=len(exps))
+    f = lambda x: sum(cf * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c for cf, (a, b, c) in zip(coef, exps))
+    lin = lambda x: 0.3 + x @ np.array([0.2, -0.1, 0.4])
+    U = np.ones((8, m.nz))
+    near = np.unique(np.concatenate([[z], *[np.where(np.linalg.norm(cen - cen[z], axis=1) < 4 * vol[z] ** (1 / 3))[0]]]))
+    for zz in near:
+        U[0, zz] = _zone_average(m, zz, f)
+        U[1, zz] = _zone_average(m, zz, lin)
+    Bf = np.zeros(m.nf)
+    w, _ = m.recon(U, Bf, z, pts, flags=O.FLAG_LINEAR_WEIGHTS)
+    np.testing.assert_allclose(w[:, 0], f(pts), rtol=0, atol=1e-11)
+    w, _ = m.recon(U, Bf, z, pts, flags=0)
+    np.testing.assert_allclose(w[:, 1], lin(pts), rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("which", ["mesh3", "mesh4"])
+def test_divergence_free_reconstruction_is_exact_for_divfree_polynomials(which, request):
+    """With consistent face data, the constrained least squares of Section IV
+    returns any divergence-free polynomial of degree <= p-1 exactly."""
+    m = request.getfixturevalue(which)
+    cen, vol, shell, _ = m.zones()
+    z = int(np.where(shell == m.n_ghost + 1)[0][21])
+    x, n, dA = m.face_quad()
+
+    def Bfield(X):
+        x_, y_, z_ = X[..., 0], X[..., 1], X[..., 2]
+        b = np.stack([0.3 + x_ * x_ - 0.5 * y_ + 0.2 * z_ * y_,
+                      -0.1 - 2 * x_ * y_ + 0.7 * z_,
+                      0.4 + 0.3 * x_ - 0.6 * y_ * x_], -1)
+        return b
+
+    U = np.ones((8, m.nz))
+    U[4] = 10.0
+    h = vol[z] ** (1 / 3)
+    near = np.where(np.linalg.norm(cen - cen[z], axis=1) < 5 * h)[0]
+    for zz in near:
+        for c in range(3):
+            U[5 + c, zz] = _zone_average(m, zz, lambda X: Bfield(X)[:, c])
+    Bf = np.einsum("fqc,fqc,fq->f", n, Bfield(x), dA) / dA.sum(1)
+    rng = np.random.default_rng(3)
+    pts = cen[z] + 0.3 * h * rng.uniform(-1, 1, size=(6, 3))
+    _, b = m.recon(U, Bf, z, pts, flags=O.FLAG_LINEAR_WEIGHTS)
+    np.testing.assert_allclose(b, Bfield(pts), rtol=0, atol=1e-11)
+
+
+def test_divergence_free_coefficients_satisfy_constraints(mesh4):
+    """Eq. (4.10) identities hold exactly and eq. (4.14) face means are met."""
+    m = mesh4
+    U, Bf = m.init_harmonic(RI.harmonic_problem())
+    cen, vol, shell, _ = m.zones()
+    zf, _ = m.zone_faces()
+    _, _, area, fz = m.faces()
+    x, n, dA = m.face_quad()
+    z = int(np.where(shell == m.n_ghost + 2)[0][5])
+    c, e, _ = m.divfree(U, Bf, z)
+    p = m.order
+    # divergence polynomial coefficients for every monomial mu with 1 <= |mu| <= p-1
+    for a in range(p):
+        for b in range(p - a):
+            for cc in range(p - a - b):
+                mu = (a, b, cc)
+                if sum(mu) == 0:
+                    continue
+                s = 0.0
+                for comp in range(3):
+                    t = list(mu); t[comp] += 1
+                    k = [i for i in range(e.shape[1]) if tuple(e[comp, i]) == tuple(t)][0]
+                    s += t[comp] * c[comp, k]
+                assert abs(s) < 1e-11
+    # face constraints: evaluate the polynomial at face points
+    h = vol[z] ** (1 / 3)
+    for lf in range(6):
+        f = zf[z, lf]
+        pts = x[f]
+        _, b = m.recon(U, Bf, z, pts)
+        sg = 1 if fz[f, 0] == z else -1
+        mean = np.sum(dA[f] * np.einsum("qc,qc->q", b, n[f])) / dA[f].sum()
+        assert abs(mean - Bf[f]) < 1e-12 * max(1, abs(Bf[f]))
+
+
+# ---------------------------------------------------------------- predictor
+@pytest.mark.parametrize("order", [3, 4])
+def test_predictor_exact_for_advected_polynomial(order):
+    """On an affine element a density polynomial of degree <= p-1 advected by
+    uniform v (p, B uniform) is reproduced exactly at every space-time node
+    after p Picard iterations (ADER-CG, eqs. 5.20-5.29)."""
+    r = O.refel(order)
+    nodes = r["nodes"]
+    N = r["N"]
+    rng = np.random.default_rng(5)
+    A = np.eye(3) * 0.1 + 0.02 * rng.normal(size=(3, 3))
+    x0 = np.array([1.2, 0.3, -0.4])
+    X = nodes @ A.T + x0
+    J = np.full(N, np.linalg.det(A))
+    h = [A[:, 0], A[:, 1], A[:, 2]]
+    met = np.zeros((N, 3, 3))
+    met[:, 0] = np.cross(h[1], h[2]); met[:, 1] = np.cross(h[2], h[0]); met[:, 2] = np.cross(h[0], h[1])
+    v = np.array([0.7, -0.3, 0.5]); B = np.array([0.2, 0.1, -0.3]); p = 0.8; gam = 5 / 3
+    exps = [(a, b, c) for a in range(order) for b in range(order - a) for c in range(order - a - b)]
+    cf = 0.05 * rng.normal(size=len(exps)); cf[0] = 1.0
+    rho = lambda x: sum(c * ((x[:, 0] - 1.2) / 0.1) ** a * ((x[:, 1] - 0.3) / 0.1) ** b
+                        * ((x[:, 2] + 0.4) / 0.1) ** cc for c, (a, b, cc) in zip(cf, exps))
+
+    def state(x):
+        rh = rho(x)
+        U = np.zeros((len(x), 8))
+        U[:, 0] = rh; U[:, 1:4] = rh[:, None] * v
+        U[:, 4] = p / (gam - 1) + 0.5 * rh * (v @ v) + 0.5 * (B @ B)
+        U[:, 5:8] = B
+        return U
+
+    dt = 0.02
+    Ulev, aU, aF = O.predict(order, dt, J, met, state(X))
+    for t in range(order):
+        tau = r["tau"][t]
+        np.testing.assert_allclose(Ulev[t] / J[:, None], state(X - v * tau * dt), rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------------- Riemann solvers
+def _state(rho, v, p, B, gam=5 / 3):
+    v = np.asarray(v, float); B = np.asarray(B, float)
+    return np.array([rho, *(rho * v), p / (gam - 1) + 0.5 * rho * v @ v + 0.5 * B @ B, *B])
+
+
+def test_hll_consistency_and_upwinding():
+    n = np.array([0.6, 0.0, 0.8])
+    U = _state(1.1, [0.1, -0.2, 0.3], 0.9, [0.2, 0.4, -0.1])
+    np.testing.assert_allclose(O.hll(U, U, n), O.flux(U).T @ n, atol=1e-15)
+    # supersonic flow along n: upwind (left) flux
+    UL = _state(1.0, 20 * n, 1.0, [0.1, 0.1, 0.1]); UR = _state(0.5, 18 * n, 0.4, [0.0, 0.2, 0.1])
+    np.testing.assert_allclose(O.hll(UL, UR, n), O.flux(UL).T @ n, atol=1e-13)
+    np.testing.assert_allclose(O.hll(UR, UL, -n), -(O.flux(UL).T @ n), atol=1e-13)
+
+
+def test_multid_emf_reduces_to_1d_hll():
+    """With data varying across one direction only, the four-state electric
+    field equals the 1-D HLL flux of the induction equation (eq. 2.3)."""
+    t = np.array([0.0, 0.0, 1.0])
+    cen = np.array([[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0]], float)
+    UL = _state(1.0, [0.3, -0.2, 0.1], 1.0, [0.5, 0.3, -0.2])
+    UR = _state(0.7, [-0.1, 0.4, 0.2], 0.6, [0.5, -0.1, 0.4])
+    U4 = np.array([UL, UR, UR, UL])
+    E = lambda U: -np.cross(U[1:4] / U[0], U[5:8])
+    E4 = np.array([E(u) for u in U4])
+    Es = O.emf4(U4, E4, cen, t)
+    n = np.array([1.0, 0.0, 0.0])
+    Fs = O.hll(UL, UR, n)
+    # E_z = -F*(B_y) along x
+    assert abs(Es - (-Fs[6])) < 1e-14
+    # and along y: states vary in the second direction
+    U4 = np.array([UL, UL, UR, UR]); E4 = np.array([E(u) for u in U4])
+    Fs = O.hll(UL, UR, np.array([0.0, 1.0, 0.0]))
+    assert abs(O.emf4(U4, E4, cen, t) - Fs[5]) < 1e-14
+
+
+# ---------------------------------------------------------------- whole step
+def test_free_stream_and_divergence(mesh3):
+    m = mesh3
+    cen, vol, shell, _ = m.zones()
+    x, n, dA = m.face_quad()
+    B = np.array([0.3, 0.2, -0.4]); v = np.array([0.3, -0.2, 0.1]); p = 1.0
+    U = np.tile(_state(1.0, v, p, B)[:, None], (1, m.nz))
+    Bf = np.einsum("fqc,c,fq->f", n, B, dA) / dA.sum(1)
+    Uo, Bo = m.step(U, Bf, 0.01)
+    g = m.n_ghost
+    act = (shell >= g) & (shell < g + m.n_rad)
+    assert np.abs(Uo - U)[:, act].max() < 1e-13
+    assert np.abs(Bo - Bf).max() < 1e-13
+
+
+def test_step_divergence_free_and_conservative(mesh4):
+    m = mesh4
+    U, Bf = m.init_harmonic(RI.harmonic_problem())
+    cen, vol, shell, _ = m.zones()
+    zf, _ = m.zone_faces()
+    _, _, area, fz = m.faces()
+    dt = m.cfl_dt(U, 0.3)
+    Uo, Bo, phi, gam = m.step(U, Bf, dt, debug=True)
+    g = m.n_ghost
+    act = (shell >= g) & (shell < g + m.n_rad)
+    sg = np.where(fz[zf][:, :, 0] == np.arange(m.nz)[:, None], 1.0, -1.0)
+    div = np.abs((sg * area[zf] * Bo[zf]).sum(1)) / (area[zf] * np.abs(Bo[zf])).sum(1)
+    assert div[act].max() < 1e-13
+    # conservation of rho, m, energy: change of the sum = boundary flux
+    bnd = np.zeros(8)
+    for z in np.where(act)[0]:
+        for lf in range(6):
+            f = zf[z, lf]
+            other = fz[f, 1] if fz[f, 0] == z else fz[f, 0]
+            if not act[other]:
+                bnd -= dt * (1 if fz[f, 0] == z else -1) * phi[f]
+    dsum = ((Uo - U)[:, act] * vol[act]).sum(1)
+    np.testing.assert_allclose(dsum[:5], bnd[:5], rtol=0, atol=1e-13 * np.abs(U[:5, act] * vol[act]).sum(1).max())
