@@ -1,0 +1,160 @@
+/*
+ * rg -- one ADER-WENO-AO divergence-free ideal-MHD timestep on a radially
+ * extruded cube-based geodesic mesh of isoparametric hexahedra, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The scheme is the one of Balsara, Florinski, Garain, Subramanian & Gurski,
+ * "Efficient, divergence-free, high order MHD on 3D spherical meshes with
+ * optimal geodesic meshing" (2019): WENO-AO reconstruction in a Taylor basis
+ * (Section III), divergence-free reconstruction of B from face averages
+ * (Section IV), ADER-CG space-time predictor on serendipity elements
+ * (Section V), and a corrector with 1-D Riemann solvers at face quadrature
+ * points, multidimensional Riemann solvers at edges and Yee-type constrained
+ * transport (Sections II.c and VI).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All calls return rg_status; on failure rg_last_error() (thread-local)
+ *   describes the problem.  Nothing throws across this boundary.
+ * - Mesh and geometry are opaque, library-owned handles (free with
+ *   rg_mesh_free / rg_geom_free).  State arrays are caller-owned.
+ * - Zones: columns are numbered col = (patch * N + j) * N + i for the six
+ *   cube patches of N x N columns; each column holds K = n_rad + 2 * n_ghost
+ *   shells (n_ghost ghost shells below r_in and above r_out).  Zone
+ *   z = col * K + k, radial index fastest.
+ * - U is double[8][n_zones] (structure of arrays): rho, rho v_x, rho v_y,
+ *   rho v_z, total energy, B_x, B_y, B_z, zone averages, rationalised units
+ *   (magnetic pressure B^2 / 2), i.e. eq. (2.2) with 4 pi absorbed into B.
+ * - Bf is double[n_faces]: face-averaged normal B, the primal magnetic
+ *   variable.  Radial faces come first, id = col * (K + 1) + kf (kf = index
+ *   of the interface, normal +r); then angular faces, id = n_radial_faces +
+ *   ae * K + k (normal from the first to the second column of angular edge
+ *   ae, as reported by rg_geom_face_data).
+ * - Edges: radial edges id = v * K + k (direction +r), then angular edges
+ *   id = n_radial_edges + ae * (K + 1) + kf.
+ * - Device pointers are HIP device memory; streams are hipStream_t passed as
+ *   void*.  Work is asynchronous on the stream unless stated otherwise.
+ */
+#ifndef RG_H
+#define RG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RG_OK = 0,
+    RG_EINVAL = 1,     /* bad argument (sizes, pointers, unsupported combination) */
+    RG_ENOMEM = 2,     /* host or device allocation failed                        */
+    RG_ESINGULAR = 3,  /* a least-squares or KKT system was singular at precompute */
+    RG_ENOTSUP = 4,    /* order / mode / mesh size not supported                  */
+    RG_EDEVICE = 5     /* a HIP runtime call failed                               */
+} rg_status;
+
+/* Geodesic shell mesh, Section II.a (cube-based, recursive great-circle
+ * bisection, N = 2^k zones per cube edge) with radial extrusion into shells
+ * of geometrically growing thickness (self-similar zones, Section V.b). */
+typedef struct {
+    int32_t n_ang;      /* zones per cube edge, a power of two (>= 2)            */
+    int32_t n_rad;      /* physical radial shells                               */
+    double r_in, r_out; /* inner / outer radius, 0 < r_in < r_out               */
+    int32_t radial;     /* 0 = geometric shells r_k = r_in (r_out/r_in)^(k/n_rad) */
+    int32_t map_order;  /* isoparametric surface map: 2 quadratic, 3 cubic (II.b) */
+    int32_t n_ghost;    /* ghost shells on each side; 0 selects 3               */
+} rg_mesh_desc;
+
+typedef struct {
+    int64_t n_ang, n_rad, n_ghost, n_shells; /* n_shells = K = n_rad + 2 n_ghost */
+    int64_t n_columns, n_zones;
+    int64_t n_faces, n_radial_faces;
+    int64_t n_edges, n_radial_edges;
+    int64_t n_vertices, n_angular_edges;
+} rg_mesh_info;
+
+typedef struct rg_mesh rg_mesh;
+typedef struct rg_geom rg_geom;
+
+/* Builds the mesh topology on the host.  Deterministic.  *out receives a
+ * handle owned by the caller (rg_mesh_free).  RG_ENOTSUP if n_ang is not a
+ * power of two, RG_EINVAL for other bad fields. */
+rg_status rg_mesh_build(const rg_mesh_desc *desc, rg_mesh **out);
+rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info);
+void rg_mesh_free(rg_mesh *mesh);
+
+/* Precision of the reconstruction and predictor contractions.  Geometry,
+ * the conservative update and constrained transport are always FP64. */
+typedef enum { RG_MODE_FP64 = 0, RG_MODE_FP32 = 1 } rg_mode;
+
+/* Geometry precompute (Section VI step 1): FP64 on the host, one radial column
+ * at a time (zones of a column are self-similar, Section V.b), then one upload
+ * to the device on `stream`.  order is 3 or 4 (the scheme's order; the mesh
+ * map_order should be order-1).  Requires n_ghost >= order - 1.  The mesh
+ * must outlive the geometry.  RG_ESINGULAR if a least-squares or KKT system
+ * is singular.  Synchronous with respect to `stream` on return. */
+rg_status rg_geom_precompute(const rg_mesh *mesh, int32_t order, int32_t mode, void *stream, rg_geom **out);
+void rg_geom_free(rg_geom *geom);
+
+/* The same precompute without any device allocation or upload: for host-side
+ * checks and initial data (the query calls and rg_init_alfven work, rg_step,
+ * rg_step_fluxes and rg_cfl_dt return RG_EINVAL).  Always FP64. */
+rg_status rg_geom_precompute_host(const rg_mesh *mesh, int32_t order, rg_geom **out);
+
+/* Host copies of geometric data, for checks and initial data.  Any pointer
+ * may be NULL.  centroid: [n_zones][3], volume: [n_zones]; face centre and
+ * unit normal (area-weighted mean, canonical orientation) [n_faces][3], area
+ * [n_faces]; edge midpoint and unit tangent [n_edges][3]. */
+rg_status rg_geom_zone_data(const rg_geom *geom, double *centroid, double *volume);
+rg_status rg_geom_face_data(const rg_geom *geom, double *center, double *normal, double *area);
+rg_status rg_geom_edge_data(const rg_geom *geom, double *midpoint, double *tangent);
+
+typedef struct {
+    double gamma;     /* ratio of specific heats                                   */
+    double dt;        /* timestep; if <= 0 it is computed from cfl (host sync) and
+                         written back here                                         */
+    double cfl;       /* CFL number for the in-sphere diameter (Section VIII)       */
+    int32_t bc_kind;  /* 0: continuative (ghost shells copy the nearest interior
+                         shell, Section VII); 1: ghost values supplied by the caller */
+    int32_t n_picard; /* 0 selects the order (Section V.d step 9)                   */
+} rg_step_params;
+
+/* One complete timestep (Section VI) on device buffers.
+ * U, Bf: state at t (device, read only).  U_out, Bf_out: state at t + dt
+ * (device).  U_out may equal U and Bf_out may equal Bf (in place).  Ghost
+ * entries of U_out / Bf_out hold the boundary-filled input.  Interior zone B
+ * of U_out is the divergence-free reconstruction's mean (Section IV.b step
+ * 10) advanced by the face fluxes.  Asynchronous on `stream` unless
+ * params->dt <= 0. */
+rg_status rg_step(const rg_geom *geom, rg_step_params *params, const double *U, const double *Bf,
+                  double *U_out, double *Bf_out, void *stream);
+
+/* Device copies of the last step's face flux integrals Phi[8][n_faces]
+ * (time-integrated over the step divided by dt, canonical normal) and edge
+ * electric-field line integrals Gam[n_edges] (canonical direction).  Entries
+ * the step did not compute are zero.  Asynchronous on `stream`. */
+rg_status rg_step_fluxes(const rg_geom *geom, double *Phi, double *Gam, void *stream);
+
+/* Timestep limit dt = cfl * min over interior zones of d_in / (|v| + c_f,max)
+ * (Section VIII) for device state U; blocks until the result is on the host. */
+rg_status rg_cfl_dt(const rg_geom *geom, const double *U, double gamma, double cfl, void *stream, double *dt);
+
+/* Initial data on the host (caller-owned host arrays U[8][n_zones],
+ * Bf[n_faces]) for a circularly polarised Alfven wave with axis frame
+ * (e1, e2, a) = frame[0..8]: B = B0 a + dB (cos phi e1 + sin phi e2),
+ * v = -(dB/sqrt(rho)) (cos phi e1 + sin phi e2), phi = 2 pi (x.a - v_A t) / wavelength.
+ * Zone averages by the zone cubature; Bf from circulations of the vector
+ * potential (divergence-free to round-off).  If noise is non-NULL it holds
+ * double[2][n_zones] in [-1, 1] and the zone averages of rho and pressure are
+ * multiplied by (1 + noise_amp * noise). */
+rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, double p, double B0, double dB,
+                         double wavelength, double gamma, double t, const double *noise, double noise_amp,
+                         double *U, double *Bf);
+
+const char *rg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

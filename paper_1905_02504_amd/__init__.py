@@ -1,0 +1,127 @@
+"""rg: ADER-WENO-AO divergence-free MHD timestep on a cube-based geodesic
+shell mesh, as HIP kernels for AMD MI355X (gfx950).
+
+The Python layer only marshals arguments to the C-ABI in include/rg.h (see
+_native.py); PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+from ._native import RGError, rg_step_params  # noqa: F401
+
+__all__ = ["ShellMHD", "RGError", "rg_step_params"]
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class ShellMHD:
+    """Mesh + precomputed geometry of one shell problem.
+
+    device=False builds only the host geometry (queries and initial data);
+    device=True also uploads it and allows steps on torch.cuda float64 tensors.
+    """
+
+    def __init__(self, n_ang, n_rad, order, r_in=1.0, r_out=2.0, map_order=None, n_ghost=3, device=True,
+                 mode=N.RG_MODE_FP64):
+        if map_order is None:
+            map_order = order - 1
+        self.order = order
+        self._mesh = N.rg_mesh_build(n_ang, n_rad, r_in, r_out, map_order, n_ghost)
+        self.info = N.rg_mesh_get_info(self._mesh)
+        self.nz = self.info["n_zones"]
+        self.nf = self.info["n_faces"]
+        self.ne = self.info["n_edges"]
+        self.K = self.info["n_shells"]
+        self.g = self.info["n_ghost"]
+        self.n_rad = n_rad
+        self.device = device
+        if device:
+            self._geom = N.rg_geom_precompute(self._mesh, order, mode, _stream())
+        else:
+            self._geom = N.rg_geom_precompute_host(self._mesh, order)
+
+    def close(self):
+        if getattr(self, "_geom", None):
+            N.rg_geom_free(self._geom)
+            self._geom = None
+        if getattr(self, "_mesh", None):
+            N.rg_mesh_free(self._mesh)
+            self._mesh = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # geometry queries ------------------------------------------------------
+    def zone_data(self):
+        cen = np.zeros((self.nz, 3)); vol = np.zeros(self.nz)
+        N.rg_geom_zone_data(self._geom, _ptr(cen), _ptr(vol))
+        return cen, vol
+
+    def face_data(self):
+        cen = np.zeros((self.nf, 3)); nrm = np.zeros((self.nf, 3)); area = np.zeros(self.nf)
+        N.rg_geom_face_data(self._geom, _ptr(cen), _ptr(nrm), _ptr(area))
+        return cen, nrm, area
+
+    def edge_data(self):
+        mid = np.zeros((self.ne, 3)); tan = np.zeros((self.ne, 3))
+        N.rg_geom_edge_data(self._geom, _ptr(mid), _ptr(tan))
+        return mid, tan
+
+    def shells(self):
+        return np.tile(np.arange(self.K), self.nz // self.K)
+
+    def interior(self):
+        k = self.shells()
+        return (k >= self.g) & (k < self.g + self.n_rad)
+
+    # initial data ------------------------------------------------------------
+    def init_alfven(self, prob, t=0.0, noise=None, noise_amp=0.0):
+        U = np.zeros((8, self.nz)); Bf = np.zeros(self.nf)
+        frame = np.ascontiguousarray(prob["frame"], np.float64).ravel()
+        nz = None if noise is None else np.ascontiguousarray(noise, np.float64)
+        N.rg_init_alfven(self._geom, _ptr(frame), prob["rho"], prob["p"], prob["B0"], prob["dB"],
+                         prob["wavelength"], prob["gamma"], float(t), _ptr(nz), float(noise_amp), _ptr(U), _ptr(Bf))
+        return U, Bf
+
+    # the step ------------------------------------------------------------------
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0):
+        """One timestep on torch.cuda float64 tensors; returns (U_out, Bf_out, dt)."""
+        import torch
+        assert U.is_cuda and U.dtype == torch.float64 and U.is_contiguous() and U.shape == (8, self.nz)
+        assert Bf.is_cuda and Bf.dtype == torch.float64 and Bf.is_contiguous() and Bf.shape == (self.nf,)
+        if U_out is None:
+            U_out = torch.empty_like(U)
+        if Bf_out is None:
+            Bf_out = torch.empty_like(Bf)
+        p = rg_step_params(gamma, dt, cfl, bc, n_picard)
+        N.rg_step(self._geom, p, U.data_ptr(), Bf.data_ptr(), U_out.data_ptr(), Bf_out.data_ptr(), _stream())
+        return U_out, Bf_out, p.dt
+
+    def fluxes(self):
+        import torch
+        Phi = torch.zeros((8, self.nf), dtype=torch.float64, device="cuda")
+        Gam = torch.zeros(self.ne, dtype=torch.float64, device="cuda")
+        N.rg_step_fluxes(self._geom, Phi.data_ptr(), Gam.data_ptr(), _stream())
+        return Phi, Gam
+
+    def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
+        return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())

@@ -1,0 +1,146 @@
+"""Thin ctypes binding of the rg C-ABI (include/rg.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+(librg.so).  The functions keep the C names; device buffers and streams come
+from PyTorch (tensor.data_ptr(), torch.cuda.current_stream().cuda_stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librg.so")
+
+RG_OK, RG_EINVAL, RG_ENOMEM, RG_ESINGULAR, RG_ENOTSUP, RG_EDEVICE = range(6)
+RG_MODE_FP64, RG_MODE_FP32 = 0, 1
+
+
+class rg_mesh_desc(C.Structure):
+    _fields_ = [("n_ang", C.c_int32), ("n_rad", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("radial", C.c_int32), ("map_order", C.c_int32), ("n_ghost", C.c_int32)]
+
+
+class rg_mesh_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_ang", "n_rad", "n_ghost", "n_shells", "n_columns", "n_zones",
+                                         "n_faces", "n_radial_faces", "n_edges", "n_radial_edges",
+                                         "n_vertices", "n_angular_edges")]
+
+
+class rg_step_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("dt", C.c_double), ("cfl", C.c_double), ("bc_kind", C.c_int32),
+                ("n_picard", C.c_int32)]
+
+
+class RGError(RuntimeError):
+    pass
+
+
+_lib = None
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load librg.so; fails loudly when the HIP extension has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RGError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+        L = C.CDLL(LIB_PATH)
+        L.rg_last_error.restype = C.c_char_p
+        L.rg_mesh_build.argtypes = [C.POINTER(rg_mesh_desc), C.POINTER(_vp)]
+        L.rg_mesh_get_info.argtypes = [_vp, C.POINTER(rg_mesh_info)]
+        L.rg_mesh_free.argtypes = [_vp]
+        L.rg_mesh_free.restype = None
+        L.rg_geom_precompute.argtypes = [_vp, C.c_int32, C.c_int32, _vp, C.POINTER(_vp)]
+        L.rg_geom_precompute_host.argtypes = [_vp, C.c_int32, C.POINTER(_vp)]
+        L.rg_geom_free.argtypes = [_vp]
+        L.rg_geom_free.restype = None
+        L.rg_geom_zone_data.argtypes = [_vp, _vp, _vp]
+        L.rg_geom_face_data.argtypes = [_vp, _vp, _vp, _vp]
+        L.rg_geom_edge_data.argtypes = [_vp, _vp, _vp]
+        L.rg_step.argtypes = [_vp, C.POINTER(rg_step_params), _vp, _vp, _vp, _vp, _vp]
+        L.rg_step_fluxes.argtypes = [_vp, _vp, _vp, _vp]
+        L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
+        L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
+        for name in ("rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
+                     "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
+                     "rg_cfl_dt", "rg_init_alfven"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != RG_OK:
+        raise RGError(f"{what} failed with status {status}: {lib().rg_last_error().decode()}")
+
+
+# ------------------------------------------------------------------ C-ABI names
+def rg_mesh_build(n_ang, n_rad, r_in=1.0, r_out=2.0, map_order=2, n_ghost=3):
+    d = rg_mesh_desc(n_ang, n_rad, r_in, r_out, 0, map_order, n_ghost)
+    h = _vp()
+    check(lib().rg_mesh_build(C.byref(d), C.byref(h)), "rg_mesh_build")
+    return h
+
+
+def rg_mesh_get_info(mesh):
+    info = rg_mesh_info()
+    check(lib().rg_mesh_get_info(mesh, C.byref(info)), "rg_mesh_get_info")
+    return {n: getattr(info, n) for n, _ in rg_mesh_info._fields_}
+
+
+def rg_mesh_free(mesh):
+    lib().rg_mesh_free(mesh)
+
+
+def rg_geom_precompute(mesh, order, mode=RG_MODE_FP64, stream=0):
+    h = _vp()
+    check(lib().rg_geom_precompute(mesh, order, mode, _vp(stream), C.byref(h)), "rg_geom_precompute")
+    return h
+
+
+def rg_geom_precompute_host(mesh, order):
+    h = _vp()
+    check(lib().rg_geom_precompute_host(mesh, order, C.byref(h)), "rg_geom_precompute_host")
+    return h
+
+
+def rg_geom_free(geom):
+    lib().rg_geom_free(geom)
+
+
+def rg_geom_zone_data(geom, centroid_ptr, volume_ptr):
+    check(lib().rg_geom_zone_data(geom, _vp(centroid_ptr), _vp(volume_ptr)), "rg_geom_zone_data")
+
+
+def rg_geom_face_data(geom, center_ptr, normal_ptr, area_ptr):
+    check(lib().rg_geom_face_data(geom, _vp(center_ptr), _vp(normal_ptr), _vp(area_ptr)), "rg_geom_face_data")
+
+
+def rg_geom_edge_data(geom, mid_ptr, tan_ptr):
+    check(lib().rg_geom_edge_data(geom, _vp(mid_ptr), _vp(tan_ptr)), "rg_geom_edge_data")
+
+
+def rg_step(geom, params: rg_step_params, U_ptr, Bf_ptr, Uo_ptr, Bfo_ptr, stream):
+    check(lib().rg_step(geom, C.byref(params), _vp(U_ptr), _vp(Bf_ptr), _vp(Uo_ptr), _vp(Bfo_ptr), _vp(stream)),
+          "rg_step")
+    return params
+
+
+def rg_step_fluxes(geom, Phi_ptr, Gam_ptr, stream):
+    check(lib().rg_step_fluxes(geom, _vp(Phi_ptr), _vp(Gam_ptr), _vp(stream)), "rg_step_fluxes")
+
+
+def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
+    out = C.c_double(0.0)
+    check(lib().rg_cfl_dt(geom, _vp(U_ptr), gamma, cfl, _vp(stream), C.byref(out)), "rg_cfl_dt")
+    return out.value
+
+
+def rg_init_alfven(geom, frame_ptr, rho, p, B0, dB, wavelength, gamma, t, noise_ptr, noise_amp, U_ptr, Bf_ptr):
+    check(lib().rg_init_alfven(geom, _vp(frame_ptr), rho, p, B0, dB, wavelength, gamma, t, _vp(noise_ptr),
+                               noise_amp, _vp(U_ptr), _vp(Bf_ptr)), "rg_init_alfven")

@@ -1,0 +1,368 @@
+// C-ABI of the rg library: argument checking, host precompute orchestration,
+// device upload and the step entry points.  No exception crosses this file.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rg_geom_host.hpp"
+
+namespace rg {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" const char *rg_last_error(void) { return g_err.c_str(); }
+
+extern "C" rg_status rg_mesh_build(const rg_mesh_desc *desc, rg_mesh **out)
+{
+    if (!desc || !out) { set_error("null argument"); return RG_EINVAL; }
+    *out = nullptr;
+    if (desc->n_rad < 1 || !(desc->r_in > 0) || !(desc->r_out > desc->r_in) || desc->radial != 0 ||
+        desc->map_order < 2 || desc->map_order > 3 || desc->n_ghost < 0 || desc->n_ang < 2) {
+        set_error("invalid mesh description");
+        return RG_EINVAL;
+    }
+    rg_mesh *m = new (std::nothrow) rg_mesh;
+    if (!m) { set_error("out of host memory"); return RG_ENOMEM; }
+    try {
+        if (!build_mesh(*desc, m->m)) {
+            delete m;
+            return RG_ENOTSUP;
+        }
+    } catch (const std::bad_alloc &) {
+        delete m;
+        set_error("out of host memory");
+        return RG_ENOMEM;
+    }
+    *out = m;
+    return RG_OK;
+}
+
+extern "C" rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info)
+{
+    if (!mesh || !info) { set_error("null argument"); return RG_EINVAL; }
+    const Mesh &m = mesh->m;
+    info->n_ang = m.N;
+    info->n_rad = m.Nr;
+    info->n_ghost = m.g;
+    info->n_shells = m.K;
+    info->n_columns = m.ncol;
+    info->n_zones = m.nzones;
+    info->n_faces = m.nfaces;
+    info->n_radial_faces = m.nrf;
+    info->n_edges = m.nedges;
+    info->n_radial_edges = m.nre;
+    info->n_vertices = m.nv;
+    info->n_angular_edges = m.nae;
+    return RG_OK;
+}
+
+extern "C" void rg_mesh_free(rg_mesh *mesh) { delete mesh; }
+
+namespace {
+
+template <typename T>
+bool upload(rg_geom *g, const std::vector<T> &h, const T **dst)
+{
+    void *p = nullptr;
+    size_t bytes = std::max<size_t>(sizeof(T), h.size() * sizeof(T));
+    if (hipMalloc(&p, bytes) != hipSuccess) return false;
+    g->allocations.push_back(p);
+    if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return false;
+    *dst = static_cast<const T *>(p);
+    return true;
+}
+
+bool alloc_zero(rg_geom *g, size_t n, double **dst)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(8, n * sizeof(double))) != hipSuccess) return false;
+    g->allocations.push_back(p);
+    if (hipMemset(p, 0, n * sizeof(double)) != hipSuccess) return false;
+    *dst = static_cast<double *>(p);
+    return true;
+}
+
+void free_geom(rg_geom *g)
+{
+    if (!g) return;
+    for (void *p : g->allocations) (void)hipFree(p);
+    delete g;
+}
+
+}  // namespace
+
+static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bool device, rg_geom **out)
+{
+    if (!mesh || !out) { set_error("null argument"); return RG_EINVAL; }
+    *out = nullptr;
+    if (order != 3 && order != 4) { set_error("order must be 3 or 4"); return RG_ENOTSUP; }
+    if (mode != RG_MODE_FP64 && mode != RG_MODE_FP32) { set_error("unknown precision mode"); return RG_ENOTSUP; }
+    const Mesh &m = mesh->m;
+    if (m.g < order - 1) { set_error("n_ghost must be at least order - 1"); return RG_EINVAL; }
+    rg_geom *g = new (std::nothrow) rg_geom;
+    if (!g) { set_error("out of host memory"); return RG_ENOMEM; }
+    g->mesh = mesh;
+    g->mode = mode;
+    RefEl &r = g->ref;
+    HostGeom hg;
+    try {
+        if (!build_refel(order, r)) { set_error("reference element construction failed"); free_geom(g); return RG_ESINGULAR; }
+        const int ncol = m.ncol, N = r.N, NC = r.NC, NS = r.NS, Q = r.Q;
+        std::vector<ColData> cols(ncol);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int c = 0; c < ncol; c++) column_pass1(m, r, c, cols[c]);
+
+        hg.stm.assign((size_t)ncol * NS, -1);
+        hg.stn.assign(ncol, 0);
+        hg.Pl.assign((size_t)ncol * NC * NS, 0.0);
+        hg.Ps.assign((size_t)ncol * 7 * 18, 0.0);
+        hg.Qs.assign((size_t)ncol * NC * NC, 0.0);
+        hg.Ev.assign((size_t)ncol * N * NC, 0.0);
+        hg.Mb.assign((size_t)ncol * r.NOUTB * r.NIN, 0.0);
+        hg.nJ.assign((size_t)ncol * N, 0.0);
+        hg.nM.assign((size_t)ncol * N * 9, 0.0);
+        hg.fevR.assign((size_t)ncol * 2 * Q * NC, 0.0);
+        hg.fnR.assign((size_t)ncol * Q * 3, 0.0);
+        hg.fwR.assign((size_t)ncol * Q, 0.0);
+        hg.dins.assign(ncol, 0.0);
+        hg.col_ae.assign((size_t)ncol * 4, 0);
+        hg.col_side.assign((size_t)ncol * 4, 0);
+        hg.col_perm.assign((size_t)ncol * 4 * Q, 0);
+        hg.col_v.assign((size_t)ncol * 4, 0);
+        hg.col_slot.assign((size_t)ncol * 12, 0);
+        hg.col_rev.assign((size_t)ncol * 12, 0);
+        hg.col_sgn.assign((size_t)ncol * 4, 0);
+        const int nae = m.nae, nv = m.nv;
+        hg.fevA.assign((size_t)nae * 2 * Q * NC, 0.0);
+        hg.fnA.assign((size_t)nae * Q * 3, 0.0);
+        hg.fwA.assign((size_t)nae * Q, 0.0);
+        hg.aeF.assign((size_t)nae * 27, 0.0);
+        hg.aeW.assign((size_t)nae * 3, 0.0);
+        hg.ae_rs.assign(nae, 0);
+        hg.vF.assign((size_t)nv * 9, 0.0);
+        hg.vN3.assign((size_t)nv * 9, 0.0);
+        hg.emid_ae.assign((size_t)nae * 3, 0.0);
+        hg.etan_ae.assign((size_t)nae * 3, 0.0);
+        hg.fcen_ae.assign((size_t)nae * 3, 0.0);
+        hg.fnrm_ae.assign((size_t)nae * 3, 0.0);
+        hg.farea_ae.assign(nae, 0.0);
+
+        int bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : bad)
+        for (int c = 0; c < ncol; c++)
+            if (!column_pass2(m, r, cols, c, hg)) bad++;
+        if (bad) { free_geom(g); return RG_ESINGULAR; }
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int ae = 0; ae < nae; ae++) angular_edge_pass(m, r, cols, ae, hg);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int v = 0; v < nv; v++) vertex_pass(m, r, cols, v, hg);
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncol; c++) column_pass4(m, hg, c, hg);
+
+        // per-zone, per-face scaled quantities and query copies
+        const int K = m.K;
+        std::vector<double> zscale(K + 1);
+        for (int k = 0; k <= K; k++) zscale[k] = m.radius[k] / m.radius[0];
+        const int64_t Z = m.nzones, NF = m.nfaces, NE = m.nedges;
+        std::vector<double> vol(Z), area(NF);
+        g->zcen.assign(Z * 3, 0.0);
+        g->zvol.assign(Z, 0.0);
+        g->fcen.assign(NF * 3, 0.0);
+        g->fnrm.assign(NF * 3, 0.0);
+        g->farea.assign(NF, 0.0);
+        g->emid.assign(NE * 3, 0.0);
+        g->etan.assign(NE * 3, 0.0);
+        g->snode.assign((size_t)ncol * 48, 0.0);
+        g->ae_rs_host = hg.ae_rs;
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncol; c++) {
+            const ColData &cd = cols[c];
+            std::memcpy(&g->snode[(size_t)c * 48], cd.sn, sizeof(cd.sn));
+            for (int k = 0; k < K; k++) {
+                int64_t z = (int64_t)c * K + k;
+                double s = zscale[k];
+                vol[z] = cd.vol * s * s * s;
+                g->zvol[z] = vol[z];
+                for (int i = 0; i < 3; i++) g->zcen[z * 3 + i] = s * cd.cen[i];
+            }
+            for (int kf = 0; kf <= K; kf++) {
+                int64_t f = (int64_t)c * (K + 1) + kf;
+                double s = zscale[kf];
+                area[f] = cd.farea[4] * s * s;
+                g->farea[f] = area[f];
+                for (int i = 0; i < 3; i++) {
+                    g->fcen[f * 3 + i] = s * cd.fcen[4][i];
+                    g->fnrm[f * 3 + i] = -cd.fnbar[4][i];
+                }
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int ae = 0; ae < nae; ae++) {
+            for (int k = 0; k < K; k++) {
+                int64_t f = m.nrf + (int64_t)ae * K + k;
+                double s = zscale[k];
+                area[f] = hg.farea_ae[ae] * s * s;
+                g->farea[f] = area[f];
+                for (int i = 0; i < 3; i++) {
+                    g->fcen[f * 3 + i] = s * hg.fcen_ae[ae * 3 + i];
+                    g->fnrm[f * 3 + i] = hg.fnrm_ae[ae * 3 + i];
+                }
+            }
+            for (int kf = 0; kf <= K; kf++) {
+                int64_t e = m.nre + (int64_t)ae * (K + 1) + kf;
+                for (int i = 0; i < 3; i++) {
+                    g->emid[e * 3 + i] = zscale[kf] * hg.emid_ae[ae * 3 + i];
+                    g->etan[e * 3 + i] = hg.etan_ae[ae * 3 + i];
+                }
+            }
+        }
+        for (int v = 0; v < nv; v++)
+            for (int k = 0; k < K; k++) {
+                int64_t e = (int64_t)v * K + k;
+                double rm = 0.5 * (m.radius[k] + m.radius[k + 1]);
+                for (int i = 0; i < 3; i++) {
+                    g->emid[e * 3 + i] = rm * m.vpos[3 * v + i];
+                    g->etan[e * 3 + i] = m.vpos[3 * v + i];
+                }
+            }
+
+        // derivative matrices in compressed rows (node i, direction d)
+        std::vector<int> dptr(N * 3 + 1, 0), dcol;
+        std::vector<double> dval;
+        for (int i = 0; i < N; i++)
+            for (int d = 0; d < 3; d++) {
+                for (int l = 0; l < N; l++) {
+                    double v = r.D[((size_t)d * N + i) * N + l];
+                    if (v != 0.0) { dcol.push_back(l); dval.push_back(v); }
+                }
+                dptr[i * 3 + d + 1] = (int)dcol.size();
+            }
+        std::vector<double> Rv = r.R, wt = r.wt, radius = m.radius, zs(zscale.begin(), zscale.end() - 1);
+        std::vector<int> vncol = m.v_ncol, aecol = m.ae_col, aev = m.ae_v;
+
+        if (!device) {
+            *out = g;
+            return RG_OK;
+        }
+        DevGeom &d = g->d;
+        d.order = order; d.N = N; d.M = r.M; d.NC = NC; d.NB = r.NB; d.Q = Q; d.NS = NS;
+        d.NIN = r.NIN; d.NOUTB = r.NOUTB; d.NFN = r.NFN; d.NEN = r.NEN;
+        d.Nang = m.N; d.Nr = m.Nr; d.g = m.g; d.K = K; d.ncol = ncol; d.nv = nv; d.nae = nae;
+        d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre;
+        bool ok = upload(g, radius, &d.radius) && upload(g, zs, &d.zscale) && upload(g, Rv, &d.R) &&
+                  upload(g, wt, &d.wt) && upload(g, dptr, &d.dptr) && upload(g, dcol, &d.dcol) &&
+                  upload(g, dval, &d.dval) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
+                  upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, hg.stm, &d.stm) &&
+                  upload(g, hg.Pl, &d.Pl) && upload(g, hg.Ps, &d.Ps) && upload(g, hg.Qs, &d.Qs) &&
+                  upload(g, hg.Ev, &d.Ev) && upload(g, hg.Mb, &d.Mb) && upload(g, hg.nJ, &d.nJ) &&
+                  upload(g, hg.nM, &d.nM) && upload(g, hg.fevR, &d.fevR) && upload(g, hg.fnR, &d.fnR) &&
+                  upload(g, hg.fwR, &d.fwR) && upload(g, hg.col_ae, &d.col_ae) &&
+                  upload(g, hg.col_side, &d.col_side) && upload(g, hg.col_perm, &d.col_perm) &&
+                  upload(g, hg.col_v, &d.col_v) && upload(g, hg.col_slot, &d.col_slot) &&
+                  upload(g, hg.col_rev, &d.col_rev) && upload(g, hg.col_sgn, &d.col_sgn) &&
+                  upload(g, hg.dins, &d.dins) && upload(g, aecol, &d.ae_col) && upload(g, aev, &d.ae_v) &&
+                  upload(g, hg.fevA, &d.fevA) && upload(g, hg.fnA, &d.fnA) && upload(g, hg.fwA, &d.fwA) &&
+                  upload(g, hg.aeF, &d.aeF) && upload(g, hg.aeW, &d.aeW) && upload(g, hg.ae_rs, &d.ae_rs) &&
+                  upload(g, vncol, &d.v_ncol) && upload(g, hg.vF, &d.vF) && upload(g, hg.vN3, &d.vN3) &&
+                  upload(g, vol, &d.vol) && upload(g, area, &d.area);
+        if (!ok) { set_error("device allocation or upload of the geometry failed"); free_geom(g); return RG_ENOMEM; }
+        ok = alloc_zero(g, (size_t)NVAR * NC * Z, &g->wcoef) && alloc_zero(g, (size_t)Q * NF, &g->bnod) &&
+             alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &g->etr) &&
+             alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
+             alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red);
+        if (!ok) { set_error("device allocation of the step work buffers failed"); free_geom(g); return RG_ENOMEM; }
+    } catch (const std::bad_alloc &) {
+        set_error("out of host memory");
+        free_geom(g);
+        return RG_ENOMEM;
+    }
+    *out = g;
+    return RG_OK;
+}
+
+extern "C" rg_status rg_geom_precompute(const rg_mesh *mesh, int32_t order, int32_t mode, void *stream, rg_geom **out)
+{
+    (void)stream;
+    return precompute(mesh, order, mode, true, out);
+}
+
+extern "C" rg_status rg_geom_precompute_host(const rg_mesh *mesh, int32_t order, rg_geom **out)
+{
+    return precompute(mesh, order, RG_MODE_FP64, false, out);
+}
+
+extern "C" void rg_geom_free(rg_geom *geom) { free_geom(geom); }
+
+extern "C" rg_status rg_geom_zone_data(const rg_geom *g, double *centroid, double *volume)
+{
+    if (!g) { set_error("null geometry"); return RG_EINVAL; }
+    if (centroid) std::memcpy(centroid, g->zcen.data(), g->zcen.size() * sizeof(double));
+    if (volume) std::memcpy(volume, g->zvol.data(), g->zvol.size() * sizeof(double));
+    return RG_OK;
+}
+
+extern "C" rg_status rg_geom_face_data(const rg_geom *g, double *center, double *normal, double *area)
+{
+    if (!g) { set_error("null geometry"); return RG_EINVAL; }
+    if (center) std::memcpy(center, g->fcen.data(), g->fcen.size() * sizeof(double));
+    if (normal) std::memcpy(normal, g->fnrm.data(), g->fnrm.size() * sizeof(double));
+    if (area) std::memcpy(area, g->farea.data(), g->farea.size() * sizeof(double));
+    return RG_OK;
+}
+
+extern "C" rg_status rg_geom_edge_data(const rg_geom *g, double *midpoint, double *tangent)
+{
+    if (!g) { set_error("null geometry"); return RG_EINVAL; }
+    if (midpoint) std::memcpy(midpoint, g->emid.data(), g->emid.size() * sizeof(double));
+    if (tangent) std::memcpy(tangent, g->etan.data(), g->etan.size() * sizeof(double));
+    return RG_OK;
+}
+
+extern "C" rg_status rg_step(const rg_geom *geom, rg_step_params *params, const double *U, const double *Bf,
+                             double *U_out, double *Bf_out, void *stream)
+{
+    if (!geom || !params || !U || !Bf || !U_out || !Bf_out) { set_error("null argument"); return RG_EINVAL; }
+    if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0) {
+        set_error("invalid step parameters");
+        return RG_EINVAL;
+    }
+    rg_geom *g = const_cast<rg_geom *>(geom);
+    if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
+    if (!(params->dt > 0.0)) {
+        if (!(params->cfl > 0.0)) { set_error("dt <= 0 needs cfl > 0"); return RG_EINVAL; }
+        double dt = 0.0;
+        rg_status s = launch_cfl(g, U, params->gamma, params->cfl, stream, &dt);
+        if (s != RG_OK) return s;
+        params->dt = dt;
+    }
+    return launch_step(g, *params, U, Bf, U_out, Bf_out, stream);
+}
+
+extern "C" rg_status rg_step_fluxes(const rg_geom *g, double *Phi, double *Gam, void *stream)
+{
+    if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (Phi && hipMemcpyAsync(Phi, g->Phi, sizeof(double) * NVAR * g->d.NF, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        return RG_EDEVICE;
+    }
+    if (Gam && hipMemcpyAsync(Gam, g->Gam, sizeof(double) * g->d.NE, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        return RG_EDEVICE;
+    }
+    return RG_OK;
+}
+
+extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
+{
+    if (!g || !g->d.vol || !U || !dt || !(cfl > 0) || !(gamma > 1)) { set_error("invalid argument"); return RG_EINVAL; }
+    return launch_cfl(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
+}

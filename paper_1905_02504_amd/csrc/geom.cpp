@@ -1,0 +1,742 @@
+// Geometry precompute (Section VI step 1), host FP64, one radial column at a
+// time.  With geometric shells every zone of a column is the column's first
+// (shell-0) zone scaled about the origin by q^k, so every reconstruction and
+// predictor matrix below is built once per column and shared by its K zones
+// (the amortisation of Sections IV.b step 7 and V.b).
+//
+// Per column:
+//  - isoparametric map (eq. 5.2): tensor Lagrange surface of order map_order
+//    through great-circle nodes, linear in the radial direction;
+//  - Gauss cubature: volume, centroid, l0 = |V|^(1/3), moments (eqs. 3.2-3.3);
+//  - WENO-AO: large-stencil least-squares rows by the parallel-axis
+//    expansion of eq. (3.4) generalised to any degree, pseudo-inverses of the
+//    large and of seven small (linear) stencils, quadratic forms of the
+//    smoothness indicators;
+//  - divergence-free B (Section IV.b steps 1-9): the KKT system with the
+//    divergence identities (4.10), face-flux constraints (4.14), closeness
+//    rows (4.3/4.6/4.9) and face nodal rows (4.15), inverted once and fused
+//    with evaluation at the ADER nodes (step 10: the new zone mean);
+//  - ADER nodes: Jacobian and flux metrics (eq. 5.11) in curl form, whose
+//    discrete divergence vanishes so uniform states stay uniform;
+//  - face quadrature (area vectors, eqs. 5.6-5.8) and edge Simpson points.
+#include <cmath>
+#include <cstring>
+
+#include "rg_geom_host.hpp"
+
+namespace rg {
+
+namespace {
+
+inline double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+inline void cross(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+inline void normalize(double *a)
+{
+    double n = std::sqrt(dot(a, a));
+    a[0] /= n; a[1] /= n; a[2] /= n;
+}
+
+void slerp(const double *a, const double *b, double t, double *o)
+{
+    double c[3];
+    cross(a, b, c);
+    double th = std::atan2(std::sqrt(dot(c, c)), dot(a, b));
+    double sa = std::sin((1 - t) * th) / std::sin(th), sb = std::sin(t * th) / std::sin(th);
+    for (int i = 0; i < 3; i++) o[i] = sa * a[i] + sb * b[i];
+}
+
+void gc_meet(const double *p1, const double *p2, const double *q1, const double *q2, const double *hint, double *o)
+{
+    double n1[3], n2[3];
+    cross(p1, p2, n1);
+    cross(q1, q2, n2);
+    cross(n1, n2, o);
+    normalize(o);
+    if (dot(o, hint) < 0) { o[0] = -o[0]; o[1] = -o[1]; o[2] = -o[2]; }
+}
+
+double lag(int mo, int a, double x)
+{
+    double v = 1.0, ta = -0.5 + double(a) / mo;
+    for (int b = 0; b <= mo; b++)
+        if (b != a) {
+            double tb = -0.5 + double(b) / mo;
+            v *= (x - tb) / (ta - tb);
+        }
+    return v;
+}
+
+double dlag(int mo, int a, double x)
+{
+    double s = 0.0, ta = -0.5 + double(a) / mo;
+    for (int b = 0; b <= mo; b++) {
+        if (b == a) continue;
+        double tb = -0.5 + double(b) / mo, v = 1.0 / (ta - tb);
+        for (int c = 0; c <= mo; c++)
+            if (c != a && c != b) {
+                double tc = -0.5 + double(c) / mo;
+                v *= (x - tc) / (ta - tc);
+            }
+        s += v;
+    }
+    return s;
+}
+
+double det3(const double *j)
+{
+    return j[0] * (j[4] * j[8] - j[5] * j[7]) - j[1] * (j[3] * j[8] - j[5] * j[6]) + j[2] * (j[3] * j[7] - j[4] * j[6]);
+}
+
+double binom(int n, int k)
+{
+    double v = 1.0;
+    for (int i = 0; i < k; i++) v = v * (n - i) / (i + 1);
+    return v;
+}
+
+double falling(int a, int b)
+{
+    double v = 1.0;
+    for (int i = 0; i < b; i++) v *= a - i;
+    return v;
+}
+
+}  // namespace
+
+// surface nodes of column c: corners, slerp points on the edges, great-circle
+// intersections inside; node (a, b) at index a + (mo+1) b
+void column_surface_nodes(const Mesh &m, int c, double *sn)
+{
+    const int mo = m.map_order, n1 = mo + 1;
+    const double *v[4];
+    for (int k = 0; k < 4; k++) v[k] = &m.vpos[3 * m.col_v[4 * c + k]];
+    double bot[4][3], top[4][3], lef[4][3], rig[4][3], hint[3];
+    for (int a = 0; a <= mo; a++) {
+        double t = double(a) / mo;
+        if (a == 0) {
+            std::memcpy(bot[a], v[0], 24); std::memcpy(top[a], v[3], 24);
+            std::memcpy(lef[a], v[0], 24); std::memcpy(rig[a], v[1], 24);
+        } else if (a == mo) {
+            std::memcpy(bot[a], v[1], 24); std::memcpy(top[a], v[2], 24);
+            std::memcpy(lef[a], v[3], 24); std::memcpy(rig[a], v[2], 24);
+        } else {
+            slerp(v[0], v[1], t, bot[a]);
+            slerp(v[3], v[2], t, top[a]);
+            slerp(v[0], v[3], t, lef[a]);
+            slerp(v[1], v[2], t, rig[a]);
+        }
+    }
+    for (int i = 0; i < 3; i++) hint[i] = v[0][i] + v[1][i] + v[2][i] + v[3][i];
+    for (int b = 0; b <= mo; b++)
+        for (int a = 0; a <= mo; a++) {
+            double *p = &sn[3 * (a + n1 * b)];
+            if (b == 0) std::memcpy(p, bot[a], 24);
+            else if (b == mo) std::memcpy(p, top[a], 24);
+            else if (a == 0) std::memcpy(p, lef[b], 24);
+            else if (a == mo) std::memcpy(p, rig[b], 24);
+            else gc_meet(bot[a], top[a], lef[b], rig[b], hint, p);
+        }
+}
+
+// map of a zone with surface nodes sn between radii r0 < r1; jac[n*3+d] = dx_n/dxi_d
+void zone_map(int mo, const double *sn, double r0, double r1, const double *xi, double *x, double *jac)
+{
+    const int n1 = mo + 1;
+    double La[4], Lb[4], dLa[4], dLb[4];
+    for (int a = 0; a <= mo; a++) {
+        La[a] = lag(mo, a, xi[0]); Lb[a] = lag(mo, a, xi[1]);
+        dLa[a] = dlag(mo, a, xi[0]); dLb[a] = dlag(mo, a, xi[1]);
+    }
+    double S[3] = {0, 0, 0}, Sa[3] = {0, 0, 0}, Sb[3] = {0, 0, 0};
+    for (int b = 0; b <= mo; b++)
+        for (int a = 0; a <= mo; a++) {
+            const double *p = &sn[3 * (a + n1 * b)];
+            for (int i = 0; i < 3; i++) {
+                S[i] += La[a] * Lb[b] * p[i];
+                Sa[i] += dLa[a] * Lb[b] * p[i];
+                Sb[i] += La[a] * dLb[b] * p[i];
+            }
+        }
+    double R = (0.5 - xi[2]) * r0 + (0.5 + xi[2]) * r1, dR = r1 - r0;
+    for (int i = 0; i < 3; i++) {
+        x[i] = R * S[i];
+        if (jac) {
+            jac[i * 3 + 0] = R * Sa[i];
+            jac[i * 3 + 1] = R * Sb[i];
+            jac[i * 3 + 2] = dR * S[i];
+        }
+    }
+}
+
+int moment_index(int a, int b, int c) { return a * 25 + b * 5 + c; }
+
+// ---------------------------------------------------------------- pass 1
+void column_pass1(const Mesh &m, const RefEl &r, int c, ColData &cd)
+{
+    const int mo = m.map_order, N = r.N, Q = r.Q;
+    column_surface_nodes(m, c, cd.sn);
+    const double r0 = m.radius[0], r1 = m.radius[1];
+    const int na = (r.order == 3) ? 8 : 10, nr = 6;
+    std::vector<double> ax(na), aw(na), rx(nr), rw(nr);
+    gauss_legendre01(na, ax.data(), aw.data());
+    gauss_legendre01(nr, rx.data(), rw.data());
+    std::vector<double> px, pw;
+    px.reserve(3 * na * na * nr);
+    double vol = 0.0, cen[3] = {0, 0, 0};
+    for (int k = 0; k < nr; k++)
+        for (int j = 0; j < na; j++)
+            for (int i = 0; i < na; i++) {
+                double xi[3] = {ax[i] - 0.5, ax[j] - 0.5, rx[k] - 0.5}, x[3], jac[9];
+                zone_map(mo, cd.sn, r0, r1, xi, x, jac);
+                double w = aw[i] * aw[j] * rw[k] * det3(jac);
+                vol += w;
+                for (int d = 0; d < 3; d++) cen[d] += w * x[d];
+                px.insert(px.end(), x, x + 3);
+                pw.push_back(w);
+            }
+    for (int d = 0; d < 3; d++) cen[d] /= vol;
+    cd.vol = vol;
+    std::memcpy(cd.cen, cen, 24);
+    cd.len = std::cbrt(vol);
+    std::fill(cd.mom, cd.mom + 125, 0.0);
+    for (size_t p = 0; p < pw.size(); p++) {
+        double X[3];
+        for (int d = 0; d < 3; d++) X[d] = (px[3 * p + d] - cen[d]) / cd.len;
+        double pa[5], pb[5], pc[5];
+        pa[0] = pb[0] = pc[0] = 1.0;
+        for (int e = 1; e < 5; e++) { pa[e] = pa[e - 1] * X[0]; pb[e] = pb[e - 1] * X[1]; pc[e] = pc[e - 1] * X[2]; }
+        for (int a = 0; a < 5; a++)
+            for (int b = 0; a + b < 5; b++)
+                for (int cc = 0; a + b + cc < 5; cc++) cd.mom[moment_index(a, b, cc)] += pw[p] * pa[a] * pb[b] * pc[cc];
+    }
+    for (int i = 0; i < 125; i++) cd.mom[i] /= vol;
+
+    // faces of the shell-0 zone: points, outward unit normals, |dA|
+    for (int lf = 0; lf < 6; lf++) {
+        int axis = lf / 2, u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
+        double sg = ((lf & 1) ? 1.0 : -1.0) * (axis == 1 ? -1.0 : 1.0);
+        double A = 0.0, fc[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
+        for (int q = 0; q < Q; q++) {
+            double xi[3], jac[9], hu[3], hv[3], dA[3];
+            face_ref_point(r, lf, q, xi);
+            zone_map(mo, cd.sn, r0, r1, xi, &cd.fx[lf][q][0], jac);
+            for (int i = 0; i < 3; i++) { hu[i] = jac[i * 3 + u]; hv[i] = jac[i * 3 + v]; }
+            cross(hu, hv, dA);
+            double w = r.gw[q % r.Q1] * r.gw[q / r.Q1], a = std::sqrt(dot(dA, dA));
+            for (int i = 0; i < 3; i++) cd.fn[lf][q][i] = sg * dA[i] / a;
+            cd.fdA[lf][q] = w * a;
+            A += w * a;
+            for (int i = 0; i < 3; i++) { fc[i] += w * a * cd.fx[lf][q][i]; nb[i] += w * sg * dA[i]; }
+        }
+        cd.farea[lf] = A;
+        for (int i = 0; i < 3; i++) cd.fcen[lf][i] = fc[i] / A;
+        normalize(nb);
+        std::memcpy(cd.fnbar[lf], nb, 24);
+    }
+    // in-sphere diameter: twice the least centroid-to-face-plane distance
+    double dmin = 1e300;
+    for (int lf = 0; lf < 6; lf++) {
+        double d[3] = {cd.fcen[lf][0] - cen[0], cd.fcen[lf][1] - cen[1], cd.fcen[lf][2] - cen[2]};
+        dmin = std::min(dmin, std::fabs(dot(d, cd.fnbar[lf])));
+    }
+    cd.dins = 2.0 * dmin;
+
+    // ADER nodes: positions, Jacobians, curl-form metrics from the interpolated
+    // products (x_l - c_l) grad_xi x_m
+    cd.nx.resize(3 * N);
+    cd.nJ.resize(N);
+    cd.nM.resize(9 * N);
+    std::vector<double> V(9 * N);
+    for (int i = 0; i < N; i++) {
+        double jac[9];
+        zone_map(mo, cd.sn, r0, r1, r.node[i].data(), &cd.nx[3 * i], jac);
+        cd.nJ[i] = det3(jac);
+        for (int n = 0; n < 3; n++) {
+            int mm = (n + 1) % 3, ll = (n + 2) % 3;
+            for (int j = 0; j < 3; j++) V[i * 9 + n * 3 + j] = (cd.nx[3 * i + ll] - cen[ll]) * jac[mm * 3 + j];
+        }
+    }
+    for (int i = 0; i < N; i++)
+        for (int n = 0; n < 3; n++) {
+            double g[3][3] = {{0}};  // g[j][d] = d/dxi_d of interpolated V_j
+            for (int l = 0; l < N; l++)
+                for (int d = 0; d < 3; d++) {
+                    double Dv = r.D[((size_t)d * N + i) * N + l];
+                    if (Dv == 0.0) continue;
+                    for (int j = 0; j < 3; j++) g[j][d] += Dv * V[l * 9 + n * 3 + j];
+                }
+            cd.nM[i * 9 + 0 * 3 + n] = -(g[2][1] - g[1][2]);
+            cd.nM[i * 9 + 1 * 3 + n] = -(g[0][2] - g[2][0]);
+            cd.nM[i * 9 + 2 * 3 + n] = -(g[1][0] - g[0][1]);
+        }
+}
+
+// Taylor-basis value X^e - C_e (constant 1 for e = 0)
+static double tbasis(const double *mom, const std::array<int, 3> &e, const double *X)
+{
+    if (e[0] + e[1] + e[2] == 0) return 1.0;
+    double v = 1.0;
+    for (int d = 0; d < 3; d++)
+        for (int k = 0; k < e[d]; k++) v *= X[d];
+    return v - mom[moment_index(e[0], e[1], e[2])];
+}
+
+// least-squares pseudo-inverse (A^T A)^-1 A^T of an n x m matrix (n >= m), row-major
+static bool pinv(int n, int m, const std::vector<double> &A, std::vector<double> &P)
+{
+    std::vector<double> G((size_t)m * m, 0.0);
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < m; j++) {
+            double s = 0.0;
+            for (int k = 0; k < n; k++) s += A[(size_t)k * m + i] * A[(size_t)k * m + j];
+            G[(size_t)i * m + j] = s;
+        }
+    std::vector<int> piv;
+    if (!lu_factor(m, G, piv)) return false;
+    P.assign((size_t)m * n, 0.0);
+    std::vector<double> col(m);
+    for (int k = 0; k < n; k++) {
+        for (int i = 0; i < m; i++) col[i] = A[(size_t)k * m + i];
+        lu_solve(m, G, piv, col.data());
+        for (int i = 0; i < m; i++) P[(size_t)i * n + k] = col[i];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------- pass 2
+bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int c, HostGeom &hg)
+{
+    const ColData &cd = cols[c];
+    const int N = r.N, NC = r.NC, NS = r.NS, Q = r.Q, NB = r.NB, p = r.order;
+    const double q = m.q;
+    // ---- stencil: face neighbours first (local faces 0..5), then the rest
+    std::vector<std::pair<int, int>> st;
+    int fnb[4];
+    for (int lf = 0; lf < 4; lf++) {
+        int ae = m.col_ae[4 * c + lf];
+        fnb[lf] = (m.ae_col[2 * ae] == c) ? m.ae_col[2 * ae + 1] : m.ae_col[2 * ae];
+        st.push_back({fnb[lf], 0});
+    }
+    st.push_back({c, -1});
+    st.push_back({c, +1});
+    std::vector<int> vn;  // columns sharing a vertex with c (not c)
+    for (int k = 0; k < 4; k++) {
+        int v = m.col_v[4 * c + k];
+        for (int s = 0; s < m.v_ncol[v]; s++) {
+            int o = m.v_col[4 * v + s];
+            if (o != c && std::find(vn.begin(), vn.end(), o) == vn.end()) vn.push_back(o);
+        }
+    }
+    auto has = [&](int col, int dk) {
+        for (auto &e : st)
+            if (e.first == col && e.second == dk) return true;
+        return false;
+    };
+    for (int o : vn)
+        if (!has(o, 0)) st.push_back({o, 0});
+    for (int dk : {-1, 1})
+        for (int o : vn)
+            if (!has(o, dk)) st.push_back({o, dk});
+    if (p == 4) {
+        for (int dk : {-2, 2}) st.push_back({c, dk});
+        for (int lf = 0; lf < 4; lf++) {
+            int c1 = fnb[lf], ae = m.col_ae[4 * c + lf];
+            int lf1 = (m.ae_col[2 * ae] == c1) ? m.ae_lf[2 * ae] : m.ae_lf[2 * ae + 1];
+            int ae2 = m.col_ae[4 * c1 + (lf1 ^ 1)];
+            int c2 = (m.ae_col[2 * ae2] == c1) ? m.ae_col[2 * ae2 + 1] : m.ae_col[2 * ae2];
+            if (c2 != c && !has(c2, 0)) st.push_back({c2, 0});
+        }
+    }
+    const int ns = (int)st.size();
+    if (ns > NS) { set_error("stencil larger than its slot count"); return false; }
+    for (int j = 0; j < NS; j++)
+        hg.stm[(size_t)c * NS + j] = (j < ns) ? st[j].first * 8 + (st[j].second + 3) : -1;
+    hg.stn[c] = ns;
+
+    // ---- large-stencil rows: average over zone j of zone 0's Taylor basis,
+    // by the parallel-axis expansion with zone j's own moments
+    std::vector<double> A((size_t)ns * NC);
+    for (int j = 0; j < ns; j++) {
+        const ColData &cj = cols[st[j].first];
+        double sc = std::pow(q, st[j].second);
+        double d[3], rho = sc * cj.len / cd.len;
+        for (int i = 0; i < 3; i++) d[i] = (sc * cj.cen[i] - cd.cen[i]) / cd.len;
+        for (int a = 0; a < NC; a++) {
+            const auto &al = r.tex[a];
+            double s = 0.0;
+            for (int b0 = 0; b0 <= al[0]; b0++)
+                for (int b1 = 0; b1 <= al[1]; b1++)
+                    for (int b2 = 0; b2 <= al[2]; b2++) {
+                        double t = binom(al[0], b0) * binom(al[1], b1) * binom(al[2], b2) *
+                                   std::pow(d[0], al[0] - b0) * std::pow(d[1], al[1] - b1) * std::pow(d[2], al[2] - b2) *
+                                   std::pow(rho, b0 + b1 + b2) * cj.mom[moment_index(b0, b1, b2)];
+                        s += t;
+                    }
+            A[(size_t)j * NC + a] = s - cd.mom[moment_index(al[0], al[1], al[2])];
+        }
+    }
+    std::vector<double> P;
+    if (!pinv(ns, NC, A, P)) { set_error("singular large-stencil least squares"); return false; }
+    double *Pl = &hg.Pl[(size_t)c * NC * NS];
+    for (int a = 0; a < NC; a++)
+        for (int j = 0; j < NS; j++) Pl[a * NS + j] = (j < ns) ? P[(size_t)a * ns + j] : 0.0;
+
+    // ---- small stencils on the six face neighbours: central, then one-sided
+    double dface[6][3];
+    for (int j = 0; j < 6; j++) {
+        const ColData &cj = cols[st[j].first];
+        double sc = std::pow(q, st[j].second);
+        for (int i = 0; i < 3; i++) dface[j][i] = (sc * cj.cen[i] - cd.cen[i]) / cd.len;
+    }
+    double *Ps = &hg.Ps[(size_t)c * 7 * 18];
+    for (int s = 0; s < 7; s++) {
+        std::vector<int> mem;
+        for (int j = 0; j < 6; j++)
+            if (s == 0 || j != ((s - 1) ^ 1)) mem.push_back(j);
+        std::vector<double> As(mem.size() * 3), Pss;
+        for (size_t k = 0; k < mem.size(); k++)
+            for (int i = 0; i < 3; i++) As[k * 3 + i] = dface[mem[k]][i];
+        if (!pinv((int)mem.size(), 3, As, Pss)) { set_error("singular small-stencil least squares"); return false; }
+        for (int i = 0; i < 18; i++) Ps[s * 18 + i] = 0.0;
+        for (int i = 0; i < 3; i++)
+            for (size_t k = 0; k < mem.size(); k++) Ps[s * 18 + i * 6 + mem[k]] = Pss[i * mem.size() + k];
+    }
+
+    // ---- smoothness quadratic form: sum over derivative multi-indices of the
+    // zone average of products of derivatives of the Taylor basis
+    double *Qs = &hg.Qs[(size_t)c * NC * NC];
+    for (int a = 0; a < NC; a++)
+        for (int b = 0; b < NC; b++) {
+            const auto &ea = r.tex[a], &eb = r.tex[b];
+            double s = 0.0;
+            for (const auto &be : r.tex) {
+                if (be[0] > ea[0] || be[1] > ea[1] || be[2] > ea[2]) continue;
+                if (be[0] > eb[0] || be[1] > eb[1] || be[2] > eb[2]) continue;
+                double f = 1.0;
+                for (int d = 0; d < 3; d++) f *= falling(ea[d], be[d]) * falling(eb[d], be[d]);
+                s += f * cd.mom[moment_index(ea[0] + eb[0] - 2 * be[0], ea[1] + eb[1] - 2 * be[1], ea[2] + eb[2] - 2 * be[2])];
+            }
+            Qs[a * NC + b] = s;
+        }
+
+    // ---- Taylor basis at the ADER nodes
+    double *Ev = &hg.Ev[(size_t)c * N * NC];
+    std::vector<double> Xn(3 * N);
+    for (int i = 0; i < N; i++) {
+        for (int d = 0; d < 3; d++) Xn[3 * i + d] = (cd.nx[3 * i + d] - cd.cen[d]) / cd.len;
+        for (int a = 0; a < NC; a++) Ev[i * NC + a] = tbasis(cd.mom, r.tex[a], &Xn[3 * i]);
+    }
+    std::memcpy(&hg.nJ[(size_t)c * N], cd.nJ.data(), sizeof(double) * N);
+    std::memcpy(&hg.nM[(size_t)c * N * 9], cd.nM.data(), sizeof(double) * N * 9);
+    hg.dins[c] = cd.dins;
+
+    // ---- radial faces: canonical data = bottom face of the shell-0 zone, normal +r
+    for (int qq = 0; qq < Q; qq++) {
+        for (int i = 0; i < 3; i++) hg.fnR[((size_t)c * Q + qq) * 3 + i] = -cd.fn[4][qq][i];
+        hg.fwR[(size_t)c * Q + qq] = cd.fdA[4][qq] / cd.farea[4];
+        double Xb[3], Xa[3];
+        for (int d = 0; d < 3; d++) {
+            Xa[d] = (cd.fx[4][qq][d] - cd.cen[d]) / cd.len;        // zone above (its bottom face)
+            Xb[d] = (q * cd.fx[4][qq][d] - cd.cen[d]) / cd.len;    // zone below (its top face)
+        }
+        for (int a = 0; a < NC; a++) {
+            hg.fevR[(((size_t)c * 2 + 0) * Q + qq) * NC + a] = tbasis(cd.mom, r.tex[a], Xb);
+            hg.fevR[(((size_t)c * 2 + 1) * Q + qq) * NC + a] = tbasis(cd.mom, r.tex[a], Xa);
+        }
+    }
+
+    // ---- face point order and orientation relative to the canonical faces
+    int perm[6][9], sgn[6];
+    for (int lf = 0; lf < 6; lf++)
+        for (int qq = 0; qq < Q; qq++) perm[lf][qq] = qq;
+    sgn[4] = -1;
+    sgn[5] = +1;
+    for (int lf = 0; lf < 4; lf++) {
+        int ae = m.col_ae[4 * c + lf];
+        int side = (m.ae_col[2 * ae] == c) ? 0 : 1;
+        hg.col_ae[4 * c + lf] = ae;
+        hg.col_side[4 * c + lf] = side;
+        sgn[lf] = side == 0 ? 1 : -1;
+        if (side == 1) {
+            const ColData &c0 = cols[m.ae_col[2 * ae]];
+            int lf0 = m.ae_lf[2 * ae];
+            for (int qq = 0; qq < Q; qq++) {
+                int best = -1;
+                double bd = 1e300;
+                for (int q0 = 0; q0 < Q; q0++) {
+                    double dd = 0;
+                    for (int i = 0; i < 3; i++) dd += (cd.fx[lf][qq][i] - c0.fx[lf0][q0][i]) * (cd.fx[lf][qq][i] - c0.fx[lf0][q0][i]);
+                    if (dd < bd) { bd = dd; best = q0; }
+                }
+                perm[lf][qq] = best;
+            }
+        }
+        for (int qq = 0; qq < Q; qq++) hg.col_perm[((size_t)c * 4 + lf) * Q + qq] = perm[lf][qq];
+    }
+
+    // ---- divergence-free B: KKT system, inverted for all inputs at once
+    const int nu = 3 * NB, nrow = nu + 6 * Q, ndiv = NC, ncon = ndiv + 6, NIN = r.NIN;
+    const int inB = 0, inF = 3 * (NC + 1), inM = 3 * (NC + 1) + 6 * Q;
+    std::vector<double> Am((size_t)nrow * nu, 0.0), Sb((size_t)nrow * NIN, 0.0);
+    std::vector<double> Cm((size_t)ncon * nu, 0.0), Sd((size_t)ncon * NIN, 0.0);
+    for (int comp = 0; comp < 3; comp++)
+        for (int k = 0; k < NB; k++) {
+            int row = comp * NB + k;
+            Am[(size_t)row * nu + row] = 1.0;
+            const auto &e = r.bex[comp][k];
+            int deg = e[0] + e[1] + e[2];
+            if (deg == 0) Sb[(size_t)row * NIN + inB + comp * (NC + 1)] = 1.0;
+            else if (deg <= p - 1) {
+                int a = 0;
+                while (r.tex[a] != e) a++;
+                Sb[(size_t)row * NIN + inB + comp * (NC + 1) + 1 + a] = 1.0;
+            }
+        }
+    for (int lf = 0; lf < 6; lf++)
+        for (int qq = 0; qq < Q; qq++) {
+            int row = nu + lf * Q + qq;
+            double X[3], wq = cd.fdA[lf][qq] / cd.farea[lf];
+            for (int d = 0; d < 3; d++) X[d] = (cd.fx[lf][qq][d] - cd.cen[d]) / cd.len;
+            for (int comp = 0; comp < 3; comp++)
+                for (int k = 0; k < NB; k++) {
+                    double val = cd.fn[lf][qq][comp] * tbasis(cd.mom, r.bex[comp][k], X);
+                    Am[(size_t)row * nu + comp * NB + k] = val;
+                    Cm[(size_t)(ndiv + lf) * nu + comp * NB + k] += wq * val;
+                }
+            Sb[(size_t)row * NIN + inF + lf * Q + perm[lf][qq]] = sgn[lf];
+        }
+    for (int lf = 0; lf < 6; lf++) Sd[(size_t)(ndiv + lf) * NIN + inM + lf] = sgn[lf];
+    for (int i = 0; i < ndiv; i++)
+        for (int comp = 0; comp < 3; comp++) {
+            std::array<int, 3> t = r.tex[i];
+            t[comp] += 1;
+            for (int k = 0; k < NB; k++)
+                if (r.bex[comp][k] == t) Cm[(size_t)i * nu + comp * NB + k] += t[comp];
+        }
+    const int nk = nu + ncon;
+    std::vector<double> K((size_t)nk * nk, 0.0), rhs((size_t)nk * NIN, 0.0);
+    for (int i = 0; i < nu; i++)
+        for (int j = 0; j < nu; j++) {
+            double s = 0.0;
+            for (int k = 0; k < nrow; k++) s += Am[(size_t)k * nu + i] * Am[(size_t)k * nu + j];
+            K[(size_t)i * nk + j] = 2.0 * s;
+        }
+    for (int i = 0; i < ncon; i++)
+        for (int j = 0; j < nu; j++) {
+            K[(size_t)(nu + i) * nk + j] = Cm[(size_t)i * nu + j];
+            K[(size_t)j * nk + nu + i] = Cm[(size_t)i * nu + j];
+        }
+    for (int i = 0; i < nu; i++)
+        for (int j = 0; j < NIN; j++) {
+            double s = 0.0;
+            for (int k = 0; k < nrow; k++) s += Am[(size_t)k * nu + i] * Sb[(size_t)k * NIN + j];
+            rhs[(size_t)i * NIN + j] = 2.0 * s;
+        }
+    for (int i = 0; i < ncon; i++)
+        for (int j = 0; j < NIN; j++) rhs[(size_t)(nu + i) * NIN + j] = Sd[(size_t)i * NIN + j];
+    std::vector<int> piv;
+    if (!lu_factor(nk, K, piv)) { set_error("singular divergence-free KKT system"); return false; }
+    std::vector<double> G((size_t)nu * NIN), col(nk);
+    for (int j = 0; j < NIN; j++) {
+        for (int i = 0; i < nk; i++) col[i] = rhs[(size_t)i * NIN + j];
+        lu_solve(nk, K, piv, col.data());
+        for (int i = 0; i < nu; i++) G[(size_t)i * NIN + j] = col[i];
+    }
+    // fused map: B at the ADER nodes, then the three new zone means
+    double *Mb = &hg.Mb[(size_t)c * r.NOUTB * NIN];
+    for (int comp = 0; comp < 3; comp++)
+        for (int i = 0; i < N; i++) {
+            double *row = &Mb[(size_t)(comp * N + i) * NIN];
+            for (int j = 0; j < NIN; j++) row[j] = 0.0;
+            for (int k = 0; k < NB; k++) {
+                double b = tbasis(cd.mom, r.bex[comp][k], &Xn[3 * i]);
+                const double *g = &G[(size_t)(comp * NB + k) * NIN];
+                for (int j = 0; j < NIN; j++) row[j] += b * g[j];
+            }
+        }
+    for (int comp = 0; comp < 3; comp++)
+        std::memcpy(&Mb[(size_t)(3 * N + comp) * NIN], &G[(size_t)(comp * NB) * NIN], sizeof(double) * NIN);
+    return true;
+}
+
+// ---------------------------------------------------------------- pass 3: angular edges, vertices
+static void symmetric_frame(const double *u0, const double *w0, const double *t, double *e1, double *e2)
+{
+    double u[3], w[3], b[3], bp[3];
+    double pu = dot(u0, t), pw = dot(w0, t);
+    for (int i = 0; i < 3; i++) { u[i] = u0[i] - pu * t[i]; w[i] = w0[i] - pw * t[i]; }
+    normalize(u);
+    normalize(w);
+    for (int i = 0; i < 3; i++) b[i] = u[i] + w[i];
+    normalize(b);
+    cross(t, b, bp);
+    const double h = std::sqrt(0.5);
+    for (int i = 0; i < 3; i++) { e1[i] = h * (b[i] - bp[i]); e2[i] = h * (b[i] + bp[i]); }
+}
+
+// local face (0..3) -> local edge on the zeta- side, and its (from, to) corners
+static const int LF_EDGE[4] = {4, 5, 0, 1};
+static const int LF_FROMTO[4][2] = {{0, 3}, {1, 2}, {0, 1}, {3, 2}};
+
+void angular_edge_pass(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int ae, HostGeom &hg)
+{
+    const int Q = r.Q, NC = r.NC;
+    const int c0 = m.ae_col[2 * ae], c1 = m.ae_col[2 * ae + 1], lf0 = m.ae_lf[2 * ae];
+    const ColData &d0 = cols[c0], &d1 = cols[c1];
+    // canonical face = local face lf0 of side 0, outward from side 0
+    for (int qq = 0; qq < Q; qq++) {
+        for (int i = 0; i < 3; i++) hg.fnA[((size_t)ae * Q + qq) * 3 + i] = d0.fn[lf0][qq][i];
+        hg.fwA[(size_t)ae * Q + qq] = d0.fdA[lf0][qq] / d0.farea[lf0];
+        double X0[3], X1[3];
+        for (int d = 0; d < 3; d++) {
+            X0[d] = (d0.fx[lf0][qq][d] - d0.cen[d]) / d0.len;
+            X1[d] = (d0.fx[lf0][qq][d] - d1.cen[d]) / d1.len;
+        }
+        for (int a = 0; a < NC; a++) {
+            hg.fevA[(((size_t)ae * 2 + 0) * Q + qq) * NC + a] = tbasis(d0.mom, r.tex[a], X0);
+            hg.fevA[(((size_t)ae * 2 + 1) * Q + qq) * NC + a] = tbasis(d1.mom, r.tex[a], X1);
+        }
+    }
+    // edge curve at interface 0 from side 0's map, canonical direction a -> b
+    int le = LF_EDGE[lf0];
+    int from = m.col_v[4 * c0 + LF_FROMTO[lf0][0]];
+    bool rev = (from != m.ae_v[2 * ae]);
+    const double simpson[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    double xm[3], tm[3];
+    double pts[3][3], tan[3][3];
+    for (int s = 0; s < 3; s++) {
+        double xi[3], jac[9];
+        edge_ref_point(le, rev ? 1.0 - 0.5 * s : 0.5 * s, xi);
+        zone_map(m.map_order, d0.sn, m.radius[0], m.radius[1], xi, pts[s], jac);
+        for (int i = 0; i < 3; i++) tan[s][i] = (rev ? -1.0 : 1.0) * jac[i * 3 + le / 4];
+        double a = std::sqrt(dot(tan[s], tan[s]));
+        hg.aeW[(size_t)ae * 3 + s] = simpson[s] * a;
+        for (int i = 0; i < 3; i++) tan[s][i] /= a;
+    }
+    std::memcpy(xm, pts[1], 24);
+    std::memcpy(tm, tan[1], 24);
+    // which column lies to the right (t x r_hat)
+    double rh[3] = {xm[0], xm[1], xm[2]}, mh[3];
+    normalize(rh);
+    cross(tm, rh, mh);
+    double dc[3] = {d1.cen[0] - xm[0], d1.cen[1] - xm[1], d1.cen[2] - xm[2]};
+    bool side1_right = dot(dc, mh) > 0;
+    hg.ae_rs[ae] = side1_right ? 1 : -1;
+    const ColData &L = side1_right ? d0 : d1, &Rr = side1_right ? d1 : d0;
+    // zones about the edge at interface 1, counter-clockwise: (L,0) (L,1) (R,1) (R,0)
+    const double q = m.q;
+    double cz[4][3];
+    for (int i = 0; i < 3; i++) {
+        cz[0][i] = L.cen[i];
+        cz[1][i] = q * L.cen[i];
+        cz[2][i] = q * Rr.cen[i];
+        cz[3][i] = Rr.cen[i];
+    }
+    double u[3], w[3];
+    for (int i = 0; i < 3; i++) {
+        u[i] = cz[1][i] + cz[2][i] - cz[0][i] - cz[3][i];
+        w[i] = cz[2][i] + cz[3][i] - cz[0][i] - cz[1][i];
+    }
+    for (int s = 0; s < 3; s++) {
+        double *F = &hg.aeF[((size_t)ae * 3 + s) * 9];
+        symmetric_frame(u, w, tan[s], F, F + 3);
+        std::memcpy(F + 6, tan[s], 24);
+    }
+    std::memcpy(&hg.emid_ae[(size_t)ae * 3], xm, 24);
+    std::memcpy(&hg.etan_ae[(size_t)ae * 3], tm, 24);
+    // face centre / normal of the canonical angular face at shell 0
+    std::memcpy(&hg.fcen_ae[(size_t)ae * 3], d0.fcen[lf0], 24);
+    std::memcpy(&hg.fnrm_ae[(size_t)ae * 3], d0.fnbar[lf0], 24);
+    hg.farea_ae[ae] = d0.farea[lf0];
+}
+
+void vertex_pass(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int v, HostGeom &hg)
+{
+    (void)r;
+    const double *t = &m.vpos[3 * v];
+    int n = m.v_ncol[v];
+    double *F = &hg.vF[(size_t)v * 9];
+    std::fill(F, F + 9, 0.0);
+    std::memcpy(F + 6, t, 24);
+    std::fill(&hg.vN3[(size_t)v * 9], &hg.vN3[(size_t)v * 9] + 9, 0.0);
+    if (n == 4) {
+        const double *c[4];
+        for (int s = 0; s < 4; s++) c[s] = cols[m.v_col[4 * v + s]].cen;
+        double u[3], w[3];
+        for (int i = 0; i < 3; i++) {
+            u[i] = c[1][i] + c[2][i] - c[0][i] - c[3][i];
+            w[i] = c[2][i] + c[3][i] - c[0][i] - c[1][i];
+        }
+        symmetric_frame(u, w, t, F, F + 3);
+    } else {
+        // normals of the angular faces between consecutive columns, along the radial line
+        for (int s = 0; s < n; s++) {
+            int ca = m.v_col[4 * v + s], cb = m.v_col[4 * v + (s + 1) % n];
+            int ae = -1, lfa = -1;
+            for (int lf = 0; lf < 4; lf++) {
+                int e = m.col_ae[4 * ca + lf];
+                int other = (m.ae_col[2 * e] == ca) ? m.ae_col[2 * e + 1] : m.ae_col[2 * e];
+                if (other == cb) { ae = e; lfa = lf; }
+            }
+            (void)ae;
+            // tangent of that face's angular edge at the vertex, from column ca's map
+            int le = LF_EDGE[lfa];
+            int cf = m.col_v[4 * ca + LF_FROMTO[lfa][0]];
+            double sv = (cf == v) ? 0.0 : 1.0, xi[3], x[3], jac[9], tg[3], nn[3];
+            edge_ref_point(le, sv, xi);
+            zone_map(m.map_order, cols[ca].sn, m.radius[0], m.radius[1], xi, x, jac);
+            for (int i = 0; i < 3; i++) tg[i] = jac[i * 3 + le / 4];
+            cross(tg, t, nn);
+            normalize(nn);
+            double dc[3];
+            for (int i = 0; i < 3; i++) dc[i] = cols[cb].cen[i] - cols[ca].cen[i];
+            if (dot(nn, dc) < 0)
+                for (int i = 0; i < 3; i++) nn[i] = -nn[i];
+            std::memcpy(&hg.vN3[(size_t)v * 9 + s * 3], nn, 24);
+        }
+    }
+}
+
+// per-column edge bookkeeping: local edge -> slot about the edge, reversal;
+// circulation signs of the angular edges about +r
+void column_pass4(const Mesh &m, const HostGeom &hg, int c, HostGeom &out)
+{
+    // local edges 0..7 are angular (on local faces eta-/eta+/xi-/xi+ at zeta-/zeta+)
+    const int LE_FACE[8] = {2, 3, 2, 3, 0, 1, 0, 1};
+    const int LE_ZUP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
+    for (int le = 0; le < 8; le++) {
+        int lf = LE_FACE[le];
+        int ae = m.col_ae[4 * c + lf];
+        int from = m.col_v[4 * c + LF_FROMTO[lf][0]];
+        int rev = (from != m.ae_v[2 * ae]);
+        bool isRight = (hg.ae_rs[ae] > 0) == (m.ae_col[2 * ae + 1] == c);
+        // zone above the interface for zeta- edges, below it for zeta+ edges
+        int slot = LE_ZUP[le] == 0 ? (isRight ? 2 : 1) : (isRight ? 3 : 0);
+        out.col_slot[(size_t)c * 12 + le] = slot;
+        out.col_rev[(size_t)c * 12 + le] = rev;
+    }
+    const int LE_CORNER[4] = {0, 1, 3, 2};
+    for (int k = 0; k < 4; k++) {
+        int v = m.col_v[4 * c + LE_CORNER[k]];
+        int slot = 0;
+        for (int s = 0; s < m.v_ncol[v]; s++)
+            if (m.v_col[4 * v + s] == c) slot = s;
+        out.col_slot[(size_t)c * 12 + 8 + k] = slot;
+        out.col_rev[(size_t)c * 12 + 8 + k] = 0;
+    }
+    // counter-clockwise traversal v0 -> v1 -> v2 -> v3 about +r
+    const int TRAV[4][2] = {{3, 0}, {1, 2}, {0, 1}, {2, 3}};
+    for (int lf = 0; lf < 4; lf++) {
+        int ae = m.col_ae[4 * c + lf];
+        int from = m.col_v[4 * c + TRAV[lf][0]];
+        out.col_sgn[(size_t)c * 4 + lf] = (from == m.ae_v[2 * ae]) ? 1 : -1;
+    }
+    for (int k = 0; k < 4; k++) out.col_v[(size_t)c * 4 + k] = m.col_v[4 * c + k];
+}
+
+}  // namespace rg

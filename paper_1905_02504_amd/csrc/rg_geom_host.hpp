@@ -1,0 +1,48 @@
+// Host-side geometry precompute: per-column shell-0 data and the flat host
+// arrays that are uploaded to the device.
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "rg_internal.hpp"
+
+namespace rg {
+
+bool build_mesh(const rg_mesh_desc &d, Mesh &m);
+
+struct ColData {
+    double sn[16 * 3];
+    double cen[3], vol = 0, len = 0;
+    double mom[125];
+    double fx[6][9][3], fn[6][9][3], fdA[6][9], farea[6], fcen[6][3], fnbar[6][3];
+    double dins = 0;
+    std::vector<double> nx, nJ, nM;
+};
+
+struct HostGeom {
+    std::vector<int> stm, stn;
+    std::vector<double> Pl, Ps, Qs, Ev, Mb, nJ, nM, fevR, fnR, fwR, dins;
+    std::vector<int> col_ae, col_side, col_perm, col_v, col_slot, col_rev, col_sgn;
+    std::vector<double> fevA, fnA, fwA, aeF, aeW;
+    std::vector<int> ae_rs;
+    std::vector<double> vF, vN3;
+    // query data
+    std::vector<double> emid_ae, etan_ae, fcen_ae, fnrm_ae, farea_ae;
+};
+
+void column_surface_nodes(const Mesh &m, int c, double *sn);
+void zone_map(int mo, const double *sn, double r0, double r1, const double *xi, double *x, double *jac);
+int moment_index(int a, int b, int c);
+void column_pass1(const Mesh &m, const RefEl &r, int c, ColData &cd);
+bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int c, HostGeom &hg);
+void angular_edge_pass(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int ae, HostGeom &hg);
+void vertex_pass(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int v, HostGeom &hg);
+void column_pass4(const Mesh &m, const HostGeom &hg, int c, HostGeom &out);
+
+// device step, implemented in the HIP translation unit
+rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,
+                      double *Bo, void *stream);
+rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt);
+
+}  // namespace rg

@@ -1,0 +1,840 @@
+// Device step of the rg library for gfx950 (FP64).  One launch per stage,
+// all on the caller's stream:
+//   bc_zones / bc_faces : continuative ghost fill (Section VII) into the output state
+//   weno               : WENO-AO in the Taylor basis, one thread per zone (Section III)
+//   face_bnodal        : limited nodal normal B on every face, eqs. (4.11)-(4.12)
+//   predictor          : divergence-free B map (Section IV.b) + ADER-CG Picard
+//                        iteration (Section V.d), one lane per serendipity node,
+//                        then time-averaged traces at face and edge points
+//   face_flux          : HLL at face quadrature points -> face flux integrals
+//   edge_emf           : multidimensional HLL electric field at edge Simpson points
+//   zone_update        : finite-volume update of the eight zone averages
+//   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
+#include <hip/hip_runtime.h>
+
+#include "rg_geom_host.hpp"
+
+namespace rg {
+
+template <int P>
+struct Tr;
+template <>
+struct Tr<3> {
+    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3;
+};
+template <>
+struct Tr<4> {
+    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4;
+};
+
+typedef long long i64;
+
+constexpr double WENO_GAMMA_HI = 0.85;
+constexpr double WENO_EPS = 1e-12;
+
+// ---------------------------------------------------------------- ideal MHD
+__device__ __forceinline__ double dev_pressure(const double *u, double gam)
+{
+    double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    double b2 = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+    return (gam - 1.0) * (u[4] - 0.5 * m2 / u[0] - 0.5 * b2);
+}
+
+// F[d][v]: flux of conserved variable v along Cartesian direction d (eq. 2.2)
+__device__ __forceinline__ void dev_flux(const double *u, double gam, double F[3][8])
+{
+    double ir = 1.0 / u[0];
+    double v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
+    double B0 = u[5], B1 = u[6], B2 = u[7];
+    double p = dev_pressure(u, gam);
+    double pt = p + 0.5 * (B0 * B0 + B1 * B1 + B2 * B2);
+    double vB = v0 * B0 + v1 * B1 + v2 * B2;
+    double v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        F[d][0] = u[1 + d];
+#pragma unroll
+        for (int i = 0; i < 3; i++) F[d][1 + i] = u[1 + d] * v[i] + (d == i ? pt : 0.0) - B[d] * B[i];
+        F[d][4] = (u[4] + pt) * v[d] - B[d] * vB;
+#pragma unroll
+        for (int i = 0; i < 3; i++) F[d][5 + i] = v[d] * B[i] - B[d] * v[i];
+    }
+}
+
+__device__ __forceinline__ double dev_fast(const double *u, double gam, const double *n)
+{
+    double ir = 1.0 / u[0];
+    double a2 = gam * dev_pressure(u, gam) * ir;
+    double b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+    double bn = u[5] * n[0] + u[6] * n[1] + u[7] * n[2];
+    double bn2 = bn * bn * ir, s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * bn2;
+    disc = disc < 0.0 ? 0.0 : disc;
+    return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+// HLL with Davis speeds along unit n (from L to R)
+__device__ __forceinline__ void dev_hll(const double *UL, const double *UR, const double *FL, const double *FR,
+                                        const double *n, double gam, double *Fs)
+{
+    double vL = (UL[1] * n[0] + UL[2] * n[1] + UL[3] * n[2]) / UL[0];
+    double vR = (UR[1] * n[0] + UR[2] * n[1] + UR[3] * n[2]) / UR[0];
+    double cL = dev_fast(UL, gam, n), cR = dev_fast(UR, gam, n);
+    double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
+    if (SL >= 0.0) {
+        for (int v = 0; v < 8; v++) Fs[v] = FL[v];
+    } else if (SR <= 0.0) {
+        for (int v = 0; v < 8; v++) Fs[v] = FR[v];
+    } else {
+        double id = 1.0 / (SR - SL);
+        for (int v = 0; v < 8; v++) Fs[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
+    }
+}
+
+__device__ __forceinline__ double dev_minmod(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return a > 0.0 ? fmin(a, b) : fmax(a, b);
+}
+
+// ---------------------------------------------------------------- boundary fill
+__global__ void bc_zones(DevGeom G, int bc, const double *U, double *Uo)
+{
+    i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= G.Z) return;
+    int k = (int)(z % G.K);
+    i64 src = z;
+    if (bc == 0) {
+        int ks = k < G.g ? G.g : (k > G.g + G.Nr - 1 ? G.g + G.Nr - 1 : k);
+        src = z - k + ks;
+    }
+    for (int v = 0; v < 8; v++) Uo[v * G.Z + z] = U[v * G.Z + src];
+}
+
+__global__ void bc_faces(DevGeom G, int bc, const double *Bf, double *Bo)
+{
+    i64 f = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= G.NF) return;
+    i64 src = f;
+    if (bc == 0) {
+        if (f < G.NRF) {
+            int kf = (int)(f % (G.K + 1));
+            int ks = kf < G.g ? G.g : (kf > G.g + G.Nr ? G.g + G.Nr : kf);
+            src = f - kf + ks;
+        } else {
+            int k = (int)((f - G.NRF) % G.K);
+            int ks = k < G.g ? G.g : (k > G.g + G.Nr - 1 ? G.g + G.Nr - 1 : k);
+            src = f - k + ks;
+        }
+    }
+    Bo[f] = Bf[src];
+}
+
+// ---------------------------------------------------------------- WENO-AO
+// zones of shells g-1 .. g+Nr (interior plus one ghost shell on each side)
+template <int P>
+__global__ __launch_bounds__(256) void weno(DevGeom G, const double *__restrict__ U, double *__restrict__ wc)
+{
+    using T = Tr<P>;
+    const int KR = G.Nr + 2;
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * KR) return;
+    int c = (int)(t / KR), k = G.g - 1 + (int)(t % KR);
+    i64 z = (i64)c * G.K + k;
+    i64 zj[T::NS];
+#pragma unroll
+    for (int j = 0; j < T::NS; j++) {
+        int m = G.stm[(i64)c * T::NS + j];
+        zj[j] = m < 0 ? z : (i64)(m >> 3) * G.K + k + (m & 7) - 3;
+    }
+    const double *Pl = G.Pl + (i64)c * T::NC * T::NS;
+    const double *Ps = G.Ps + (i64)c * 7 * 18;
+    const double *Qs = G.Qs + (i64)c * T::NC * T::NC;
+    const double gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+    for (int v = 0; v < 8; v++) {
+        const double *Uv = U + v * G.Z;
+        double u0 = Uv[z];
+        double du[T::NS];
+#pragma unroll
+        for (int j = 0; j < T::NS; j++) du[j] = Uv[zj[j]] - u0;
+        double chi[T::NC];
+#pragma unroll
+        for (int a = 0; a < T::NC; a++) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < T::NS; j++) s += Pl[a * T::NS + j] * du[j];
+            chi[a] = s;
+        }
+        double cs[7][3];
+#pragma unroll
+        for (int s = 0; s < 7; s++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < 6; j++) acc += Ps[s * 18 + i * 6 + j] * du[j];
+                cs[s][i] = acc;
+            }
+        double bhi = 0.0;
+#pragma unroll
+        for (int a = 0; a < T::NC; a++) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < T::NC; b++) s += Qs[a * T::NC + b] * chi[b];
+            bhi += chi[a] * s;
+        }
+        double w0 = WENO_GAMMA_HI / ((bhi + WENO_EPS) * (bhi + WENO_EPS)), tot = w0, ws[7];
+#pragma unroll
+        for (int s = 0; s < 7; s++) {
+            double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+            ws[s] = gs / ((b + WENO_EPS) * (b + WENO_EPS));
+            tot += ws[s];
+        }
+        double itot = 1.0 / tot;
+        w0 *= itot;
+        double* out = wc + (i64)v * T::NC * G.Z + z;
+#pragma unroll
+        for (int a = 0; a < T::NC; a++) {
+            double lin = 0.0, nl = 0.0;
+            if (a < 3)
+#pragma unroll
+                for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
+            out[(i64)a * G.Z] = w0 / WENO_GAMMA_HI * (chi[a] - lin) + nl;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- face nodal B
+// radial faces kf in [g-1, g+Nr+1], angular faces in shells [g-1, g+Nr]
+template <int P>
+__global__ __launch_bounds__(256) void face_bnodal(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
+                                                   const double *__restrict__ wc, double *__restrict__ bnod)
+{
+    using T = Tr<P>;
+    const int nrad = G.Nr + 3, nang = G.Nr + 2;
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    i64 nR = (i64)G.ncol * nrad;
+    if (t >= nR + (i64)G.nae * nang) return;
+    i64 f, z[2];
+    bool have[2];
+    const double *fev[2], *nrm, *fw;
+    if (t < nR) {
+        int c = (int)(t / nrad), kf = G.g - 1 + (int)(t % nrad);
+        f = (i64)c * (G.K + 1) + kf;
+        z[0] = (i64)c * G.K + kf - 1;
+        z[1] = (i64)c * G.K + kf;
+        have[0] = (kf - 1 >= G.g - 1) && (kf - 1 <= G.g + G.Nr);
+        have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
+        fev[0] = G.fevR + ((i64)c * 2 + 0) * T::Q * T::NC;
+        fev[1] = G.fevR + ((i64)c * 2 + 1) * T::Q * T::NC;
+        nrm = G.fnR + (i64)c * T::Q * 3;
+        fw = G.fwR + (i64)c * T::Q;
+    } else {
+        i64 u = t - nR;
+        int ae = (int)(u / nang), k = G.g - 1 + (int)(u % nang);
+        f = G.NRF + (i64)ae * G.K + k;
+        z[0] = (i64)G.ae_col[2 * ae] * G.K + k;
+        z[1] = (i64)G.ae_col[2 * ae + 1] * G.K + k;
+        have[0] = have[1] = true;
+        fev[0] = G.fevA + ((i64)ae * 2 + 0) * T::Q * T::NC;
+        fev[1] = G.fevA + ((i64)ae * 2 + 1) * T::Q * T::NC;
+        nrm = G.fnA + (i64)ae * T::Q * 3;
+        fw = G.fwA + (i64)ae * T::Q;
+    }
+    double mean = Bf[f];
+    double bn[T::Q];
+#pragma unroll
+    for (int q = 0; q < T::Q; q++) {
+        double d[2] = {0.0, 0.0};
+        for (int s = 0; s < 2; s++) {
+            if (!have[s]) continue;
+            double B[3];
+            for (int c3 = 0; c3 < 3; c3++) {
+                double acc = U[(5 + c3) * G.Z + z[s]];
+                const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z[s];
+#pragma unroll
+                for (int a = 0; a < T::NC; a++) acc += cf[(i64)a * G.Z] * fev[s][q * T::NC + a];
+                B[c3] = acc;
+            }
+            d[s] = B[0] * nrm[q * 3] + B[1] * nrm[q * 3 + 1] + B[2] * nrm[q * 3 + 2] - mean;
+        }
+        if (!have[0]) d[0] = d[1];
+        if (!have[1]) d[1] = d[0];
+        bn[q] = mean + dev_minmod(d[0], d[1]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < T::Q; q++) s += fw[q] * bn[q];
+#pragma unroll
+    for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = bn[q] + (mean - s);
+}
+
+// ---------------------------------------------------------------- predictor
+// local edges 0..7 are angular: local face holding them and whether they lie
+// on the upper (zeta+) interface; 8..11 radial at corners v0, v1, v3, v2
+__constant__ int LE_FACE[8] = {2, 3, 2, 3, 0, 1, 0, 1};
+__constant__ int LE_UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
+__constant__ int LE_CORNER[4] = {0, 1, 3, 2};
+
+template <int P>
+__device__ __forceinline__ void mapped_flux(const double *u, double J, const double *met, double fac, double gam,
+                                            double out[3][8])
+{
+    double w[8], F[3][8];
+    double iJ = 1.0 / J;
+#pragma unroll
+    for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
+    dev_flux(w, gam, F);
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int v = 0; v < 8; v++)
+            out[d][v] = fac * (met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v]);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam, int npic, const double *__restrict__ U,
+                                                const double *__restrict__ Bf, const double *__restrict__ wc,
+                                                const double *__restrict__ bnod, double *__restrict__ zoneB,
+                                                double *__restrict__ ftr, double *__restrict__ etr)
+{
+    using T = Tr<P>;
+    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1;
+    constexpr int XS = E * 24;           // exchange words per node
+    __shared__ double s_in[ZPW][T::NIN];
+    __shared__ double s_x[ZPW][N][XS];
+    const int lane = threadIdx.x, zl = lane / N, i = lane % N;
+    const int KR = G.Nr + 2;
+    const i64 nzr = (i64)G.ncol * KR;
+    const i64 zt = (i64)blockIdx.x * ZPW + zl;
+    const bool active = (zl < ZPW) && (zt < nzr);
+    int c = 0, k = 0;
+    i64 z = 0;
+    if (active) {
+        c = (int)(zt / KR);
+        k = G.g - 1 + (int)(zt % KR);
+        z = (i64)c * G.K + k;
+    }
+    // face ids of the six local faces
+    i64 fid[6];
+    if (active) {
+        for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+        fid[4] = (i64)c * (G.K + 1) + k;
+        fid[5] = fid[4] + 1;
+        // inputs of the divergence-free map
+        for (int j = i; j < T::NIN; j += N) {
+            double val;
+            if (j < 3 * (T::NC + 1)) {
+                int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+                val = a == 0 ? U[(5 + comp) * G.Z + z] : wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z];
+            } else if (j < 3 * (T::NC + 1) + 6 * T::Q) {
+                int jj = j - 3 * (T::NC + 1), lf = jj / T::Q, qc = jj % T::Q;
+                val = bnod[(i64)qc * G.NF + fid[lf]];
+            } else {
+                int lf = j - 3 * (T::NC + 1) - 6 * T::Q;
+                val = Bf[fid[lf]];
+            }
+            s_in[zl][j] = val;
+        }
+    }
+    __syncthreads();
+
+    double Ua[8], Ut[E][8], J = 1.0, met[9], fac = 0.0;
+    if (active) {
+        const double *Ev = G.Ev + ((i64)c * N + i) * T::NC;
+        for (int v = 0; v < 5; v++) {
+            double acc = U[v * G.Z + z];
+            const double *cf = wc + (i64)v * T::NC * G.Z + z;
+#pragma unroll
+            for (int a = 0; a < T::NC; a++) acc += Ev[a] * cf[(i64)a * G.Z];
+            Ua[v] = acc;
+        }
+        const double *Mb = G.Mb + (i64)c * T::NOUTB * T::NIN;
+        for (int comp = 0; comp < 3; comp++) {
+            const double *row = Mb + (i64)(comp * N + i) * T::NIN;
+            double acc = 0.0;
+#pragma unroll 4
+            for (int j = 0; j < T::NIN; j++) acc += row[j] * s_in[zl][j];
+            Ua[5 + comp] = acc;
+        }
+        if (i < 3) {
+            const double *row = Mb + (i64)(3 * N + i) * T::NIN;
+            double acc = 0.0;
+            for (int j = 0; j < T::NIN; j++) acc += row[j] * s_in[zl][j];
+            zoneB[(i64)i * G.Z + z] = acc;
+        }
+        J = G.nJ[(i64)c * N + i];
+        for (int m = 0; m < 9; m++) met[m] = G.nM[((i64)c * N + i) * 9 + m];
+        fac = dt / G.zscale[k];
+#pragma unroll
+        for (int v = 0; v < 8; v++) Ua[v] *= J;
+#pragma unroll
+        for (int t = 0; t < E; t++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v];
+    }
+    const int *dptr = G.dptr;
+    for (int it = 0; it < npic; it++) {
+        if (active) {
+            double Gx[E][3][8], F[3][8];
+            mapped_flux<P>(Ua, J, met, fac, gam, F);
+#pragma unroll
+            for (int t = 0; t < E; t++) {
+                double r = G.R[t * T::M + 0];
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+#pragma unroll
+                    for (int v = 0; v < 8; v++) Gx[t][d][v] = r * F[d][v];
+            }
+#pragma unroll
+            for (int s = 0; s < E; s++) {
+                mapped_flux<P>(Ut[s], J, met, fac, gam, F);
+#pragma unroll
+                for (int t = 0; t < E; t++) {
+                    double r = G.R[t * T::M + s + 1];
+#pragma unroll
+                    for (int d = 0; d < 3; d++)
+#pragma unroll
+                        for (int v = 0; v < 8; v++) Gx[t][d][v] += r * F[d][v];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < E; t++)
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+#pragma unroll
+                    for (int v = 0; v < 8; v++) s_x[zl][i][(t * 3 + d) * 8 + v] = Gx[t][d][v];
+        }
+        __syncthreads();
+        if (active) {
+            double acc[E][8];
+#pragma unroll
+            for (int t = 0; t < E; t++)
+#pragma unroll
+                for (int v = 0; v < 8; v++) acc[t][v] = 0.0;
+            for (int d = 0; d < 3; d++) {
+                int r0 = dptr[i * 3 + d], r1 = dptr[i * 3 + d + 1];
+                for (int p = r0; p < r1; p++) {
+                    int l = G.dcol[p];
+                    double dv = G.dval[p];
+#pragma unroll
+                    for (int t = 0; t < E; t++)
+#pragma unroll
+                        for (int v = 0; v < 8; v++) acc[t][v] += dv * s_x[zl][l][(t * 3 + d) * 8 + v];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < E; t++)
+#pragma unroll
+                for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - acc[t][v];
+        }
+        __syncthreads();
+    }
+    // time averages of state and physical flux over the Gauss levels
+    if (active) {
+        double aU[8], aF[3][8], w[8], F[3][8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) { aU[v] = 0.0; aF[0][v] = aF[1][v] = aF[2][v] = 0.0; }
+        double iJ = 1.0 / J;
+#pragma unroll
+        for (int t = 0; t < E; t++) {
+            double wt = G.wt[t + 1];
+#pragma unroll
+            for (int v = 0; v < 8; v++) w[v] = Ut[t][v] * iJ;
+            dev_flux(w, gam, F);
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                aU[v] += wt * w[v];
+                aF[0][v] += wt * F[0][v];
+                aF[1][v] += wt * F[1][v];
+                aF[2][v] += wt * F[2][v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            s_x[zl][i][v] = aU[v];
+            s_x[zl][i][8 + v] = aF[0][v];
+            s_x[zl][i][16 + v] = aF[1][v];
+            s_x[zl][i][24 + v] = aF[2][v];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    // traces: face quadrature points, then edge Simpson points
+    const int nwork = 6 * T::Q + 36;
+    for (int w = i; w < nwork; w += N) {
+        if (w < 6 * T::Q) {
+            int lf = w / T::Q, ql = w % T::Q;
+            double Uq[8], Fq[3][8];
+#pragma unroll
+            for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
+            for (int kk = 0; kk < T::NFN; kk++) {
+                int l = G.fnode[lf * T::NFN + kk];
+                double wgt = G.fint[(lf * T::Q + ql) * T::NFN + kk];
+                const double *sx = s_x[zl][l];
+#pragma unroll
+                for (int v = 0; v < 8; v++) {
+                    Uq[v] += wgt * sx[v];
+                    Fq[0][v] += wgt * sx[8 + v];
+                    Fq[1][v] += wgt * sx[16 + v];
+                    Fq[2][v] += wgt * sx[24 + v];
+                }
+            }
+            int qc, side;
+            const double *n;
+            if (lf >= 4) {
+                qc = ql;
+                side = lf == 4 ? 1 : 0;
+                n = G.fnR + ((i64)c * T::Q + qc) * 3;
+            } else {
+                qc = G.col_perm[((i64)c * 4 + lf) * T::Q + ql];
+                side = G.col_side[4 * c + lf];
+                n = G.fnA + ((i64)G.col_ae[4 * c + lf] * T::Q + qc) * 3;
+            }
+            i64 f = fid[lf];
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                ftr[((i64)(v * T::Q + qc) * 2 + side) * G.NF + f] = Uq[v];
+                ftr[((i64)((8 + v) * T::Q + qc) * 2 + side) * G.NF + f] = n[0] * Fq[0][v] + n[1] * Fq[1][v] + n[2] * Fq[2][v];
+            }
+        } else {
+            int we = w - 6 * T::Q, le = we / 3, pl = we % 3;
+            double Uq[8], Fq[3][8];
+#pragma unroll
+            for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
+            for (int kk = 0; kk < T::NEN; kk++) {
+                int l = G.enode[le * T::NEN + kk];
+                double wgt = G.eint[(le * 3 + pl) * T::NEN + kk];
+                const double *sx = s_x[zl][l];
+#pragma unroll
+                for (int v = 0; v < 8; v++) {
+                    Uq[v] += wgt * sx[v];
+                    Fq[0][v] += wgt * sx[8 + v];
+                    Fq[1][v] += wgt * sx[16 + v];
+                    Fq[2][v] += wgt * sx[24 + v];
+                }
+            }
+            int rev = G.col_rev[(i64)c * 12 + le], slot = G.col_slot[(i64)c * 12 + le];
+            int pc = rev ? 2 - pl : pl;
+            i64 e;
+            if (le < 8) {
+                int ae = G.col_ae[4 * c + LE_FACE[le]];
+                e = G.NRE + (i64)ae * (G.K + 1) + k + LE_UP[le];
+            } else {
+                e = (i64)G.col_v[4 * c + LE_CORNER[le - 8]] * G.K + k;
+            }
+            double vals[11];
+#pragma unroll
+            for (int v = 0; v < 8; v++) vals[v] = Uq[v];
+            vals[8] = Fq[2][6];   // E_x = H[B_y]
+            vals[9] = Fq[0][7];   // E_y = F[B_z]
+            vals[10] = Fq[1][5];  // E_z = G[B_x]   (eq. 2.3)
+#pragma unroll
+            for (int v = 0; v < 11; v++) etr[((i64)(v * 3 + pc) * 4 + slot) * G.NE + e] = vals[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- face fluxes
+// radial faces kf in [g, g+Nr], angular faces in shells [g, g+Nr-1]
+template <int P>
+__global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const double *__restrict__ ftr,
+                                                 double *__restrict__ Phi)
+{
+    using T = Tr<P>;
+    const int nrad = G.Nr + 1, nang = G.Nr;
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    i64 nR = (i64)G.ncol * nrad;
+    if (t >= nR + (i64)G.nae * nang) return;
+    i64 f;
+    const double *nrm, *fw;
+    if (t < nR) {
+        int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
+        f = (i64)c * (G.K + 1) + kf;
+        nrm = G.fnR + (i64)c * T::Q * 3;
+        fw = G.fwR + (i64)c * T::Q;
+    } else {
+        i64 u = t - nR;
+        int ae = (int)(u / nang), k = G.g + (int)(u % nang);
+        f = G.NRF + (i64)ae * G.K + k;
+        nrm = G.fnA + (i64)ae * T::Q * 3;
+        fw = G.fwA + (i64)ae * T::Q;
+    }
+    double area = G.area[f], acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] = 0.0;
+    for (int q = 0; q < T::Q; q++) {
+        double UL[8], UR[8], FL[8], FR[8], Fs[8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            UL[v] = ftr[((i64)(v * T::Q + q) * 2 + 0) * G.NF + f];
+            UR[v] = ftr[((i64)(v * T::Q + q) * 2 + 1) * G.NF + f];
+            FL[v] = ftr[((i64)((8 + v) * T::Q + q) * 2 + 0) * G.NF + f];
+            FR[v] = ftr[((i64)((8 + v) * T::Q + q) * 2 + 1) * G.NF + f];
+        }
+        dev_hll(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
+        double w = fw[q] * area;
+#pragma unroll
+        for (int v = 0; v < 8; v++) acc[v] += w * Fs[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) Phi[(i64)v * G.NF + f] = acc[v];
+}
+
+// ---------------------------------------------------------------- edge electric fields
+__device__ __forceinline__ double emf4(const double U[4][8], const double Et[4], const double *F, double gam)
+{
+    const double *e1 = F, *e2 = F + 3;
+    double ap1 = 0.0, am1 = 0.0, ap2 = 0.0, am2 = 0.0, B1[4], B2[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        double ir = 1.0 / U[s][0];
+        double v1 = (U[s][1] * e1[0] + U[s][2] * e1[1] + U[s][3] * e1[2]) * ir;
+        double v2 = (U[s][1] * e2[0] + U[s][2] * e2[1] + U[s][3] * e2[2]) * ir;
+        double c1 = dev_fast(U[s], gam, e1), c2 = dev_fast(U[s], gam, e2);
+        ap1 = fmax(ap1, v1 + c1);
+        am1 = fmax(am1, c1 - v1);
+        ap2 = fmax(ap2, v2 + c2);
+        am2 = fmax(am2, c2 - v2);
+        B1[s] = U[s][5] * e1[0] + U[s][6] * e1[1] + U[s][7] * e1[2];
+        B2[s] = U[s][5] * e2[0] + U[s][6] * e2[1] + U[s][7] * e2[2];
+    }
+    // slots counter-clockwise: 0 SW, 1 SE, 2 NE, 3 NW
+    double Es = (ap1 * ap2 * Et[0] + ap1 * am2 * Et[3] + am1 * ap2 * Et[1] + am1 * am2 * Et[2]) / ((ap1 + am1) * (ap2 + am2));
+    Es += ap1 * am1 * (0.5 * (B2[1] + B2[2]) - 0.5 * (B2[0] + B2[3])) / (ap1 + am1);
+    Es -= ap2 * am2 * (0.5 * (B1[2] + B1[3]) - 0.5 * (B1[0] + B1[1])) / (ap2 + am2);
+    return Es;
+}
+
+// three zones about an edge: mean of the 1-D HLL induction fluxes of the three faces
+__device__ double emf3(const double U[4][8], const double E[4][3], const double *N3, const double *t, double gam)
+{
+    double acc = 0.0;
+    for (int s = 0; s < 3; s++) {
+        int s2 = (s + 1) % 3;
+        const double *n = N3 + 3 * s;
+        double FL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, FR[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Fs[8];
+        FL[5] = n[1] * E[s][2] - n[2] * E[s][1];
+        FL[6] = n[2] * E[s][0] - n[0] * E[s][2];
+        FL[7] = n[0] * E[s][1] - n[1] * E[s][0];
+        FR[5] = n[1] * E[s2][2] - n[2] * E[s2][1];
+        FR[6] = n[2] * E[s2][0] - n[0] * E[s2][2];
+        FR[7] = n[0] * E[s2][1] - n[1] * E[s2][0];
+        dev_hll(U[s], U[s2], FL, FR, n, gam, Fs);
+        double tn[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
+        acc -= Fs[5] * tn[0] + Fs[6] * tn[1] + Fs[7] * tn[2];
+    }
+    return acc / 3.0;
+}
+
+// radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr]
+__global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const double *__restrict__ etr, double *__restrict__ Gam)
+{
+    const int nrad = G.Nr, nang = G.Nr + 1;
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    i64 nR = (i64)G.nv * nrad;
+    if (t >= nR + (i64)G.nae * nang) return;
+    const double simpson[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    i64 e;
+    int nzs;
+    const double *frame[3];
+    double wl[3];
+    const double *N3 = nullptr;
+    if (t < nR) {
+        int v = (int)(t / nrad), k = G.g + (int)(t % nrad);
+        e = (i64)v * G.K + k;
+        nzs = G.v_ncol[v];
+        double len = G.radius[k + 1] - G.radius[k];
+        for (int p = 0; p < 3; p++) { frame[p] = G.vF + (i64)v * 9; wl[p] = simpson[p] * len; }
+        N3 = G.vN3 + (i64)v * 9;
+    } else {
+        i64 u = t - nR;
+        int ae = (int)(u / nang), kf = G.g + (int)(u % nang);
+        e = G.NRE + (i64)ae * (G.K + 1) + kf;
+        nzs = 4;
+        double s = G.radius[kf] / G.radius[0];
+        for (int p = 0; p < 3; p++) { frame[p] = G.aeF + ((i64)ae * 3 + p) * 9; wl[p] = G.aeW[(i64)ae * 3 + p] * s; }
+    }
+    double gsum = 0.0;
+    for (int p = 0; p < 3; p++) {
+        double U[4][8], E[4][3], Et[4];
+        const double *tt = frame[p] + 6;
+        for (int s = 0; s < nzs; s++) {
+#pragma unroll
+            for (int v = 0; v < 8; v++) U[s][v] = etr[((i64)(v * 3 + p) * 4 + s) * G.NE + e];
+#pragma unroll
+            for (int v = 0; v < 3; v++) E[s][v] = etr[((i64)((8 + v) * 3 + p) * 4 + s) * G.NE + e];
+            Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
+        }
+        double Es = (nzs == 4) ? emf4(U, Et, frame[p], gam) : emf3(U, E, N3, tt, gam);
+        gsum += wl[p] * Es;
+    }
+    Gam[e] = gsum;
+}
+
+// ---------------------------------------------------------------- updates
+__global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const double *__restrict__ Phi,
+                                                   const double *__restrict__ zoneB, double *Uo)
+{
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * G.Nr) return;
+    int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
+    i64 z = (i64)c * G.K + k;
+    i64 f[6];
+    double sg[6];
+    for (int lf = 0; lf < 4; lf++) {
+        f[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+        sg[lf] = G.col_side[4 * c + lf] == 0 ? 1.0 : -1.0;
+    }
+    f[4] = (i64)c * (G.K + 1) + k;
+    f[5] = f[4] + 1;
+    sg[4] = -1.0;
+    sg[5] = 1.0;
+    double cfac = dt / G.vol[z];
+    for (int v = 0; v < 8; v++) {
+        double acc = 0.0;
+        for (int lf = 0; lf < 6; lf++) acc += sg[lf] * Phi[(i64)v * G.NF + f[lf]];
+        double base = v < 5 ? Uo[v * G.Z + z] : zoneB[(v - 5) * G.Z + z];
+        Uo[v * G.Z + z] = base - cfac * acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void face_ct(DevGeom G, double dt, const double *__restrict__ Gam, double *Bo)
+{
+    const int nrad = G.Nr + 1, nang = G.Nr;
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    i64 nR = (i64)G.ncol * nrad;
+    if (t >= nR + (i64)G.nae * nang) return;
+    i64 f;
+    double circ = 0.0;
+    if (t < nR) {
+        int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
+        f = (i64)c * (G.K + 1) + kf;
+        for (int lf = 0; lf < 4; lf++)
+            circ += G.col_sgn[4 * c + lf] * Gam[G.NRE + (i64)G.col_ae[4 * c + lf] * (G.K + 1) + kf];
+    } else {
+        i64 u = t - nR;
+        int ae = (int)(u / nang), k = G.g + (int)(u % nang);
+        f = G.NRF + (i64)ae * G.K + k;
+        i64 ea0 = G.NRE + (i64)ae * (G.K + 1) + k;
+        double lp = Gam[ea0] + Gam[(i64)G.ae_v[2 * ae + 1] * G.K + k] - Gam[ea0 + 1] - Gam[(i64)G.ae_v[2 * ae] * G.K + k];
+        circ = G.ae_rs[ae] * lp;
+    }
+    Bo[f] -= dt / G.area[f] * circ;
+}
+
+// ---------------------------------------------------------------- CFL
+__global__ __launch_bounds__(256) void cfl_partial(DevGeom G, double gam, double cfl, const double *__restrict__ U,
+                                                   double *red)
+{
+    __shared__ double sm[256];
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    double best = 1e300;
+    if (t < (i64)G.ncol * G.Nr) {
+        int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
+        i64 z = (i64)c * G.K + k;
+        double u[8];
+        for (int v = 0; v < 8; v++) u[v] = U[v * G.Z + z];
+        double ir = 1.0 / u[0];
+        double vv = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir;
+        double a2 = gam * dev_pressure(u, gam) * ir, b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+        best = cfl * G.dins[c] * G.zscale[k] / (vv + sqrt(a2 + b2));
+    }
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void cfl_final(int n, double *red)
+{
+    __shared__ double sm[256];
+    double best = 1e300;
+    for (int i = threadIdx.x; i < n; i += 256) best = fmin(best, red[i]);
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[65535] = sm[0];
+}
+
+// ---------------------------------------------------------------- host launch
+static inline unsigned nblocks(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define RG_LAUNCH_CHECK()                                            \
+    do {                                                             \
+        hipError_t e_ = hipGetLastError();                           \
+        if (e_ != hipSuccess) {                                      \
+            set_error(std::string("kernel launch failed: ") + hipGetErrorString(e_)); \
+            return RG_EDEVICE;                                       \
+        }                                                            \
+    } while (0)
+
+template <int P>
+static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf, double *Uo,
+                            double *Bo, hipStream_t st)
+{
+    const DevGeom &G = g->d;
+    const int npic = prm.n_picard > 0 ? prm.n_picard : P;
+    const double dt = prm.dt, gam = prm.gamma;
+    bc_zones<<<nblocks(G.Z, 256), 256, 0, st>>>(G, prm.bc_kind, U, Uo);
+    bc_faces<<<nblocks(G.NF, 256), 256, 0, st>>>(G, prm.bc_kind, Bf, Bo);
+    RG_LAUNCH_CHECK();
+    const i64 nzr = (i64)G.ncol * (G.Nr + 2);
+    weno<P><<<nblocks(nzr, 256), 256, 0, st>>>(G, Uo, g->wcoef);
+    RG_LAUNCH_CHECK();
+    const i64 nbn = (i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2);
+    face_bnodal<P><<<nblocks(nbn, 256), 256, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod);
+    RG_LAUNCH_CHECK();
+    constexpr int ZPW = 64 / Tr<P>::N;
+    predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, Bo, g->wcoef, g->bnod, g->zoneB,
+                                                                    g->ftr, g->etr);
+    RG_LAUNCH_CHECK();
+    const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
+    face_flux<P><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, g->ftr, g->Phi);
+    const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
+    edge_emf<<<nblocks(nee, 256), 256, 0, st>>>(G, gam, g->etr, g->Gam);
+    RG_LAUNCH_CHECK();
+    zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
+    face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo, double *Bo,
+                      void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g->d.order == 3) return step_order<3>(g, p, U, Bf, Uo, Bo, st);
+    if (g->d.order == 4) return step_order<4>(g, p, U, Bf, Uo, Bo, st);
+    set_error("unsupported order");
+    return RG_ENOTSUP;
+}
+
+rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGeom &G = g->d;
+    i64 n = (i64)G.ncol * G.Nr;
+    unsigned nb = nblocks(n, 256);
+    if (nb > 65535) {
+        set_error("mesh too large for the CFL reduction");
+        return RG_ENOTSUP;
+    }
+    cfl_partial<<<nb, 256, 0, st>>>(G, gamma, cfl, U, g->red);
+    cfl_final<<<1, 256, 0, st>>>((int)nb, g->red);
+    RG_LAUNCH_CHECK();
+    if (hipMemcpyAsync(dt, g->red + 65535, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("CFL reduction copy failed");
+        return RG_EDEVICE;
+    }
+    return RG_OK;
+}
+
+}  // namespace rg
