@@ -1,0 +1,159 @@
+#!/usr/bin/env python
+"""Throughput of one fourth-order ADER-WENO-AO divergence-free MHD step on one
+MI355X: zone-updates per second on a 6 x 128 x 128 angular x 128 radial
+cube-based geodesic shell (12,582,912 zones, cubic isoparametric zones) with
+a circularly polarised Alfven wave plus 1% seeded noise in density and
+pressure (synthetic, seeded).  Prints one JSON line.
+
+Timed region: K steps of the HIP library on device-resident state, bracketed
+by torch.cuda.synchronize() and HIP events on the library's stream.  Mesh and
+geometry construction and initial data are excluded (reported separately).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+MACHINE_BALANCE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(order, sample_n=8, sample_nr=8):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    import rg_inputs as RI
+    from oracle import oracle as O
+    m = O.OracleMesh(sample_n, sample_nr, order=order, n_ghost=order - 1)
+    prob = RI.alfven_problem()
+    U, Bf = m.init_alfven(prob)
+    noise = RI.white_noise(m.nz)
+    U[0] *= 1 + 0.01 * noise[0]
+    dt = m.cfl_dt(U, 0.3, prob["gamma"])
+    t0 = time.perf_counter()
+    m.step(U, Bf, dt, gamma=prob["gamma"])
+    el = time.perf_counter() - t0
+    zones = 6 * sample_n * sample_n * sample_nr
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": zones / el, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one order-{order} step on 6x{sample_n}x{sample_n}x{sample_nr} zones "
+                      f"(Alfven wave + noise), {el:.2f} s, geometry excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-ang", type=int, default=128)
+    ap.add_argument("--n-rad", type=int, default=128)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--cfl", type=float, default=0.3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the step is one GPU's share of the mesh); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1905_02504_amd as R
+    import rg_inputs as RI
+
+    t0 = time.perf_counter()
+    shell = R.ShellMHD(args.n_ang, args.n_rad, args.order, n_ghost=max(3, args.order - 1))
+    t_geom = time.perf_counter() - t0
+    log(f"[bench] geometry {t_geom:.1f}s, zones {shell.nz}")
+    prob = RI.alfven_problem()
+    t0 = time.perf_counter()
+    noise = RI.white_noise(shell.nz)
+    U_h, Bf_h = shell.init_alfven(prob, noise=noise, noise_amp=0.01)
+    t_init = time.perf_counter() - t0
+    log(f"[bench] initial data {t_init:.1f}s")
+    U = torch.from_numpy(U_h).cuda()
+    Bf = torch.from_numpy(Bf_h).cuda()
+    del U_h, Bf_h, noise
+    U2 = torch.empty_like(U)
+    Bf2 = torch.empty_like(Bf)
+    gam = prob["gamma"]
+    dt = shell.cfl_dt(U, args.cfl, gam)
+    for _ in range(args.warmup):
+        shell.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+        U, U2, Bf, Bf2 = U2, U, Bf2, Bf
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    shell.profile_begin()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        shell.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+        U, U2, Bf, Bf2 = U2, U, Bf2, Bf
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    stage_ms, nrec = shell.profile_end()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    interior = 6 * args.n_ang * args.n_ang * args.n_rad
+    value = interior * args.steps / (total_ms * 1e-3)
+    log(f"[bench] {ms_step:.2f} ms/step, stages (ms/step): " +
+        ", ".join(f"{k} {v / nrec:.2f}" for k, v in stage_ms.items()))
+    # sanity: finite state, divergence-free B is checked by the tests
+    if not torch.isfinite(U).all():
+        log("[bench] non-finite state after the timed steps")
+        sys.exit(1)
+
+    flops, bytes_ = shell.work()
+    dom = max(stage_ms, key=stage_ms.get)
+    dom_s = stage_ms[dom] / nrec * 1e-3
+    intensity = flops[dom] / max(bytes_[dom], 1.0)
+    if intensity >= MACHINE_BALANCE:
+        achieved = flops[dom] / dom_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom}
+    else:
+        achieved = bytes_[dom] / dom_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom}
+    out = {
+        "metric": "zone-updates/s per ADER step (4th order), FP64",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ADER-WENO-AO MHD step, order {args.order}, 6x{args.n_ang}x{args.n_ang} angular x "
+                               f"{args.n_rad} radial = {interior} zones, Alfven wave + 1% noise, CFL {args.cfl}",
+                   "zones": interior, "order": args.order, "dt": dt,
+                   "setup_s": {"geometry": round(t_geom, 2), "initial_data": round(t_init, 2)},
+                   "stage_ms_per_step": {k: round(v / nrec, 4) for k, v in stage_ms.items()}},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(args.order)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

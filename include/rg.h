@@ -151,6 +151,23 @@ rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, d
                          double wavelength, double gamma, double t, const double *noise, double noise_amp,
                          double *U, double *Bf);
 
+/* Per-stage timing with HIP events recorded on the step's own stream.
+ * After rg_profile_begin, every rg_step records events around its seven
+ * stages: 0 boundary fill, 1 WENO-AO, 2 face nodal B, 3 divergence-free B +
+ * ADER predictor + traces, 4 face HLL fluxes, 5 edge EMFs, 6 FV update + CT.
+ * rg_profile_end waits for the recorded events, writes the summed
+ * milliseconds of each stage to ms[7] and the number of recorded steps to
+ * *nsteps, releases the events and stops recording. */
+rg_status rg_profile_begin(rg_geom *geom);
+rg_status rg_profile_end(rg_geom *geom, double *ms, int32_t *nsteps);
+
+/* Algorithmic work of one rg_step on this geometry, per stage (numbering of
+ * rg_profile_end): flops[7] floating-point operations (an FMA counts 2) of
+ * the formulas each stage evaluates, bytes[7] minimum HBM traffic (each
+ * input read once, each output written once, per-column matrices amortised
+ * over the column).  Host only. */
+rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
+
 const char *rg_last_error(void);
 
 #ifdef __cplusplus

@@ -125,3 +125,15 @@ class ShellMHD:
 
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())
+
+    # per-stage timing ----------------------------------------------------------
+    def profile_begin(self):
+        N.rg_profile_begin(self._geom)
+
+    def profile_end(self):
+        """-> ({stage: summed ms}, number of steps)"""
+        return N.rg_profile_end(self._geom)
+
+    def work(self):
+        """-> ({stage: flops per step}, {stage: algorithmic HBM bytes per step})"""
+        return N.rg_geom_work(self._geom)

@@ -66,7 +66,11 @@ def lib():
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
-        for name in ("rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
+        L.rg_geom_work.argtypes = [_vp, _dp, _dp]
+        L.rg_geom_work.restype = C.c_int
+        L.rg_profile_begin.argtypes = [_vp]
+        L.rg_profile_end.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
+        for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
                      "rg_cfl_dt", "rg_init_alfven"):
             getattr(L, name).restype = C.c_int
@@ -144,3 +148,24 @@ def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
 def rg_init_alfven(geom, frame_ptr, rho, p, B0, dB, wavelength, gamma, t, noise_ptr, noise_amp, U_ptr, Bf_ptr):
     check(lib().rg_init_alfven(geom, _vp(frame_ptr), rho, p, B0, dB, wavelength, gamma, t, _vp(noise_ptr),
                                noise_amp, _vp(U_ptr), _vp(Bf_ptr)), "rg_init_alfven")
+
+
+STAGES = ("bc_fill", "weno", "face_bnodal", "predictor", "face_flux", "edge_emf", "update_ct")
+
+
+def rg_profile_begin(geom):
+    check(lib().rg_profile_begin(geom), "rg_profile_begin")
+
+
+def rg_profile_end(geom):
+    ms = (C.c_double * 7)()
+    n = C.c_int32(0)
+    check(lib().rg_profile_end(geom, ms, C.byref(n)), "rg_profile_end")
+    return dict(zip(STAGES, list(ms))), n.value
+
+
+def rg_geom_work(geom):
+    f = (C.c_double * 7)()
+    b = (C.c_double * 7)()
+    check(lib().rg_geom_work(geom, f, b), "rg_geom_work")
+    return dict(zip(STAGES, list(f))), dict(zip(STAGES, list(b)))

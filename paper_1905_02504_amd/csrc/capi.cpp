@@ -366,3 +366,72 @@ extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, 
     if (!g || !g->d.vol || !U || !dt || !(cfl > 0) || !(gamma > 1)) { set_error("invalid argument"); return RG_EINVAL; }
     return launch_cfl(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
 }
+
+extern "C" rg_status rg_profile_begin(rg_geom *g)
+{
+    if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }
+    if (g->prof_on) { set_error("profiling already active"); return RG_EINVAL; }
+    g->prof_on = true;
+    return RG_OK;
+}
+
+extern "C" rg_status rg_profile_end(rg_geom *g, double *ms, int32_t *nsteps)
+{
+    if (!g || !ms || !nsteps) { set_error("null argument"); return RG_EINVAL; }
+    if (!g->prof_on) { set_error("profiling not active"); return RG_EINVAL; }
+    int n = 0;
+    rg_status s = profile_end(g, ms, &n);
+    *nsteps = n;
+    return s;
+}
+
+// Algorithmic work of one step, per stage (same numbering as the stage
+// timers): floating-point operations counted from the formulas each stage
+// evaluates (one FMA = 2), and the minimum HBM bytes: every input read once,
+// every output written once, per-column matrices amortised over the column.
+extern "C" rg_status rg_geom_work(const rg_geom *g, double *flops, double *bytes)
+{
+    if (!g || !flops || !bytes) { set_error("null argument"); return RG_EINVAL; }
+    const RefEl &r = g->ref;
+    const Mesh &m = g->mesh->m;
+    const double N = r.N, NC = r.NC, NS = r.NS, Q = r.Q, NIN = r.NIN, E = r.M - 1, K = m.K;
+    const double zr = (double)m.ncol * (m.Nr + 2);                       // reconstructed zones
+    const double zi = (double)m.ncol * m.Nr;                             // interior zones
+    const double fb = (double)m.ncol * (m.Nr + 3) + (double)m.nae * (m.Nr + 2);  // faces with nodal B
+    const double ff = (double)m.ncol * (m.Nr + 1) + (double)m.nae * m.Nr;        // flux / CT faces
+    const double ee = (double)m.nv * m.Nr + (double)m.nae * (m.Nr + 1);          // EMF edges
+    double nnz = 0;
+    for (double v : r.D) nnz += (v != 0.0);
+    const double nnz_node = nnz / N;        // over the three directions
+    const double FLUX = 96, MAPPED = FLUX + 9 + 3 * 8 * 6, FAST = 22, HLL = 2 * FAST + 14 + 8 * 7;
+    // 0 boundary fill
+    flops[0] = 0;
+    bytes[0] = 2.0 * 8 * (8.0 * m.nzones + (double)m.nfaces);
+    // 1 WENO-AO per variable: differences, large and small least squares,
+    // smoothness forms, weights and the adaptive-order blend
+    double wv = NS + 2 * NC * NS + 7 * 3 * 6 * 2 + 2 * NC * NC + 2 * NC + 90 + 2 * NC + 84;
+    flops[1] = zr * 8 * wv;
+    bytes[1] = 8 * (zr * (8 + 8 * NC) + m.ncol * (NC * NS + 126 + NC * NC));
+    // 2 face nodal B: both sides' WENO B at Q points, minmod, mean restore
+    flops[2] = fb * Q * (2 * 3 * 2 * (NC + 1) + 2 * 6 + 4 + 4);
+    bytes[2] = 8 * (fb * (2 * (3 + 3 * NC) + 1 + Q) + m.ncol * (2 * Q * NC + 4 * Q) + m.nae * (2 * Q * NC + 4 * Q));
+    // 3 divergence-free map + ADER-CG Picard iterations + time averages + traces
+    double init = N * (5 * 2 * NC + 3 * 2 * NIN + 8) + 3 * 2 * NIN;
+    double iter = N * ((1 + E) * MAPPED + E * (E + 1) * 24 * 2 + nnz_node * E * 8 * 2 + E * 8);
+    double avg = N * E * (FLUX + 8 + 32 * 2);
+    double trc = 6 * Q * (r.NFN * 32 * 2 + 8 * 3 * 2) + 36 * (r.NEN * 32 * 2);
+    flops[3] = zr * (init + r.order * iter + avg + trc);
+    bytes[3] = 8 * (zr * (8 * NC + 8 + 6 * Q + 6 + 3 + 6 * Q * 16 + 36 * 11) +
+                    m.ncol * (r.NOUTB * NIN + N * NC + N * 10));
+    // 4 face HLL fluxes
+    flops[4] = ff * Q * (HLL + 2 + 16);
+    bytes[4] = 8 * (ff * (2 * 16 * Q + 8 + 1) + m.ncol * 4 * Q + m.nae * 4 * Q);
+    // 5 edge EMFs (four-state solver at three Simpson points)
+    flops[5] = ee * 3 * (4 * (2 * FAST + 4 * 5 + 8) + 40);
+    bytes[5] = 8 * (ee * (3 * 4 * 11 + 1) + m.nae * 30.0 + m.nv * 18.0);
+    // 6 finite-volume update and constrained transport
+    flops[6] = zi * (8 * 6 * 2 + 8 * 2) + ff * 10;
+    bytes[6] = 8 * (zi * (6 * 8 + 8 + 3 + 8 + 1) + ff * (4 + 2 + 1));
+    (void)K;
+    return RG_OK;
+}

@@ -50,7 +50,7 @@ extern "C" rg_status rg_init_alfven(const rg_geom *g, const double *frame, doubl
     w.rho = rho; w.p = p; w.B0 = B0; w.dB = dB; w.kw = 2.0 * M_PI / wavelength; w.t = t; w.gam = gamma;
     const int K = m.K, mo = m.map_order;
     const int64_t Z = m.nzones;
-    const int na = 5, nr = 4;
+    const int na = 4, nr = 3;
     double ax[8], aw[8], rx[8], rw[8], gx[8], gw[8];
     gauss_legendre01(na, ax, aw);
     gauss_legendre01(nr, rx, rw);

@@ -43,6 +43,7 @@ void column_pass4(const Mesh &m, const HostGeom &hg, int c, HostGeom &out);
 // device step, implemented in the HIP translation unit
 rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,
                       double *Bo, void *stream);
+rg_status profile_end(rg_geom *g, double *ms, int *nsteps);
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt);
 
 }  // namespace rg

@@ -149,4 +149,9 @@ struct rg_geom {
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes
     std::vector<int> ae_rs_host; // +1 if side 1 of an angular edge is right of its direction
+    // optional per-stage timing: one set of RG_NSTAGE+1 events per recorded step
+    bool prof_on = false;
+    std::vector<void *> prof_events;
 };
+
+#define RG_NSTAGE 7

@@ -775,6 +775,17 @@ static inline unsigned nblocks(i64 n, int bs) { return (unsigned)((n + bs - 1) /
         }                                                            \
     } while (0)
 
+// stage markers for optional per-stage timing (0 bc, 1 weno, 2 face_bnodal,
+// 3 predictor, 4 face_flux, 5 edge_emf, 6 update)
+struct StageMarks {
+    hipEvent_t ev[RG_NSTAGE + 1];
+    bool on = false;
+    void mark(int i, hipStream_t st)
+    {
+        if (on) (void)hipEventRecord(ev[i], st);
+    }
+};
+
 template <int P>
 static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf, double *Uo,
                             double *Bo, hipStream_t st)
@@ -782,28 +793,67 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     const DevGeom &G = g->d;
     const int npic = prm.n_picard > 0 ? prm.n_picard : P;
     const double dt = prm.dt, gam = prm.gamma;
+    StageMarks sm;
+    if (g->prof_on) {
+        sm.on = true;
+        for (int i = 0; i <= RG_NSTAGE; i++) {
+            if (hipEventCreate(&sm.ev[i]) != hipSuccess) { set_error("hipEventCreate failed"); return RG_EDEVICE; }
+            g->prof_events.push_back((void *)sm.ev[i]);
+        }
+    }
+    sm.mark(0, st);
     bc_zones<<<nblocks(G.Z, 256), 256, 0, st>>>(G, prm.bc_kind, U, Uo);
     bc_faces<<<nblocks(G.NF, 256), 256, 0, st>>>(G, prm.bc_kind, Bf, Bo);
     RG_LAUNCH_CHECK();
+    sm.mark(1, st);
     const i64 nzr = (i64)G.ncol * (G.Nr + 2);
     weno<P><<<nblocks(nzr, 256), 256, 0, st>>>(G, Uo, g->wcoef);
     RG_LAUNCH_CHECK();
+    sm.mark(2, st);
     const i64 nbn = (i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2);
     face_bnodal<P><<<nblocks(nbn, 256), 256, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod);
     RG_LAUNCH_CHECK();
+    sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
     predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, Bo, g->wcoef, g->bnod, g->zoneB,
                                                                     g->ftr, g->etr);
     RG_LAUNCH_CHECK();
+    sm.mark(4, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     face_flux<P><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, g->ftr, g->Phi);
+    RG_LAUNCH_CHECK();
+    sm.mark(5, st);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     edge_emf<<<nblocks(nee, 256), 256, 0, st>>>(G, gam, g->etr, g->Gam);
     RG_LAUNCH_CHECK();
+    sm.mark(6, st);
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
     face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
     RG_LAUNCH_CHECK();
+    sm.mark(7, st);
     return RG_OK;
+}
+
+rg_status profile_end(rg_geom *g, double *ms, int *nsteps)
+{
+    for (int i = 0; i < RG_NSTAGE; i++) ms[i] = 0.0;
+    const size_t per = RG_NSTAGE + 1, n = g->prof_events.size() / per;
+    rg_status st = RG_OK;
+    for (size_t s = 0; s < n; s++) {
+        hipEvent_t *ev = reinterpret_cast<hipEvent_t *>(&g->prof_events[s * per]);
+        if (hipEventSynchronize(ev[RG_NSTAGE]) != hipSuccess) st = RG_EDEVICE;
+        for (int i = 0; i < RG_NSTAGE && st == RG_OK; i++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = RG_EDEVICE;
+            ms[i] += t;
+        }
+    }
+    for (void *e : g->prof_events) (void)hipEventDestroy((hipEvent_t)e);
+    g->prof_events.clear();
+    g->prof_on = false;
+    *nsteps = (int)n;
+    if (st != RG_OK) set_error("reading the stage timers failed");
+    return st;
 }
 
 rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo, double *Bo,
