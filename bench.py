@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--cfl", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the step is one GPU's share of the mesh); got --gpus {args.gpus}",
@@ -88,6 +90,13 @@ def main():
     U2 = torch.empty_like(U)
     Bf2 = torch.empty_like(Bf)
     gam = prob["gamma"]
+    if args.calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     dt = shell.cfl_dt(U, args.cfl, gam)
     for _ in range(args.warmup):
         shell.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
