@@ -234,17 +234,39 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                 }
             }
 
-        // derivative matrices in compressed rows (node i, direction d)
-        std::vector<int> dptr(N * 3 + 1, 0), dcol;
-        std::vector<double> dval;
-        for (int i = 0; i < N; i++)
-            for (int d = 0; d < 3; d++) {
+        // derivative matrices as padded rows per node over the three directions;
+        // an entry addresses the node-fastest flux slab in the predictor's LDS
+        int NZ = 0;
+        for (int i = 0; i < N; i++) {
+            int n = 0;
+            for (int d = 0; d < 3; d++)
+                for (int l = 0; l < N; l++) n += r.D[((size_t)d * N + i) * N + l] != 0.0;
+            NZ = std::max(NZ, n);
+        }
+        std::vector<int> doff((size_t)N * NZ);
+        std::vector<double> dval((size_t)N * NZ);
+        for (int i = 0; i < N; i++) {
+            int n = 0;
+            for (int d = 0; d < 3; d++)
                 for (int l = 0; l < N; l++) {
                     double v = r.D[((size_t)d * N + i) * N + l];
-                    if (v != 0.0) { dcol.push_back(l); dval.push_back(v); }
+                    if (v != 0.0) { doff[(size_t)i * NZ + n] = d * 8 * N + l; dval[(size_t)i * NZ + n] = v; n++; }
                 }
-                dptr[i * 3 + d + 1] = (int)dcol.size();
-            }
+            for (; n < NZ; n++) { doff[(size_t)i * NZ + n] = i; dval[(size_t)i * NZ + n] = 0.0; }
+        }
+        // node-fastest / output-fastest copies of the per-column matrices
+        std::vector<double> EvT((size_t)ncol * NC * N), MbT((size_t)ncol * r.NIN * r.NOUTB), nMT((size_t)ncol * 9 * N);
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncol; c++) {
+            for (int i = 0; i < N; i++)
+                for (int a = 0; a < NC; a++) EvT[((size_t)c * NC + a) * N + i] = hg.Ev[((size_t)c * N + i) * NC + a];
+            for (int o = 0; o < r.NOUTB; o++)
+                for (int j = 0; j < r.NIN; j++)
+                    MbT[((size_t)c * r.NIN + j) * r.NOUTB + o] = hg.Mb[((size_t)c * r.NOUTB + o) * r.NIN + j];
+            for (int i = 0; i < N; i++)
+                for (int mm = 0; mm < 9; mm++) nMT[((size_t)c * 9 + mm) * N + i] = hg.nM[((size_t)c * N + i) * 9 + mm];
+        }
+        std::vector<double>().swap(hg.Mb);
         std::vector<double> Rv = r.R, wt = r.wt, radius = m.radius, zs(zscale.begin(), zscale.end() - 1);
         std::vector<int> vncol = m.v_ncol, aecol = m.ae_col, aev = m.ae_v;
 
@@ -256,14 +278,13 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         d.order = order; d.N = N; d.M = r.M; d.NC = NC; d.NB = r.NB; d.Q = Q; d.NS = NS;
         d.NIN = r.NIN; d.NOUTB = r.NOUTB; d.NFN = r.NFN; d.NEN = r.NEN;
         d.Nang = m.N; d.Nr = m.Nr; d.g = m.g; d.K = K; d.ncol = ncol; d.nv = nv; d.nae = nae;
-        d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre;
+        d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre; d.NZ = NZ;
         bool ok = upload(g, radius, &d.radius) && upload(g, zs, &d.zscale) && upload(g, Rv, &d.R) &&
-                  upload(g, wt, &d.wt) && upload(g, dptr, &d.dptr) && upload(g, dcol, &d.dcol) &&
-                  upload(g, dval, &d.dval) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
+                  upload(g, wt, &d.wt) && upload(g, doff, &d.doff) && upload(g, dval, &d.dval) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
                   upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, hg.stm, &d.stm) &&
                   upload(g, hg.Pl, &d.Pl) && upload(g, hg.Ps, &d.Ps) && upload(g, hg.Qs, &d.Qs) &&
-                  upload(g, hg.Ev, &d.Ev) && upload(g, hg.Mb, &d.Mb) && upload(g, hg.nJ, &d.nJ) &&
-                  upload(g, hg.nM, &d.nM) && upload(g, hg.fevR, &d.fevR) && upload(g, hg.fnR, &d.fnR) &&
+                  upload(g, EvT, &d.Ev) && upload(g, MbT, &d.Mb) && upload(g, hg.nJ, &d.nJ) &&
+                  upload(g, nMT, &d.nM) && upload(g, hg.fevR, &d.fevR) && upload(g, hg.fnR, &d.fnR) &&
                   upload(g, hg.fwR, &d.fwR) && upload(g, hg.col_ae, &d.col_ae) &&
                   upload(g, hg.col_side, &d.col_side) && upload(g, hg.col_perm, &d.col_perm) &&
                   upload(g, hg.col_v, &d.col_v) && upload(g, hg.col_slot, &d.col_slot) &&

@@ -83,9 +83,9 @@ struct DevGeom {
     const double *zscale;   // K: zone length scale relative to shell 0
     const double *R;        // (M-1) x M
     const double *wt;       // M
-    const int *dptr;        // N*3 + 1 CSR row pointers of the derivative matrices
-    const int *dcol;        // CSR columns
-    const double *dval;     // CSR values
+    const int *doff;        // N x NZ  derivative entries per node: (d * 8) * N + l, padded with i
+    const double *dval;     // N x NZ  values D_d[i][l], padded with 0
+    int NZ;                 // entries per node (padded)
     const int *fnode;       // 6 x NFN
     const double *fint;     // 6 x Q x NFN
     const int *enode;       // 12 x NEN
@@ -95,10 +95,10 @@ struct DevGeom {
     const double *Pl;       // ncol x NC x NS
     const double *Ps;       // ncol x 7 x 3 x 6
     const double *Qs;       // ncol x NC x NC
-    const double *Ev;       // ncol x N x NC
-    const double *Mb;       // ncol x NOUTB x NIN
+    const double *Ev;       // ncol x NC x N      Taylor basis at the ADER nodes (node fastest)
+    const double *Mb;       // ncol x NIN x NOUTB divergence-free map, transposed (output fastest)
     const double *nJ;       // ncol x N
-    const double *nM;       // ncol x N x 9   (J a^d)_n
+    const double *nM;       // ncol x 9 x N       (J a^d)_n at the nodes (node fastest)
     const double *fevR;     // ncol x 2 x Q x NC
     const double *fnR;      // ncol x Q x 3
     const double *fwR;      // ncol x Q

@@ -20,11 +20,11 @@ template <int P>
 struct Tr;
 template <>
 struct Tr<3> {
-    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3;
+    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3, NZ = 18;
 };
 template <>
 struct Tr<4> {
-    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4;
+    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4, NZ = 20;
 };
 
 typedef long long i64;
@@ -141,22 +141,26 @@ __global__ __launch_bounds__(256) void weno(DevGeom G, const double *__restrict_
     if (t >= (i64)G.ncol * KR) return;
     int c = (int)(t / KR), k = G.g - 1 + (int)(t % KR);
     i64 z = (i64)c * G.K + k;
-    i64 zj[T::NS];
+    int dz[T::NS];   // member zone minus this zone (fits 32 bits)
 #pragma unroll
     for (int j = 0; j < T::NS; j++) {
         int m = G.stm[(i64)c * T::NS + j];
-        zj[j] = m < 0 ? z : (i64)(m >> 3) * G.K + k + (m & 7) - 3;
+        dz[j] = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
     }
     const double *Pl = G.Pl + (i64)c * T::NC * T::NS;
     const double *Ps = G.Ps + (i64)c * 7 * 18;
     const double *Qs = G.Qs + (i64)c * T::NC * T::NC;
     const double gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+#pragma unroll 1
     for (int v = 0; v < 8; v++) {
+        // keep the column matrices from being hoisted out of the variable loop
+        // (they would not fit in registers); they are re-read from cache
+        __asm__ __volatile__("" ::: "memory");
         const double *Uv = U + v * G.Z;
         double u0 = Uv[z];
         double du[T::NS];
 #pragma unroll
-        for (int j = 0; j < T::NS; j++) du[j] = Uv[zj[j]] - u0;
+        for (int j = 0; j < T::NS; j++) du[j] = Uv[z + dz[j]] - u0;
         double chi[T::NC];
 #pragma unroll
         for (int a = 0; a < T::NC; a++) {
@@ -242,31 +246,41 @@ __global__ __launch_bounds__(256) void face_bnodal(DevGeom G, const double *__re
         fw = G.fwA + (i64)ae * T::Q;
     }
     double mean = Bf[f];
+    // both sides' WENO B at the Q points: every coefficient is read once
+    double Bq[2][3][T::Q];
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        if (!have[s]) continue;
+#pragma unroll
+        for (int c3 = 0; c3 < 3; c3++) {
+            double m0 = U[(5 + c3) * G.Z + z[s]];
+#pragma unroll
+            for (int q = 0; q < T::Q; q++) Bq[s][c3][q] = m0;
+            const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z[s];
+            for (int a = 0; a < T::NC; a++) {
+                double ca = cf[(i64)a * G.Z];
+#pragma unroll
+                for (int q = 0; q < T::Q; q++) Bq[s][c3][q] += ca * fev[s][q * T::NC + a];
+            }
+        }
+    }
     double bn[T::Q];
 #pragma unroll
     for (int q = 0; q < T::Q; q++) {
         double d[2] = {0.0, 0.0};
-        for (int s = 0; s < 2; s++) {
-            if (!have[s]) continue;
-            double B[3];
-            for (int c3 = 0; c3 < 3; c3++) {
-                double acc = U[(5 + c3) * G.Z + z[s]];
-                const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z[s];
 #pragma unroll
-                for (int a = 0; a < T::NC; a++) acc += cf[(i64)a * G.Z] * fev[s][q * T::NC + a];
-                B[c3] = acc;
-            }
-            d[s] = B[0] * nrm[q * 3] + B[1] * nrm[q * 3 + 1] + B[2] * nrm[q * 3 + 2] - mean;
-        }
+        for (int s = 0; s < 2; s++)
+            if (have[s])
+                d[s] = Bq[s][0][q] * nrm[q * 3] + Bq[s][1][q] * nrm[q * 3 + 1] + Bq[s][2][q] * nrm[q * 3 + 2] - mean;
         if (!have[0]) d[0] = d[1];
         if (!have[1]) d[1] = d[0];
         bn[q] = mean + dev_minmod(d[0], d[1]);
     }
-    double s = 0.0;
+    double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < T::Q; q++) s += fw[q] * bn[q];
+    for (int q = 0; q < T::Q; q++) sum += fw[q] * bn[q];
 #pragma unroll
-    for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = bn[q] + (mean - s);
+    for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = bn[q] + (mean - sum);
 }
 
 // ---------------------------------------------------------------- predictor
@@ -277,11 +291,10 @@ __constant__ int LE_UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
 __constant__ int LE_CORNER[4] = {0, 1, 3, 2};
 
 template <int P>
-__device__ __forceinline__ void mapped_flux(const double *u, double J, const double *met, double fac, double gam,
+__device__ __forceinline__ void mapped_flux(const double *u, double iJ, const double *met, double fac, double gam,
                                             double out[3][8])
 {
     double w[8], F[3][8];
-    double iJ = 1.0 / J;
 #pragma unroll
     for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
     dev_flux(w, gam, F);
@@ -292,6 +305,10 @@ __device__ __forceinline__ void mapped_flux(const double *u, double J, const dou
             out[d][v] = fac * (met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v]);
 }
 
+// One wavefront holds 64 / N zones, one lane per serendipity node.  The
+// nodal fluxes of every time level are exchanged through LDS (node fastest)
+// and the derivative matrices are applied level by level, so each lane keeps
+// only its own node's state in registers.
 template <int P>
 __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam, int npic, const double *__restrict__ U,
                                                 const double *__restrict__ Bf, const double *__restrict__ wc,
@@ -299,10 +316,10 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
                                                 double *__restrict__ ftr, double *__restrict__ etr)
 {
     using T = Tr<P>;
-    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1;
-    constexpr int XS = E * 24;           // exchange words per node
+    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ;
+    constexpr int SLAB = 24 * N;             // one time level: [d * 8 + v][node]
     __shared__ double s_in[ZPW][T::NIN];
-    __shared__ double s_x[ZPW][N][XS];
+    __shared__ double s_f[ZPW][E * SLAB];
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
@@ -310,18 +327,16 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
     const bool active = (zl < ZPW) && (zt < nzr);
     int c = 0, k = 0;
     i64 z = 0;
+    i64 fid[6];
     if (active) {
         c = (int)(zt / KR);
         k = G.g - 1 + (int)(zt % KR);
         z = (i64)c * G.K + k;
-    }
-    // face ids of the six local faces
-    i64 fid[6];
-    if (active) {
         for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
         fid[4] = (i64)c * (G.K + 1) + k;
         fid[5] = fid[4] + 1;
-        // inputs of the divergence-free map
+        // inputs of the divergence-free map: WENO B (mean + coefficients),
+        // limited face nodal values, face means
         for (int j = i; j < T::NIN; j += N) {
             double val;
             if (j < 3 * (T::NC + 1)) {
@@ -331,102 +346,112 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
                 int jj = j - 3 * (T::NC + 1), lf = jj / T::Q, qc = jj % T::Q;
                 val = bnod[(i64)qc * G.NF + fid[lf]];
             } else {
-                int lf = j - 3 * (T::NC + 1) - 6 * T::Q;
-                val = Bf[fid[lf]];
+                val = Bf[fid[j - 3 * (T::NC + 1) - 6 * T::Q]];
             }
             s_in[zl][j] = val;
         }
     }
     __syncthreads();
 
-    double Ua[8], Ut[E][8], J = 1.0, met[9], fac = 0.0;
+    double Ua[8], Ut[E][8], dFa[8], met[9], iJ = 1.0, fac = 0.0;
+    int doff[NZ];
+    double dv[NZ];
+#pragma unroll
+    for (int p = 0; p < NZ; p++) {
+        doff[p] = G.doff[i * NZ + p];
+        dv[p] = G.dval[i * NZ + p];
+    }
     if (active) {
-        const double *Ev = G.Ev + ((i64)c * N + i) * T::NC;
+        const double *Ev = G.Ev + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
             double acc = U[v * G.Z + z];
             const double *cf = wc + (i64)v * T::NC * G.Z + z;
 #pragma unroll
-            for (int a = 0; a < T::NC; a++) acc += Ev[a] * cf[(i64)a * G.Z];
+            for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * cf[(i64)a * G.Z];
             Ua[v] = acc;
         }
-        const double *Mb = G.Mb + (i64)c * T::NOUTB * T::NIN;
-        for (int comp = 0; comp < 3; comp++) {
-            const double *row = Mb + (i64)(comp * N + i) * T::NIN;
-            double acc = 0.0;
+        const double *Mb = G.Mb + (i64)c * T::NIN * T::NOUTB;
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, bm = 0.0;
+        const int mrow = 3 * N + (i < 3 ? i : 0);
 #pragma unroll 4
-            for (int j = 0; j < T::NIN; j++) acc += row[j] * s_in[zl][j];
-            Ua[5 + comp] = acc;
+        for (int j = 0; j < T::NIN; j++) {
+            double x = s_in[zl][j];
+            const double *row = Mb + (i64)j * T::NOUTB;
+            b0 += row[i] * x;
+            b1 += row[N + i] * x;
+            b2 += row[2 * N + i] * x;
+            bm += row[mrow] * x;
         }
-        if (i < 3) {
-            const double *row = Mb + (i64)(3 * N + i) * T::NIN;
-            double acc = 0.0;
-            for (int j = 0; j < T::NIN; j++) acc += row[j] * s_in[zl][j];
-            zoneB[(i64)i * G.Z + z] = acc;
-        }
-        J = G.nJ[(i64)c * N + i];
-        for (int m = 0; m < 9; m++) met[m] = G.nM[((i64)c * N + i) * 9 + m];
+        Ua[5] = b0;
+        Ua[6] = b1;
+        Ua[7] = b2;
+        if (i < 3) zoneB[(i64)i * G.Z + z] = bm;
+        double J = G.nJ[(i64)c * N + i];
+        iJ = 1.0 / J;
+#pragma unroll
+        for (int m = 0; m < 9; m++) met[m] = G.nM[((i64)c * 9 + m) * N + i];
         fac = dt / G.zscale[k];
 #pragma unroll
         for (int v = 0; v < 8; v++) Ua[v] *= J;
+        // level tau = 0: its flux derivative is the same in every iteration
+        double F[3][8];
+        mapped_flux<P>(Ua, iJ, met, fac, gam, F);
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) s_f[zl][(d * 8 + v) * N + i] = F[d][v];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < 8; v++) dFa[v] = 0.0;
+#pragma unroll
+        for (int p = 0; p < NZ; p++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) dFa[v] += dv[p] * s_f[zl][doff[p] + v * N];
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
             for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v];
     }
-    const int *dptr = G.dptr;
+    __syncthreads();
     for (int it = 0; it < npic; it++) {
         if (active) {
-            double Gx[E][3][8], F[3][8];
-            mapped_flux<P>(Ua, J, met, fac, gam, F);
 #pragma unroll
-            for (int t = 0; t < E; t++) {
-                double r = G.R[t * T::M + 0];
+            for (int s = 0; s < E; s++) {
+                double F[3][8];
+                mapped_flux<P>(Ut[s], iJ, met, fac, gam, F);
 #pragma unroll
                 for (int d = 0; d < 3; d++)
 #pragma unroll
-                    for (int v = 0; v < 8; v++) Gx[t][d][v] = r * F[d][v];
+                    for (int v = 0; v < 8; v++) s_f[zl][s * SLAB + (d * 8 + v) * N + i] = F[d][v];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < E; t++) {
+                double r = G.R[t * T::M];
+#pragma unroll
+                for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - r * dFa[v];
             }
 #pragma unroll
             for (int s = 0; s < E; s++) {
-                mapped_flux<P>(Ut[s], J, met, fac, gam, F);
+                double acc[8];
+#pragma unroll
+                for (int v = 0; v < 8; v++) acc[v] = 0.0;
+                const double *slab = &s_f[zl][s * SLAB];
+#pragma unroll
+                for (int p = 0; p < NZ; p++)
+#pragma unroll
+                    for (int v = 0; v < 8; v++) acc[v] += dv[p] * slab[doff[p] + v * N];
 #pragma unroll
                 for (int t = 0; t < E; t++) {
                     double r = G.R[t * T::M + s + 1];
 #pragma unroll
-                    for (int d = 0; d < 3; d++)
-#pragma unroll
-                        for (int v = 0; v < 8; v++) Gx[t][d][v] += r * F[d][v];
+                    for (int v = 0; v < 8; v++) Ut[t][v] -= r * acc[v];
                 }
             }
-#pragma unroll
-            for (int t = 0; t < E; t++)
-#pragma unroll
-                for (int d = 0; d < 3; d++)
-#pragma unroll
-                    for (int v = 0; v < 8; v++) s_x[zl][i][(t * 3 + d) * 8 + v] = Gx[t][d][v];
-        }
-        __syncthreads();
-        if (active) {
-            double acc[E][8];
-#pragma unroll
-            for (int t = 0; t < E; t++)
-#pragma unroll
-                for (int v = 0; v < 8; v++) acc[t][v] = 0.0;
-            for (int d = 0; d < 3; d++) {
-                int r0 = dptr[i * 3 + d], r1 = dptr[i * 3 + d + 1];
-                for (int p = r0; p < r1; p++) {
-                    int l = G.dcol[p];
-                    double dv = G.dval[p];
-#pragma unroll
-                    for (int t = 0; t < E; t++)
-#pragma unroll
-                        for (int v = 0; v < 8; v++) acc[t][v] += dv * s_x[zl][l][(t * 3 + d) * 8 + v];
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < E; t++)
-#pragma unroll
-                for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - acc[t][v];
         }
         __syncthreads();
     }
@@ -435,7 +460,6 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
         double aU[8], aF[3][8], w[8], F[3][8];
 #pragma unroll
         for (int v = 0; v < 8; v++) { aU[v] = 0.0; aF[0][v] = aF[1][v] = aF[2][v] = 0.0; }
-        double iJ = 1.0 / J;
 #pragma unroll
         for (int t = 0; t < E; t++) {
             double wt = G.wt[t + 1];
@@ -452,32 +476,32 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
         }
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            s_x[zl][i][v] = aU[v];
-            s_x[zl][i][8 + v] = aF[0][v];
-            s_x[zl][i][16 + v] = aF[1][v];
-            s_x[zl][i][24 + v] = aF[2][v];
+            s_f[zl][v * N + i] = aU[v];
+            s_f[zl][(8 + v) * N + i] = aF[0][v];
+            s_f[zl][(16 + v) * N + i] = aF[1][v];
+            s_f[zl][(24 + v) * N + i] = aF[2][v];
         }
     }
     __syncthreads();
     if (!active) return;
     // traces: face quadrature points, then edge Simpson points
+    const double *sx = s_f[zl];
     const int nwork = 6 * T::Q + 36;
     for (int w = i; w < nwork; w += N) {
+        double Uq[8], Fq[3][8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
         if (w < 6 * T::Q) {
             int lf = w / T::Q, ql = w % T::Q;
-            double Uq[8], Fq[3][8];
-#pragma unroll
-            for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
             for (int kk = 0; kk < T::NFN; kk++) {
                 int l = G.fnode[lf * T::NFN + kk];
                 double wgt = G.fint[(lf * T::Q + ql) * T::NFN + kk];
-                const double *sx = s_x[zl][l];
 #pragma unroll
                 for (int v = 0; v < 8; v++) {
-                    Uq[v] += wgt * sx[v];
-                    Fq[0][v] += wgt * sx[8 + v];
-                    Fq[1][v] += wgt * sx[16 + v];
-                    Fq[2][v] += wgt * sx[24 + v];
+                    Uq[v] += wgt * sx[v * N + l];
+                    Fq[0][v] += wgt * sx[(8 + v) * N + l];
+                    Fq[1][v] += wgt * sx[(16 + v) * N + l];
+                    Fq[2][v] += wgt * sx[(24 + v) * N + l];
                 }
             }
             int qc, side;
@@ -491,27 +515,23 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
                 side = G.col_side[4 * c + lf];
                 n = G.fnA + ((i64)G.col_ae[4 * c + lf] * T::Q + qc) * 3;
             }
-            i64 f = fid[lf];
+            double *o = ftr + ((fid[lf] * 2 + side) * T::Q + qc) * 16;
 #pragma unroll
             for (int v = 0; v < 8; v++) {
-                ftr[((i64)(v * T::Q + qc) * 2 + side) * G.NF + f] = Uq[v];
-                ftr[((i64)((8 + v) * T::Q + qc) * 2 + side) * G.NF + f] = n[0] * Fq[0][v] + n[1] * Fq[1][v] + n[2] * Fq[2][v];
+                o[v] = Uq[v];
+                o[8 + v] = n[0] * Fq[0][v] + n[1] * Fq[1][v] + n[2] * Fq[2][v];
             }
         } else {
             int we = w - 6 * T::Q, le = we / 3, pl = we % 3;
-            double Uq[8], Fq[3][8];
-#pragma unroll
-            for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
             for (int kk = 0; kk < T::NEN; kk++) {
                 int l = G.enode[le * T::NEN + kk];
                 double wgt = G.eint[(le * 3 + pl) * T::NEN + kk];
-                const double *sx = s_x[zl][l];
 #pragma unroll
                 for (int v = 0; v < 8; v++) {
-                    Uq[v] += wgt * sx[v];
-                    Fq[0][v] += wgt * sx[8 + v];
-                    Fq[1][v] += wgt * sx[16 + v];
-                    Fq[2][v] += wgt * sx[24 + v];
+                    Uq[v] += wgt * sx[v * N + l];
+                    Fq[0][v] += wgt * sx[(8 + v) * N + l];
+                    Fq[1][v] += wgt * sx[(16 + v) * N + l];
+                    Fq[2][v] += wgt * sx[(24 + v) * N + l];
                 }
             }
             int rev = G.col_rev[(i64)c * 12 + le], slot = G.col_slot[(i64)c * 12 + le];
@@ -523,14 +543,12 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
             } else {
                 e = (i64)G.col_v[4 * c + LE_CORNER[le - 8]] * G.K + k;
             }
-            double vals[11];
+            double *o = etr + ((e * 4 + slot) * 3 + pc) * 11;
 #pragma unroll
-            for (int v = 0; v < 8; v++) vals[v] = Uq[v];
-            vals[8] = Fq[2][6];   // E_x = H[B_y]
-            vals[9] = Fq[0][7];   // E_y = F[B_z]
-            vals[10] = Fq[1][5];  // E_z = G[B_x]   (eq. 2.3)
-#pragma unroll
-            for (int v = 0; v < 11; v++) etr[((i64)(v * 3 + pc) * 4 + slot) * G.NE + e] = vals[v];
+            for (int v = 0; v < 8; v++) o[v] = Uq[v];
+            o[8] = Fq[2][6];   // E_x = H[B_y]
+            o[9] = Fq[0][7];   // E_y = F[B_z]
+            o[10] = Fq[1][5];  // E_z = G[B_x]   (eq. 2.3)
         }
     }
 }
@@ -567,10 +585,11 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const do
         double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            UL[v] = ftr[((i64)(v * T::Q + q) * 2 + 0) * G.NF + f];
-            UR[v] = ftr[((i64)(v * T::Q + q) * 2 + 1) * G.NF + f];
-            FL[v] = ftr[((i64)((8 + v) * T::Q + q) * 2 + 0) * G.NF + f];
-            FR[v] = ftr[((i64)((8 + v) * T::Q + q) * 2 + 1) * G.NF + f];
+            const double *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
+            UL[v] = a[v];
+            FL[v] = a[8 + v];
+            UR[v] = b[v];
+            FR[v] = b[8 + v];
         }
         dev_hll(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
         double w = fw[q] * area;
@@ -607,7 +626,7 @@ __device__ __forceinline__ double emf4(const double U[4][8], const double Et[4],
 }
 
 // three zones about an edge: mean of the 1-D HLL induction fluxes of the three faces
-__device__ double emf3(const double U[4][8], const double E[4][3], const double *N3, const double *t, double gam)
+__device__ __forceinline__ double emf3(const double U[4][8], const double E[4][3], const double *N3, const double *t, double gam)
 {
     double acc = 0.0;
     for (int s = 0; s < 3; s++) {
@@ -659,11 +678,14 @@ __global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const dou
     for (int p = 0; p < 3; p++) {
         double U[4][8], E[4][3], Et[4];
         const double *tt = frame[p] + 6;
-        for (int s = 0; s < nzs; s++) {
+        // all four slots are read (a three-zone edge leaves slot 3 unused)
 #pragma unroll
-            for (int v = 0; v < 8; v++) U[s][v] = etr[((i64)(v * 3 + p) * 4 + s) * G.NE + e];
+        for (int s = 0; s < 4; s++) {
+            const double *rec = etr + ((e * 4 + s) * 3 + p) * 11;
 #pragma unroll
-            for (int v = 0; v < 3; v++) E[s][v] = etr[((i64)((8 + v) * 3 + p) * 4 + s) * G.NE + e];
+            for (int v = 0; v < 8; v++) U[s][v] = rec[v];
+#pragma unroll
+            for (int v = 0; v < 3; v++) E[s][v] = rec[8 + v];
             Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
         }
         double Es = (nzs == 4) ? emf4(U, Et, frame[p], gam) : emf3(U, E, N3, tt, gam);
