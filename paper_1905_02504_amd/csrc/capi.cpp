@@ -243,16 +243,26 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                 for (int l = 0; l < N; l++) n += r.D[((size_t)d * N + i) * N + l] != 0.0;
             NZ = std::max(NZ, n);
         }
+        // Each entry packs twice the value (an integer: the entries are
+        // multiples of 1/2) in the high 16 bits and the slab offset d*8*N + l
+        // in the low 16 bits.
         std::vector<int> doff((size_t)N * NZ);
-        std::vector<double> dval((size_t)N * NZ);
         for (int i = 0; i < N; i++) {
             int n = 0;
             for (int d = 0; d < 3; d++)
                 for (int l = 0; l < N; l++) {
                     double v = r.D[((size_t)d * N + i) * N + l];
-                    if (v != 0.0) { doff[(size_t)i * NZ + n] = d * 8 * N + l; dval[(size_t)i * NZ + n] = v; n++; }
+                    if (v != 0.0) {
+                        int twice = (int)std::lround(2.0 * v);
+                        if (2.0 * v != (double)twice || std::abs(twice) > 32767 || d * 8 * N + l > 65535) {
+                            set_error("derivative matrix entry is not a small multiple of 1/2");
+                            return RG_EINVAL;
+                        }
+                        doff[(size_t)i * NZ + n] = (int)((unsigned)twice << 16) | (d * 8 * N + l);
+                        n++;
+                    }
                 }
-            for (; n < NZ; n++) { doff[(size_t)i * NZ + n] = i; dval[(size_t)i * NZ + n] = 0.0; }
+            for (; n < NZ; n++) doff[(size_t)i * NZ + n] = i;
         }
         // node-fastest / output-fastest copies of the per-column matrices
         std::vector<double> EvT((size_t)ncol * NC * N), MbT((size_t)ncol * r.NIN * r.NOUTB), nMT((size_t)ncol * 9 * N);
@@ -280,7 +290,7 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         d.Nang = m.N; d.Nr = m.Nr; d.g = m.g; d.K = K; d.ncol = ncol; d.nv = nv; d.nae = nae;
         d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre; d.NZ = NZ;
         bool ok = upload(g, radius, &d.radius) && upload(g, zs, &d.zscale) && upload(g, Rv, &d.R) &&
-                  upload(g, wt, &d.wt) && upload(g, doff, &d.doff) && upload(g, dval, &d.dval) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
+                  upload(g, wt, &d.wt) && upload(g, doff, &d.doff) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
                   upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, hg.stm, &d.stm) &&
                   upload(g, hg.Pl, &d.Pl) && upload(g, hg.Ps, &d.Ps) && upload(g, hg.Qs, &d.Qs) &&
                   upload(g, EvT, &d.Ev) && upload(g, MbT, &d.Mb) && upload(g, hg.nJ, &d.nJ) &&
@@ -298,7 +308,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         ok = alloc_zero(g, (size_t)NVAR * NC * Z, &g->wcoef) && alloc_zero(g, (size_t)Q * NF, &g->bnod) &&
              alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &g->etr) &&
              alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
-             alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red);
+             alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red) &&
+             alloc_zero(g, (size_t)ncol * (m.Nr + 2) * 3 * N, &g->bnode);
         if (!ok) { set_error("device allocation of the step work buffers failed"); free_geom(g); return RG_ENOMEM; }
     } catch (const std::bad_alloc &) {
         set_error("out of host memory");

@@ -83,8 +83,8 @@ struct DevGeom {
     const double *zscale;   // K: zone length scale relative to shell 0
     const double *R;        // (M-1) x M
     const double *wt;       // M
-    const int *doff;        // N x NZ  derivative entries per node: (d * 8) * N + l, padded with i
-    const double *dval;     // N x NZ  values D_d[i][l], padded with 0
+    const int *doff;        // N x NZ  derivative entries per node: (2 D_d[i][l]) << 16 | (d * 8) * N + l,
+                            //         padded with i (value 0)
     int NZ;                 // entries per node (padded)
     const int *fnode;       // 6 x NFN
     const double *fint;     // 6 x Q x NFN
@@ -146,6 +146,7 @@ struct rg_geom {
     // work buffers (device)
     double *wcoef = nullptr, *bnod = nullptr, *ftr = nullptr, *etr = nullptr;
     double *Phi = nullptr, *Gam = nullptr, *zoneB = nullptr, *red = nullptr;
+    double *bnode = nullptr;   // divergence-free B at the ADER nodes, [recon zone][3N]
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes
     std::vector<int> ae_rs_host; // +1 if side 1 of an angular edge is right of its direction

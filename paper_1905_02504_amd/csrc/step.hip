@@ -305,21 +305,112 @@ __device__ __forceinline__ void mapped_flux(const double *u, double iJ, const do
             out[d][v] = fac * (met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v]);
 }
 
-// One wavefront holds 64 / N zones, one lane per serendipity node.  The
-// nodal fluxes of every time level are exchanged through LDS (node fastest)
-// and the derivative matrices are applied level by level, so each lane keeps
-// only its own node's state in registers.
+// Divergence-free B (Section IV.b): for every zone of a column the fused
+// per-column map (KKT inverse followed by evaluation at the ADER nodes and the
+// new zone mean) is applied to the zone's inputs -- its WENO B, the limited
+// nodal normal B of its six faces and their face averages.  Per column this is
+// a dense product Out^T (NOUTB x zones) = Mb^T (NOUTB x NIN) In^T (NIN x zones),
+// done on the FP64 matrix cores: one wavefront owns 16 zones of a column and
+// all output rows, stepping through the inputs four at a time
+// (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16 (i % 4), element i / 4).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 template <int P>
-__global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam, int npic, const double *__restrict__ U,
-                                                const double *__restrict__ Bf, const double *__restrict__ wc,
-                                                const double *__restrict__ bnod, double *__restrict__ zoneB,
+__global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
+                                           const double *__restrict__ wc, const double *__restrict__ bnod,
+                                           double *__restrict__ bnode, double *__restrict__ zoneB)
+{
+    using T = Tr<P>;
+    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16;
+    constexpr int NA = 3 * (T::NC + 1), NQ = NA + 6 * T::Q;
+    static_assert(NIN % 4 == 0, "input count must be a multiple of 4");
+    const int KR = G.Nr + 2, nt = (KR + 15) / 16;
+    const int c = blockIdx.x / nt, tile = blockIdx.x % nt;
+    const int l = threadIdx.x, g = l >> 4, jz = l & 15;
+    const int kk = tile * 16 + jz;
+    const bool active = kk < KR;
+    const int k = G.g - 1 + (active ? kk : 0);
+    const i64 z = (i64)c * G.K + k;
+    const i64 fr = (i64)c * (G.K + 1) + k;
+    i64 fa[4];
+#pragma unroll
+    for (int lf = 0; lf < 4; lf++) fa[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    const double *Mb = G.Mb + (i64)c * NIN * NOUT;
+    dbl4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; m++) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int s = 0; s < KT; s++) {
+        // B operand: input j = 4s + g of zone jz
+        const int j = 4 * s + g;
+        const double *src;
+        i64 idx;
+        if (j < NA) {
+            int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+            src = a == 0 ? U + (i64)(5 + comp) * G.Z : wc + ((i64)(5 + comp) * T::NC + a - 1) * G.Z;
+            idx = z;
+        } else {
+            int lf, qc = 0;
+            if (j < NQ) { lf = (j - NA) / T::Q; qc = (j - NA) % T::Q; src = bnod + (i64)qc * G.NF; }
+            else { lf = j - NQ; src = Bf; }
+            idx = lf == 4 ? fr : lf == 5 ? fr + 1 : lf == 0 ? fa[0] : lf == 1 ? fa[1] : lf == 2 ? fa[2] : fa[3];
+        }
+        const double b = active ? src[idx] : 0.0;
+        const double *mrow = Mb + (i64)j * NOUT;
+#pragma unroll
+        for (int m = 0; m < MT; m++) {
+            const int r = m * 16 + jz;
+            const double a = (m < MT - 1 || r < NOUT) ? mrow[r] : 0.0;
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
+        }
+    }
+    if (!active) return;
+    const i64 zr = (i64)c * KR + kk;
+#pragma unroll
+    for (int m = 0; m < MT; m++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = m * 16 + g + 4 * v;
+            if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = acc[m][v];
+            else if (r < NOUT) zoneB[(i64)(r - 3 * T::N) * G.Z + z] = acc[m][v];
+        }
+}
+
+// acc += (D_xi F_xi + D_eta F_eta + D_zeta F_zeta) at this lane's node, the
+// fluxes read from the node-fastest LDS slab.  The packed entries hold twice
+// the matrix value; halving the sum at the end is exact.
+template <int N, int NZ>
+__device__ __forceinline__ void apply_d(const int (&dpk)[NZ], const double *sf, double (&acc)[8])
+{
+    double s[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) s[v] = 0.0;
+#pragma unroll
+    for (int p = 0; p < NZ; p++) {
+        int pk = dpk[p];
+        double dv = (double)(pk >> 16);
+        const double *col = sf + (pk & 0xffff);
+#pragma unroll
+        for (int v = 0; v < 8; v++) s[v] += dv * col[v * N];
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] += 0.5 * s[v];
+}
+
+// ADER-CG predictor (Section V.d).  One wavefront holds 64 / N zones, one lane
+// per serendipity node.  Each time level's nodal fluxes pass through LDS
+// (node fastest) and the derivative matrices are applied level by level, so a
+// lane keeps only its own node's state in registers.
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void predictor(DevGeom G, double dt, double gam, int npic, const double *__restrict__ U,
+                                                const double *__restrict__ wc, const double *__restrict__ bnode,
                                                 double *__restrict__ ftr, double *__restrict__ etr)
 {
     using T = Tr<P>;
-    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ;
-    constexpr int SLAB = 24 * N;             // one time level: [d * 8 + v][node]
-    __shared__ double s_in[ZPW][T::NIN];
-    __shared__ double s_f[ZPW][E * SLAB];
+    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ, NCF = T::NC + 1;
+    __shared__ double s_c[ZPW][5 * NCF];
+    __shared__ double s_f[ZPW][32 * N];
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
@@ -327,65 +418,34 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
     const bool active = (zl < ZPW) && (zt < nzr);
     int c = 0, k = 0;
     i64 z = 0;
-    i64 fid[6];
     if (active) {
         c = (int)(zt / KR);
         k = G.g - 1 + (int)(zt % KR);
         z = (i64)c * G.K + k;
-        for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
-        fid[4] = (i64)c * (G.K + 1) + k;
-        fid[5] = fid[4] + 1;
-        // inputs of the divergence-free map: WENO B (mean + coefficients),
-        // limited face nodal values, face means
-        for (int j = i; j < T::NIN; j += N) {
-            double val;
-            if (j < 3 * (T::NC + 1)) {
-                int comp = j / (T::NC + 1), a = j % (T::NC + 1);
-                val = a == 0 ? U[(5 + comp) * G.Z + z] : wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z];
-            } else if (j < 3 * (T::NC + 1) + 6 * T::Q) {
-                int jj = j - 3 * (T::NC + 1), lf = jj / T::Q, qc = jj % T::Q;
-                val = bnod[(i64)qc * G.NF + fid[lf]];
-            } else {
-                val = Bf[fid[j - 3 * (T::NC + 1) - 6 * T::Q]];
-            }
-            s_in[zl][j] = val;
+        for (int j = i; j < 5 * NCF; j += N) {
+            int v = j / NCF, a = j % NCF;
+            s_c[zl][j] = a == 0 ? U[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
         }
     }
+    int dpk[NZ];
+#pragma unroll
+    for (int p = 0; p < NZ; p++) dpk[p] = G.doff[i * NZ + p];
     __syncthreads();
 
     double Ua[8], Ut[E][8], dFa[8], met[9], iJ = 1.0, fac = 0.0;
-    int doff[NZ];
-    double dv[NZ];
-#pragma unroll
-    for (int p = 0; p < NZ; p++) {
-        doff[p] = G.doff[i * NZ + p];
-        dv[p] = G.dval[i * NZ + p];
-    }
+    double *sf = s_f[zl < ZPW ? zl : 0];
     if (active) {
         const double *Ev = G.Ev + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
-            double acc = U[v * G.Z + z];
-            const double *cf = wc + (i64)v * T::NC * G.Z + z;
+            double acc = s_c[zl][v * NCF];
 #pragma unroll
-            for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * cf[(i64)a * G.Z];
+            for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[zl][v * NCF + 1 + a];
             Ua[v] = acc;
         }
-        const double *Mb = G.Mb + (i64)c * T::NIN * T::NOUTB;
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0, bm = 0.0;
-        const int mrow = 3 * N + (i < 3 ? i : 0);
-#pragma unroll 4
-        for (int j = 0; j < T::NIN; j++) {
-            double x = s_in[zl][j];
-            const double *row = Mb + (i64)j * T::NOUTB;
-            b0 += row[i] * x;
-            b1 += row[N + i] * x;
-            b2 += row[2 * N + i] * x;
-            bm += row[mrow] * x;
-        }
-        Ua[5] = b0;
-        Ua[6] = b1;
-        Ua[7] = b2;
-        if (i < 3) zoneB[(i64)i * G.Z + z] = bm;
+        const double *bn = bnode + zt * (3 * N) + i;
+        Ua[5] = bn[0];
+        Ua[6] = bn[N];
+        Ua[7] = bn[2 * N];
         double J = G.nJ[(i64)c * N + i];
         iJ = 1.0 / J;
 #pragma unroll
@@ -399,16 +459,13 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
 #pragma unroll
         for (int d = 0; d < 3; d++)
 #pragma unroll
-            for (int v = 0; v < 8; v++) s_f[zl][(d * 8 + v) * N + i] = F[d][v];
+            for (int v = 0; v < 8; v++) sf[(d * 8 + v) * N + i] = F[d][v];
     }
     __syncthreads();
     if (active) {
 #pragma unroll
         for (int v = 0; v < 8; v++) dFa[v] = 0.0;
-#pragma unroll
-        for (int p = 0; p < NZ; p++)
-#pragma unroll
-            for (int v = 0; v < 8; v++) dFa[v] += dv[p] * s_f[zl][doff[p] + v * N];
+        apply_d<N, NZ>(dpk, sf, dFa);
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
@@ -416,44 +473,36 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
     }
     __syncthreads();
     for (int it = 0; it < npic; it++) {
-        if (active) {
+        // derivative of each level's flux; a level's state is dead once its
+        // flux is in LDS, so at most E + 1 vectors of eight are live here
+        double A[E][8];
 #pragma unroll
-            for (int s = 0; s < E; s++) {
+        for (int s = 0; s < E; s++) {
+            if (active) {
                 double F[3][8];
                 mapped_flux<P>(Ut[s], iJ, met, fac, gam, F);
 #pragma unroll
                 for (int d = 0; d < 3; d++)
 #pragma unroll
-                    for (int v = 0; v < 8; v++) s_f[zl][s * SLAB + (d * 8 + v) * N + i] = F[d][v];
+                    for (int v = 0; v < 8; v++) sf[(d * 8 + v) * N + i] = F[d][v];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 8; v++) A[s][v] = 0.0;
+            if (active) apply_d<N, NZ>(dpk, sf, A[s]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < E; t++) {
+            double r0 = G.R[t * T::M];
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                double u = Ua[v] - r0 * dFa[v];
+#pragma unroll
+                for (int s = 0; s < E; s++) u -= G.R[t * T::M + s + 1] * A[s][v];
+                Ut[t][v] = u;
             }
         }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int t = 0; t < E; t++) {
-                double r = G.R[t * T::M];
-#pragma unroll
-                for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - r * dFa[v];
-            }
-#pragma unroll
-            for (int s = 0; s < E; s++) {
-                double acc[8];
-#pragma unroll
-                for (int v = 0; v < 8; v++) acc[v] = 0.0;
-                const double *slab = &s_f[zl][s * SLAB];
-#pragma unroll
-                for (int p = 0; p < NZ; p++)
-#pragma unroll
-                    for (int v = 0; v < 8; v++) acc[v] += dv[p] * slab[doff[p] + v * N];
-#pragma unroll
-                for (int t = 0; t < E; t++) {
-                    double r = G.R[t * T::M + s + 1];
-#pragma unroll
-                    for (int v = 0; v < 8; v++) Ut[t][v] -= r * acc[v];
-                }
-            }
-        }
-        __syncthreads();
     }
     // time averages of state and physical flux over the Gauss levels
     if (active) {
@@ -476,16 +525,20 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
         }
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            s_f[zl][v * N + i] = aU[v];
-            s_f[zl][(8 + v) * N + i] = aF[0][v];
-            s_f[zl][(16 + v) * N + i] = aF[1][v];
-            s_f[zl][(24 + v) * N + i] = aF[2][v];
+            sf[v * N + i] = aU[v];
+            sf[(8 + v) * N + i] = aF[0][v];
+            sf[(16 + v) * N + i] = aF[1][v];
+            sf[(24 + v) * N + i] = aF[2][v];
         }
     }
     __syncthreads();
     if (!active) return;
     // traces: face quadrature points, then edge Simpson points
-    const double *sx = s_f[zl];
+    i64 fid[6];
+    for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    fid[4] = (i64)c * (G.K + 1) + k;
+    fid[5] = fid[4] + 1;
+    const double *sx = sf;
     const int nwork = 6 * T::Q + 36;
     for (int w = i; w < nwork; w += N) {
         double Uq[8], Fq[3][8];
@@ -493,6 +546,7 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
         for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
         if (w < 6 * T::Q) {
             int lf = w / T::Q, ql = w % T::Q;
+            #pragma unroll 2
             for (int kk = 0; kk < T::NFN; kk++) {
                 int l = G.fnode[lf * T::NFN + kk];
                 double wgt = G.fint[(lf * T::Q + ql) * T::NFN + kk];
@@ -523,6 +577,7 @@ __global__ __launch_bounds__(64) void predictor(DevGeom G, double dt, double gam
             }
         } else {
             int we = w - 6 * T::Q, le = we / 3, pl = we % 3;
+            #pragma unroll 2
             for (int kk = 0; kk < T::NEN; kk++) {
                 int l = G.enode[le * T::NEN + kk];
                 double wgt = G.eint[(le * 3 + pl) * T::NEN + kk];
@@ -837,8 +892,11 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
-    predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, Bo, g->wcoef, g->bnod, g->zoneB,
-                                                                    g->ftr, g->etr);
+    const int ntile = (G.Nr + 2 + 15) / 16;
+    bmap<P><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod, g->bnode, g->zoneB);
+    RG_LAUNCH_CHECK();
+    predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, g->wcoef, g->bnode, g->ftr,
+                                                                    g->etr);
     RG_LAUNCH_CHECK();
     sm.mark(4, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
