@@ -244,8 +244,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
             NZ = std::max(NZ, n);
         }
         // Each entry packs twice the value (an integer: the entries are
-        // multiples of 1/2) in the high 16 bits and the slab offset d*8*N + l
-        // in the low 16 bits.
+        // multiples of 1/2) in the high 16 bits and the slab offset
+        // d*8*(N+1) + l in the low 16 bits (the slab rows are N+1 long).
         std::vector<int> doff((size_t)N * NZ);
         for (int i = 0; i < N; i++) {
             int n = 0;
@@ -254,11 +254,12 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                     double v = r.D[((size_t)d * N + i) * N + l];
                     if (v != 0.0) {
                         int twice = (int)std::lround(2.0 * v);
-                        if (2.0 * v != (double)twice || std::abs(twice) > 32767 || d * 8 * N + l > 65535) {
+                        const int off = d * 8 * (N + 1) + l;
+                        if (2.0 * v != (double)twice || std::abs(twice) > 32767 || off > 65535) {
                             set_error("derivative matrix entry is not a small multiple of 1/2");
                             return RG_EINVAL;
                         }
-                        doff[(size_t)i * NZ + n] = (int)((unsigned)twice << 16) | (d * 8 * N + l);
+                        doff[(size_t)i * NZ + n] = (int)((unsigned)twice << 16) | off;
                         n++;
                     }
                 }
@@ -291,7 +292,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre; d.NZ = NZ;
         bool ok = upload(g, radius, &d.radius) && upload(g, zs, &d.zscale) && upload(g, Rv, &d.R) &&
                   upload(g, wt, &d.wt) && upload(g, doff, &d.doff) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
-                  upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, hg.stm, &d.stm) &&
+                  upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, r.fintc, &d.fintc) &&
+                  upload(g, r.eintc, &d.eintc) && upload(g, hg.stm, &d.stm) &&
                   upload(g, hg.Pl, &d.Pl) && upload(g, hg.Ps, &d.Ps) && upload(g, hg.Qs, &d.Qs) &&
                   upload(g, EvT, &d.Ev) && upload(g, MbT, &d.Mb) && upload(g, hg.nJ, &d.nJ) &&
                   upload(g, nMT, &d.nM) && upload(g, hg.fevR, &d.fevR) && upload(g, hg.fnR, &d.fnR) &&

@@ -261,19 +261,43 @@ bool build_refel(int order, RefEl &r)
     r.NEN = p;
     r.fnode.assign(6 * r.NFN, -1);
     r.fint.assign((size_t)6 * r.Q * r.NFN, 0.0);
+    // Face nodes are listed in one order for every face: by their position in
+    // the face's two free coordinates (lower axis first), as found on face 0.
+    // The weights at the face quadrature points are then the same for all six
+    // faces (fintc), which the predictor relies on.
     for (int lf = 0; lf < 6; lf++) {
-        int axis = lf / 2;
+        int axis = lf / 2, ua = axis == 0 ? 1 : 0, va = axis == 2 ? 1 : 2;
         double fix = (lf & 1) ? 0.5 : -0.5;
-        int n = 0;
-        for (int l = 0; l < N; l++)
-            if (r.node[l][axis] == fix) r.fnode[lf * r.NFN + n++] = l;
-        if (n != r.NFN) return false;
+        for (int k = 0; k < r.NFN; k++) {
+            int n = 0;
+            if (lf == 0) {
+                for (int l = 0; l < N; l++)
+                    if (r.node[l][0] == -0.5 && n++ == k) r.fnode[k] = l;
+                continue;
+            }
+            const auto &ref = r.node[r.fnode[k]];
+            for (int l = 0; l < N; l++)
+                if (r.node[l][axis] == fix && r.node[l][ua] == ref[1] && r.node[l][va] == ref[2]) {
+                    r.fnode[lf * r.NFN + k] = l;
+                    n++;
+                }
+            if (n != 1) return false;
+        }
+        for (int k = 0; k < r.NFN; k++)
+            if (r.fnode[lf * r.NFN + k] < 0) return false;
         for (int q = 0; q < r.Q; q++) {
             double xi[3];
             face_ref_point(r, lf, q, xi);
             for (int k = 0; k < r.NFN; k++) r.fint[((size_t)lf * r.Q + q) * r.NFN + k] = r.psi(r.fnode[lf * r.NFN + k], xi);
         }
     }
+    r.fintc.assign((size_t)r.NFN * r.Q, 0.0);
+    for (int k = 0; k < r.NFN; k++)
+        for (int q = 0; q < r.Q; q++) r.fintc[(size_t)k * r.Q + q] = r.fint[(size_t)q * r.NFN + k];
+    for (int lf = 1; lf < 6; lf++)
+        for (int q = 0; q < r.Q; q++)
+            for (int k = 0; k < r.NFN; k++)
+                if (std::abs(r.fint[((size_t)lf * r.Q + q) * r.NFN + k] - r.fintc[(size_t)k * r.Q + q]) > 1e-13) return false;
     r.enode.assign(12 * r.NEN, -1);
     r.eint.assign((size_t)12 * 3 * r.NEN, 0.0);
     for (int le = 0; le < 12; le++) {
@@ -290,6 +314,15 @@ bool build_refel(int order, RefEl &r)
             for (int k = 0; k < r.NEN; k++) r.eint[((size_t)le * 3 + s) * r.NEN + k] = r.psi(r.enode[le * r.NEN + k], xi);
         }
     }
+    // edge nodes are listed by index, which orders them alike along every
+    // edge; the Simpson-point weights are therefore shared (eintc)
+    r.eintc.assign((size_t)r.NEN * 3, 0.0);
+    for (int k = 0; k < r.NEN; k++)
+        for (int s = 0; s < 3; s++) r.eintc[(size_t)k * 3 + s] = r.eint[(size_t)s * r.NEN + k];
+    for (int le = 1; le < 12; le++)
+        for (int s = 0; s < 3; s++)
+            for (int k = 0; k < r.NEN; k++)
+                if (std::abs(r.eint[((size_t)le * 3 + s) * r.NEN + k] - r.eintc[(size_t)k * 3 + s]) > 1e-13) return false;
     return true;
 }
 

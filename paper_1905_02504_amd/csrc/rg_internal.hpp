@@ -59,6 +59,8 @@ struct RefEl {
     std::vector<double> fint;  // 6 x Q x NFN weights
     std::vector<int> enode;    // 12 x NEN nodes on each local edge
     std::vector<double> eint;  // 12 x 3 x NEN weights
+    std::vector<double> fintc; // NFN x Q  weights shared by all faces (node k, point q)
+    std::vector<double> eintc; // NEN x 3  weights shared by all edges (node k, point s)
     double psi(int l, const double *xi) const;
     double dpsi(int l, int d, const double *xi) const;
 };
@@ -83,13 +85,15 @@ struct DevGeom {
     const double *zscale;   // K: zone length scale relative to shell 0
     const double *R;        // (M-1) x M
     const double *wt;       // M
-    const int *doff;        // N x NZ  derivative entries per node: (2 D_d[i][l]) << 16 | (d * 8) * N + l,
+    const int *doff;        // N x NZ  derivative entries per node: (2 D_d[i][l]) << 16 | (d * 8) * (N + 1) + l,
                             //         padded with i (value 0)
     int NZ;                 // entries per node (padded)
     const int *fnode;       // 6 x NFN
     const double *fint;     // 6 x Q x NFN
     const int *enode;       // 12 x NEN
     const double *eint;     // 12 x 3 x NEN
+    const double *fintc;    // NFN x Q, identical for every face
+    const double *eintc;    // NEN x 3, identical for every edge
     // per column
     const int *stm;         // ncol x NS   member = col * 8 + (dk + 3), -1 if empty
     const double *Pl;       // ncol x NC x NS

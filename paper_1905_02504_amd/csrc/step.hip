@@ -46,8 +46,9 @@ __device__ __forceinline__ void dev_flux(const double *u, double gam, double F[3
     double ir = 1.0 / u[0];
     double v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
     double B0 = u[5], B1 = u[6], B2 = u[7];
-    double p = dev_pressure(u, gam);
-    double pt = p + 0.5 * (B0 * B0 + B1 * B1 + B2 * B2);
+    double hb2 = 0.5 * (B0 * B0 + B1 * B1 + B2 * B2);
+    double p = (gam - 1.0) * (u[4] - 0.5 * (u[1] * v0 + u[2] * v1 + u[3] * v2) - hb2);
+    double pt = p + hb2;
     double vB = v0 * B0 + v1 * B1 + v2 * B2;
     double v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
 #pragma unroll
@@ -291,7 +292,7 @@ __constant__ int LE_UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
 __constant__ int LE_CORNER[4] = {0, 1, 3, 2};
 
 template <int P>
-__device__ __forceinline__ void mapped_flux(const double *u, double iJ, const double *met, double fac, double gam,
+__device__ __forceinline__ void mapped_flux(const double *u, double iJ, const double *met, double gam,
                                             double out[3][8])
 {
     double w[8], F[3][8];
@@ -302,7 +303,7 @@ __device__ __forceinline__ void mapped_flux(const double *u, double iJ, const do
     for (int d = 0; d < 3; d++)
 #pragma unroll
         for (int v = 0; v < 8; v++)
-            out[d][v] = fac * (met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v]);
+            out[d][v] = met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v];
 }
 
 // Divergence-free B (Section IV.b): for every zone of a column the fused
@@ -378,9 +379,10 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
 }
 
 // acc += (D_xi F_xi + D_eta F_eta + D_zeta F_zeta) at this lane's node, the
-// fluxes read from the node-fastest LDS slab.  The packed entries hold twice
-// the matrix value; halving the sum at the end is exact.
-template <int N, int NZ>
+// fluxes read from the node-fastest LDS slab (rows of SN = N + 1 doubles).
+// The packed entries hold twice the matrix value; halving the sum at the end
+// is exact.
+template <int SN, int NZ>
 __device__ __forceinline__ void apply_d(const int (&dpk)[NZ], const double *sf, double (&acc)[8])
 {
     double s[8];
@@ -392,7 +394,7 @@ __device__ __forceinline__ void apply_d(const int (&dpk)[NZ], const double *sf, 
         double dv = (double)(pk >> 16);
         const double *col = sf + (pk & 0xffff);
 #pragma unroll
-        for (int v = 0; v < 8; v++) s[v] += dv * col[v * N];
+        for (int v = 0; v < 8; v++) s[v] += dv * col[v * SN];
     }
 #pragma unroll
     for (int v = 0; v < 8; v++) acc[v] += 0.5 * s[v];
@@ -408,19 +410,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                                                 double *__restrict__ ftr, double *__restrict__ etr)
 {
     using T = Tr<P>;
-    constexpr int N = T::N, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ, NCF = T::NC + 1;
+    // slab rows are N + 1 long so that lanes reading one node's different
+    // variables fall into different LDS banks
+    constexpr int N = T::N, SN = N + 1, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ, NCF = T::NC + 1;
     __shared__ double s_c[ZPW][5 * NCF];
-    __shared__ double s_f[ZPW][32 * N];
+    __shared__ double s_f[ZPW][32 * SN];
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
-    const i64 zt = (i64)blockIdx.x * ZPW + zl;
-    const bool active = (zl < ZPW) && (zt < nzr);
+    // zone counts stay below 2^31 (checked at launch)
+    const unsigned zt = blockIdx.x * ZPW + zl;
+    const bool active = (zl < ZPW) && (zt < (unsigned)nzr);
     int c = 0, k = 0;
     i64 z = 0;
     if (active) {
-        c = (int)(zt / KR);
-        k = G.g - 1 + (int)(zt % KR);
+        c = (int)(zt / (unsigned)KR);
+        k = G.g - 1 + (int)(zt % (unsigned)KR);
         z = (i64)c * G.K + k;
         for (int j = i; j < 5 * NCF; j += N) {
             int v = j / NCF, a = j % NCF;
@@ -442,30 +447,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[zl][v * NCF + 1 + a];
             Ua[v] = acc;
         }
-        const double *bn = bnode + zt * (3 * N) + i;
+        const double *bn = bnode + (i64)zt * (3 * N) + i;
         Ua[5] = bn[0];
         Ua[6] = bn[N];
         Ua[7] = bn[2 * N];
         double J = G.nJ[(i64)c * N + i];
         iJ = 1.0 / J;
-#pragma unroll
-        for (int m = 0; m < 9; m++) met[m] = G.nM[((i64)c * 9 + m) * N + i];
+        // metric terms scaled by dt over the zone's size: the predictor works in
+        // reference time and space
         fac = dt / G.zscale[k];
+#pragma unroll
+        for (int m = 0; m < 9; m++) met[m] = fac * G.nM[((i64)c * 9 + m) * N + i];
 #pragma unroll
         for (int v = 0; v < 8; v++) Ua[v] *= J;
         // level tau = 0: its flux derivative is the same in every iteration
         double F[3][8];
-        mapped_flux<P>(Ua, iJ, met, fac, gam, F);
+        mapped_flux<P>(Ua, iJ, met, gam, F);
 #pragma unroll
         for (int d = 0; d < 3; d++)
 #pragma unroll
-            for (int v = 0; v < 8; v++) sf[(d * 8 + v) * N + i] = F[d][v];
+            for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
     }
     __syncthreads();
     if (active) {
 #pragma unroll
         for (int v = 0; v < 8; v++) dFa[v] = 0.0;
-        apply_d<N, NZ>(dpk, sf, dFa);
+        apply_d<SN, NZ>(dpk, sf, dFa);
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
@@ -480,16 +487,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         for (int s = 0; s < E; s++) {
             if (active) {
                 double F[3][8];
-                mapped_flux<P>(Ut[s], iJ, met, fac, gam, F);
+                mapped_flux<P>(Ut[s], iJ, met, gam, F);
 #pragma unroll
                 for (int d = 0; d < 3; d++)
 #pragma unroll
-                    for (int v = 0; v < 8; v++) sf[(d * 8 + v) * N + i] = F[d][v];
+                    for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
             }
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < 8; v++) A[s][v] = 0.0;
-            if (active) apply_d<N, NZ>(dpk, sf, A[s]);
+            if (active) apply_d<SN, NZ>(dpk, sf, A[s]);
             __syncthreads();
         }
 #pragma unroll
@@ -525,85 +532,117 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         }
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            sf[v * N + i] = aU[v];
-            sf[(8 + v) * N + i] = aF[0][v];
-            sf[(16 + v) * N + i] = aF[1][v];
-            sf[(24 + v) * N + i] = aF[2][v];
+            sf[v * SN + i] = aU[v];
+            sf[(8 + v) * SN + i] = aF[0][v];
+            sf[(16 + v) * SN + i] = aF[1][v];
+            sf[(24 + v) * SN + i] = aF[2][v];
         }
     }
     __syncthreads();
-    if (!active) return;
-    // traces: face quadrature points, then edge Simpson points
-    i64 fid[6];
-    for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
-    fid[4] = (i64)c * (G.K + 1) + k;
-    fid[5] = fid[4] + 1;
-    const double *sx = sf;
-    const int nwork = 6 * T::Q + 36;
-    for (int w = i; w < nwork; w += N) {
-        double Uq[8], Fq[3][8];
+    // Traces.  Faces: one task per (zone, face, variable) interpolates the
+    // averaged state and the three flux components of its variable from the
+    // face's nodes to all face quadrature points (weights shared by the six
+    // faces), then forms the outward-normal flux.
+#pragma unroll 1
+    for (int t = lane; t < ZPW * 48; t += 64) {
+        const int zq = t / 48, lf = (t % 48) / 8, v = t % 8;
+        const unsigned ztq = blockIdx.x * ZPW + zq;
+        if (ztq >= (unsigned)nzr) continue;
+        const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
+        const double *sx = s_f[zq];
+        double x[T::NFN][4];
 #pragma unroll
-        for (int v = 0; v < 8; v++) { Uq[v] = 0.0; Fq[0][v] = Fq[1][v] = Fq[2][v] = 0.0; }
-        if (w < 6 * T::Q) {
-            int lf = w / T::Q, ql = w % T::Q;
-            #pragma unroll 2
-            for (int kk = 0; kk < T::NFN; kk++) {
-                int l = G.fnode[lf * T::NFN + kk];
-                double wgt = G.fint[(lf * T::Q + ql) * T::NFN + kk];
+        for (int kk = 0; kk < T::NFN; kk++) {
+            const int l = G.fnode[lf * T::NFN + kk];
 #pragma unroll
-                for (int v = 0; v < 8; v++) {
-                    Uq[v] += wgt * sx[v * N + l];
-                    Fq[0][v] += wgt * sx[(8 + v) * N + l];
-                    Fq[1][v] += wgt * sx[(16 + v) * N + l];
-                    Fq[2][v] += wgt * sx[(24 + v) * N + l];
-                }
-            }
-            int qc, side;
-            const double *n;
-            if (lf >= 4) {
-                qc = ql;
-                side = lf == 4 ? 1 : 0;
-                n = G.fnR + ((i64)c * T::Q + qc) * 3;
-            } else {
-                qc = G.col_perm[((i64)c * 4 + lf) * T::Q + ql];
-                side = G.col_side[4 * c + lf];
-                n = G.fnA + ((i64)G.col_ae[4 * c + lf] * T::Q + qc) * 3;
-            }
-            double *o = ftr + ((fid[lf] * 2 + side) * T::Q + qc) * 16;
-#pragma unroll
-            for (int v = 0; v < 8; v++) {
-                o[v] = Uq[v];
-                o[8 + v] = n[0] * Fq[0][v] + n[1] * Fq[1][v] + n[2] * Fq[2][v];
-            }
+            for (int j = 0; j < 4; j++) x[kk][j] = sx[(8 * j + v) * SN + l];
+        }
+        i64 fid;
+        int side;
+        const double *nrm;
+        const int *perm = nullptr;
+        if (lf >= 4) {
+            fid = (i64)cq * (G.K + 1) + kq + (lf - 4);
+            side = lf == 4 ? 1 : 0;
+            nrm = G.fnR + (i64)cq * T::Q * 3;
         } else {
-            int we = w - 6 * T::Q, le = we / 3, pl = we % 3;
-            #pragma unroll 2
-            for (int kk = 0; kk < T::NEN; kk++) {
-                int l = G.enode[le * T::NEN + kk];
-                double wgt = G.eint[(le * 3 + pl) * T::NEN + kk];
+            const int ae = G.col_ae[4 * cq + lf];
+            fid = G.NRF + (i64)ae * G.K + kq;
+            side = G.col_side[4 * cq + lf];
+            nrm = G.fnA + (i64)ae * T::Q * 3;
+            perm = G.col_perm + ((i64)cq * 4 + lf) * T::Q;
+        }
+        double *o = ftr + (fid * 2 + side) * T::Q * 16;
+        // one row of quadrature points at a time: its weights are uniform
+        // across the wavefront and stay in scalar registers
+#pragma unroll 1
+        for (int b = 0; b < T::Q1; b++) {
+            double aq[T::Q1][4];
 #pragma unroll
-                for (int v = 0; v < 8; v++) {
-                    Uq[v] += wgt * sx[v * N + l];
-                    Fq[0][v] += wgt * sx[(8 + v) * N + l];
-                    Fq[1][v] += wgt * sx[(16 + v) * N + l];
-                    Fq[2][v] += wgt * sx[(24 + v) * N + l];
+            for (int a = 0; a < T::Q1; a++) aq[a][0] = aq[a][1] = aq[a][2] = aq[a][3] = 0.0;
+            const double *wrow = G.fintc + b * T::Q1;
+#pragma unroll
+            for (int kk = 0; kk < T::NFN; kk++)
+#pragma unroll
+                for (int a = 0; a < T::Q1; a++) {
+                    const double w = wrow[kk * T::Q + a];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) aq[a][j] += w * x[kk][j];
+                }
+#pragma unroll
+            for (int a = 0; a < T::Q1; a++) {
+                const int q = a + T::Q1 * b;
+                const int qc = perm ? perm[q] : q;
+                const double *n = nrm + qc * 3;
+                o[qc * 16 + v] = aq[a][0];
+                o[qc * 16 + 8 + v] = n[0] * aq[a][1] + n[1] * aq[a][2] + n[2] * aq[a][3];
+            }
+        }
+    }
+    // Edges: one task per (zone, edge) interpolates the averaged state and the
+    // three electric-field components (eq. 2.3) to the edge's Simpson points.
+    if (lane < ZPW * 12) {
+        const int zq = lane / 12, le = lane % 12;
+        const unsigned ztq = blockIdx.x * ZPW + zq;
+        if (ztq < (unsigned)nzr) {
+            const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
+            const double *sx = s_f[zq];
+            double ae3[3][11];
+#pragma unroll
+            for (int p = 0; p < 3; p++)
+#pragma unroll
+                for (int v = 0; v < 11; v++) ae3[p][v] = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < T::NEN; kk++) {
+                const int l = G.enode[le * T::NEN + kk];
+                double x[11];
+#pragma unroll
+                for (int v = 0; v < 8; v++) x[v] = sx[v * SN + l];
+                x[8] = sx[(24 + 6) * SN + l];    // E_x = H[B_y]
+                x[9] = sx[(8 + 7) * SN + l];     // E_y = F[B_z]
+                x[10] = sx[(16 + 5) * SN + l];   // E_z = G[B_x]
+#pragma unroll
+                for (int p = 0; p < 3; p++) {
+                    const double w = G.eintc[kk * 3 + p];
+#pragma unroll
+                    for (int v = 0; v < 11; v++) ae3[p][v] += w * x[v];
                 }
             }
-            int rev = G.col_rev[(i64)c * 12 + le], slot = G.col_slot[(i64)c * 12 + le];
-            int pc = rev ? 2 - pl : pl;
+            const int rev = G.col_rev[(i64)cq * 12 + le], slot = G.col_slot[(i64)cq * 12 + le];
             i64 e;
             if (le < 8) {
-                int ae = G.col_ae[4 * c + LE_FACE[le]];
-                e = G.NRE + (i64)ae * (G.K + 1) + k + LE_UP[le];
+                const int ae = G.col_ae[4 * cq + LE_FACE[le]];
+                e = G.NRE + (i64)ae * (G.K + 1) + kq + LE_UP[le];
             } else {
-                e = (i64)G.col_v[4 * c + LE_CORNER[le - 8]] * G.K + k;
+                e = (i64)G.col_v[4 * cq + LE_CORNER[le - 8]] * G.K + kq;
             }
-            double *o = etr + ((e * 4 + slot) * 3 + pc) * 11;
+            double *o = etr + (e * 4 + slot) * 3 * 11;
 #pragma unroll
-            for (int v = 0; v < 8; v++) o[v] = Uq[v];
-            o[8] = Fq[2][6];   // E_x = H[B_y]
-            o[9] = Fq[0][7];   // E_y = F[B_z]
-            o[10] = Fq[1][5];  // E_z = G[B_x]   (eq. 2.3)
+            for (int p = 0; p < 3; p++) {
+                const int pc = rev ? 2 - p : p;
+#pragma unroll
+                for (int v = 0; v < 11; v++) o[pc * 11 + v] = ae3[p][v];
+            }
         }
     }
 }
