@@ -356,9 +356,16 @@ int mesh_build_geometry(rgo_mesh *m)
         for (int q = 0; q < Q; q++)
             for (int i = 0; i < 3; i++) nbar[i] += m->fdA[f * RGO_MAXQ + q] * m->fn[(f * RGO_MAXQ + q) * 3 + i];
         for (int k = 0; k < 4; k++) {
+            /* right-hand rule about the face normal: the edge runs
+             * counter-clockwise when n x (its midpoint - an interior point)
+             * points along it.  The midpoint of the opposite edge (local
+             * edges pair up as k, k^1) serves as the interior point; the
+             * face centroid does not, since on a thin curved face it can sag
+             * below an edge. */
             int e = m->zone_edge[12 * z + LF_EDGES[lf][k]];
-            const double *xm = &m->ex[e * 9 + 3], *tm = &m->et[e * 9 + 3];
-            double r[3] = {xm[0] - m->fcen[3 * f], xm[1] - m->fcen[3 * f + 1], xm[2] - m->fcen[3 * f + 2]}, ccw[3];
+            int eo = m->zone_edge[12 * z + LF_EDGES[lf][k ^ 1]];
+            const double *xm = &m->ex[e * 9 + 3], *tm = &m->et[e * 9 + 3], *xo = &m->ex[eo * 9 + 3];
+            double r[3] = {xm[0] - xo[0], xm[1] - xo[1], xm[2] - xo[2]}, ccw[3];
             cross3(nbar, r, ccw);
             m->face_edges[4 * f + k] = e;
             m->face_esign[4 * f + k] = dot3(ccw, tm) > 0 ? 1 : -1;

@@ -171,6 +171,24 @@ def test_face_closure(mesh4):
     assert worst < 1e-13
 
 
+@pytest.mark.parametrize("n_rad", [4, 64])
+def test_face_circulations_have_zero_divergence(n_rad):
+    """div curl = 0 discretely: any edge circulations, summed around each face
+    with the face's edge signs, give face fluxes whose sum over every zone's
+    faces vanishes.  64 radial shells make the zones thin enough that a
+    curved face's centroid sags below its lower edge, which a sign test
+    against the centroid gets wrong."""
+    m = O.OracleMesh(4, n_rad, order=3, n_ghost=2)
+    fe, fs = m.face_edges()
+    zf, _ = m.zone_faces()
+    _, _, area, fz = m.faces()
+    G = np.random.default_rng(7).standard_normal(m.ne)
+    flux = (fs * G[fe]).sum(1)
+    sg = np.where(fz[zf][:, :, 0] == np.arange(m.nz)[:, None], 1.0, -1.0)
+    div = np.abs((sg * flux[zf]).sum(1))
+    assert div.max() < 1e-12 * np.abs(G).max()
+
+
 @pytest.mark.parametrize("which", ["mesh3", "mesh4"])
 def test_curl_metrics_have_zero_discrete_divergence(which, request):
     m = request.getfixturevalue(which)
