@@ -152,20 +152,24 @@ rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, d
                          double *U, double *Bf);
 
 /* Per-stage timing with HIP events recorded on the step's own stream.
- * After rg_profile_begin, every rg_step records events around its seven
- * stages: 0 boundary fill, 1 WENO-AO, 2 face nodal B, 3 divergence-free B +
- * ADER predictor + traces, 4 face HLL fluxes, 5 edge EMFs, 6 FV update + CT.
- * rg_profile_end waits for the recorded events, writes the summed
- * milliseconds of each stage to ms[7] and the number of recorded steps to
- * *nsteps, releases the events and stops recording. */
+ * After rg_profile_begin, every rg_step records events around its
+ * RG_NSTAGES stages: 0 boundary fill, 1 WENO-AO, 2 face nodal B,
+ * 3 divergence-free B map (KKT solve and evaluation at the ADER nodes, one
+ * kernel), 4 ADER predictor + traces (one kernel), 5 face HLL fluxes,
+ * 6 edge EMFs, 7 FV update + CT.  rg_profile_end waits for the recorded
+ * events, writes the summed milliseconds of each stage to ms[RG_NSTAGES]
+ * and the number of recorded steps to *nsteps, releases the events and
+ * stops recording. */
+#define RG_NSTAGES 8
 rg_status rg_profile_begin(rg_geom *geom);
 rg_status rg_profile_end(rg_geom *geom, double *ms, int32_t *nsteps);
 
-/* Algorithmic work of one rg_step on this geometry, per stage (numbering of
- * rg_profile_end): flops[7] floating-point operations (an FMA counts 2) of
- * the formulas each stage evaluates, bytes[7] minimum HBM traffic (each
- * input read once, each output written once, per-column matrices amortised
- * over the column).  Host only. */
+/* Algorithmic work of one rg_step on this geometry with the default number
+ * of Picard sweeps (the order), per stage (numbering of rg_profile_end):
+ * flops[RG_NSTAGES] floating-point operations (an FMA counts 2) of the
+ * formulas each stage evaluates, bytes[RG_NSTAGES] minimum HBM traffic
+ * (each input read once, each output written once, per-column matrices
+ * amortised over the column).  Host only. */
 rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
 
 const char *rg_last_error(void);

@@ -150,7 +150,8 @@ def rg_init_alfven(geom, frame_ptr, rho, p, B0, dB, wavelength, gamma, t, noise_
                                noise_amp, _vp(U_ptr), _vp(Bf_ptr)), "rg_init_alfven")
 
 
-STAGES = ("bc_fill", "weno", "face_bnodal", "predictor", "face_flux", "edge_emf", "update_ct")
+STAGES = ("bc_fill", "weno", "face_bnodal", "bmap", "predictor", "face_flux", "edge_emf", "update_ct")
+RG_NSTAGES = len(STAGES)
 
 
 def rg_profile_begin(geom):
@@ -158,14 +159,14 @@ def rg_profile_begin(geom):
 
 
 def rg_profile_end(geom):
-    ms = (C.c_double * 7)()
+    ms = (C.c_double * RG_NSTAGES)()
     n = C.c_int32(0)
     check(lib().rg_profile_end(geom, ms, C.byref(n)), "rg_profile_end")
     return dict(zip(STAGES, list(ms))), n.value
 
 
 def rg_geom_work(geom):
-    f = (C.c_double * 7)()
-    b = (C.c_double * 7)()
+    f = (C.c_double * RG_NSTAGES)()
+    b = (C.c_double * RG_NSTAGES)()
     check(lib().rg_geom_work(geom, f, b), "rg_geom_work")
     return dict(zip(STAGES, list(f))), dict(zip(STAGES, list(b)))

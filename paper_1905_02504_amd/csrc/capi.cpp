@@ -437,7 +437,7 @@ extern "C" rg_status rg_geom_work(const rg_geom *g, double *flops, double *bytes
     double nnz = 0;
     for (double v : r.D) nnz += (v != 0.0);
     const double nnz_node = nnz / N;        // over the three directions
-    const double FLUX = 96, MAPPED = FLUX + 9 + 3 * 8 * 6, FAST = 22, HLL = 2 * FAST + 14 + 8 * 7;
+    const double FLUX = 96, FAST = 22, HLL = 2 * FAST + 14 + 8 * 7;
     // 0 boundary fill
     flops[0] = 0;
     bytes[0] = 2.0 * 8 * (8.0 * m.nzones + (double)m.nfaces);
@@ -449,23 +449,29 @@ extern "C" rg_status rg_geom_work(const rg_geom *g, double *flops, double *bytes
     // 2 face nodal B: both sides' WENO B at Q points, minmod, mean restore
     flops[2] = fb * Q * (2 * 3 * 2 * (NC + 1) + 2 * 6 + 4 + 4);
     bytes[2] = 8 * (fb * (2 * (3 + 3 * NC) + 1 + Q) + m.ncol * (2 * Q * NC + 4 * Q) + m.nae * (2 * Q * NC + 4 * Q));
-    // 3 divergence-free map + ADER-CG Picard iterations + time averages + traces
-    double init = N * (5 * 2 * NC + 3 * 2 * NIN + 8) + 3 * 2 * NIN;
-    double iter = N * ((1 + E) * MAPPED + E * (E + 1) * 24 * 2 + nnz_node * E * 8 * 2 + E * 8);
-    double avg = N * E * (FLUX + 8 + 32 * 2);
-    double trc = 6 * Q * (r.NFN * 32 * 2 + 8 * 3 * 2) + 36 * (r.NEN * 32 * 2);
-    flops[3] = zr * (init + r.order * iter + avg + trc);
-    bytes[3] = 8 * (zr * (8 * NC + 8 + 6 * Q + 6 + 3 + 6 * Q * 16 + 36 * 11) +
-                    m.ncol * (r.NOUTB * NIN + N * NC + N * 10));
-    // 4 face HLL fluxes
-    flops[4] = ff * Q * (HLL + 2 + 16);
-    bytes[4] = 8 * (ff * (2 * 16 * Q + 8 + 1) + m.ncol * 4 * Q + m.nae * 4 * Q);
-    // 5 edge EMFs (four-state solver at three Simpson points)
-    flops[5] = ee * 3 * (4 * (2 * FAST + 4 * 5 + 8) + 40);
-    bytes[5] = 8 * (ee * (3 * 4 * 11 + 1) + m.nae * 30.0 + m.nv * 18.0);
-    // 6 finite-volume update and constrained transport
-    flops[6] = zi * (8 * 6 * 2 + 8 * 2) + ff * 10;
-    bytes[6] = 8 * (zi * (6 * 8 + 8 + 3 + 8 + 1) + ff * (4 + 2 + 1));
+    // 3 divergence-free B map: dense per-column product
+    flops[3] = zr * NIN * r.NOUTB * 2;
+    bytes[3] = 8 * (zr * (NIN + r.NOUTB) + m.ncol * (NIN * r.NOUTB));
+    // 4 ADER-CG predictor: nodal state, the tau = 0 flux derivative, a first
+    // sweep from the constant guess (no flux evaluations), order - 1 full
+    // sweeps, time averages, then traces at face points and edge points
+    const double MAPPED = 8 + FLUX + 24 * 5, DERIV = nnz_node * 8 * 2, UPD = (E + 1) * 8 * 2;
+    double init = N * (5 * NC * 2 + 8 + MAPPED + DERIV);
+    double first = N * E * UPD;
+    double sweep = N * E * (MAPPED + DERIV + UPD);
+    double avg = N * E * (8 + FLUX + 32 * 2);
+    double trc = 6 * 8 * Q * r.NFN * 4 * 2 + 6 * Q * 8 * 5 + 12 * 3 * r.NEN * 11 * 2;
+    flops[4] = zr * (init + first + (r.order - 1) * sweep + avg + trc);
+    bytes[4] = 8 * (zr * (5 * (NC + 1) + 3 * N + 6 * Q * 16 + 36 * 11) + m.ncol * N * (NC + 10));
+    // 5 face HLL fluxes
+    flops[5] = ff * Q * (HLL + 2 + 16);
+    bytes[5] = 8 * (ff * (2 * 16 * Q + 8 + 1) + m.ncol * 4 * Q + m.nae * 4 * Q);
+    // 6 edge EMFs (four-state solver at three Simpson points)
+    flops[6] = ee * 3 * (4 * (2 * FAST + 4 * 5 + 8) + 40);
+    bytes[6] = 8 * (ee * (3 * 4 * 11 + 1) + m.nae * 30.0 + m.nv * 18.0);
+    // 7 finite-volume update and constrained transport
+    flops[7] = zi * (8 * 6 * 2 + 8 * 2) + ff * 10;
+    bytes[7] = 8 * (zi * (6 * 8 + 8 + 3 + 8 + 1) + ff * (4 + 2 + 1));
     (void)K;
     return RG_OK;
 }

@@ -286,25 +286,54 @@ static double tbasis(const double *mom, const std::array<int, 3> &e, const doubl
     return v - mom[moment_index(e[0], e[1], e[2])];
 }
 
-// least-squares pseudo-inverse (A^T A)^-1 A^T of an n x m matrix (n >= m), row-major
+// least-squares pseudo-inverse of an n x m matrix A (n >= m, full column
+// rank, row-major): P = R^-1 Q^T from a Householder QR factorisation, which
+// keeps the conditioning of A itself (the normal equations would square it,
+// and the stencils of thin shells are poorly conditioned).  P is m x n.
 static bool pinv(int n, int m, const std::vector<double> &A, std::vector<double> &P)
 {
-    std::vector<double> G((size_t)m * m, 0.0);
-    for (int i = 0; i < m; i++)
-        for (int j = 0; j < m; j++) {
-            double s = 0.0;
-            for (int k = 0; k < n; k++) s += A[(size_t)k * m + i] * A[(size_t)k * m + j];
-            G[(size_t)i * m + j] = s;
+    std::vector<double> R(A), Qt((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) Qt[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n);
+    for (int j = 0; j < m; j++) {
+        double nrm = 0.0;
+        for (int i = j; i < n; i++) nrm += R[(size_t)i * m + j] * R[(size_t)i * m + j];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0)) return false;
+        const double a = R[(size_t)j * m + j], alpha = a > 0 ? -nrm : nrm;
+        double vn = 0.0;
+        for (int i = j; i < n; i++) {
+            v[i] = R[(size_t)i * m + j] - (i == j ? alpha : 0.0);
+            vn += v[i] * v[i];
         }
-    std::vector<int> piv;
-    if (!lu_factor(m, G, piv)) return false;
-    P.assign((size_t)m * n, 0.0);
-    std::vector<double> col(m);
-    for (int k = 0; k < n; k++) {
-        for (int i = 0; i < m; i++) col[i] = A[(size_t)k * m + i];
-        lu_solve(m, G, piv, col.data());
-        for (int i = 0; i < m; i++) P[(size_t)i * n + k] = col[i];
+        if (!(vn > 0.0)) continue;
+        // apply H = I - 2 v v^T / (v^T v) to the remaining columns of R and to Q^T
+        for (int k = j; k < m; k++) {
+            double d = 0.0;
+            for (int i = j; i < n; i++) d += v[i] * R[(size_t)i * m + k];
+            d *= 2.0 / vn;
+            for (int i = j; i < n; i++) R[(size_t)i * m + k] -= d * v[i];
+        }
+        for (int k = 0; k < n; k++) {
+            double d = 0.0;
+            for (int i = j; i < n; i++) d += v[i] * Qt[(size_t)i * n + k];
+            d *= 2.0 / vn;
+            for (int i = j; i < n; i++) Qt[(size_t)i * n + k] -= d * v[i];
+        }
     }
+    // rank check relative to the largest diagonal entry of R
+    double dmax = 0.0;
+    for (int j = 0; j < m; j++) dmax = std::max(dmax, std::abs(R[(size_t)j * m + j]));
+    for (int j = 0; j < m; j++)
+        if (!(std::abs(R[(size_t)j * m + j]) > 1e-14 * dmax)) return false;
+    // back substitution R P = (Q^T)[0:m, :]
+    P.assign((size_t)m * n, 0.0);
+    for (int k = 0; k < n; k++)
+        for (int i = m - 1; i >= 0; i--) {
+            double s = Qt[(size_t)i * n + k];
+            for (int l = i + 1; l < m; l++) s -= R[(size_t)i * m + l] * P[(size_t)l * n + k];
+            P[(size_t)i * n + k] = s / R[(size_t)i * m + i];
+        }
     return true;
 }
 

@@ -159,4 +159,4 @@ struct rg_geom {
     std::vector<void *> prof_events;
 };
 
-#define RG_NSTAGE 7
+#define RG_NSTAGE RG_NSTAGES

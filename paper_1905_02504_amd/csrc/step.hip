@@ -133,138 +133,136 @@ __global__ void bc_faces(DevGeom G, int bc, const double *Bf, double *Bo)
 
 // ---------------------------------------------------------------- WENO-AO
 // zones of shells g-1 .. g+Nr (interior plus one ghost shell on each side)
+// WENO-AO reconstruction (Section III) of variable v of zone (c, k).  All
+// lanes of a wavefront lie in column c, so the column's stencil offsets and
+// least-squares matrices are uniform and read as scalars.
 template <int P>
-__global__ __launch_bounds__(256) void weno(DevGeom G, const double *__restrict__ U, double *__restrict__ wc)
+__device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restrict__ U, double *__restrict__ wc,
+                                         const double *__restrict__ Pl, const double *__restrict__ Ps,
+                                         const double *__restrict__ Qs, int c, int k, int v)
 {
     using T = Tr<P>;
-    const int KR = G.Nr + 2;
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (i64)G.ncol * KR) return;
-    int c = (int)(t / KR), k = G.g - 1 + (int)(t % KR);
-    i64 z = (i64)c * G.K + k;
-    int dz[T::NS];   // member zone minus this zone (fits 32 bits)
+    const i64 z = (i64)c * G.K + k;
+    const double gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+    const double *Uv = U + (i64)v * G.Z;
+    const double u0 = Uv[z];
+    double du[T::NS];
 #pragma unroll
     for (int j = 0; j < T::NS; j++) {
-        int m = G.stm[(i64)c * T::NS + j];
-        dz[j] = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
+        const int m = G.stm[(i64)c * T::NS + j];   // member zone minus this zone fits 32 bits
+        const int dz = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
+        du[j] = Uv[z + dz] - u0;
     }
-    const double *Pl = G.Pl + (i64)c * T::NC * T::NS;
-    const double *Ps = G.Ps + (i64)c * 7 * 18;
-    const double *Qs = G.Qs + (i64)c * T::NC * T::NC;
-    const double gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+    double chi[T::NC];
+#pragma unroll
+    for (int a = 0; a < T::NC; a++) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < T::NS; j++) s += Pl[a * T::NS + j] * du[j];
+        chi[a] = s;
+    }
+    double cs[7][3];
+#pragma unroll
+    for (int s = 0; s < 7; s++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; j++) acc += Ps[s * 18 + i * 6 + j] * du[j];
+            cs[s][i] = acc;
+        }
+    double bhi = 0.0;
+#pragma unroll
+    for (int a = 0; a < T::NC; a++) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < T::NC; b++) s += Qs[a * T::NC + b] * chi[b];
+        bhi += chi[a] * s;
+    }
+    double w0 = WENO_GAMMA_HI / ((bhi + WENO_EPS) * (bhi + WENO_EPS)), tot = w0, ws[7];
+#pragma unroll
+    for (int s = 0; s < 7; s++) {
+        double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+        ws[s] = gs / ((b + WENO_EPS) * (b + WENO_EPS));
+        tot += ws[s];
+    }
+    double itot = 1.0 / tot;
+    w0 *= itot;
+    double *out = wc + (i64)v * T::NC * G.Z + z;
+#pragma unroll
+    for (int a = 0; a < T::NC; a++) {
+        double lin = 0.0, nl = 0.0;
+        if (a < 3)
+#pragma unroll
+            for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
+        out[(i64)a * G.Z] = w0 / WENO_GAMMA_HI * (chi[a] - lin) + nl;
+    }
+}
+
+// One wavefront per run of up to 64 shells of one column, the eight
+// variables in turn.  With a short tail (nleft shells, at most 8) each column
+// gets one more wavefront whose lanes take (tail shell, variable) pairs.
+template <int P>
+__global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restrict__ U, double *__restrict__ wc,
+                                                const double *__restrict__ PlA, const double *__restrict__ PsA,
+                                                const double *__restrict__ QsA, int nchunk, int nu, int nleft)
+{
+    using T = Tr<P>;
+    const int per = nchunk + (nleft > 0);
+    const int c = blockIdx.x / per, ch = blockIdx.x % per;
+    const double *__restrict__ Pl = PlA + (i64)c * T::NC * T::NS;
+    const double *__restrict__ Ps = PsA + (i64)c * 7 * 18;
+    const double *__restrict__ Qs = QsA + (i64)c * T::NC * T::NC;
+    if (ch < nchunk) {
+        const int kk = ch * 64 + threadIdx.x;
+        if (kk >= nu) return;
 #pragma unroll 1
-    for (int v = 0; v < 8; v++) {
-        // keep the column matrices from being hoisted out of the variable loop
-        // (they would not fit in registers); they are re-read from cache
-        __asm__ __volatile__("" ::: "memory");
-        const double *Uv = U + v * G.Z;
-        double u0 = Uv[z];
-        double du[T::NS];
-#pragma unroll
-        for (int j = 0; j < T::NS; j++) du[j] = Uv[z + dz[j]] - u0;
-        double chi[T::NC];
-#pragma unroll
-        for (int a = 0; a < T::NC; a++) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < T::NS; j++) s += Pl[a * T::NS + j] * du[j];
-            chi[a] = s;
+        for (int v = 0; v < 8; v++) {
+            // an opaque zero offset keeps the matrix reads inside the loop (the
+            // matrices would not fit in registers); they are re-read from cache
+            int vo = 0;
+            __asm__ __volatile__("" : "+s"(vo));
+            weno_var<P>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
         }
-        double cs[7][3];
-#pragma unroll
-        for (int s = 0; s < 7; s++)
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < 6; j++) acc += Ps[s * 18 + i * 6 + j] * du[j];
-                cs[s][i] = acc;
-            }
-        double bhi = 0.0;
-#pragma unroll
-        for (int a = 0; a < T::NC; a++) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < T::NC; b++) s += Qs[a * T::NC + b] * chi[b];
-            bhi += chi[a] * s;
-        }
-        double w0 = WENO_GAMMA_HI / ((bhi + WENO_EPS) * (bhi + WENO_EPS)), tot = w0, ws[7];
-#pragma unroll
-        for (int s = 0; s < 7; s++) {
-            double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
-            ws[s] = gs / ((b + WENO_EPS) * (b + WENO_EPS));
-            tot += ws[s];
-        }
-        double itot = 1.0 / tot;
-        w0 *= itot;
-        double* out = wc + (i64)v * T::NC * G.Z + z;
-#pragma unroll
-        for (int a = 0; a < T::NC; a++) {
-            double lin = 0.0, nl = 0.0;
-            if (a < 3)
-#pragma unroll
-                for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
-            out[(i64)a * G.Z] = w0 / WENO_GAMMA_HI * (chi[a] - lin) + nl;
-        }
+    } else {
+        const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
+        if (kk >= nu + nleft) return;
+        weno_var<P>(G, U, wc, Pl, Ps, Qs, c, G.g - 1 + kk, v);
     }
 }
 
 // ---------------------------------------------------------------- face nodal B
 // radial faces kf in [g-1, g+Nr+1], angular faces in shells [g-1, g+Nr]
+// Limited nodal normal B on one face (Section IV.b): both sides' WENO B at
+// the face quadrature points, MinMod of their deviations from the face mean,
+// then the mean restored.  A missing side takes the other side's value.
+
+// component c3 of one side's WENO B at the face quadrature points
 template <int P>
-__global__ __launch_bounds__(256) void face_bnodal(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
-                                                   const double *__restrict__ wc, double *__restrict__ bnod)
+__device__ __forceinline__ void bnodal_side(const DevGeom &G, const double *__restrict__ U,
+                                            const double *__restrict__ wc, i64 z, const double *fev, int c3,
+                                            double (&Bq)[Tr<P>::Q])
 {
     using T = Tr<P>;
-    const int nrad = G.Nr + 3, nang = G.Nr + 2;
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    i64 nR = (i64)G.ncol * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    i64 f, z[2];
-    bool have[2];
-    const double *fev[2], *nrm, *fw;
-    if (t < nR) {
-        int c = (int)(t / nrad), kf = G.g - 1 + (int)(t % nrad);
-        f = (i64)c * (G.K + 1) + kf;
-        z[0] = (i64)c * G.K + kf - 1;
-        z[1] = (i64)c * G.K + kf;
-        have[0] = (kf - 1 >= G.g - 1) && (kf - 1 <= G.g + G.Nr);
-        have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
-        fev[0] = G.fevR + ((i64)c * 2 + 0) * T::Q * T::NC;
-        fev[1] = G.fevR + ((i64)c * 2 + 1) * T::Q * T::NC;
-        nrm = G.fnR + (i64)c * T::Q * 3;
-        fw = G.fwR + (i64)c * T::Q;
-    } else {
-        i64 u = t - nR;
-        int ae = (int)(u / nang), k = G.g - 1 + (int)(u % nang);
-        f = G.NRF + (i64)ae * G.K + k;
-        z[0] = (i64)G.ae_col[2 * ae] * G.K + k;
-        z[1] = (i64)G.ae_col[2 * ae + 1] * G.K + k;
-        have[0] = have[1] = true;
-        fev[0] = G.fevA + ((i64)ae * 2 + 0) * T::Q * T::NC;
-        fev[1] = G.fevA + ((i64)ae * 2 + 1) * T::Q * T::NC;
-        nrm = G.fnA + (i64)ae * T::Q * 3;
-        fw = G.fwA + (i64)ae * T::Q;
+    const double m0 = U[(5 + c3) * G.Z + z];
+#pragma unroll
+    for (int q = 0; q < T::Q; q++) Bq[q] = m0;
+    const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z;
+    for (int a = 0; a < T::NC; a++) {
+        const double ca = cf[(i64)a * G.Z];
+#pragma unroll
+        for (int q = 0; q < T::Q; q++) Bq[q] += ca * fev[q * T::NC + a];
     }
-    double mean = Bf[f];
-    // both sides' WENO B at the Q points: every coefficient is read once
-    double Bq[2][3][T::Q];
-#pragma unroll
-    for (int s = 0; s < 2; s++) {
-        if (!have[s]) continue;
-#pragma unroll
-        for (int c3 = 0; c3 < 3; c3++) {
-            double m0 = U[(5 + c3) * G.Z + z[s]];
-#pragma unroll
-            for (int q = 0; q < T::Q; q++) Bq[s][c3][q] = m0;
-            const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z[s];
-            for (int a = 0; a < T::NC; a++) {
-                double ca = cf[(i64)a * G.Z];
-#pragma unroll
-                for (int q = 0; q < T::Q; q++) Bq[s][c3][q] += ca * fev[s][q * T::NC + a];
-            }
-        }
-    }
+}
+
+// MinMod of the two sides' normal components, mean restore, store
+template <int P, class BQ>
+__device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__restrict__ Bf, double *__restrict__ bnod,
+                                              i64 f, const bool (&have)[2], const BQ &Bq, const double *nrm,
+                                              const double *fw)
+{
+    using T = Tr<P>;
+    const double mean = Bf[f];
     double bn[T::Q];
 #pragma unroll
     for (int q = 0; q < T::Q; q++) {
@@ -272,7 +270,7 @@ __global__ __launch_bounds__(256) void face_bnodal(DevGeom G, const double *__re
 #pragma unroll
         for (int s = 0; s < 2; s++)
             if (have[s])
-                d[s] = Bq[s][0][q] * nrm[q * 3] + Bq[s][1][q] * nrm[q * 3 + 1] + Bq[s][2][q] * nrm[q * 3 + 2] - mean;
+                d[s] = Bq(s, 0, q) * nrm[q * 3] + Bq(s, 1, q) * nrm[q * 3 + 1] + Bq(s, 2, q) * nrm[q * 3 + 2] - mean;
         if (!have[0]) d[0] = d[1];
         if (!have[1]) d[1] = d[0];
         bn[q] = mean + dev_minmod(d[0], d[1]);
@@ -282,6 +280,80 @@ __global__ __launch_bounds__(256) void face_bnodal(DevGeom G, const double *__re
     for (int q = 0; q < T::Q; q++) sum += fw[q] * bn[q];
 #pragma unroll
     for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = bn[q] + (mean - sum);
+}
+
+// Geometry of a face: radial face kf of column owner, or the angular face of
+// angular edge owner in shell kf.
+template <int P, bool RADIAL>
+struct FaceSides {
+    i64 f, z[2];
+    bool have[2];
+    const double *fev[2], *nrm, *fw;
+    __device__ __forceinline__ FaceSides(const DevGeom &G, int owner, int kf)
+    {
+        using T = Tr<P>;
+        if (RADIAL) {
+            f = (i64)owner * (G.K + 1) + kf;
+            z[0] = (i64)owner * G.K + kf - 1;
+            z[1] = (i64)owner * G.K + kf;
+            have[0] = (kf - 1 >= G.g - 1) && (kf - 1 <= G.g + G.Nr);
+            have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
+            fev[0] = G.fevR + ((i64)owner * 2 + 0) * T::Q * T::NC;
+            fev[1] = G.fevR + ((i64)owner * 2 + 1) * T::Q * T::NC;
+            nrm = G.fnR + (i64)owner * T::Q * 3;
+            fw = G.fwR + (i64)owner * T::Q;
+        } else {
+            f = G.NRF + (i64)owner * G.K + kf;
+            z[0] = (i64)G.ae_col[2 * owner] * G.K + kf;
+            z[1] = (i64)G.ae_col[2 * owner + 1] * G.K + kf;
+            have[0] = have[1] = true;
+            fev[0] = G.fevA + ((i64)owner * 2 + 0) * T::Q * T::NC;
+            fev[1] = G.fevA + ((i64)owner * 2 + 1) * T::Q * T::NC;
+            nrm = G.fnA + (i64)owner * T::Q * 3;
+            fw = G.fwA + (i64)owner * T::Q;
+        }
+    }
+};
+
+// One wavefront per run of up to 64 faces of one column (RADIAL) or of one
+// angular edge, so the face geometry is uniform across the wavefront.  A
+// short tail (nleft faces, at most 8) gets one more wavefront per owner whose
+// lanes take (face, side, component) triples and meet in LDS.
+template <int P, bool RADIAL>
+__global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *__restrict__ U,
+                                                       const double *__restrict__ Bf, const double *__restrict__ wc,
+                                                       double *__restrict__ bnod, int nchunk, int nu, int nleft)
+{
+    using T = Tr<P>;
+    const int per = nchunk + (nleft > 0);
+    const int owner = blockIdx.x / per, ch = blockIdx.x % per;
+    if (ch < nchunk) {
+        const int kk = ch * 64 + threadIdx.x;
+        if (kk >= nu) return;
+        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + kk);
+        double Bq[2][3][T::Q];
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++)
+            if (fs.have[sd])
+#pragma unroll
+                for (int c3 = 0; c3 < 3; c3++) bnodal_side<P>(G, U, wc, fs.z[sd], fs.fev[sd], c3, Bq[sd][c3]);
+        bnodal_finish<P>(G, Bf, bnod, fs.f, fs.have, [&](int sd, int c3, int q) { return Bq[sd][c3][q]; }, fs.nrm,
+                         fs.fw);
+        return;
+    }
+    __shared__ double s_bq[8][2][3][T::Q];
+    const int t = threadIdx.x, fi = t / 6, sd = (t % 6) / 3, c3 = t % 3;
+    if (fi < nleft) {
+        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + nu + fi);
+        const bool hv = sd ? fs.have[1] : fs.have[0];
+        if (hv) bnodal_side<P>(G, U, wc, sd ? fs.z[1] : fs.z[0], sd ? fs.fev[1] : fs.fev[0], c3, s_bq[fi][sd][c3]);
+    }
+    __syncthreads();
+    if (t < nleft) {
+        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + nu + t);
+        bnodal_finish<P>(G, Bf, bnod, fs.f, fs.have, [&](int s2, int k3, int q) { return s_bq[t][s2][k3][q]; },
+                         fs.nrm, fs.fw);
+    }
 }
 
 // ---------------------------------------------------------------- predictor
@@ -473,13 +545,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 #pragma unroll
         for (int v = 0; v < 8; v++) dFa[v] = 0.0;
         apply_d<SN, NZ>(dpk, sf, dFa);
+        // The first sweep starts from the same state at every level, so each
+        // level's flux derivative equals the one at tau = 0: it needs no flux
+        // evaluations and gives the same numbers as the general sweep below.
+        const double on = npic > 0 ? 1.0 : 0.0;
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
-            for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v];
+            for (int v = 0; v < 8; v++) {
+                double u = Ua[v] - on * G.R[t * T::M] * dFa[v];
+#pragma unroll
+                for (int s = 0; s < E; s++) u -= on * G.R[t * T::M + s + 1] * dFa[v];
+                Ut[t][v] = u;
+            }
     }
     __syncthreads();
-    for (int it = 0; it < npic; it++) {
+    for (int it = 1; it < npic; it++) {
         // derivative of each level's flux; a level's state is dead once its
         // flux is in LDS, so at most E + 1 vectors of eight are live here
         double A[E][8];
@@ -891,8 +972,21 @@ static inline unsigned nblocks(i64 n, int bs) { return (unsigned)((n + bs - 1) /
         }                                                            \
     } while (0)
 
+// Runs of up to 64 items along a column: n = nu + nleft, the first nu items
+// in nchunk wavefront-sized runs; a short tail (1 to 8 items beyond a
+// multiple of 64) is left to nleft for the kernels' tail mode.
+struct RunSplit {
+    int nchunk, nu, nleft;
+};
+static RunSplit run_split(int n)
+{
+    const int r = n % 64;
+    if (n >= 64 && r >= 1 && r <= 8) return {n / 64, (n / 64) * 64, r};
+    return {(n + 63) / 64, n, 0};
+}
+
 // stage markers for optional per-stage timing (0 bc, 1 weno, 2 face_bnodal,
-// 3 predictor, 4 face_flux, 5 edge_emf, 6 update)
+// 3 bmap, 4 predictor, 5 face_flux, 6 edge_emf, 7 update)
 struct StageMarks {
     hipEvent_t ev[RG_NSTAGE + 1];
     bool on = false;
@@ -923,33 +1017,39 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(1, st);
     const i64 nzr = (i64)G.ncol * (G.Nr + 2);
-    weno<P><<<nblocks(nzr, 256), 256, 0, st>>>(G, Uo, g->wcoef);
+    const RunSplit wr = run_split(G.Nr + 2);
+    weno_cols<P><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(G, Uo, g->wcoef, G.Pl, G.Ps,
+                                                                                       G.Qs, wr.nchunk, wr.nu, wr.nleft);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
-    const i64 nbn = (i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2);
-    face_bnodal<P><<<nblocks(nbn, 256), 256, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod);
+    const RunSplit br = run_split(G.Nr + 3), ba = run_split(G.Nr + 2);
+    face_bnodal_runs<P, true><<<(unsigned)((i64)G.ncol * (br.nchunk + (br.nleft > 0))), 64, 0, st>>>(
+        G, Uo, Bo, g->wcoef, g->bnod, br.nchunk, br.nu, br.nleft);
+    face_bnodal_runs<P, false><<<(unsigned)((i64)G.nae * (ba.nchunk + (ba.nleft > 0))), 64, 0, st>>>(
+        G, Uo, Bo, g->wcoef, g->bnod, ba.nchunk, ba.nu, ba.nleft);
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
     const int ntile = (G.Nr + 2 + 15) / 16;
     bmap<P><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod, g->bnode, g->zoneB);
     RG_LAUNCH_CHECK();
+    sm.mark(4, st);
     predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, g->wcoef, g->bnode, g->ftr,
                                                                     g->etr);
     RG_LAUNCH_CHECK();
-    sm.mark(4, st);
+    sm.mark(5, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     face_flux<P><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, g->ftr, g->Phi);
     RG_LAUNCH_CHECK();
-    sm.mark(5, st);
+    sm.mark(6, st);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     edge_emf<<<nblocks(nee, 256), 256, 0, st>>>(G, gam, g->etr, g->Gam);
     RG_LAUNCH_CHECK();
-    sm.mark(6, st);
+    sm.mark(7, st);
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
     face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
     RG_LAUNCH_CHECK();
-    sm.mark(7, st);
+    sm.mark(8, st);
     return RG_OK;
 }
 

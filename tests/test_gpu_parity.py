@@ -124,3 +124,13 @@ def test_parity_alfven_fourth_order_subset():
     lib, res, _ = run_case(4, 16, 16, "alfven", cfl=0.3, bc=1)
     for k, v in res.items():
         assert v < bound(k), (k, v)
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_parity_long_columns(order):
+    """64 radial shells: the reconstructed shells (66), radial faces (67) and
+    angular faces (66) per column run one wavefront-sized run past 64, so the
+    kernels' short-tail paths are exercised alongside the full runs."""
+    lib, res, _ = run_case(order, 4, 64, "harmonic", cfl=0.4)
+    for k, v in res.items():
+        assert v < bound(k), (k, v)
