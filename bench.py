@@ -30,6 +30,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}>", "face_bnodal": "face_bnodal_runs<{p}, false>",
+                "bmap": "bmap<{p}>", "predictor": "predictor<{p}>", "face_flux": "face_flux<{p}>",
+                "edge_emf": "edge_emf", "update_ct": "zone_update"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a copy of known size) from the committed rocprofv3 summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_step_order4_6x128cubed.md")
+    src = os.path.join(ROOT, "paper_1905_02504_amd", "csrc", "step.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith(f"traffic {kernel} "):
+            kv = dict(t.split("=", 1) for t in line.split()[2:])
+            if kv.get("step_hip_sha256") != sha:
+                return None
+            return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def cpu_baseline(order, sample_n=8, sample_nr=8):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
@@ -130,14 +154,18 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     dom_s = stage_ms[dom] / nrec * 1e-3
     intensity = flops[dom] / max(bytes_[dom], 1.0)
+    kname = STAGE_KERNEL[dom].format(p=args.order)
+    traffic = measured_traffic(kname) if (args.n_ang, args.n_rad, args.order) == (128, 128, 4) else None
     if intensity >= MACHINE_BALANCE:
         achieved = flops[dom] / dom_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom}
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic, "kernel": kname,
+                "algorithmic_flops": flops[dom], "algorithmic_bytes": bytes_[dom]}
     else:
         achieved = bytes_[dom] / dom_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
+                "algorithmic_flops": flops[dom], "algorithmic_bytes": bytes_[dom]}
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,

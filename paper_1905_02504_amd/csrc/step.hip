@@ -1,11 +1,14 @@
 // Device step of the rg library for gfx950 (FP64).  One launch per stage,
 // all on the caller's stream:
 //   bc_zones / bc_faces : continuative ghost fill (Section VII) into the output state
-//   weno               : WENO-AO in the Taylor basis, one thread per zone (Section III)
-//   face_bnodal        : limited nodal normal B on every face, eqs. (4.11)-(4.12)
-//   predictor          : divergence-free B map (Section IV.b) + ADER-CG Picard
-//                        iteration (Section V.d), one lane per serendipity node,
-//                        then time-averaged traces at face and edge points
+//   weno_cols          : WENO-AO in the Taylor basis (Section III), one wavefront
+//                        per run of shells of one column
+//   face_bnodal_runs   : limited nodal normal B on every face, eqs. (4.11)-(4.12)
+//   bmap               : divergence-free B (Section IV.b) as one dense per-column
+//                        map on the FP64 matrix cores, evaluated at the ADER nodes
+//   predictor          : ADER-CG Picard iteration (Section V.d), one lane per
+//                        serendipity node, then time-averaged traces at face and
+//                        edge points
 //   face_flux          : HLL at face quadrature points -> face flux integrals
 //   edge_emf           : multidimensional HLL electric field at edge Simpson points
 //   zone_update        : finite-volume update of the eight zone averages
@@ -96,6 +99,16 @@ __device__ __forceinline__ double dev_minmod(double a, double b)
 {
     if (!(a * b > 0.0)) return 0.0;
     return a > 0.0 ? fmin(a, b) : fmax(a, b);
+}
+
+// Workgroups are dispatched round-robin over the eight XCDs, each with its
+// own L2.  Renumbering so that XCD x runs one contiguous range of logical
+// blocks keeps the blocks of a column (which share its geometry tables) in
+// one L2.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
 }
 
 // ---------------------------------------------------------------- boundary fill
@@ -209,7 +222,8 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
-    const int c = blockIdx.x / per, ch = blockIdx.x % per;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = lb / per, ch = lb % per;
     const double *__restrict__ Pl = PlA + (i64)c * T::NC * T::NS;
     const double *__restrict__ Ps = PsA + (i64)c * 7 * 18;
     const double *__restrict__ Qs = QsA + (i64)c * T::NC * T::NC;
@@ -326,7 +340,8 @@ __global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
-    const int owner = blockIdx.x / per, ch = blockIdx.x % per;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int owner = lb / per, ch = lb % per;
     if (ch < nchunk) {
         const int kk = ch * 64 + threadIdx.x;
         if (kk >= nu) return;
@@ -399,7 +414,8 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
     constexpr int NA = 3 * (T::NC + 1), NQ = NA + 6 * T::Q;
     static_assert(NIN % 4 == 0, "input count must be a multiple of 4");
     const int KR = G.Nr + 2, nt = (KR + 15) / 16;
-    const int c = blockIdx.x / nt, tile = blockIdx.x % nt;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = lb / nt, tile = lb % nt;
     const int l = threadIdx.x, g = l >> 4, jz = l & 15;
     const int kk = tile * 16 + jz;
     const bool active = kk < KR;
@@ -491,7 +507,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
     // zone counts stay below 2^31 (checked at launch)
-    const unsigned zt = blockIdx.x * ZPW + zl;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned zt = lb * ZPW + zl;
     const bool active = (zl < ZPW) && (zt < (unsigned)nzr);
     int c = 0, k = 0;
     i64 z = 0;
@@ -627,7 +644,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 #pragma unroll 1
     for (int t = lane; t < ZPW * 48; t += 64) {
         const int zq = t / 48, lf = (t % 48) / 8, v = t % 8;
-        const unsigned ztq = blockIdx.x * ZPW + zq;
+        const unsigned ztq = lb * ZPW + zq;
         if (ztq >= (unsigned)nzr) continue;
         const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
         const double *sx = s_f[zq];
@@ -684,7 +701,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     // three electric-field components (eq. 2.3) to the edge's Simpson points.
     if (lane < ZPW * 12) {
         const int zq = lane / 12, le = lane % 12;
-        const unsigned ztq = blockIdx.x * ZPW + zq;
+        const unsigned ztq = lb * ZPW + zq;
         if (ztq < (unsigned)nzr) {
             const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
             const double *sx = s_f[zq];
