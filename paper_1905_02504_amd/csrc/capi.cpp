@@ -7,6 +7,7 @@
 #include <new>
 #include <string>
 
+#include "dtab.hpp"
 #include "rg_geom_host.hpp"
 
 namespace rg {
@@ -67,6 +68,32 @@ extern "C" rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info)
 extern "C" void rg_mesh_free(rg_mesh *mesh) { delete mesh; }
 
 namespace {
+
+// D_d[i][l] == D_0[S_d(i)][S_d(l)] with D_0 and the swaps S_d from dtab.hpp
+template <int P>
+bool check_dtab_order(const RefEl &r)
+{
+    using D = DTab<P>;
+    const int N = r.N;
+    std::vector<double> D0((size_t)N * N, 0.0);
+    for (int e = 0; e < D::NNZ; e++) D0[(size_t)D::E[e][0] * N + D::E[e][1]] = 0.5 * D::E[e][2];
+    for (int d = 0; d < 3; d++)
+        for (int i = 0; i < N; i++)
+            for (int l = 0; l < N; l++) {
+                const int si = d == 0 ? i : d == 1 ? D::SWAP1[i] : D::SWAP2[i];
+                const int sl = d == 0 ? l : d == 1 ? D::SWAP1[l] : D::SWAP2[l];
+                if (r.D[((size_t)d * N + i) * N + l] != D0[(size_t)si * N + sl]) return false;
+            }
+    return true;
+}
+
+bool check_dtab(const RefEl &r)
+{
+    if (r.order == 3) return r.N == 20 && check_dtab_order<3>(r);
+    if (r.order == 4) return r.N == 32 && check_dtab_order<4>(r);
+    return false;
+}
+
 
 template <typename T>
 bool upload(rg_geom *g, const std::vector<T> &h, const T **dst)
@@ -234,36 +261,12 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                 }
             }
 
-        // derivative matrices as padded rows per node over the three directions;
-        // an entry addresses the node-fastest flux slab in the predictor's LDS
-        int NZ = 0;
-        for (int i = 0; i < N; i++) {
-            int n = 0;
-            for (int d = 0; d < 3; d++)
-                for (int l = 0; l < N; l++) n += r.D[((size_t)d * N + i) * N + l] != 0.0;
-            NZ = std::max(NZ, n);
-        }
-        // Each entry packs twice the value (an integer: the entries are
-        // multiples of 1/2) in the high 16 bits and the slab offset
-        // d*8*(N+1) + l in the low 16 bits (the slab rows are N+1 long).
-        std::vector<int> doff((size_t)N * NZ);
-        for (int i = 0; i < N; i++) {
-            int n = 0;
-            for (int d = 0; d < 3; d++)
-                for (int l = 0; l < N; l++) {
-                    double v = r.D[((size_t)d * N + i) * N + l];
-                    if (v != 0.0) {
-                        int twice = (int)std::lround(2.0 * v);
-                        const int off = d * 8 * (N + 1) + l;
-                        if (2.0 * v != (double)twice || std::abs(twice) > 32767 || off > 65535) {
-                            set_error("derivative matrix entry is not a small multiple of 1/2");
-                            return RG_EINVAL;
-                        }
-                        doff[(size_t)i * NZ + n] = (int)((unsigned)twice << 16) | off;
-                        n++;
-                    }
-                }
-            for (; n < NZ; n++) doff[(size_t)i * NZ + n] = i;
+        // The predictor applies the derivative matrices from compile-time
+        // tables (D_0 and the coordinate swaps); they must match the computed
+        // matrices exactly.
+        if (!check_dtab(r)) {
+            set_error("derivative matrices differ from the compiled-in tables");
+            return RG_EINVAL;
         }
         // node-fastest / output-fastest copies of the per-column matrices
         std::vector<double> EvT((size_t)ncol * NC * N), MbT((size_t)ncol * r.NIN * r.NOUTB), nMT((size_t)ncol * 9 * N);
@@ -289,9 +292,9 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         d.order = order; d.N = N; d.M = r.M; d.NC = NC; d.NB = r.NB; d.Q = Q; d.NS = NS;
         d.NIN = r.NIN; d.NOUTB = r.NOUTB; d.NFN = r.NFN; d.NEN = r.NEN;
         d.Nang = m.N; d.Nr = m.Nr; d.g = m.g; d.K = K; d.ncol = ncol; d.nv = nv; d.nae = nae;
-        d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre; d.NZ = NZ;
+        d.Z = Z; d.NF = NF; d.NRF = m.nrf; d.NE = NE; d.NRE = m.nre;
         bool ok = upload(g, radius, &d.radius) && upload(g, zs, &d.zscale) && upload(g, Rv, &d.R) &&
-                  upload(g, wt, &d.wt) && upload(g, doff, &d.doff) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
+                  upload(g, wt, &d.wt) && upload(g, r.fnode, &d.fnode) && upload(g, r.fint, &d.fint) &&
                   upload(g, r.enode, &d.enode) && upload(g, r.eint, &d.eint) && upload(g, r.fintc, &d.fintc) &&
                   upload(g, r.eintc, &d.eintc) && upload(g, hg.stm, &d.stm) &&
                   upload(g, hg.Pl, &d.Pl) && upload(g, hg.Ps, &d.Ps) && upload(g, hg.Qs, &d.Qs) &&

@@ -85,9 +85,6 @@ struct DevGeom {
     const double *zscale;   // K: zone length scale relative to shell 0
     const double *R;        // (M-1) x M
     const double *wt;       // M
-    const int *doff;        // N x NZ  derivative entries per node: (2 D_d[i][l]) << 16 | (d * 8) * (N + 1) + l,
-                            //         padded with i (value 0)
-    int NZ;                 // entries per node (padded)
     const int *fnode;       // 6 x NFN
     const double *fint;     // 6 x Q x NFN
     const int *enode;       // 12 x NEN

@@ -15,6 +15,7 @@
 //   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
 #include <hip/hip_runtime.h>
 
+#include "dtab.hpp"
 #include "rg_geom_host.hpp"
 
 namespace rg {
@@ -23,11 +24,11 @@ template <int P>
 struct Tr;
 template <>
 struct Tr<3> {
-    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3, NZ = 18;
+    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3;
 };
 template <>
 struct Tr<4> {
-    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4, NZ = 20;
+    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4;
 };
 
 typedef long long i64;
@@ -466,26 +467,55 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
         }
 }
 
-// acc += (D_xi F_xi + D_eta F_eta + D_zeta F_zeta) at this lane's node, the
-// fluxes read from the node-fastest LDS slab (rows of SN = N + 1 doubles).
-// The packed entries hold twice the matrix value; halving the sum at the end
-// is exact.
-template <int SN, int NZ>
-__device__ __forceinline__ void apply_d(const int (&dpk)[NZ], const double *sf, double (&acc)[8])
+// Flux derivatives through the LDS slab.  Node lanes store the flux along
+// direction d of their node at the node's position under the coordinate swap
+// xi <-> d (identity for d = 0), so every one of the 24 (direction, variable)
+// rows holds its values in the xi-derivative's own node order.  One lane per
+// row then applies the xi-derivative matrix D_0, whose sparsity and entries
+// (multiples of 1/2) are compile-time constants, in place: a row is read
+// once into registers and each value is reused by all the outputs that need
+// it.  D_d = S_d D_0 S_d for the swap S_d, so slot i of row (d, v) ends up
+// holding the d-derivative at node S_d(i).
+template <int SN>
+__device__ __forceinline__ void put_flux(double *sf, int i, int i1, int i2, const double (&F)[3][8])
 {
-    double s[8];
 #pragma unroll
-    for (int v = 0; v < 8; v++) s[v] = 0.0;
-#pragma unroll
-    for (int p = 0; p < NZ; p++) {
-        int pk = dpk[p];
-        double dv = (double)(pk >> 16);
-        const double *col = sf + (pk & 0xffff);
-#pragma unroll
-        for (int v = 0; v < 8; v++) s[v] += dv * col[v * SN];
+    for (int v = 0; v < 8; v++) {
+        sf[v * SN + i] = F[0][v];
+        sf[(8 + v) * SN + i1] = F[1][v];
+        sf[(16 + v) * SN + i2] = F[2][v];
     }
+}
+
+template <int P, int SN, int ZS, int ZPW>
+__device__ __forceinline__ void deriv_rows(double *slab, int lane)
+{
+    using D = DTab<P>;
+    constexpr int N = Tr<P>::N;
+#pragma unroll 1
+    for (int t = lane; t < ZPW * 24; t += 64) {
+        double *row = slab + (t / 24) * ZS + (t % 24) * SN;
+        double x[N];
 #pragma unroll
-    for (int v = 0; v < 8; v++) acc[v] += 0.5 * s[v];
+        for (int j = 0; j < N; j++) x[j] = row[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < D::NNZ; e++) {
+            acc += (0.5 * D::E[e][2]) * x[D::E[e][1]];
+            if (e == D::NNZ - 1 || D::E[e + 1][0] != D::E[e][0]) {
+                row[D::E[e][0]] = acc;
+                acc = 0.0;
+            }
+        }
+    }
+}
+
+// acc = sum over the three directions of the derivative at node i
+template <int SN>
+__device__ __forceinline__ void get_deriv(const double *sf, int i, int i1, int i2, double (&acc)[8])
+{
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] = sf[v * SN + i] + sf[(8 + v) * SN + i1] + sf[(16 + v) * SN + i2];
 }
 
 // ADER-CG predictor (Section V.d).  One wavefront holds 64 / N zones, one lane
@@ -500,9 +530,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     using T = Tr<P>;
     // slab rows are N + 1 long so that lanes reading one node's different
     // variables fall into different LDS banks
-    constexpr int N = T::N, SN = N + 1, ZPW = 64 / N, E = T::M - 1, NZ = T::NZ, NCF = T::NC + 1;
+    // zone slabs are padded by four doubles so that the two zones' rows fall
+    // into different LDS banks
+    constexpr int N = T::N, SN = N + 1, ZS = 32 * SN + 4, ZPW = 64 / N, E = T::M - 1, NCF = T::NC + 1;
     __shared__ double s_c[ZPW][5 * NCF];
-    __shared__ double s_f[ZPW][32 * SN];
+    __shared__ double s_f[ZPW * ZS];
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
@@ -521,13 +553,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             s_c[zl][j] = a == 0 ? U[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
         }
     }
-    int dpk[NZ];
-#pragma unroll
-    for (int p = 0; p < NZ; p++) dpk[p] = G.doff[i * NZ + p];
+    const int i1 = DTab<P>::SWAP1[i], i2 = DTab<P>::SWAP2[i];
     __syncthreads();
 
     double Ua[8], Ut[E][8], dFa[8], met[9], iJ = 1.0, fac = 0.0;
-    double *sf = s_f[zl < ZPW ? zl : 0];
+    double *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
     if (active) {
         const double *Ev = G.Ev + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
@@ -552,16 +582,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         // level tau = 0: its flux derivative is the same in every iteration
         double F[3][8];
         mapped_flux<P>(Ua, iJ, met, gam, F);
-#pragma unroll
-        for (int d = 0; d < 3; d++)
-#pragma unroll
-            for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
+        put_flux<SN>(sf, i, i1, i2, F);
     }
     __syncthreads();
+    deriv_rows<P, SN, ZS, ZPW>(s_f, lane);
+    __syncthreads();
     if (active) {
-#pragma unroll
-        for (int v = 0; v < 8; v++) dFa[v] = 0.0;
-        apply_d<SN, NZ>(dpk, sf, dFa);
+        get_deriv<SN>(sf, i, i1, i2, dFa);
         // The first sweep starts from the same state at every level, so each
         // level's flux derivative equals the one at tau = 0: it needs no flux
         // evaluations and gives the same numbers as the general sweep below.
@@ -586,15 +613,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             if (active) {
                 double F[3][8];
                 mapped_flux<P>(Ut[s], iJ, met, gam, F);
-#pragma unroll
-                for (int d = 0; d < 3; d++)
-#pragma unroll
-                    for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
+                put_flux<SN>(sf, i, i1, i2, F);
             }
+            __syncthreads();
+            deriv_rows<P, SN, ZS, ZPW>(s_f, lane);
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < 8; v++) A[s][v] = 0.0;
-            if (active) apply_d<SN, NZ>(dpk, sf, A[s]);
+            if (active) get_deriv<SN>(sf, i, i1, i2, A[s]);
             __syncthreads();
         }
 #pragma unroll
@@ -647,7 +673,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         const unsigned ztq = lb * ZPW + zq;
         if (ztq >= (unsigned)nzr) continue;
         const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
-        const double *sx = s_f[zq];
+        const double *sx = s_f + zq * ZS;
         double x[T::NFN][4];
 #pragma unroll
         for (int kk = 0; kk < T::NFN; kk++) {
@@ -704,7 +730,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         const unsigned ztq = lb * ZPW + zq;
         if (ztq < (unsigned)nzr) {
             const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
-            const double *sx = s_f[zq];
+            const double *sx = s_f + zq * ZS;
             double ae3[3][11];
 #pragma unroll
             for (int p = 0; p < 3; p++)
