@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--cfl", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--calib", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -108,11 +109,9 @@ def main():
     U_h, Bf_h = shell.init_alfven(prob, noise=noise, noise_amp=0.01)
     t_init = time.perf_counter() - t0
     log(f"[bench] initial data {t_init:.1f}s")
-    U = torch.from_numpy(U_h).cuda()
-    Bf = torch.from_numpy(Bf_h).cuda()
+    U0 = torch.from_numpy(U_h).cuda()
+    Bf0 = torch.from_numpy(Bf_h).cuda()
     del U_h, Bf_h, noise
-    U2 = torch.empty_like(U)
-    Bf2 = torch.empty_like(Bf)
     gam = prob["gamma"]
     if args.calib:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -121,34 +120,43 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
-    dt = shell.cfl_dt(U, args.cfl, gam)
-    for _ in range(args.warmup):
-        shell.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
-        U, U2, Bf, Bf2 = U2, U, Bf2, Bf
-    torch.cuda.synchronize()
-    log("[bench] warmup done")
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    shell.profile_begin()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        shell.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
-        U, U2, Bf, Bf2 = U2, U, Bf2, Bf
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    stage_ms, nrec = shell.profile_end()
-    total_ms = ev0.elapsed_time(ev1)
+    dt = shell.cfl_dt(U0, args.cfl, gam)
+
+    def run(sh):
+        """warmup + timed steps from the initial state; returns the final state"""
+        U, Bf = U0.clone(), Bf0.clone()
+        U2, Bf2 = torch.empty_like(U), torch.empty_like(Bf)
+        for _ in range(args.warmup):
+            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+            U, U2, Bf, Bf2 = U2, U, Bf2, Bf
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        sh.profile_begin()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+            U, U2, Bf, Bf2 = U2, U, Bf2, Bf
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        stage_ms, nrec = sh.profile_end()
+        del U2, Bf2
+        return U, Bf, ev0.elapsed_time(ev1), stage_ms, nrec
+
+    U, Bf, total_ms, stage_ms, nrec = run(shell)
     ms_step = total_ms / args.steps
     interior = 6 * args.n_ang * args.n_ang * args.n_rad
     value = interior * args.steps / (total_ms * 1e-3)
     log(f"[bench] {ms_step:.2f} ms/step, stages (ms/step): " +
         ", ".join(f"{k} {v / nrec:.2f}" for k, v in stage_ms.items()))
-    # sanity: finite state, divergence-free B is checked by the tests
     if not torch.isfinite(U).all():
         log("[bench] non-finite state after the timed steps")
         sys.exit(1)
+    diag64 = shell.diag(U, Bf, gam)
+    log(f"[bench] FP64: max relative div B {diag64['div_rel_max']:.2e}, "
+        f"min rho {diag64['rho_min']:.4f}, min p {diag64['p_min']:.4f}")
 
     flops, bytes_ = shell.work()
     dom = max(stage_ms, key=stage_ms.get)
@@ -166,6 +174,33 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
                 "algorithmic_flops": flops[dom], "algorithmic_bytes": bytes_[dom]}
+    mixed = None
+    if not args.no_mixed:
+        from paper_1905_02504_amd import _native as NV
+        inter = torch.from_numpy(shell.interior()).cuda()
+        shell.close()   # its work buffers and those of the FP32 geometry do not both fit in HBM
+        t0 = time.perf_counter()
+        shell32 = R.ShellMHD(args.n_ang, args.n_rad, args.order, n_ghost=max(3, args.order - 1),
+                             mode=NV.RG_MODE_FP32)
+        log(f"[bench] FP32-form geometry {time.perf_counter() - t0:.1f}s")
+        U32, Bf32, total32, stage32, nrec32 = run(shell32)
+        ms32 = total32 / args.steps
+        log(f"[bench] FP32 form: {ms32:.2f} ms/step, stages (ms/step): " +
+            ", ".join(f"{k} {v / nrec32:.2f}" for k, v in stage32.items()))
+        names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
+        a64, a32 = U[:, inter], U32[:, inter]
+        l1 = ((a32 - a64).abs().sum(1) / a64.abs().sum(1)).cpu().numpy()
+        l1b = float((Bf32 - Bf).abs().sum() / Bf.abs().sum())
+        diag32 = shell32.diag(U32, Bf32, gam)
+        mixed = {"mode": "fp32 (reconstruction, predictor and traces; geometry, div-free map, Riemann solvers, "
+                         "update and CT in fp64)",
+                 "value": interior * args.steps / (total32 * 1e-3), "ms_per_step": ms32,
+                 "speedup_vs_fp64": ms_step / ms32,
+                 "rel_l1_vs_fp64_after_steps": args.warmup + args.steps,
+                 "rel_l1_vs_fp64": {k: float(v) for k, v in zip(names, l1)}, "rel_l1_face_B": l1b,
+                 "div_b_rel_max": diag32["div_rel_max"],
+                 "stage_ms_per_step": {k: round(v / nrec32, 4) for k, v in stage32.items()}}
+        shell32.close()
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,
@@ -185,6 +220,8 @@ def main():
                    "setup_s": {"geometry": round(t_geom, 2), "initial_data": round(t_init, 2)},
                    "stage_ms_per_step": {k: round(v / nrec, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
+        "div_b_rel_max": diag64["div_rel_max"],
+        "mixed": mixed,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle sample)")

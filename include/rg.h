@@ -83,8 +83,15 @@ rg_status rg_mesh_build(const rg_mesh_desc *desc, rg_mesh **out);
 rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info);
 void rg_mesh_free(rg_mesh *mesh);
 
-/* Precision of the reconstruction and predictor contractions.  Geometry,
- * the conservative update and constrained transport are always FP64. */
+/* Precision of the reconstruction and predictor contractions (the paper's
+ * scheme is FP64 throughout; RG_MODE_FP32 is the reduced-precision form).
+ * In RG_MODE_FP32 the WENO-AO contractions and weights, the face nodal B
+ * contractions, the ADER-CG predictor (fluxes, derivatives, Picard updates,
+ * time averages) and the face / edge traces are computed and stored in FP32,
+ * from FP32 copies of the per-column tables.  Geometry precompute, the state
+ * U and Bf, the divergence-free map (FP64 matrix cores), the Riemann solvers,
+ * the conservative update and constrained transport stay FP64, so div B
+ * stays at round-off in either mode. */
 typedef enum { RG_MODE_FP64 = 0, RG_MODE_FP32 = 1 } rg_mode;
 
 /* Geometry precompute (Section VI step 1): FP64 on the host, one radial column
@@ -150,6 +157,21 @@ rg_status rg_cfl_dt(const rg_geom *geom, const double *U, double gamma, double c
 rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, double p, double B0, double dB,
                          double wavelength, double gamma, double t, const double *noise, double noise_amp,
                          double *U, double *Bf);
+
+/* Diagnostics of a state on the device (for checks after a step; not part of
+ * the scheme): over the interior zones, the largest relative divergence
+ * |sum_faces sigma A <B.n>| / sum_faces A |<B.n>| (sigma = +1 on outward
+ * faces), the volume-weighted sums sum V U_v of the eight conserved
+ * variables, and the smallest density and gas pressure.  U and Bf are device
+ * buffers in the rg_step layout.  Deterministic (fixed reduction order);
+ * synchronises `stream` before returning. */
+typedef struct {
+    double div_rel_max;
+    double sums[8];
+    double rho_min, p_min;
+} rg_diag_out;
+rg_status rg_diag(const rg_geom *geom, const double *U, const double *Bf, double gamma, void *stream,
+                  rg_diag_out *out);
 
 /* Per-stage timing with HIP events recorded on the step's own stream.
  * After rg_profile_begin, every rg_step records events around its

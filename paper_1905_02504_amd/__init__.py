@@ -127,6 +127,10 @@ class ShellMHD:
         return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())
 
     # per-stage timing ----------------------------------------------------------
+    def diag(self, U, Bf, gamma=5.0 / 3.0):
+        """rg_diag: max relative div B, volume-weighted sums, min rho and p."""
+        return N.rg_diag(self._geom, U.data_ptr(), Bf.data_ptr(), gamma, _stream())
+
     def profile_begin(self):
         N.rg_profile_begin(self._geom)
 

@@ -32,6 +32,11 @@ class rg_step_params(C.Structure):
                 ("n_picard", C.c_int32)]
 
 
+class rg_diag_out(C.Structure):
+    _fields_ = [("div_rel_max", C.c_double), ("sums", C.c_double * 8), ("rho_min", C.c_double),
+                ("p_min", C.c_double)]
+
+
 class RGError(RuntimeError):
     pass
 
@@ -67,12 +72,13 @@ def lib():
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
         L.rg_geom_work.argtypes = [_vp, _dp, _dp]
+        L.rg_diag.argtypes = [_vp, _vp, _vp, C.c_double, _vp, C.POINTER(rg_diag_out)]
         L.rg_geom_work.restype = C.c_int
         L.rg_profile_begin.argtypes = [_vp]
         L.rg_profile_end.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
-                     "rg_cfl_dt", "rg_init_alfven"):
+                     "rg_cfl_dt", "rg_init_alfven", "rg_diag"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -148,6 +154,12 @@ def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
 def rg_init_alfven(geom, frame_ptr, rho, p, B0, dB, wavelength, gamma, t, noise_ptr, noise_amp, U_ptr, Bf_ptr):
     check(lib().rg_init_alfven(geom, _vp(frame_ptr), rho, p, B0, dB, wavelength, gamma, t, _vp(noise_ptr),
                                noise_amp, _vp(U_ptr), _vp(Bf_ptr)), "rg_init_alfven")
+
+
+def rg_diag(geom, U_ptr, Bf_ptr, gamma, stream):
+    out = rg_diag_out()
+    check(lib().rg_diag(geom, _vp(U_ptr), _vp(Bf_ptr), gamma, _vp(stream), C.byref(out)), "rg_diag")
+    return {"div_rel_max": out.div_rel_max, "sums": list(out.sums), "rho_min": out.rho_min, "p_min": out.p_min}
 
 
 STAGES = ("bc_fill", "weno", "face_bnodal", "bmap", "predictor", "face_flux", "edge_emf", "update_ct")

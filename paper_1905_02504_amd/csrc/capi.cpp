@@ -107,6 +107,13 @@ bool upload(rg_geom *g, const std::vector<T> &h, const T **dst)
     return true;
 }
 
+// FP32 copy of a double table (precision mode RG_MODE_FP32)
+bool upload_f32(rg_geom *g, const std::vector<double> &h, const float **dst)
+{
+    std::vector<float> f(h.begin(), h.end());
+    return upload(g, f, dst);
+}
+
 bool alloc_zero(rg_geom *g, size_t n, double **dst)
 {
     void *p = nullptr;
@@ -309,6 +316,11 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                   upload(g, hg.aeF, &d.aeF) && upload(g, hg.aeW, &d.aeW) && upload(g, hg.ae_rs, &d.ae_rs) &&
                   upload(g, vncol, &d.v_ncol) && upload(g, hg.vF, &d.vF) && upload(g, hg.vN3, &d.vN3) &&
                   upload(g, vol, &d.vol) && upload(g, area, &d.area);
+        if (ok && mode == RG_MODE_FP32)
+            ok = upload_f32(g, hg.Pl, &d.PlF) && upload_f32(g, hg.Ps, &d.PsF) && upload_f32(g, hg.Qs, &d.QsF) &&
+                 upload_f32(g, EvT, &d.EvF) && upload_f32(g, hg.nJ, &d.nJF) && upload_f32(g, nMT, &d.nMF) &&
+                 upload_f32(g, hg.fevR, &d.fevRF) && upload_f32(g, hg.fevA, &d.fevAF) &&
+                 upload_f32(g, r.fintc, &d.fintcF) && upload_f32(g, r.eintc, &d.eintcF);
         if (!ok) { set_error("device allocation or upload of the geometry failed"); free_geom(g); return RG_ENOMEM; }
         ok = alloc_zero(g, (size_t)NVAR * NC * Z, &g->wcoef) && alloc_zero(g, (size_t)Q * NF, &g->bnod) &&
              alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &g->etr) &&
@@ -396,6 +408,14 @@ extern "C" rg_status rg_step_fluxes(const rg_geom *g, double *Phi, double *Gam, 
         return RG_EDEVICE;
     }
     return RG_OK;
+}
+
+extern "C" rg_status rg_diag(const rg_geom *g, const double *U, const double *Bf, double gamma, void *stream,
+                             rg_diag_out *out)
+{
+    if (!g || !U || !Bf || !out || !(gamma > 1.0)) { set_error("invalid argument"); return RG_EINVAL; }
+    if (!g->d.vol) { set_error("geometry was built without a device copy"); return RG_EINVAL; }
+    return launch_diag(const_cast<rg_geom *>(g), U, Bf, gamma, stream, out);
 }
 
 extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)

@@ -127,6 +127,9 @@ struct DevGeom {
     // per zone / face
     const double *vol;      // Z
     const double *area;     // NF
+    // FP32 copies of the tables read by the reconstruction and predictor
+    // contractions (precision mode RG_MODE_FP32 only; null otherwise)
+    const float *PlF, *PsF, *QsF, *EvF, *nJF, *nMF, *fevRF, *fevAF, *fintcF, *eintcF;
 };
 
 }  // namespace rg

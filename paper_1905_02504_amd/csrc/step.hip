@@ -44,26 +44,36 @@ __device__ __forceinline__ double dev_pressure(const double *u, double gam)
     return (gam - 1.0) * (u[4] - 0.5 * m2 / u[0] - 0.5 * b2);
 }
 
-// F[d][v]: flux of conserved variable v along Cartesian direction d (eq. 2.2)
-__device__ __forceinline__ void dev_flux(const double *u, double gam, double F[3][8])
+// F[d][v]: flux of conserved variable v along Cartesian direction d (eq. 2.2),
+// in the arithmetic type R of the caller
+template <class R>
+__device__ __forceinline__ void dev_flux(const R *u, R gam, R F[3][8])
 {
-    double ir = 1.0 / u[0];
-    double v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
-    double B0 = u[5], B1 = u[6], B2 = u[7];
-    double hb2 = 0.5 * (B0 * B0 + B1 * B1 + B2 * B2);
-    double p = (gam - 1.0) * (u[4] - 0.5 * (u[1] * v0 + u[2] * v1 + u[3] * v2) - hb2);
-    double pt = p + hb2;
-    double vB = v0 * B0 + v1 * B1 + v2 * B2;
-    double v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
+    R ir = R(1) / u[0];
+    R v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
+    R B0 = u[5], B1 = u[6], B2 = u[7];
+    R hb2 = R(0.5) * (B0 * B0 + B1 * B1 + B2 * B2);
+    R p = (gam - R(1)) * (u[4] - R(0.5) * (u[1] * v0 + u[2] * v1 + u[3] * v2) - hb2);
+    R pt = p + hb2;
+    R vB = v0 * B0 + v1 * B1 + v2 * B2;
+    R v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         F[d][0] = u[1 + d];
 #pragma unroll
-        for (int i = 0; i < 3; i++) F[d][1 + i] = u[1 + d] * v[i] + (d == i ? pt : 0.0) - B[d] * B[i];
+        for (int i = 0; i < 3; i++) F[d][1 + i] = u[1 + d] * v[i] + (d == i ? pt : R(0)) - B[d] * B[i];
         F[d][4] = (u[4] + pt) * v[d] - B[d] * vB;
 #pragma unroll
         for (int i = 0; i < 3; i++) F[d][5 + i] = v[d] * B[i] - B[d] * v[i];
     }
+}
+
+// geometry table of precision R: the FP64 table or its FP32 copy
+template <class R>
+__device__ __forceinline__ const R *pick(const double *d, const float *f)
+{
+    if constexpr (sizeof(R) == sizeof(double)) return d;
+    else return f;
 }
 
 __device__ __forceinline__ double dev_fast(const double *u, double gam, const double *n)
@@ -150,84 +160,84 @@ __global__ void bc_faces(DevGeom G, int bc, const double *Bf, double *Bo)
 // WENO-AO reconstruction (Section III) of variable v of zone (c, k).  All
 // lanes of a wavefront lie in column c, so the column's stencil offsets and
 // least-squares matrices are uniform and read as scalars.
-template <int P>
-__device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restrict__ U, double *__restrict__ wc,
-                                         const double *__restrict__ Pl, const double *__restrict__ Ps,
-                                         const double *__restrict__ Qs, int c, int k, int v)
+template <int P, class R>
+__device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restrict__ U, R *__restrict__ wc,
+                                         const R *__restrict__ Pl, const R *__restrict__ Ps, const R *__restrict__ Qs,
+                                         int c, int k, int v)
 {
     using T = Tr<P>;
     const i64 z = (i64)c * G.K + k;
-    const double gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+    const R ghi = R(WENO_GAMMA_HI), gs = R((1.0 - WENO_GAMMA_HI) / 7.0), eps = R(WENO_EPS);
     const double *Uv = U + (i64)v * G.Z;
     const double u0 = Uv[z];
-    double du[T::NS];
+    R du[T::NS];
 #pragma unroll
     for (int j = 0; j < T::NS; j++) {
         const int m = G.stm[(i64)c * T::NS + j];   // member zone minus this zone fits 32 bits
         const int dz = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
-        du[j] = Uv[z + dz] - u0;
+        du[j] = R(Uv[z + dz] - u0);
     }
-    double chi[T::NC];
+    R chi[T::NC];
 #pragma unroll
     for (int a = 0; a < T::NC; a++) {
-        double s = 0.0;
+        R s = R(0);
 #pragma unroll
         for (int j = 0; j < T::NS; j++) s += Pl[a * T::NS + j] * du[j];
         chi[a] = s;
     }
-    double cs[7][3];
+    R cs[7][3];
 #pragma unroll
     for (int s = 0; s < 7; s++)
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            double acc = 0.0;
+            R acc = R(0);
 #pragma unroll
             for (int j = 0; j < 6; j++) acc += Ps[s * 18 + i * 6 + j] * du[j];
             cs[s][i] = acc;
         }
-    double bhi = 0.0;
+    R bhi = R(0);
 #pragma unroll
     for (int a = 0; a < T::NC; a++) {
-        double s = 0.0;
+        R s = R(0);
 #pragma unroll
         for (int b = 0; b < T::NC; b++) s += Qs[a * T::NC + b] * chi[b];
         bhi += chi[a] * s;
     }
-    double w0 = WENO_GAMMA_HI / ((bhi + WENO_EPS) * (bhi + WENO_EPS)), tot = w0, ws[7];
+    R w0 = ghi / ((bhi + eps) * (bhi + eps)), tot = w0, ws[7];
 #pragma unroll
     for (int s = 0; s < 7; s++) {
-        double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
-        ws[s] = gs / ((b + WENO_EPS) * (b + WENO_EPS));
+        R b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+        ws[s] = gs / ((b + eps) * (b + eps));
         tot += ws[s];
     }
-    double itot = 1.0 / tot;
+    R itot = R(1) / tot;
     w0 *= itot;
-    double *out = wc + (i64)v * T::NC * G.Z + z;
+    R *out = wc + (i64)v * T::NC * G.Z + z;
 #pragma unroll
     for (int a = 0; a < T::NC; a++) {
-        double lin = 0.0, nl = 0.0;
+        R lin = R(0), nl = R(0);
         if (a < 3)
 #pragma unroll
             for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
-        out[(i64)a * G.Z] = w0 / WENO_GAMMA_HI * (chi[a] - lin) + nl;
+        out[(i64)a * G.Z] = w0 / ghi * (chi[a] - lin) + nl;
     }
 }
 
 // One wavefront per run of up to 64 shells of one column, the eight
 // variables in turn.  With a short tail (nleft shells, at most 8) each column
 // gets one more wavefront whose lanes take (tail shell, variable) pairs.
-template <int P>
-__global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restrict__ U, double *__restrict__ wc,
-                                                const double *__restrict__ PlA, const double *__restrict__ PsA,
-                                                const double *__restrict__ QsA, int nchunk, int nu, int nleft)
+template <int P, class R>
+__global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restrict__ U, R *__restrict__ wc,
+                                                const R *__restrict__ PlA, const R *__restrict__ PsA,
+                                                const R *__restrict__ QsA, int nchunk, int nu, int nleft)
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int c = lb / per, ch = lb % per;
-    const double *__restrict__ Pl = PlA + (i64)c * T::NC * T::NS;
-    const double *__restrict__ Ps = PsA + (i64)c * 7 * 18;
-    const double *__restrict__ Qs = QsA + (i64)c * T::NC * T::NC;
+    const R *__restrict__ Pl = PlA + (i64)c * T::NC * T::NS;
+    const R *__restrict__ Ps = PsA + (i64)c * 7 * 18;
+    const R *__restrict__ Qs = QsA + (i64)c * T::NC * T::NC;
     if (ch < nchunk) {
         const int kk = ch * 64 + threadIdx.x;
         if (kk >= nu) return;
@@ -237,12 +247,12 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
             // matrices would not fit in registers); they are re-read from cache
             int vo = 0;
             __asm__ __volatile__("" : "+s"(vo));
-            weno_var<P>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
+            weno_var<P, R>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
         }
     } else {
         const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
         if (kk >= nu + nleft) return;
-        weno_var<P>(G, U, wc, Pl, Ps, Qs, c, G.g - 1 + kk, v);
+        weno_var<P, R>(G, U, wc, Pl, Ps, Qs, c, G.g - 1 + kk, v);
     }
 }
 
@@ -253,26 +263,26 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
 // then the mean restored.  A missing side takes the other side's value.
 
 // component c3 of one side's WENO B at the face quadrature points
-template <int P>
+template <int P, class R>
 __device__ __forceinline__ void bnodal_side(const DevGeom &G, const double *__restrict__ U,
-                                            const double *__restrict__ wc, i64 z, const double *fev, int c3,
-                                            double (&Bq)[Tr<P>::Q])
+                                            const R *__restrict__ wc, i64 z, const R *fev, int c3,
+                                            R (&Bq)[Tr<P>::Q])
 {
     using T = Tr<P>;
-    const double m0 = U[(5 + c3) * G.Z + z];
+    const R m0 = R(U[(5 + c3) * G.Z + z]);
 #pragma unroll
     for (int q = 0; q < T::Q; q++) Bq[q] = m0;
-    const double *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z;
+    const R *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z;
     for (int a = 0; a < T::NC; a++) {
-        const double ca = cf[(i64)a * G.Z];
+        const R ca = cf[(i64)a * G.Z];
 #pragma unroll
         for (int q = 0; q < T::Q; q++) Bq[q] += ca * fev[q * T::NC + a];
     }
 }
 
 // MinMod of the two sides' normal components, mean restore, store
-template <int P, class BQ>
-__device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__restrict__ Bf, double *__restrict__ bnod,
+template <int P, class R, class BQ>
+__device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__restrict__ Bf, R *__restrict__ bnod,
                                               i64 f, const bool (&have)[2], const BQ &Bq, const double *nrm,
                                               const double *fw)
 {
@@ -285,7 +295,8 @@ __device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__
 #pragma unroll
         for (int s = 0; s < 2; s++)
             if (have[s])
-                d[s] = Bq(s, 0, q) * nrm[q * 3] + Bq(s, 1, q) * nrm[q * 3 + 1] + Bq(s, 2, q) * nrm[q * 3 + 2] - mean;
+                d[s] = double(Bq(s, 0, q)) * nrm[q * 3] + double(Bq(s, 1, q)) * nrm[q * 3 + 1] +
+                       double(Bq(s, 2, q)) * nrm[q * 3 + 2] - mean;
         if (!have[0]) d[0] = d[1];
         if (!have[1]) d[1] = d[0];
         bn[q] = mean + dev_minmod(d[0], d[1]);
@@ -294,36 +305,39 @@ __device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__
 #pragma unroll
     for (int q = 0; q < T::Q; q++) sum += fw[q] * bn[q];
 #pragma unroll
-    for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = bn[q] + (mean - sum);
+    for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = R(bn[q] + (mean - sum));
 }
 
 // Geometry of a face: radial face kf of column owner, or the angular face of
 // angular edge owner in shell kf.
-template <int P, bool RADIAL>
+template <int P, bool RADIAL, class R>
 struct FaceSides {
     i64 f, z[2];
     bool have[2];
-    const double *fev[2], *nrm, *fw;
+    const R *fev[2];
+    const double *nrm, *fw;
     __device__ __forceinline__ FaceSides(const DevGeom &G, int owner, int kf)
     {
         using T = Tr<P>;
         if (RADIAL) {
+            const R *fv = pick<R>(G.fevR, G.fevRF);
             f = (i64)owner * (G.K + 1) + kf;
             z[0] = (i64)owner * G.K + kf - 1;
             z[1] = (i64)owner * G.K + kf;
             have[0] = (kf - 1 >= G.g - 1) && (kf - 1 <= G.g + G.Nr);
             have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
-            fev[0] = G.fevR + ((i64)owner * 2 + 0) * T::Q * T::NC;
-            fev[1] = G.fevR + ((i64)owner * 2 + 1) * T::Q * T::NC;
+            fev[0] = fv + ((i64)owner * 2 + 0) * T::Q * T::NC;
+            fev[1] = fv + ((i64)owner * 2 + 1) * T::Q * T::NC;
             nrm = G.fnR + (i64)owner * T::Q * 3;
             fw = G.fwR + (i64)owner * T::Q;
         } else {
+            const R *fv = pick<R>(G.fevA, G.fevAF);
             f = G.NRF + (i64)owner * G.K + kf;
             z[0] = (i64)G.ae_col[2 * owner] * G.K + kf;
             z[1] = (i64)G.ae_col[2 * owner + 1] * G.K + kf;
             have[0] = have[1] = true;
-            fev[0] = G.fevA + ((i64)owner * 2 + 0) * T::Q * T::NC;
-            fev[1] = G.fevA + ((i64)owner * 2 + 1) * T::Q * T::NC;
+            fev[0] = fv + ((i64)owner * 2 + 0) * T::Q * T::NC;
+            fev[1] = fv + ((i64)owner * 2 + 1) * T::Q * T::NC;
             nrm = G.fnA + (i64)owner * T::Q * 3;
             fw = G.fwA + (i64)owner * T::Q;
         }
@@ -334,10 +348,10 @@ struct FaceSides {
 // angular edge, so the face geometry is uniform across the wavefront.  A
 // short tail (nleft faces, at most 8) gets one more wavefront per owner whose
 // lanes take (face, side, component) triples and meet in LDS.
-template <int P, bool RADIAL>
+template <int P, bool RADIAL, class R>
 __global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *__restrict__ U,
-                                                       const double *__restrict__ Bf, const double *__restrict__ wc,
-                                                       double *__restrict__ bnod, int nchunk, int nu, int nleft)
+                                                       const double *__restrict__ Bf, const R *__restrict__ wc,
+                                                       R *__restrict__ bnod, int nchunk, int nu, int nleft)
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
@@ -346,29 +360,29 @@ __global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *
     if (ch < nchunk) {
         const int kk = ch * 64 + threadIdx.x;
         if (kk >= nu) return;
-        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + kk);
-        double Bq[2][3][T::Q];
+        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + kk);
+        R Bq[2][3][T::Q];
 #pragma unroll
         for (int sd = 0; sd < 2; sd++)
             if (fs.have[sd])
 #pragma unroll
-                for (int c3 = 0; c3 < 3; c3++) bnodal_side<P>(G, U, wc, fs.z[sd], fs.fev[sd], c3, Bq[sd][c3]);
-        bnodal_finish<P>(G, Bf, bnod, fs.f, fs.have, [&](int sd, int c3, int q) { return Bq[sd][c3][q]; }, fs.nrm,
-                         fs.fw);
+                for (int c3 = 0; c3 < 3; c3++) bnodal_side<P, R>(G, U, wc, fs.z[sd], fs.fev[sd], c3, Bq[sd][c3]);
+        bnodal_finish<P, R>(G, Bf, bnod, fs.f, fs.have, [&](int sd, int c3, int q) { return Bq[sd][c3][q]; },
+                            fs.nrm, fs.fw);
         return;
     }
-    __shared__ double s_bq[8][2][3][T::Q];
+    __shared__ R s_bq[8][2][3][T::Q];
     const int t = threadIdx.x, fi = t / 6, sd = (t % 6) / 3, c3 = t % 3;
     if (fi < nleft) {
-        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + nu + fi);
+        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + nu + fi);
         const bool hv = sd ? fs.have[1] : fs.have[0];
-        if (hv) bnodal_side<P>(G, U, wc, sd ? fs.z[1] : fs.z[0], sd ? fs.fev[1] : fs.fev[0], c3, s_bq[fi][sd][c3]);
+        if (hv) bnodal_side<P, R>(G, U, wc, sd ? fs.z[1] : fs.z[0], sd ? fs.fev[1] : fs.fev[0], c3, s_bq[fi][sd][c3]);
     }
     __syncthreads();
     if (t < nleft) {
-        const FaceSides<P, RADIAL> fs(G, owner, G.g - 1 + nu + t);
-        bnodal_finish<P>(G, Bf, bnod, fs.f, fs.have, [&](int s2, int k3, int q) { return s_bq[t][s2][k3][q]; },
-                         fs.nrm, fs.fw);
+        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + nu + t);
+        bnodal_finish<P, R>(G, Bf, bnod, fs.f, fs.have, [&](int s2, int k3, int q) { return s_bq[t][s2][k3][q]; },
+                            fs.nrm, fs.fw);
     }
 }
 
@@ -379,14 +393,13 @@ __constant__ int LE_FACE[8] = {2, 3, 2, 3, 0, 1, 0, 1};
 __constant__ int LE_UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
 __constant__ int LE_CORNER[4] = {0, 1, 3, 2};
 
-template <int P>
-__device__ __forceinline__ void mapped_flux(const double *u, double iJ, const double *met, double gam,
-                                            double out[3][8])
+template <class R>
+__device__ __forceinline__ void mapped_flux(const R *u, R iJ, const R *met, R gam, R out[3][8])
 {
-    double w[8], F[3][8];
+    R w[8], F[3][8];
 #pragma unroll
     for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
-    dev_flux(w, gam, F);
+    dev_flux<R>(w, gam, F);
 #pragma unroll
     for (int d = 0; d < 3; d++)
 #pragma unroll
@@ -405,10 +418,10 @@ __device__ __forceinline__ void mapped_flux(const double *u, double iJ, const do
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <int P>
+template <int P, class R>
 __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
-                                           const double *__restrict__ wc, const double *__restrict__ bnod,
-                                           double *__restrict__ bnode, double *__restrict__ zoneB)
+                                           const R *__restrict__ wc, const R *__restrict__ bnod,
+                                           R *__restrict__ bnode, double *__restrict__ zoneB)
 {
     using T = Tr<P>;
     constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16;
@@ -434,19 +447,17 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
     for (int s = 0; s < KT; s++) {
         // B operand: input j = 4s + g of zone jz
         const int j = 4 * s + g;
-        const double *src;
-        i64 idx;
-        if (j < NA) {
-            int comp = j / (T::NC + 1), a = j % (T::NC + 1);
-            src = a == 0 ? U + (i64)(5 + comp) * G.Z : wc + ((i64)(5 + comp) * T::NC + a - 1) * G.Z;
-            idx = z;
-        } else {
-            int lf, qc = 0;
-            if (j < NQ) { lf = (j - NA) / T::Q; qc = (j - NA) % T::Q; src = bnod + (i64)qc * G.NF; }
-            else { lf = j - NQ; src = Bf; }
-            idx = lf == 4 ? fr : lf == 5 ? fr + 1 : lf == 0 ? fa[0] : lf == 1 ? fa[1] : lf == 2 ? fa[2] : fa[3];
+        double b = 0.0;
+        if (active) {
+            if (j < NA) {
+                const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+                b = a == 0 ? U[(i64)(5 + comp) * G.Z + z] : double(wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z]);
+            } else {
+                const int lf = j < NQ ? (j - NA) / T::Q : j - NQ;
+                const i64 idx = lf == 4 ? fr : lf == 5 ? fr + 1 : lf == 0 ? fa[0] : lf == 1 ? fa[1] : lf == 2 ? fa[2] : fa[3];
+                b = j < NQ ? double(bnod[(i64)((j - NA) % T::Q) * G.NF + idx]) : Bf[idx];
+            }
         }
-        const double b = active ? src[idx] : 0.0;
         const double *mrow = Mb + (i64)j * NOUT;
 #pragma unroll
         for (int m = 0; m < MT; m++) {
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int r = m * 16 + g + 4 * v;
-            if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = acc[m][v];
+            if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = R(acc[m][v]);
             else if (r < NOUT) zoneB[(i64)(r - 3 * T::N) * G.Z + z] = acc[m][v];
         }
 }
@@ -476,8 +487,8 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
 // once into registers and each value is reused by all the outputs that need
 // it.  D_d = S_d D_0 S_d for the swap S_d, so slot i of row (d, v) ends up
 // holding the d-derivative at node S_d(i).
-template <int SN>
-__device__ __forceinline__ void put_flux(double *sf, int i, int i1, int i2, const double (&F)[3][8])
+template <int SN, class R>
+__device__ __forceinline__ void put_flux(R *sf, int i, int i1, int i2, const R (&F)[3][8])
 {
 #pragma unroll
     for (int v = 0; v < 8; v++) {
@@ -487,32 +498,32 @@ __device__ __forceinline__ void put_flux(double *sf, int i, int i1, int i2, cons
     }
 }
 
-template <int P, int SN, int ZS, int ZPW>
-__device__ __forceinline__ void deriv_rows(double *slab, int lane)
+template <int P, int SN, int ZS, int ZPW, class R>
+__device__ __forceinline__ void deriv_rows(R *slab, int lane)
 {
     using D = DTab<P>;
     constexpr int N = Tr<P>::N;
 #pragma unroll 1
     for (int t = lane; t < ZPW * 24; t += 64) {
-        double *row = slab + (t / 24) * ZS + (t % 24) * SN;
-        double x[N];
+        R *row = slab + (t / 24) * ZS + (t % 24) * SN;
+        R x[N];
 #pragma unroll
         for (int j = 0; j < N; j++) x[j] = row[j];
-        double acc = 0.0;
+        R acc = R(0);
 #pragma unroll
         for (int e = 0; e < D::NNZ; e++) {
-            acc += (0.5 * D::E[e][2]) * x[D::E[e][1]];
+            acc += R(0.5 * D::E[e][2]) * x[D::E[e][1]];
             if (e == D::NNZ - 1 || D::E[e + 1][0] != D::E[e][0]) {
                 row[D::E[e][0]] = acc;
-                acc = 0.0;
+                acc = R(0);
             }
         }
     }
 }
 
 // acc = sum over the three directions of the derivative at node i
-template <int SN>
-__device__ __forceinline__ void get_deriv(const double *sf, int i, int i1, int i2, double (&acc)[8])
+template <int SN, class R>
+__device__ __forceinline__ void get_deriv(const R *sf, int i, int i1, int i2, R (&acc)[8])
 {
 #pragma unroll
     for (int v = 0; v < 8; v++) acc[v] = sf[v * SN + i] + sf[(8 + v) * SN + i1] + sf[(16 + v) * SN + i2];
@@ -522,10 +533,10 @@ __device__ __forceinline__ void get_deriv(const double *sf, int i, int i1, int i
 // per serendipity node.  Each time level's nodal fluxes pass through LDS
 // (node fastest) and the derivative matrices are applied level by level, so a
 // lane keeps only its own node's state in registers.
-template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void predictor(DevGeom G, double dt, double gam, int npic, const double *__restrict__ U,
-                                                const double *__restrict__ wc, const double *__restrict__ bnode,
-                                                double *__restrict__ ftr, double *__restrict__ etr)
+template <int P, class R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void predictor(
+    DevGeom G, double dt, double gamma, int npic, const double *__restrict__ U, const R *__restrict__ wc,
+    const R *__restrict__ bnode, R *__restrict__ ftr, R *__restrict__ etr)
 {
     using T = Tr<P>;
     // slab rows are N + 1 long so that lanes reading one node's different
@@ -533,8 +544,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     // zone slabs are padded by four doubles so that the two zones' rows fall
     // into different LDS banks
     constexpr int N = T::N, SN = N + 1, ZS = 32 * SN + 4, ZPW = 64 / N, E = T::M - 1, NCF = T::NC + 1;
-    __shared__ double s_c[ZPW][5 * NCF];
-    __shared__ double s_f[ZPW * ZS];
+    __shared__ R s_c[ZPW][5 * NCF];
+    __shared__ R s_f[ZPW * ZS];
+    const R gam = R(gamma);
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
@@ -550,56 +562,57 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         z = (i64)c * G.K + k;
         for (int j = i; j < 5 * NCF; j += N) {
             int v = j / NCF, a = j % NCF;
-            s_c[zl][j] = a == 0 ? U[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
+            s_c[zl][j] = a == 0 ? R(U[v * G.Z + z]) : wc[((i64)v * T::NC + a - 1) * G.Z + z];
         }
     }
     const int i1 = DTab<P>::SWAP1[i], i2 = DTab<P>::SWAP2[i];
     __syncthreads();
 
-    double Ua[8], Ut[E][8], dFa[8], met[9], iJ = 1.0, fac = 0.0;
-    double *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
+    R Ua[8], Ut[E][8], dFa[8], met[9], iJ = R(1);
+    R *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
     if (active) {
-        const double *Ev = G.Ev + (i64)c * T::NC * N + i;
+        const R *Ev = pick<R>(G.Ev, G.EvF) + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
-            double acc = s_c[zl][v * NCF];
+            R acc = s_c[zl][v * NCF];
 #pragma unroll
             for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[zl][v * NCF + 1 + a];
             Ua[v] = acc;
         }
-        const double *bn = bnode + (i64)zt * (3 * N) + i;
+        const R *bn = bnode + (i64)zt * (3 * N) + i;
         Ua[5] = bn[0];
         Ua[6] = bn[N];
         Ua[7] = bn[2 * N];
-        double J = G.nJ[(i64)c * N + i];
-        iJ = 1.0 / J;
+        const R J = pick<R>(G.nJ, G.nJF)[(i64)c * N + i];
+        iJ = R(1) / J;
         // metric terms scaled by dt over the zone's size: the predictor works in
         // reference time and space
-        fac = dt / G.zscale[k];
+        const R fac = R(dt / G.zscale[k]);
+        const R *nM = pick<R>(G.nM, G.nMF);
 #pragma unroll
-        for (int m = 0; m < 9; m++) met[m] = fac * G.nM[((i64)c * 9 + m) * N + i];
+        for (int m = 0; m < 9; m++) met[m] = fac * nM[((i64)c * 9 + m) * N + i];
 #pragma unroll
         for (int v = 0; v < 8; v++) Ua[v] *= J;
         // level tau = 0: its flux derivative is the same in every iteration
-        double F[3][8];
-        mapped_flux<P>(Ua, iJ, met, gam, F);
-        put_flux<SN>(sf, i, i1, i2, F);
+        R F[3][8];
+        mapped_flux<R>(Ua, iJ, met, gam, F);
+        put_flux<SN, R>(sf, i, i1, i2, F);
     }
     __syncthreads();
-    deriv_rows<P, SN, ZS, ZPW>(s_f, lane);
+    deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
     __syncthreads();
     if (active) {
-        get_deriv<SN>(sf, i, i1, i2, dFa);
+        get_deriv<SN, R>(sf, i, i1, i2, dFa);
         // The first sweep starts from the same state at every level, so each
         // level's flux derivative equals the one at tau = 0: it needs no flux
         // evaluations and gives the same numbers as the general sweep below.
-        const double on = npic > 0 ? 1.0 : 0.0;
+        const R on = npic > 0 ? R(1) : R(0);
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
             for (int v = 0; v < 8; v++) {
-                double u = Ua[v] - on * G.R[t * T::M] * dFa[v];
+                R u = Ua[v] - on * R(G.R[t * T::M]) * dFa[v];
 #pragma unroll
-                for (int s = 0; s < E; s++) u -= on * G.R[t * T::M + s + 1] * dFa[v];
+                for (int s = 0; s < E; s++) u -= on * R(G.R[t * T::M + s + 1]) * dFa[v];
                 Ut[t][v] = u;
             }
     }
@@ -607,45 +620,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     for (int it = 1; it < npic; it++) {
         // derivative of each level's flux; a level's state is dead once its
         // flux is in LDS, so at most E + 1 vectors of eight are live here
-        double A[E][8];
+        R A[E][8];
 #pragma unroll
         for (int s = 0; s < E; s++) {
             if (active) {
-                double F[3][8];
-                mapped_flux<P>(Ut[s], iJ, met, gam, F);
-                put_flux<SN>(sf, i, i1, i2, F);
+                R F[3][8];
+                mapped_flux<R>(Ut[s], iJ, met, gam, F);
+                put_flux<SN, R>(sf, i, i1, i2, F);
             }
             __syncthreads();
-            deriv_rows<P, SN, ZS, ZPW>(s_f, lane);
+            deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
             __syncthreads();
 #pragma unroll
-            for (int v = 0; v < 8; v++) A[s][v] = 0.0;
-            if (active) get_deriv<SN>(sf, i, i1, i2, A[s]);
+            for (int v = 0; v < 8; v++) A[s][v] = R(0);
+            if (active) get_deriv<SN, R>(sf, i, i1, i2, A[s]);
             __syncthreads();
         }
 #pragma unroll
         for (int t = 0; t < E; t++) {
-            double r0 = G.R[t * T::M];
+            const R r0 = R(G.R[t * T::M]);
 #pragma unroll
             for (int v = 0; v < 8; v++) {
-                double u = Ua[v] - r0 * dFa[v];
+                R u = Ua[v] - r0 * dFa[v];
 #pragma unroll
-                for (int s = 0; s < E; s++) u -= G.R[t * T::M + s + 1] * A[s][v];
+                for (int s = 0; s < E; s++) u -= R(G.R[t * T::M + s + 1]) * A[s][v];
                 Ut[t][v] = u;
             }
         }
     }
     // time averages of state and physical flux over the Gauss levels
     if (active) {
-        double aU[8], aF[3][8], w[8], F[3][8];
+        R aU[8], aF[3][8], w[8], F[3][8];
 #pragma unroll
-        for (int v = 0; v < 8; v++) { aU[v] = 0.0; aF[0][v] = aF[1][v] = aF[2][v] = 0.0; }
+        for (int v = 0; v < 8; v++) { aU[v] = R(0); aF[0][v] = aF[1][v] = aF[2][v] = R(0); }
 #pragma unroll
         for (int t = 0; t < E; t++) {
-            double wt = G.wt[t + 1];
+            const R wt = R(G.wt[t + 1]);
 #pragma unroll
             for (int v = 0; v < 8; v++) w[v] = Ut[t][v] * iJ;
-            dev_flux(w, gam, F);
+            dev_flux<R>(w, gam, F);
 #pragma unroll
             for (int v = 0; v < 8; v++) {
                 aU[v] += wt * w[v];
@@ -673,8 +686,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         const unsigned ztq = lb * ZPW + zq;
         if (ztq >= (unsigned)nzr) continue;
         const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
-        const double *sx = s_f + zq * ZS;
-        double x[T::NFN][4];
+        const R *sx = s_f + zq * ZS;
+        R x[T::NFN][4];
 #pragma unroll
         for (int kk = 0; kk < T::NFN; kk++) {
             const int l = G.fnode[lf * T::NFN + kk];
@@ -696,20 +709,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             nrm = G.fnA + (i64)ae * T::Q * 3;
             perm = G.col_perm + ((i64)cq * 4 + lf) * T::Q;
         }
-        double *o = ftr + (fid * 2 + side) * T::Q * 16;
+        R *o = ftr + (fid * 2 + side) * T::Q * 16;
         // one row of quadrature points at a time: its weights are uniform
         // across the wavefront and stay in scalar registers
 #pragma unroll 1
         for (int b = 0; b < T::Q1; b++) {
-            double aq[T::Q1][4];
+            R aq[T::Q1][4];
 #pragma unroll
-            for (int a = 0; a < T::Q1; a++) aq[a][0] = aq[a][1] = aq[a][2] = aq[a][3] = 0.0;
-            const double *wrow = G.fintc + b * T::Q1;
+            for (int a = 0; a < T::Q1; a++) aq[a][0] = aq[a][1] = aq[a][2] = aq[a][3] = R(0);
+            const R *wrow = pick<R>(G.fintc, G.fintcF) + b * T::Q1;
 #pragma unroll
             for (int kk = 0; kk < T::NFN; kk++)
 #pragma unroll
                 for (int a = 0; a < T::Q1; a++) {
-                    const double w = wrow[kk * T::Q + a];
+                    const R w = wrow[kk * T::Q + a];
 #pragma unroll
                     for (int j = 0; j < 4; j++) aq[a][j] += w * x[kk][j];
                 }
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                 const int qc = perm ? perm[q] : q;
                 const double *n = nrm + qc * 3;
                 o[qc * 16 + v] = aq[a][0];
-                o[qc * 16 + 8 + v] = n[0] * aq[a][1] + n[1] * aq[a][2] + n[2] * aq[a][3];
+                o[qc * 16 + 8 + v] = R(n[0]) * aq[a][1] + R(n[1]) * aq[a][2] + R(n[2]) * aq[a][3];
             }
         }
     }
@@ -730,16 +743,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         const unsigned ztq = lb * ZPW + zq;
         if (ztq < (unsigned)nzr) {
             const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
-            const double *sx = s_f + zq * ZS;
-            double ae3[3][11];
+            const R *sx = s_f + zq * ZS;
+            const R *ew = pick<R>(G.eintc, G.eintcF);
+            R ae3[3][11];
 #pragma unroll
             for (int p = 0; p < 3; p++)
 #pragma unroll
-                for (int v = 0; v < 11; v++) ae3[p][v] = 0.0;
+                for (int v = 0; v < 11; v++) ae3[p][v] = R(0);
 #pragma unroll
             for (int kk = 0; kk < T::NEN; kk++) {
                 const int l = G.enode[le * T::NEN + kk];
-                double x[11];
+                R x[11];
 #pragma unroll
                 for (int v = 0; v < 8; v++) x[v] = sx[v * SN + l];
                 x[8] = sx[(24 + 6) * SN + l];    // E_x = H[B_y]
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                 x[10] = sx[(16 + 5) * SN + l];   // E_z = G[B_x]
 #pragma unroll
                 for (int p = 0; p < 3; p++) {
-                    const double w = G.eintc[kk * 3 + p];
+                    const R w = ew[kk * 3 + p];
 #pragma unroll
                     for (int v = 0; v < 11; v++) ae3[p][v] += w * x[v];
                 }
@@ -760,7 +774,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             } else {
                 e = (i64)G.col_v[4 * cq + LE_CORNER[le - 8]] * G.K + kq;
             }
-            double *o = etr + (e * 4 + slot) * 3 * 11;
+            R *o = etr + (e * 4 + slot) * 3 * 11;
 #pragma unroll
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
@@ -773,8 +787,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 
 // ---------------------------------------------------------------- face fluxes
 // radial faces kf in [g, g+Nr], angular faces in shells [g, g+Nr-1]
-template <int P>
-__global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const double *__restrict__ ftr,
+template <int P, class R>
+__global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
                                                  double *__restrict__ Phi)
 {
     using T = Tr<P>;
@@ -803,7 +817,7 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const do
         double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            const double *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
+            const R *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
             UL[v] = a[v];
             FL[v] = a[8 + v];
             UR[v] = b[v];
@@ -865,7 +879,8 @@ __device__ __forceinline__ double emf3(const double U[4][8], const double E[4][3
 }
 
 // radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr]
-__global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const double *__restrict__ etr, double *__restrict__ Gam)
+template <class R>
+__global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam)
 {
     const int nrad = G.Nr, nang = G.Nr + 1;
     i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -899,7 +914,7 @@ __global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const dou
         // all four slots are read (a three-zone edge leaves slot 3 unused)
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            const double *rec = etr + ((e * 4 + s) * 3 + p) * 11;
+            const R *rec = etr + ((e * 4 + s) * 3 + p) * 11;
 #pragma unroll
             for (int v = 0; v < 8; v++) U[s][v] = rec[v];
 #pragma unroll
@@ -1003,6 +1018,74 @@ __global__ __launch_bounds__(256) void cfl_final(int n, double *red)
     if (threadIdx.x == 0) red[65535] = sm[0];
 }
 
+// ---------------------------------------------------------------- diagnostics
+// Per interior zone: relative div B |sum sigma A <B.n>| / sum A |<B.n>|, the
+// volume-weighted conserved sums and the smallest density and pressure.
+// A fixed grid strides over the zones; partial results per block, then one
+// block reduces them in a fixed order (deterministic).
+constexpr int DIAG_BLOCKS = 1024, DIAG_NV = 11;   // div max, 8 sums, rho min, p min
+
+__device__ __forceinline__ void diag_combine(double *a, const double *b)
+{
+    a[0] = fmax(a[0], b[0]);
+    for (int v = 1; v < 9; v++) a[v] += b[v];
+    a[9] = fmin(a[9], b[9]);
+    a[10] = fmin(a[10], b[10]);
+}
+
+__global__ __launch_bounds__(256) void diag_partial(DevGeom G, double gam, const double *__restrict__ U,
+                                                    const double *__restrict__ Bf, double *red)
+{
+    __shared__ double sm[256][DIAG_NV];
+    double acc[DIAG_NV] = {0.0, 0, 0, 0, 0, 0, 0, 0, 0, 1e300, 1e300};
+    const i64 n = (i64)G.ncol * G.Nr;
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
+        const i64 z = (i64)c * G.K + k;
+        double num = 0.0, den = 0.0;
+        const i64 fr = (i64)c * (G.K + 1) + k;
+        num += G.area[fr + 1] * Bf[fr + 1] - G.area[fr] * Bf[fr];
+        den += G.area[fr + 1] * fabs(Bf[fr + 1]) + G.area[fr] * fabs(Bf[fr]);
+        for (int lf = 0; lf < 4; lf++) {
+            const i64 f = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+            const double sg = G.col_side[4 * c + lf] == 0 ? 1.0 : -1.0;
+            num += sg * G.area[f] * Bf[f];
+            den += G.area[f] * fabs(Bf[f]);
+        }
+        acc[0] = fmax(acc[0], den > 0.0 ? fabs(num) / den : 0.0);
+        double u[8];
+        for (int v = 0; v < 8; v++) {
+            u[v] = U[v * G.Z + z];
+            acc[1 + v] += G.vol[z] * u[v];
+        }
+        acc[9] = fmin(acc[9], u[0]);
+        acc[10] = fmin(acc[10], dev_pressure(u, gam));
+    }
+    for (int v = 0; v < DIAG_NV; v++) sm[threadIdx.x][v] = acc[v];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) diag_combine(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int v = 0; v < DIAG_NV; v++) red[(i64)blockIdx.x * DIAG_NV + v] = sm[0][v];
+}
+
+__global__ __launch_bounds__(256) void diag_final(double *red)
+{
+    __shared__ double sm[256][DIAG_NV];
+    double acc[DIAG_NV] = {0.0, 0, 0, 0, 0, 0, 0, 0, 0, 1e300, 1e300};
+    for (int b = threadIdx.x; b < DIAG_BLOCKS; b += 256) diag_combine(acc, red + (i64)b * DIAG_NV);
+    for (int v = 0; v < DIAG_NV; v++) sm[threadIdx.x][v] = acc[v];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) diag_combine(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int v = 0; v < DIAG_NV; v++) red[DIAG_BLOCKS * DIAG_NV + v] = sm[0][v];
+}
+
 // ---------------------------------------------------------------- host launch
 static inline unsigned nblocks(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -1014,6 +1097,13 @@ static inline unsigned nblocks(i64 n, int bs) { return (unsigned)((n + bs - 1) /
             return RG_EDEVICE;                                       \
         }                                                            \
     } while (0)
+
+template <class R>
+static const R *pick_host(const double *d, const float *f)
+{
+    if constexpr (sizeof(R) == sizeof(double)) return d;
+    else return f;
+}
 
 // Runs of up to 64 items along a column: n = nu + nleft, the first nu items
 // in nchunk wavefront-sized runs; a short tail (1 to 8 items beyond a
@@ -1039,11 +1129,15 @@ struct StageMarks {
     }
 };
 
-template <int P>
+template <int P, class R>
 static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf, double *Uo,
                             double *Bo, hipStream_t st)
 {
     const DevGeom &G = g->d;
+    // work buffers hold R values (they are sized for doubles)
+    R *wcoef = reinterpret_cast<R *>(g->wcoef), *bnod = reinterpret_cast<R *>(g->bnod);
+    R *bnode = reinterpret_cast<R *>(g->bnode), *ftr = reinterpret_cast<R *>(g->ftr);
+    R *etr = reinterpret_cast<R *>(g->etr);
     const int npic = prm.n_picard > 0 ? prm.n_picard : P;
     const double dt = prm.dt, gam = prm.gamma;
     StageMarks sm;
@@ -1061,32 +1155,32 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     sm.mark(1, st);
     const i64 nzr = (i64)G.ncol * (G.Nr + 2);
     const RunSplit wr = run_split(G.Nr + 2);
-    weno_cols<P><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(G, Uo, g->wcoef, G.Pl, G.Ps,
-                                                                                       G.Qs, wr.nchunk, wr.nu, wr.nleft);
+    weno_cols<P, R><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
+        G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF), wr.nchunk,
+        wr.nu, wr.nleft);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
     const RunSplit br = run_split(G.Nr + 3), ba = run_split(G.Nr + 2);
-    face_bnodal_runs<P, true><<<(unsigned)((i64)G.ncol * (br.nchunk + (br.nleft > 0))), 64, 0, st>>>(
-        G, Uo, Bo, g->wcoef, g->bnod, br.nchunk, br.nu, br.nleft);
-    face_bnodal_runs<P, false><<<(unsigned)((i64)G.nae * (ba.nchunk + (ba.nleft > 0))), 64, 0, st>>>(
-        G, Uo, Bo, g->wcoef, g->bnod, ba.nchunk, ba.nu, ba.nleft);
+    face_bnodal_runs<P, true, R><<<(unsigned)((i64)G.ncol * (br.nchunk + (br.nleft > 0))), 64, 0, st>>>(
+        G, Uo, Bo, wcoef, bnod, br.nchunk, br.nu, br.nleft);
+    face_bnodal_runs<P, false, R><<<(unsigned)((i64)G.nae * (ba.nchunk + (ba.nleft > 0))), 64, 0, st>>>(
+        G, Uo, Bo, wcoef, bnod, ba.nchunk, ba.nu, ba.nleft);
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
     const int ntile = (G.Nr + 2 + 15) / 16;
-    bmap<P><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, g->wcoef, g->bnod, g->bnode, g->zoneB);
+    bmap<P, R><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, wcoef, bnod, bnode, g->zoneB);
     RG_LAUNCH_CHECK();
     sm.mark(4, st);
-    predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, g->wcoef, g->bnode, g->ftr,
-                                                                    g->etr);
+    predictor<P, R><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, wcoef, bnode, ftr, etr);
     RG_LAUNCH_CHECK();
     sm.mark(5, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
-    face_flux<P><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, g->ftr, g->Phi);
+    face_flux<P, R><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, ftr, g->Phi);
     RG_LAUNCH_CHECK();
     sm.mark(6, st);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
-    edge_emf<<<nblocks(nee, 256), 256, 0, st>>>(G, gam, g->etr, g->Gam);
+    edge_emf<R><<<nblocks(nee, 256), 256, 0, st>>>(G, gam, etr, g->Gam);
     RG_LAUNCH_CHECK();
     sm.mark(7, st);
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
@@ -1122,8 +1216,9 @@ rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, cons
                       void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (g->d.order == 3) return step_order<3>(g, p, U, Bf, Uo, Bo, st);
-    if (g->d.order == 4) return step_order<4>(g, p, U, Bf, Uo, Bo, st);
+    const bool f32 = g->mode == RG_MODE_FP32;
+    if (g->d.order == 3) return f32 ? step_order<3, float>(g, p, U, Bf, Uo, Bo, st) : step_order<3, double>(g, p, U, Bf, Uo, Bo, st);
+    if (g->d.order == 4) return f32 ? step_order<4, float>(g, p, U, Bf, Uo, Bo, st) : step_order<4, double>(g, p, U, Bf, Uo, Bo, st);
     set_error("unsupported order");
     return RG_ENOTSUP;
 }
@@ -1149,4 +1244,26 @@ rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void
     return RG_OK;
 }
 
+}  // namespace rg
+
+namespace rg {
+rg_status launch_diag(rg_geom *g, const double *U, const double *Bf, double gamma, void *stream, rg_diag_out *out)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    static_assert((DIAG_BLOCKS + 1) * DIAG_NV <= 65536, "diagnostics fit the reduction buffer");
+    diag_partial<<<DIAG_BLOCKS, 256, 0, st>>>(g->d, gamma, U, Bf, g->red);
+    diag_final<<<1, 256, 0, st>>>(g->red);
+    RG_LAUNCH_CHECK();
+    double h[DIAG_NV];
+    if (hipMemcpyAsync(h, g->red + DIAG_BLOCKS * DIAG_NV, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("diagnostics copy failed");
+        return RG_EDEVICE;
+    }
+    out->div_rel_max = h[0];
+    for (int v = 0; v < 8; v++) out->sums[v] = h[1 + v];
+    out->rho_min = h[9];
+    out->p_min = h[10];
+    return RG_OK;
+}
 }  // namespace rg
