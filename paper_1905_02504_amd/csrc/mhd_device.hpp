@@ -1,0 +1,289 @@
+// Device building blocks shared by the step (step.hip) and its adjoint
+// (adjoint.hip): element traits, ideal-MHD point functions, the Riemann
+// solvers and the WENO-AO combination.  The point functions are templates on
+// the scalar type T: double (or float) for the step, and `dual` (a value with
+// one tangent) for the adjoint, which takes exact local derivatives by
+// forward differentiation of the same code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dtab.hpp"
+#include "rg_geom_host.hpp"
+
+namespace rg {
+
+template <int P>
+struct Tr;
+template <>
+struct Tr<3> {
+    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3;
+};
+template <>
+struct Tr<4> {
+    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4;
+};
+
+typedef long long i64;
+
+constexpr double WENO_GAMMA_HI = 0.85;
+constexpr double WENO_EPS = 1e-12;
+
+// local edges 0..7 are angular: local face holding them and whether they lie
+// on the upper (zeta+) interface; 8..11 radial at corners v0, v1, v3, v2
+struct LocalEdges {
+    static constexpr int FACE[8] = {2, 3, 2, 3, 0, 1, 0, 1};
+    static constexpr int UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
+    static constexpr int CORNER[4] = {0, 1, 3, 2};
+};
+
+// ---------------------------------------------------------------- dual numbers
+struct dual {
+    double v, d;
+    __device__ __forceinline__ dual() : v(0.0), d(0.0) {}
+    __device__ __forceinline__ dual(double x) : v(x), d(0.0) {}
+    __device__ __forceinline__ dual(double x, double t) : v(x), d(t) {}
+};
+__device__ __forceinline__ dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ dual operator-(dual a) { return dual(-a.v, -a.d); }
+__device__ __forceinline__ dual operator*(dual a, dual b) { return dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ dual operator/(dual a, dual b)
+{
+    const double q = a.v / b.v;
+    return dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ dual &operator+=(dual &a, dual b) { return a = a + b; }
+__device__ __forceinline__ dual &operator-=(dual &a, dual b) { return a = a - b; }
+__device__ __forceinline__ dual &operator*=(dual &a, dual b) { return a = a * b; }
+__device__ __forceinline__ bool operator<(dual a, dual b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>(dual a, dual b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<=(dual a, dual b) { return a.v <= b.v; }
+__device__ __forceinline__ bool operator>=(dual a, dual b) { return a.v >= b.v; }
+
+// scalar functions with one spelling for every T (the derivative of max/min
+// follows the selected argument, as the step's branch does)
+__device__ __forceinline__ double ssqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float ssqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ dual ssqrt(dual x)
+{
+    const double r = sqrt(x.v);
+    return dual(r, x.v > 0.0 ? 0.5 * x.d / r : 0.0);
+}
+__device__ __forceinline__ double smax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double smin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float smax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ dual smax(dual a, dual b) { return a.v >= b.v ? a : b; }
+__device__ __forceinline__ dual smin(dual a, dual b) { return a.v <= b.v ? a : b; }
+__device__ __forceinline__ double value(double x) { return x; }
+__device__ __forceinline__ double value(dual x) { return x.v; }
+
+// ---------------------------------------------------------------- ideal MHD
+template <class T>
+__device__ __forceinline__ T dev_pressure(const T *u, T gam)
+{
+    T m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    T b2 = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+    return (gam - T(1.0)) * (u[4] - T(0.5) * m2 / u[0] - T(0.5) * b2);
+}
+
+// F[d][v]: flux of conserved variable v along Cartesian direction d (eq. 2.2)
+template <class T>
+__device__ __forceinline__ void dev_flux(const T *u, T gam, T F[3][8])
+{
+    T ir = T(1) / u[0];
+    T v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
+    T B0 = u[5], B1 = u[6], B2 = u[7];
+    T hb2 = T(0.5) * (B0 * B0 + B1 * B1 + B2 * B2);
+    T p = (gam - T(1)) * (u[4] - T(0.5) * (u[1] * v0 + u[2] * v1 + u[3] * v2) - hb2);
+    T pt = p + hb2;
+    T vB = v0 * B0 + v1 * B1 + v2 * B2;
+    T v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        F[d][0] = u[1 + d];
+#pragma unroll
+        for (int i = 0; i < 3; i++) F[d][1 + i] = u[1 + d] * v[i] + (d == i ? pt : T(0)) - B[d] * B[i];
+        F[d][4] = (u[4] + pt) * v[d] - B[d] * vB;
+#pragma unroll
+        for (int i = 0; i < 3; i++) F[d][5 + i] = v[d] * B[i] - B[d] * v[i];
+    }
+}
+
+// flux contracted with the scaled metric terms at a node (eq. 5.23)
+template <class T>
+__device__ __forceinline__ void mapped_flux(const T *u, T iJ, const T *met, T gam, T out[3][8])
+{
+    T w[8], F[3][8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
+    dev_flux<T>(w, gam, F);
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int v = 0; v < 8; v++)
+            out[d][v] = met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v];
+}
+
+// fast magnetosonic speed along unit n
+template <class T>
+__device__ __forceinline__ T dev_fast(const T *u, T gam, const double *n)
+{
+    T ir = T(1.0) / u[0];
+    T a2 = gam * dev_pressure<T>(u, gam) * ir;
+    T b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+    T bn = u[5] * n[0] + u[6] * n[1] + u[7] * n[2];
+    T bn2 = bn * bn * ir, s = a2 + b2;
+    T disc = s * s - T(4.0) * a2 * bn2;
+    disc = disc < T(0.0) ? T(0.0) : disc;
+    return ssqrt(T(0.5) * (s + ssqrt(disc)));
+}
+
+// HLL with Davis speeds along unit n (from L to R)
+template <class T>
+__device__ __forceinline__ void dev_hll(const T *UL, const T *UR, const T *FL, const T *FR, const double *n, T gam,
+                                        T *Fs)
+{
+    T vL = (UL[1] * n[0] + UL[2] * n[1] + UL[3] * n[2]) / UL[0];
+    T vR = (UR[1] * n[0] + UR[2] * n[1] + UR[3] * n[2]) / UR[0];
+    T cL = dev_fast<T>(UL, gam, n), cR = dev_fast<T>(UR, gam, n);
+    T SL = smin(vL - cL, vR - cR), SR = smax(vL + cL, vR + cR);
+    if (SL >= T(0.0)) {
+        for (int v = 0; v < 8; v++) Fs[v] = FL[v];
+    } else if (SR <= T(0.0)) {
+        for (int v = 0; v < 8; v++) Fs[v] = FR[v];
+    } else {
+        T id = T(1.0) / (SR - SL);
+        for (int v = 0; v < 8; v++) Fs[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
+    }
+}
+
+__device__ __forceinline__ double dev_minmod(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return a > 0.0 ? fmin(a, b) : fmax(a, b);
+}
+
+// four-state multidimensional HLL electric field along t in the frame F = (e1, e2, t)
+template <class T>
+__device__ __forceinline__ T emf4(const T U[4][8], const T Et[4], const double *F, T gam)
+{
+    const double *e1 = F, *e2 = F + 3;
+    T ap1 = T(0.0), am1 = T(0.0), ap2 = T(0.0), am2 = T(0.0), B1[4], B2[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        T ir = T(1.0) / U[s][0];
+        T v1 = (U[s][1] * e1[0] + U[s][2] * e1[1] + U[s][3] * e1[2]) * ir;
+        T v2 = (U[s][1] * e2[0] + U[s][2] * e2[1] + U[s][3] * e2[2]) * ir;
+        T c1 = dev_fast<T>(U[s], gam, e1), c2 = dev_fast<T>(U[s], gam, e2);
+        ap1 = smax(ap1, v1 + c1);
+        am1 = smax(am1, c1 - v1);
+        ap2 = smax(ap2, v2 + c2);
+        am2 = smax(am2, c2 - v2);
+        B1[s] = U[s][5] * e1[0] + U[s][6] * e1[1] + U[s][7] * e1[2];
+        B2[s] = U[s][5] * e2[0] + U[s][6] * e2[1] + U[s][7] * e2[2];
+    }
+    // slots counter-clockwise: 0 SW, 1 SE, 2 NE, 3 NW
+    T Es = (ap1 * ap2 * Et[0] + ap1 * am2 * Et[3] + am1 * ap2 * Et[1] + am1 * am2 * Et[2]) / ((ap1 + am1) * (ap2 + am2));
+    Es += ap1 * am1 * (T(0.5) * (B2[1] + B2[2]) - T(0.5) * (B2[0] + B2[3])) / (ap1 + am1);
+    Es -= ap2 * am2 * (T(0.5) * (B1[2] + B1[3]) - T(0.5) * (B1[0] + B1[1])) / (ap2 + am2);
+    return Es;
+}
+
+// three zones about an edge: mean of the 1-D HLL induction fluxes of the three faces
+template <class T>
+__device__ __forceinline__ T emf3(const T U[4][8], const T E[4][3], const double *N3, const double *t, T gam)
+{
+    T acc = T(0.0);
+    for (int s = 0; s < 3; s++) {
+        int s2 = (s + 1) % 3;
+        const double *n = N3 + 3 * s;
+        T FL[8], FR[8], Fs[8];
+        for (int v = 0; v < 8; v++) FL[v] = FR[v] = T(0.0);
+        FL[5] = n[1] * E[s][2] - n[2] * E[s][1];
+        FL[6] = n[2] * E[s][0] - n[0] * E[s][2];
+        FL[7] = n[0] * E[s][1] - n[1] * E[s][0];
+        FR[5] = n[1] * E[s2][2] - n[2] * E[s2][1];
+        FR[6] = n[2] * E[s2][0] - n[0] * E[s2][2];
+        FR[7] = n[0] * E[s2][1] - n[1] * E[s2][0];
+        dev_hll<T>(U[s], U[s2], FL, FR, n, gam, Fs);
+        double tn[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
+        acc -= Fs[5] * tn[0] + Fs[6] * tn[1] + Fs[7] * tn[2];
+    }
+    return acc / T(3.0);
+}
+
+// WENO-AO combination (Section III) of one variable from its stencil
+// differences du: large-stencil and small-stencil least squares, smoothness
+// indicators, nonlinear weights and the adaptive-order blend.  Matrices of
+// precision R, arithmetic in T.
+template <int P, class T, class R>
+__device__ __forceinline__ void weno_core(const T (&du)[Tr<P>::NS], const R *__restrict__ Pl,
+                                          const R *__restrict__ Ps, const R *__restrict__ Qs, T (&out)[Tr<P>::NC])
+{
+    using Tt = Tr<P>;
+    const T ghi = T(WENO_GAMMA_HI), gs = T((1.0 - WENO_GAMMA_HI) / 7.0), eps = T(WENO_EPS);
+    T chi[Tt::NC];
+#pragma unroll
+    for (int a = 0; a < Tt::NC; a++) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < Tt::NS; j++) s += T(Pl[a * Tt::NS + j]) * du[j];
+        chi[a] = s;
+    }
+    T cs[7][3];
+#pragma unroll
+    for (int s = 0; s < 7; s++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; j++) acc += T(Ps[s * 18 + i * 6 + j]) * du[j];
+            cs[s][i] = acc;
+        }
+    T bhi = T(0);
+#pragma unroll
+    for (int a = 0; a < Tt::NC; a++) {
+        T s = T(0);
+#pragma unroll
+        for (int b = 0; b < Tt::NC; b++) s += T(Qs[a * Tt::NC + b]) * chi[b];
+        bhi += chi[a] * s;
+    }
+    T w0 = ghi / ((bhi + eps) * (bhi + eps)), tot = w0, ws[7];
+#pragma unroll
+    for (int s = 0; s < 7; s++) {
+        T b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+        ws[s] = gs / ((b + eps) * (b + eps));
+        tot += ws[s];
+    }
+    T itot = T(1) / tot;
+    w0 *= itot;
+#pragma unroll
+    for (int a = 0; a < Tt::NC; a++) {
+        T lin = T(0), nl = T(0);
+        if (a < 3)
+#pragma unroll
+            for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
+        out[a] = w0 / ghi * (chi[a] - lin) + nl;
+    }
+}
+
+// geometry table of precision R: the FP64 table or its FP32 copy
+template <class R>
+__device__ __forceinline__ const R *pick(const double *d, const float *f)
+{
+    if constexpr (sizeof(R) == sizeof(double)) return d;
+    else return f;
+}
+
+// Workgroups are dispatched round-robin over the eight XCDs, each with its
+// own L2.  Renumbering so that XCD x runs one contiguous range of logical
+// blocks keeps the blocks of a column (which share its geometry tables) in
+// one L2.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+}  // namespace rg

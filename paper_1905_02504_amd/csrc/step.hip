@@ -13,114 +13,9 @@
 //   edge_emf           : multidimensional HLL electric field at edge Simpson points
 //   zone_update        : finite-volume update of the eight zone averages
 //   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
-#include <hip/hip_runtime.h>
-
-#include "dtab.hpp"
-#include "rg_geom_host.hpp"
+#include "mhd_device.hpp"
 
 namespace rg {
-
-template <int P>
-struct Tr;
-template <>
-struct Tr<3> {
-    static constexpr int N = 20, M = 3, NC = 9, NB = 16, Q1 = 2, Q = 4, NS = 26, NIN = 60, NOUTB = 63, NFN = 8, NEN = 3;
-};
-template <>
-struct Tr<4> {
-    static constexpr int N = 32, M = 4, NC = 19, NB = 30, Q1 = 3, Q = 9, NS = 32, NIN = 120, NOUTB = 99, NFN = 12, NEN = 4;
-};
-
-typedef long long i64;
-
-constexpr double WENO_GAMMA_HI = 0.85;
-constexpr double WENO_EPS = 1e-12;
-
-// ---------------------------------------------------------------- ideal MHD
-__device__ __forceinline__ double dev_pressure(const double *u, double gam)
-{
-    double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-    double b2 = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
-    return (gam - 1.0) * (u[4] - 0.5 * m2 / u[0] - 0.5 * b2);
-}
-
-// F[d][v]: flux of conserved variable v along Cartesian direction d (eq. 2.2),
-// in the arithmetic type R of the caller
-template <class R>
-__device__ __forceinline__ void dev_flux(const R *u, R gam, R F[3][8])
-{
-    R ir = R(1) / u[0];
-    R v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
-    R B0 = u[5], B1 = u[6], B2 = u[7];
-    R hb2 = R(0.5) * (B0 * B0 + B1 * B1 + B2 * B2);
-    R p = (gam - R(1)) * (u[4] - R(0.5) * (u[1] * v0 + u[2] * v1 + u[3] * v2) - hb2);
-    R pt = p + hb2;
-    R vB = v0 * B0 + v1 * B1 + v2 * B2;
-    R v[3] = {v0, v1, v2}, B[3] = {B0, B1, B2};
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        F[d][0] = u[1 + d];
-#pragma unroll
-        for (int i = 0; i < 3; i++) F[d][1 + i] = u[1 + d] * v[i] + (d == i ? pt : R(0)) - B[d] * B[i];
-        F[d][4] = (u[4] + pt) * v[d] - B[d] * vB;
-#pragma unroll
-        for (int i = 0; i < 3; i++) F[d][5 + i] = v[d] * B[i] - B[d] * v[i];
-    }
-}
-
-// geometry table of precision R: the FP64 table or its FP32 copy
-template <class R>
-__device__ __forceinline__ const R *pick(const double *d, const float *f)
-{
-    if constexpr (sizeof(R) == sizeof(double)) return d;
-    else return f;
-}
-
-__device__ __forceinline__ double dev_fast(const double *u, double gam, const double *n)
-{
-    double ir = 1.0 / u[0];
-    double a2 = gam * dev_pressure(u, gam) * ir;
-    double b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
-    double bn = u[5] * n[0] + u[6] * n[1] + u[7] * n[2];
-    double bn2 = bn * bn * ir, s = a2 + b2;
-    double disc = s * s - 4.0 * a2 * bn2;
-    disc = disc < 0.0 ? 0.0 : disc;
-    return sqrt(0.5 * (s + sqrt(disc)));
-}
-
-// HLL with Davis speeds along unit n (from L to R)
-__device__ __forceinline__ void dev_hll(const double *UL, const double *UR, const double *FL, const double *FR,
-                                        const double *n, double gam, double *Fs)
-{
-    double vL = (UL[1] * n[0] + UL[2] * n[1] + UL[3] * n[2]) / UL[0];
-    double vR = (UR[1] * n[0] + UR[2] * n[1] + UR[3] * n[2]) / UR[0];
-    double cL = dev_fast(UL, gam, n), cR = dev_fast(UR, gam, n);
-    double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
-    if (SL >= 0.0) {
-        for (int v = 0; v < 8; v++) Fs[v] = FL[v];
-    } else if (SR <= 0.0) {
-        for (int v = 0; v < 8; v++) Fs[v] = FR[v];
-    } else {
-        double id = 1.0 / (SR - SL);
-        for (int v = 0; v < 8; v++) Fs[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
-    }
-}
-
-__device__ __forceinline__ double dev_minmod(double a, double b)
-{
-    if (!(a * b > 0.0)) return 0.0;
-    return a > 0.0 ? fmin(a, b) : fmax(a, b);
-}
-
-// Workgroups are dispatched round-robin over the eight XCDs, each with its
-// own L2.  Renumbering so that XCD x runs one contiguous range of logical
-// blocks keeps the blocks of a column (which share its geometry tables) in
-// one L2.  A bijection of [0, nb) for any nb.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
-{
-    const unsigned q = nb / 8, r = nb % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
 
 // ---------------------------------------------------------------- boundary fill
 __global__ void bc_zones(DevGeom G, int bc, const double *U, double *Uo)
@@ -167,7 +62,6 @@ __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restr
 {
     using T = Tr<P>;
     const i64 z = (i64)c * G.K + k;
-    const R ghi = R(WENO_GAMMA_HI), gs = R((1.0 - WENO_GAMMA_HI) / 7.0), eps = R(WENO_EPS);
     const double *Uv = U + (i64)v * G.Z;
     const double u0 = Uv[z];
     R du[T::NS];
@@ -177,50 +71,11 @@ __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restr
         const int dz = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
         du[j] = R(Uv[z + dz] - u0);
     }
-    R chi[T::NC];
-#pragma unroll
-    for (int a = 0; a < T::NC; a++) {
-        R s = R(0);
-#pragma unroll
-        for (int j = 0; j < T::NS; j++) s += Pl[a * T::NS + j] * du[j];
-        chi[a] = s;
-    }
-    R cs[7][3];
-#pragma unroll
-    for (int s = 0; s < 7; s++)
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            R acc = R(0);
-#pragma unroll
-            for (int j = 0; j < 6; j++) acc += Ps[s * 18 + i * 6 + j] * du[j];
-            cs[s][i] = acc;
-        }
-    R bhi = R(0);
-#pragma unroll
-    for (int a = 0; a < T::NC; a++) {
-        R s = R(0);
-#pragma unroll
-        for (int b = 0; b < T::NC; b++) s += Qs[a * T::NC + b] * chi[b];
-        bhi += chi[a] * s;
-    }
-    R w0 = ghi / ((bhi + eps) * (bhi + eps)), tot = w0, ws[7];
-#pragma unroll
-    for (int s = 0; s < 7; s++) {
-        R b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
-        ws[s] = gs / ((b + eps) * (b + eps));
-        tot += ws[s];
-    }
-    R itot = R(1) / tot;
-    w0 *= itot;
+    R o[T::NC];
+    weno_core<P, R, R>(du, Pl, Ps, Qs, o);
     R *out = wc + (i64)v * T::NC * G.Z + z;
 #pragma unroll
-    for (int a = 0; a < T::NC; a++) {
-        R lin = R(0), nl = R(0);
-        if (a < 3)
-#pragma unroll
-            for (int s = 0; s < 7; s++) { lin += gs * cs[s][a]; nl += ws[s] * itot * cs[s][a]; }
-        out[(i64)a * G.Z] = w0 / ghi * (chi[a] - lin) + nl;
-    }
+    for (int a = 0; a < T::NC; a++) out[(i64)a * G.Z] = o[a];
 }
 
 // One wavefront per run of up to 64 shells of one column, the eight
@@ -387,26 +242,6 @@ __global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *
 }
 
 // ---------------------------------------------------------------- predictor
-// local edges 0..7 are angular: local face holding them and whether they lie
-// on the upper (zeta+) interface; 8..11 radial at corners v0, v1, v3, v2
-__constant__ int LE_FACE[8] = {2, 3, 2, 3, 0, 1, 0, 1};
-__constant__ int LE_UP[8] = {0, 0, 1, 1, 0, 0, 1, 1};
-__constant__ int LE_CORNER[4] = {0, 1, 3, 2};
-
-template <class R>
-__device__ __forceinline__ void mapped_flux(const R *u, R iJ, const R *met, R gam, R out[3][8])
-{
-    R w[8], F[3][8];
-#pragma unroll
-    for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
-    dev_flux<R>(w, gam, F);
-#pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-        for (int v = 0; v < 8; v++)
-            out[d][v] = met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v];
-}
-
 // Divergence-free B (Section IV.b): for every zone of a column the fused
 // per-column map (KKT inverse followed by evaluation at the ADER nodes and the
 // new zone mean) is applied to the zone's inputs -- its WENO B, the limited
@@ -769,10 +604,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             const int rev = G.col_rev[(i64)cq * 12 + le], slot = G.col_slot[(i64)cq * 12 + le];
             i64 e;
             if (le < 8) {
-                const int ae = G.col_ae[4 * cq + LE_FACE[le]];
-                e = G.NRE + (i64)ae * (G.K + 1) + kq + LE_UP[le];
+                const int ae = G.col_ae[4 * cq + LocalEdges::FACE[le]];
+                e = G.NRE + (i64)ae * (G.K + 1) + kq + LocalEdges::UP[le];
             } else {
-                e = (i64)G.col_v[4 * cq + LE_CORNER[le - 8]] * G.K + kq;
+                e = (i64)G.col_v[4 * cq + LocalEdges::CORNER[le - 8]] * G.K + kq;
             }
             R *o = etr + (e * 4 + slot) * 3 * 11;
 #pragma unroll
@@ -823,7 +658,7 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
             UR[v] = b[v];
             FR[v] = b[8 + v];
         }
-        dev_hll(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
+        dev_hll<double>(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
         double w = fw[q] * area;
 #pragma unroll
         for (int v = 0; v < 8; v++) acc[v] += w * Fs[v];
@@ -833,51 +668,6 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
 }
 
 // ---------------------------------------------------------------- edge electric fields
-__device__ __forceinline__ double emf4(const double U[4][8], const double Et[4], const double *F, double gam)
-{
-    const double *e1 = F, *e2 = F + 3;
-    double ap1 = 0.0, am1 = 0.0, ap2 = 0.0, am2 = 0.0, B1[4], B2[4];
-#pragma unroll
-    for (int s = 0; s < 4; s++) {
-        double ir = 1.0 / U[s][0];
-        double v1 = (U[s][1] * e1[0] + U[s][2] * e1[1] + U[s][3] * e1[2]) * ir;
-        double v2 = (U[s][1] * e2[0] + U[s][2] * e2[1] + U[s][3] * e2[2]) * ir;
-        double c1 = dev_fast(U[s], gam, e1), c2 = dev_fast(U[s], gam, e2);
-        ap1 = fmax(ap1, v1 + c1);
-        am1 = fmax(am1, c1 - v1);
-        ap2 = fmax(ap2, v2 + c2);
-        am2 = fmax(am2, c2 - v2);
-        B1[s] = U[s][5] * e1[0] + U[s][6] * e1[1] + U[s][7] * e1[2];
-        B2[s] = U[s][5] * e2[0] + U[s][6] * e2[1] + U[s][7] * e2[2];
-    }
-    // slots counter-clockwise: 0 SW, 1 SE, 2 NE, 3 NW
-    double Es = (ap1 * ap2 * Et[0] + ap1 * am2 * Et[3] + am1 * ap2 * Et[1] + am1 * am2 * Et[2]) / ((ap1 + am1) * (ap2 + am2));
-    Es += ap1 * am1 * (0.5 * (B2[1] + B2[2]) - 0.5 * (B2[0] + B2[3])) / (ap1 + am1);
-    Es -= ap2 * am2 * (0.5 * (B1[2] + B1[3]) - 0.5 * (B1[0] + B1[1])) / (ap2 + am2);
-    return Es;
-}
-
-// three zones about an edge: mean of the 1-D HLL induction fluxes of the three faces
-__device__ __forceinline__ double emf3(const double U[4][8], const double E[4][3], const double *N3, const double *t, double gam)
-{
-    double acc = 0.0;
-    for (int s = 0; s < 3; s++) {
-        int s2 = (s + 1) % 3;
-        const double *n = N3 + 3 * s;
-        double FL[8] = {0, 0, 0, 0, 0, 0, 0, 0}, FR[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Fs[8];
-        FL[5] = n[1] * E[s][2] - n[2] * E[s][1];
-        FL[6] = n[2] * E[s][0] - n[0] * E[s][2];
-        FL[7] = n[0] * E[s][1] - n[1] * E[s][0];
-        FR[5] = n[1] * E[s2][2] - n[2] * E[s2][1];
-        FR[6] = n[2] * E[s2][0] - n[0] * E[s2][2];
-        FR[7] = n[0] * E[s2][1] - n[1] * E[s2][0];
-        dev_hll(U[s], U[s2], FL, FR, n, gam, Fs);
-        double tn[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
-        acc -= Fs[5] * tn[0] + Fs[6] * tn[1] + Fs[7] * tn[2];
-    }
-    return acc / 3.0;
-}
-
 // radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr]
 template <class R>
 __global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam)
@@ -921,7 +711,7 @@ __global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const R *
             for (int v = 0; v < 3; v++) E[s][v] = rec[8 + v];
             Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
         }
-        double Es = (nzs == 4) ? emf4(U, Et, frame[p], gam) : emf3(U, E, N3, tt, gam);
+        double Es = (nzs == 4) ? emf4<double>(U, Et, frame[p], gam) : emf3<double>(U, E, N3, tt, gam);
         gsum += wl[p] * Es;
     }
     Gam[e] = gsum;
@@ -992,7 +782,7 @@ __global__ __launch_bounds__(256) void cfl_partial(DevGeom G, double gam, double
         for (int v = 0; v < 8; v++) u[v] = U[v * G.Z + z];
         double ir = 1.0 / u[0];
         double vv = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir;
-        double a2 = gam * dev_pressure(u, gam) * ir, b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+        double a2 = gam * dev_pressure<double>(u, gam) * ir, b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
         best = cfl * G.dins[c] * G.zscale[k] / (vv + sqrt(a2 + b2));
     }
     sm[threadIdx.x] = best;
@@ -1059,7 +849,7 @@ __global__ __launch_bounds__(256) void diag_partial(DevGeom G, double gam, const
             acc[1 + v] += G.vol[z] * u[v];
         }
         acc[9] = fmin(acc[9], u[0]);
-        acc[10] = fmin(acc[10], dev_pressure(u, gam));
+        acc[10] = fmin(acc[10], dev_pressure<double>(u, gam));
     }
     for (int v = 0; v < DIAG_NV; v++) sm[threadIdx.x][v] = acc[v];
     __syncthreads();
@@ -1221,6 +1011,16 @@ rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, cons
     if (g->d.order == 4) return f32 ? step_order<4, float>(g, p, U, Bf, Uo, Bo, st) : step_order<4, double>(g, p, U, Bf, Uo, Bo, st);
     set_error("unsupported order");
     return RG_ENOTSUP;
+}
+
+rg_status launch_bc(rg_geom *g, int bc_kind, const double *U, const double *Bf, double *Uo, double *Bo, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGeom &G = g->d;
+    bc_zones<<<nblocks(G.Z, 256), 256, 0, st>>>(G, bc_kind, U, Uo);
+    bc_faces<<<nblocks(G.NF, 256), 256, 0, st>>>(G, bc_kind, Bf, Bo);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
 }
 
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
