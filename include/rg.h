@@ -136,6 +136,25 @@ typedef struct {
 rg_status rg_step(const rg_geom *geom, rg_step_params *params, const double *U, const double *Bf,
                   double *U_out, double *Bf_out, void *stream);
 
+/* Adjoint of one rg_step (its vector-Jacobian product) at the state
+ * (U_n, Bf_n), with params->dt held fixed (dt > 0 required: a dt taken from
+ * the CFL condition would itself depend on the state).  Given the gradients
+ * gU_np1[8][n_zones], gBf_np1[n_faces] of a scalar loss with respect to the
+ * step's outputs U_out, Bf_out, writes the gradients gU_n, gBf_n with
+ * respect to U_n, Bf_n (all device buffers, rg_step layout; the outputs may
+ * not alias the incoming gradients).  Exact derivative of the computed
+ * step: the Picard sweeps of the predictor (Section V.d) are differentiated
+ * as unrolled, the WENO-AO weights (Section III) through their nonlinear
+ * dependence, and at the kinks (MinMod of eq. 4.11, the HLL branch and the
+ * min/max of the signal speeds) the branch the forward step took is
+ * differentiated.  Recomputes the forward step internally (its work buffers
+ * and rg_step_fluxes data are overwritten).  Deterministic: every gradient
+ * is gathered by its owner, no floating-point atomics.  FP64 geometries only
+ * (RG_ENOTSUP for RG_MODE_FP32); device work buffers are allocated on the
+ * first call (RG_ENOMEM).  Asynchronous on `stream`. */
+rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *params, const double *U_n, const double *Bf_n,
+                          const double *gU_np1, const double *gBf_np1, double *gU_n, double *gBf_n, void *stream);
+
 /* Device copies of the last step's face flux integrals Phi[8][n_faces]
  * (time-integrated over the step divided by dt, canonical normal) and edge
  * electric-field line integrals Gam[n_edges] (canonical direction).  Entries

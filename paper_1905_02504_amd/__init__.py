@@ -116,6 +116,34 @@ class ShellMHD:
         N.rg_step(self._geom, p, U.data_ptr(), Bf.data_ptr(), U_out.data_ptr(), Bf_out.data_ptr(), _stream())
         return U_out, Bf_out, p.dt
 
+    def step_adjoint(self, U, Bf, gU1, gBf1, dt, gamma=5.0 / 3.0, bc=0, n_picard=0, gU=None, gBf=None):
+        """rg_step_adjoint: the gradients with respect to (U, Bf) of a loss whose
+        gradients with respect to the step's outputs are (gU1, gBf1); dt fixed."""
+        import torch
+        for t, shape in ((U, (8, self.nz)), (Bf, (self.nf,)), (gU1, (8, self.nz)), (gBf1, (self.nf,))):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape == shape
+        if not dt > 0:
+            raise ValueError("the adjoint needs a fixed dt > 0")
+        if gU is None:
+            gU = torch.empty_like(U)
+        if gBf is None:
+            gBf = torch.empty_like(Bf)
+        p = rg_step_params(gamma, dt, 0.0, bc, n_picard)
+        N.rg_step_adjoint(self._geom, p, U.data_ptr(), Bf.data_ptr(), gU1.data_ptr(), gBf1.data_ptr(),
+                          gU.data_ptr(), gBf.data_ptr(), _stream())
+        return gU, gBf
+
+    def step_ad(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, n_picard=0):
+        """Differentiable step (torch autograd): saves (U, Bf) as the step's
+        checkpoint and recomputes the rest in the backward pass."""
+        return _step_function().apply(U, Bf, self, float(dt), float(gamma), int(bc), int(n_picard))
+
+    def rollout(self, U, Bf, dt, n_steps, gamma=5.0 / 3.0, bc=0, n_picard=0):
+        """n_steps differentiable steps with fixed dt (one checkpoint per step)."""
+        for _ in range(n_steps):
+            U, Bf = self.step_ad(U, Bf, dt, gamma=gamma, bc=bc, n_picard=n_picard)
+        return U, Bf
+
     def fluxes(self):
         import torch
         Phi = torch.zeros((8, self.nf), dtype=torch.float64, device="cuda")
@@ -141,3 +169,36 @@ class ShellMHD:
     def work(self):
         """-> ({stage: flops per step}, {stage: algorithmic HBM bytes per step})"""
         return N.rg_geom_work(self._geom)
+
+
+_STEP_FN = None
+
+
+def _step_function():
+    """torch.autograd.Function around rg_step / rg_step_adjoint (built on first use)."""
+    global _STEP_FN
+    if _STEP_FN is not None:
+        return _STEP_FN
+    import torch
+
+    class StepFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, U, Bf, shell, dt, gamma, bc, n_picard):
+            U = U.detach().contiguous()
+            Bf = Bf.detach().contiguous()
+            U1, Bf1, _ = shell.step(U, Bf, dt, gamma=gamma, bc=bc, n_picard=n_picard)
+            ctx.save_for_backward(U, Bf)
+            ctx.cfg = (shell, dt, gamma, bc, n_picard)
+            return U1, Bf1
+
+        @staticmethod
+        def backward(ctx, gU1, gBf1):
+            U, Bf = ctx.saved_tensors
+            shell, dt, gamma, bc, n_picard = ctx.cfg
+            gU1 = torch.zeros_like(U) if gU1 is None else gU1.contiguous()
+            gBf1 = torch.zeros_like(Bf) if gBf1 is None else gBf1.contiguous()
+            gU, gBf = shell.step_adjoint(U, Bf, gU1, gBf1, dt, gamma=gamma, bc=bc, n_picard=n_picard)
+            return gU, gBf, None, None, None, None, None
+
+    _STEP_FN = StepFn
+    return StepFn

@@ -289,7 +289,39 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         }
         std::vector<double>().swap(hg.Mb);
         std::vector<double> Rv = r.R, wt = r.wt, radius = m.radius, zs(zscale.begin(), zscale.end() - 1);
-        std::vector<int> vncol = m.v_ncol, aecol = m.ae_col, aev = m.ae_v;
+        std::vector<int> vncol = m.v_ncol, aecol = m.ae_col, aev = m.ae_v, aelf = m.ae_lf;
+        // adjoint tables: angular edges at each vertex, and for every column
+        // the (stencil column, slot, radial offset) of the WENO stencils that
+        // hold it
+        std::vector<int> vae((size_t)nv * 4, -1), vcnt(nv, 0);
+        for (int ae = 0; ae < nae; ae++)
+            for (int s = 0; s < 2; s++) {
+                const int v = m.ae_v[2 * ae + s];
+                if (vcnt[v] >= 4) { set_error("vertex with more than four angular edges"); free_geom(g); return RG_ENOTSUP; }
+                vae[(size_t)v * 4 + vcnt[v]++] = ae;
+            }
+        for (int v = 0; v < nv; v++)
+            if (vcnt[v] != m.v_ncol[v]) { set_error("vertex edge count differs from its column count"); free_geom(g); return RG_ENOTSUP; }
+        std::vector<int> invp(ncol + 1, 0), inve;
+        for (int c2 = 0; c2 < ncol; c2++)
+            for (int j = 0; j < NS; j++) {
+                const int mm = hg.stm[(size_t)c2 * NS + j];
+                if (mm >= 0) invp[(mm >> 3) + 1]++;
+            }
+        for (int c = 0; c < ncol; c++) invp[c + 1] += invp[c];
+        inve.assign((size_t)invp[ncol] * 3, 0);
+        {
+            std::vector<int> fill(invp.begin(), invp.end() - 1);
+            for (int c2 = 0; c2 < ncol; c2++)
+                for (int j = 0; j < NS; j++) {
+                    const int mm = hg.stm[(size_t)c2 * NS + j];
+                    if (mm < 0) continue;
+                    const int e = fill[mm >> 3]++;
+                    inve[(size_t)e * 3] = c2;
+                    inve[(size_t)e * 3 + 1] = j;
+                    inve[(size_t)e * 3 + 2] = (mm & 7) - 3;
+                }
+        }
 
         if (!device) {
             *out = g;
@@ -315,7 +347,9 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                   upload(g, hg.fevA, &d.fevA) && upload(g, hg.fnA, &d.fnA) && upload(g, hg.fwA, &d.fwA) &&
                   upload(g, hg.aeF, &d.aeF) && upload(g, hg.aeW, &d.aeW) && upload(g, hg.ae_rs, &d.ae_rs) &&
                   upload(g, vncol, &d.v_ncol) && upload(g, hg.vF, &d.vF) && upload(g, hg.vN3, &d.vN3) &&
-                  upload(g, vol, &d.vol) && upload(g, area, &d.area);
+                  upload(g, vol, &d.vol) && upload(g, area, &d.area) && upload(g, r.D, &d.Dfull) &&
+                  upload(g, aelf, &d.ae_lf) && upload(g, vae, &d.v_ae) && upload(g, invp, &d.inv_ptr) &&
+                  upload(g, inve, &d.inv_ent);
         if (ok && mode == RG_MODE_FP32)
             ok = upload_f32(g, hg.Pl, &d.PlF) && upload_f32(g, hg.Ps, &d.PsF) && upload_f32(g, hg.Qs, &d.QsF) &&
                  upload_f32(g, EvT, &d.EvF) && upload_f32(g, hg.nJ, &d.nJF) && upload_f32(g, nMT, &d.nMF) &&
@@ -393,6 +427,51 @@ extern "C" rg_status rg_step(const rg_geom *geom, rg_step_params *params, const 
         params->dt = dt;
     }
     return launch_step(g, *params, U, Bf, U_out, Bf_out, stream);
+}
+
+namespace {
+bool alloc_adjoint(rg_geom *g)
+{
+    AdjBuffers &A = g->adj;
+    if (A.ready) return true;
+    const DevGeom &d = g->d;
+    const size_t Z = d.Z, NF = d.NF, NE = d.NE, nzr = (size_t)d.ncol * (d.Nr + 2);
+    const size_t NA = 3 * (size_t)(d.NC + 1);
+    bool ok = alloc_zero(g, 8 * Z, &A.Utmp) && alloc_zero(g, NF, &A.Btmp) && alloc_zero(g, 8 * Z, &A.Ubc) &&
+              alloc_zero(g, NF, &A.Bbc) && alloc_zero(g, 8 * Z, &A.gUo) && alloc_zero(g, NF, &A.gBo) &&
+              alloc_zero(g, 3 * Z, &A.gzoneB) && alloc_zero(g, 8 * (size_t)d.NC * Z, &A.gwc) &&
+              alloc_zero(g, (size_t)16 * d.Q * 2 * NF, &A.gftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &A.getr) &&
+              alloc_zero(g, NE, &A.gGam) && alloc_zero(g, 8 * NF, &A.gPhi) &&
+              alloc_zero(g, nzr * 3 * d.N, &A.gbnode) && alloc_zero(g, (size_t)d.Q * NF, &A.gbnod) &&
+              alloc_zero(g, nzr * (d.NIN - NA), &A.gside) && alloc_zero(g, NF * 2 * (3 + 3 * (size_t)d.NC), &A.gsb) &&
+              alloc_zero(g, 8 * (size_t)d.NS * nzr, &A.gdu);
+    A.ready = ok;
+    return ok;
+}
+}  // namespace
+
+extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *params, const double *U_n,
+                                     const double *Bf_n, const double *gU_np1, const double *gBf_np1, double *gU_n,
+                                     double *gBf_n, void *stream)
+{
+    if (!geom || !params || !U_n || !Bf_n || !gU_np1 || !gBf_np1 || !gU_n || !gBf_n) {
+        set_error("null argument");
+        return RG_EINVAL;
+    }
+    if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0 ||
+        !(params->dt > 0.0)) {
+        set_error("invalid step parameters (the adjoint needs a fixed dt > 0)");
+        return RG_EINVAL;
+    }
+    rg_geom *g = const_cast<rg_geom *>(geom);
+    if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
+    if (g->mode != RG_MODE_FP64) { set_error("the adjoint is implemented for the FP64 form only"); return RG_ENOTSUP; }
+    if ((const void *)gU_n == (const void *)gU_np1 || (const void *)gBf_n == (const void *)gBf_np1) {
+        set_error("the adjoint cannot run in place");
+        return RG_EINVAL;
+    }
+    if (!alloc_adjoint(g)) { set_error("device allocation of the adjoint buffers failed"); return RG_ENOMEM; }
+    return launch_adjoint(g, *params, U_n, Bf_n, gU_np1, gBf_np1, gU_n, gBf_n, stream);
 }
 
 extern "C" rg_status rg_step_fluxes(const rg_geom *g, double *Phi, double *Gam, void *stream)

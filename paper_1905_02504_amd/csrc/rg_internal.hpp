@@ -130,6 +130,21 @@ struct DevGeom {
     // FP32 copies of the tables read by the reconstruction and predictor
     // contractions (precision mode RG_MODE_FP32 only; null otherwise)
     const float *PlF, *PsF, *QsF, *EvF, *nJF, *nMF, *fevRF, *fevAF, *fintcF, *eintcF;
+    // tables used only by the adjoint of the step
+    const double *Dfull;    // 3 x N x N  d psi_l / d xi_d at node i, [d][i][l]
+    const int *ae_lf;       // nae x 2    local face of the angular edge in each column
+    const int *v_ae;        // nv x 4     angular edges at each vertex (v_ncol of them)
+    const int *inv_ptr;     // ncol + 1   CSR over member columns of the WENO stencils
+    const int *inv_ent;     // n x 3      (stencil column, slot, radial offset dk) per entry
+};
+
+// Device buffers of the adjoint of the step, allocated on its first call
+struct AdjBuffers {
+    bool ready = false;
+    double *Utmp = nullptr, *Btmp = nullptr, *Ubc = nullptr, *Bbc = nullptr;
+    double *gUo = nullptr, *gBo = nullptr, *gzoneB = nullptr, *gwc = nullptr, *gftr = nullptr, *getr = nullptr;
+    double *gGam = nullptr, *gPhi = nullptr, *gbnode = nullptr, *gbnod = nullptr, *gside = nullptr, *gsb = nullptr;
+    double *gdu = nullptr;
 };
 
 }  // namespace rg
@@ -151,6 +166,7 @@ struct rg_geom {
     double *wcoef = nullptr, *bnod = nullptr, *ftr = nullptr, *etr = nullptr;
     double *Phi = nullptr, *Gam = nullptr, *zoneB = nullptr, *red = nullptr;
     double *bnode = nullptr;   // divergence-free B at the ADER nodes, [recon zone][3N]
+    rg::AdjBuffers adj;
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes
     std::vector<int> ae_rs_host; // +1 if side 1 of an angular edge is right of its direction

@@ -156,3 +156,11 @@ def white_noise(n: int, seed: int = SEED_NOISE, count: int = 2) -> np.ndarray:
     """Uniform(-1, 1) noise, shape (count, n)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, size=(count, n))
+
+
+def loss_targets(n: int, rho0: float = 1.0, b0: float = 1.0, amp: float = 0.01) -> tuple:
+    """Per-zone targets (rho*, b*) of the adjoint checks' loss:
+    rho0 (1 + amp U(-1,1)) from SEED_TARGET[0] and b0 (1 + amp U(-1,1)) from SEED_TARGET[1]."""
+    r = np.random.default_rng(SEED_TARGET[0]).uniform(-1.0, 1.0, size=n)
+    b = np.random.default_rng(SEED_TARGET[1]).uniform(-1.0, 1.0, size=n)
+    return rho0 * (1.0 + amp * r), b0 * (1.0 + amp * b)

@@ -39,6 +39,15 @@ def test_argument_errors_are_reported():
         N.rg_geom_precompute_host(m, 4)  # ghost depth below order - 1
     with pytest.raises(N.RGError):
         N.rg_geom_precompute_host(m, 5)
+    # the adjoint needs a fixed dt > 0 and a geometry with device data; both
+    # are checked before any buffer is touched
+    g = N.rg_geom_precompute_host(m, 3)
+    fake = 1 << 20
+    for dt in (0.0, 1e-3):
+        p = N.rg_step_params(5.0 / 3.0, dt, 0.0, 0, 0)
+        with pytest.raises(N.RGError):
+            N.rg_step_adjoint(g, p, fake, fake, fake, fake, fake + 8, fake + 8, None)
+    N.rg_geom_free(g)
     N.rg_mesh_free(m)
 
 
