@@ -3,38 +3,28 @@
 //
 //   face_ct, zone_update  : linear; transposed as gathers over the faces of an
 //                           edge and the zones of a face
-//   edge_emf, face_flux   : pointwise Riemann solvers; exact local Jacobians by
-//                           forward differentiation (dual numbers) of the
-//                           step's own solver code, contracted with the
-//                           incoming gradient
-//   predictor             : recomputed per zone, then the traces, time
-//                           averages and the unrolled Picard sweeps reversed
-//                           (flux Jacobians again by dual numbers, derivative
-//                           matrices transposed)
+//   edge_emf, face_flux   : reverse-mode derivatives of the pointwise Riemann
+//                           solvers, written out by hand (mhd_adjoint.hpp)
+//   predictor             : recomputed per zone in the step's own wavefront
+//                           layout, then the traces, time averages and the
+//                           unrolled Picard sweeps reversed (flux Jacobians
+//                           transposed by hand, derivative matrices
+//                           transposed through the same LDS slab)
 //   bmap                  : linear, the transposed per-column map
 //   face_bnodal           : MinMod and mean restore reversed per face
-//   weno                  : exact derivative of the WENO-AO combination
-//                           (nonlinear weights included) by dual numbers
+//   weno                  : reverse-mode derivative of the WENO-AO
+//                           combination, nonlinear weights included
 //   boundary fill         : ghost copies accumulated into their sources
 //
 // Every gradient contribution to a zone or face is gathered by the one thread
 // that owns the target, in a fixed order: no floating-point atomics, so the
 // result is deterministic.  The forward quantities the reversal needs are
 // recomputed by running the step first.
-#include "mhd_device.hpp"
+#include "mhd_adjoint.hpp"
 
 namespace rg {
 
 namespace {
-
-// Picard sweeps the adjoint keeps in LDS (the sweeps' states are all needed
-// in reverse)
-constexpr int ADJ_MAX_PICARD = 6;
-
-__global__ void fill_zero(double *p, i64 n)
-{
-    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) p[t] = 0.0;
-}
 
 inline unsigned nblk(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -127,15 +117,19 @@ __global__ void adj_update_zones(DevGeom G, const double *__restrict__ gU, doubl
     const bool interior = k >= G.g && k < G.g + G.Nr;
     for (int v = 0; v < 8; v++) {
         const double g = gU[(i64)v * G.Z + z];
-        if (interior && v >= 5) gzoneB[(i64)(v - 5) * G.Z + z] = g;
-        else gUo[(i64)v * G.Z + z] = g;
+        if (interior && v >= 5) {
+            gzoneB[(i64)(v - 5) * G.Z + z] = g;
+            gUo[(i64)v * G.Z + z] = 0.0;
+        } else {
+            gUo[(i64)v * G.Z + z] = g;
+        }
     }
 }
 
 // ---------------------------------------------------------------- Riemann solvers
 template <int P>
-__global__ void adj_face_flux(DevGeom G, double gam, const double *__restrict__ ftr, const double *__restrict__ gPhi,
-                              double *__restrict__ gftr)
+__global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, const double *__restrict__ ftr,
+                                                     const double *__restrict__ gPhi, double *__restrict__ gftr)
 {
     using T = Tr<P>;
     const int nrad = G.Nr + 1, nang = G.Nr;
@@ -161,28 +155,29 @@ __global__ void adj_face_flux(DevGeom G, double gam, const double *__restrict__ 
     for (int v = 0; v < 8; v++) gPhiF[v] = gPhi[(i64)v * G.NF + f];
     for (int q = 0; q < T::Q; q++) {
         const double *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
-        double *ga = gftr + ((f * 2 + 0) * T::Q + q) * 16, *gb = gftr + ((f * 2 + 1) * T::Q + q) * 16;
+        double UL[8], UR[8], FL[8], FR[8], gFs[8], gUL[8], gUR[8], gFL[8], gFR[8];
         const double w = fw[q] * area;
-        // inputs in the order UL, FL (side 0 record), UR, FR (side 1 record)
-        for (int in = 0; in < 32; in++) {
-            dual UL[8], UR[8], FL[8], FR[8], Fs[8];
-            for (int v = 0; v < 8; v++) {
-                UL[v] = dual(a[v], in == v ? 1.0 : 0.0);
-                FL[v] = dual(a[8 + v], in == 8 + v ? 1.0 : 0.0);
-                UR[v] = dual(b[v], in == 16 + v ? 1.0 : 0.0);
-                FR[v] = dual(b[8 + v], in == 24 + v ? 1.0 : 0.0);
-            }
-            dev_hll<dual>(UL, UR, FL, FR, nrm + q * 3, dual(gam), Fs);
-            double s = 0.0;
-            for (int v = 0; v < 8; v++) s += Fs[v].d * gPhiF[v];
-            if (in < 16) ga[in] = w * s;
-            else gb[in - 16] = w * s;
+        for (int v = 0; v < 8; v++) {
+            UL[v] = a[v];
+            FL[v] = a[8 + v];
+            UR[v] = b[v];
+            FR[v] = b[8 + v];
+            gFs[v] = w * gPhiF[v];
+            gUL[v] = gUR[v] = gFL[v] = gFR[v] = 0.0;
+        }
+        hll_vjp(UL, UR, FL, FR, nrm + q * 3, gam, gFs, gUL, gUR, gFL, gFR);
+        double *ga = gftr + ((f * 2 + 0) * T::Q + q) * 16, *gb = gftr + ((f * 2 + 1) * T::Q + q) * 16;
+        for (int v = 0; v < 8; v++) {
+            ga[v] = gUL[v];
+            ga[8 + v] = gFL[v];
+            gb[v] = gUR[v];
+            gb[8 + v] = gFR[v];
         }
     }
 }
 
-__global__ void adj_edge_emf(DevGeom G, double gam, const double *__restrict__ etr, const double *__restrict__ gGam,
-                             double *__restrict__ getr)
+__global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const double *__restrict__ etr,
+                                                    const double *__restrict__ gGam, double *__restrict__ getr)
 {
     const int nrad = G.Nr, nang = G.Nr + 1;
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,124 +207,200 @@ __global__ void adj_edge_emf(DevGeom G, double gam, const double *__restrict__ e
     const double ge = gGam[e];
     for (int p = 0; p < 3; p++) {
         const double *tt = frame[p] + 6;
-        for (int in = 0; in < nzs * 11; in++) {
-            dual U[4][8], E[4][3], Et[4];
-            for (int s = 0; s < 4; s++) {
-                const double *rec = etr + ((e * 4 + s) * 3 + p) * 11;
-                for (int v = 0; v < 8; v++) U[s][v] = dual(rec[v], in == s * 11 + v ? 1.0 : 0.0);
-                for (int v = 0; v < 3; v++) E[s][v] = dual(rec[8 + v], in == s * 11 + 8 + v ? 1.0 : 0.0);
-                Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
-            }
-            const dual Es = (nzs == 4) ? emf4<dual>(U, Et, frame[p], dual(gam)) : emf3<dual>(U, E, N3, tt, dual(gam));
-            getr[((e * 4 + in / 11) * 3 + p) * 11 + in % 11] = wl[p] * ge * Es.d;
+        double U[4][8], E[4][3], Et[4], gU[4][8], gE[4][3], gEt[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const double *rec = etr + ((e * 4 + s) * 3 + p) * 11;
+#pragma unroll
+            for (int v = 0; v < 8; v++) { U[s][v] = rec[v]; gU[s][v] = 0.0; }
+#pragma unroll
+            for (int v = 0; v < 3; v++) { E[s][v] = rec[8 + v]; gE[s][v] = 0.0; }
+            Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
+            gEt[s] = 0.0;
+        }
+        if (nzs == 4) {
+            emf4_vjp(U, Et, frame[p], gam, wl[p] * ge, gU, gEt);
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int v = 0; v < 3; v++) gE[s][v] = gEt[s] * tt[v];
+        } else {
+            emf3_vjp(U, E, N3, tt, gam, wl[p] * ge, gU, gE);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            if (s >= nzs) continue;
+            double *o = getr + ((e * 4 + s) * 3 + p) * 11;
+#pragma unroll
+            for (int v = 0; v < 8; v++) o[v] = gU[s][v];
+#pragma unroll
+            for (int v = 0; v < 3; v++) o[8 + v] = gE[s][v];
         }
     }
 }
 
 // ---------------------------------------------------------------- predictor
-// One zone per block; lanes below N are the zone's serendipity nodes.
+// The predictor's wavefront layout: 64 / N zones per wavefront, one lane per
+// serendipity node, the derivative matrices applied through the LDS slab.
+// A lane keeps its node's initial state, tau = 0 derivative and the states of
+// one Picard sweep in registers; the states of earlier sweeps are recomputed
+// from the first sweep when the reversal reaches them.
 template <int P>
-__global__ __launch_bounds__(64) void adj_predictor(DevGeom G, double dt, double gamma, int npic,
-                                                    const double *__restrict__ Uo, const double *__restrict__ wc,
-                                                    const double *__restrict__ bnode, const double *__restrict__ gftr,
-                                                    const double *__restrict__ getr, double *__restrict__ gUo,
-                                                    double *__restrict__ gwc, double *__restrict__ gbnode)
+struct PredLayout {
+    static constexpr int N = Tr<P>::N, SN = N + 1, ZS = 32 * SN + 4, ZPW = 64 / N, E = Tr<P>::M - 1;
+};
+
+// one Picard sweep: Ut <- Ua - R0 dFa - sum_s R_s D F(Ut_s)   (all lanes call it)
+template <int P>
+__device__ __forceinline__ void picard_sweep(const DevGeom &G, double *s_f, double *sf, int lane, int i, int i1, int i2,
+                                             bool active, const double (&Ua)[8], const double (&dFa)[8], double iJ,
+                                             const double (&met)[9], double gam, double (&Ut)[Tr<P>::M - 1][8])
 {
-    using T = Tr<P>;
-    constexpr int N = T::N, E = T::M - 1, NCF = T::NC + 1, NPMAX = ADJ_MAX_PICARD;
-    __shared__ double s_c[5 * NCF];
-    __shared__ double s_ut[NPMAX + 1][E][8][N];   // Ut after each sweep (index 0: the initial copy of Ua)
-    __shared__ double s_a[3][8][N];               // flux / gradient slab
-    __shared__ double s_red[5][N];
-    const int KR = G.Nr + 2;
-    const i64 zt = blockIdx.x;
-    const int c = (int)(zt / KR), k = G.g - 1 + (int)(zt % KR);
-    const i64 z = (i64)c * G.K + k;
-    const int i = threadIdx.x;
-    const bool node = i < N;
-    const double *D = G.Dfull;   // [3][N][N]
-    for (int j = i; j < 5 * NCF; j += 64) {
-        const int v = j / NCF, a = j % NCF;
-        s_c[j] = a == 0 ? Uo[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
+    using L = PredLayout<P>;
+    constexpr int E = L::E, M = Tr<P>::M;
+    double A[E][8];
+#pragma unroll
+    for (int s = 0; s < E; s++) {
+        if (active) {
+            double F[3][8];
+            mapped_flux<double>(Ut[s], iJ, met, gam, F);
+            put_flux<L::SN, double>(sf, i, i1, i2, F);
+        }
+        __syncthreads();
+        deriv_rows<P, L::SN, L::ZS, L::ZPW, double>(s_f, lane);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 8; v++) A[s][v] = 0.0;
+        if (active) get_deriv<L::SN, double>(sf, i, i1, i2, A[s]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < E; t++)
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            double u = Ua[v] - G.R[t * M] * dFa[v];
+#pragma unroll
+            for (int s = 0; s < E; s++) u -= G.R[t * M + s + 1] * A[s][v];
+            Ut[t][v] = u;
+        }
+}
+
+// gF[d][v] = sum_i D_d[i][node] g[i][v] for the lane's node (all lanes call it)
+template <int P>
+__device__ __forceinline__ void deriv_transpose(double *s_f, double *sf, int lane, int i, int i1, int i2, bool active,
+                                                const double (&g)[8], double (&gF)[3][8])
+{
+    using L = PredLayout<P>;
+    if (active) {
+        const double G3[3][8] = {{g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]},
+                                 {g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]},
+                                 {g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]}};
+        put_flux<L::SN, double>(sf, i, i1, i2, G3);
     }
     __syncthreads();
-    double Ua[8], dFa[8], met[9], iJ = 1.0, J = 1.0;
+    deriv_rows<P, L::SN, L::ZS, L::ZPW, double, true>(s_f, lane);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+        gF[0][v] = active ? sf[v * L::SN + i] : 0.0;
+        gF[1][v] = active ? sf[(8 + v) * L::SN + i1] : 0.0;
+        gF[2][v] = active ? sf[(16 + v) * L::SN + i2] : 0.0;
+    }
+    __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void adj_predictor(
+    DevGeom G, double dt, double gamma, int npic, const double *__restrict__ U, const double *__restrict__ wc,
+    const double *__restrict__ bnode, const double *__restrict__ gftr, const double *__restrict__ getr,
+    double *__restrict__ gUo, double *__restrict__ gwc, double *__restrict__ gbnode)
+{
+    using T = Tr<P>;
+    using L = PredLayout<P>;
+    constexpr int N = T::N, M = T::M, ZS = L::ZS, ZPW = L::ZPW, E = L::E, NCF = T::NC + 1;
+    __shared__ double s_c[ZPW][5 * NCF];
+    __shared__ double s_f[ZPW * ZS];
     const double gam = gamma;
-    if (node) {
+    const int lane = threadIdx.x, zl = lane / N, i = lane % N;
+    const int KR = G.Nr + 2;
+    const i64 nzr = (i64)G.ncol * KR;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned zt = lb * ZPW + zl;
+    const bool active = (zl < ZPW) && (zt < (unsigned)nzr);
+    int c = 0, k = 0;
+    i64 z = 0;
+    if (active) {
+        c = (int)(zt / (unsigned)KR);
+        k = G.g - 1 + (int)(zt % (unsigned)KR);
+        z = (i64)c * G.K + k;
+        for (int j = i; j < 5 * NCF; j += N) {
+            const int v = j / NCF, a = j % NCF;
+            s_c[zl][j] = a == 0 ? U[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
+        }
+    }
+    const int i1 = DTab<P>::SWAP1[i], i2 = DTab<P>::SWAP2[i];
+    __syncthreads();
+    double Ua[8], dFa[8], met[9], iJ = 1.0, J = 1.0;
+    double *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
+    for (int v = 0; v < 8; v++) Ua[v] = dFa[v] = 0.0;
+    for (int m = 0; m < 9; m++) met[m] = 0.0;
+    if (active) {
         const double *Ev = G.Ev + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
-            double acc = s_c[v * NCF];
-            for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[v * NCF + 1 + a];
+            double acc = s_c[zl][v * NCF];
+#pragma unroll
+            for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[zl][v * NCF + 1 + a];
             Ua[v] = acc;
         }
-        const double *bn = bnode + zt * (3 * N) + i;
+        const double *bn = bnode + (i64)zt * (3 * N) + i;
         Ua[5] = bn[0];
         Ua[6] = bn[N];
         Ua[7] = bn[2 * N];
         J = G.nJ[(i64)c * N + i];
         iJ = 1.0 / J;
         const double fac = dt / G.zscale[k];
+#pragma unroll
         for (int m = 0; m < 9; m++) met[m] = fac * G.nM[((i64)c * 9 + m) * N + i];
+#pragma unroll
         for (int v = 0; v < 8; v++) Ua[v] *= J;
-    }
-    // ---- forward recomputation
-    auto flux_to_slab = [&](const double *u) {
         double F[3][8];
-        mapped_flux<double>(u, iJ, met, gam, F);
-        for (int d = 0; d < 3; d++)
-            for (int v = 0; v < 8; v++) s_a[d][v][i] = F[d][v];
-    };
-    auto deriv_from_slab = [&](double *out) {   // out[v] = sum_d sum_l D_d[i][l] F_d[l][v]
-        for (int v = 0; v < 8; v++) out[v] = 0.0;
-        for (int d = 0; d < 3; d++)
-            for (int l = 0; l < N; l++) {
-                const double w = D[((i64)d * N + i) * N + l];
-                if (w != 0.0)
-                    for (int v = 0; v < 8; v++) out[v] += w * s_a[d][v][l];
-            }
-    };
-    if (node) flux_to_slab(Ua);
-    __syncthreads();
-    if (node) deriv_from_slab(dFa);
-    __syncthreads();
-    if (node)
-        for (int t = 0; t < E; t++)
-            for (int v = 0; v < 8; v++) s_ut[0][t][v][i] = Ua[v];
-    for (int it = 1; it <= npic; it++) {
-        double A[E][8];
-        for (int s = 0; s < E; s++) {
-            if (it == 1) {
-                for (int v = 0; v < 8; v++) A[s][v] = dFa[v];
-            } else {
-                double u[8];
-                if (node) {
-                    for (int v = 0; v < 8; v++) u[v] = s_ut[it - 1][s][v][i];
-                    flux_to_slab(u);
-                }
-                __syncthreads();
-                if (node) deriv_from_slab(A[s]);
-                __syncthreads();
-            }
-        }
-        if (node)
-            for (int t = 0; t < E; t++)
-                for (int v = 0; v < 8; v++) {
-                    double u = Ua[v] - G.R[t * T::M] * dFa[v];
-                    for (int s = 0; s < E; s++) u -= G.R[t * T::M + s + 1] * A[s][v];
-                    s_ut[it][t][v][i] = u;
-                }
-        __syncthreads();
+        mapped_flux<double>(Ua, iJ, met, gam, F);
+        put_flux<L::SN, double>(sf, i, i1, i2, F);
     }
-    // ---- traces reversed: gradients of the time-averaged state and flux at this node
-    double gaU[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gaF[3][8];
-    for (int d = 0; d < 3; d++)
-        for (int v = 0; v < 8; v++) gaF[d][v] = 0.0;
-    if (node) {
+    __syncthreads();
+    deriv_rows<P, L::SN, ZS, ZPW, double>(s_f, lane);
+    __syncthreads();
+    if (active) get_deriv<L::SN, double>(sf, i, i1, i2, dFa);
+    __syncthreads();
+    // the first sweep from the constant guess: Ut_t = Ua - (R0_t + sum_s R_ts) dFa
+    double cR[E];
+#pragma unroll
+    for (int t = 0; t < E; t++) {
+        double acc = G.R[t * M];
+#pragma unroll
+        for (int s = 0; s < E; s++) acc += G.R[t * M + s + 1];
+        cR[t] = npic > 0 ? acc : 0.0;
+    }
+    double Ut[E][8];
+#pragma unroll
+    for (int t = 0; t < E; t++)
+#pragma unroll
+        for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - cR[t] * dFa[v];
+    for (int it = 2; it <= npic; it++) picard_sweep<P>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
+
+    // ---- traces reversed: gradients of the node's time-averaged state and flux
+    double gaU[8], gaF[3][8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) gaU[v] = gaF[0][v] = gaF[1][v] = gaF[2][v] = 0.0;
+    if (active) {
+#pragma unroll 1
         for (int lf = 0; lf < 6; lf++) {
             int kk = -1;
             for (int j = 0; j < T::NFN; j++)
                 if (G.fnode[lf * T::NFN + j] == i) kk = j;
             if (kk < 0) continue;
+            // faces outside the flux stage's range carry no gradient
+            if (lf >= 4 ? (k + lf - 4 < G.g || k + lf - 4 > G.g + G.Nr) : (k < G.g || k > G.g + G.Nr - 1)) continue;
             i64 fid;
             int side;
             const double *nrm;
@@ -346,22 +417,32 @@ __global__ __launch_bounds__(64) void adj_predictor(DevGeom G, double dt, double
                 perm = G.col_perm + ((i64)c * 4 + lf) * T::Q;
             }
             const double *go = gftr + (fid * 2 + side) * T::Q * 16;
+#pragma unroll 1
             for (int q = 0; q < T::Q; q++) {
                 const int qc = perm ? perm[q] : q;
                 const double w = G.fintc[kk * T::Q + q];
                 const double *n = nrm + qc * 3;
+                const double *gq = go + qc * 16;
+#pragma unroll
                 for (int v = 0; v < 8; v++) {
-                    gaU[v] += w * go[qc * 16 + v];
-                    const double gn = w * go[qc * 16 + 8 + v];
-                    for (int d = 0; d < 3; d++) gaF[d][v] += gn * n[d];
+                    gaU[v] += w * gq[v];
+                    const double gn = w * gq[8 + v];
+                    gaF[0][v] += gn * n[0];
+                    gaF[1][v] += gn * n[1];
+                    gaF[2][v] += gn * n[2];
                 }
             }
         }
+#pragma unroll 1
         for (int le = 0; le < 12; le++) {
             int kk = -1;
             for (int j = 0; j < T::NEN; j++)
                 if (G.enode[le * T::NEN + j] == i) kk = j;
             if (kk < 0) continue;
+            // edges outside the EMF stage's range carry no gradient
+            if (le < 8 ? (k + LocalEdges::UP[le] < G.g || k + LocalEdges::UP[le] > G.g + G.Nr)
+                       : (k < G.g || k > G.g + G.Nr - 1))
+                continue;
             const int rev = G.col_rev[(i64)c * 12 + le], slot = G.col_slot[(i64)c * 12 + le];
             i64 e;
             if (le < 8) {
@@ -374,6 +455,7 @@ __global__ __launch_bounds__(64) void adj_predictor(DevGeom G, double dt, double
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
                 const double w = G.eintc[kk * 3 + p];
+#pragma unroll
                 for (int v = 0; v < 8; v++) gaU[v] += w * go[pc * 11 + v];
                 gaF[2][6] += w * go[pc * 11 + 8];   // E_x = H[B_y]
                 gaF[0][7] += w * go[pc * 11 + 9];   // E_y = F[B_z]
@@ -381,164 +463,177 @@ __global__ __launch_bounds__(64) void adj_predictor(DevGeom G, double dt, double
             }
         }
     }
-    // ---- time averages reversed
-    double gUt[E][8];
-    if (node)
-        for (int t = 0; t < E; t++) {
-            const double wt = G.wt[t + 1];
-            double w[8];
-            for (int v = 0; v < 8; v++) w[v] = s_ut[npic][t][v][i] * iJ;
-            for (int cmp = 0; cmp < 8; cmp++) {
-                dual wd[8], F[3][8];
-                for (int v = 0; v < 8; v++) wd[v] = dual(w[v], v == cmp ? 1.0 : 0.0);
-                dev_flux<dual>(wd, dual(gam), F);
-                double s = gaU[cmp];
-                for (int d = 0; d < 3; d++)
-                    for (int v = 0; v < 8; v++) s += F[d][v].d * gaF[d][v];
-                gUt[t][cmp] = wt * s * iJ;
-            }
-        }
-    // ---- Picard sweeps reversed
-    double gUa[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gdFa[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int it = npic; it >= 1; it--) {
-        if (node)
-            for (int t = 0; t < E; t++)
-                for (int v = 0; v < 8; v++) {
-                    gUa[v] += gUt[t][v];
-                    gdFa[v] -= G.R[t * T::M] * gUt[t][v];
-                }
-        double gprev[E][8];
-        for (int s = 0; s < E; s++)
-            for (int v = 0; v < 8; v++) gprev[s][v] = 0.0;
-        for (int s = 0; s < E; s++) {
-            double gA[8];
-            for (int v = 0; v < 8; v++) {
-                gA[v] = 0.0;
-                for (int t = 0; t < E; t++) gA[v] -= G.R[t * T::M + s + 1] * gUt[t][v];
-            }
-            if (it == 1) {
-                // the first sweep's derivatives are the tau = 0 ones
-                for (int v = 0; v < 8; v++) gdFa[v] += gA[v];
-                continue;
-            }
-            // A_s = D F(Ut_{it-1}[s]): transpose D through the slab
-            if (node)
-                for (int v = 0; v < 8; v++) s_a[0][v][i] = gA[v];
-            __syncthreads();
-            double gF[3][8];
-            if (node)
-                for (int d = 0; d < 3; d++)
-                    for (int v = 0; v < 8; v++) {
-                        double acc = 0.0;
-                        for (int r = 0; r < N; r++) {
-                            const double w = D[((i64)d * N + r) * N + i];
-                            if (w != 0.0) acc += w * s_a[0][v][r];
-                        }
-                        gF[d][v] = acc;
-                    }
-            __syncthreads();
-            if (node) {
-                double u[8];
-                for (int v = 0; v < 8; v++) u[v] = s_ut[it - 1][s][v][i];
-                for (int cmp = 0; cmp < 8; cmp++) {
-                    dual ud[8], F[3][8], metd[9];
-                    for (int v = 0; v < 8; v++) ud[v] = dual(u[v], v == cmp ? 1.0 : 0.0);
-                    for (int m = 0; m < 9; m++) metd[m] = dual(met[m]);
-                    mapped_flux<dual>(ud, dual(iJ), metd, dual(gam), F);
-                    double acc = 0.0;
-                    for (int d = 0; d < 3; d++)
-                        for (int v = 0; v < 8; v++) acc += F[d][v].d * gF[d][v];
-                    gprev[s][cmp] += acc;
-                }
-            }
-        }
-        for (int t = 0; t < E; t++)
-            for (int v = 0; v < 8; v++) gUt[t][v] = gprev[t][v];
+    // ---- time averages reversed: gX_t = wt_t / J (gaU + (dF/dw)^T gaF) at w = Ut_t / J
+    double gX[E][8];
+#pragma unroll
+    for (int t = 0; t < E; t++) {
+        double w[8], gw[8];
+        const double wt = G.wt[t + 1];
+#pragma unroll
+        for (int v = 0; v < 8; v++) { w[v] = active ? Ut[t][v] * iJ : (v == 0 ? 1.0 : 0.0); gw[v] = gaU[v]; }
+        if (active) flux_vjp(w, gam, gaF, gw);
+#pragma unroll
+        for (int v = 0; v < 8; v++) gX[t][v] = wt * iJ * gw[v];
     }
-    if (npic == 0 && node)
+    // ---- Picard sweeps reversed, last first
+    double gUa[8], gdFa[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) gUa[v] = gdFa[v] = 0.0;
+    for (int it = npic; it >= 2; it--) {
+        // the states this sweep started from
+#pragma unroll
         for (int t = 0; t < E; t++)
-            for (int v = 0; v < 8; v++) gUa[v] += gUt[t][v];
-    // ---- tau = 0 derivative reversed: dFa = D F(Ua)
-    if (node)
-        for (int v = 0; v < 8; v++) s_a[0][v][i] = gdFa[v];
-    __syncthreads();
-    if (node) {
-        double gF[3][8];
-        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - cR[t] * dFa[v];
+        for (int r = 2; r < it; r++) picard_sweep<P>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
+#pragma unroll
+        for (int t = 0; t < E; t++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                gUa[v] += gX[t][v];
+                gdFa[v] -= G.R[t * M] * gX[t][v];
+            }
+        // A_s = D F(Ut_s): the gradient of each level's start state; it
+        // replaces that state in Ut (no longer needed) and becomes gX
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+            double gA[8], gF[3][8], gu[8];
+#pragma unroll
             for (int v = 0; v < 8; v++) {
                 double acc = 0.0;
-                for (int r = 0; r < N; r++) {
-                    const double w = D[((i64)d * N + r) * N + i];
-                    if (w != 0.0) acc += w * s_a[0][v][r];
-                }
-                gF[d][v] = acc;
+#pragma unroll
+                for (int t = 0; t < E; t++) acc -= G.R[t * M + s + 1] * gX[t][v];
+                gA[v] = acc;
+                gu[v] = 0.0;
             }
-        for (int cmp = 0; cmp < 8; cmp++) {
-            dual ud[8], F[3][8], metd[9];
-            for (int v = 0; v < 8; v++) ud[v] = dual(Ua[v], v == cmp ? 1.0 : 0.0);
-            for (int m = 0; m < 9; m++) metd[m] = dual(met[m]);
-            mapped_flux<dual>(ud, dual(iJ), metd, dual(gam), F);
-            double acc = 0.0;
-            for (int d = 0; d < 3; d++)
-                for (int v = 0; v < 8; v++) acc += F[d][v].d * gF[d][v];
-            gUa[cmp] += acc;
+            deriv_transpose<P>(s_f, sf, lane, i, i1, i2, active, gA, gF);
+            if (active) mapped_flux_vjp(Ut[s], iJ, met, gam, gF, gu);
+#pragma unroll
+            for (int v = 0; v < 8; v++) Ut[s][v] = gu[v];
         }
+#pragma unroll
+        for (int t = 0; t < E; t++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) gX[t][v] = Ut[t][v];
     }
-    __syncthreads();
+    // first sweep (or none): Ut_t = Ua - cR_t dFa
+#pragma unroll
+    for (int t = 0; t < E; t++)
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            gUa[v] += gX[t][v];
+            gdFa[v] -= cR[t] * gX[t][v];
+        }
+    // ---- tau = 0 derivative reversed: dFa = D F(Ua)
+    {
+        double gF[3][8];
+        deriv_transpose<P>(s_f, sf, lane, i, i1, i2, active, gdFa, gF);
+        if (active) mapped_flux_vjp(Ua, iJ, met, gam, gF, gUa);
+    }
     // ---- nodal initial state reversed: Ua = J (fluid polynomial | divergence-free B)
-    if (node) {
+    double *s_red = s_f;   // [ZPW][5][N], free once the slab is idle
+    if (active) {
+#pragma unroll
         for (int v = 0; v < 8; v++) gUa[v] *= J;
-        for (int v = 5; v < 8; v++) gbnode[zt * (3 * N) + (v - 5) * N + i] = gUa[v];
-        for (int v = 0; v < 5; v++) s_red[v][i] = gUa[v];
+        for (int v = 5; v < 8; v++) gbnode[(i64)zt * (3 * N) + (v - 5) * N + i] = gUa[v];
+        for (int v = 0; v < 5; v++) s_red[(zl * 5 + v) * N + i] = gUa[v];
     }
     __syncthreads();
-    for (int j = i; j < 5 * NCF; j += 64) {
-        const int v = j / NCF, a = j % NCF;
+    for (int j = lane; j < ZPW * 5 * NCF; j += 64) {
+        const int zq = j / (5 * NCF), v = (j % (5 * NCF)) / NCF, a = j % NCF;
+        const unsigned ztq = lb * ZPW + zq;
+        if (ztq >= (unsigned)nzr) continue;
+        const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
+        const i64 zq64 = (i64)cq * G.K + kq;
+        const double *r = s_red + (zq * 5 + v) * N;
         double acc = 0.0;
         if (a == 0) {
-            for (int n = 0; n < N; n++) acc += s_red[v][n];
-            gUo[(i64)v * G.Z + z] += acc;
+            for (int n = 0; n < N; n++) acc += r[n];
+            gUo[(i64)v * G.Z + zq64] += acc;
         } else {
-            const double *Ev = G.Ev + ((i64)c * T::NC + a - 1) * N;
-            for (int n = 0; n < N; n++) acc += Ev[n] * s_red[v][n];
-            gwc[((i64)v * T::NC + a - 1) * G.Z + z] = acc;
+            const double *Ev = G.Ev + ((i64)cq * T::NC + a - 1) * N;
+            for (int n = 0; n < N; n++) acc += Ev[n] * r[n];
+            gwc[((i64)v * T::NC + a - 1) * G.Z + zq64] = acc;
         }
     }
 }
 
 // ---------------------------------------------------------------- divergence-free B map
-// gIn = Mb gOut per zone (Mb stored input-major, output fastest): writes the
-// zone's share of the gradient of its inputs -- B means and WENO B
+// MbA[c][r][j] = Mb[c][j][r]: the column's map with outputs outermost, so that
+// the transposed product reads it like the step reads Mb
+__global__ void transpose_map(const double *__restrict__ Mb, double *__restrict__ MbA, i64 ncol, int nin, int nout)
+{
+    const i64 n = ncol * nin * nout;
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const i64 c = t / ((i64)nin * nout);
+        const int rem = (int)(t % ((i64)nin * nout)), j = rem / nout, r = rem % nout;
+        MbA[(c * nout + r) * nin + j] = Mb[t];
+    }
+}
+
+// gIn = Mb gOut per zone, on the FP64 matrix cores as in the step's map: one
+// wavefront owns 16 zones of a column and all input rows, stepping through
+// the outputs four at a time (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4).
+// Writes the zone's share of the gradient of its inputs: B means and WENO B
 // coefficients (zone owned), and per local face the limited nodal values and
-// the face mean (gathered per face afterwards).
+// the face mean, gside[(lf Q + q) or (6 Q + lf)][zr], gathered per face
+// afterwards.
 template <int P>
-__global__ void adj_bmap(DevGeom G, const double *__restrict__ gbnode, const double *__restrict__ gzoneB,
-                         double *__restrict__ gUo, double *__restrict__ gwc, double *__restrict__ gside)
+__global__ __launch_bounds__(64) void adj_bmap(DevGeom G, const double *__restrict__ MbA,
+                                               const double *__restrict__ gbnode, const double *__restrict__ gzoneB,
+                                               double *__restrict__ gUo, double *__restrict__ gwc,
+                                               double *__restrict__ gside)
 {
     using T = Tr<P>;
-    constexpr int NIN = T::NIN, NOUT = T::NOUTB, NA = 3 * (T::NC + 1), NQ = NA + 6 * T::Q;
-    const int KR = G.Nr + 2;
-    const i64 zr = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (zr >= (i64)G.ncol * KR) return;
-    const int c = (int)(zr / KR), k = G.g - 1 + (int)(zr % KR);
+    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = (NOUT + 3) / 4, MT = (NIN + 15) / 16;
+    constexpr int NA = 3 * (T::NC + 1), N3 = 3 * T::N;
+    const int KR = G.Nr + 2, nt = (KR + 15) / 16;
+    const i64 nzr = (i64)G.ncol * KR;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = lb / nt, tile = lb % nt;
+    const int l = threadIdx.x, g = l >> 4, jz = l & 15;
+    const int kk = tile * 16 + jz;
+    const bool active = kk < KR;
+    const int k = G.g - 1 + (active ? kk : 0);
     const i64 z = (i64)c * G.K + k;
+    const i64 zr = (i64)c * KR + (active ? kk : 0);
     const bool interior = k >= G.g && k < G.g + G.Nr;
-    double gout[NOUT];
-    for (int r = 0; r < 3 * T::N; r++) gout[r] = gbnode[zr * (3 * T::N) + r];
-    for (int r = 0; r < 3; r++) gout[3 * T::N + r] = interior ? gzoneB[(i64)r * G.Z + z] : 0.0;
-    const double *Mb = G.Mb + (i64)c * NIN * NOUT;
-    for (int j = 0; j < NIN; j++) {
-        double acc = 0.0;
-        for (int r = 0; r < NOUT; r++) acc += Mb[(i64)j * NOUT + r] * gout[r];
-        if (j < NA) {
-            const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
-            if (a == 0) gUo[(i64)(5 + comp) * G.Z + z] += acc;
-            else gwc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z] = acc;
-        } else {
-            gside[zr * (NIN - NA) + (j - NA)] = acc;   // [6][Q] nodal values, then [6] face means
+    const double *M = MbA + (i64)c * NOUT * NIN;
+    dbl4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; m++) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int s = 0; s < KT; s++) {
+        // B operand: output gradient r = 4s + g of zone jz
+        const int r = 4 * s + g;
+        double b = 0.0;
+        if (active && r < NOUT)
+            b = r < N3 ? gbnode[zr * N3 + r] : (interior ? gzoneB[(i64)(r - N3) * G.Z + z] : 0.0);
+        const double *mrow = M + (i64)(r < NOUT ? r : 0) * NIN;
+#pragma unroll
+        for (int m = 0; m < MT; m++) {
+            const int j = m * 16 + jz;
+            const double a = (r < NOUT && (m < MT - 1 || j < NIN)) ? mrow[j] : 0.0;
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
         }
     }
-    (void)NQ;
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < MT; m++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int j = m * 16 + g + 4 * v;
+            if (j >= NIN) continue;
+            const double x = acc[m][v];
+            if (j < NA) {
+                const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+                if (a == 0) gUo[(i64)(5 + comp) * G.Z + z] += x;
+                else gwc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z] = x;
+            } else {
+                gside[(i64)(j - NA) * nzr + zr] = x;
+            }
+        }
 }
 
 // per face of the face-nodal set: sum the two zones' shares from adj_bmap
@@ -547,7 +642,6 @@ __global__ void adj_face_gather_bmap(DevGeom G, const double *__restrict__ gside
                                      double *__restrict__ gBo)
 {
     using T = Tr<P>;
-    constexpr int NIS = T::NIN - 3 * (T::NC + 1);   // 6Q + 6
     const int nrad = G.Nr + 3, nang = G.Nr + 2, KR = G.Nr + 2;
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const i64 nR = (i64)G.ncol * nrad;
@@ -568,21 +662,22 @@ __global__ void adj_face_gather_bmap(DevGeom G, const double *__restrict__ gside
             lf[s] = G.ae_lf[2 * ae + s];
         }
     }
+    const i64 nzr = (i64)G.ncol * KR;
     for (int q = 0; q < T::Q; q++) {
         double acc = 0.0;
         for (int s = 0; s < 2; s++)
-            if (zr[s] >= 0) acc += gside[zr[s] * NIS + lf[s] * T::Q + q];
+            if (zr[s] >= 0) acc += gside[(i64)(lf[s] * T::Q + q) * nzr + zr[s]];
         gbnod[(i64)q * G.NF + f] = acc;
     }
     double acc = 0.0;
     for (int s = 0; s < 2; s++)
-        if (zr[s] >= 0) acc += gside[zr[s] * NIS + 6 * T::Q + lf[s]];
+        if (zr[s] >= 0) acc += gside[(i64)(6 * T::Q + lf[s]) * nzr + zr[s]];
     gBo[f] += acc;
 }
 
 // ---------------------------------------------------------------- face nodal B
 // Reverse of MinMod + mean restore on one face; the two sides' shares (B mean
-// and WENO B coefficients of each side's zone) go to gsb[f][side][3 + 3 NC].
+// and WENO B coefficients of each side's zone) go to gsb[side][3 + 3 NC][f].
 template <int P>
 __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const double *__restrict__ Bo,
                                 const double *__restrict__ wc, const double *__restrict__ gbnod,
@@ -625,16 +720,18 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
     double d[2][T::Q];
     for (int s = 0; s < 2; s++) {
         if (!have[s]) continue;
-        for (int q = 0; q < T::Q; q++) {
-            double B[3];
-            for (int c3 = 0; c3 < 3; c3++) {
-                double b = Uo[(5 + c3) * G.Z + z[s]];
-                for (int a = 0; a < T::NC; a++)
-                    b += wc[((i64)(5 + c3) * T::NC + a) * G.Z + z[s]] * fev[s][q * T::NC + a];
-                B[c3] = b;
+        // the step's sum order: component mean, then the coefficients in turn
+        double Bq[3][T::Q];
+        for (int c3 = 0; c3 < 3; c3++) {
+            const double m0 = Uo[(5 + c3) * G.Z + z[s]];
+            for (int q = 0; q < T::Q; q++) Bq[c3][q] = m0;
+            for (int a = 0; a < T::NC; a++) {
+                const double ca = wc[((i64)(5 + c3) * T::NC + a) * G.Z + z[s]];
+                for (int q = 0; q < T::Q; q++) Bq[c3][q] += ca * fev[s][q * T::NC + a];
             }
-            d[s][q] = B[0] * nrm[q * 3] + B[1] * nrm[q * 3 + 1] + B[2] * nrm[q * 3 + 2] - mean;
         }
+        for (int q = 0; q < T::Q; q++)
+            d[s][q] = Bq[0][q] * nrm[q * 3] + Bq[1][q] * nrm[q * 3 + 1] + Bq[2][q] * nrm[q * 3 + 2] - mean;
     }
     for (int q = 0; q < T::Q; q++) {
         if (!have[0]) d[0][q] = d[1][q];
@@ -661,20 +758,23 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
         if (!have[1]) { gd[0][q] += gd[1][q]; gd[1][q] = 0.0; }
     }
     for (int s = 0; s < 2; s++) {
-        double *o = gsb + (f * 2 + s) * NSB;
+        double *o = gsb + (i64)s * NSB * G.NF + f;
         if (!have[s]) {
-            for (int j = 0; j < NSB; j++) o[j] = 0.0;
+            for (int j = 0; j < NSB; j++) o[(i64)j * G.NF] = 0.0;
             continue;
         }
         for (int q = 0; q < T::Q; q++) gmean -= gd[s][q];
         for (int c3 = 0; c3 < 3; c3++) {
-            double gm0 = 0.0;
-            for (int q = 0; q < T::Q; q++) gm0 += gd[s][q] * nrm[q * 3 + c3];
-            o[c3] = gm0;
+            double gq[T::Q], gm0 = 0.0;
+            for (int q = 0; q < T::Q; q++) {
+                gq[q] = gd[s][q] * nrm[q * 3 + c3];
+                gm0 += gq[q];
+            }
+            o[(i64)c3 * G.NF] = gm0;
             for (int a = 0; a < T::NC; a++) {
                 double acc = 0.0;
-                for (int q = 0; q < T::Q; q++) acc += gd[s][q] * nrm[q * 3 + c3] * fev[s][q * T::NC + a];
-                o[3 + c3 * T::NC + a] = acc;
+                for (int q = 0; q < T::Q; q++) acc += gq[q] * fev[s][q * T::NC + a];
+                o[(i64)(3 + c3 * T::NC + a) * G.NF] = acc;
             }
         }
     }
@@ -705,53 +805,71 @@ __global__ void adj_zone_gather_bnodal(DevGeom G, const double *__restrict__ gsb
     sd[5] = 0;
     for (int c3 = 0; c3 < 3; c3++) {
         double acc = 0.0;
-        for (int lf = 0; lf < 6; lf++) acc += gsb[(f[lf] * 2 + sd[lf]) * NSB + c3];
+        for (int lf = 0; lf < 6; lf++) acc += gsb[((i64)sd[lf] * NSB + c3) * G.NF + f[lf]];
         gUo[(i64)(5 + c3) * G.Z + z] += acc;
         for (int a = 0; a < T::NC; a++) {
             double s = 0.0;
-            for (int lf = 0; lf < 6; lf++) s += gsb[(f[lf] * 2 + sd[lf]) * NSB + 3 + c3 * T::NC + a];
+            for (int lf = 0; lf < 6; lf++) s += gsb[((i64)sd[lf] * NSB + 3 + c3 * T::NC + a) * G.NF + f[lf]];
             gwc[((i64)(5 + c3) * T::NC + a) * G.Z + z] += s;
         }
     }
 }
 
 // ---------------------------------------------------------------- WENO-AO
-// gdu[v][j][zr] = d(coefficients)/d(du_j)^T gwc, exact through the nonlinear
-// weights (one tangent pass per stencil member)
+// gdu[v][j][zr] = d(coefficients)/d(du_j)^T gwc for variable v of
+// reconstructed zone zr, exact through the nonlinear weights.  The step's
+// layout: one wavefront per run of up to 64 shells of a column (the column's
+// matrices uniform, read as scalars), a short tail as (shell, variable) lanes.
 template <int P>
-__global__ void adj_weno(DevGeom G, const double *__restrict__ Uo, const double *__restrict__ gwc,
-                         double *__restrict__ gdu)
+__device__ __forceinline__ void weno_var_vjp(const DevGeom &G, const double *__restrict__ U,
+                                             const double *__restrict__ gwc, double *__restrict__ gdu,
+                                             const double *__restrict__ Pl, const double *__restrict__ Ps,
+                                             const double *__restrict__ Qs, int c, int k, int v)
 {
     using T = Tr<P>;
     const int KR = G.Nr + 2;
-    const i64 nzr = (i64)G.ncol * KR;
-    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nzr * 8) return;
-    const int v = (int)(t / nzr);
-    const i64 zr = t % nzr;
-    const int c = (int)(zr / KR), k = G.g - 1 + (int)(zr % KR);
+    const i64 nzr = (i64)G.ncol * KR, zr = (i64)c * KR + (k - (G.g - 1));
     const i64 z = (i64)c * G.K + k;
-    const double *Pl = G.Pl + (i64)c * T::NC * T::NS, *Ps = G.Ps + (i64)c * 7 * 18, *Qs = G.Qs + (i64)c * T::NC * T::NC;
-    const double *Uv = Uo + (i64)v * G.Z;
+    const double *Uv = U + (i64)v * G.Z;
     const double u0 = Uv[z];
     double du[T::NS], go[T::NC];
-    bool used[T::NS];
+#pragma unroll
     for (int j = 0; j < T::NS; j++) {
         const int m = G.stm[(i64)c * T::NS + j];
-        used[j] = m >= 0;
         const int dz = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
         du[j] = Uv[z + dz] - u0;
     }
+#pragma unroll
     for (int a = 0; a < T::NC; a++) go[a] = gwc[((i64)v * T::NC + a) * G.Z + z];
-    for (int j = 0; j < T::NS; j++) {
-        double g = 0.0;
-        if (used[j]) {
-            dual dd[T::NS], o[T::NC];
-            for (int jj = 0; jj < T::NS; jj++) dd[jj] = dual(du[jj], jj == j ? 1.0 : 0.0);
-            weno_core<P, dual, double>(dd, Pl, Ps, Qs, o);
-            for (int a = 0; a < T::NC; a++) g += o[a].d * go[a];
+    double *o = gdu + (i64)v * T::NS * nzr + zr;
+    const int *stm = G.stm + (i64)c * T::NS;
+    weno_core_vjp<P>(du, Pl, Ps, Qs, go, [&](int j, double g) { o[(i64)j * nzr] = stm[j] >= 0 ? g : 0.0; });
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void adj_weno(DevGeom G, const double *__restrict__ U, const double *__restrict__ gwc,
+                                               double *__restrict__ gdu, int nchunk, int nu, int nleft)
+{
+    using T = Tr<P>;
+    const int per = nchunk + (nleft > 0);
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = lb / per, ch = lb % per;
+    const double *__restrict__ Pl = G.Pl + (i64)c * T::NC * T::NS;
+    const double *__restrict__ Ps = G.Ps + (i64)c * 7 * 18;
+    const double *__restrict__ Qs = G.Qs + (i64)c * T::NC * T::NC;
+    if (ch < nchunk) {
+        const int kk = ch * 64 + threadIdx.x;
+        if (kk >= nu) return;
+#pragma unroll 1
+        for (int v = 0; v < 8; v++) {
+            int vo = 0;
+            __asm__ __volatile__("" : "+s"(vo));
+            weno_var_vjp<P>(G, U, gwc, gdu, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
         }
-        gdu[((i64)v * T::NS + j) * nzr + zr] = g;
+    } else {
+        const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
+        if (kk >= nu + nleft) return;
+        weno_var_vjp<P>(G, U, gwc, gdu, Pl, Ps, Qs, c, G.g - 1 + kk, v);
     }
 }
 
@@ -865,33 +983,21 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     using T = Tr<P>;
     AdjBuffers &A = g->adj;
     const int npic = prm.n_picard > 0 ? prm.n_picard : P;
-    if (npic > ADJ_MAX_PICARD) {
-        set_error("the adjoint supports at most " + std::to_string(ADJ_MAX_PICARD) + " Picard sweeps");
-        return RG_ENOTSUP;
-    }
     const double dt = prm.dt, gam = prm.gamma;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
-    // forward step into scratch outputs: refreshes the step's work buffers
-    // (WENO coefficients, face nodal B, nodal B, traces) at this state
-    rg_step_params fp = prm;
-    rg_status s = launch_step(g, fp, U, Bf, A.Utmp, A.Btmp, st);
+    // the step's stages up to the predictor, at this state: the boundary-filled
+    // working state, WENO coefficients, face nodal B, nodal B and traces
+    rg_status s = launch_step_front(g, prm, U, Bf, A.Ubc, A.Bbc, st);
     if (s != RG_OK) return s;
-    // the boundary-filled working state the step started from
-    s = launch_bc(g, prm.bc_kind, U, Bf, A.Ubc, A.Bbc, st);
-    if (s != RG_OK) return s;
-    const unsigned zb = 2048;
-    fill_zero<<<zb, 256, 0, st>>>(A.gUo, 8 * G.Z);
-    fill_zero<<<zb, 256, 0, st>>>(A.gBo, G.NF);
-    fill_zero<<<zb, 256, 0, st>>>(A.gzoneB, 3 * G.Z);
-    fill_zero<<<zb, 256, 0, st>>>(A.gwc, 8 * (i64)T::NC * G.Z);
-    fill_zero<<<zb, 256, 0, st>>>(A.gftr, (i64)16 * T::Q * 2 * G.NF);
-    fill_zero<<<zb, 256, 0, st>>>(A.getr, (i64)11 * 3 * 4 * G.NE);
-    fill_zero<<<zb, 256, 0, st>>>(A.gGam, G.NE);
-    fill_zero<<<zb, 256, 0, st>>>(A.gbnod, (i64)T::Q * G.NF);
-    RG_ADJ_CHECK();
-    // CT and update
-    copy_state<<<zb, 256, 0, st>>>(gBf1, A.gBo, G.NF);
+    if (!A.map_ready) {
+        transpose_map<<<2048, 256, 0, st>>>(G.Mb, A.MbA, (i64)G.ncol, T::NIN, T::NOUTB);
+        RG_ADJ_CHECK();
+        A.map_ready = true;
+    }
+    // CT and update (every entry of gBo, gGam, gPhi, gUo and the interior
+    // entries of gzoneB are written here)
+    copy_state<<<2048, 256, 0, st>>>(gBf1, A.gBo, G.NF);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     adj_ct<<<nblk(nee, 256), 256, 0, st>>>(G, dt, gBf1, A.gGam);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
@@ -899,22 +1005,26 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     adj_update_zones<<<nblk(G.Z, 256), 256, 0, st>>>(G, gU1, A.gUo, A.gzoneB);
     RG_ADJ_CHECK();
     // Riemann solvers
-    adj_face_flux<P><<<nblk(nff, 128), 128, 0, st>>>(G, gam, g->ftr, A.gPhi, A.gftr);
-    adj_edge_emf<<<nblk(nee, 128), 128, 0, st>>>(G, gam, g->etr, A.gGam, A.getr);
+    adj_face_flux<P><<<nblk(nff, 256), 256, 0, st>>>(G, gam, g->ftr, A.gPhi, A.gftr);
+    adj_edge_emf<<<nblk(nee, 256), 256, 0, st>>>(G, gam, g->etr, A.gGam, A.getr);
     RG_ADJ_CHECK();
     // predictor
-    adj_predictor<P><<<(unsigned)nzr, 64, 0, st>>>(G, dt, gam, npic, A.Ubc, g->wcoef, g->bnode, A.gftr, A.getr,
-                                                    A.gUo, A.gwc, A.gbnode);
+    constexpr int ZPW = PredLayout<P>::ZPW;
+    adj_predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, A.Ubc, g->wcoef, g->bnode,
+                                                                       A.gftr, A.getr, A.gUo, A.gwc, A.gbnode);
     RG_ADJ_CHECK();
     // divergence-free map, then face nodal B
-    adj_bmap<P><<<nblk(nzr, 128), 128, 0, st>>>(G, A.gbnode, A.gzoneB, A.gUo, A.gwc, A.gside);
+    const int ntile = (G.Nr + 2 + 15) / 16;
+    adj_bmap<P><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, A.MbA, A.gbnode, A.gzoneB, A.gUo, A.gwc, A.gside);
     const i64 nbn = (i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2);
     adj_face_gather_bmap<P><<<nblk(nbn, 256), 256, 0, st>>>(G, A.gside, A.gbnod, A.gBo);
     adj_face_bnodal<P><<<nblk(nbn, 128), 128, 0, st>>>(G, A.Ubc, A.Bbc, g->wcoef, A.gbnod, A.gBo, A.gsb);
     adj_zone_gather_bnodal<P><<<nblk(nzr, 256), 256, 0, st>>>(G, A.gsb, A.gUo, A.gwc);
     RG_ADJ_CHECK();
     // WENO-AO
-    adj_weno<P><<<nblk(nzr * 8, 64), 64, 0, st>>>(G, A.Ubc, A.gwc, A.gdu);
+    const RunSplit wr = run_split(G.Nr + 2);
+    adj_weno<P><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(G, A.Ubc, A.gwc, A.gdu,
+                                                                                      wr.nchunk, wr.nu, wr.nleft);
     adj_weno_gather<P><<<nblk(G.Z, 256), 256, 0, st>>>(G, A.gdu, A.gUo);
     RG_ADJ_CHECK();
     // boundary fill

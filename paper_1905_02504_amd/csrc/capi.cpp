@@ -77,6 +77,11 @@ bool check_dtab_order(const RefEl &r)
     const int N = r.N;
     std::vector<double> D0((size_t)N * N, 0.0);
     for (int e = 0; e < D::NNZ; e++) D0[(size_t)D::E[e][0] * N + D::E[e][1]] = 0.5 * D::E[e][2];
+    // the transposed table holds the same entries, indexed (column, row), in row order
+    for (int e = 0; e < D::NNZ; e++) {
+        if (D0[(size_t)D::ET[e][1] * N + D::ET[e][0]] != 0.5 * D::ET[e][2]) return false;
+        if (e > 0 && D::ET[e][0] < D::ET[e - 1][0]) return false;
+    }
     for (int d = 0; d < 3; d++)
         for (int i = 0; i < N; i++)
             for (int l = 0; l < N; l++) {
@@ -437,8 +442,8 @@ bool alloc_adjoint(rg_geom *g)
     const DevGeom &d = g->d;
     const size_t Z = d.Z, NF = d.NF, NE = d.NE, nzr = (size_t)d.ncol * (d.Nr + 2);
     const size_t NA = 3 * (size_t)(d.NC + 1);
-    bool ok = alloc_zero(g, 8 * Z, &A.Utmp) && alloc_zero(g, NF, &A.Btmp) && alloc_zero(g, 8 * Z, &A.Ubc) &&
-              alloc_zero(g, NF, &A.Bbc) && alloc_zero(g, 8 * Z, &A.gUo) && alloc_zero(g, NF, &A.gBo) &&
+    bool ok = alloc_zero(g, 8 * Z, &A.Ubc) && alloc_zero(g, NF, &A.Bbc) &&
+              alloc_zero(g, (size_t)d.ncol * d.NIN * d.NOUTB, &A.MbA) && alloc_zero(g, 8 * Z, &A.gUo) && alloc_zero(g, NF, &A.gBo) &&
               alloc_zero(g, 3 * Z, &A.gzoneB) && alloc_zero(g, 8 * (size_t)d.NC * Z, &A.gwc) &&
               alloc_zero(g, (size_t)16 * d.Q * 2 * NF, &A.gftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &A.getr) &&
               alloc_zero(g, NE, &A.gGam) && alloc_zero(g, 8 * NF, &A.gPhi) &&

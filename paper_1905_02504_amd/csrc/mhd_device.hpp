@@ -1,9 +1,8 @@
 // Device building blocks shared by the step (step.hip) and its adjoint
 // (adjoint.hip): element traits, ideal-MHD point functions, the Riemann
-// solvers and the WENO-AO combination.  The point functions are templates on
-// the scalar type T: double (or float) for the step, and `dual` (a value with
-// one tangent) for the adjoint, which takes exact local derivatives by
-// forward differentiation of the same code.
+// solvers, the WENO-AO combination and the derivative-matrix slab.  The point
+// functions are templates on the scalar type: double for the FP64 step and
+// the adjoint's recomputation, float for the reduced-precision form.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,47 +35,16 @@ struct LocalEdges {
     static constexpr int CORNER[4] = {0, 1, 3, 2};
 };
 
-// ---------------------------------------------------------------- dual numbers
-struct dual {
-    double v, d;
-    __device__ __forceinline__ dual() : v(0.0), d(0.0) {}
-    __device__ __forceinline__ dual(double x) : v(x), d(0.0) {}
-    __device__ __forceinline__ dual(double x, double t) : v(x), d(t) {}
-};
-__device__ __forceinline__ dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ dual operator-(dual a) { return dual(-a.v, -a.d); }
-__device__ __forceinline__ dual operator*(dual a, dual b) { return dual(a.v * b.v, a.d * b.v + a.v * b.d); }
-__device__ __forceinline__ dual operator/(dual a, dual b)
-{
-    const double q = a.v / b.v;
-    return dual(q, (a.d - q * b.d) / b.v);
-}
-__device__ __forceinline__ dual &operator+=(dual &a, dual b) { return a = a + b; }
-__device__ __forceinline__ dual &operator-=(dual &a, dual b) { return a = a - b; }
-__device__ __forceinline__ dual &operator*=(dual &a, dual b) { return a = a * b; }
-__device__ __forceinline__ bool operator<(dual a, dual b) { return a.v < b.v; }
-__device__ __forceinline__ bool operator>(dual a, dual b) { return a.v > b.v; }
-__device__ __forceinline__ bool operator<=(dual a, dual b) { return a.v <= b.v; }
-__device__ __forceinline__ bool operator>=(dual a, dual b) { return a.v >= b.v; }
-
-// scalar functions with one spelling for every T (the derivative of max/min
-// follows the selected argument, as the step's branch does)
+// scalar functions with one spelling for every T
 __device__ __forceinline__ double ssqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float ssqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ dual ssqrt(dual x)
-{
-    const double r = sqrt(x.v);
-    return dual(r, x.v > 0.0 ? 0.5 * x.d / r : 0.0);
-}
 __device__ __forceinline__ double smax(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ double smin(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float smax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
-__device__ __forceinline__ dual smax(dual a, dual b) { return a.v >= b.v ? a : b; }
-__device__ __forceinline__ dual smin(dual a, dual b) { return a.v <= b.v ? a : b; }
-__device__ __forceinline__ double value(double x) { return x; }
-__device__ __forceinline__ double value(dual x) { return x.v; }
+
+// accumulator of v_mfma_f64_16x16x4f64
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- ideal MHD
 template <class T>
@@ -268,12 +236,85 @@ __device__ __forceinline__ void weno_core(const T (&du)[Tr<P>::NS], const R *__r
     }
 }
 
+// Flux derivatives through the LDS slab.  Node lanes store the flux along
+// direction d of their node at the node's position under the coordinate swap
+// xi <-> d (identity for d = 0), so every one of the 24 (direction, variable)
+// rows holds its values in the xi-derivative's own node order.  One lane per
+// row then applies the xi-derivative matrix D_0, whose sparsity and entries
+// (multiples of 1/2) are compile-time constants, in place: a row is read
+// once into registers and each value is reused by all the outputs that need
+// it.  D_d = S_d D_0 S_d for the swap S_d, so slot i of row (d, v) ends up
+// holding the d-derivative at node S_d(i).
+template <int SN, class R>
+__device__ __forceinline__ void put_flux(R *sf, int i, int i1, int i2, const R (&F)[3][8])
+{
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+        sf[v * SN + i] = F[0][v];
+        sf[(8 + v) * SN + i1] = F[1][v];
+        sf[(16 + v) * SN + i2] = F[2][v];
+    }
+}
+
+// entry e of D_0 (or of D_0^T), field k: row, column, twice the value
+template <int P, bool TRANS>
+__device__ constexpr int dent(int e, int k)
+{
+    return TRANS ? DTab<P>::ET[e][k] : DTab<P>::E[e][k];
+}
+
+// With TRANS the transposed table D_0^T is applied instead: slot S_d(l) of
+// row (d, v) then holds sum_i D_d[i][l] x_i for values x_i stored at S_d(i).
+template <int P, int SN, int ZS, int ZPW, class R, bool TRANS = false>
+__device__ __forceinline__ void deriv_rows(R *slab, int lane)
+{
+    using D = DTab<P>;
+    constexpr int N = Tr<P>::N;
+#pragma unroll 1
+    for (int t = lane; t < ZPW * 24; t += 64) {
+        R *row = slab + (t / 24) * ZS + (t % 24) * SN;
+        R x[N];
+#pragma unroll
+        for (int j = 0; j < N; j++) x[j] = row[j];
+        R acc = R(0);
+#pragma unroll
+        for (int e = 0; e < D::NNZ; e++) {
+            acc += R(0.5 * dent<P, TRANS>(e, 2)) * x[dent<P, TRANS>(e, 1)];
+            if (e == D::NNZ - 1 || dent<P, TRANS>(e + 1, 0) != dent<P, TRANS>(e, 0)) {
+                row[dent<P, TRANS>(e, 0)] = acc;
+                acc = R(0);
+            }
+        }
+    }
+}
+
+// acc = sum over the three directions of the derivative at node i
+template <int SN, class R>
+__device__ __forceinline__ void get_deriv(const R *sf, int i, int i1, int i2, R (&acc)[8])
+{
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] = sf[v * SN + i] + sf[(8 + v) * SN + i1] + sf[(16 + v) * SN + i2];
+}
+
 // geometry table of precision R: the FP64 table or its FP32 copy
 template <class R>
 __device__ __forceinline__ const R *pick(const double *d, const float *f)
 {
     if constexpr (sizeof(R) == sizeof(double)) return d;
     else return f;
+}
+
+// Runs of up to 64 items along a column: n = nu + nleft, the first nu items
+// in nchunk wavefront-sized runs; a short tail (1 to 8 items beyond a
+// multiple of 64) is left to nleft for the kernels' tail mode.
+struct RunSplit {
+    int nchunk, nu, nleft;
+};
+inline RunSplit run_split(int n)
+{
+    const int r = n % 64;
+    if (n >= 64 && r >= 1 && r <= 8) return {n / 64, (n / 64) * 64, r};
+    return {(n + 63) / 64, n, 0};
 }
 
 // Workgroups are dispatched round-robin over the eight XCDs, each with its

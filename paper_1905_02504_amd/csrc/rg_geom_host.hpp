@@ -45,7 +45,10 @@ rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, cons
                       double *Bo, void *stream);
 rg_status profile_end(rg_geom *g, double *ms, int *nsteps);
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt);
-rg_status launch_bc(rg_geom *g, int bc_kind, const double *U, const double *Bf, double *Uo, double *Bo, void *stream);
+// stages 0-4 of the step only (boundary fill into Uo / Bo, reconstruction,
+// divergence-free B, predictor and traces), FP64
+rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,
+                            double *Bo, void *stream);
 rg_status launch_adjoint(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, const double *gU1,
                          const double *gBf1, double *gU, double *gBf, void *stream);
 rg_status launch_diag(rg_geom *g, const double *U, const double *Bf, double gamma, void *stream, rg_diag_out *out);

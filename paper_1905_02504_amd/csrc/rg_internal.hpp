@@ -140,8 +140,8 @@ struct DevGeom {
 
 // Device buffers of the adjoint of the step, allocated on its first call
 struct AdjBuffers {
-    bool ready = false;
-    double *Utmp = nullptr, *Btmp = nullptr, *Ubc = nullptr, *Bbc = nullptr;
+    bool ready = false, map_ready = false;
+    double *Ubc = nullptr, *Bbc = nullptr, *MbA = nullptr;
     double *gUo = nullptr, *gBo = nullptr, *gzoneB = nullptr, *gwc = nullptr, *gftr = nullptr, *getr = nullptr;
     double *gGam = nullptr, *gPhi = nullptr, *gbnode = nullptr, *gbnod = nullptr, *gside = nullptr, *gsb = nullptr;
     double *gdu = nullptr;

@@ -251,7 +251,6 @@ __global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *
 // all output rows, stepping through the inputs four at a time
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int P, class R>
 __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
@@ -311,57 +310,6 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
             if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = R(acc[m][v]);
             else if (r < NOUT) zoneB[(i64)(r - 3 * T::N) * G.Z + z] = acc[m][v];
         }
-}
-
-// Flux derivatives through the LDS slab.  Node lanes store the flux along
-// direction d of their node at the node's position under the coordinate swap
-// xi <-> d (identity for d = 0), so every one of the 24 (direction, variable)
-// rows holds its values in the xi-derivative's own node order.  One lane per
-// row then applies the xi-derivative matrix D_0, whose sparsity and entries
-// (multiples of 1/2) are compile-time constants, in place: a row is read
-// once into registers and each value is reused by all the outputs that need
-// it.  D_d = S_d D_0 S_d for the swap S_d, so slot i of row (d, v) ends up
-// holding the d-derivative at node S_d(i).
-template <int SN, class R>
-__device__ __forceinline__ void put_flux(R *sf, int i, int i1, int i2, const R (&F)[3][8])
-{
-#pragma unroll
-    for (int v = 0; v < 8; v++) {
-        sf[v * SN + i] = F[0][v];
-        sf[(8 + v) * SN + i1] = F[1][v];
-        sf[(16 + v) * SN + i2] = F[2][v];
-    }
-}
-
-template <int P, int SN, int ZS, int ZPW, class R>
-__device__ __forceinline__ void deriv_rows(R *slab, int lane)
-{
-    using D = DTab<P>;
-    constexpr int N = Tr<P>::N;
-#pragma unroll 1
-    for (int t = lane; t < ZPW * 24; t += 64) {
-        R *row = slab + (t / 24) * ZS + (t % 24) * SN;
-        R x[N];
-#pragma unroll
-        for (int j = 0; j < N; j++) x[j] = row[j];
-        R acc = R(0);
-#pragma unroll
-        for (int e = 0; e < D::NNZ; e++) {
-            acc += R(0.5 * D::E[e][2]) * x[D::E[e][1]];
-            if (e == D::NNZ - 1 || D::E[e + 1][0] != D::E[e][0]) {
-                row[D::E[e][0]] = acc;
-                acc = R(0);
-            }
-        }
-    }
-}
-
-// acc = sum over the three directions of the derivative at node i
-template <int SN, class R>
-__device__ __forceinline__ void get_deriv(const R *sf, int i, int i1, int i2, R (&acc)[8])
-{
-#pragma unroll
-    for (int v = 0; v < 8; v++) acc[v] = sf[v * SN + i] + sf[(8 + v) * SN + i1] + sf[(16 + v) * SN + i2];
 }
 
 // ADER-CG predictor (Section V.d).  One wavefront holds 64 / N zones, one lane
@@ -895,19 +843,6 @@ static const R *pick_host(const double *d, const float *f)
     else return f;
 }
 
-// Runs of up to 64 items along a column: n = nu + nleft, the first nu items
-// in nchunk wavefront-sized runs; a short tail (1 to 8 items beyond a
-// multiple of 64) is left to nleft for the kernels' tail mode.
-struct RunSplit {
-    int nchunk, nu, nleft;
-};
-static RunSplit run_split(int n)
-{
-    const int r = n % 64;
-    if (n >= 64 && r >= 1 && r <= 8) return {n / 64, (n / 64) * 64, r};
-    return {(n + 63) / 64, n, 0};
-}
-
 // stage markers for optional per-stage timing (0 bc, 1 weno, 2 face_bnodal,
 // 3 bmap, 4 predictor, 5 face_flux, 6 edge_emf, 7 update)
 struct StageMarks {
@@ -921,7 +856,7 @@ struct StageMarks {
 
 template <int P, class R>
 static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf, double *Uo,
-                            double *Bo, hipStream_t st)
+                            double *Bo, hipStream_t st, bool front_only = false)
 {
     const DevGeom &G = g->d;
     // work buffers hold R values (they are sized for doubles)
@@ -931,7 +866,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     const int npic = prm.n_picard > 0 ? prm.n_picard : P;
     const double dt = prm.dt, gam = prm.gamma;
     StageMarks sm;
-    if (g->prof_on) {
+    if (g->prof_on && !front_only) {
         sm.on = true;
         for (int i = 0; i <= RG_NSTAGE; i++) {
             if (hipEventCreate(&sm.ev[i]) != hipSuccess) { set_error("hipEventCreate failed"); return RG_EDEVICE; }
@@ -964,6 +899,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     sm.mark(4, st);
     predictor<P, R><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, wcoef, bnode, ftr, etr);
     RG_LAUNCH_CHECK();
+    if (front_only) return RG_OK;
     sm.mark(5, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     face_flux<P, R><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, ftr, g->Phi);
@@ -1013,14 +949,18 @@ rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, cons
     return RG_ENOTSUP;
 }
 
-rg_status launch_bc(rg_geom *g, int bc_kind, const double *U, const double *Bf, double *Uo, double *Bo, void *stream)
+rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,
+                            double *Bo, void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const DevGeom &G = g->d;
-    bc_zones<<<nblocks(G.Z, 256), 256, 0, st>>>(G, bc_kind, U, Uo);
-    bc_faces<<<nblocks(G.NF, 256), 256, 0, st>>>(G, bc_kind, Bf, Bo);
-    RG_LAUNCH_CHECK();
-    return RG_OK;
+    if (g->mode != RG_MODE_FP64) {
+        set_error("FP64 geometry required");
+        return RG_ENOTSUP;
+    }
+    if (g->d.order == 3) return step_order<3, double>(g, p, U, Bf, Uo, Bo, st, true);
+    if (g->d.order == 4) return step_order<4, double>(g, p, U, Bf, Uo, Bo, st, true);
+    set_error("unsupported order");
+    return RG_ENOTSUP;
 }
 
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
