@@ -155,6 +155,20 @@ rg_status rg_step(const rg_geom *geom, rg_step_params *params, const double *U, 
 rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *params, const double *U_n, const double *Bf_n,
                           const double *gU_np1, const double *gBf_np1, double *gU_n, double *gBf_n, void *stream);
 
+/* Discrete Stokes map (eqs. 2.5-2.6 without the time step): given line
+ * integrals of a vector potential along every edge, edge_circ[n_edges]
+ * (canonical edge direction), writes the face averages of the normal
+ * component of its curl, Bf[f] = (1/A_f) sum_e s_fe edge_circ[e], for every
+ * face (canonical normal; s_fe = +-1 by the right-hand rule).  The result is
+ * divergence-free to round-off.  Device buffers; asynchronous on `stream`. */
+rg_status rg_stokes(const rg_geom *geom, const double *edge_circ, double *Bf, void *stream);
+
+/* Transpose of rg_stokes: g_edge_circ[e] = sum_f s_fe gBf[f] / A_f over every
+ * face holding edge e (all edges written); turns a gradient with respect to
+ * face B into one with respect to the edge line integrals of the vector
+ * potential.  Device buffers; asynchronous on `stream`. */
+rg_status rg_stokes_T(const rg_geom *geom, const double *gBf, double *g_edge_circ, void *stream);
+
 /* Device copies of the last step's face flux integrals Phi[8][n_faces]
  * (time-integrated over the step divided by dt, canonical normal) and edge
  * electric-field line integrals Gam[n_edges] (canonical direction).  Entries
@@ -214,6 +228,9 @@ rg_status rg_profile_end(rg_geom *geom, double *ms, int32_t *nsteps);
 rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
 
 const char *rg_last_error(void);
+
+/* Name and one-line meaning of a status code (static string). */
+const char *rg_status_str(rg_status status);
 
 #ifdef __cplusplus
 }

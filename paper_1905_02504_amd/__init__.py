@@ -144,6 +144,24 @@ class ShellMHD:
             U, Bf = self.step_ad(U, Bf, dt, gamma=gamma, bc=bc, n_picard=n_picard)
         return U, Bf
 
+    def stokes(self, circ, Bf=None):
+        """rg_stokes: face-averaged normal curl A from edge line integrals of A."""
+        import torch
+        assert circ.is_cuda and circ.dtype == torch.float64 and circ.is_contiguous() and circ.shape == (self.ne,)
+        if Bf is None:
+            Bf = torch.empty(self.nf, dtype=torch.float64, device=circ.device)
+        N.rg_stokes(self._geom, circ.data_ptr(), Bf.data_ptr(), _stream())
+        return Bf
+
+    def stokes_T(self, gBf, gcirc=None):
+        """rg_stokes_T: the transpose of stokes (face-B gradient -> edge gradient)."""
+        import torch
+        assert gBf.is_cuda and gBf.dtype == torch.float64 and gBf.is_contiguous() and gBf.shape == (self.nf,)
+        if gcirc is None:
+            gcirc = torch.empty(self.ne, dtype=torch.float64, device=gBf.device)
+        N.rg_stokes_T(self._geom, gBf.data_ptr(), gcirc.data_ptr(), _stream())
+        return gcirc
+
     def fluxes(self):
         import torch
         Phi = torch.zeros((8, self.nf), dtype=torch.float64, device="cuda")

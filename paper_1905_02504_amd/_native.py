@@ -69,6 +69,10 @@ def lib():
         L.rg_step.argtypes = [_vp, C.POINTER(rg_step_params), _vp, _vp, _vp, _vp, _vp]
         L.rg_step_fluxes.argtypes = [_vp, _vp, _vp, _vp]
         L.rg_step_adjoint.argtypes = [_vp, C.POINTER(rg_step_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.rg_stokes.argtypes = [_vp, _vp, _vp, _vp]
+        L.rg_stokes_T.argtypes = [_vp, _vp, _vp, _vp]
+        L.rg_status_str.argtypes = [C.c_int]
+        L.rg_status_str.restype = C.c_char_p
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
@@ -79,7 +83,7 @@ def lib():
         L.rg_profile_end.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
-                     "rg_step_adjoint", "rg_cfl_dt", "rg_init_alfven", "rg_diag"):
+                     "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_diag"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -87,7 +91,7 @@ def lib():
 
 def check(status: int, what: str):
     if status != RG_OK:
-        raise RGError(f"{what} failed with status {status}: {lib().rg_last_error().decode()}")
+        raise RGError(f"{what} failed ({lib().rg_status_str(status).decode()}): {lib().rg_last_error().decode()}")
 
 
 # ------------------------------------------------------------------ C-ABI names
@@ -145,6 +149,18 @@ def rg_step(geom, params: rg_step_params, U_ptr, Bf_ptr, Uo_ptr, Bfo_ptr, stream
 def rg_step_adjoint(geom, params: rg_step_params, U_ptr, Bf_ptr, gU1_ptr, gBf1_ptr, gU_ptr, gBf_ptr, stream):
     check(lib().rg_step_adjoint(geom, C.byref(params), _vp(U_ptr), _vp(Bf_ptr), _vp(gU1_ptr), _vp(gBf1_ptr),
                                 _vp(gU_ptr), _vp(gBf_ptr), _vp(stream)), "rg_step_adjoint")
+
+
+def rg_stokes(geom, circ_ptr, Bf_ptr, stream):
+    check(lib().rg_stokes(geom, _vp(circ_ptr), _vp(Bf_ptr), _vp(stream)), "rg_stokes")
+
+
+def rg_stokes_T(geom, gBf_ptr, gcirc_ptr, stream):
+    check(lib().rg_stokes_T(geom, _vp(gBf_ptr), _vp(gcirc_ptr), _vp(stream)), "rg_stokes_T")
+
+
+def rg_status_str(status: int) -> str:
+    return lib().rg_status_str(int(status)).decode()
 
 
 def rg_step_fluxes(geom, Phi_ptr, Gam_ptr, stream):

@@ -29,11 +29,15 @@ namespace {
 inline unsigned nblk(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------- constrained transport
-// gGam[e] = sum over the CT faces f holding edge e of -(dt/A_f) s_fe gBf[f],
-// with s_fe the sign with which face_ct adds Gam[e] into face f's circulation.
-__global__ void adj_ct(DevGeom G, double dt, const double *__restrict__ gBf, double *__restrict__ gGam)
+// Transpose of the face circulation (eqs. 2.5-2.6) over the faces of shells
+// k0..k1: gGam[e] = sum over the faces f holding edge e of
+// scale / A_f * s_fe * gBf[f], with s_fe the sign with which edge e enters
+// f's circulation.  Edges: radial in shells [k0, k1], angular at interfaces
+// [k0, k1 + 1].
+__global__ __launch_bounds__(256) void circ_transpose(DevGeom G, double scale, int k0, int k1,
+                                                      const double *__restrict__ gBf, double *__restrict__ gGam)
 {
-    const int nrad = G.Nr, nang = G.Nr + 1;
+    const int nrad = k1 - k0 + 1, nang = k1 - k0 + 2;
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const i64 nR = (i64)G.nv * nrad;
     if (t >= nR + (i64)G.nae * nang) return;
@@ -41,33 +45,33 @@ __global__ void adj_ct(DevGeom G, double dt, const double *__restrict__ gBf, dou
     i64 e;
     if (t < nR) {
         // radial edge of vertex v in shell k: the angular faces (ae, k) of the
-        // angular edges at v, through lp = ... + Gam[v1 edge] - ... - Gam[v0 edge]
-        const int v = (int)(t / nrad), k = G.g + (int)(t % nrad);
+        // angular edges at v, through +Gam[edge at a's second vertex] - Gam[at its first]
+        const int v = (int)(t / nrad), k = k0 + (int)(t % nrad);
         e = (i64)v * G.K + k;
         for (int s = 0; s < G.v_ncol[v]; s++) {
             const int ae = G.v_ae[4 * v + s];
             const double sg = (G.ae_v[2 * ae + 1] == v) ? 1.0 : -1.0;
             const i64 f = G.NRF + (i64)ae * G.K + k;
-            acc += -(dt / G.area[f]) * G.ae_rs[ae] * sg * gBf[f];
+            acc += scale / G.area[f] * G.ae_rs[ae] * sg * gBf[f];
         }
     } else {
         const i64 u = t - nR;
-        const int ae = (int)(u / nang), kf = G.g + (int)(u % nang);
+        const int ae = (int)(u / nang), kf = k0 + (int)(u % nang);
         e = G.NRE + (i64)ae * (G.K + 1) + kf;
         // radial faces kf of the two columns sharing the angular edge
         for (int s = 0; s < 2; s++) {
             const int c = G.ae_col[2 * ae + s], lf = G.ae_lf[2 * ae + s];
             const i64 f = (i64)c * (G.K + 1) + kf;
-            acc += -(dt / G.area[f]) * G.col_sgn[4 * c + lf] * gBf[f];
+            acc += scale / G.area[f] * G.col_sgn[4 * c + lf] * gBf[f];
         }
         // angular faces of the shells above (as lower ring) and below (as upper ring)
-        if (kf <= G.g + G.Nr - 1) {
+        if (kf <= k1) {
             const i64 f = G.NRF + (i64)ae * G.K + kf;
-            acc += -(dt / G.area[f]) * G.ae_rs[ae] * gBf[f];
+            acc += scale / G.area[f] * G.ae_rs[ae] * gBf[f];
         }
-        if (kf - 1 >= G.g) {
+        if (kf - 1 >= k0) {
             const i64 f = G.NRF + (i64)ae * G.K + kf - 1;
-            acc -= -(dt / G.area[f]) * G.ae_rs[ae] * gBf[f];
+            acc -= scale / G.area[f] * G.ae_rs[ae] * gBf[f];
         }
     }
     gGam[e] = acc;
@@ -999,7 +1003,7 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     // entries of gzoneB are written here)
     copy_state<<<2048, 256, 0, st>>>(gBf1, A.gBo, G.NF);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
-    adj_ct<<<nblk(nee, 256), 256, 0, st>>>(G, dt, gBf1, A.gGam);
+    circ_transpose<<<nblk(nee, 256), 256, 0, st>>>(G, -dt, G.g, G.g + G.Nr - 1, gBf1, A.gGam);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     adj_update_faces<<<nblk(nff, 256), 256, 0, st>>>(G, dt, gU1, A.gPhi);
     adj_update_zones<<<nblk(G.Z, 256), 256, 0, st>>>(G, gU1, A.gUo, A.gzoneB);
@@ -1030,6 +1034,16 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     // boundary fill
     adj_bc_zones<<<nblk(G.Z, 256), 256, 0, st>>>(G, prm.bc_kind, A.gUo, gU);
     adj_bc_faces<<<nblk(G.NF, 256), 256, 0, st>>>(G, prm.bc_kind, A.gBo, gBf);
+    RG_ADJ_CHECK();
+    return RG_OK;
+}
+
+rg_status launch_stokes_T(rg_geom *g, const double *gBf, double *gcirc, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGeom &G = g->d;
+    const i64 ne = (i64)G.nv * G.K + (i64)G.nae * (G.K + 1);
+    circ_transpose<<<nblk(ne, 256), 256, 0, st>>>(G, 1.0, 0, G.K - 1, gBf, gcirc);
     RG_ADJ_CHECK();
     return RG_OK;
 }

@@ -21,6 +21,19 @@ using namespace rg;
 
 extern "C" const char *rg_last_error(void) { return g_err.c_str(); }
 
+extern "C" const char *rg_status_str(rg_status s)
+{
+    switch (s) {
+    case RG_OK: return "RG_OK: success";
+    case RG_EINVAL: return "RG_EINVAL: bad argument";
+    case RG_ENOMEM: return "RG_ENOMEM: allocation failed";
+    case RG_ESINGULAR: return "RG_ESINGULAR: singular least-squares or KKT system";
+    case RG_ENOTSUP: return "RG_ENOTSUP: unsupported order, mode or mesh size";
+    case RG_EDEVICE: return "RG_EDEVICE: HIP runtime call failed";
+    }
+    return "unknown rg_status";
+}
+
 extern "C" rg_status rg_mesh_build(const rg_mesh_desc *desc, rg_mesh **out)
 {
     if (!desc || !out) { set_error("null argument"); return RG_EINVAL; }
@@ -477,6 +490,20 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
     }
     if (!alloc_adjoint(g)) { set_error("device allocation of the adjoint buffers failed"); return RG_ENOMEM; }
     return launch_adjoint(g, *params, U_n, Bf_n, gU_np1, gBf_np1, gU_n, gBf_n, stream);
+}
+
+extern "C" rg_status rg_stokes(const rg_geom *g, const double *edge_circ, double *Bf, void *stream)
+{
+    if (!g || !edge_circ || !Bf) { set_error("null argument"); return RG_EINVAL; }
+    if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
+    return launch_stokes(const_cast<rg_geom *>(g), edge_circ, Bf, stream);
+}
+
+extern "C" rg_status rg_stokes_T(const rg_geom *g, const double *gBf, double *g_edge_circ, void *stream)
+{
+    if (!g || !gBf || !g_edge_circ) { set_error("null argument"); return RG_EINVAL; }
+    if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
+    return launch_stokes_T(const_cast<rg_geom *>(g), gBf, g_edge_circ, stream);
 }
 
 extern "C" rg_status rg_step_fluxes(const rg_geom *g, double *Phi, double *Gam, void *stream)

@@ -51,6 +51,8 @@ rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U
                             double *Bo, void *stream);
 rg_status launch_adjoint(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, const double *gU1,
                          const double *gBf1, double *gU, double *gBf, void *stream);
+rg_status launch_stokes(rg_geom *g, const double *circ, double *Bf, void *stream);
+rg_status launch_stokes_T(rg_geom *g, const double *gBf, double *gcirc, void *stream);
 rg_status launch_diag(rg_geom *g, const double *U, const double *Bf, double gamma, void *stream, rg_diag_out *out);
 
 }  // namespace rg

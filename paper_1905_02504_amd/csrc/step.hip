@@ -692,28 +692,49 @@ __global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const d
     }
 }
 
-__global__ __launch_bounds__(256) void face_ct(DevGeom G, double dt, const double *__restrict__ Gam, double *Bo)
+// Circulation of edge values Gam about a face (right-hand rule about its
+// canonical normal): the discrete Stokes sum of eqs. 2.5-2.6.  Faces of
+// shells k0..k1: radial faces kf in [k0, k1 + 1], angular faces k in [k0, k1];
+// thread t < nR takes radial face (c, kf), the rest angular face (ae, k).
+__device__ __forceinline__ double face_circulation(const DevGeom &G, const double *__restrict__ Gam, i64 t, int k0,
+                                                   int k1, i64 &f)
 {
-    const int nrad = G.Nr + 1, nang = G.Nr;
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    i64 nR = (i64)G.ncol * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    i64 f;
-    double circ = 0.0;
+    const int nrad = k1 - k0 + 2, nang = k1 - k0 + 1;
+    const i64 nR = (i64)G.ncol * nrad;
     if (t < nR) {
-        int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
+        const int c = (int)(t / nrad), kf = k0 + (int)(t % nrad);
         f = (i64)c * (G.K + 1) + kf;
+        double circ = 0.0;
         for (int lf = 0; lf < 4; lf++)
             circ += G.col_sgn[4 * c + lf] * Gam[G.NRE + (i64)G.col_ae[4 * c + lf] * (G.K + 1) + kf];
-    } else {
-        i64 u = t - nR;
-        int ae = (int)(u / nang), k = G.g + (int)(u % nang);
-        f = G.NRF + (i64)ae * G.K + k;
-        i64 ea0 = G.NRE + (i64)ae * (G.K + 1) + k;
-        double lp = Gam[ea0] + Gam[(i64)G.ae_v[2 * ae + 1] * G.K + k] - Gam[ea0 + 1] - Gam[(i64)G.ae_v[2 * ae] * G.K + k];
-        circ = G.ae_rs[ae] * lp;
+        return circ;
     }
+    const i64 u = t - nR;
+    const int ae = (int)(u / nang), k = k0 + (int)(u % nang);
+    f = G.NRF + (i64)ae * G.K + k;
+    const i64 ea0 = G.NRE + (i64)ae * (G.K + 1) + k;
+    const double lp = Gam[ea0] + Gam[(i64)G.ae_v[2 * ae + 1] * G.K + k] - Gam[ea0 + 1] - Gam[(i64)G.ae_v[2 * ae] * G.K + k];
+    return G.ae_rs[ae] * lp;
+}
+
+__global__ __launch_bounds__(256) void face_ct(DevGeom G, double dt, const double *__restrict__ Gam, double *Bo)
+{
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr) return;
+    i64 f;
+    const double circ = face_circulation(G, Gam, t, G.g, G.g + G.Nr - 1, f);
     Bo[f] -= dt / G.area[f] * circ;
+}
+
+// Face averages of the normal component of curl A from the line integrals of
+// A along every edge (Stokes), for every face of the mesh
+__global__ __launch_bounds__(256) void stokes_faces(DevGeom G, const double *__restrict__ circ_e, double *__restrict__ Bf)
+{
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * (G.K + 1) + (i64)G.nae * G.K) return;
+    i64 f;
+    const double circ = face_circulation(G, circ_e, t, 0, G.K - 1, f);
+    Bf[f] = circ / G.area[f];
 }
 
 // ---------------------------------------------------------------- CFL
@@ -961,6 +982,15 @@ rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U
     if (g->d.order == 4) return step_order<4, double>(g, p, U, Bf, Uo, Bo, st, true);
     set_error("unsupported order");
     return RG_ENOTSUP;
+}
+
+rg_status launch_stokes(rg_geom *g, const double *circ, double *Bf, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGeom &G = g->d;
+    stokes_faces<<<nblocks(G.NF, 256), 256, 0, st>>>(G, circ, Bf);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
 }
 
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)

@@ -1,0 +1,81 @@
+"""The discrete Stokes map (rg_stokes) and its transpose (rg_stokes_T).
+
+rg_stokes turns edge line integrals of a vector potential into face-averaged
+normal B (eqs. 2.5-2.6 without the time step).  Checked against the same sum
+written with the oracle's face-edge incidence, signs and face areas; its
+output must be divergence-free to round-off for any edge values (the
+boundary of a zone's boundary is empty); and rg_stokes_T must be its exact
+transpose.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("order,n_ang,n_rad", [(3, 4, 5), (4, 8, 6)])
+def test_stokes_matches_oracle_incidence(order, n_ang, n_rad):
+    import paper_1905_02504_amd as R
+    from oracle import oracle as O
+    from tests.parity_util import Mapping, rel_err
+    from tests.test_gpu_parity import div_rel_max
+    print(f"[stokes] order={order} N={n_ang} Nr={n_rad}", flush=True)
+    om = O.OracleMesh(n_ang, n_rad, order=order, n_ghost=order - 1)
+    lib = R.ShellMHD(n_ang, n_rad, order, n_ghost=order - 1)
+    mp = Mapping(lib, om)
+    circ_o = np.random.default_rng(21).uniform(-1.0, 1.0, size=om.ne)
+    fe, fs = om.face_edges()
+    _, _, area_o, _ = om.faces()
+    Bf_o = (fs * circ_o[fe]).sum(1) / area_o
+    circ = torch.from_numpy(mp.Gam(circ_o)).cuda()
+    Bf = lib.stokes(circ)
+    torch.cuda.synchronize()
+    err = rel_err(Bf.cpu().numpy(), mp.Bf(Bf_o)).max()
+    div = div_rel_max(om, mp, Bf.cpu().numpy())
+    print(f"[stokes] max relative difference {err:.2e}, div B {div:.2e}", flush=True)
+    assert err < 1e-13
+    assert div < 1e-13
+
+
+def test_stokes_transpose_is_exact():
+    import paper_1905_02504_amd as R
+    lib = R.ShellMHD(8, 8, 4, n_ghost=3)
+    rng = np.random.default_rng(22)
+    c = torch.from_numpy(rng.uniform(-1, 1, size=lib.ne)).cuda()
+    g = torch.from_numpy(rng.uniform(-1, 1, size=lib.nf)).cuda()
+    lhs = float((g * lib.stokes(c)).sum())
+    rhs = float((lib.stokes_T(g) * c).sum())
+    terms = float((g * lib.stokes(c)).abs().sum())
+    print(f"[stokes] <g, S c> = {lhs:.15e}, <S^T g, c> = {rhs:.15e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-13 * terms
+
+
+def test_vector_potential_gradient_through_a_step():
+    """dL/dA for a loss after one step: stokes_T applied to the step adjoint's
+    face-B gradient, against central differences in the edge values."""
+    import paper_1905_02504_amd as R
+    from tests.test_gpu_adjoint import roughen
+    import rg_inputs as RI
+    lib = R.ShellMHD(4, 5, 3, n_ghost=2)
+    prob = RI.alfven_problem()
+    U_h, Bf_h = lib.init_alfven(prob)
+    U_h, _ = roughen(U_h, Bf_h, prob["gamma"])
+    U = torch.from_numpy(U_h).cuda()
+    rng = np.random.default_rng(23)
+    circ = torch.from_numpy(rng.uniform(-1, 1, size=lib.ne) * 0.05).cuda()
+    gam = prob["gamma"]
+    dt = lib.cfl_dt(U, 0.4, gam)
+    gU1 = torch.from_numpy(rng.uniform(-1, 1, size=U.shape)).cuda()
+    gB1 = torch.from_numpy(rng.uniform(-1, 1, size=lib.nf)).cuda()
+    Bf = lib.stokes(circ)
+    _, gB = lib.step_adjoint(U, Bf, gU1, gB1, dt, gamma=gam)
+    gcirc = lib.stokes_T(gB)
+    d = torch.from_numpy(rng.uniform(-1, 1, size=lib.ne) * 0.05).cuda()
+    h = 1e-6
+    Up, Bp, _ = lib.step(U, lib.stokes((circ + h * d).contiguous()), dt, gamma=gam)
+    Um, Bm, _ = lib.step(U, lib.stokes((circ - h * d).contiguous()), dt, gamma=gam)
+    fd = float(((Up - Um) / (2 * h) * gU1).sum() + ((Bp - Bm) / (2 * h) * gB1).sum())
+    a = float((gcirc * d).sum())
+    print(f"[stokes] dL/dA . d: adjoint {a:.12e} FD {fd:.12e}", flush=True)
+    assert abs(a - fd) <= 1e-6 * max(abs(a), abs(fd))

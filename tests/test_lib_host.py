@@ -51,6 +51,13 @@ def test_argument_errors_are_reported():
     N.rg_mesh_free(m)
 
 
+def test_status_strings():
+    from paper_1905_02504_amd import _native as N
+    names = [N.rg_status_str(i).split(":")[0] for i in range(6)]
+    assert names == ["RG_OK", "RG_EINVAL", "RG_ENOMEM", "RG_ESINGULAR", "RG_ENOTSUP", "RG_EDEVICE"]
+    assert N.rg_status_str(99) == "unknown rg_status"
+
+
 def test_mesh_counts_match_formulas():
     import paper_1905_02504_amd as R
     s = R.ShellMHD(8, 5, 3, n_ghost=2, device=False)
