@@ -124,6 +124,9 @@ typedef struct {
     int32_t bc_kind;  /* 0: continuative (ghost shells copy the nearest interior
                          shell, Section VII); 1: ghost values supplied by the caller */
     int32_t n_picard; /* 0 selects the order (Section V.d step 9)                   */
+    double weno_eps;  /* epsilon of the WENO-AO nonlinear weights
+                         gamma_s / (beta_s + eps)^2 (Section III; beta in units of
+                         the squared zone data); 0 selects 1e-4                   */
 } rg_step_params;
 
 /* One complete timestep (Section VI) on device buffers.

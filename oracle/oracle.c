@@ -8,11 +8,11 @@
 #include <stdlib.h>
 #include <string.h>
 
-int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, const double *U,
-                 const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam);
-int rgo_run_recon(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z, int npts,
-                  const double *pts, double *weno_vals, double *divB_vals);
-int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z,
+int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam);
+int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
+                  int npts, const double *pts, double *weno_vals, double *divB_vals);
+int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                            double *coeffs, int *exps, double *face_nodal);
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U);
 void rgo_run_init_harmonic(const rgo_mesh *m, const double *rho, const double *v, const double *A, double p,
@@ -160,22 +160,22 @@ double rgo_sphericity(const rgo_mesh *m, int samples)
     return worst;
 }
 
-int rgo_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, const double *U,
-             const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
+int rgo_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+             const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
 {
-    return rgo_run_step(m, gamma, dt, bc_kind, flags, U, Bf, Uout, Bfout, dbgPhi, dbgGam);
+    return rgo_run_step(m, gamma, dt, bc_kind, flags, weno_eps, U, Bf, Uout, Bfout, dbgPhi, dbgGam);
 }
 
-int rgo_recon(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z, int npts,
+int rgo_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z, int npts,
               const double *pts, double *weno, double *divB)
 {
-    return rgo_run_recon(m, flags, U, Bf, z, npts, pts, weno, divB);
+    return rgo_run_recon(m, flags, weno_eps, U, Bf, z, npts, pts, weno, divB);
 }
 
-int rgo_divfree(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z, double *coeffs,
-                int *exps, double *face_nodal)
+int rgo_divfree(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
+                double *coeffs, int *exps, double *face_nodal)
 {
-    return rgo_run_divfree_coeffs(m, flags, U, Bf, z, coeffs, exps, face_nodal);
+    return rgo_run_divfree_coeffs(m, flags, weno_eps, U, Bf, z, coeffs, exps, face_nodal);
 }
 
 double rgo_cfl_dt(const rgo_mesh *m, double gamma, double cfl, const double *U)

@@ -58,12 +58,12 @@ def lib():
         L.rgo_sphericity.restype = C.c_double
         L.rgo_sphericity.argtypes = [C.c_void_p, C.c_int]
         L.rgo_step.restype = C.c_int
-        L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
-                               C.c_void_p, C.c_void_p]
+        L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp,
+                               _dp, C.c_void_p, C.c_void_p]
         L.rgo_recon.restype = C.c_int
-        L.rgo_recon.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.rgo_recon.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
         L.rgo_divfree.restype = C.c_int
-        L.rgo_divfree.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, _dp, _ip, _dp]
+        L.rgo_divfree.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, _dp, _ip, _dp]
         L.rgo_cfl_dt.restype = C.c_double
         L.rgo_cfl_dt.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp]
         L.rgo_init_harmonic.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
@@ -89,6 +89,13 @@ def lib():
 
 NVAR = 8
 FLAG_LINEAR_WEIGHTS = 1
+# epsilon of the WENO-AO nonlinear weights w_s ~ gamma_s / (beta_s + eps)^2
+# (Section III defers the weights to the WENO-AO literature).  The smoothness
+# indicators are in units of the squared zone data; 1e-4 lets the weights
+# reach the linear ones on smooth, resolved data, which the scheme needs for
+# the design order reported in Section VII (Tables I-II), while jumps with
+# beta >> eps still switch to the small stencils.
+WENO_EPS = 1e-4
 
 
 class OracleMesh:
@@ -178,12 +185,12 @@ class OracleMesh:
         return U, Bf
 
     # the method -----------------------------------------------------------
-    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False):
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS):
         U = np.ascontiguousarray(U, np.float64); Bf = np.ascontiguousarray(Bf, np.float64)
         Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
         phi = np.zeros((self.nf, NVAR)) if debug else None
         gam = np.zeros(self.ne) if debug else None
-        rc = lib().rgo_step(self._h, gamma, dt, bc, flags, U, Bf, Uo, Bo,
+        rc = lib().rgo_step(self._h, gamma, dt, bc, flags, weno_eps, U, Bf, Uo, Bo,
                             phi.ctypes.data if debug else None, gam.ctypes.data if debug else None)
         if rc != 0:
             raise RuntimeError("oracle step failed")
@@ -191,20 +198,20 @@ class OracleMesh:
             return Uo, Bo, phi, gam
         return Uo, Bo
 
-    def recon(self, U, Bf, z, pts, flags=0):
+    def recon(self, U, Bf, z, pts, flags=0, weno_eps=WENO_EPS):
         pts = np.ascontiguousarray(pts, np.float64)
         w = np.zeros((len(pts), NVAR)); b = np.zeros((len(pts), 3))
-        rc = lib().rgo_recon(self._h, flags, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
+        rc = lib().rgo_recon(self._h, flags, weno_eps, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
                              len(pts), pts, w, b)
         if rc != 0:
             raise RuntimeError("oracle reconstruction failed")
         return w, b
 
-    def divfree(self, U, Bf, z, flags=0):
+    def divfree(self, U, Bf, z, flags=0, weno_eps=WENO_EPS):
         nb = 16 if self.order == 3 else 30
         Q = (self.order - 1) ** 2
         c = np.zeros(3 * nb); e = np.zeros((3 * nb, 3), np.int32); fn = np.zeros((6, Q))
-        rc = lib().rgo_divfree(self._h, flags, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
+        rc = lib().rgo_divfree(self._h, flags, weno_eps, np.ascontiguousarray(U), np.ascontiguousarray(Bf), int(z),
                                c, e, fn)
         if rc != nb:
             raise RuntimeError("oracle divergence-free reconstruction failed")

@@ -25,7 +25,6 @@
 #include <string.h>
 
 #define WENO_GAMMA_HI 0.85
-#define WENO_EPS 1e-12
 #define FLAG_LINEAR_WEIGHTS 1
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -137,6 +136,7 @@ typedef struct {
     const rgo_mesh *m;
     double gamma, dt;
     int flags;
+    double weno_eps;        /* epsilon of the WENO-AO weights */
     int deg, nc, nbx;       /* reconstruction degree p-1, # Taylor coeffs, # B coeffs per component */
     int te[40][3];          /* Taylor multi-indices 1..deg */
     int be[3][40][3];       /* divergence-free basis per component */
@@ -259,11 +259,12 @@ static void weno_zone(step_ws *w, int z)
             }
             bhi /= m->vol[z];
             double tot = 0.0;
-            wgt[0] = WENO_GAMMA_HI / ((bhi + WENO_EPS) * (bhi + WENO_EPS));
+            const double eps = w->weno_eps;
+            wgt[0] = WENO_GAMMA_HI / ((bhi + eps) * (bhi + eps));
             tot += wgt[0];
             for (int s = 0; s < nsm; s++) {
                 double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
-                wgt[1 + s] = gs / ((b + WENO_EPS) * (b + WENO_EPS));
+                wgt[1 + s] = gs / ((b + eps) * (b + eps));
                 tot += wgt[1 + s];
             }
             for (int s = 0; s <= nsm; s++) wgt[s] /= tot;
@@ -669,8 +670,8 @@ static void setup_bases(step_ws *w)
     }
 }
 
-int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, const double *U,
-                 const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
+int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
@@ -678,6 +679,7 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     w.gamma = gamma;
     w.dt = dt;
     w.flags = flags;
+    w.weno_eps = weno_eps;
     setup_bases(&w);
     const int nz = m->nz, nf = m->nf, ne = m->ne, N = m->ref.N, g = m->n_ghost, Nr = m->n_rad;
     w.U = malloc(sizeof(double) * NVAR * nz);
@@ -772,13 +774,14 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
 }
 
 /* reconstructed fields of one zone at arbitrary points (test access) */
-int rgo_run_recon(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z, int npts,
-                  const double *pts, double *weno_vals, double *divB_vals)
+int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
+                  int npts, const double *pts, double *weno_vals, double *divB_vals)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
     w.m = m;
     w.flags = flags;
+    w.weno_eps = weno_eps;
     w.gamma = 5.0 / 3.0;
     setup_bases(&w);
     const int nz = m->nz, nf = m->nf;
@@ -810,13 +813,14 @@ int rgo_run_recon(const rgo_mesh *m, int flags, const double *U, const double *B
 }
 
 /* divergence-identity residual of the B coefficients and nodal face values (test access) */
-int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, const double *U, const double *Bf, int z,
+int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                            double *coeffs, int *exps, double *face_nodal)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
     w.m = m;
     w.flags = flags;
+    w.weno_eps = weno_eps;
     setup_bases(&w);
     const int nz = m->nz, nf = m->nf, Q = m->nq_face * m->nq_face;
     w.U = malloc(sizeof(double) * NVAR * nz);

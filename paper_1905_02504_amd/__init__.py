@@ -103,7 +103,7 @@ class ShellMHD:
         return U, Bf
 
     # the step ------------------------------------------------------------------
-    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0):
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0, weno_eps=0.0):
         """One timestep on torch.cuda float64 tensors; returns (U_out, Bf_out, dt)."""
         import torch
         assert U.is_cuda and U.dtype == torch.float64 and U.is_contiguous() and U.shape == (8, self.nz)
@@ -112,11 +112,12 @@ class ShellMHD:
             U_out = torch.empty_like(U)
         if Bf_out is None:
             Bf_out = torch.empty_like(Bf)
-        p = rg_step_params(gamma, dt, cfl, bc, n_picard)
+        p = rg_step_params(gamma, dt, cfl, bc, n_picard, weno_eps)
         N.rg_step(self._geom, p, U.data_ptr(), Bf.data_ptr(), U_out.data_ptr(), Bf_out.data_ptr(), _stream())
         return U_out, Bf_out, p.dt
 
-    def step_adjoint(self, U, Bf, gU1, gBf1, dt, gamma=5.0 / 3.0, bc=0, n_picard=0, gU=None, gBf=None):
+    def step_adjoint(self, U, Bf, gU1, gBf1, dt, gamma=5.0 / 3.0, bc=0, n_picard=0, gU=None, gBf=None,
+                     weno_eps=0.0):
         """rg_step_adjoint: the gradients with respect to (U, Bf) of a loss whose
         gradients with respect to the step's outputs are (gU1, gBf1); dt fixed."""
         import torch
@@ -128,7 +129,7 @@ class ShellMHD:
             gU = torch.empty_like(U)
         if gBf is None:
             gBf = torch.empty_like(Bf)
-        p = rg_step_params(gamma, dt, 0.0, bc, n_picard)
+        p = rg_step_params(gamma, dt, 0.0, bc, n_picard, weno_eps)
         N.rg_step_adjoint(self._geom, p, U.data_ptr(), Bf.data_ptr(), gU1.data_ptr(), gBf1.data_ptr(),
                           gU.data_ptr(), gBf.data_ptr(), _stream())
         return gU, gBf

@@ -131,115 +131,81 @@ __global__ void adj_update_zones(DevGeom G, const double *__restrict__ gU, doubl
 }
 
 // ---------------------------------------------------------------- Riemann solvers
+// one lane per face quadrature point (the step's face_flux layout)
 template <int P>
 __global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, const double *__restrict__ ftr,
                                                      const double *__restrict__ gPhi, double *__restrict__ gftr)
 {
     using T = Tr<P>;
-    const int nrad = G.Nr + 1, nang = G.Nr;
+    const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    const i64 nR = (i64)G.ncol * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    i64 f;
+    if (t >= nff * T::Q) return;
+    const int q = (int)(t % T::Q);
     const double *nrm, *fw;
-    if (t < nR) {
-        const int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
-        f = (i64)c * (G.K + 1) + kf;
-        nrm = G.fnR + (i64)c * T::Q * 3;
-        fw = G.fwR + (i64)c * T::Q;
-    } else {
-        const i64 u = t - nR;
-        const int ae = (int)(u / nang), k = G.g + (int)(u % nang);
-        f = G.NRF + (i64)ae * G.K + k;
-        nrm = G.fnA + (i64)ae * T::Q * 3;
-        fw = G.fwA + (i64)ae * T::Q;
+    const i64 f = flux_face<P>(G, t / T::Q, nrm, fw);
+    const double w = fw[q] * G.area[f];
+    const double *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
+    double UL[8], UR[8], FL[8], FR[8], gFs[8], gUL[8], gUR[8], gFL[8], gFR[8];
+    for (int v = 0; v < 8; v++) {
+        UL[v] = a[v];
+        FL[v] = a[8 + v];
+        UR[v] = b[v];
+        FR[v] = b[8 + v];
+        gFs[v] = w * gPhi[(i64)v * G.NF + f];
+        gUL[v] = gUR[v] = gFL[v] = gFR[v] = 0.0;
     }
-    const double area = G.area[f];
-    double gPhiF[8];
-    for (int v = 0; v < 8; v++) gPhiF[v] = gPhi[(i64)v * G.NF + f];
-    for (int q = 0; q < T::Q; q++) {
-        const double *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
-        double UL[8], UR[8], FL[8], FR[8], gFs[8], gUL[8], gUR[8], gFL[8], gFR[8];
-        const double w = fw[q] * area;
-        for (int v = 0; v < 8; v++) {
-            UL[v] = a[v];
-            FL[v] = a[8 + v];
-            UR[v] = b[v];
-            FR[v] = b[8 + v];
-            gFs[v] = w * gPhiF[v];
-            gUL[v] = gUR[v] = gFL[v] = gFR[v] = 0.0;
-        }
-        hll_vjp(UL, UR, FL, FR, nrm + q * 3, gam, gFs, gUL, gUR, gFL, gFR);
-        double *ga = gftr + ((f * 2 + 0) * T::Q + q) * 16, *gb = gftr + ((f * 2 + 1) * T::Q + q) * 16;
-        for (int v = 0; v < 8; v++) {
-            ga[v] = gUL[v];
-            ga[8 + v] = gFL[v];
-            gb[v] = gUR[v];
-            gb[8 + v] = gFR[v];
-        }
+    hll_vjp(UL, UR, FL, FR, nrm + q * 3, gam, gFs, gUL, gUR, gFL, gFR);
+    double *ga = gftr + ftr_at<P>(f, q, 0), *gb = ga + 16;
+    for (int v = 0; v < 8; v++) {
+        ga[v] = gUL[v];
+        ga[8 + v] = gFL[v];
+        gb[v] = gUR[v];
+        gb[8 + v] = gFR[v];
     }
 }
 
+// one lane per (edge, Simpson point) (the step's edge_emf layout)
 __global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const double *__restrict__ etr,
                                                     const double *__restrict__ gGam, double *__restrict__ getr)
 {
-    const int nrad = G.Nr, nang = G.Nr + 1;
+    const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    const i64 nR = (i64)G.nv * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    const double simpson[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
-    i64 e;
+    if (t >= nee * 3) return;
+    const int p = (int)(t % 3);
+    const double *frame, *N3;
+    double wl;
     int nzs;
-    const double *frame[3];
-    double wl[3];
-    const double *N3 = nullptr;
-    if (t < nR) {
-        const int v = (int)(t / nrad), k = G.g + (int)(t % nrad);
-        e = (i64)v * G.K + k;
-        nzs = G.v_ncol[v];
-        const double len = G.radius[k + 1] - G.radius[k];
-        for (int p = 0; p < 3; p++) { frame[p] = G.vF + (i64)v * 9; wl[p] = simpson[p] * len; }
-        N3 = G.vN3 + (i64)v * 9;
-    } else {
-        const i64 u = t - nR;
-        const int ae = (int)(u / nang), kf = G.g + (int)(u % nang);
-        e = G.NRE + (i64)ae * (G.K + 1) + kf;
-        nzs = 4;
-        const double s = G.radius[kf] / G.radius[0];
-        for (int p = 0; p < 3; p++) { frame[p] = G.aeF + ((i64)ae * 3 + p) * 9; wl[p] = G.aeW[(i64)ae * 3 + p] * s; }
+    const i64 e = emf_edge(G, t / 3, p, frame, wl, nzs, N3);
+    const double *tt = frame + 6;
+    const double g = wl * gGam[e];
+    const double *rec = etr + etr_at(e, p, 0);
+    double U[4][8], E[4][3], Et[4], gU[4][8], gE[4][3], gEt[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+#pragma unroll
+        for (int v = 0; v < 8; v++) { U[s][v] = rec[s * 11 + v]; gU[s][v] = 0.0; }
+#pragma unroll
+        for (int v = 0; v < 3; v++) { E[s][v] = rec[s * 11 + 8 + v]; gE[s][v] = 0.0; }
+        Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
+        gEt[s] = 0.0;
     }
-    const double ge = gGam[e];
-    for (int p = 0; p < 3; p++) {
-        const double *tt = frame[p] + 6;
-        double U[4][8], E[4][3], Et[4], gU[4][8], gE[4][3], gEt[4];
+    if (nzs == 4) {
+        emf4_vjp(U, Et, frame, gam, g, gU, gEt);
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-            const double *rec = etr + ((e * 4 + s) * 3 + p) * 11;
+        for (int s = 0; s < 4; s++)
 #pragma unroll
-            for (int v = 0; v < 8; v++) { U[s][v] = rec[v]; gU[s][v] = 0.0; }
+            for (int v = 0; v < 3; v++) gE[s][v] = gEt[s] * tt[v];
+    } else {
+        emf3_vjp(U, E, N3, tt, gam, g, gU, gE);
+    }
+    double *o = getr + etr_at(e, p, 0);
 #pragma unroll
-            for (int v = 0; v < 3; v++) { E[s][v] = rec[8 + v]; gE[s][v] = 0.0; }
-            Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
-            gEt[s] = 0.0;
-        }
-        if (nzs == 4) {
-            emf4_vjp(U, Et, frame[p], gam, wl[p] * ge, gU, gEt);
+    for (int s = 0; s < 4; s++) {
+        if (s >= nzs) continue;
 #pragma unroll
-            for (int s = 0; s < 4; s++)
+        for (int v = 0; v < 8; v++) o[s * 11 + v] = gU[s][v];
 #pragma unroll
-                for (int v = 0; v < 3; v++) gE[s][v] = gEt[s] * tt[v];
-        } else {
-            emf3_vjp(U, E, N3, tt, gam, wl[p] * ge, gU, gE);
-        }
-#pragma unroll
-        for (int s = 0; s < 4; s++) {
-            if (s >= nzs) continue;
-            double *o = getr + ((e * 4 + s) * 3 + p) * 11;
-#pragma unroll
-            for (int v = 0; v < 8; v++) o[v] = gU[s][v];
-#pragma unroll
-            for (int v = 0; v < 3; v++) o[8 + v] = gE[s][v];
-        }
+        for (int v = 0; v < 3; v++) o[s * 11 + 8 + v] = gE[s][v];
     }
 }
 
@@ -420,13 +386,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
                 nrm = G.fnA + (i64)ae * T::Q * 3;
                 perm = G.col_perm + ((i64)c * 4 + lf) * T::Q;
             }
-            const double *go = gftr + (fid * 2 + side) * T::Q * 16;
+            const double *go = gftr + ftr_at<P>(fid, 0, side);   // point q at go + 32 q
 #pragma unroll 1
             for (int q = 0; q < T::Q; q++) {
                 const int qc = perm ? perm[q] : q;
                 const double w = G.fintc[kk * T::Q + q];
                 const double *n = nrm + qc * 3;
-                const double *gq = go + qc * 16;
+                const double *gq = go + qc * 32;
 #pragma unroll
                 for (int v = 0; v < 8; v++) {
                     gaU[v] += w * gq[v];
@@ -455,15 +421,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
             } else {
                 e = (i64)G.col_v[4 * c + LocalEdges::CORNER[le - 8]] * G.K + k;
             }
-            const double *go = getr + (e * 4 + slot) * 3 * 11;
+            const double *go = getr + etr_at(e, 0, slot);   // point p at go + 44 p
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
                 const double w = G.eintc[kk * 3 + p];
 #pragma unroll
-                for (int v = 0; v < 8; v++) gaU[v] += w * go[pc * 11 + v];
-                gaF[2][6] += w * go[pc * 11 + 8];   // E_x = H[B_y]
-                gaF[0][7] += w * go[pc * 11 + 9];   // E_y = F[B_z]
-                gaF[1][5] += w * go[pc * 11 + 10];  // E_z = G[B_x]
+                for (int v = 0; v < 8; v++) gaU[v] += w * go[pc * 44 + v];
+                gaF[2][6] += w * go[pc * 44 + 8];   // E_x = H[B_y]
+                gaF[0][7] += w * go[pc * 44 + 9];   // E_y = F[B_z]
+                gaF[1][5] += w * go[pc * 44 + 10];  // E_z = G[B_x]
             }
         }
     }
@@ -828,7 +794,7 @@ template <int P>
 __device__ __forceinline__ void weno_var_vjp(const DevGeom &G, const double *__restrict__ U,
                                              const double *__restrict__ gwc, double *__restrict__ gdu,
                                              const double *__restrict__ Pl, const double *__restrict__ Ps,
-                                             const double *__restrict__ Qs, int c, int k, int v)
+                                             const double *__restrict__ Qs, double eps, int c, int k, int v)
 {
     using T = Tr<P>;
     const int KR = G.Nr + 2;
@@ -847,12 +813,12 @@ __device__ __forceinline__ void weno_var_vjp(const DevGeom &G, const double *__r
     for (int a = 0; a < T::NC; a++) go[a] = gwc[((i64)v * T::NC + a) * G.Z + z];
     double *o = gdu + (i64)v * T::NS * nzr + zr;
     const int *stm = G.stm + (i64)c * T::NS;
-    weno_core_vjp<P>(du, Pl, Ps, Qs, go, [&](int j, double g) { o[(i64)j * nzr] = stm[j] >= 0 ? g : 0.0; });
+    weno_core_vjp<P>(du, Pl, Ps, Qs, eps, go, [&](int j, double g) { o[(i64)j * nzr] = stm[j] >= 0 ? g : 0.0; });
 }
 
 template <int P>
 __global__ __launch_bounds__(64) void adj_weno(DevGeom G, const double *__restrict__ U, const double *__restrict__ gwc,
-                                               double *__restrict__ gdu, int nchunk, int nu, int nleft)
+                                               double *__restrict__ gdu, double eps, int nchunk, int nu, int nleft)
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
@@ -868,12 +834,12 @@ __global__ __launch_bounds__(64) void adj_weno(DevGeom G, const double *__restri
         for (int v = 0; v < 8; v++) {
             int vo = 0;
             __asm__ __volatile__("" : "+s"(vo));
-            weno_var_vjp<P>(G, U, gwc, gdu, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
+            weno_var_vjp<P>(G, U, gwc, gdu, Pl + vo, Ps + vo, Qs + vo, eps, c, G.g - 1 + kk, v);
         }
     } else {
         const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
         if (kk >= nu + nleft) return;
-        weno_var_vjp<P>(G, U, gwc, gdu, Pl, Ps, Qs, c, G.g - 1 + kk, v);
+        weno_var_vjp<P>(G, U, gwc, gdu, Pl, Ps, Qs, eps, c, G.g - 1 + kk, v);
     }
 }
 
@@ -1009,8 +975,8 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     adj_update_zones<<<nblk(G.Z, 256), 256, 0, st>>>(G, gU1, A.gUo, A.gzoneB);
     RG_ADJ_CHECK();
     // Riemann solvers
-    adj_face_flux<P><<<nblk(nff, 256), 256, 0, st>>>(G, gam, g->ftr, A.gPhi, A.gftr);
-    adj_edge_emf<<<nblk(nee, 256), 256, 0, st>>>(G, gam, g->etr, A.gGam, A.getr);
+    adj_face_flux<P><<<nblk(nff * T::Q, 256), 256, 0, st>>>(G, gam, g->ftr, A.gPhi, A.gftr);
+    adj_edge_emf<<<nblk(nee * 3, 256), 256, 0, st>>>(G, gam, g->etr, A.gGam, A.getr);
     RG_ADJ_CHECK();
     // predictor
     constexpr int ZPW = PredLayout<P>::ZPW;
@@ -1027,8 +993,8 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     RG_ADJ_CHECK();
     // WENO-AO
     const RunSplit wr = run_split(G.Nr + 2);
-    adj_weno<P><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(G, A.Ubc, A.gwc, A.gdu,
-                                                                                      wr.nchunk, wr.nu, wr.nleft);
+    adj_weno<P><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
+        G, A.Ubc, A.gwc, A.gdu, weno_eps(prm), wr.nchunk, wr.nu, wr.nleft);
     adj_weno_gather<P><<<nblk(G.Z, 256), 256, 0, st>>>(G, A.gdu, A.gUo);
     RG_ADJ_CHECK();
     // boundary fill

@@ -431,7 +431,8 @@ extern "C" rg_status rg_step(const rg_geom *geom, rg_step_params *params, const 
                              double *U_out, double *Bf_out, void *stream)
 {
     if (!geom || !params || !U || !Bf || !U_out || !Bf_out) { set_error("null argument"); return RG_EINVAL; }
-    if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0) {
+    if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0 ||
+        !(params->weno_eps >= 0.0)) {
         set_error("invalid step parameters");
         return RG_EINVAL;
     }
@@ -477,7 +478,7 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
         return RG_EINVAL;
     }
     if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0 ||
-        !(params->dt > 0.0)) {
+        !(params->weno_eps >= 0.0) || !(params->dt > 0.0)) {
         set_error("invalid step parameters (the adjoint needs a fixed dt > 0)");
         return RG_EINVAL;
     }

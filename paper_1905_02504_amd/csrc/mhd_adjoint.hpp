@@ -280,11 +280,11 @@ __device__ __forceinline__ void emf3_vjp(const double (&U)[4][8], const double (
 template <int P, class Out>
 __device__ __forceinline__ void weno_core_vjp(const double (&du)[Tr<P>::NS], const double *__restrict__ Pl,
                                               const double *__restrict__ Ps, const double *__restrict__ Qs,
-                                              const double (&go)[Tr<P>::NC], Out &&out)
+                                              double eps, const double (&go)[Tr<P>::NC], Out &&out)
 {
     using Tt = Tr<P>;
     constexpr int NC = Tt::NC, NS = Tt::NS;
-    const double ghi = WENO_GAMMA_HI, gs = (1.0 - WENO_GAMMA_HI) / 7.0, eps = WENO_EPS;
+    const double ghi = WENO_GAMMA_HI, gs = (1.0 - WENO_GAMMA_HI) / 7.0;
     double chi[NC];
 #pragma unroll
     for (int a = 0; a < NC; a++) {

@@ -25,7 +25,8 @@ struct Tr<4> {
 typedef long long i64;
 
 constexpr double WENO_GAMMA_HI = 0.85;
-constexpr double WENO_EPS = 1e-12;
+// epsilon of the nonlinear weights when the step parameters leave it at 0
+constexpr double WENO_EPS_DEFAULT = 1e-4;
 
 // local edges 0..7 are angular: local face holding them and whether they lie
 // on the upper (zeta+) interface; 8..11 radial at corners v0, v1, v3, v2
@@ -45,6 +46,66 @@ __device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
 
 // accumulator of v_mfma_f64_16x16x4f64
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Trace records written by the predictor and read by the Riemann solvers.
+// Face record (face f, quadrature point q, side s): the 8 time-averaged
+// conserved variables, then the 8 time-averaged normal fluxes; the two sides
+// of a point are adjacent, [f][q][side][16].  Edge record (edge e, Simpson
+// point p, slot s): the 8 variables, then the 3 components of E;
+// [e][p][slot][11].
+template <int P>
+__host__ __device__ __forceinline__ long long ftr_at(long long f, int q, int side)
+{
+    return ((f * Tr<P>::Q + q) * 2 + side) * 16;
+}
+__host__ __device__ __forceinline__ long long etr_at(long long e, int p, int slot) { return ((e * 3 + p) * 4 + slot) * 11; }
+
+// Faces of the flux stage: radial faces kf in [g, g+Nr], angular faces in shells [g, g+Nr-1]; face
+// index t of that range -> face id, unit normals and weights of its points
+template <int P>
+__device__ __forceinline__ i64 flux_face(const DevGeom &G, i64 t, const double *&nrm, const double *&fw)
+{
+    using T = Tr<P>;
+    const int nrad = G.Nr + 1, nang = G.Nr;
+    const i64 nR = (i64)G.ncol * nrad;
+    if (t < nR) {
+        const int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
+        nrm = G.fnR + (i64)c * T::Q * 3;
+        fw = G.fwR + (i64)c * T::Q;
+        return (i64)c * (G.K + 1) + kf;
+    }
+    const i64 u = t - nR;
+    const int ae = (int)(u / nang), k = G.g + (int)(u % nang);
+    nrm = G.fnA + (i64)ae * T::Q * 3;
+    fw = G.fwA + (i64)ae * T::Q;
+    return G.NRF + (i64)ae * G.K + k;
+}
+
+// Edges of the EMF stage: radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr];
+// edge index t of that range -> edge id, the frame and line weight of its
+// Simpson point p, number of zones around it (3 or 4) and, at valence-3
+// vertices, the three face normals
+__device__ __forceinline__ i64 emf_edge(const DevGeom &G, i64 t, int p, const double *&frame, double &wl, int &nzs,
+                                        const double *&N3)
+{
+    const int nrad = G.Nr, nang = G.Nr + 1;
+    const i64 nR = (i64)G.nv * nrad;
+    if (t < nR) {
+        const int v = (int)(t / nrad), k = G.g + (int)(t % nrad);
+        nzs = G.v_ncol[v];
+        wl = (p == 1 ? 4.0 / 6.0 : 1.0 / 6.0) * (G.radius[k + 1] - G.radius[k]);
+        frame = G.vF + (i64)v * 9;
+        N3 = G.vN3 + (i64)v * 9;
+        return (i64)v * G.K + k;
+    }
+    const i64 u = t - nR;
+    const int ae = (int)(u / nang), kf = G.g + (int)(u % nang);
+    nzs = 4;
+    wl = G.aeW[(i64)ae * 3 + p] * (G.radius[kf] / G.radius[0]);
+    frame = G.aeF + ((i64)ae * 3 + p) * 9;
+    N3 = nullptr;
+    return G.NRE + (i64)ae * (G.K + 1) + kf;
+}
 
 // ---------------------------------------------------------------- ideal MHD
 template <class T>
@@ -78,19 +139,38 @@ __device__ __forceinline__ void dev_flux(const T *u, T gam, T F[3][8])
     }
 }
 
-// flux contracted with the scaled metric terms at a node (eq. 5.23)
+// flux contracted with the scaled metric terms at a node (eq. 5.23):
+// out[d] = sum_c met[d][c] F_c(u / J).  Each contraction is the physical flux
+// along the (non-unit) vector n = met[d][.], formed directly from n.m, n.v
+// and n.B instead of from the three Cartesian fluxes.
 template <class T>
 __device__ __forceinline__ void mapped_flux(const T *u, T iJ, const T *met, T gam, T out[3][8])
 {
-    T w[8], F[3][8];
+    T w[8];
 #pragma unroll
     for (int v = 0; v < 8; v++) w[v] = u[v] * iJ;
-    dev_flux<T>(w, gam, F);
+    const T ir = T(1) / w[0];
+    const T v0 = w[1] * ir, v1 = w[2] * ir, v2 = w[3] * ir;
+    const T B0 = w[5], B1 = w[6], B2 = w[7];
+    const T hb2 = T(0.5) * (B0 * B0 + B1 * B1 + B2 * B2);
+    const T p = (gam - T(1)) * (w[4] - T(0.5) * (w[1] * v0 + w[2] * v1 + w[3] * v2) - hb2);
+    const T pt = p + hb2, Ept = w[4] + pt;
+    const T vB = v0 * B0 + v1 * B1 + v2 * B2;
 #pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-        for (int v = 0; v < 8; v++)
-            out[d][v] = met[d * 3 + 0] * F[0][v] + met[d * 3 + 1] * F[1][v] + met[d * 3 + 2] * F[2][v];
+    for (int d = 0; d < 3; d++) {
+        const T n0 = met[d * 3 + 0], n1 = met[d * 3 + 1], n2 = met[d * 3 + 2];
+        const T mn = w[1] * n0 + w[2] * n1 + w[3] * n2;
+        const T vn = mn * ir;
+        const T Bn = B0 * n0 + B1 * n1 + B2 * n2;
+        out[d][0] = mn;
+        out[d][1] = mn * v0 + n0 * pt - Bn * B0;
+        out[d][2] = mn * v1 + n1 * pt - Bn * B1;
+        out[d][3] = mn * v2 + n2 * pt - Bn * B2;
+        out[d][4] = Ept * vn - Bn * vB;
+        out[d][5] = vn * B0 - Bn * v0;
+        out[d][6] = vn * B1 - Bn * v1;
+        out[d][7] = vn * B2 - Bn * v2;
+    }
 }
 
 // fast magnetosonic speed along unit n
@@ -187,10 +267,11 @@ __device__ __forceinline__ T emf3(const T U[4][8], const T E[4][3], const double
 // precision R, arithmetic in T.
 template <int P, class T, class R>
 __device__ __forceinline__ void weno_core(const T (&du)[Tr<P>::NS], const R *__restrict__ Pl,
-                                          const R *__restrict__ Ps, const R *__restrict__ Qs, T (&out)[Tr<P>::NC])
+                                          const R *__restrict__ Ps, const R *__restrict__ Qs, T eps,
+                                          T (&out)[Tr<P>::NC])
 {
     using Tt = Tr<P>;
-    const T ghi = T(WENO_GAMMA_HI), gs = T((1.0 - WENO_GAMMA_HI) / 7.0), eps = T(WENO_EPS);
+    const T ghi = T(WENO_GAMMA_HI), gs = T((1.0 - WENO_GAMMA_HI) / 7.0);
     T chi[Tt::NC];
 #pragma unroll
     for (int a = 0; a < Tt::NC; a++) {
@@ -316,6 +397,9 @@ inline RunSplit run_split(int n)
     if (n >= 64 && r >= 1 && r <= 8) return {n / 64, (n / 64) * 64, r};
     return {(n + 63) / 64, n, 0};
 }
+
+// the step's WENO-AO epsilon (0 selects the default)
+inline double weno_eps(const rg_step_params &p) { return p.weno_eps > 0.0 ? p.weno_eps : WENO_EPS_DEFAULT; }
 
 // Workgroups are dispatched round-robin over the eight XCDs, each with its
 // own L2.  Renumbering so that XCD x runs one contiguous range of logical

@@ -58,7 +58,7 @@ __global__ void bc_faces(DevGeom G, int bc, const double *Bf, double *Bo)
 template <int P, class R>
 __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restrict__ U, R *__restrict__ wc,
                                          const R *__restrict__ Pl, const R *__restrict__ Ps, const R *__restrict__ Qs,
-                                         int c, int k, int v)
+                                         R eps, int c, int k, int v)
 {
     using T = Tr<P>;
     const i64 z = (i64)c * G.K + k;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restr
         du[j] = R(Uv[z + dz] - u0);
     }
     R o[T::NC];
-    weno_core<P, R, R>(du, Pl, Ps, Qs, o);
+    weno_core<P, R, R>(du, Pl, Ps, Qs, eps, o);
     R *out = wc + (i64)v * T::NC * G.Z + z;
 #pragma unroll
     for (int a = 0; a < T::NC; a++) out[(i64)a * G.Z] = o[a];
@@ -84,7 +84,7 @@ __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restr
 template <int P, class R>
 __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restrict__ U, R *__restrict__ wc,
                                                 const R *__restrict__ PlA, const R *__restrict__ PsA,
-                                                const R *__restrict__ QsA, int nchunk, int nu, int nleft)
+                                                const R *__restrict__ QsA, R eps, int nchunk, int nu, int nleft)
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
@@ -102,12 +102,12 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
             // matrices would not fit in registers); they are re-read from cache
             int vo = 0;
             __asm__ __volatile__("" : "+s"(vo));
-            weno_var<P, R>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, c, G.g - 1 + kk, v);
+            weno_var<P, R>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, eps, c, G.g - 1 + kk, v);
         }
     } else {
         const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
         if (kk >= nu + nleft) return;
-        weno_var<P, R>(G, U, wc, Pl, Ps, Qs, c, G.g - 1 + kk, v);
+        weno_var<P, R>(G, U, wc, Pl, Ps, Qs, eps, c, G.g - 1 + kk, v);
     }
 }
 
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             nrm = G.fnA + (i64)ae * T::Q * 3;
             perm = G.col_perm + ((i64)cq * 4 + lf) * T::Q;
         }
-        R *o = ftr + (fid * 2 + side) * T::Q * 16;
+        R *o = ftr + ftr_at<P>(fid, 0, side);   // point q at o + 32 q
         // one row of quadrature points at a time: its weights are uniform
         // across the wavefront and stay in scalar registers
 #pragma unroll 1
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                 const int q = a + T::Q1 * b;
                 const int qc = perm ? perm[q] : q;
                 const double *n = nrm + qc * 3;
-                o[qc * 16 + v] = aq[a][0];
-                o[qc * 16 + 8 + v] = R(n[0]) * aq[a][1] + R(n[1]) * aq[a][2] + R(n[2]) * aq[a][3];
+                o[qc * 32 + v] = aq[a][0];
+                o[qc * 32 + 8 + v] = R(n[0]) * aq[a][1] + R(n[1]) * aq[a][2] + R(n[2]) * aq[a][3];
             }
         }
     }
@@ -557,112 +557,108 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             } else {
                 e = (i64)G.col_v[4 * cq + LocalEdges::CORNER[le - 8]] * G.K + kq;
             }
-            R *o = etr + (e * 4 + slot) * 3 * 11;
+            R *o = etr + etr_at(e, 0, slot);   // point p at o + 44 p
 #pragma unroll
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
 #pragma unroll
-                for (int v = 0; v < 11; v++) o[pc * 11 + v] = ae3[p][v];
+                for (int v = 0; v < 11; v++) o[pc * 44 + v] = ae3[p][v];
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- face fluxes
-// radial faces kf in [g, g+Nr], angular faces in shells [g, g+Nr-1]
+// HLL at every face quadrature point, one lane per point (each reads its
+// point's two adjacent side records), then the weighted sum over a face's
+// points in order.  256 / Q faces per block.
 template <int P, class R>
 __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
                                                  double *__restrict__ Phi)
 {
     using T = Tr<P>;
-    const int nrad = G.Nr + 1, nang = G.Nr;
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    i64 nR = (i64)G.ncol * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    i64 f;
-    const double *nrm, *fw;
-    if (t < nR) {
-        int c = (int)(t / nrad), kf = G.g + (int)(t % nrad);
-        f = (i64)c * (G.K + 1) + kf;
-        nrm = G.fnR + (i64)c * T::Q * 3;
-        fw = G.fwR + (i64)c * T::Q;
-    } else {
-        i64 u = t - nR;
-        int ae = (int)(u / nang), k = G.g + (int)(u % nang);
-        f = G.NRF + (i64)ae * G.K + k;
-        nrm = G.fnA + (i64)ae * T::Q * 3;
-        fw = G.fwA + (i64)ae * T::Q;
-    }
-    double area = G.area[f], acc[8];
-#pragma unroll
-    for (int v = 0; v < 8; v++) acc[v] = 0.0;
-    for (int q = 0; q < T::Q; q++) {
+    constexpr int FPB = 256 / T::Q;
+    __shared__ double s_q[FPB * T::Q][9];
+    const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
+    const int tid = threadIdx.x, fl = tid / T::Q, q = tid % T::Q;
+    const i64 t = (i64)blockIdx.x * FPB + fl;
+    if (fl < FPB && t < nff) {
+        const double *nrm, *fw;
+        const i64 f = flux_face<P>(G, t, nrm, fw);
+        const R *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
         double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            const R *a = ftr + ((f * 2 + 0) * T::Q + q) * 16, *b = ftr + ((f * 2 + 1) * T::Q + q) * 16;
             UL[v] = a[v];
             FL[v] = a[8 + v];
             UR[v] = b[v];
             FR[v] = b[8 + v];
         }
         dev_hll<double>(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
-        double w = fw[q] * area;
+        const double w = fw[q] * G.area[f];
 #pragma unroll
-        for (int v = 0; v < 8; v++) acc[v] += w * Fs[v];
+        for (int v = 0; v < 8; v++) s_q[tid][v] = w * Fs[v];
     }
+    __syncthreads();
+    // one thread per (face, variable), faces fastest
+    for (int j = tid; j < FPB * 8; j += 256) {
+        const int f2 = j % FPB, v = j / FPB;
+        const i64 t2 = (i64)blockIdx.x * FPB + f2;
+        if (t2 >= nff) continue;
+        const double *nrm, *fw;
+        const i64 f = flux_face<P>(G, t2, nrm, fw);
+        double acc = 0.0;
 #pragma unroll
-    for (int v = 0; v < 8; v++) Phi[(i64)v * G.NF + f] = acc[v];
+        for (int qq = 0; qq < T::Q; qq++) acc += s_q[f2 * T::Q + qq][v];
+        Phi[(i64)v * G.NF + f] = acc;
+    }
 }
 
 // ---------------------------------------------------------------- edge electric fields
-// radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr]
+// one lane per (edge, Simpson point), 64 edges per block, then the line
+// integral summed over the three points in order
 template <class R>
-__global__ __launch_bounds__(256) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam)
+__global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam)
 {
-    const int nrad = G.Nr, nang = G.Nr + 1;
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    i64 nR = (i64)G.nv * nrad;
-    if (t >= nR + (i64)G.nae * nang) return;
-    const double simpson[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
-    i64 e;
-    int nzs;
-    const double *frame[3];
-    double wl[3];
-    const double *N3 = nullptr;
-    if (t < nR) {
-        int v = (int)(t / nrad), k = G.g + (int)(t % nrad);
-        e = (i64)v * G.K + k;
-        nzs = G.v_ncol[v];
-        double len = G.radius[k + 1] - G.radius[k];
-        for (int p = 0; p < 3; p++) { frame[p] = G.vF + (i64)v * 9; wl[p] = simpson[p] * len; }
-        N3 = G.vN3 + (i64)v * 9;
-    } else {
-        i64 u = t - nR;
-        int ae = (int)(u / nang), kf = G.g + (int)(u % nang);
-        e = G.NRE + (i64)ae * (G.K + 1) + kf;
-        nzs = 4;
-        double s = G.radius[kf] / G.radius[0];
-        for (int p = 0; p < 3; p++) { frame[p] = G.aeF + ((i64)ae * 3 + p) * 9; wl[p] = G.aeW[(i64)ae * 3 + p] * s; }
-    }
-    double gsum = 0.0;
-    for (int p = 0; p < 3; p++) {
+    __shared__ double s_p[192];
+    const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
+    const int tid = threadIdx.x, el = tid / 3, p = tid % 3;
+    const i64 t = (i64)blockIdx.x * 64 + el;
+    if (t < nee) {
+        const double *frame, *N3;
+        double wl;
+        int nzs;
+        const i64 e = emf_edge(G, t, p, frame, wl, nzs, N3);
         double U[4][8], E[4][3], Et[4];
-        const double *tt = frame[p] + 6;
+        const double *tt = frame + 6;
         // all four slots are read (a three-zone edge leaves slot 3 unused)
+        const R *rec = etr + etr_at(e, p, 0);
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            const R *rec = etr + ((e * 4 + s) * 3 + p) * 11;
 #pragma unroll
-            for (int v = 0; v < 8; v++) U[s][v] = rec[v];
+            for (int v = 0; v < 8; v++) U[s][v] = rec[s * 11 + v];
 #pragma unroll
-            for (int v = 0; v < 3; v++) E[s][v] = rec[8 + v];
+            for (int v = 0; v < 3; v++) E[s][v] = rec[s * 11 + 8 + v];
             Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
         }
-        double Es = (nzs == 4) ? emf4<double>(U, Et, frame[p], gam) : emf3<double>(U, E, N3, tt, gam);
-        gsum += wl[p] * Es;
+        const double Es = (nzs == 4) ? emf4<double>(U, Et, frame, gam) : emf3<double>(U, E, N3, tt, gam);
+        s_p[tid] = wl * Es;
     }
-    Gam[e] = gsum;
+    __syncthreads();
+    if (tid < 64) {
+        const i64 t2 = (i64)blockIdx.x * 64 + tid;
+        if (t2 < nee) {
+            const double *frame, *N3;
+            double wl;
+            int nzs;
+            const i64 e = emf_edge(G, t2, 0, frame, wl, nzs, N3);
+            double gsum = 0.0;
+            gsum += s_p[3 * tid];
+            gsum += s_p[3 * tid + 1];
+            gsum += s_p[3 * tid + 2];
+            Gam[e] = gsum;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- updates
@@ -902,8 +898,8 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     const i64 nzr = (i64)G.ncol * (G.Nr + 2);
     const RunSplit wr = run_split(G.Nr + 2);
     weno_cols<P, R><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
-        G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF), wr.nchunk,
-        wr.nu, wr.nleft);
+        G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF),
+        R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
     const RunSplit br = run_split(G.Nr + 3), ba = run_split(G.Nr + 2);
@@ -923,11 +919,11 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     if (front_only) return RG_OK;
     sm.mark(5, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
-    face_flux<P, R><<<nblocks(nff, 256), 256, 0, st>>>(G, gam, ftr, g->Phi);
+    face_flux<P, R><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi);
     RG_LAUNCH_CHECK();
     sm.mark(6, st);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
-    edge_emf<R><<<nblocks(nee, 256), 256, 0, st>>>(G, gam, etr, g->Gam);
+    edge_emf<R><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam);
     RG_LAUNCH_CHECK();
     sm.mark(7, st);
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
