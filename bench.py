@@ -30,31 +30,43 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}>", "face_bnodal": "face_bnodal_runs<{p}, false>",
-                "bmap": "bmap<{p}>", "predictor": "predictor<{p}>", "face_flux": "face_flux<{p}>",
-                "edge_emf": "edge_emf", "update_ct": "zone_update"}
+STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}, double>",
+                "face_bnodal": "face_bnodal_runs<{p}, false, double>", "bmap": "bmap<{p}, double>",
+                "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double>",
+                "edge_emf": "edge_emf<double>", "update_ct": "zone_update"}
+
+
+KERNEL_SOURCES = ("step.hip", "mhd_device.hpp", "dtab.hpp")
+
+
+def kernel_sources_sha256():
+    """hash of the sources the step's kernels are compiled from"""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1905_02504_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
     against a copy of known size) from the committed rocprofv3 summary, or None
-    when the kernel source has changed since the counters were taken."""
-    import hashlib
+    when the kernel sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_step_order4_6x128cubed.md")
-    src = os.path.join(ROOT, "paper_1905_02504_amd", "csrc", "step.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_sources_sha256()
+    head = f"traffic {kernel} "
     for line in open(path):
-        if line.startswith(f"traffic {kernel} "):
-            kv = dict(t.split("=", 1) for t in line.split()[2:])
-            if kv.get("step_hip_sha256") != sha:
+        if line.startswith(head):
+            kv = dict(t.split("=", 1) for t in line[len(head):].split())
+            if kv.get("kernel_sources_sha256") != sha:
                 return None
             return float(kv["read_bytes"]) + float(kv["write_bytes"])
     return None
 
 
-def cpu_baseline(order, sample_n=8, sample_nr=8):
+def cpu_baseline(order, sample_n=16, sample_nr=16):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
     import rg_inputs as RI
@@ -75,6 +87,51 @@ def cpu_baseline(order, sample_n=8, sample_nr=8):
                       f"(Alfven wave + noise), {el:.2f} s, geometry excluded"}
 
 
+def time_adjoint(reps=5):
+    """Forward step and its adjoint (rg_step_adjoint, forward recomputation
+    included) on the differentiation workload: third order, 6 x 32 x 32 x 32
+    zones, Alfven wave + 1% noise, fixed dt.  HIP events on the stream the
+    library runs on."""
+    import torch
+    import paper_1905_02504_amd as R
+    import rg_inputs as RI
+    sh = R.ShellMHD(32, 32, 3, n_ghost=2)
+    prob = RI.alfven_problem()
+    U_h, Bf_h = sh.init_alfven(prob, noise=RI.white_noise(sh.nz), noise_amp=0.01)
+    U, Bf = torch.from_numpy(U_h).cuda(), torch.from_numpy(Bf_h).cuda()
+    gam = prob["gamma"]
+    dt = sh.cfl_dt(U, 0.4, gam)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    gU1 = torch.rand(U.shape, dtype=torch.float64, device="cuda", generator=gen)
+    gB1 = torch.rand(Bf.shape, dtype=torch.float64, device="cuda", generator=gen)
+    U1, B1 = torch.empty_like(U), torch.empty_like(Bf)
+    gU, gB = torch.empty_like(U), torch.empty_like(Bf)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_fwd = timed(lambda: sh.step(U, Bf, dt, gamma=gam, U_out=U1, Bf_out=B1))
+    t_adj = timed(lambda: sh.step_adjoint(U, Bf, gU1, gB1, dt, gamma=gam, gU=gU, gBf=gB))
+    if not (torch.isfinite(gU).all() and torch.isfinite(gB).all()):
+        raise RuntimeError("non-finite adjoint")
+    interior = 6 * 32 * 32 * 32
+    sh.close()
+    return {"workload": "third order, 6x32x32 angular x 32 radial = 196608 zones, Alfven wave + 1% noise, "
+                        "fixed dt; adjoint includes its recomputation of the step up to the predictor",
+            "ms_per_step": t_fwd, "ms_per_adjoint": t_adj, "adjoint_over_step": t_adj / t_fwd,
+            "adjoint_zone_updates_per_s": interior / (t_adj * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +143,7 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-form run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--calib", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -201,6 +259,13 @@ def main():
                  "div_b_rel_max": diag32["div_rel_max"],
                  "stage_ms_per_step": {k: round(v / nrec32, 4) for k, v in stage32.items()}}
         shell32.close()
+    adjoint = None
+    if not args.no_adjoint:
+        if args.no_mixed:
+            shell.close()   # (the FP32 run closed it otherwise)
+        adjoint = time_adjoint()
+        log(f"[bench] adjoint (order 3, 6x32^3): step {adjoint['ms_per_step']:.2f} ms, "
+            f"adjoint {adjoint['ms_per_adjoint']:.2f} ms ({adjoint['adjoint_over_step']:.1f}x)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,
@@ -222,6 +287,7 @@ def main():
         "roofline": roof,
         "div_b_rel_max": diag64["div_rel_max"],
         "mixed": mixed,
+        "adjoint": adjoint,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle sample)")

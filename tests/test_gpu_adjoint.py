@@ -162,8 +162,8 @@ def test_adjoint_against_oracle_differences():
     import paper_1905_02504_amd as R
     from oracle import oracle as O
     from tests.parity_util import Mapping
-    order, n_ang, n_rad = 3, 4, 4
-    say("[adjoint] oracle FD, order 3, 6x4x4x4")
+    order, n_ang, n_rad = 3, 8, 8
+    say("[adjoint] oracle FD, order 3, 6x8x8x8")
     om = O.OracleMesh(n_ang, n_rad, order=order, n_ghost=order - 1)
     lib = R.ShellMHD(n_ang, n_rad, order, n_ghost=order - 1)
     mp = Mapping(lib, om)
@@ -259,15 +259,16 @@ def test_rollout_gradient_third_order_6x32cubed_4_steps():
     Alfven state, dt fixed from the initial state).
 
     (a) The autograd gradient equals the hand-chained adjoints bit for bit
-    (one checkpoint per step, forward recomputed).  (b) Directional
-    derivatives against central differences of the loss, for directions
-    confined to a patch of the outer shells.  At this size a step has millions
-    of MinMod and HLL decisions, and a global direction flips some of them
-    within +-1e-6; the patch and h = 1e-8 (with the loss difference formed
-    without cancellation) keep the quotient clear of flips.  The difference
-    is measured against sum |g * d|, the size of the terms of the inner
-    product (a quotient at h = 1e-8 carries rounding of about 1e-8 of each
-    term, which a small net derivative would otherwise magnify)."""
+    (one checkpoint per step, forward recomputed).  (b) 32 seeded directional
+    derivatives against central differences of the loss: 16 in the initial
+    conserved variables and 16 in the vector potential (edge line integrals
+    of A, mapped to face B by rg_stokes; their gradient is rg_stokes_T of the
+    face-B gradient).  Each direction is confined to a ball of zones / edges
+    around a seeded point of the outer shells: at this size a step takes
+    millions of MinMod and HLL decisions, and a global direction flips some
+    of them within +-h.  The quotients use h = 1e-7 and 1e-8 with the loss
+    difference formed without cancellation, and the difference is measured
+    against sum |g * d|, the size of the terms of the inner product."""
     say("[adjoint] rollout, order 3, 6x32^3, 4 steps")
     lib, U0, B0, gam, dt, lo, gU, gB = rollout_case(32, 32)
     assert torch.isfinite(gU).all() and torch.isfinite(gB).all()
@@ -285,18 +286,38 @@ def test_rollout_gradient_third_order_6x32cubed_4_steps():
         for n in range(3, -1, -1):
             gUn, gBn = lib.step_adjoint(states[n][0], states[n][1], gUn, gBn, dt, gamma=gam)
     assert torch.equal(gUn, gU) and torch.equal(gBn, gB)
-    # (b) patch directions against differences
+    # (b) localised directions against differences
+    gA = lib.stokes_T(gB.contiguous())
+    zc, _ = lib.zone_data()
+    em, _ = lib.edge_data()
     k = lib.shells()
-    col = np.arange(lib.nz) // lib.K
-    patch = torch.from_numpy((col < 96) & (k >= lib.g + lib.n_rad - 6)).cuda()
+    outer_h = ((k >= lib.g + lib.n_rad - 4) & (k < lib.g + lib.n_rad))
+    rng = np.random.default_rng(600)
+    centres = zc[rng.choice(np.where(outer_h)[0], 32, replace=False)]
+    brms = B0.pow(2).mean().sqrt()
     worst = 0.0
-    for d in range(4):
-        dU, dB = directions(U0, B0, 500 + 2 * d)
-        dU = (dU * patch).contiguous()
-        dB = torch.zeros_like(dB)
-        a = float((gU * dU).sum())
-        terms = float((gU * dU).abs().sum())
-        fd = rollout_fd(lib, U0, B0, gam, dt, lo, dU, dB, 1e-8)
-        say(f"[adjoint] rollout direction {d}: autograd {a:.12e} FD {fd:.12e} (sum of |terms| {terms:.3e})")
-        worst = max(worst, abs(a - fd) / terms)
+    for d in range(32):
+        x0 = centres[d]
+        if d < 16:
+            near = torch.from_numpy(np.linalg.norm(zc - x0, axis=1) < 0.15).cuda()
+            dU, _ = directions(U0, B0, 700 + 2 * d)
+            dU = (dU * near).contiguous()
+            dB = torch.zeros_like(B0)
+            a = float((gU * dU).sum())
+            terms = float((gU * dU).abs().sum())
+        else:
+            near = torch.from_numpy(np.linalg.norm(em - x0, axis=1) < 0.15).cuda()
+            dA = (seeded((lib.ne,), 700 + 2 * d) * near).contiguous()
+            dB = lib.stokes(dA)
+            scale = float(brms / dB.pow(2).mean().sqrt())
+            dA = (dA * scale).contiguous()
+            dB = (dB * scale).contiguous()
+            dU = torch.zeros_like(U0)
+            a = float((gA * dA).sum())
+            terms = float((gB * dB).abs().sum())
+        fd = [rollout_fd(lib, U0, B0, gam, dt, lo, dU, dB, h) for h in (1e-7, 1e-8)]
+        err = min(abs(a - f) for f in fd) / terms
+        say(f"[adjoint] rollout direction {d} ({'U' if d < 16 else 'A'}): autograd {a:.12e} "
+            f"FD {fd[0]:.12e} / {fd[1]:.12e}, difference / sum |terms| {err:.2e}")
+        worst = max(worst, err)
     assert worst < TOL
