@@ -60,8 +60,9 @@ __host__ __device__ __forceinline__ long long ftr_at(long long f, int q, int sid
 }
 __host__ __device__ __forceinline__ long long etr_at(long long e, int p, int slot) { return ((e * 3 + p) * 4 + slot) * 11; }
 
-// Faces of the flux stage: radial faces kf in [g, g+Nr], angular faces in shells [g, g+Nr-1]; face
-// index t of that range -> face id, unit normals and weights of its points
+// Faces of the flux stage (radial faces kf in [g, g+Nr], angular faces in
+// shells [g, g+Nr-1]): face index t of that range -> face id, unit normals
+// and weights of its quadrature points
 template <int P>
 __device__ __forceinline__ i64 flux_face(const DevGeom &G, i64 t, const double *&nrm, const double *&fw)
 {
@@ -81,10 +82,10 @@ __device__ __forceinline__ i64 flux_face(const DevGeom &G, i64 t, const double *
     return G.NRF + (i64)ae * G.K + k;
 }
 
-// Edges of the EMF stage: radial edges in shells [g, g+Nr-1], angular edges at interfaces [g, g+Nr];
-// edge index t of that range -> edge id, the frame and line weight of its
-// Simpson point p, number of zones around it (3 or 4) and, at valence-3
-// vertices, the three face normals
+// Edges of the EMF stage (radial edges in shells [g, g+Nr-1], angular edges at
+// interfaces [g, g+Nr]): edge index t of that range -> edge id, the frame and
+// line weight of its Simpson point p, the number of zones around it (3 or 4)
+// and, at valence-3 vertices, the three face normals
 __device__ __forceinline__ i64 emf_edge(const DevGeom &G, i64 t, int p, const double *&frame, double &wl, int &nzs,
                                         const double *&N3)
 {

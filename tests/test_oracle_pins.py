@@ -234,6 +234,25 @@ def test_lsq_reproduces_polynomials(which, request):
 
 
 @pytest.mark.parametrize("which", ["mesh3", "mesh4"])
+def test_weno_weights_tend_to_linear_weights_as_eps_dominates(which, request):
+    """The nonlinear weights gamma_s / (beta_s + eps)^2 tend to the linear ones
+    when eps dominates every smoothness indicator: the reconstruction then
+    equals the linear-weight mode up to O(beta / eps), whatever the data."""
+    m = request.getfixturevalue(which)
+    rng = np.random.default_rng(11)
+    cen, vol, shell, _ = m.zones()
+    z = int(np.where(shell == m.n_ghost + 1)[0][7])
+    pts = cen[z] + 0.3 * vol[z] ** (1 / 3) * rng.uniform(-1, 1, size=(5, 3))
+    U = 1.0 + 0.5 * rng.uniform(-1, 1, size=(8, m.nz))      # rough data: beta = O(0.1)
+    Bf = rng.uniform(-1, 1, size=m.nf)
+    lin, _ = m.recon(U, Bf, z, pts, flags=O.FLAG_LINEAR_WEIGHTS)
+    big, _ = m.recon(U, Bf, z, pts, flags=0, weno_eps=1e8)
+    small, _ = m.recon(U, Bf, z, pts, flags=0, weno_eps=1e-12)
+    np.testing.assert_allclose(big, lin, rtol=0, atol=1e-7)
+    assert np.abs(small - lin).max() > 1e-3                   # on rough data the weights do act
+
+
+@pytest.mark.parametrize("which", ["mesh3", "mesh4"])
 def test_divergence_free_reconstruction_is_exact_for_divfree_polynomials(which, request):
     """With consistent face data, the constrained least squares of Section IV
     returns any divergence-free polynomial of degree <= p-1 exactly."""

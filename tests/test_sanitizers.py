@@ -1,0 +1,144 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+
+Two small drivers are compiled with -fsanitize=address,undefined and run:
+the oracle (one third- and one fourth-order step on tiny meshes), and the
+library's host side (mesh build, geometry precompute without a device, the
+host initialiser, argument errors) with the device launchers replaced by
+stubs that refuse.  A sanitizer report makes the run exit non-zero.
+"""
+import os
+import shutil
+import subprocess
+import textwrap
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1905_02504_amd", "csrc")
+ODIR = os.path.join(ROOT, "oracle")
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g", "-O1"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23",
+           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1:exitcode=24", OMP_NUM_THREADS="2")
+
+pytestmark = pytest.mark.slow
+
+ORACLE_DRIVER = textwrap.dedent(r"""
+    #include <stdint.h>
+    #include <stdio.h>
+    #include <stdlib.h>
+    typedef struct rgo_mesh rgo_mesh;
+    rgo_mesh *rgo_create(int, int, double, double, int, int, int);
+    void rgo_destroy(rgo_mesh *);
+    void rgo_sizes(const rgo_mesh *, int64_t *);
+    int rgo_step(const rgo_mesh *, double, double, int, int, double, const double *, const double *, double *,
+                 double *, double *, double *);
+    static int run(int order, int ghost) {
+        rgo_mesh *m = rgo_create(2, 3, 1.0, 2.0, ghost, order - 1, order);
+        if (!m) return 1;
+        int64_t s[8];
+        rgo_sizes(m, s);
+        int64_t nz = s[0], nf = s[1];
+        double *U = calloc(8 * nz, sizeof(double)), *Bf = calloc(nf, sizeof(double));
+        double *Uo = calloc(8 * nz, sizeof(double)), *Bo = calloc(nf, sizeof(double));
+        for (int64_t z = 0; z < nz; z++) {
+            double rho = 1.0 + 0.1 * ((z * 37) % 11) / 11.0, vx = 0.05 * ((z * 13) % 7) / 7.0;
+            U[z] = rho; U[nz + z] = rho * vx; U[4 * nz + z] = 1.5 + 0.5 * rho * vx * vx;
+        }
+        int rc = rgo_step(m, 5.0 / 3.0, 1e-3, 0, 0, 1e-4, U, Bf, Uo, Bo, NULL, NULL);
+        for (int64_t i = 0; i < 8 * nz; i++) if (Uo[i] != Uo[i]) rc = 2;
+        free(U); free(Bf); free(Uo); free(Bo);
+        rgo_destroy(m);
+        return rc;
+    }
+    int main(void) {
+        int rc = run(3, 2) | run(4, 3);
+        printf("oracle driver rc=%d\n", rc);
+        return rc;
+    }
+""")
+
+LIB_DRIVER = textwrap.dedent(r"""
+    #include <cstdio>
+    #include <vector>
+    #include "rg_geom_host.hpp"
+    namespace rg {
+    // the device side is not linked: every launcher refuses
+    rg_status launch_step(rg_geom *, const rg_step_params &, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status profile_end(rg_geom *, double *, int *) { return RG_ENOTSUP; }
+    rg_status launch_cfl(rg_geom *, const double *, double, double, void *, double *) { return RG_ENOTSUP; }
+    rg_status launch_step_front(rg_geom *, const rg_step_params &, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_adjoint(rg_geom *, const rg_step_params &, const double *, const double *, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_stokes(rg_geom *, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_stokes_T(rg_geom *, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_diag(rg_geom *, const double *, const double *, double, void *, rg_diag_out *) { return RG_ENOTSUP; }
+    }
+    static int run(int order) {
+        rg_mesh_desc d{4, 3, 1.0, 2.0, 0, order - 1, 3};
+        rg_mesh *m = nullptr;
+        if (rg_mesh_build(&d, &m) != RG_OK) return 1;
+        rg_mesh_info info;
+        rg_mesh_get_info(m, &info);
+        rg_geom *g = nullptr;
+        if (rg_geom_precompute_host(m, order, &g) != RG_OK) { std::printf("%s\n", rg_last_error()); return 2; }
+        std::vector<double> cen(3 * info.n_zones), vol(info.n_zones), U(8 * info.n_zones), Bf(info.n_faces);
+        std::vector<double> fc(3 * info.n_faces), fn(3 * info.n_faces), fa(info.n_faces);
+        std::vector<double> em(3 * info.n_edges), et(3 * info.n_edges);
+        rg_geom_zone_data(g, cen.data(), vol.data());
+        rg_geom_face_data(g, fc.data(), fn.data(), fa.data());
+        rg_geom_edge_data(g, em.data(), et.data());
+        const double frame[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        int rc = rg_init_alfven(g, frame, 1.0, 0.1, 1.0, 0.1, 1.0, 5.0 / 3.0, 0.0, nullptr, 0.0, U.data(), Bf.data());
+        // without device data the step entry points refuse
+        rg_step_params p{5.0 / 3.0, 1e-3, 0.0, 0, 0, 0.0};
+        if (rg_step(g, &p, U.data(), Bf.data(), U.data(), Bf.data(), nullptr) == RG_OK) rc = 3;
+        double work_f[RG_NSTAGES], work_b[RG_NSTAGES];
+        rg_geom_work(g, work_f, work_b);
+        rg_geom_free(g);
+        rg_mesh_free(m);
+        return rc;
+    }
+    int main() {
+        rg_mesh *m = nullptr;
+        rg_mesh_desc bad{12, 3, 1.0, 2.0, 0, 2, 3};
+        int rc = rg_mesh_build(&bad, &m) == RG_OK;
+        rc |= run(3) | run(4);
+        std::printf("library host driver rc=%d\n", rc);
+        return rc;
+    }
+""")
+
+
+def _need(tool):
+    if shutil.which(tool) is None:
+        pytest.skip(f"{tool} not available")
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    _need("gcc")
+    drv = tmp_path / "oracle_driver.c"
+    drv.write_text(ORACLE_DRIVER)
+    srcs = [os.path.join(ODIR, s) for s in ("la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "init.c", "oracle.c")]
+    exe = tmp_path / "oracle_driver"
+    subprocess.run(["gcc", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", *SAN, str(drv), *srcs, "-o", str(exe), "-lm"],
+                   check=True, capture_output=True)
+    res = subprocess.run([str(exe)], env=ENV, capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stdout + res.stderr[-4000:]
+
+
+def test_library_host_side_under_sanitizers(tmp_path):
+    _need("g++")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if not os.path.exists(os.path.join(rocm, "include", "hip", "hip_runtime_api.h")):
+        pytest.skip("HIP headers not available")
+    drv = tmp_path / "lib_driver.cpp"
+    drv.write_text(LIB_DRIVER)
+    srcs = [os.path.join(CSRC, s) for s in ("mesh.cpp", "refel.cpp", "geom.cpp", "init.cpp", "capi.cpp")]
+    exe = tmp_path / "lib_driver"
+    cmd = ["g++", "-std=c++17", "-fopenmp", *SAN, "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include",
+           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", str(drv), *srcs, "-o", str(exe),
+           f"-L{rocm}/lib", "-lamdhip64", f"-Wl,-rpath,{rocm}/lib"]
+    build = subprocess.run(cmd, capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr[-4000:]
+    env = dict(ENV, ASAN_OPTIONS="detect_leaks=0:exitcode=23")   # the HIP runtime's own allocations
+    res = subprocess.run([str(exe)], env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stdout + res.stderr[-4000:]
