@@ -9,7 +9,8 @@
 #include <string.h>
 
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam);
+                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
+                 unsigned char *fallback_zones);
 int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                   int npts, const double *pts, double *weno_vals, double *divB_vals);
 int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
@@ -160,10 +161,13 @@ double rgo_sphericity(const rgo_mesh *m, int samples)
     return worst;
 }
 
+/* flags: 1 linear WENO weights (checks), 2 first-order fallback; fallback_zones
+ * (may be NULL) receives 1 for every zone the fallback took */
 int rgo_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-             const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
+             const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
+             unsigned char *fallback_zones)
 {
-    return rgo_run_step(m, gamma, dt, bc_kind, flags, weno_eps, U, Bf, Uout, Bfout, dbgPhi, dbgGam);
+    return rgo_run_step(m, gamma, dt, bc_kind, flags, weno_eps, U, Bf, Uout, Bfout, dbgPhi, dbgGam, fallback_zones);
 }
 
 int rgo_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z, int npts,

@@ -59,7 +59,7 @@ def lib():
         L.rgo_sphericity.argtypes = [C.c_void_p, C.c_int]
         L.rgo_step.restype = C.c_int
         L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp,
-                               _dp, C.c_void_p, C.c_void_p]
+                               _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rgo_recon.restype = C.c_int
         L.rgo_recon.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
         L.rgo_divfree.restype = C.c_int
@@ -89,6 +89,10 @@ def lib():
 
 NVAR = 8
 FLAG_LINEAR_WEIGHTS = 1
+# a-posteriori first-order fallback for zones the high-order update would
+# leave with non-positive density or pressure (the step's own positivity
+# measure; the paper defers positivity to the ruggedised-WENO literature)
+FLAG_FALLBACK = 2
 # epsilon of the WENO-AO nonlinear weights w_s ~ gamma_s / (beta_s + eps)^2
 # (Section III defers the weights to the WENO-AO literature).  The smoothness
 # indicators are in units of the squared zone data; 1e-4 lets the weights
@@ -185,18 +189,23 @@ class OracleMesh:
         return U, Bf
 
     # the method -----------------------------------------------------------
-    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS):
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS, fallback=False):
+        """One step.  With fallback=True the first-order fallback is on and the
+        per-zone flags (uint8, 1 = the zone fell back) are returned last."""
         U = np.ascontiguousarray(U, np.float64); Bf = np.ascontiguousarray(Bf, np.float64)
         Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
         phi = np.zeros((self.nf, NVAR)) if debug else None
         gam = np.zeros(self.ne) if debug else None
+        fz = np.zeros(self.nz, np.uint8)
+        if fallback:
+            flags |= FLAG_FALLBACK
         rc = lib().rgo_step(self._h, gamma, dt, bc, flags, weno_eps, U, Bf, Uo, Bo,
-                            phi.ctypes.data if debug else None, gam.ctypes.data if debug else None)
+                            phi.ctypes.data if debug else None, gam.ctypes.data if debug else None,
+                            fz.ctypes.data)
         if rc != 0:
             raise RuntimeError("oracle step failed")
-        if debug:
-            return Uo, Bo, phi, gam
-        return Uo, Bo
+        out = (Uo, Bo, phi, gam) if debug else (Uo, Bo)
+        return out + (fz,) if fallback else out
 
     def recon(self, U, Bf, z, pts, flags=0, weno_eps=WENO_EPS):
         pts = np.ascontiguousarray(pts, np.float64)

@@ -26,6 +26,7 @@
 
 #define WENO_GAMMA_HI 0.85
 #define FLAG_LINEAR_WEIGHTS 1
+#define FLAG_FALLBACK 2
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
@@ -149,6 +150,7 @@ typedef struct {
     double *avgU, *avgF;    /* nz * N * 8, nz * N * 24 */
     double *Phi;            /* nf * 8 */
     double *Gam;            /* ne */
+    int first_order;        /* traces are the zones' states at t^n (the fallback's re-solve) */
 } step_ws;
 
 static int zone_of(const rgo_mesh *m, int qd, int k) { return qd * m->ktot + k; }
@@ -500,11 +502,28 @@ static void predictor_zone(step_ws *w, int z)
     free(Ua);
 }
 
-/* time-averaged state and flux of zone z at reference point xi */
+/* State of zone z at t^n as the step sees it: the density, momentum and
+ * energy averages after the boundary fill, and the mean of the
+ * divergence-free reconstruction of B (step 10 of Section IV.b) */
+static void zone_state(const step_ws *w, int z, double *U)
+{
+    const int nz = w->m->nz;
+    for (int v = 0; v < IBX; v++) U[v] = w->U[(size_t)v * nz + z];
+    for (int c = 0; c < 3; c++) U[IBX + c] = w->bc[((size_t)z * 3 + c) * w->nbx];
+}
+
+/* time-averaged state and flux of zone z at reference point xi; in the
+ * re-solve of the first-order fallback, the zone's constant state at t^n and
+ * the physical flux of that state instead */
 static void trace(const step_ws *w, int z, const double *xi, double *U, double F[3][NVAR])
 {
     const rgo_mesh *m = w->m;
     const int N = m->ref.N;
+    if (w->first_order) {
+        zone_state(w, z, U);
+        phys_flux(U, w->gamma, F);
+        return;
+    }
     for (int v = 0; v < NVAR; v++) { U[v] = 0.0; F[0][v] = F[1][v] = F[2][v] = 0.0; }
     for (int l = 0; l < N; l++) {
         double p = refel_psi(&m->ref, l, xi);
@@ -649,6 +668,26 @@ static void edge_emf(step_ws *w, int e)
     w->Gam[e] = G;
 }
 
+/* zone averages of zone z after the finite-volume update with the current
+ * face fluxes; zone B starts from the divergence-free reconstruction's mean
+ * (step 10 of Section IV.b) */
+static void update_zone(const step_ws *w, int z, double *u)
+{
+    const rgo_mesh *m = w->m;
+    const int nz = m->nz;
+    double acc[NVAR] = {0};
+    for (int lf = 0; lf < 6; lf++) {
+        int f = m->zone_face[6 * z + lf];
+        double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0;
+        for (int v = 0; v < NVAR; v++) acc[v] += sg * w->Phi[(size_t)f * NVAR + v];
+    }
+    const double *bcz = &w->bc[(size_t)z * 3 * w->nbx];
+    for (int v = 0; v < NVAR; v++) {
+        double base = (v >= IBX) ? bcz[(v - IBX) * w->nbx] : w->U[(size_t)v * nz + z];
+        u[v] = base - w->dt / m->vol[z] * acc[v];
+    }
+}
+
 /* ---------------- the step ---------------- */
 static void setup_bases(step_ws *w)
 {
@@ -671,7 +710,8 @@ static void setup_bases(step_ws *w)
 }
 
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam)
+                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
+                 unsigned char *fallback_zones)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
@@ -739,22 +779,50 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     for (int e = 0; e < ne; e++)
         if (eupd[e]) edge_emf(&w, e);
 
+    /* first-order fallback (flag FLAG_FALLBACK).  The paper leaves positivity
+     * to the ruggedised-WENO literature (Section I); this oracle follows the
+     * step's own definition: an interior zone is flagged when the update with
+     * the high-order fluxes would leave its density or pressure not positive
+     * (or not finite), and every face and edge of a flagged zone is solved
+     * again with the same Riemann solvers on the zones' constant states at
+     * t^n; the update below then takes those fluxes and electric fields */
+    char *bad = calloc(nz, 1);
+    if (flags & FLAG_FALLBACK) {
+        for (int z = 0; z < nz; z++) {
+            if (!upd[z]) continue;
+            double u[NVAR];
+            update_zone(&w, z, u);
+            bad[z] = !(u[IRHO] > 0.0 && pressure(u, gamma) > 0.0);
+        }
+        char *fbad = calloc(nf, 1), *ebad = calloc(ne, 1);
+        for (int z = 0; z < nz; z++)
+            if (bad[z])
+                for (int lf = 0; lf < 6; lf++) {
+                    int f = m->zone_face[6 * z + lf];
+                    fbad[f] = 1;
+                    for (int k = 0; k < 4; k++) ebad[m->face_edges[4 * f + k]] = 1;
+                }
+        w.first_order = 1;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int f = 0; f < nf; f++)
+            if (fbad[f]) face_flux(&w, f);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int e = 0; e < ne; e++)
+            if (ebad[e]) edge_emf(&w, e);
+        w.first_order = 0;
+        free(fbad); free(ebad);
+    }
+    if (fallback_zones) memcpy(fallback_zones, bad, nz);
+    free(bad);
+
     /* finite-volume update of the eight zone averages, zone B taken from the
      * divergence-free reconstruction (step 10 of Section IV.b) */
     memcpy(Uout, w.U, sizeof(double) * NVAR * nz);
     for (int z = 0; z < nz; z++) {
         if (!upd[z]) continue;
-        double acc[NVAR] = {0};
-        for (int lf = 0; lf < 6; lf++) {
-            int f = m->zone_face[6 * z + lf];
-            double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0;
-            for (int v = 0; v < NVAR; v++) acc[v] += sg * w.Phi[(size_t)f * NVAR + v];
-        }
-        const double *bcz = &w.bc[(size_t)z * 3 * w.nbx];
-        for (int v = 0; v < NVAR; v++) {
-            double base = (v >= IBX) ? bcz[(v - IBX) * w.nbx] : w.U[(size_t)v * nz + z];
-            Uout[(size_t)v * nz + z] = base - dt / m->vol[z] * acc[v];
-        }
+        double u[NVAR];
+        update_zone(&w, z, u);
+        for (int v = 0; v < NVAR; v++) Uout[(size_t)v * nz + z] = u[v];
     }
     /* constrained transport: Faraday's law on each face (eqs. 2.5-2.6) */
     memcpy(Bfout, w.Bf, sizeof(double) * nf);

@@ -9,6 +9,7 @@ into problem-definition parameters:
   re-expressed as homogeneous polynomials: f(x) = sum_k a_k x^e_k / |x|^deg_k
   over the 35 monomials of degree <= 4 listed by MONOMIALS;
 * the propagation axis and transverse frame of a circularly polarised wave;
+* the parameters of a magnetised blast and its piecewise-constant pressure;
 * per-zone white-noise arrays.
 
 The two consumers (the oracle under oracle/ and the library's field
@@ -150,6 +151,23 @@ def alfven_problem() -> dict:
     """Circularly polarised Alfven wave: B0 = 1 along a, dB = 0.1, rho = 1, p = 0.1."""
     return {"frame": wave_frame(), "rho": 1.0, "p": 0.1, "B0": 1.0, "dB": 0.1,
             "wavelength": 1.0, "gamma": 5.0 / 3.0}
+
+
+def blast_problem(p_in: float = 1000.0, radius: float = 0.1) -> dict:
+    """Magnetised blast, after the blast problem of Section VIII.b rescaled to the
+    shell 1 <= r <= 2: rho = 1, v = 0, p = 0.1, gamma = 1.4, uniform B of
+    magnitude 10 / sqrt(4 pi) along the seeded axis a (plasma beta 2p/B^2 about
+    0.025, rationalised units), and p = p_in inside the ball of the given
+    radius centred at 1.5 a."""
+    frame = wave_frame()
+    return {"frame": frame, "rho": 1.0, "p": 0.1, "B0": 10.0 / math.sqrt(4.0 * math.pi), "dB": 0.0,
+            "wavelength": 1.0, "gamma": 1.4, "p_in": p_in, "radius": radius, "centre": 1.5 * frame[2]}
+
+
+def blast_pressure(prob: dict, centroids: np.ndarray) -> np.ndarray:
+    """Per-zone pressure of the blast: p_in for zones whose centroid lies in the ball, p elsewhere."""
+    inside = np.linalg.norm(centroids - prob["centre"], axis=1) < prob["radius"]
+    return np.where(inside, prob["p_in"], prob["p"])
 
 
 def white_noise(n: int, seed: int = SEED_NOISE, count: int = 2) -> np.ndarray:
