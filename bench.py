@@ -32,8 +32,8 @@ def log(msg):
 
 STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}, double>",
                 "face_bnodal": "face_bnodal_runs<{p}, false, double>", "bmap": "bmap<{p}, double>",
-                "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double>",
-                "edge_emf": "edge_emf<double>", "update_ct": "zone_update"}
+                "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double, false>",
+                "edge_emf": "edge_emf<double, false>", "update_ct": "zone_update"}
 
 
 KERNEL_SOURCES = ("step.hip", "mhd_device.hpp", "dtab.hpp")

@@ -127,7 +127,27 @@ typedef struct {
     double weno_eps;  /* epsilon of the WENO-AO nonlinear weights
                          gamma_s / (beta_s + eps)^2 (Section III; beta in units of
                          the squared zone data); 0 selects 1e-4                   */
+    int32_t fallback; /* 0: off; 1: first-order fallback for positivity (below)  */
 } rg_step_params;
+
+/* First-order fallback (params->fallback = 1).  Section I leaves positive
+ * pressures under strong magnetic fields to ruggedised WENO schemes from
+ * other work; this step takes an a-posteriori per-zone order drop.  After the
+ * high-order face fluxes and edge electric fields are computed, every
+ * interior zone whose update with them would leave a density or pressure
+ * that is not positive (or not finite) is flagged; every face and every edge
+ * of a flagged zone is then solved again with the same HLL and
+ * multidimensional solvers, each trace replaced by its zone's constant state
+ * at t (the density, momentum and energy averages after the boundary fill
+ * and the mean of the divergence-free reconstruction of B).  A re-solved face
+ * can drive a neighbour negative, so the check is repeated with the new
+ * fluxes and the newly flagged zones are re-solved too, for up to 4 rounds
+ * (stopping when a round flags no new zone); the update and the constrained
+ * transport then take the final values.  Conservation and the
+ * discrete div B of the face field are kept; a flagged zone can still come
+ * out non-positive (rg_diag reports the minima).  With no zone flagged the
+ * result equals the plain step bit for bit; the extra passes cost a few
+ * per cent of the step.  rg_step_adjoint refuses it (RG_ENOTSUP). */
 
 /* One complete timestep (Section VI) on device buffers.
  * U, Bf: state at t (device, read only).  U_out, Bf_out: state at t + dt
@@ -178,6 +198,11 @@ rg_status rg_stokes_T(const rg_geom *geom, const double *gBf, double *g_edge_cir
  * the step did not compute are zero.  Asynchronous on `stream`. */
 rg_status rg_step_fluxes(const rg_geom *geom, double *Phi, double *Gam, void *stream);
 
+/* Device copy of the last rg_step's fallback flags, flags[n_zones] (uint8):
+ * 1 for every zone the first-order fallback took, 0 elsewhere (all 0 after a
+ * step with the fallback off).  Asynchronous on `stream`. */
+rg_status rg_step_fallback_zones(const rg_geom *geom, uint8_t *flags, void *stream);
+
 /* Timestep limit dt = cfl * min over interior zones of d_in / (|v| + c_f,max)
  * (Section VIII) for device state U; blocks until the result is on the host. */
 rg_status rg_cfl_dt(const rg_geom *geom, const double *U, double gamma, double cfl, void *stream, double *dt);
@@ -214,7 +239,8 @@ rg_status rg_diag(const rg_geom *geom, const double *U, const double *Bf, double
  * RG_NSTAGES stages: 0 boundary fill, 1 WENO-AO, 2 face nodal B,
  * 3 divergence-free B map (KKT solve and evaluation at the ADER nodes, one
  * kernel), 4 ADER predictor + traces (one kernel), 5 face HLL fluxes,
- * 6 edge EMFs, 7 FV update + CT.  rg_profile_end waits for the recorded
+ * 6 edge EMFs, 7 FV update + CT (with the passes of the first-order
+ * fallback when it is on).  rg_profile_end waits for the recorded
  * events, writes the summed milliseconds of each stage to ms[RG_NSTAGES]
  * and the number of recorded steps to *nsteps, releases the events and
  * stops recording. */

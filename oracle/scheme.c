@@ -27,6 +27,7 @@
 #define WENO_GAMMA_HI 0.85
 #define FLAG_LINEAR_WEIGHTS 1
 #define FLAG_FALLBACK 2
+#define FALLBACK_ROUNDS 4
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
@@ -782,34 +783,41 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     /* first-order fallback (flag FLAG_FALLBACK).  The paper leaves positivity
      * to the ruggedised-WENO literature (Section I); this oracle follows the
      * step's own definition: an interior zone is flagged when the update with
-     * the high-order fluxes would leave its density or pressure not positive
+     * the current fluxes would leave its density or pressure not positive
      * (or not finite), and every face and edge of a flagged zone is solved
      * again with the same Riemann solvers on the zones' constant states at
-     * t^n; the update below then takes those fluxes and electric fields */
+     * t^n.  A re-solved face can in turn drive a neighbour negative, so the
+     * check is repeated with the new fluxes, for at most FALLBACK_ROUNDS
+     * rounds and until a round flags no new zone; the update below then takes
+     * the final fluxes and electric fields */
     char *bad = calloc(nz, 1);
     if (flags & FLAG_FALLBACK) {
-        for (int z = 0; z < nz; z++) {
-            if (!upd[z]) continue;
-            double u[NVAR];
-            update_zone(&w, z, u);
-            bad[z] = !(u[IRHO] > 0.0 && pressure(u, gamma) > 0.0);
-        }
         char *fbad = calloc(nf, 1), *ebad = calloc(ne, 1);
-        for (int z = 0; z < nz; z++)
-            if (bad[z])
+        for (int round = 0; round < FALLBACK_ROUNDS; round++) {
+            int added = 0;
+            for (int z = 0; z < nz; z++) {
+                if (!upd[z] || bad[z]) continue;
+                double u[NVAR];
+                update_zone(&w, z, u);
+                if (u[IRHO] > 0.0 && pressure(u, gamma) > 0.0) continue;
+                bad[z] = 1;
+                added = 1;
                 for (int lf = 0; lf < 6; lf++) {
                     int f = m->zone_face[6 * z + lf];
                     fbad[f] = 1;
                     for (int k = 0; k < 4; k++) ebad[m->face_edges[4 * f + k]] = 1;
                 }
-        w.first_order = 1;
+            }
+            if (!added) break;
+            w.first_order = 1;
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int f = 0; f < nf; f++)
-            if (fbad[f]) face_flux(&w, f);
+            for (int f = 0; f < nf; f++)
+                if (fbad[f]) face_flux(&w, f);
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int e = 0; e < ne; e++)
-            if (ebad[e]) edge_emf(&w, e);
-        w.first_order = 0;
+            for (int e = 0; e < ne; e++)
+                if (ebad[e]) edge_emf(&w, e);
+            w.first_order = 0;
+        }
         free(fbad); free(ebad);
     }
     if (fallback_zones) memcpy(fallback_zones, bad, nz);

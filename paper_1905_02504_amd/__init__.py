@@ -103,8 +103,11 @@ class ShellMHD:
         return U, Bf
 
     # the step ------------------------------------------------------------------
-    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0, weno_eps=0.0):
-        """One timestep on torch.cuda float64 tensors; returns (U_out, Bf_out, dt)."""
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0, weno_eps=0.0,
+             fallback=False):
+        """One timestep on torch.cuda float64 tensors; returns (U_out, Bf_out, dt).
+        fallback=True turns on the first-order fallback for zones the high-order
+        update would leave with non-positive density or pressure."""
         import torch
         assert U.is_cuda and U.dtype == torch.float64 and U.is_contiguous() and U.shape == (8, self.nz)
         assert Bf.is_cuda and Bf.dtype == torch.float64 and Bf.is_contiguous() and Bf.shape == (self.nf,)
@@ -112,7 +115,7 @@ class ShellMHD:
             U_out = torch.empty_like(U)
         if Bf_out is None:
             Bf_out = torch.empty_like(Bf)
-        p = rg_step_params(gamma, dt, cfl, bc, n_picard, weno_eps)
+        p = rg_step_params(gamma, dt, cfl, bc, n_picard, weno_eps, int(bool(fallback)))
         N.rg_step(self._geom, p, U.data_ptr(), Bf.data_ptr(), U_out.data_ptr(), Bf_out.data_ptr(), _stream())
         return U_out, Bf_out, p.dt
 
@@ -129,7 +132,7 @@ class ShellMHD:
             gU = torch.empty_like(U)
         if gBf is None:
             gBf = torch.empty_like(Bf)
-        p = rg_step_params(gamma, dt, 0.0, bc, n_picard, weno_eps)
+        p = rg_step_params(gamma, dt, 0.0, bc, n_picard, weno_eps, 0)
         N.rg_step_adjoint(self._geom, p, U.data_ptr(), Bf.data_ptr(), gU1.data_ptr(), gBf1.data_ptr(),
                           gU.data_ptr(), gBf.data_ptr(), _stream())
         return gU, gBf
@@ -169,6 +172,13 @@ class ShellMHD:
         Gam = torch.zeros(self.ne, dtype=torch.float64, device="cuda")
         N.rg_step_fluxes(self._geom, Phi.data_ptr(), Gam.data_ptr(), _stream())
         return Phi, Gam
+
+    def fallback_zones(self):
+        """Per-zone flags (uint8 on the device) of the last step's first-order fallback."""
+        import torch
+        flags = torch.empty(self.nz, dtype=torch.uint8, device="cuda")
+        N.rg_step_fallback_zones(self._geom, flags.data_ptr(), _stream())
+        return flags
 
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())

@@ -379,7 +379,15 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
              alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
              alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red) &&
              alloc_zero(g, (size_t)ncol * (m.Nr + 2) * 3 * N, &g->bnode);
+        // face and edge marks contiguous (cleared together), zone flags at a
+        // 256-byte aligned offset after them
+        double *fb = nullptr;
+        const size_t marks = ((size_t)NF + NE + 255) / 256 * 256;
+        ok = ok && alloc_zero(g, (marks + Z + 7) / 8, &fb);
         if (!ok) { set_error("device allocation of the step work buffers failed"); free_geom(g); return RG_ENOMEM; }
+        g->ffl = reinterpret_cast<unsigned char *>(fb);
+        g->efl = g->ffl + NF;
+        g->zfl = g->ffl + marks;
     } catch (const std::bad_alloc &) {
         set_error("out of host memory");
         free_geom(g);
@@ -432,7 +440,7 @@ extern "C" rg_status rg_step(const rg_geom *geom, rg_step_params *params, const 
 {
     if (!geom || !params || !U || !Bf || !U_out || !Bf_out) { set_error("null argument"); return RG_EINVAL; }
     if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0 ||
-        !(params->weno_eps >= 0.0)) {
+        !(params->weno_eps >= 0.0) || params->fallback < 0 || params->fallback > 1) {
         set_error("invalid step parameters");
         return RG_EINVAL;
     }
@@ -485,6 +493,10 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
     rg_geom *g = const_cast<rg_geom *>(geom);
     if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
     if (g->mode != RG_MODE_FP64) { set_error("the adjoint is implemented for the FP64 form only"); return RG_ENOTSUP; }
+    if (params->fallback != 0) {
+        set_error("the first-order fallback has no adjoint (run the adjoint with fallback = 0)");
+        return RG_ENOTSUP;
+    }
     if ((const void *)gU_n == (const void *)gU_np1 || (const void *)gBf_n == (const void *)gBf_np1) {
         set_error("the adjoint cannot run in place");
         return RG_EINVAL;
@@ -516,6 +528,18 @@ extern "C" rg_status rg_step_fluxes(const rg_geom *g, double *Phi, double *Gam, 
         return RG_EDEVICE;
     }
     if (Gam && hipMemcpyAsync(Gam, g->Gam, sizeof(double) * g->d.NE, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        return RG_EDEVICE;
+    }
+    return RG_OK;
+}
+
+extern "C" rg_status rg_step_fallback_zones(const rg_geom *g, uint8_t *flags, void *stream)
+{
+    if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }
+    if (!flags) { set_error("null argument"); return RG_EINVAL; }
+    if (hipMemcpyAsync(flags, g->zfl, (size_t)g->d.Z, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)) !=
+        hipSuccess) {
         set_error("hipMemcpyAsync failed");
         return RG_EDEVICE;
     }

@@ -166,6 +166,11 @@ struct rg_geom {
     double *wcoef = nullptr, *bnod = nullptr, *ftr = nullptr, *etr = nullptr;
     double *Phi = nullptr, *Gam = nullptr, *zoneB = nullptr, *red = nullptr;
     double *bnode = nullptr;   // divergence-free B at the ADER nodes, [recon zone][3N]
+    // first-order fallback: per-zone flags [Z], marks of the faces [NF] and
+    // edges [NE] to solve again (one allocation), and whether zfl holds flags
+    // of a step that had the fallback on
+    unsigned char *zfl = nullptr, *ffl = nullptr, *efl = nullptr;
+    bool fb_dirty = false;
     rg::AdjBuffers adj;
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes

@@ -572,9 +572,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 // HLL at every face quadrature point, one lane per point (each reads its
 // point's two adjacent side records), then the weighted sum over a face's
 // points in order.  256 / Q faces per block.
-template <int P, class R>
+// MARKED: only faces with mark[f] set are solved and written (the re-solve of
+// the first-order fallback).
+template <int P, class R, bool MARKED = false>
 __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
-                                                 double *__restrict__ Phi)
+                                                 double *__restrict__ Phi, const unsigned char *__restrict__ mark = nullptr)
 {
     using T = Tr<P>;
     constexpr int FPB = 256 / T::Q;
@@ -582,9 +584,14 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
     const int tid = threadIdx.x, fl = tid / T::Q, q = tid % T::Q;
     const i64 t = (i64)blockIdx.x * FPB + fl;
-    if (fl < FPB && t < nff) {
-        const double *nrm, *fw;
-        const i64 f = flux_face<P>(G, t, nrm, fw);
+    const double *nrm = nullptr, *fw = nullptr;
+    i64 f = 0;
+    bool live = fl < FPB && t < nff;
+    if (live) {
+        f = flux_face<P>(G, t, nrm, fw);
+        if (MARKED) live = mark[f] != 0;
+    }
+    if (live) {
         const R *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
         double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
@@ -605,30 +612,38 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
         const int f2 = j % FPB, v = j / FPB;
         const i64 t2 = (i64)blockIdx.x * FPB + f2;
         if (t2 >= nff) continue;
-        const double *nrm, *fw;
-        const i64 f = flux_face<P>(G, t2, nrm, fw);
+        const double *nrm2, *fw2;
+        const i64 fo = flux_face<P>(G, t2, nrm2, fw2);
+        if (MARKED && !mark[fo]) continue;
         double acc = 0.0;
 #pragma unroll
         for (int qq = 0; qq < T::Q; qq++) acc += s_q[f2 * T::Q + qq][v];
-        Phi[(i64)v * G.NF + f] = acc;
+        Phi[(i64)v * G.NF + fo] = acc;
     }
 }
 
 // ---------------------------------------------------------------- edge electric fields
 // one lane per (edge, Simpson point), 64 edges per block, then the line
 // integral summed over the three points in order
-template <class R>
-__global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam)
+// MARKED: only edges with mark[e] set are solved and written
+template <class R, bool MARKED = false>
+__global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam,
+                                                const unsigned char *__restrict__ mark = nullptr)
 {
     __shared__ double s_p[192];
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     const int tid = threadIdx.x, el = tid / 3, p = tid % 3;
     const i64 t = (i64)blockIdx.x * 64 + el;
-    if (t < nee) {
-        const double *frame, *N3;
-        double wl;
-        int nzs;
-        const i64 e = emf_edge(G, t, p, frame, wl, nzs, N3);
+    const double *frame = nullptr, *N3 = nullptr;
+    double wl = 0.0;
+    int nzs = 4;
+    i64 e = 0;
+    bool live = t < nee;
+    if (live) {
+        e = emf_edge(G, t, p, frame, wl, nzs, N3);
+        if (MARKED) live = mark[e] != 0;
+    }
+    if (live) {
         double U[4][8], E[4][3], Et[4];
         const double *tt = frame + 6;
         // all four slots are read (a three-zone edge leaves slot 3 unused)
@@ -648,27 +663,29 @@ __global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *
     if (tid < 64) {
         const i64 t2 = (i64)blockIdx.x * 64 + tid;
         if (t2 < nee) {
-            const double *frame, *N3;
-            double wl;
-            int nzs;
-            const i64 e = emf_edge(G, t2, 0, frame, wl, nzs, N3);
+            const double *frame2, *N32;
+            double wl2;
+            int nzs2;
+            const i64 eo = emf_edge(G, t2, 0, frame2, wl2, nzs2, N32);
+            if (MARKED && !mark[eo]) return;
             double gsum = 0.0;
             gsum += s_p[3 * tid];
             gsum += s_p[3 * tid + 1];
             gsum += s_p[3 * tid + 2];
-            Gam[e] = gsum;
+            Gam[eo] = gsum;
         }
     }
 }
 
 // ---------------------------------------------------------------- updates
-__global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const double *__restrict__ Phi,
-                                                   const double *__restrict__ zoneB, double *Uo)
+// Zone averages of interior zone (c, k) after the finite-volume update with
+// the face fluxes Phi; zone B starts from the divergence-free reconstruction's
+// mean (step 10 of Section IV.b)
+__device__ __forceinline__ void updated_zone(const DevGeom &G, double dt, const double *__restrict__ Phi,
+                                             const double *__restrict__ zoneB, const double *Uo, int c, int k,
+                                             double u[8])
 {
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (i64)G.ncol * G.Nr) return;
-    int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
-    i64 z = (i64)c * G.K + k;
+    const i64 z = (i64)c * G.K + k;
     i64 f[6];
     double sg[6];
     for (int lf = 0; lf < 4; lf++) {
@@ -679,12 +696,149 @@ __global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const d
     f[5] = f[4] + 1;
     sg[4] = -1.0;
     sg[5] = 1.0;
-    double cfac = dt / G.vol[z];
+    const double cfac = dt / G.vol[z];
     for (int v = 0; v < 8; v++) {
         double acc = 0.0;
         for (int lf = 0; lf < 6; lf++) acc += sg[lf] * Phi[(i64)v * G.NF + f[lf]];
-        double base = v < 5 ? Uo[v * G.Z + z] : zoneB[(v - 5) * G.Z + z];
-        Uo[v * G.Z + z] = base - cfac * acc;
+        const double base = v < 5 ? Uo[v * G.Z + z] : zoneB[(v - 5) * G.Z + z];
+        u[v] = base - cfac * acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const double *__restrict__ Phi,
+                                                   const double *__restrict__ zoneB, double *Uo)
+{
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * G.Nr) return;
+    const int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
+    double u[8];
+    updated_zone(G, dt, Phi, zoneB, Uo, c, k, u);
+    const i64 z = (i64)c * G.K + k;
+    for (int v = 0; v < 8; v++) Uo[v * G.Z + z] = u[v];
+}
+
+// ---------------------------------------------------------------- first-order fallback
+// Section I leaves positivity under strong fields to ruggedised schemes from
+// other work; the step's fallback is an a-posteriori per-zone order drop.
+constexpr int FALLBACK_ROUNDS = 4;
+
+// zero n bytes (16 per lane; m 16-byte aligned)
+__global__ __launch_bounds__(256) void fb_clear(unsigned char *__restrict__ m, i64 n)
+{
+    const i64 i = ((i64)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (i + 16 <= n) {
+        *reinterpret_cast<uint4 *>(m + i) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (i64 j = i; j < n; j++) m[j] = 0;
+    }
+}
+
+// One round of the check.  Round 0 writes every zone's flag: 1 for an
+// interior zone whose update with the current fluxes leaves a density or
+// pressure that is not positive (NaN included).  A re-solved face can drive a
+// neighbour negative, so later rounds re-check the unflagged zones that touch
+// a marked face (the fluxes of every other zone are those of round 0, which
+// it passed) and add the bad ones.  A flagged zone marks its six faces and
+// twelve edges (every writer of a mark writes 1; marks of earlier rounds were
+// written by earlier launches, so what a zone reads does not depend on the
+// order of the lanes).
+__global__ __launch_bounds__(256) void fb_flag(DevGeom G, double dt, double gam, int round,
+                                               const double *__restrict__ Phi, const double *__restrict__ zoneB,
+                                               const double *__restrict__ Uo, unsigned char *__restrict__ zfl,
+                                               unsigned char *__restrict__ ffl, unsigned char *__restrict__ efl)
+{
+    const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= G.Z) return;
+    const int c = (int)(z / G.K), k = (int)(z % G.K);
+    if (k < G.g || k >= G.g + G.Nr) {
+        if (round == 0) zfl[z] = 0;
+        return;
+    }
+    i64 fid[6];
+    for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    fid[4] = (i64)c * (G.K + 1) + k;
+    fid[5] = fid[4] + 1;
+    if (round > 0) {
+        if (zfl[z]) return;
+        bool touched = false;
+        for (int lf = 0; lf < 6; lf++) touched |= ffl[fid[lf]] != 0;
+        if (!touched) return;
+    }
+    double u[8];
+    updated_zone(G, dt, Phi, zoneB, Uo, c, k, u);
+    const bool ok = u[0] > 0.0 && dev_pressure<double>(u, gam) > 0.0;
+    if (round == 0) zfl[z] = ok ? 0 : 1;
+    if (ok) return;
+    zfl[z] = 1;
+    for (int lf = 0; lf < 6; lf++) ffl[fid[lf]] = 1;
+    for (int le = 0; le < 8; le++)
+        efl[G.NRE + (i64)G.col_ae[4 * c + LocalEdges::FACE[le]] * (G.K + 1) + k + LocalEdges::UP[le]] = 1;
+    for (int j = 0; j < 4; j++) efl[(i64)G.col_v[4 * c + LocalEdges::CORNER[j]] * G.K + k] = 1;
+}
+
+// Constant traces for the re-solve: every zone of the predictor's range
+// (shells g-1 .. g+Nr) writes, on each of its marked faces and edges, its
+// state at t^n (density, momentum and energy averages of Uo before the
+// update, the divergence-free mean B) and the physical flux of that state in
+// the records the predictor fills (face: the state and the normal flux at each
+// quadrature point; edge: the state and E = (H[B_y], F[B_z], G[B_x]) at each
+// Simpson point).
+template <int P, class R>
+__global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const double *__restrict__ Uo,
+                                                 const double *__restrict__ zoneB, const unsigned char *__restrict__ ffl,
+                                                 const unsigned char *__restrict__ efl, R *__restrict__ ftr,
+                                                 R *__restrict__ etr)
+{
+    using T = Tr<P>;
+    const int KR = G.Nr + 2;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * KR) return;
+    const int c = (int)(t / KR), k = G.g - 1 + (int)(t % KR);
+    const i64 z = (i64)c * G.K + k;
+    i64 fid[6], eid[12];
+    for (int lf = 0; lf < 4; lf++) fid[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    fid[4] = (i64)c * (G.K + 1) + k;
+    fid[5] = fid[4] + 1;
+    for (int le = 0; le < 8; le++)
+        eid[le] = G.NRE + (i64)G.col_ae[4 * c + LocalEdges::FACE[le]] * (G.K + 1) + k + LocalEdges::UP[le];
+    for (int j = 0; j < 4; j++) eid[8 + j] = (i64)G.col_v[4 * c + LocalEdges::CORNER[j]] * G.K + k;
+    bool any = false;
+    for (int lf = 0; lf < 6; lf++) any |= ffl[fid[lf]] != 0;
+    for (int le = 0; le < 12; le++) any |= efl[eid[le]] != 0;
+    if (!any) return;
+    double u[8], F[3][8];
+    for (int v = 0; v < 5; v++) u[v] = Uo[v * G.Z + z];
+    for (int v = 5; v < 8; v++) u[v] = zoneB[(v - 5) * G.Z + z];
+    dev_flux<double>(u, gam, F);
+    for (int lf = 0; lf < 6; lf++) {
+        if (!ffl[fid[lf]]) continue;
+        int side;
+        const double *nrm;
+        if (lf >= 4) {
+            side = lf == 4 ? 1 : 0;
+            nrm = G.fnR + (i64)c * T::Q * 3;
+        } else {
+            side = G.col_side[4 * c + lf];
+            nrm = G.fnA + (i64)G.col_ae[4 * c + lf] * T::Q * 3;
+        }
+        R *o = ftr + ftr_at<P>(fid[lf], 0, side);   // point q at o + 32 q
+        for (int q = 0; q < T::Q; q++) {
+            const double *n = nrm + q * 3;
+            for (int v = 0; v < 8; v++) {
+                o[q * 32 + v] = R(u[v]);
+                o[q * 32 + 8 + v] = R(n[0] * F[0][v] + n[1] * F[1][v] + n[2] * F[2][v]);
+            }
+        }
+    }
+    for (int le = 0; le < 12; le++) {
+        if (!efl[eid[le]]) continue;
+        R *o = etr + etr_at(eid[le], 0, G.col_slot[(i64)c * 12 + le]);   // point p at o + 44 p
+        for (int p = 0; p < 3; p++) {
+            for (int v = 0; v < 8; v++) o[p * 44 + v] = R(u[v]);
+            o[p * 44 + 8] = R(F[2][6]);
+            o[p * 44 + 9] = R(F[0][7]);
+            o[p * 44 + 10] = R(F[1][5]);
+        }
     }
 }
 
@@ -926,6 +1080,24 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     edge_emf<R><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam);
     RG_LAUNCH_CHECK();
     sm.mark(7, st);
+    if (prm.fallback) {
+        fb_clear<<<nblocks((G.NF + G.NE + 15) / 16, 256), 256, 0, st>>>(g->ffl, G.NF + G.NE);
+        // a fixed number of rounds (no host synchronisation); a round that
+        // flags no new zone re-solves the same marks to the same values
+        for (int round = 0; round < FALLBACK_ROUNDS; round++) {
+            fb_flag<<<nblocks(G.Z, 256), 256, 0, st>>>(G, dt, gam, round, g->Phi, g->zoneB, Uo, g->zfl, g->ffl,
+                                                      g->efl);
+            fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->zoneB, g->ffl, g->efl, ftr, etr);
+            face_flux<P, R, true><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl);
+            edge_emf<R, true><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam, g->efl);
+            RG_LAUNCH_CHECK();
+        }
+        g->fb_dirty = true;
+    } else if (g->fb_dirty) {
+        fb_clear<<<nblocks((G.Z + 15) / 16, 256), 256, 0, st>>>(g->zfl, G.Z);
+        RG_LAUNCH_CHECK();
+        g->fb_dirty = false;
+    }
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
     face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
     RG_LAUNCH_CHECK();
