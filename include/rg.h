@@ -137,9 +137,11 @@ typedef struct {
  * interior zone whose update with them would leave a density or pressure
  * that is not positive (or not finite) is flagged; every face and every edge
  * of a flagged zone is then solved again with the same HLL and
- * multidimensional solvers, each trace replaced by its zone's constant state
- * at t (the density, momentum and energy averages after the boundary fill
- * and the mean of the divergence-free reconstruction of B).  A re-solved face
+ * multidimensional solvers, each trace replaced by its zone's conserved
+ * state at t (its eight averages after the boundary fill), and a flagged
+ * zone advances its B average from its own value rather than from the
+ * reconstruction's mean, so that its update is the first-order
+ * finite-volume scheme on its own averages.  A re-solved face
  * can drive a neighbour negative, so the check is repeated with the new
  * fluxes and the newly flagged zones are re-solved too, for up to 4 rounds
  * (stopping when a round flags no new zone); the update and the constrained

@@ -503,19 +503,17 @@ static void predictor_zone(step_ws *w, int z)
     free(Ua);
 }
 
-/* State of zone z at t^n as the step sees it: the density, momentum and
- * energy averages after the boundary fill, and the mean of the
- * divergence-free reconstruction of B (step 10 of Section IV.b) */
+/* Conserved state of zone z at t^n: its eight averages after the boundary
+ * fill (zone B as carried, consistent with the total energy) */
 static void zone_state(const step_ws *w, int z, double *U)
 {
     const int nz = w->m->nz;
-    for (int v = 0; v < IBX; v++) U[v] = w->U[(size_t)v * nz + z];
-    for (int c = 0; c < 3; c++) U[IBX + c] = w->bc[((size_t)z * 3 + c) * w->nbx];
+    for (int v = 0; v < NVAR; v++) U[v] = w->U[(size_t)v * nz + z];
 }
 
 /* time-averaged state and flux of zone z at reference point xi; in the
- * re-solve of the first-order fallback, the zone's constant state at t^n and
- * the physical flux of that state instead */
+ * re-solve of the first-order fallback, the zone's conserved state at t^n
+ * and the physical flux of that state instead */
 static void trace(const step_ws *w, int z, const double *xi, double *U, double F[3][NVAR])
 {
     const rgo_mesh *m = w->m;
@@ -671,8 +669,10 @@ static void edge_emf(step_ws *w, int e)
 
 /* zone averages of zone z after the finite-volume update with the current
  * face fluxes; zone B starts from the divergence-free reconstruction's mean
- * (step 10 of Section IV.b) */
-static void update_zone(const step_ws *w, int z, double *u)
+ * (step 10 of Section IV.b), or, for a zone of the first-order fallback
+ * (own != 0), from its own conserved B, so that its update is the
+ * first-order finite-volume scheme on its eight averages */
+static void update_zone(const step_ws *w, int z, int own, double *u)
 {
     const rgo_mesh *m = w->m;
     const int nz = m->nz;
@@ -684,7 +684,7 @@ static void update_zone(const step_ws *w, int z, double *u)
     }
     const double *bcz = &w->bc[(size_t)z * 3 * w->nbx];
     for (int v = 0; v < NVAR; v++) {
-        double base = (v >= IBX) ? bcz[(v - IBX) * w->nbx] : w->U[(size_t)v * nz + z];
+        double base = (v >= IBX && !own) ? bcz[(v - IBX) * w->nbx] : w->U[(size_t)v * nz + z];
         u[v] = base - w->dt / m->vol[z] * acc[v];
     }
 }
@@ -785,11 +785,13 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
      * step's own definition: an interior zone is flagged when the update with
      * the current fluxes would leave its density or pressure not positive
      * (or not finite), and every face and edge of a flagged zone is solved
-     * again with the same Riemann solvers on the zones' constant states at
-     * t^n.  A re-solved face can in turn drive a neighbour negative, so the
-     * check is repeated with the new fluxes, for at most FALLBACK_ROUNDS
-     * rounds and until a round flags no new zone; the update below then takes
-     * the final fluxes and electric fields */
+     * again with the same Riemann solvers on the zones' conserved states at
+     * t^n, and a flagged zone's B average is advanced from its own value
+     * (not the reconstruction's mean), so its update is the first-order
+     * finite-volume scheme.  A re-solved face can in turn drive a neighbour
+     * negative, so the check is repeated with the new fluxes, for at most
+     * FALLBACK_ROUNDS rounds and until a round flags no new zone; the update
+     * below then takes the final fluxes and electric fields */
     char *bad = calloc(nz, 1);
     if (flags & FLAG_FALLBACK) {
         char *fbad = calloc(nf, 1), *ebad = calloc(ne, 1);
@@ -798,7 +800,7 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
             for (int z = 0; z < nz; z++) {
                 if (!upd[z] || bad[z]) continue;
                 double u[NVAR];
-                update_zone(&w, z, u);
+                update_zone(&w, z, 0, u);
                 if (u[IRHO] > 0.0 && pressure(u, gamma) > 0.0) continue;
                 bad[z] = 1;
                 added = 1;
@@ -821,7 +823,6 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
         free(fbad); free(ebad);
     }
     if (fallback_zones) memcpy(fallback_zones, bad, nz);
-    free(bad);
 
     /* finite-volume update of the eight zone averages, zone B taken from the
      * divergence-free reconstruction (step 10 of Section IV.b) */
@@ -829,9 +830,10 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     for (int z = 0; z < nz; z++) {
         if (!upd[z]) continue;
         double u[NVAR];
-        update_zone(&w, z, u);
+        update_zone(&w, z, bad[z], u);
         for (int v = 0; v < NVAR; v++) Uout[(size_t)v * nz + z] = u[v];
     }
+    free(bad);
     /* constrained transport: Faraday's law on each face (eqs. 2.5-2.6) */
     memcpy(Bfout, w.Bf, sizeof(double) * nf);
     for (int f = 0; f < nf; f++) {

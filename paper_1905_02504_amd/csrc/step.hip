@@ -679,11 +679,10 @@ __global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *
 
 // ---------------------------------------------------------------- updates
 // Zone averages of interior zone (c, k) after the finite-volume update with
-// the face fluxes Phi; zone B starts from the divergence-free reconstruction's
-// mean (step 10 of Section IV.b)
+// the face fluxes Phi; zone B starts from Bbase, the divergence-free
+// reconstruction's mean (step 10 of Section IV.b) [3][Z]
 __device__ __forceinline__ void updated_zone(const DevGeom &G, double dt, const double *__restrict__ Phi,
-                                             const double *__restrict__ zoneB, const double *Uo, int c, int k,
-                                             double u[8])
+                                             const double *Bbase, const double *Uo, int c, int k, double u[8])
 {
     const i64 z = (i64)c * G.K + k;
     i64 f[6];
@@ -700,20 +699,25 @@ __device__ __forceinline__ void updated_zone(const DevGeom &G, double dt, const 
     for (int v = 0; v < 8; v++) {
         double acc = 0.0;
         for (int lf = 0; lf < 6; lf++) acc += sg[lf] * Phi[(i64)v * G.NF + f[lf]];
-        const double base = v < 5 ? Uo[v * G.Z + z] : zoneB[(v - 5) * G.Z + z];
+        const double base = v < 5 ? Uo[v * G.Z + z] : Bbase[(v - 5) * G.Z + z];
         u[v] = base - cfac * acc;
     }
 }
 
+// zfl (null without the fallback): a flagged zone advances its own B average
+// instead of the reconstruction's mean, so that its update is the first-order
+// finite-volume scheme on its eight averages
 __global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const double *__restrict__ Phi,
-                                                   const double *__restrict__ zoneB, double *Uo)
+                                                   const double *__restrict__ zoneB, double *Uo,
+                                                   const unsigned char *__restrict__ zfl)
 {
     i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (i64)G.ncol * G.Nr) return;
     const int c = (int)(t / G.Nr), k = G.g + (int)(t % G.Nr);
-    double u[8];
-    updated_zone(G, dt, Phi, zoneB, Uo, c, k, u);
     const i64 z = (i64)c * G.K + k;
+    const bool own = zfl && zfl[z];
+    double u[8];
+    updated_zone(G, dt, Phi, own ? Uo + 5 * G.Z : zoneB, Uo, c, k, u);
     for (int v = 0; v < 8; v++) Uo[v * G.Z + z] = u[v];
 }
 
@@ -778,14 +782,13 @@ __global__ __launch_bounds__(256) void fb_flag(DevGeom G, double dt, double gam,
 
 // Constant traces for the re-solve: every zone of the predictor's range
 // (shells g-1 .. g+Nr) writes, on each of its marked faces and edges, its
-// state at t^n (density, momentum and energy averages of Uo before the
-// update, the divergence-free mean B) and the physical flux of that state in
-// the records the predictor fills (face: the state and the normal flux at each
-// quadrature point; edge: the state and E = (H[B_y], F[B_z], G[B_x]) at each
-// Simpson point).
+// conserved state at t^n (its eight averages in Uo before the update) and the
+// physical flux of that state in the records the predictor fills (face: the
+// state and the normal flux at each quadrature point; edge: the state and
+// E = (H[B_y], F[B_z], G[B_x]) at each Simpson point).
 template <int P, class R>
 __global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const double *__restrict__ Uo,
-                                                 const double *__restrict__ zoneB, const unsigned char *__restrict__ ffl,
+                                                 const unsigned char *__restrict__ ffl,
                                                  const unsigned char *__restrict__ efl, R *__restrict__ ftr,
                                                  R *__restrict__ etr)
 {
@@ -808,7 +811,7 @@ __global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const do
     if (!any) return;
     double u[8], F[3][8];
     for (int v = 0; v < 5; v++) u[v] = Uo[v * G.Z + z];
-    for (int v = 5; v < 8; v++) u[v] = zoneB[(v - 5) * G.Z + z];
+    for (int v = 5; v < 8; v++) u[v] = Uo[v * G.Z + z];
     dev_flux<double>(u, gam, F);
     for (int lf = 0; lf < 6; lf++) {
         if (!ffl[fid[lf]]) continue;
@@ -1087,7 +1090,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
         for (int round = 0; round < FALLBACK_ROUNDS; round++) {
             fb_flag<<<nblocks(G.Z, 256), 256, 0, st>>>(G, dt, gam, round, g->Phi, g->zoneB, Uo, g->zfl, g->ffl,
                                                       g->efl);
-            fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->zoneB, g->ffl, g->efl, ftr, etr);
+            fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->ffl, g->efl, ftr, etr);
             face_flux<P, R, true><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl);
             edge_emf<R, true><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam, g->efl);
             RG_LAUNCH_CHECK();
@@ -1098,7 +1101,8 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
         RG_LAUNCH_CHECK();
         g->fb_dirty = false;
     }
-    zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo);
+    zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo,
+                                                                  prm.fallback ? g->zfl : nullptr);
     face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
     RG_LAUNCH_CHECK();
     sm.mark(8, st);

@@ -4,11 +4,12 @@ The paper leaves positivity to the ruggedised-WENO literature.  The step's
 fallback is defined in the oracle: an interior zone whose high-order update
 would leave a non-positive (or non-finite) density or pressure is flagged, and
 every face and edge of a flagged zone is solved again with the same Riemann
-solvers on the zones' constant states at t^n.  These tests pin that
-definition against what fixes it from outside the fallback code: the plain
-step's own output (which zones are flagged), the pinned HLL solver and the
-face quadrature (the re-solved fluxes), and the invariants the update must
-keep (conservation, div B, positivity of the flagged zones).
+solvers on the zones' conserved states at t^n, a flagged zone taking the
+first-order finite-volume update of its own eight averages.  These tests pin
+that definition against what fixes it from outside the fallback code: the
+plain step's own output (which zones are flagged), the pinned HLL solver and
+the face quadrature (the re-solved fluxes), the update formula, and the
+invariants the update must keep (conservation, div B, positivity).
 """
 import numpy as np
 import pytest
@@ -114,34 +115,38 @@ def test_fallback_changes_only_faces_and_edges_of_flagged_zones(case):
 
 
 def test_refluxed_faces_are_hll_of_the_zone_states_over_the_face_quadrature(case):
-    """Phi_f = sum_q dA_q HLL(U_L, U_R; n_q) with U the zone's density, momentum
-    and energy averages and the divergence-free reconstruction's mean B."""
+    """Phi_f = sum_q dA_q HLL(U_L, U_R; n_q) with U the zones' eight averages."""
     m, gam = case["m"], case["gam"]
-    U1, B1 = case["U1"], case["B1"]
+    U1 = case["U1"]
     flags = case["fb"][4].astype(bool)
     zf, _ = m.zone_faces()
     _, _, _, fz = m.faces()
     _, qn, qdA = m.face_quad()
-    # zones whose reconstruction stencils stay clear of the ghost shells (the
-    # step refills those; divfree() below reads U1 as given)
-    shell = m.zones()[2]
-    deep = (shell >= m.n_ghost + 3) & (shell < m.n_ghost + m.n_rad - 3)
+    act = _interior(m)   # ghost zones are refilled by the step
     faces = np.unique(zf[flags].ravel())
-    faces = [f for f in faces if deep[fz[f, 0]] and deep[fz[f, 1]]]
+    faces = [f for f in faces if act[fz[f, 0]] and act[fz[f, 1]]]
     assert len(faces) > 0
-
-    def state(z):
-        c, e, _ = m.divfree(U1, B1, z)
-        const = np.where((e == 0).all(axis=2))
-        Bm = np.zeros(3)
-        Bm[const[0]] = c[const]
-        return np.concatenate([U1[:5, z], Bm])
-
     phif = case["fb"][2]
-    for f in faces[:12]:
-        UL, UR = state(fz[f, 0]), state(fz[f, 1])
+    for f in faces:
+        UL, UR = U1[:, fz[f, 0]], U1[:, fz[f, 1]]
         ref = sum(qdA[f, q] * O.hll(UL, UR, qn[f, q], gam) for q in range(qn.shape[1]))
         np.testing.assert_allclose(phif[f], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_flagged_zones_take_the_first_order_update_of_their_own_averages(case):
+    """A flagged zone's eight averages, its B included, are advanced from its
+    own values at t^n by the face fluxes (the first-order finite-volume
+    scheme); unflagged zones start B from the reconstruction's mean."""
+    m, dt = case["m"], case["dt"]
+    U1 = case["U1"]
+    Uo, _, phi, _, flags = case["fb"]
+    _, vol, _, _ = m.zones()
+    zf, _ = m.zone_faces()
+    _, _, _, fz = m.faces()
+    for z in np.where(flags)[0]:
+        sg = np.where(fz[zf[z], 0] == z, 1.0, -1.0)
+        ref = U1[:, z] - dt / vol[z] * (sg[:, None] * phi[zf[z]]).sum(0)
+        np.testing.assert_allclose(Uo[:, z], ref, rtol=1e-13, atol=1e-13 * np.abs(U1[:, z]).max())
 
 
 def test_fallback_step_is_conservative_divergence_free_and_positive(case):
