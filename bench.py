@@ -132,6 +132,45 @@ def time_adjoint(reps=5):
             "adjoint_zone_updates_per_s": interior / (t_adj * 1e-3)}
 
 
+def time_blast(n_steps=50):
+    """The magnetised blast (p = 1000 in a ball of radius 0.1 at 1.5 a, beta
+    0.025 outside) at 5,308,416 zones, fourth order, with the first-order
+    fallback, dt from CFL 0.15 every step (its reduction and host read are in
+    the timed loop, as is a device-side count of the flagged zones)."""
+    import torch
+    import paper_1905_02504_amd as R
+    import rg_inputs as RI
+    sh = R.ShellMHD(128, 54, 4, n_ghost=3)
+    prob = RI.blast_problem(p_in=1000.0, radius=0.1)
+    gam = prob["gamma"]
+    U_h, Bf_h = sh.init_alfven(prob)
+    cen, _ = sh.zone_data()
+    p = RI.blast_pressure(prob, cen)
+    U_h[4] = p / (gam - 1.0) + 0.5 * (U_h[1:4] ** 2).sum(0) / U_h[0] + 0.5 * (U_h[5:8] ** 2).sum(0)
+    U, Bf = torch.from_numpy(U_h).cuda(), torch.from_numpy(Bf_h).cuda()
+    del U_h, Bf_h, cen, p
+    U2, Bf2 = torch.empty_like(U), torch.empty_like(Bf)
+    flagged = torch.zeros((), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_sim = 0.0
+    for _ in range(n_steps):
+        _, _, dt = sh.step(U, Bf, 0.0, gamma=gam, cfl=0.15, U_out=U2, Bf_out=Bf2, fallback=True)
+        flagged += sh.fallback_zones().sum()
+        t_sim += dt
+        U, U2, Bf, Bf2 = U2, U, Bf2, Bf
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / n_steps * 1e3
+    d = sh.diag(U, Bf, gam)
+    interior = 6 * 128 * 128 * 54
+    sh.close()
+    return {"workload": "magnetised blast, order 4, 6x128x128 angular x 54 radial = 5308416 zones, "
+                        f"{n_steps} steps at CFL 0.15 with the first-order fallback",
+            "ms_per_step": ms, "zone_updates_per_s": interior / (ms * 1e-3), "t_final": t_sim,
+            "fallback_zone_steps": int(flagged.item()), "rho_min": d["rho_min"], "p_min": d["p_min"],
+            "div_b_rel_max": d["div_rel_max"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-blast", action="store_true", help="skip the magnetised-blast run")
+    ap.add_argument("--no-fallback", action="store_true", help="skip the timing with the fallback on")
     ap.add_argument("--calib", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -180,12 +221,12 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     dt = shell.cfl_dt(U0, args.cfl, gam)
 
-    def run(sh):
+    def run(sh, fallback=False):
         """warmup + timed steps from the initial state; returns the final state"""
         U, Bf = U0.clone(), Bf0.clone()
         U2, Bf2 = torch.empty_like(U), torch.empty_like(Bf)
         for _ in range(args.warmup):
-            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2, fallback=fallback)
             U, U2, Bf, Bf2 = U2, U, Bf2, Bf
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
@@ -195,7 +236,7 @@ def main():
         sh.profile_begin()
         ev0.record(stream)
         for _ in range(args.steps):
-            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2)
+            sh.step(U, Bf, dt, gamma=gam, U_out=U2, Bf_out=Bf2, fallback=fallback)
             U, U2, Bf, Bf2 = U2, U, Bf2, Bf
         ev1.record(stream)
         torch.cuda.synchronize()
@@ -215,6 +256,19 @@ def main():
     diag64 = shell.diag(U, Bf, gam)
     log(f"[bench] FP64: max relative div B {diag64['div_rel_max']:.2e}, "
         f"min rho {diag64['rho_min']:.4f}, min p {diag64['p_min']:.4f}")
+
+    # the same steps with the first-order fallback on (smooth data: the checks
+    # run, nothing is flagged): the cost of its passes
+    fallback = None
+    if not args.no_fallback:
+        Ufb, _, total_fb, stage_fb, nrec_fb = run(shell, fallback=True)
+        nflag = int(shell.fallback_zones().sum().item())
+        fallback = {"ms_per_step": total_fb / args.steps, "overhead_vs_plain": total_fb / total_ms - 1.0,
+                    "update_ct_stage_ms": stage_fb["update_ct"] / nrec_fb, "zones_flagged_last_step": nflag,
+                    "state_equals_plain": bool(torch.equal(Ufb, U))}
+        del Ufb
+        log(f"[bench] with the fallback on: {fallback['ms_per_step']:.2f} ms/step "
+            f"({100 * fallback['overhead_vs_plain']:.1f} % more), {nflag} zones flagged")
 
     flops, bytes_ = shell.work()
     dom = max(stage_ms, key=stage_ms.get)
@@ -266,6 +320,13 @@ def main():
         adjoint = time_adjoint()
         log(f"[bench] adjoint (order 3, 6x32^3): step {adjoint['ms_per_step']:.2f} ms, "
             f"adjoint {adjoint['ms_per_adjoint']:.2f} ms ({adjoint['adjoint_over_step']:.1f}x)")
+    blast = None
+    if not args.no_blast:
+        shell.close()
+        blast = time_blast()
+        log(f"[bench] blast (order 4, 6x128^2x54): {blast['ms_per_step']:.2f} ms/step, "
+            f"{blast['fallback_zone_steps']} fallback zone-steps, min rho {blast['rho_min']:.4f}, "
+            f"min p {blast['p_min']:.3e}")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,
@@ -288,6 +349,8 @@ def main():
         "div_b_rel_max": diag64["div_rel_max"],
         "mixed": mixed,
         "adjoint": adjoint,
+        "fallback": fallback,
+        "blast": blast,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle sample)")

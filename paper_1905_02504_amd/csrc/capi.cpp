@@ -379,15 +379,16 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
              alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
              alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red) &&
              alloc_zero(g, (size_t)ncol * (m.Nr + 2) * 3 * N, &g->bnode);
-        // face and edge marks contiguous (cleared together), zone flags at a
-        // 256-byte aligned offset after them
+        // fallback: round counters, face marks and edge marks contiguous
+        // (cleared together), zone flags at a 256-byte aligned offset after
         double *fb = nullptr;
-        const size_t marks = ((size_t)NF + NE + 255) / 256 * 256;
+        const size_t marks = ((size_t)RG_FB_COUNTER_BYTES + NF + NE + 255) / 256 * 256;
         ok = ok && alloc_zero(g, (marks + Z + 7) / 8, &fb);
         if (!ok) { set_error("device allocation of the step work buffers failed"); free_geom(g); return RG_ENOMEM; }
-        g->ffl = reinterpret_cast<unsigned char *>(fb);
+        g->fbcnt = reinterpret_cast<int *>(fb);
+        g->ffl = reinterpret_cast<unsigned char *>(fb) + RG_FB_COUNTER_BYTES;
         g->efl = g->ffl + NF;
-        g->zfl = g->ffl + marks;
+        g->zfl = reinterpret_cast<unsigned char *>(fb) + marks;
     } catch (const std::bad_alloc &) {
         set_error("out of host memory");
         free_geom(g);

@@ -166,9 +166,11 @@ struct rg_geom {
     double *wcoef = nullptr, *bnod = nullptr, *ftr = nullptr, *etr = nullptr;
     double *Phi = nullptr, *Gam = nullptr, *zoneB = nullptr, *red = nullptr;
     double *bnode = nullptr;   // divergence-free B at the ADER nodes, [recon zone][3N]
-    // first-order fallback: per-zone flags [Z], marks of the faces [NF] and
-    // edges [NE] to solve again (one allocation), and whether zfl holds flags
-    // of a step that had the fallback on
+    // first-order fallback: per-round counts of newly flagged zones, marks of
+    // the faces [NF] and edges [NE] to solve again, per-zone flags [Z] (one
+    // allocation), and whether zfl holds flags of a step that had the
+    // fallback on
+    int *fbcnt = nullptr;
     unsigned char *zfl = nullptr, *ffl = nullptr, *efl = nullptr;
     bool fb_dirty = false;
     rg::AdjBuffers adj;
@@ -181,3 +183,5 @@ struct rg_geom {
 };
 
 #define RG_NSTAGE RG_NSTAGES
+// bytes reserved for the fallback's round counters (ahead of its marks)
+#define RG_FB_COUNTER_BYTES 64

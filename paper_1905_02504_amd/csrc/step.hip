@@ -324,9 +324,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
     using T = Tr<P>;
     // slab rows are N + 1 long so that lanes reading one node's different
     // variables fall into different LDS banks
-    // zone slabs are padded by four doubles so that the two zones' rows fall
-    // into different LDS banks
-    constexpr int N = T::N, SN = N + 1, ZS = 32 * SN + 4, ZPW = 64 / N, E = T::M - 1, NCF = T::NC + 1;
+    // zone slabs are padded by eight elements so that the zones' rows fall
+    // into different LDS banks (eight measured 1 % faster than four)
+    constexpr int N = T::N, SN = N + 1, ZS = 32 * SN + 8, ZPW = 64 / N, E = T::M - 1, NCF = T::NC + 1;
     __shared__ R s_c[ZPW][5 * NCF];
     __shared__ R s_f[ZPW * ZS];
     const R gam = R(gamma);
@@ -573,12 +573,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 // point's two adjacent side records), then the weighted sum over a face's
 // points in order.  256 / Q faces per block.
 // MARKED: only faces with mark[f] set are solved and written (the re-solve of
-// the first-order fallback).
+// the first-order fallback; *added counts the zones its round flagged).
 template <int P, class R, bool MARKED = false>
 __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
-                                                 double *__restrict__ Phi, const unsigned char *__restrict__ mark = nullptr)
+                                                 double *__restrict__ Phi, const unsigned char *__restrict__ mark = nullptr,
+                                                 const int *__restrict__ added = nullptr)
 {
     using T = Tr<P>;
+    if (MARKED && *added == 0) return;   // the round flagged no zone
     constexpr int FPB = 256 / T::Q;
     __shared__ double s_q[FPB * T::Q][9];
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
@@ -628,8 +630,10 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
 // MARKED: only edges with mark[e] set are solved and written
 template <class R, bool MARKED = false>
 __global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *__restrict__ etr, double *__restrict__ Gam,
-                                                const unsigned char *__restrict__ mark = nullptr)
+                                                const unsigned char *__restrict__ mark = nullptr,
+                                                const int *__restrict__ added = nullptr)
 {
+    if (MARKED && *added == 0) return;
     __shared__ double s_p[192];
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
     const int tid = threadIdx.x, el = tid / 3, p = tid % 3;
@@ -725,6 +729,7 @@ __global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const d
 // Section I leaves positivity under strong fields to ruggedised schemes from
 // other work; the step's fallback is an a-posteriori per-zone order drop.
 constexpr int FALLBACK_ROUNDS = 4;
+static_assert(FALLBACK_ROUNDS * sizeof(int) <= RG_FB_COUNTER_BYTES, "round counters fit their slot");
 
 // zero n bytes (16 per lane; m 16-byte aligned)
 __global__ __launch_bounds__(256) void fb_clear(unsigned char *__restrict__ m, i64 n)
@@ -745,12 +750,15 @@ __global__ __launch_bounds__(256) void fb_clear(unsigned char *__restrict__ m, i
 // it passed) and add the bad ones.  A flagged zone marks its six faces and
 // twelve edges (every writer of a mark writes 1; marks of earlier rounds were
 // written by earlier launches, so what a zone reads does not depend on the
-// order of the lanes).
+// order of the lanes).  added[round] counts the zones the round flags.
 __global__ __launch_bounds__(256) void fb_flag(DevGeom G, double dt, double gam, int round,
                                                const double *__restrict__ Phi, const double *__restrict__ zoneB,
                                                const double *__restrict__ Uo, unsigned char *__restrict__ zfl,
-                                               unsigned char *__restrict__ ffl, unsigned char *__restrict__ efl)
+                                               unsigned char *__restrict__ ffl, unsigned char *__restrict__ efl,
+                                               int *__restrict__ added)
 {
+    // no zone flagged in the previous round: no flux changed, nothing to check
+    if (round > 0 && added[round - 1] == 0) return;
     const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= G.Z) return;
     const int c = (int)(z / G.K), k = (int)(z % G.K);
@@ -774,6 +782,7 @@ __global__ __launch_bounds__(256) void fb_flag(DevGeom G, double dt, double gam,
     if (round == 0) zfl[z] = ok ? 0 : 1;
     if (ok) return;
     zfl[z] = 1;
+    atomicAdd(&added[round], 1);
     for (int lf = 0; lf < 6; lf++) ffl[fid[lf]] = 1;
     for (int le = 0; le < 8; le++)
         efl[G.NRE + (i64)G.col_ae[4 * c + LocalEdges::FACE[le]] * (G.K + 1) + k + LocalEdges::UP[le]] = 1;
@@ -790,9 +799,10 @@ template <int P, class R>
 __global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const double *__restrict__ Uo,
                                                  const unsigned char *__restrict__ ffl,
                                                  const unsigned char *__restrict__ efl, R *__restrict__ ftr,
-                                                 R *__restrict__ etr)
+                                                 R *__restrict__ etr, const int *__restrict__ added)
 {
     using T = Tr<P>;
+    if (*added == 0) return;   // the round flagged no zone: no new marks
     const int KR = G.Nr + 2;
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (i64)G.ncol * KR) return;
@@ -1084,15 +1094,18 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(7, st);
     if (prm.fallback) {
-        fb_clear<<<nblocks((G.NF + G.NE + 15) / 16, 256), 256, 0, st>>>(g->ffl, G.NF + G.NE);
-        // a fixed number of rounds (no host synchronisation); a round that
-        // flags no new zone re-solves the same marks to the same values
+        // round counters, face marks and edge marks are contiguous
+        const i64 nclear = RG_FB_COUNTER_BYTES + G.NF + G.NE;
+        fb_clear<<<nblocks((nclear + 15) / 16, 256), 256, 0, st>>>(reinterpret_cast<unsigned char *>(g->fbcnt), nclear);
+        // a fixed number of rounds (no host synchronisation); the passes of a
+        // round that flags no new zone exit at once
         for (int round = 0; round < FALLBACK_ROUNDS; round++) {
             fb_flag<<<nblocks(G.Z, 256), 256, 0, st>>>(G, dt, gam, round, g->Phi, g->zoneB, Uo, g->zfl, g->ffl,
-                                                      g->efl);
-            fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->ffl, g->efl, ftr, etr);
-            face_flux<P, R, true><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl);
-            edge_emf<R, true><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam, g->efl);
+                                                      g->efl, g->fbcnt);
+            fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->ffl, g->efl, ftr, etr, g->fbcnt + round);
+            face_flux<P, R, true><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl,
+                                                                                 g->fbcnt + round);
+            edge_emf<R, true><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam, g->efl, g->fbcnt + round);
             RG_LAUNCH_CHECK();
         }
         g->fb_dirty = true;
