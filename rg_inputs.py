@@ -10,6 +10,7 @@ into problem-definition parameters:
   over the 35 monomials of degree <= 4 listed by MONOMIALS;
 * the propagation axis and transverse frame of a circularly polarised wave;
 * the parameters of a magnetised blast and its piecewise-constant pressure;
+* the spherical Sod shock tube (a radial jump in density and pressure);
 * per-zone white-noise arrays.
 
 The two consumers (the oracle under oracle/ and the library's field
@@ -168,6 +169,22 @@ def blast_pressure(prob: dict, centroids: np.ndarray) -> np.ndarray:
     """Per-zone pressure of the blast: p_in for zones whose centroid lies in the ball, p elsewhere."""
     inside = np.linalg.norm(centroids - prob["centre"], axis=1) < prob["radius"]
     return np.where(inside, prob["p_in"], prob["p"])
+
+
+def sod_problem() -> dict:
+    """Spherical Sod shock tube (Section VIII.c): shell 2 <= r <= 3, (rho, p, v) =
+    (1, 1, 0) for r <= 2.5 and (0.125, 0.1, 0) outside, B = 0, gamma = 1.4,
+    final time 0.2."""
+    return {"r_in": 2.0, "r_out": 3.0, "r0": 2.5, "left": (1.0, 0.0, 1.0), "right": (0.125, 0.0, 0.1),
+            "gamma": 1.4, "t_end": 0.2}
+
+
+def sod_primitives(prob: dict, centroids: np.ndarray) -> tuple:
+    """Per-zone (rho, p) of the Sod problem from each zone's centroid radius."""
+    inner = np.linalg.norm(centroids, axis=1) <= prob["r0"]
+    rho = np.where(inner, prob["left"][0], prob["right"][0])
+    p = np.where(inner, prob["left"][2], prob["right"][2])
+    return rho, p
 
 
 def white_noise(n: int, seed: int = SEED_NOISE, count: int = 2) -> np.ndarray:
