@@ -90,22 +90,14 @@ def cpu_baseline(order, sample_n=16, sample_nr=16):
 def time_adjoint(reps=5):
     """Forward step and its adjoint (rg_step_adjoint, forward recomputation
     included) on the differentiation workload: third order, 6 x 32 x 32 x 32
-    zones, Alfven wave + 1% noise, fixed dt.  HIP events on the stream the
-    library runs on."""
+    zones, Alfven wave + 1% noise, fixed dt; the FP64 step and the FP32 form.
+    HIP events on the stream the library runs on."""
     import torch
     import paper_1905_02504_amd as R
+    from paper_1905_02504_amd import _native as NV
     import rg_inputs as RI
-    sh = R.ShellMHD(32, 32, 3, n_ghost=2)
     prob = RI.alfven_problem()
-    U_h, Bf_h = sh.init_alfven(prob, noise=RI.white_noise(sh.nz), noise_amp=0.01)
-    U, Bf = torch.from_numpy(U_h).cuda(), torch.from_numpy(Bf_h).cuda()
     gam = prob["gamma"]
-    dt = sh.cfl_dt(U, 0.4, gam)
-    gen = torch.Generator(device="cuda").manual_seed(7)
-    gU1 = torch.rand(U.shape, dtype=torch.float64, device="cuda", generator=gen)
-    gB1 = torch.rand(Bf.shape, dtype=torch.float64, device="cuda", generator=gen)
-    U1, B1 = torch.empty_like(U), torch.empty_like(Bf)
-    gU, gB = torch.empty_like(U), torch.empty_like(Bf)
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -120,16 +112,33 @@ def time_adjoint(reps=5):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    t_fwd = timed(lambda: sh.step(U, Bf, dt, gamma=gam, U_out=U1, Bf_out=B1))
-    t_adj = timed(lambda: sh.step_adjoint(U, Bf, gU1, gB1, dt, gamma=gam, gU=gU, gBf=gB))
-    if not (torch.isfinite(gU).all() and torch.isfinite(gB).all()):
-        raise RuntimeError("non-finite adjoint")
+    out, dt = [], None
+    for mode in (NV.RG_MODE_FP64, NV.RG_MODE_FP32):
+        sh = R.ShellMHD(32, 32, 3, n_ghost=2, mode=mode)
+        U_h, Bf_h = sh.init_alfven(prob, noise=RI.white_noise(sh.nz), noise_amp=0.01)
+        U, Bf = torch.from_numpy(U_h).cuda(), torch.from_numpy(Bf_h).cuda()
+        if dt is None:
+            dt = sh.cfl_dt(U, 0.4, gam)
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        gU1 = torch.rand(U.shape, dtype=torch.float64, device="cuda", generator=gen)
+        gB1 = torch.rand(Bf.shape, dtype=torch.float64, device="cuda", generator=gen)
+        U1, B1 = torch.empty_like(U), torch.empty_like(Bf)
+        gU, gB = torch.empty_like(U), torch.empty_like(Bf)
+        t_fwd = timed(lambda: sh.step(U, Bf, dt, gamma=gam, U_out=U1, Bf_out=B1))
+        t_adj = timed(lambda: sh.step_adjoint(U, Bf, gU1, gB1, dt, gamma=gam, gU=gU, gBf=gB))
+        if not (torch.isfinite(gU).all() and torch.isfinite(gB).all()):
+            raise RuntimeError("non-finite adjoint")
+        out.append((t_fwd, t_adj, gU, gB))
+        sh.close()
+    (t_fwd, t_adj, gU, gB), (t_fwd32, t_adj32, gU32, gB32) = out
     interior = 6 * 32 * 32 * 32
-    sh.close()
     return {"workload": "third order, 6x32x32 angular x 32 radial = 196608 zones, Alfven wave + 1% noise, "
                         "fixed dt; adjoint includes its recomputation of the step up to the predictor",
             "ms_per_step": t_fwd, "ms_per_adjoint": t_adj, "adjoint_over_step": t_adj / t_fwd,
-            "adjoint_zone_updates_per_s": interior / (t_adj * 1e-3)}
+            "adjoint_zone_updates_per_s": interior / (t_adj * 1e-3),
+            "fp32": {"ms_per_step": t_fwd32, "ms_per_adjoint": t_adj32, "adjoint_speedup_vs_fp64": t_adj / t_adj32,
+                     "rel_l2_vs_fp64_adjoint": {"zone_state": float((gU32 - gU).norm() / gU.norm()),
+                                                "face_B": float((gB32 - gB).norm() / gB.norm())}}}
 
 
 def time_blast(n_steps=50):
@@ -319,7 +328,8 @@ def main():
             shell.close()   # (the FP32 run closed it otherwise)
         adjoint = time_adjoint()
         log(f"[bench] adjoint (order 3, 6x32^3): step {adjoint['ms_per_step']:.2f} ms, "
-            f"adjoint {adjoint['ms_per_adjoint']:.2f} ms ({adjoint['adjoint_over_step']:.1f}x)")
+            f"adjoint {adjoint['ms_per_adjoint']:.2f} ms ({adjoint['adjoint_over_step']:.1f}x); FP32 form: "
+            f"step {adjoint['fp32']['ms_per_step']:.2f} ms, adjoint {adjoint['fp32']['ms_per_adjoint']:.2f} ms")
     blast = None
     if not args.no_blast:
         shell.close()

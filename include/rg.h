@@ -174,9 +174,11 @@ rg_status rg_step(const rg_geom *geom, rg_step_params *params, const double *U, 
  * min/max of the signal speeds) the branch the forward step took is
  * differentiated.  Recomputes the forward step internally (its work buffers
  * and rg_step_fluxes data are overwritten).  Deterministic: every gradient
- * is gathered by its owner, no floating-point atomics.  FP64 geometries only
- * (RG_ENOTSUP for RG_MODE_FP32); device work buffers are allocated on the
- * first call (RG_ENOMEM).  Asynchronous on `stream`. */
+ * is gathered by its owner, no floating-point atomics.  On an RG_MODE_FP32
+ * geometry it is the adjoint of that form: the FP32 forward is recomputed, the
+ * predictor is reversed in FP32 and the rest in FP64, and the gradients are
+ * FP64.  Device work buffers are allocated on the first call (RG_ENOMEM).
+ * Asynchronous on `stream`. */
 rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *params, const double *U_n, const double *Bf_n,
                           const double *gU_np1, const double *gBf_np1, double *gU_n, double *gBf_n, void *stream);
 

@@ -1,5 +1,7 @@
 // Adjoint of one step (the vector-Jacobian product of rg_step at a given
-// state, dt held fixed), FP64.  The step's stages are reversed one by one:
+// state, dt held fixed), of the FP64 step or of the FP32 form (whose
+// predictor is recomputed and reversed in FP32; the rest of the reversal and
+// every gradient buffer stay FP64).  The step's stages are reversed one by one:
 //
 //   face_ct, zone_update  : linear; transposed as gathers over the faces of an
 //                           edge and the zones of a face
@@ -131,9 +133,11 @@ __global__ void adj_update_zones(DevGeom G, const double *__restrict__ gU, doubl
 }
 
 // ---------------------------------------------------------------- Riemann solvers
-// one lane per face quadrature point (the step's face_flux layout)
-template <int P>
-__global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, const double *__restrict__ ftr,
+// one lane per face quadrature point (the step's face_flux layout); the traces
+// are stored in the step form's precision R, the solver runs in FP64 as in
+// the step
+template <int P, class R>
+__global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
                                                      const double *__restrict__ gPhi, double *__restrict__ gftr)
 {
     using T = Tr<P>;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, cons
     const double *nrm, *fw;
     const i64 f = flux_face<P>(G, t / T::Q, nrm, fw);
     const double w = fw[q] * G.area[f];
-    const double *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
+    const R *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
     double UL[8], UR[8], FL[8], FR[8], gFs[8], gUL[8], gUR[8], gFL[8], gFR[8];
     for (int v = 0; v < 8; v++) {
         UL[v] = a[v];
@@ -165,7 +169,8 @@ __global__ __launch_bounds__(256) void adj_face_flux(DevGeom G, double gam, cons
 }
 
 // one lane per (edge, Simpson point) (the step's edge_emf layout)
-__global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const double *__restrict__ etr,
+template <class R>
+__global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const R *__restrict__ etr,
                                                     const double *__restrict__ gGam, double *__restrict__ getr)
 {
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const
     const i64 e = emf_edge(G, t / 3, p, frame, wl, nzs, N3);
     const double *tt = frame + 6;
     const double g = wl * gGam[e];
-    const double *rec = etr + etr_at(e, p, 0);
+    const R *rec = etr + etr_at(e, p, 0);
     double U[4][8], E[4][3], Et[4], gU[4][8], gE[4][3], gEt[4];
 #pragma unroll
     for (int s = 0; s < 4; s++) {
@@ -221,76 +226,79 @@ struct PredLayout {
 };
 
 // one Picard sweep: Ut <- Ua - R0 dFa - sum_s R_s D F(Ut_s)   (all lanes call it)
-template <int P>
-__device__ __forceinline__ void picard_sweep(const DevGeom &G, double *s_f, double *sf, int lane, int i, int i1, int i2,
-                                             bool active, const double (&Ua)[8], const double (&dFa)[8], double iJ,
-                                             const double (&met)[9], double gam, double (&Ut)[Tr<P>::M - 1][8])
+template <int P, class R>
+__device__ __forceinline__ void picard_sweep(const DevGeom &G, R *s_f, R *sf, int lane, int i, int i1, int i2,
+                                             bool active, const R (&Ua)[8], const R (&dFa)[8], R iJ,
+                                             const R (&met)[9], R gam, R (&Ut)[Tr<P>::M - 1][8])
 {
     using L = PredLayout<P>;
     constexpr int E = L::E, M = Tr<P>::M;
-    double A[E][8];
+    R A[E][8];
 #pragma unroll
     for (int s = 0; s < E; s++) {
         if (active) {
-            double F[3][8];
-            mapped_flux<double>(Ut[s], iJ, met, gam, F);
-            put_flux<L::SN, double>(sf, i, i1, i2, F);
+            R F[3][8];
+            mapped_flux<R>(Ut[s], iJ, met, gam, F);
+            put_flux<L::SN, R>(sf, i, i1, i2, F);
         }
         __syncthreads();
-        deriv_rows<P, L::SN, L::ZS, L::ZPW, double>(s_f, lane);
+        deriv_rows<P, L::SN, L::ZS, L::ZPW, R>(s_f, lane);
         __syncthreads();
 #pragma unroll
-        for (int v = 0; v < 8; v++) A[s][v] = 0.0;
-        if (active) get_deriv<L::SN, double>(sf, i, i1, i2, A[s]);
+        for (int v = 0; v < 8; v++) A[s][v] = R(0);
+        if (active) get_deriv<L::SN, R>(sf, i, i1, i2, A[s]);
         __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < E; t++)
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            double u = Ua[v] - G.R[t * M] * dFa[v];
+            R u = Ua[v] - R(G.R[t * M]) * dFa[v];
 #pragma unroll
-            for (int s = 0; s < E; s++) u -= G.R[t * M + s + 1] * A[s][v];
+            for (int s = 0; s < E; s++) u -= R(G.R[t * M + s + 1]) * A[s][v];
             Ut[t][v] = u;
         }
 }
 
 // gF[d][v] = sum_i D_d[i][node] g[i][v] for the lane's node (all lanes call it)
-template <int P>
-__device__ __forceinline__ void deriv_transpose(double *s_f, double *sf, int lane, int i, int i1, int i2, bool active,
-                                                const double (&g)[8], double (&gF)[3][8])
+template <int P, class R>
+__device__ __forceinline__ void deriv_transpose(R *s_f, R *sf, int lane, int i, int i1, int i2, bool active,
+                                                const R (&g)[8], R (&gF)[3][8])
 {
     using L = PredLayout<P>;
     if (active) {
-        const double G3[3][8] = {{g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]},
+        const R G3[3][8] = {{g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]},
                                  {g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]},
                                  {g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7]}};
-        put_flux<L::SN, double>(sf, i, i1, i2, G3);
+        put_flux<L::SN, R>(sf, i, i1, i2, G3);
     }
     __syncthreads();
-    deriv_rows<P, L::SN, L::ZS, L::ZPW, double, true>(s_f, lane);
+    deriv_rows<P, L::SN, L::ZS, L::ZPW, R, true>(s_f, lane);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 8; v++) {
-        gF[0][v] = active ? sf[v * L::SN + i] : 0.0;
-        gF[1][v] = active ? sf[(8 + v) * L::SN + i1] : 0.0;
-        gF[2][v] = active ? sf[(16 + v) * L::SN + i2] : 0.0;
+        gF[0][v] = active ? sf[v * L::SN + i] : R(0);
+        gF[1][v] = active ? sf[(8 + v) * L::SN + i1] : R(0);
+        gF[2][v] = active ? sf[(16 + v) * L::SN + i2] : R(0);
     }
     __syncthreads();
 }
 
-template <int P>
+// R: the precision of the step form (its stored coefficients and nodal B, and
+// the arithmetic of the recomputed predictor and of its reversal); the
+// incoming and outgoing gradients are FP64.
+template <int P, class R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void adj_predictor(
-    DevGeom G, double dt, double gamma, int npic, const double *__restrict__ U, const double *__restrict__ wc,
-    const double *__restrict__ bnode, const double *__restrict__ gftr, const double *__restrict__ getr,
+    DevGeom G, double dt, double gamma, int npic, const double *__restrict__ U, const R *__restrict__ wc,
+    const R *__restrict__ bnode, const double *__restrict__ gftr, const double *__restrict__ getr,
     double *__restrict__ gUo, double *__restrict__ gwc, double *__restrict__ gbnode)
 {
     using T = Tr<P>;
     using L = PredLayout<P>;
     constexpr int N = T::N, M = T::M, ZS = L::ZS, ZPW = L::ZPW, E = L::E, NCF = T::NC + 1;
-    __shared__ double s_c[ZPW][5 * NCF];
-    __shared__ double s_f[ZPW * ZS];
-    const double gam = gamma;
+    __shared__ R s_c[ZPW][5 * NCF];
+    __shared__ R s_f[ZPW * ZS];
+    const R gam = R(gamma);
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
     const i64 nzr = (i64)G.ncol * KR;
@@ -305,63 +313,64 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
         z = (i64)c * G.K + k;
         for (int j = i; j < 5 * NCF; j += N) {
             const int v = j / NCF, a = j % NCF;
-            s_c[zl][j] = a == 0 ? U[v * G.Z + z] : wc[((i64)v * T::NC + a - 1) * G.Z + z];
+            s_c[zl][j] = a == 0 ? R(U[v * G.Z + z]) : wc[((i64)v * T::NC + a - 1) * G.Z + z];
         }
     }
     const int i1 = DTab<P>::SWAP1[i], i2 = DTab<P>::SWAP2[i];
     __syncthreads();
-    double Ua[8], dFa[8], met[9], iJ = 1.0, J = 1.0;
-    double *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
-    for (int v = 0; v < 8; v++) Ua[v] = dFa[v] = 0.0;
-    for (int m = 0; m < 9; m++) met[m] = 0.0;
+    R Ua[8], dFa[8], met[9], iJ = R(1), J = R(1);
+    R *sf = s_f + (zl < ZPW ? zl : 0) * ZS;
+    for (int v = 0; v < 8; v++) Ua[v] = dFa[v] = R(0);
+    for (int m = 0; m < 9; m++) met[m] = R(0);
     if (active) {
-        const double *Ev = G.Ev + (i64)c * T::NC * N + i;
+        const R *Ev = pick<R>(G.Ev, G.EvF) + (i64)c * T::NC * N + i;
         for (int v = 0; v < 5; v++) {
-            double acc = s_c[zl][v * NCF];
+            R acc = s_c[zl][v * NCF];
 #pragma unroll
             for (int a = 0; a < T::NC; a++) acc += Ev[a * N] * s_c[zl][v * NCF + 1 + a];
             Ua[v] = acc;
         }
-        const double *bn = bnode + (i64)zt * (3 * N) + i;
+        const R *bn = bnode + (i64)zt * (3 * N) + i;
         Ua[5] = bn[0];
         Ua[6] = bn[N];
         Ua[7] = bn[2 * N];
-        J = G.nJ[(i64)c * N + i];
-        iJ = 1.0 / J;
-        const double fac = dt / G.zscale[k];
+        J = pick<R>(G.nJ, G.nJF)[(i64)c * N + i];
+        iJ = R(1) / J;
+        const R fac = R(dt / G.zscale[k]);
+        const R *nM = pick<R>(G.nM, G.nMF);
 #pragma unroll
-        for (int m = 0; m < 9; m++) met[m] = fac * G.nM[((i64)c * 9 + m) * N + i];
+        for (int m = 0; m < 9; m++) met[m] = fac * nM[((i64)c * 9 + m) * N + i];
 #pragma unroll
         for (int v = 0; v < 8; v++) Ua[v] *= J;
-        double F[3][8];
-        mapped_flux<double>(Ua, iJ, met, gam, F);
-        put_flux<L::SN, double>(sf, i, i1, i2, F);
+        R F[3][8];
+        mapped_flux<R>(Ua, iJ, met, gam, F);
+        put_flux<L::SN, R>(sf, i, i1, i2, F);
     }
     __syncthreads();
-    deriv_rows<P, L::SN, ZS, ZPW, double>(s_f, lane);
+    deriv_rows<P, L::SN, ZS, ZPW, R>(s_f, lane);
     __syncthreads();
-    if (active) get_deriv<L::SN, double>(sf, i, i1, i2, dFa);
+    if (active) get_deriv<L::SN, R>(sf, i, i1, i2, dFa);
     __syncthreads();
     // the first sweep from the constant guess: Ut_t = Ua - (R0_t + sum_s R_ts) dFa
-    double cR[E];
+    R cR[E];
 #pragma unroll
     for (int t = 0; t < E; t++) {
-        double acc = G.R[t * M];
+        R acc = R(G.R[t * M]);
 #pragma unroll
-        for (int s = 0; s < E; s++) acc += G.R[t * M + s + 1];
-        cR[t] = npic > 0 ? acc : 0.0;
+        for (int s = 0; s < E; s++) acc += R(G.R[t * M + s + 1]);
+        cR[t] = npic > 0 ? acc : R(0);
     }
-    double Ut[E][8];
+    R Ut[E][8];
 #pragma unroll
     for (int t = 0; t < E; t++)
 #pragma unroll
         for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - cR[t] * dFa[v];
-    for (int it = 2; it <= npic; it++) picard_sweep<P>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
+    for (int it = 2; it <= npic; it++) picard_sweep<P, R>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
 
     // ---- traces reversed: gradients of the node's time-averaged state and flux
-    double gaU[8], gaF[3][8];
+    R gaU[8], gaF[3][8];
 #pragma unroll
-    for (int v = 0; v < 8; v++) gaU[v] = gaF[0][v] = gaF[1][v] = gaF[2][v] = 0.0;
+    for (int v = 0; v < 8; v++) gaU[v] = gaF[0][v] = gaF[1][v] = gaF[2][v] = R(0);
     if (active) {
 #pragma unroll 1
         for (int lf = 0; lf < 6; lf++) {
@@ -390,16 +399,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
 #pragma unroll 1
             for (int q = 0; q < T::Q; q++) {
                 const int qc = perm ? perm[q] : q;
-                const double w = G.fintc[kk * T::Q + q];
+                const R w = pick<R>(G.fintc, G.fintcF)[kk * T::Q + q];
                 const double *n = nrm + qc * 3;
                 const double *gq = go + qc * 32;
 #pragma unroll
                 for (int v = 0; v < 8; v++) {
-                    gaU[v] += w * gq[v];
-                    const double gn = w * gq[8 + v];
-                    gaF[0][v] += gn * n[0];
-                    gaF[1][v] += gn * n[1];
-                    gaF[2][v] += gn * n[2];
+                    gaU[v] += w * R(gq[v]);
+                    const R gn = w * R(gq[8 + v]);
+                    gaF[0][v] += gn * R(n[0]);
+                    gaF[1][v] += gn * R(n[1]);
+                    gaF[2][v] += gn * R(n[2]);
                 }
             }
         }
@@ -424,60 +433,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
             const double *go = getr + etr_at(e, 0, slot);   // point p at go + 44 p
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
-                const double w = G.eintc[kk * 3 + p];
+                const R w = pick<R>(G.eintc, G.eintcF)[kk * 3 + p];
 #pragma unroll
-                for (int v = 0; v < 8; v++) gaU[v] += w * go[pc * 44 + v];
-                gaF[2][6] += w * go[pc * 44 + 8];   // E_x = H[B_y]
-                gaF[0][7] += w * go[pc * 44 + 9];   // E_y = F[B_z]
-                gaF[1][5] += w * go[pc * 44 + 10];  // E_z = G[B_x]
+                for (int v = 0; v < 8; v++) gaU[v] += w * R(go[pc * 44 + v]);
+                gaF[2][6] += w * R(go[pc * 44 + 8]);   // E_x = H[B_y]
+                gaF[0][7] += w * R(go[pc * 44 + 9]);   // E_y = F[B_z]
+                gaF[1][5] += w * R(go[pc * 44 + 10]);  // E_z = G[B_x]
             }
         }
     }
     // ---- time averages reversed: gX_t = wt_t / J (gaU + (dF/dw)^T gaF) at w = Ut_t / J
-    double gX[E][8];
+    R gX[E][8];
 #pragma unroll
     for (int t = 0; t < E; t++) {
-        double w[8], gw[8];
-        const double wt = G.wt[t + 1];
+        R w[8], gw[8];
+        const R wt = R(G.wt[t + 1]);
 #pragma unroll
-        for (int v = 0; v < 8; v++) { w[v] = active ? Ut[t][v] * iJ : (v == 0 ? 1.0 : 0.0); gw[v] = gaU[v]; }
-        if (active) flux_vjp(w, gam, gaF, gw);
+        for (int v = 0; v < 8; v++) { w[v] = active ? Ut[t][v] * iJ : (v == 0 ? R(1) : R(0)); gw[v] = gaU[v]; }
+        if (active) flux_vjp<R>(w, gam, gaF, gw);
 #pragma unroll
         for (int v = 0; v < 8; v++) gX[t][v] = wt * iJ * gw[v];
     }
     // ---- Picard sweeps reversed, last first
-    double gUa[8], gdFa[8];
+    R gUa[8], gdFa[8];
 #pragma unroll
-    for (int v = 0; v < 8; v++) gUa[v] = gdFa[v] = 0.0;
+    for (int v = 0; v < 8; v++) gUa[v] = gdFa[v] = R(0);
     for (int it = npic; it >= 2; it--) {
         // the states this sweep started from
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
             for (int v = 0; v < 8; v++) Ut[t][v] = Ua[v] - cR[t] * dFa[v];
-        for (int r = 2; r < it; r++) picard_sweep<P>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
+        for (int r = 2; r < it; r++) picard_sweep<P, R>(G, s_f, sf, lane, i, i1, i2, active, Ua, dFa, iJ, met, gam, Ut);
 #pragma unroll
         for (int t = 0; t < E; t++)
 #pragma unroll
             for (int v = 0; v < 8; v++) {
                 gUa[v] += gX[t][v];
-                gdFa[v] -= G.R[t * M] * gX[t][v];
+                gdFa[v] -= R(G.R[t * M]) * gX[t][v];
             }
         // A_s = D F(Ut_s): the gradient of each level's start state; it
         // replaces that state in Ut (no longer needed) and becomes gX
 #pragma unroll
         for (int s = 0; s < E; s++) {
-            double gA[8], gF[3][8], gu[8];
+            R gA[8], gF[3][8], gu[8];
 #pragma unroll
             for (int v = 0; v < 8; v++) {
-                double acc = 0.0;
+                R acc = R(0);
 #pragma unroll
-                for (int t = 0; t < E; t++) acc -= G.R[t * M + s + 1] * gX[t][v];
+                for (int t = 0; t < E; t++) acc -= R(G.R[t * M + s + 1]) * gX[t][v];
                 gA[v] = acc;
-                gu[v] = 0.0;
+                gu[v] = R(0);
             }
-            deriv_transpose<P>(s_f, sf, lane, i, i1, i2, active, gA, gF);
-            if (active) mapped_flux_vjp(Ut[s], iJ, met, gam, gF, gu);
+            deriv_transpose<P, R>(s_f, sf, lane, i, i1, i2, active, gA, gF);
+            if (active) mapped_flux_vjp<R>(Ut[s], iJ, met, gam, gF, gu);
 #pragma unroll
             for (int v = 0; v < 8; v++) Ut[s][v] = gu[v];
         }
@@ -496,16 +505,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
         }
     // ---- tau = 0 derivative reversed: dFa = D F(Ua)
     {
-        double gF[3][8];
-        deriv_transpose<P>(s_f, sf, lane, i, i1, i2, active, gdFa, gF);
-        if (active) mapped_flux_vjp(Ua, iJ, met, gam, gF, gUa);
+        R gF[3][8];
+        deriv_transpose<P, R>(s_f, sf, lane, i, i1, i2, active, gdFa, gF);
+        if (active) mapped_flux_vjp<R>(Ua, iJ, met, gam, gF, gUa);
     }
     // ---- nodal initial state reversed: Ua = J (fluid polynomial | divergence-free B)
-    double *s_red = s_f;   // [ZPW][5][N], free once the slab is idle
+    R *s_red = s_f;   // [ZPW][5][N], free once the slab is idle
     if (active) {
 #pragma unroll
         for (int v = 0; v < 8; v++) gUa[v] *= J;
-        for (int v = 5; v < 8; v++) gbnode[(i64)zt * (3 * N) + (v - 5) * N + i] = gUa[v];
+        for (int v = 5; v < 8; v++) gbnode[(i64)zt * (3 * N) + (v - 5) * N + i] = double(gUa[v]);
         for (int v = 0; v < 5; v++) s_red[(zl * 5 + v) * N + i] = gUa[v];
     }
     __syncthreads();
@@ -515,14 +524,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
         if (ztq >= (unsigned)nzr) continue;
         const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
         const i64 zq64 = (i64)cq * G.K + kq;
-        const double *r = s_red + (zq * 5 + v) * N;
+        const R *r = s_red + (zq * 5 + v) * N;
         double acc = 0.0;
         if (a == 0) {
-            for (int n = 0; n < N; n++) acc += r[n];
+            for (int n = 0; n < N; n++) acc += double(r[n]);
             gUo[(i64)v * G.Z + zq64] += acc;
         } else {
             const double *Ev = G.Ev + ((i64)cq * T::NC + a - 1) * N;
-            for (int n = 0; n < N; n++) acc += Ev[n] * r[n];
+            for (int n = 0; n < N; n++) acc += Ev[n] * double(r[n]);
             gwc[((i64)v * T::NC + a - 1) * G.Z + zq64] = acc;
         }
     }
@@ -648,9 +657,11 @@ __global__ void adj_face_gather_bmap(DevGeom G, const double *__restrict__ gside
 // ---------------------------------------------------------------- face nodal B
 // Reverse of MinMod + mean restore on one face; the two sides' shares (B mean
 // and WENO B coefficients of each side's zone) go to gsb[side][3 + 3 NC][f].
-template <int P>
+// Each side's B at the points is recomputed as the step computes it, in the
+// step form's precision R, so that MinMod takes the step's branch.
+template <int P, class R>
 __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const double *__restrict__ Bo,
-                                const double *__restrict__ wc, const double *__restrict__ gbnod,
+                                const R *__restrict__ wc, const double *__restrict__ gbnod,
                                 double *__restrict__ gBo, double *__restrict__ gsb)
 {
     using T = Tr<P>;
@@ -662,6 +673,7 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
     i64 f, z[2];
     bool have[2];
     const double *fev[2], *nrm, *fw;
+    const R *fevr[2];
     if (t < nR) {
         const int c = (int)(t / nrad), kf = G.g - 1 + (int)(t % nrad);
         f = (i64)c * (G.K + 1) + kf;
@@ -671,6 +683,8 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
         have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
         fev[0] = G.fevR + ((i64)c * 2 + 0) * T::Q * T::NC;
         fev[1] = G.fevR + ((i64)c * 2 + 1) * T::Q * T::NC;
+        fevr[0] = pick<R>(G.fevR, G.fevRF) + ((i64)c * 2 + 0) * T::Q * T::NC;
+        fevr[1] = pick<R>(G.fevR, G.fevRF) + ((i64)c * 2 + 1) * T::Q * T::NC;
         nrm = G.fnR + (i64)c * T::Q * 3;
         fw = G.fwR + (i64)c * T::Q;
     } else {
@@ -682,6 +696,8 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
         have[0] = have[1] = true;
         fev[0] = G.fevA + ((i64)ae * 2 + 0) * T::Q * T::NC;
         fev[1] = G.fevA + ((i64)ae * 2 + 1) * T::Q * T::NC;
+        fevr[0] = pick<R>(G.fevA, G.fevAF) + ((i64)ae * 2 + 0) * T::Q * T::NC;
+        fevr[1] = pick<R>(G.fevA, G.fevAF) + ((i64)ae * 2 + 1) * T::Q * T::NC;
         nrm = G.fnA + (i64)ae * T::Q * 3;
         fw = G.fwA + (i64)ae * T::Q;
     }
@@ -691,17 +707,18 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
     for (int s = 0; s < 2; s++) {
         if (!have[s]) continue;
         // the step's sum order: component mean, then the coefficients in turn
-        double Bq[3][T::Q];
+        R Bq[3][T::Q];
         for (int c3 = 0; c3 < 3; c3++) {
-            const double m0 = Uo[(5 + c3) * G.Z + z[s]];
+            const R m0 = R(Uo[(5 + c3) * G.Z + z[s]]);
             for (int q = 0; q < T::Q; q++) Bq[c3][q] = m0;
             for (int a = 0; a < T::NC; a++) {
-                const double ca = wc[((i64)(5 + c3) * T::NC + a) * G.Z + z[s]];
-                for (int q = 0; q < T::Q; q++) Bq[c3][q] += ca * fev[s][q * T::NC + a];
+                const R ca = wc[((i64)(5 + c3) * T::NC + a) * G.Z + z[s]];
+                for (int q = 0; q < T::Q; q++) Bq[c3][q] += ca * fevr[s][q * T::NC + a];
             }
         }
         for (int q = 0; q < T::Q; q++)
-            d[s][q] = Bq[0][q] * nrm[q * 3] + Bq[1][q] * nrm[q * 3 + 1] + Bq[2][q] * nrm[q * 3 + 2] - mean;
+            d[s][q] = double(Bq[0][q]) * nrm[q * 3] + double(Bq[1][q]) * nrm[q * 3 + 1] +
+                      double(Bq[2][q]) * nrm[q * 3 + 2] - mean;
     }
     for (int q = 0; q < T::Q; q++) {
         if (!have[0]) d[0][q] = d[1][q];
@@ -945,7 +962,10 @@ __global__ void copy_state(const double *__restrict__ src, double *__restrict__ 
 
 }  // namespace
 
-template <int P>
+// R: the precision of the step form being differentiated (double, or float
+// for RG_MODE_FP32, whose reconstruction coefficients, face nodal B, nodal B
+// and traces are stored in FP32 and whose predictor computes in FP32)
+template <int P, class R>
 static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf,
                                const double *gU1, const double *gBf1, double *gU, double *gBf, hipStream_t st)
 {
@@ -975,20 +995,22 @@ static rg_status adjoint_order(rg_geom *g, const rg_step_params &prm, const doub
     adj_update_zones<<<nblk(G.Z, 256), 256, 0, st>>>(G, gU1, A.gUo, A.gzoneB);
     RG_ADJ_CHECK();
     // Riemann solvers
-    adj_face_flux<P><<<nblk(nff * T::Q, 256), 256, 0, st>>>(G, gam, g->ftr, A.gPhi, A.gftr);
-    adj_edge_emf<<<nblk(nee * 3, 256), 256, 0, st>>>(G, gam, g->etr, A.gGam, A.getr);
+    const R *ftr = reinterpret_cast<const R *>(g->ftr), *etr = reinterpret_cast<const R *>(g->etr);
+    const R *wcoef = reinterpret_cast<const R *>(g->wcoef), *bnode = reinterpret_cast<const R *>(g->bnode);
+    adj_face_flux<P, R><<<nblk(nff * T::Q, 256), 256, 0, st>>>(G, gam, ftr, A.gPhi, A.gftr);
+    adj_edge_emf<R><<<nblk(nee * 3, 256), 256, 0, st>>>(G, gam, etr, A.gGam, A.getr);
     RG_ADJ_CHECK();
     // predictor
     constexpr int ZPW = PredLayout<P>::ZPW;
-    adj_predictor<P><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, A.Ubc, g->wcoef, g->bnode,
-                                                                       A.gftr, A.getr, A.gUo, A.gwc, A.gbnode);
+    adj_predictor<P, R><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, A.Ubc, wcoef, bnode,
+                                                                          A.gftr, A.getr, A.gUo, A.gwc, A.gbnode);
     RG_ADJ_CHECK();
     // divergence-free map, then face nodal B
     const int ntile = (G.Nr + 2 + 15) / 16;
     adj_bmap<P><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, A.MbA, A.gbnode, A.gzoneB, A.gUo, A.gwc, A.gside);
     const i64 nbn = (i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2);
     adj_face_gather_bmap<P><<<nblk(nbn, 256), 256, 0, st>>>(G, A.gside, A.gbnod, A.gBo);
-    adj_face_bnodal<P><<<nblk(nbn, 128), 128, 0, st>>>(G, A.Ubc, A.Bbc, g->wcoef, A.gbnod, A.gBo, A.gsb);
+    adj_face_bnodal<P, R><<<nblk(nbn, 128), 128, 0, st>>>(G, A.Ubc, A.Bbc, wcoef, A.gbnod, A.gBo, A.gsb);
     adj_zone_gather_bnodal<P><<<nblk(nzr, 256), 256, 0, st>>>(G, A.gsb, A.gUo, A.gwc);
     RG_ADJ_CHECK();
     // WENO-AO
@@ -1018,8 +1040,13 @@ rg_status launch_adjoint(rg_geom *g, const rg_step_params &p, const double *U, c
                          const double *gBf1, double *gU, double *gBf, void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (g->d.order == 3) return adjoint_order<3>(g, p, U, Bf, gU1, gBf1, gU, gBf, st);
-    if (g->d.order == 4) return adjoint_order<4>(g, p, U, Bf, gU1, gBf1, gU, gBf, st);
+    const bool f32 = g->mode == RG_MODE_FP32;
+    if (g->d.order == 3)
+        return f32 ? adjoint_order<3, float>(g, p, U, Bf, gU1, gBf1, gU, gBf, st)
+                   : adjoint_order<3, double>(g, p, U, Bf, gU1, gBf1, gU, gBf, st);
+    if (g->d.order == 4)
+        return f32 ? adjoint_order<4, float>(g, p, U, Bf, gU1, gBf1, gU, gBf, st)
+                   : adjoint_order<4, double>(g, p, U, Bf, gU1, gBf1, gU, gBf, st);
     set_error("unsupported order");
     return RG_ENOTSUP;
 }

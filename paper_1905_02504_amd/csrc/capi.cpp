@@ -493,7 +493,6 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
     }
     rg_geom *g = const_cast<rg_geom *>(geom);
     if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
-    if (g->mode != RG_MODE_FP64) { set_error("the adjoint is implemented for the FP64 form only"); return RG_ENOTSUP; }
     if (params->fallback != 0) {
         set_error("the first-order fallback has no adjoint (run the adjoint with fallback = 0)");
         return RG_ENOTSUP;

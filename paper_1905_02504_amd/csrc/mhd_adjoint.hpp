@@ -1,5 +1,6 @@
 // Reverse-mode (vector-Jacobian) counterparts of the point functions in
-// mhd_device.hpp, written out by hand, FP64.  Each takes the forward inputs,
+// mhd_device.hpp, written out by hand: FP64, and the flux reverses also for
+// the FP32 form's predictor.  Each takes the forward inputs,
 // recomputes what it needs, and ADDS the input gradients for a given output
 // gradient.  At a kink (min / max, the HLL branch, the clamp of the fast-speed
 // discriminant) the branch the forward function takes is differentiated, with
@@ -10,36 +11,37 @@
 namespace rg {
 
 // gw += (dF/dw)^T G for the physical flux F[d][v] of dev_flux (eq. 2.2)
-__device__ __forceinline__ void flux_vjp(const double *u, double gam, const double (&G)[3][8], double *gw)
+template <class T>
+__device__ __forceinline__ void flux_vjp(const T *u, T gam, const T (&G)[3][8], T *gw)
 {
-    const double ir = 1.0 / u[0];
-    const double m[3] = {u[1], u[2], u[3]};
-    const double v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
-    const double B[3] = {u[5], u[6], u[7]};
-    const double hb2 = 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-    const double p = (gam - 1.0) * (u[4] - 0.5 * (m[0] * v[0] + m[1] * v[1] + m[2] * v[2]) - hb2);
-    const double pt = p + hb2;
-    const double vB = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
-    double gm[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-    double gpt = 0.0, gvB = 0.0, gE = 0.0;
+    const T ir = T(1) / u[0];
+    const T m[3] = {u[1], u[2], u[3]};
+    const T v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    const T B[3] = {u[5], u[6], u[7]};
+    const T hb2 = T(0.5) * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    const T p = (gam - T(1)) * (u[4] - T(0.5) * (m[0] * v[0] + m[1] * v[1] + m[2] * v[2]) - hb2);
+    const T pt = p + hb2;
+    const T vB = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    T gm[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+    T gpt = T(0), gvB = T(0), gE = T(0);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         gm[d] += G[d][0];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            const double g1 = G[d][1 + i];
+            const T g1 = G[d][1 + i];
             gm[d] += g1 * v[i];
             gv[i] += g1 * m[d];
             gB[d] -= g1 * B[i];
             gB[i] -= g1 * B[d];
-            const double g5 = G[d][5 + i];
+            const T g5 = G[d][5 + i];
             gv[d] += g5 * B[i];
             gB[i] += g5 * v[d];
             gB[d] -= g5 * v[i];
             gv[i] -= g5 * B[d];
         }
         gpt += G[d][1 + d];
-        const double g4 = G[d][4];
+        const T g4 = G[d][4];
         gE += g4 * v[d];
         gpt += g4 * v[d];
         gv[d] += g4 * (u[4] + pt);
@@ -47,15 +49,15 @@ __device__ __forceinline__ void flux_vjp(const double *u, double gam, const doub
         gvB -= g4 * B[d];
     }
     // vB, pt = p + hb2, p, hb2, v = m / rho
-    const double gp = gpt, gm1 = gam - 1.0;
-    double ghb2 = gpt - gm1 * gp, gir = 0.0;
+    const T gp = gpt, gm1 = gam - T(1);
+    T ghb2 = gpt - gm1 * gp, gir = T(0);
     gE += gm1 * gp;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         gv[i] += gvB * B[i];
         gB[i] += gvB * v[i];
-        gm[i] -= 0.5 * gm1 * gp * v[i];
-        gv[i] -= 0.5 * gm1 * gp * m[i];
+        gm[i] -= T(0.5) * gm1 * gp * v[i];
+        gv[i] -= T(0.5) * gm1 * gp * m[i];
     }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
@@ -75,17 +77,17 @@ __device__ __forceinline__ void flux_vjp(const double *u, double gam, const doub
 
 // gu += (d out / du)^T gOut for mapped_flux (flux of u / J contracted with
 // the scaled metric terms)
-__device__ __forceinline__ void mapped_flux_vjp(const double *u, double iJ, const double *met, double gam,
-                                                const double (&gOut)[3][8], double *gu)
+template <class T>
+__device__ __forceinline__ void mapped_flux_vjp(const T *u, T iJ, const T *met, T gam, const T (&gOut)[3][8], T *gu)
 {
-    double w[8], G[3][8], gw[8];
+    T w[8], G[3][8], gw[8];
 #pragma unroll
-    for (int v = 0; v < 8; v++) { w[v] = u[v] * iJ; gw[v] = 0.0; }
+    for (int v = 0; v < 8; v++) { w[v] = u[v] * iJ; gw[v] = T(0); }
 #pragma unroll
     for (int c = 0; c < 3; c++)
 #pragma unroll
         for (int v = 0; v < 8; v++) G[c][v] = met[c] * gOut[0][v] + met[3 + c] * gOut[1][v] + met[6 + c] * gOut[2][v];
-    flux_vjp(w, gam, G, gw);
+    flux_vjp<T>(w, gam, G, gw);
 #pragma unroll
     for (int v = 0; v < 8; v++) gu[v] += gw[v] * iJ;
 }

@@ -1159,12 +1159,11 @@ rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U
                             double *Bo, void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (g->mode != RG_MODE_FP64) {
-        set_error("FP64 geometry required");
-        return RG_ENOTSUP;
-    }
-    if (g->d.order == 3) return step_order<3, double>(g, p, U, Bf, Uo, Bo, st, true);
-    if (g->d.order == 4) return step_order<4, double>(g, p, U, Bf, Uo, Bo, st, true);
+    const bool f32 = g->mode == RG_MODE_FP32;
+    if (g->d.order == 3)
+        return f32 ? step_order<3, float>(g, p, U, Bf, Uo, Bo, st, true) : step_order<3, double>(g, p, U, Bf, Uo, Bo, st, true);
+    if (g->d.order == 4)
+        return f32 ? step_order<4, float>(g, p, U, Bf, Uo, Bo, st, true) : step_order<4, double>(g, p, U, Bf, Uo, Bo, st, true);
     set_error("unsupported order");
     return RG_ENOTSUP;
 }
