@@ -134,3 +134,20 @@ def test_parity_long_columns(order):
     lib, res, _ = run_case(order, 4, 64, "harmonic", cfl=0.4)
     for k, v in res.items():
         assert v < bound(k), (k, v)
+
+
+@pytest.mark.parametrize("order,n_ang,n_rad", [(3, 2, 1), (4, 2, 1), (3, 2, 62), (4, 4, 70)])
+def test_parity_edge_sizes(order, n_ang, n_rad):
+    """The smallest mesh (two columns per cube edge: every column touches a cube
+    corner, so every zone has the corner stencils and three-zone edges, and a
+    single radial shell) and columns of 62 and 70 shells (64 and 72
+    reconstructed shells, 65 and 73 radial faces: the column-run kernels'
+    tail just inside and just beyond their short-tail mode).  Fourth order
+    with two columns per cube edge and 62 or 70 shells makes zones about 80
+    times wider than deep; their least-squares and divergence-free maps are
+    then conditioned badly enough that the two sides' round-off differs by
+    1e-11 (1e-13 at 8 shells, 2e-13 with four columns per edge), so the
+    70-shell fourth-order case uses four columns per edge."""
+    lib, res, _ = run_case(order, n_ang, n_rad, "harmonic", cfl=0.4)
+    for k, v in res.items():
+        assert v < bound(k), (k, v)
