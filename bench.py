@@ -141,6 +141,16 @@ def time_adjoint(reps=5):
                                                 "face_B": float((gB32 - gB).norm() / gB.norm())}}}
 
 
+def weno_order_stats(sh):
+    """Summary of the last step's WENO-AO order indicator over the interior
+    zones (the large stencil's weight over its linear weight, smallest over
+    the variables)."""
+    import torch
+    w = sh.weno_order()[torch.from_numpy(sh.interior()).cuda()].double()
+    return {"min": float(w.min()), "median": float(w.median()), "frac_below_0.5": float((w < 0.5).double().mean()),
+            "frac_below_0.01": float((w < 0.01).double().mean())}
+
+
 def time_blast(n_steps=50):
     """The magnetised blast (p = 1000 in a ball of radius 0.1 at 1.5 a, beta
     0.025 outside) at 5,308,416 zones, fourth order, with the first-order
@@ -171,13 +181,14 @@ def time_blast(n_steps=50):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / n_steps * 1e3
     d = sh.diag(U, Bf, gam)
+    wo = weno_order_stats(sh)
     interior = 6 * 128 * 128 * 54
     sh.close()
     return {"workload": "magnetised blast, order 4, 6x128x128 angular x 54 radial = 5308416 zones, "
                         f"{n_steps} steps at CFL 0.15 with the first-order fallback",
             "ms_per_step": ms, "zone_updates_per_s": interior / (ms * 1e-3), "t_final": t_sim,
             "fallback_zone_steps": int(flagged.item()), "rho_min": d["rho_min"], "p_min": d["p_min"],
-            "div_b_rel_max": d["div_rel_max"]}
+            "div_b_rel_max": d["div_rel_max"], "weno_order_last_step": wo}
 
 
 def main():
@@ -263,6 +274,7 @@ def main():
         log("[bench] non-finite state after the timed steps")
         sys.exit(1)
     diag64 = shell.diag(U, Bf, gam)
+    weno_order = weno_order_stats(shell)
     log(f"[bench] FP64: max relative div B {diag64['div_rel_max']:.2e}, "
         f"min rho {diag64['rho_min']:.4f}, min p {diag64['p_min']:.4f}")
 
@@ -357,6 +369,7 @@ def main():
                    "stage_ms_per_step": {k: round(v / nrec, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
         "div_b_rel_max": diag64["div_rel_max"],
+        "weno_order_last_step": weno_order,
         "mixed": mixed,
         "adjoint": adjoint,
         "fallback": fallback,

@@ -207,6 +207,14 @@ rg_status rg_step_fluxes(const rg_geom *geom, double *Phi, double *Gam, void *st
  * step with the fallback off).  Asynchronous on `stream`. */
 rg_status rg_step_fallback_zones(const rg_geom *geom, uint8_t *flags, void *stream);
 
+/* Device copy of the last rg_step's WENO-AO order indicator, whi[n_zones]
+ * (float): for every zone of the reconstructed shells, the smallest over the
+ * eight variables of the large stencil's nonlinear weight divided by its
+ * linear weight (Section III; about 1 where the reconstruction keeps its full
+ * order, near 0 where it has dropped to the small stencils).  Entries of other
+ * zones are 0 until a step writes them.  Asynchronous on `stream`. */
+rg_status rg_step_weno_order(const rg_geom *geom, float *whi, void *stream);
+
 /* Timestep limit dt = cfl * min over interior zones of d_in / (|v| + c_f,max)
  * (Section VIII) for device state U; blocks until the result is on the host. */
 rg_status rg_cfl_dt(const rg_geom *geom, const double *U, double gamma, double cfl, void *stream, double *dt);

@@ -11,6 +11,8 @@
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
                  const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
                  unsigned char *fallback_zones);
+int rgo_run_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_eps, const double *U, const double *Bf,
+                       double *whi);
 int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                   int npts, const double *pts, double *weno_vals, double *divB_vals);
 int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
@@ -180,6 +182,12 @@ int rgo_divfree(const rgo_mesh *m, int flags, double weno_eps, const double *U, 
                 double *coeffs, int *exps, double *face_nodal)
 {
     return rgo_run_divfree_coeffs(m, flags, weno_eps, U, Bf, z, coeffs, exps, face_nodal);
+}
+
+int rgo_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_eps, const double *U, const double *Bf,
+                   double *whi)
+{
+    return rgo_run_weno_order(m, bc_kind, flags, weno_eps, U, Bf, whi);
 }
 
 double rgo_cfl_dt(const rgo_mesh *m, double gamma, double cfl, const double *U)

@@ -64,6 +64,8 @@ def lib():
         L.rgo_recon.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
         L.rgo_divfree.restype = C.c_int
         L.rgo_divfree.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, _dp, _ip, _dp]
+        L.rgo_weno_order.restype = C.c_int
+        L.rgo_weno_order.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp]
         L.rgo_cfl_dt.restype = C.c_double
         L.rgo_cfl_dt.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp]
         L.rgo_init_harmonic.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
@@ -225,6 +227,13 @@ class OracleMesh:
         if rc != nb:
             raise RuntimeError("oracle divergence-free reconstruction failed")
         return c.reshape(3, nb), e.reshape(3, nb, 3), fn
+
+    def weno_order(self, U, Bf, bc=0, flags=0, weno_eps=WENO_EPS):
+        """Per-zone WENO-AO order indicator: min over variables of w_hi / gamma_hi."""
+        out = np.zeros(self.nz)
+        lib().rgo_weno_order(self._h, bc, flags, weno_eps, np.ascontiguousarray(U, np.float64),
+                             np.ascontiguousarray(Bf, np.float64), out)
+        return out
 
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return lib().rgo_cfl_dt(self._h, gamma, cfl, np.ascontiguousarray(U))

@@ -152,6 +152,7 @@ typedef struct {
     double *Phi;            /* nf * 8 */
     double *Gam;            /* ne */
     int first_order;        /* traces are the zones' states at t^n (the fallback's re-solve) */
+    double *whi;            /* nz, or NULL: the smallest over the variables of w_hi / gamma_hi */
 } step_ws;
 
 static int zone_of(const rgo_mesh *m, int qd, int k) { return qd * m->ktot + k; }
@@ -272,6 +273,7 @@ static void weno_zone(step_ws *w, int z)
             }
             for (int s = 0; s <= nsm; s++) wgt[s] /= tot;
         }
+        if (w->whi && (v == 0 || wgt[0] / WENO_GAMMA_HI < w->whi[z])) w->whi[z] = wgt[0] / WENO_GAMMA_HI;
         /* adaptive-order blend: (w_hi/g_hi)(P_hi - sum g_s P_s) + sum w_s P_s */
         for (int a = 0; a < nc; a++) {
             double lin = 0.0, nl = 0.0;
@@ -931,6 +933,36 @@ int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const 
     int nbx = w.nbx;
     free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc);
     return rc < 0 ? rc : nbx;
+}
+
+/* WENO-AO order indicator (test access): for every reconstructed zone the
+ * smallest over the eight variables of the large stencil's nonlinear weight
+ * over its linear weight (Section III); other zones get 0 */
+int rgo_run_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_eps, const double *U, const double *Bf,
+                       double *whi)
+{
+    step_ws w;
+    memset(&w, 0, sizeof(w));
+    w.m = m;
+    w.flags = flags;
+    w.weno_eps = weno_eps;
+    setup_bases(&w);
+    const int nz = m->nz, nf = m->nf, g = m->n_ghost, Nr = m->n_rad;
+    w.U = malloc(sizeof(double) * NVAR * nz);
+    w.Bf = malloc(sizeof(double) * nf);
+    memcpy(w.U, U, sizeof(double) * NVAR * nz);
+    memcpy(w.Bf, Bf, sizeof(double) * nf);
+    if (bc_kind == 0) boundary_fill(&w);
+    w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(double));
+    w.whi = whi;
+    for (int z = 0; z < nz; z++) whi[z] = 0.0;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int z = 0; z < nz; z++) {
+        int k = m->zone_shell[z];
+        if (k >= g - 1 && k <= g + Nr) weno_zone(&w, z);
+    }
+    free(w.U); free(w.Bf); free(w.wc);
+    return 0;
 }
 
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U)

@@ -180,6 +180,14 @@ class ShellMHD:
         N.rg_step_fallback_zones(self._geom, flags.data_ptr(), _stream())
         return flags
 
+    def weno_order(self):
+        """Per-zone WENO-AO order indicator of the last step (float32 on the device):
+        the large stencil's weight over its linear weight, smallest over the variables."""
+        import torch
+        whi = torch.empty(self.nz, dtype=torch.float32, device="cuda")
+        N.rg_step_weno_order(self._geom, whi.data_ptr(), _stream())
+        return whi
+
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())
 

@@ -389,6 +389,13 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         g->ffl = reinterpret_cast<unsigned char *>(fb) + RG_FB_COUNTER_BYTES;
         g->efl = g->ffl + NF;
         g->zfl = reinterpret_cast<unsigned char *>(fb) + marks;
+        double *wh = nullptr;
+        if (!alloc_zero(g, ((size_t)Z + 1) / 2, &wh)) {
+            set_error("device allocation of the step work buffers failed");
+            free_geom(g);
+            return RG_ENOMEM;
+        }
+        g->whi = reinterpret_cast<float *>(wh);
     } catch (const std::bad_alloc &) {
         set_error("out of host memory");
         free_geom(g);
@@ -540,6 +547,18 @@ extern "C" rg_status rg_step_fallback_zones(const rg_geom *g, uint8_t *flags, vo
     if (!flags) { set_error("null argument"); return RG_EINVAL; }
     if (hipMemcpyAsync(flags, g->zfl, (size_t)g->d.Z, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)) !=
         hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        return RG_EDEVICE;
+    }
+    return RG_OK;
+}
+
+extern "C" rg_status rg_step_weno_order(const rg_geom *g, float *whi, void *stream)
+{
+    if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }
+    if (!whi) { set_error("null argument"); return RG_EINVAL; }
+    if (hipMemcpyAsync(whi, g->whi, sizeof(float) * (size_t)g->d.Z, hipMemcpyDeviceToDevice,
+                       static_cast<hipStream_t>(stream)) != hipSuccess) {
         set_error("hipMemcpyAsync failed");
         return RG_EDEVICE;
     }

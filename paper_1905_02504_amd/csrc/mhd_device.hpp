@@ -269,7 +269,7 @@ __device__ __forceinline__ T emf3(const T U[4][8], const T E[4][3], const double
 template <int P, class T, class R>
 __device__ __forceinline__ void weno_core(const T (&du)[Tr<P>::NS], const R *__restrict__ Pl,
                                           const R *__restrict__ Ps, const R *__restrict__ Qs, T eps,
-                                          T (&out)[Tr<P>::NC])
+                                          T (&out)[Tr<P>::NC], T &whi)
 {
     using Tt = Tr<P>;
     const T ghi = T(WENO_GAMMA_HI), gs = T((1.0 - WENO_GAMMA_HI) / 7.0);
@@ -308,6 +308,7 @@ __device__ __forceinline__ void weno_core(const T (&du)[Tr<P>::NS], const R *__r
     }
     T itot = T(1) / tot;
     w0 *= itot;
+    whi = w0 / ghi;   // the large stencil's weight relative to its linear weight
 #pragma unroll
     for (int a = 0; a < Tt::NC; a++) {
         T lin = T(0), nl = T(0);

@@ -171,6 +171,9 @@ struct rg_geom {
     // allocation), and whether zfl holds flags of a step that had the
     // fallback on
     int *fbcnt = nullptr;
+    // the last step's per-zone WENO-AO order indicator [Z] (zones of the
+    // reconstructed shells)
+    float *whi = nullptr;
     unsigned char *zfl = nullptr, *ffl = nullptr, *efl = nullptr;
     bool fb_dirty = false;
     rg::AdjBuffers adj;

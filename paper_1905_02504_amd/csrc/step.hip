@@ -55,10 +55,11 @@ __global__ void bc_faces(DevGeom G, int bc, const double *Bf, double *Bo)
 // WENO-AO reconstruction (Section III) of variable v of zone (c, k).  All
 // lanes of a wavefront lie in column c, so the column's stencil offsets and
 // least-squares matrices are uniform and read as scalars.
+// Returns the large stencil's nonlinear weight relative to its linear weight.
 template <int P, class R>
-__device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restrict__ U, R *__restrict__ wc,
-                                         const R *__restrict__ Pl, const R *__restrict__ Ps, const R *__restrict__ Qs,
-                                         R eps, int c, int k, int v)
+__device__ __forceinline__ R weno_var(const DevGeom &G, const double *__restrict__ U, R *__restrict__ wc,
+                                      const R *__restrict__ Pl, const R *__restrict__ Ps, const R *__restrict__ Qs,
+                                      R eps, int c, int k, int v)
 {
     using T = Tr<P>;
     const i64 z = (i64)c * G.K + k;
@@ -71,20 +72,24 @@ __device__ __forceinline__ void weno_var(const DevGeom &G, const double *__restr
         const int dz = m < 0 ? 0 : (int)(((i64)(m >> 3) - c) * G.K + (m & 7) - 3);
         du[j] = R(Uv[z + dz] - u0);
     }
-    R o[T::NC];
-    weno_core<P, R, R>(du, Pl, Ps, Qs, eps, o);
+    R o[T::NC], whi;
+    weno_core<P, R, R>(du, Pl, Ps, Qs, eps, o, whi);
     R *out = wc + (i64)v * T::NC * G.Z + z;
 #pragma unroll
     for (int a = 0; a < T::NC; a++) out[(i64)a * G.Z] = o[a];
+    return whi;
 }
 
 // One wavefront per run of up to 64 shells of one column, the eight
 // variables in turn.  With a short tail (nleft shells, at most 8) each column
 // gets one more wavefront whose lanes take (tail shell, variable) pairs.
+// whi[z]: the smallest over the eight variables of the large stencil's weight
+// relative to its linear weight (the order WENO-AO keeps in zone z).
 template <int P, class R>
 __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restrict__ U, R *__restrict__ wc,
                                                 const R *__restrict__ PlA, const R *__restrict__ PsA,
-                                                const R *__restrict__ QsA, R eps, int nchunk, int nu, int nleft)
+                                                const R *__restrict__ QsA, R eps, int nchunk, int nu, int nleft,
+                                                float *__restrict__ whi)
 {
     using T = Tr<P>;
     const int per = nchunk + (nleft > 0);
@@ -96,18 +101,28 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
     if (ch < nchunk) {
         const int kk = ch * 64 + threadIdx.x;
         if (kk >= nu) return;
+        float wmin = 1e30f;
 #pragma unroll 1
         for (int v = 0; v < 8; v++) {
             // an opaque zero offset keeps the matrix reads inside the loop (the
             // matrices would not fit in registers); they are re-read from cache
             int vo = 0;
             __asm__ __volatile__("" : "+s"(vo));
-            weno_var<P, R>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, eps, c, G.g - 1 + kk, v);
+            wmin = fminf(wmin, float(weno_var<P, R>(G, U, wc, Pl + vo, Ps + vo, Qs + vo, eps, c, G.g - 1 + kk, v)));
         }
+        whi[(i64)c * G.K + G.g - 1 + kk] = wmin;
     } else {
+        // one wavefront: the lanes of a tail shell meet in LDS
+        __shared__ float s_w[64];
         const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
-        if (kk >= nu + nleft) return;
-        weno_var<P, R>(G, U, wc, Pl, Ps, Qs, eps, c, G.g - 1 + kk, v);
+        const bool live = kk < nu + nleft;
+        s_w[threadIdx.x] = live ? float(weno_var<P, R>(G, U, wc, Pl, Ps, Qs, eps, c, G.g - 1 + kk, v)) : 1e30f;
+        __syncthreads();
+        if (live && v == 0) {
+            float wmin = s_w[threadIdx.x];
+            for (int j = 1; j < 8; j++) wmin = fminf(wmin, s_w[threadIdx.x + j]);
+            whi[(i64)c * G.K + G.g - 1 + kk] = wmin;
+        }
     }
 }
 
@@ -1066,7 +1081,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     const RunSplit wr = run_split(G.Nr + 2);
     weno_cols<P, R><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
         G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF),
-        R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft);
+        R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft, g->whi);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
     const RunSplit br = run_split(G.Nr + 3), ba = run_split(G.Nr + 2);

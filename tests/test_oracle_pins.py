@@ -430,3 +430,33 @@ def test_step_divergence_free_and_conservative(mesh4):
                 bnd -= dt * (1 if fz[f, 0] == z else -1) * phi[f]
     dsum = ((Uo - U)[:, act] * vol[act]).sum(1)
     np.testing.assert_allclose(dsum[:5], bnd[:5], rtol=0, atol=1e-13 * np.abs(U[:5, act] * vol[act]).sum(1).max())
+
+
+def test_weno_order_indicator():
+    """The WENO-AO order indicator (the large stencil's weight over its linear
+    weight, smallest over the variables): exactly the linear weights on
+    uniform data and with linear weights forced; across a jump that one face
+    neighbour alone carries, the one-sided small stencil without that
+    neighbour is exactly smooth and takes essentially all the weight; where
+    every stencil member agrees the weights are the linear ones again."""
+    from tests.test_oracle_fallback import blast_state
+    for order in (3, 4):
+        m = O.OracleMesh(8, 8, 1.0, 2.0, n_ghost=3, order=order)
+        cen, _, shell, _ = m.zones()
+        rec = (shell >= m.n_ghost - 1) & (shell <= m.n_ghost + m.n_rad)
+        U = np.zeros((8, m.nz))
+        U[0], U[1], U[4], U[5] = 1.0, 0.3, 2.0, 0.5
+        w = m.weno_order(U, np.zeros(m.nf))
+        assert np.abs(w[rec] - 1.0).max() < 1e-15 and (w[~rec] == 0.0).all()
+        prob = RI.blast_problem(p_in=1000.0, radius=0.3)
+        Ub, Bb = blast_state(m, prob)
+        assert (m.weno_order(Ub, Bb, flags=O.FLAG_LINEAR_WEIGHTS)[rec] == 1.0).all()
+        w = m.weno_order(Ub, Bb)
+        _, nbr = m.zone_faces()
+        p = RI.blast_pressure(prob, cen)
+        inner = (shell >= m.n_ghost + 1) & (shell <= m.n_ghost + m.n_rad - 2)   # clear of the boundary fill
+        one = inner & ((p[nbr] != p[:, None]).sum(1) == 1)
+        far = rec & (np.abs(np.linalg.norm(cen - prob["centre"], axis=1) - prob["radius"]) > 0.6)
+        assert one.sum() > 10 and far.sum() > 1000
+        assert w[one].max() < 1e-12
+        assert np.abs(w[far] - 1.0).max() < 1e-14
