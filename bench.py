@@ -67,24 +67,38 @@ def measured_traffic(kernel):
 
 
 def cpu_baseline(order, sample_n=16, sample_nr=16):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the same workload, on
+    all the OpenMP threads it gets, and on one thread for a smaller sample."""
+    import ctypes
     import numpy as np
     import rg_inputs as RI
     from oracle import oracle as O
-    m = O.OracleMesh(sample_n, sample_nr, order=order, n_ghost=order - 1)
     prob = RI.alfven_problem()
-    U, Bf = m.init_alfven(prob)
-    noise = RI.white_noise(m.nz)
-    U[0] *= 1 + 0.01 * noise[0]
-    dt = m.cfl_dt(U, 0.3, prob["gamma"])
-    t0 = time.perf_counter()
-    m.step(U, Bf, dt, gamma=prob["gamma"])
-    el = time.perf_counter() - t0
-    zones = 6 * sample_n * sample_n * sample_nr
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": zones / el, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+
+    def one_step(n, nr):
+        m = O.OracleMesh(n, nr, order=order, n_ghost=order - 1)
+        U, Bf = m.init_alfven(prob)
+        noise = RI.white_noise(m.nz)
+        U[0] *= 1 + 0.01 * noise[0]
+        dt = m.cfl_dt(U, 0.3, prob["gamma"])
+        t0 = time.perf_counter()
+        m.step(U, Bf, dt, gamma=prob["gamma"])
+        return time.perf_counter() - t0, 6 * n * n * nr
+
+    O.lib()   # the oracle's OpenMP runtime is the process's libgomp
+    gomp = ctypes.CDLL("libgomp.so.1")
+    threads = gomp.omp_get_max_threads()
+    el, zones = one_step(sample_n, sample_nr)
+    gomp.omp_set_num_threads(1)
+    try:
+        el1, zones1 = one_step(4, 8)
+    finally:
+        gomp.omp_set_num_threads(threads)
+    return {"value": zones / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one order-{order} step on 6x{sample_n}x{sample_n}x{sample_nr} zones "
-                      f"(Alfven wave + noise), {el:.2f} s, geometry excluded"}
+                      f"(Alfven wave + noise), {el:.2f} s, geometry excluded",
+            "single_thread": {"value": zones1 / el1, "sample": f"one order-{order} step on 6x4x4x8 zones, "
+                                                                f"{el1:.2f} s"}}
 
 
 def time_adjoint(reps=5):
@@ -139,6 +153,38 @@ def time_adjoint(reps=5):
             "fp32": {"ms_per_step": t_fwd32, "ms_per_adjoint": t_adj32, "adjoint_speedup_vs_fp64": t_adj / t_adj32,
                      "rel_l2_vs_fp64_adjoint": {"zone_state": float((gU32 - gU).norm() / gU.norm()),
                                                 "face_B": float((gB32 - gB).norm() / gB.norm())}}}
+
+
+def measured_peaks(reps=5):
+    """Attainable rates on this GPU, beside the datasheet peaks: the FP64
+    vector FMA rate of rg_fma_probe (16 independent chains per lane) and the
+    bandwidth of a 2 GiB device-to-device copy (bytes read + written)."""
+    import torch
+    from paper_1905_02504_amd import _native as NV
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    n, iters = 256 * 8192, 2048
+    sink = torch.empty(n, dtype=torch.float64, device="cuda")
+    t = timed(lambda: NV.rg_fma_probe(sink.data_ptr(), n, iters, stream.cuda_stream))
+    fp64 = 2.0 * 16 * iters * n / t / 1e12
+    del sink
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    t = timed(lambda: b.copy_(a))
+    gbs = 2.0 * a.numel() * 8 / t / 1e9
+    del a, b
+    return {"fp64_valu_tflops": fp64, "hbm_copy_gbs": gbs}
 
 
 def weno_order_stats(sh):
@@ -307,6 +353,12 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
                 "algorithmic_flops": flops[dom], "algorithmic_bytes": bytes_[dom]}
+    peaks = measured_peaks()
+    roof["measured_peak"] = peaks["fp64_valu_tflops"] if roof["unit"] == "TFLOP/s" else peaks["hbm_copy_gbs"]
+    roof["frac_of_measured_peak"] = roof["achieved"] / roof["measured_peak"]
+    log(f"[bench] measured peaks: FP64 FMA {peaks['fp64_valu_tflops']:.1f} TFLOP/s, device copy "
+        f"{peaks['hbm_copy_gbs']:.0f} GB/s; dominant kernel at {100 * roof['frac_of_measured_peak']:.1f} % of the "
+        f"measured peak")
     mixed = None
     if not args.no_mixed:
         from paper_1905_02504_amd import _native as NV
@@ -368,6 +420,7 @@ def main():
                    "setup_s": {"geometry": round(t_geom, 2), "initial_data": round(t_init, 2)},
                    "stage_ms_per_step": {k: round(v / nrec, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
+        "measured_peaks": peaks,
         "div_b_rel_max": diag64["div_rel_max"],
         "weno_order_last_step": weno_order,
         "mixed": mixed,

@@ -268,6 +268,13 @@ rg_status rg_profile_end(rg_geom *geom, double *ms, int32_t *nsteps);
  * amortised over the column).  Host only. */
 rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
 
+/* Benchmark helper (not part of the scheme): launches n_threads (a multiple
+ * of 256) lanes that each run iters x 16 independent FP64 FMAs and write one
+ * double to sink[n_threads] (device).  Timed by the caller, it gives the
+ * attainable FP64 vector rate (2 x 16 x iters x n_threads flops).
+ * Asynchronous on `stream`. */
+rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters, void *stream);
+
 const char *rg_last_error(void);
 
 /* Name and one-line meaning of a status code (static string). */

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librg.so")
-SOURCES = ["mesh.cpp", "refel.cpp", "geom.cpp", "capi.cpp", "init.cpp", "step.hip", "adjoint.hip"]
+SOURCES = ["mesh.cpp", "refel.cpp", "geom.cpp", "capi.cpp", "init.cpp", "step.hip", "adjoint.hip", "probe.hip"]
 ARCH = "gfx950"
 
 

@@ -579,6 +579,12 @@ extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, 
     return launch_cfl(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
 }
 
+extern "C" rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters, void *stream)
+{
+    if (!sink) { set_error("null argument"); return RG_EINVAL; }
+    return launch_fma_probe(sink, (long long)n_threads, (int)iters, stream);
+}
+
 extern "C" rg_status rg_profile_begin(rg_geom *g)
 {
     if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }
