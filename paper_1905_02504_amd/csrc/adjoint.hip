@@ -845,13 +845,19 @@ __global__ __launch_bounds__(64) void adj_weno(DevGeom G, const double *__restri
     const double *__restrict__ Ps = G.Ps + (i64)c * 7 * 18;
     const double *__restrict__ Qs = G.Qs + (i64)c * T::NC * T::NC;
     if (ch < nchunk) {
+        // the column's matrices staged in LDS once, read as broadcasts
+        __shared__ double sPl[T::NC * T::NS], sPs[7 * 18], sQs[T::NC * T::NC];
+        for (int j = threadIdx.x; j < T::NC * T::NS; j += 64) sPl[j] = Pl[j];
+        for (int j = threadIdx.x; j < 7 * 18; j += 64) sPs[j] = Ps[j];
+        for (int j = threadIdx.x; j < T::NC * T::NC; j += 64) sQs[j] = Qs[j];
+        __syncthreads();
         const int kk = ch * 64 + threadIdx.x;
         if (kk >= nu) return;
 #pragma unroll 1
         for (int v = 0; v < 8; v++) {
             int vo = 0;
             __asm__ __volatile__("" : "+s"(vo));
-            weno_var_vjp<P>(G, U, gwc, gdu, Pl + vo, Ps + vo, Qs + vo, eps, c, G.g - 1 + kk, v);
+            weno_var_vjp<P>(G, U, gwc, gdu, sPl + vo, sPs + vo, sQs + vo, eps, c, G.g - 1 + kk, v);
         }
     } else {
         const int kk = nu + (int)threadIdx.x / 8, v = threadIdx.x % 8;
