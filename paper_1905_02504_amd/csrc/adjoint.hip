@@ -188,29 +188,27 @@ __global__ __launch_bounds__(256) void adj_edge_emf(DevGeom G, double gam, const
 #pragma unroll
     for (int s = 0; s < 4; s++) {
 #pragma unroll
-        for (int v = 0; v < 8; v++) { U[s][v] = rec[s * 11 + v]; gU[s][v] = 0.0; }
+        for (int v = 0; v < 8; v++) { U[s][v] = rec[s * 9 + v]; gU[s][v] = 0.0; }
+        Et[s] = rec[s * 9 + 8];
 #pragma unroll
-        for (int v = 0; v < 3; v++) { E[s][v] = rec[s * 11 + 8 + v]; gE[s][v] = 0.0; }
-        Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
+        for (int v = 0; v < 3; v++) { E[s][v] = Et[s] * tt[v]; gE[s][v] = 0.0; }
         gEt[s] = 0.0;
     }
     if (nzs == 4) {
         emf4_vjp(U, Et, frame, gam, g, gU, gEt);
-#pragma unroll
-        for (int s = 0; s < 4; s++)
-#pragma unroll
-            for (int v = 0; v < 3; v++) gE[s][v] = gEt[s] * tt[v];
     } else {
+        // the solver took E = Et t
         emf3_vjp(U, E, N3, tt, gam, g, gU, gE);
+#pragma unroll
+        for (int s = 0; s < 4; s++) gEt[s] = gE[s][0] * tt[0] + gE[s][1] * tt[1] + gE[s][2] * tt[2];
     }
     double *o = getr + etr_at(e, p, 0);
 #pragma unroll
     for (int s = 0; s < 4; s++) {
         if (s >= nzs) continue;
 #pragma unroll
-        for (int v = 0; v < 8; v++) o[s * 11 + v] = gU[s][v];
-#pragma unroll
-        for (int v = 0; v < 3; v++) o[s * 11 + 8 + v] = gE[s][v];
+        for (int v = 0; v < 8; v++) o[s * 9 + v] = gU[s][v];
+        o[s * 9 + 8] = gEt[s];
     }
 }
 
@@ -430,15 +428,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ad
             } else {
                 e = (i64)G.col_v[4 * c + LocalEdges::CORNER[le - 8]] * G.K + k;
             }
-            const double *go = getr + etr_at(e, 0, slot);   // point p at go + 44 p
+            const double *go = getr + etr_at(e, 0, slot);   // point p at go + 36 p
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
                 const R w = pick<R>(G.eintc, G.eintcF)[kk * 3 + p];
+                const double *t = edge_tangent(G, c, le, pc);
 #pragma unroll
-                for (int v = 0; v < 8; v++) gaU[v] += w * R(go[pc * 44 + v]);
-                gaF[2][6] += w * R(go[pc * 44 + 8]);   // E_x = H[B_y]
-                gaF[0][7] += w * R(go[pc * 44 + 9]);   // E_y = F[B_z]
-                gaF[1][5] += w * R(go[pc * 44 + 10]);  // E_z = G[B_x]
+                for (int v = 0; v < 8; v++) gaU[v] += w * R(go[pc * 36 + v]);
+                const R gt = w * R(go[pc * 36 + 8]);   // the record held E . t
+                gaF[2][6] += gt * R(t[0]);   // E_x = H[B_y]
+                gaF[0][7] += gt * R(t[1]);   // E_y = F[B_z]
+                gaF[1][5] += gt * R(t[2]);   // E_z = G[B_x]
             }
         }
     }

@@ -375,7 +375,7 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                  upload_f32(g, r.fintc, &d.fintcF) && upload_f32(g, r.eintc, &d.eintcF);
         if (!ok) { set_error("device allocation or upload of the geometry failed"); free_geom(g); return RG_ENOMEM; }
         ok = alloc_zero(g, (size_t)NVAR * NC * Z, &g->wcoef) && alloc_zero(g, (size_t)Q * NF, &g->bnod) &&
-             alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &g->etr) &&
+             alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)9 * 3 * 4 * NE, &g->etr) &&
              alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
              alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red) &&
              alloc_zero(g, (size_t)ncol * (m.Nr + 2) * 3 * N, &g->bnode);
@@ -475,7 +475,7 @@ bool alloc_adjoint(rg_geom *g)
     bool ok = alloc_zero(g, 8 * Z, &A.Ubc) && alloc_zero(g, NF, &A.Bbc) &&
               alloc_zero(g, (size_t)d.ncol * d.NIN * d.NOUTB, &A.MbA) && alloc_zero(g, 8 * Z, &A.gUo) && alloc_zero(g, NF, &A.gBo) &&
               alloc_zero(g, 3 * Z, &A.gzoneB) && alloc_zero(g, 8 * (size_t)d.NC * Z, &A.gwc) &&
-              alloc_zero(g, (size_t)16 * d.Q * 2 * NF, &A.gftr) && alloc_zero(g, (size_t)11 * 3 * 4 * NE, &A.getr) &&
+              alloc_zero(g, (size_t)16 * d.Q * 2 * NF, &A.gftr) && alloc_zero(g, (size_t)9 * 3 * 4 * NE, &A.getr) &&
               alloc_zero(g, NE, &A.gGam) && alloc_zero(g, 8 * NF, &A.gPhi) &&
               alloc_zero(g, nzr * 3 * d.N, &A.gbnode) && alloc_zero(g, (size_t)d.Q * NF, &A.gbnod) &&
               alloc_zero(g, nzr * (d.NIN - NA), &A.gside) && alloc_zero(g, NF * 2 * (3 + 3 * (size_t)d.NC), &A.gsb) &&
@@ -646,13 +646,13 @@ extern "C" rg_status rg_geom_work(const rg_geom *g, double *flops, double *bytes
     double avg = N * E * (8 + FLUX + 32 * 2);
     double trc = 6 * 8 * Q * r.NFN * 4 * 2 + 6 * Q * 8 * 5 + 12 * 3 * r.NEN * 11 * 2;
     flops[4] = zr * (init + first + (r.order - 1) * sweep + avg + trc);
-    bytes[4] = 8 * (zr * (5 * (NC + 1) + 3 * N + 6 * Q * 16 + 36 * 11) + m.ncol * N * (NC + 10));
+    bytes[4] = 8 * (zr * (5 * (NC + 1) + 3 * N + 6 * Q * 16 + 36 * 9) + m.ncol * N * (NC + 10));
     // 5 face HLL fluxes
     flops[5] = ff * Q * (HLL + 2 + 16);
     bytes[5] = 8 * (ff * (2 * 16 * Q + 8 + 1) + m.ncol * 4 * Q + m.nae * 4 * Q);
     // 6 edge EMFs (four-state solver at three Simpson points)
     flops[6] = ee * 3 * (4 * (2 * FAST + 4 * 5 + 8) + 40);
-    bytes[6] = 8 * (ee * (3 * 4 * 11 + 1) + m.nae * 30.0 + m.nv * 18.0);
+    bytes[6] = 8 * (ee * (3 * 4 * 9 + 1) + m.nae * 30.0 + m.nv * 18.0);
     // 7 finite-volume update and constrained transport
     flops[7] = zi * (8 * 6 * 2 + 8 * 2) + ff * 10;
     bytes[7] = 8 * (zi * (6 * 8 + 8 + 3 + 8 + 1) + ff * (4 + 2 + 1));

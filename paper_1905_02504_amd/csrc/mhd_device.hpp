@@ -51,14 +51,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // Face record (face f, quadrature point q, side s): the 8 time-averaged
 // conserved variables, then the 8 time-averaged normal fluxes; the two sides
 // of a point are adjacent, [f][q][side][16].  Edge record (edge e, Simpson
-// point p, slot s): the 8 variables, then the 3 components of E;
-// [e][p][slot][11].
+// point p, slot s): the 8 variables, then E . t, the electric field along the
+// edge's canonical direction at that point (the only component either edge
+// solver uses); [e][p][slot][9].
 template <int P>
 __host__ __device__ __forceinline__ long long ftr_at(long long f, int q, int side)
 {
     return ((f * Tr<P>::Q + q) * 2 + side) * 16;
 }
-__host__ __device__ __forceinline__ long long etr_at(long long e, int p, int slot) { return ((e * 3 + p) * 4 + slot) * 11; }
+__host__ __device__ __forceinline__ long long etr_at(long long e, int p, int slot) { return ((e * 3 + p) * 4 + slot) * 9; }
 
 // Faces of the flux stage (radial faces kf in [g, g+Nr], angular faces in
 // shells [g, g+Nr-1]): face index t of that range -> face id, unit normals
@@ -106,6 +107,14 @@ __device__ __forceinline__ i64 emf_edge(const DevGeom &G, i64 t, int p, const do
     frame = G.aeF + ((i64)ae * 3 + p) * 9;
     N3 = nullptr;
     return G.NRE + (i64)ae * (G.K + 1) + kf;
+}
+
+// Canonical unit tangent at Simpson point p (canonical order) of local edge le
+// of column c: the third row of the frame the EMF stage uses
+__device__ __forceinline__ const double *edge_tangent(const DevGeom &G, int c, int le, int p)
+{
+    if (le < 8) return G.aeF + ((i64)G.col_ae[4 * c + LocalEdges::FACE[le]] * 3 + p) * 9 + 6;
+    return G.vF + (i64)G.col_v[4 * c + LocalEdges::CORNER[le - 8]] * 9 + 6;
 }
 
 // ---------------------------------------------------------------- ideal MHD

@@ -542,12 +542,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         }
     }
     // Edges: one task per (zone, edge) interpolates the averaged state and the
-    // three electric-field components (eq. 2.3) to the edge's Simpson points.
+    // three electric-field components (eq. 2.3) to the edge's Simpson points
+    // and keeps E . t there.
     if (lane < ZPW * 12) {
         const int zq = lane / 12, le = lane % 12;
         const unsigned ztq = lb * ZPW + zq;
         if (ztq < (unsigned)nzr) {
             const int cq = (int)(ztq / (unsigned)KR), kq = G.g - 1 + (int)(ztq % (unsigned)KR);
+            const int rev = G.col_rev[(i64)cq * 12 + le], slot = G.col_slot[(i64)cq * 12 + le];
+            // the tangents first, so that their loads overlap the interpolation
+            R tv[3][3];
+#pragma unroll
+            for (int p = 0; p < 3; p++) {
+                const double *t = edge_tangent(G, cq, le, rev ? 2 - p : p);
+                tv[p][0] = R(t[0]);
+                tv[p][1] = R(t[1]);
+                tv[p][2] = R(t[2]);
+            }
             const R *sx = s_f + zq * ZS;
             const R *ew = pick<R>(G.eintc, G.eintcF);
             R ae3[3][11];
@@ -571,7 +582,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                     for (int v = 0; v < 11; v++) ae3[p][v] += w * x[v];
                 }
             }
-            const int rev = G.col_rev[(i64)cq * 12 + le], slot = G.col_slot[(i64)cq * 12 + le];
             i64 e;
             if (le < 8) {
                 const int ae = G.col_ae[4 * cq + LocalEdges::FACE[le]];
@@ -579,12 +589,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             } else {
                 e = (i64)G.col_v[4 * cq + LocalEdges::CORNER[le - 8]] * G.K + kq;
             }
-            R *o = etr + etr_at(e, 0, slot);   // point p at o + 44 p
+            R *o = etr + etr_at(e, 0, slot);   // point p at o + 36 p
 #pragma unroll
             for (int p = 0; p < 3; p++) {
                 const int pc = rev ? 2 - p : p;
 #pragma unroll
-                for (int v = 0; v < 11; v++) o[pc * 44 + v] = ae3[p][v];
+                for (int v = 0; v < 8; v++) o[pc * 36 + v] = ae3[p][v];
+                o[pc * 36 + 8] = tv[p][0] * ae3[p][8] + tv[p][1] * ae3[p][9] + tv[p][2] * ae3[p][10];
             }
         }
     }
@@ -672,15 +683,16 @@ __global__ __launch_bounds__(192) void edge_emf(DevGeom G, double gam, const R *
     if (live) {
         double U[4][8], E[4][3], Et[4];
         const double *tt = frame + 6;
-        // all four slots are read (a three-zone edge leaves slot 3 unused)
-        const R *rec = etr + etr_at(e, p, 0);
+        // all four slots are read (a three-zone edge leaves slot 3 unused);
+        // the three-zone solver takes E along t, the only part it projects on
 #pragma unroll
         for (int s = 0; s < 4; s++) {
+            const R *rec = etr + etr_at(e, p, s);
 #pragma unroll
-            for (int v = 0; v < 8; v++) U[s][v] = rec[s * 11 + v];
+            for (int v = 0; v < 8; v++) U[s][v] = rec[v];
+            Et[s] = rec[8];
 #pragma unroll
-            for (int v = 0; v < 3; v++) E[s][v] = rec[s * 11 + 8 + v];
-            Et[s] = E[s][0] * tt[0] + E[s][1] * tt[1] + E[s][2] * tt[2];
+            for (int v = 0; v < 3; v++) E[s][v] = Et[s] * tt[v];
         }
         const double Es = (nzs == 4) ? emf4<double>(U, Et, frame, gam) : emf3<double>(U, E, N3, tt, gam);
         s_p[tid] = wl * Es;
@@ -816,7 +828,7 @@ __global__ __launch_bounds__(256) void fb_flag(DevGeom G, double dt, double gam,
 // conserved state at t^n (its eight averages in Uo before the update) and the
 // physical flux of that state in the records the predictor fills (face: the
 // state and the normal flux at each quadrature point; edge: the state and
-// E = (H[B_y], F[B_z], G[B_x]) at each Simpson point).
+// E . t with E = (H[B_y], F[B_z], G[B_x]) at each Simpson point).
 template <int P, class R>
 __global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const double *__restrict__ Uo,
                                                  const unsigned char *__restrict__ ffl,
@@ -867,12 +879,11 @@ __global__ __launch_bounds__(256) void fb_traces(DevGeom G, double gam, const do
     }
     for (int le = 0; le < 12; le++) {
         if (!efl[eid[le]]) continue;
-        R *o = etr + etr_at(eid[le], 0, G.col_slot[(i64)c * 12 + le]);   // point p at o + 44 p
+        R *o = etr + etr_at(eid[le], 0, G.col_slot[(i64)c * 12 + le]);   // point p at o + 36 p
         for (int p = 0; p < 3; p++) {
-            for (int v = 0; v < 8; v++) o[p * 44 + v] = R(u[v]);
-            o[p * 44 + 8] = R(F[2][6]);
-            o[p * 44 + 9] = R(F[0][7]);
-            o[p * 44 + 10] = R(F[1][5]);
+            const double *t = edge_tangent(G, c, le, p);
+            for (int v = 0; v < 8; v++) o[p * 36 + v] = R(u[v]);
+            o[p * 36 + 8] = R(t[0] * F[2][6] + t[1] * F[0][7] + t[2] * F[1][5]);
         }
     }
 }
