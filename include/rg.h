@@ -231,6 +231,25 @@ rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, d
                          double wavelength, double gamma, double t, const double *noise, double noise_amp,
                          double *U, double *Bf);
 
+/* Initial data on the host (caller-owned host arrays U[8][n_zones],
+ * Bf[n_faces]) for the spherical shock tubes of Section VIII.c, with the pole
+ * on the z axis.  left and right are double[7] primitive states
+ * (rho, p, v_r, v_theta, v_phi, B_theta, B_phi) for r <= rm and r > rm; the
+ * fluid jump has no taper.  B = Br0 sin(theta) (r0/r)^2 r_hat
+ * + (sin(theta)/2) T(r) phi_hat with T(r) = B_phiL (1 - tanh((r - rm)/delta))
+ * + B_phiR (1 + tanh((r - rm)/delta)): the toroidal part is the curl of the
+ * radial vector potential A_r = (r cos(theta)/2) T(r) of that section, whose
+ * edge circulations (5-point Gauss on four pieces of each edge) give the face
+ * values by Stokes; the radial part, which has no vector potential on a shell,
+ * adds to each radial face the flux through the solid angle it subtends (the
+ * same number for all radial faces of a column), so Bf is divergence-free to
+ * round-off.  Zone averages by the zone cubature.  Works on a host-only
+ * geometry.  RG_EINVAL if a density or pressure is not positive, if
+ * r0, rm, delta <= 0 or gamma <= 1, or if B_theta is not 0 on either side (a
+ * radial potential cannot produce it). */
+rg_status rg_init_tube(const rg_geom *geom, const double *left, const double *right, double Br0, double r0,
+                       double rm, double delta, double gamma, double *U, double *Bf);
+
 /* Diagnostics of a state on the device (for checks after a step; not part of
  * the scheme): over the interior zones, the largest relative divergence
  * |sum_faces sigma A <B.n>| / sum_faces A |<B.n>| (sigma = +1 on outward

@@ -20,6 +20,8 @@ int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const 
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U);
 void rgo_run_init_harmonic(const rgo_mesh *m, const double *rho, const double *v, const double *A, double p,
                            double gamma, double *U, double *Bf);
+void rgo_run_init_tube(const rgo_mesh *m, const double *left, const double *right, double Br0, double r0,
+                       double rm, double delta, double gamma, double *U, double *Bf);
 void rgo_run_init_alfven(const rgo_mesh *m, const double *frame, double rho, double p, double B0, double dB,
                          double wavelength, double gamma, double t, double *U, double *Bf);
 int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const double *J, const double *met,
@@ -205,6 +207,14 @@ void rgo_init_alfven(const rgo_mesh *m, const double *frame, double rho, double 
                      double wavelength, double gamma, double t, double *U, double *Bf)
 {
     rgo_run_init_alfven(m, frame, rho, p, B0, dB, wavelength, gamma, t, U, Bf);
+}
+
+/* spherical shock tube (Section VIII.c): states (rho, p, v_r, v_theta, v_phi,
+ * B_theta, B_phi) inside and outside r = rm, B_r = Br0 sin(theta) (r0/r)^2 */
+void rgo_init_tube(const rgo_mesh *m, const double *left, const double *right, double Br0, double r0, double rm,
+                   double delta, double gamma, double *U, double *Bf)
+{
+    rgo_run_init_tube(m, left, right, Br0, r0, rm, delta, gamma, U, Bf);
 }
 
 /* reference-element matrices for checks: time nodes and weights, nodes,

@@ -71,6 +71,8 @@ def lib():
         L.rgo_init_harmonic.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
         L.rgo_init_alfven.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.rgo_init_tube.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, _dp, _dp]
         L.rgo_refel_query.restype = C.c_int
         L.rgo_refel_query.argtypes = [C.c_int, _ip, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
@@ -188,6 +190,17 @@ class OracleMesh:
         lib().rgo_init_alfven(self._h, np.ascontiguousarray(prob["frame"], np.float64).ravel(),
                               prob["rho"], prob["p"], prob["B0"], prob["dB"], prob["wavelength"],
                               prob["gamma"], float(t), U, Bf)
+        return U, Bf
+
+    def init_tube(self, prob):
+        """Spherical shock tube (Section VIII.c): prob holds the primitive states
+        'left' and 'right' (rho, p, v_r, v_theta, v_phi, B_theta, B_phi; B_theta
+        must be 0), 'Br0', 'r0', 'rm', 'delta' and 'gamma'."""
+        U = np.zeros((NVAR, self.nz)); Bf = np.zeros(self.nf)
+        L, R = (np.ascontiguousarray(prob[k], np.float64) for k in ("left", "right"))
+        assert L.shape == (7,) and R.shape == (7,) and L[5] == 0.0 and R[5] == 0.0
+        lib().rgo_init_tube(self._h, L, R, float(prob["Br0"]), float(prob["r0"]), float(prob["rm"]),
+                            float(prob["delta"]), float(prob["gamma"]), U, Bf)
         return U, Bf
 
     # the method -----------------------------------------------------------

@@ -102,6 +102,18 @@ class ShellMHD:
                          prob["wavelength"], prob["gamma"], float(t), _ptr(nz), float(noise_amp), _ptr(U), _ptr(Bf))
         return U, Bf
 
+    def init_tube(self, prob):
+        """rg_init_tube: host (U, Bf) of a spherical shock tube; prob holds 'left' and
+        'right' (rho, p, v_r, v_theta, v_phi, B_theta, B_phi), 'Br0', 'r0', 'rm',
+        'delta' and 'gamma'."""
+        U = np.zeros((8, self.nz)); Bf = np.zeros(self.nf)
+        L, R = (np.ascontiguousarray(prob[k], np.float64) for k in ("left", "right"))
+        if L.shape != (7,) or R.shape != (7,):
+            raise ValueError("left and right are 7 primitive values each")
+        N.rg_init_tube(self._geom, _ptr(L), _ptr(R), float(prob["Br0"]), float(prob["r0"]), float(prob["rm"]),
+                       float(prob["delta"]), float(prob["gamma"]), _ptr(U), _ptr(Bf))
+        return U, Bf
+
     # the step ------------------------------------------------------------------
     def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0, weno_eps=0.0,
              fallback=False):

@@ -79,6 +79,8 @@ def lib():
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
+        L.rg_init_tube.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   _vp, _vp]
         L.rg_geom_work.argtypes = [_vp, _dp, _dp]
         L.rg_diag.argtypes = [_vp, _vp, _vp, C.c_double, _vp, C.POINTER(rg_diag_out)]
         L.rg_geom_work.restype = C.c_int
@@ -87,7 +89,7 @@ def lib():
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
                      "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
-                     "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_diag"):
+                     "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -187,6 +189,11 @@ def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
     out = C.c_double(0.0)
     check(lib().rg_cfl_dt(geom, _vp(U_ptr), gamma, cfl, _vp(stream), C.byref(out)), "rg_cfl_dt")
     return out.value
+
+
+def rg_init_tube(geom, left_ptr, right_ptr, Br0, r0, rm, delta, gamma, U_ptr, Bf_ptr):
+    check(lib().rg_init_tube(geom, _vp(left_ptr), _vp(right_ptr), Br0, r0, rm, delta, gamma, _vp(U_ptr), _vp(Bf_ptr)),
+          "rg_init_tube")
 
 
 def rg_init_alfven(geom, frame_ptr, rho, p, B0, dB, wavelength, gamma, t, noise_ptr, noise_amp, U_ptr, Bf_ptr):

@@ -187,6 +187,37 @@ def sod_primitives(prob: dict, centroids: np.ndarray) -> tuple:
     return rho, p
 
 
+SQRT4PI = float(np.sqrt(4.0 * np.pi))
+
+
+def _tube(r_in, r_out, n_rad, left, right, Br0, gamma, t_end):
+    rm = 4.5
+    return {"r_in": r_in, "r_out": r_out, "left": tuple(left), "right": tuple(right), "Br0": Br0, "r0": 4.5,
+            "rm": rm, "delta": 0.5 * rm * np.log(r_out / r_in) / n_rad, "gamma": gamma, "t_end": t_end}
+
+
+def brio_wu_problem(n_rad: int) -> dict:
+    """Spherical Brio-Wu tube (Section VIII.c), pole on the z axis: shell
+    4 <= r <= 6, states (rho, p, v_r, v_theta, v_phi, B_theta, B_phi) =
+    (1, 1, 0, 0, 0, 0, 1) for r <= 4.5 and (0.125, 0.1, 0, 0, 0, 0, -1) outside,
+    B_r = 0.75 sin(theta) (4.5 / r)^2, gamma = 2, final time 0.1.  The paper
+    gives the fields in units with magnetic pressure B^2 / (8 pi); here they are
+    divided by sqrt(4 pi) for the step's B^2 / 2.  The toroidal field's taper
+    is half the zone width at r = 4.5 for n_rad geometric shells."""
+    return _tube(4.0, 6.0, n_rad, (1.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0), (0.125, 0.1, 0.0, 0.0, 0.0, 0.0, -1.0),
+                 0.75, 2.0, 0.1)
+
+
+def ryu_jones_problem(n_rad: int) -> dict:
+    """Spherical Ryu-Jones tube (Section VIII.c): shell 3 <= r <= 6, states
+    (1, 20, 10, 0, 0, 0, 5) for r <= 4.5 and (1, 1, -10, 0, 0, 0, 5) outside,
+    B_r = 5 sin(theta) (4.5 / r)^2, gamma = 5/3, final time 0.06; fields
+    divided by sqrt(4 pi) as for brio_wu_problem."""
+    b = 5.0 / SQRT4PI
+    return _tube(3.0, 6.0, n_rad, (1.0, 20.0, 10.0, 0.0, 0.0, 0.0, b), (1.0, 1.0, -10.0, 0.0, 0.0, 0.0, b),
+                 b, 5.0 / 3.0, 0.06)
+
+
 def white_noise(n: int, seed: int = SEED_NOISE, count: int = 2) -> np.ndarray:
     """Uniform(-1, 1) noise, shape (count, n)."""
     rng = np.random.default_rng(seed)

@@ -10,6 +10,16 @@
   Heun's method in time, zero-gradient ends).  With ``planar=True`` the
   r^2 weights and the source are dropped, which turns it into the planar
   scheme that the exact solution pins.
+* ``mhd_equator`` — the same kind of scheme for ideal MHD in the equatorial
+  plane of a spherical problem with no theta or phi dependence: variables
+  (rho, rho v_r, rho v_phi, E, B_phi) with the radial field B_r = C / r^2
+  fixed, each conserved in its own radial weight,
+      d(r^m q)/dt + d(r^m F)/dr = r^m S,  m = (2, 2, 3, 2, 1),
+  and the one source S_r = (2 p + B_r^2 + rho v_phi^2) / r of the radial
+  momentum (the B_phi pressure and hoop stress cancel); the B_r^2 part of the
+  source is integrated exactly over each cell, so a uniform state threaded by
+  B_r = C / r^2 stays at rest.  HLL with fast-magnetosonic Davis speeds.
+  With ``planar=True`` the weights and the source are dropped and B_r = C.
 
 Neither shares anything with the library or the oracle; they give the
 physical solution the 3-D step must approach on a spherically symmetric
@@ -139,6 +149,86 @@ def spherical_euler(r_in, r_out, n, r0, left, right, gam, t_end, cfl=0.4, planar
     while t < t_end:
         rho, u, p = prim(U)
         dt = cfl * dr / np.max(np.abs(u) + _sound(p, rho, gam))
+        dt = min(dt, t_end - t)
+        U1 = U + dt * rhs(U)
+        U = 0.5 * (U + U1 + dt * rhs(U1))
+        t += dt
+    return rc, np.array(prim(U))
+
+
+def _fast(rho, p, bn, bt, gam):
+    a2, n2, t2 = gam * p / rho, bn * bn / rho, bt * bt / rho
+    s = a2 + n2 + t2
+    return np.sqrt(0.5 * (s + np.sqrt(np.maximum(s * s - 4.0 * a2 * n2, 0.0))))
+
+
+def mhd_equator(r_in, r_out, n, rm, left, right, C, gam, t_end, cfl=0.4, planar=False, init=None):
+    """Cell-centred radii and (rho, v_r, v_phi, p, B_phi) at t_end.  left and
+    right are (rho, p, v_r, v_phi, B_phi) inside and outside r = rm; init, if
+    given, maps the cell centres to those five primitive arrays instead."""
+    edges = np.linspace(r_in, r_out, n + 1)
+    rc = 0.5 * (edges[:-1] + edges[1:])
+    dr = edges[1] - edges[0]
+    m = np.array([0, 0, 0, 0, 0]) if planar else np.array([2, 2, 3, 2, 1])
+    wf = edges[None, :] ** m[:, None]                                     # face weights r^m
+    vol = (edges[None, 1:] ** (m[:, None] + 1) - edges[None, :-1] ** (m[:, None] + 1)) / (m[:, None] + 1)
+    if planar:
+        Brf = np.full(n + 1, C)
+        Br2c = np.full(n, C * C)
+    else:
+        Brf = C / edges ** 2
+        Br2c = C * C * (1.0 / edges[:-1] - 1.0 / edges[1:]) / vol[0]      # cell average of B_r^2 (weight r^2)
+    if init is None:
+        inner = rc <= rm
+        w0 = [np.where(inner, a, b) for a, b in zip(left, right)]
+        rho, p, vr, vp, bp = w0
+    else:
+        rho, p, vr, vp, bp = init(rc)
+
+    def cons(rho, vr, vp, p, bp, br2):
+        return np.array([rho, rho * vr, rho * vp, p / (gam - 1) + 0.5 * rho * (vr * vr + vp * vp) + 0.5 * (br2 + bp * bp), bp])
+
+    def prim(U):
+        rho = U[0]
+        vr, vp = U[1] / rho, U[2] / rho
+        p = (gam - 1) * (U[3] - 0.5 * rho * (vr * vr + vp * vp) - 0.5 * (Br2c + U[4] ** 2))
+        return rho, vr, vp, p, U[4]
+
+    def flux(rho, vr, vp, p, bp, br):
+        ps = p + 0.5 * (br * br + bp * bp)
+        E = p / (gam - 1) + 0.5 * rho * (vr * vr + vp * vp) + 0.5 * (br * br + bp * bp)
+        return np.array([rho * vr, rho * vr * vr + ps - br * br, rho * vr * vp - br * bp,
+                         (E + ps) * vr - br * (vr * br + vp * bp), vr * bp - vp * br])
+
+    U = cons(rho, vr, vp, p, bp, Br2c)
+
+    def rhs(U):
+        q = np.array(prim(U))                                 # rho, vr, vp, p, bp
+        qg = np.concatenate([q[:, :1], q[:, :1], q, q[:, -1:], q[:, -1:]], axis=1)
+        d = _minmod(qg[:, 1:-1] - qg[:, :-2], qg[:, 2:] - qg[:, 1:-1])
+        qL = qg[:, 1:-2] + 0.5 * d[:, :-1]
+        qR = qg[:, 2:-1] - 0.5 * d[:, 1:]
+        FL, FR = flux(*qL, Brf), flux(*qR, Brf)
+        UL = cons(qL[0], qL[1], qL[2], qL[3], qL[4], Brf * Brf)
+        UR = cons(qR[0], qR[1], qR[2], qR[3], qR[4], Brf * Brf)
+        cL, cR = _fast(qL[0], qL[3], Brf, qL[4], gam), _fast(qR[0], qR[3], Brf, qR[4], gam)
+        sL = np.minimum(qL[1] - cL, qR[1] - cR)
+        sR = np.maximum(qL[1] + cL, qR[1] + cR)
+        Fh = np.where(sL >= 0, FL, np.where(sR <= 0, FR, (sR * FL - sL * FR + sL * sR * (UR - UL)) / (sR - sL)))
+        Fw = Fh * wf
+        out = -(Fw[:, 1:] - Fw[:, :-1]) / vol
+        if not planar:
+            rho, vr, vp, p, bp = q
+            src = (2.0 * p + rho * vp * vp) * 0.5 * (edges[1:] ** 2 - edges[:-1] ** 2)
+            src = src + 0.5 * C * C * (edges[:-1] ** -2.0 - edges[1:] ** -2.0)
+            out[1] += src / vol[1]
+        return out
+
+    t = 0.0
+    while t < t_end:
+        rho, vr, vp, p, bp = prim(U)
+        br = Brf[:-1] if planar else C / rc ** 2
+        dt = cfl * dr / np.max(np.abs(vr) + _fast(rho, p, br, bp, gam))
         dt = min(dt, t_end - t)
         U1 = U + dt * rhs(U)
         U = 0.5 * (U + U1 + dt * rhs(U1))
