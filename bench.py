@@ -31,7 +31,7 @@ def log(msg):
 
 
 STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}, double>",
-                "face_bnodal": "face_bnodal_runs<{p}, false, double>", "bmap": "bmap<{p}, double>",
+                "face_bnodal": "zone_face_bn<{p}, double>", "bmap": "bmap<{p}, double>",
                 "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double, false>",
                 "edge_emf": "edge_emf<double, false>", "update_ct": "zone_update"}
 

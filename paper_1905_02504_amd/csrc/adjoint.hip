@@ -716,9 +716,13 @@ __global__ void adj_face_bnodal(DevGeom G, const double *__restrict__ Uo, const 
                 for (int q = 0; q < T::Q; q++) Bq[c3][q] += ca * fevr[s][q * T::NC + a];
             }
         }
-        for (int q = 0; q < T::Q; q++)
-            d[s][q] = double(Bq[0][q]) * nrm[q * 3] + double(Bq[1][q]) * nrm[q * 3 + 1] +
-                      double(Bq[2][q]) * nrm[q * 3 + 2] - mean;
+        // the normal component adds the components' products in order, as the step does
+        for (int q = 0; q < T::Q; q++) {
+            double bn = double(Bq[0][q]) * nrm[q * 3];
+            bn += double(Bq[1][q]) * nrm[q * 3 + 1];
+            bn += double(Bq[2][q]) * nrm[q * 3 + 2];
+            d[s][q] = bn - mean;
+        }
     }
     for (int q = 0; q < T::Q; q++) {
         if (!have[0]) d[0][q] = d[1][q];

@@ -375,6 +375,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                  upload_f32(g, r.fintc, &d.fintcF) && upload_f32(g, r.eintc, &d.eintcF);
         if (!ok) { set_error("device allocation or upload of the geometry failed"); free_geom(g); return RG_ENOMEM; }
         ok = alloc_zero(g, (size_t)NVAR * NC * Z, &g->wcoef) && alloc_zero(g, (size_t)Q * NF, &g->bnod) &&
+             // the face traces; earlier in the step the same memory carries the
+             // two sides' normal B at the face points (2 Q NF doubles)
              alloc_zero(g, (size_t)16 * Q * 2 * NF, &g->ftr) && alloc_zero(g, (size_t)9 * 3 * 4 * NE, &g->etr) &&
              alloc_zero(g, (size_t)NVAR * NF, &g->Phi) && alloc_zero(g, (size_t)NE, &g->Gam) &&
              alloc_zero(g, (size_t)3 * Z, &g->zoneB) && alloc_zero(g, 65536, &g->red) &&

@@ -3,7 +3,9 @@
 //   bc_zones / bc_faces : continuative ghost fill (Section VII) into the output state
 //   weno_cols          : WENO-AO in the Taylor basis (Section III), one wavefront
 //                        per run of shells of one column
-//   face_bnodal_runs   : limited nodal normal B on every face, eqs. (4.11)-(4.12)
+//   zone_face_bn /     : limited nodal normal B on every face, eqs. (4.11)-(4.12):
+//   face_bn_limit        each zone's normal B at its faces' points, then per face
+//                        the MinMod and the mean restore
 //   bmap               : divergence-free B (Section IV.b) as one dense per-column
 //                        map on the FP64 matrix cores, evaluated at the ADER nodes
 //   predictor          : ADER-CG Picard iteration (Section V.d), one lane per
@@ -134,36 +136,114 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
 }
 
 // ---------------------------------------------------------------- face nodal B
-// radial faces kf in [g-1, g+Nr+1], angular faces in shells [g-1, g+Nr]
-// Limited nodal normal B on one face (Section IV.b): both sides' WENO B at
-// the face quadrature points, MinMod of their deviations from the face mean,
-// then the mean restored.  A missing side takes the other side's value.
-
-// component c3 of one side's WENO B at the face quadrature points
+// Limited nodal normal B on every face of the reconstructed shells (radial
+// faces kf in [g-1, g+Nr+1], angular faces in shells [g-1, g+Nr]), Section
+// IV.b: both sides' WENO B at the face quadrature points, the MinMod of their
+// normal components' deviations from the face mean, then the mean restored.
+// A missing side takes the other side's value.
+// Two passes that read every zone's WENO B once.  zone_face_bn: one wavefront per run of up to 64 zones of a column,
+// whose six faces' evaluation tables and normals it stages in LDS (read
+// there at addresses uniform across the wavefront); each lane evaluates its
+// zone's B at the quadrature points of its six faces and stores the normal
+// component in sbn[(side * Q + q) * NF + f].  face_bn_limit: one lane per
+// face, the MinMod of the two sides' deviations from the face mean and the
+// mean restore.  Each component sums its mean and then the coefficients in
+// order, and the normal component adds the three components' products in
+// order, as the adjoint's recomputation of this stage does.
 template <int P, class R>
-__device__ __forceinline__ void bnodal_side(const DevGeom &G, const double *__restrict__ U,
-                                            const R *__restrict__ wc, i64 z, const R *fev, int c3,
-                                            R (&Bq)[Tr<P>::Q])
+__global__ __launch_bounds__(64) void zone_face_bn(DevGeom G, const double *__restrict__ U,
+                                                   const R *__restrict__ wc, double *__restrict__ sbn, int nchunk)
 {
     using T = Tr<P>;
-    const R m0 = R(U[(5 + c3) * G.Z + z]);
+    constexpr int QN = T::Q * T::NC;
+    __shared__ R s_fev[6][QN];
+    __shared__ double s_nrm[6][T::Q * 3];
+    const int KR = G.Nr + 2;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = (int)(lb / (unsigned)nchunk), kk = (int)(lb % (unsigned)nchunk) * 64 + (int)threadIdx.x;
+    const R *fvR = pick<R>(G.fevR, G.fevRF), *fvA = pick<R>(G.fevA, G.fevAF);
+    for (int j = threadIdx.x; j < 6 * QN; j += 64) {
+        const int lf = j / QN, i = j % QN;
+        const R *fev = lf >= 4 ? fvR + ((i64)c * 2 + (lf == 4 ? 1 : 0)) * QN
+                               : fvA + ((i64)G.col_ae[4 * c + lf] * 2 + G.col_side[4 * c + lf]) * QN;
+        s_fev[lf][i] = fev[i];
+    }
+    for (int j = threadIdx.x; j < 6 * T::Q * 3; j += 64) {
+        const int lf = j / (T::Q * 3), i = j % (T::Q * 3);
+        const double *nrm = lf >= 4 ? G.fnR + (i64)c * T::Q * 3 : G.fnA + (i64)G.col_ae[4 * c + lf] * T::Q * 3;
+        s_nrm[lf][i] = nrm[i];
+    }
+    __syncthreads();
+    if (kk >= KR) return;
+    const int k = G.g - 1 + kk;
+    const i64 z = (i64)c * G.K + k;
+    R cf[3][T::NC + 1];
 #pragma unroll
-    for (int q = 0; q < T::Q; q++) Bq[q] = m0;
-    const R *cf = wc + (i64)(5 + c3) * T::NC * G.Z + z;
-    for (int a = 0; a < T::NC; a++) {
-        const R ca = cf[(i64)a * G.Z];
+    for (int c3 = 0; c3 < 3; c3++) {
+        cf[c3][0] = R(U[(5 + c3) * G.Z + z]);
 #pragma unroll
-        for (int q = 0; q < T::Q; q++) Bq[q] += ca * fev[q * T::NC + a];
+        for (int a = 0; a < T::NC; a++) cf[c3][a + 1] = wc[((i64)(5 + c3) * T::NC + a) * G.Z + z];
+    }
+#pragma unroll 1
+    for (int lf = 0; lf < 6; lf++) {
+        i64 f;
+        int side;
+        if (lf >= 4) {   // lower face: this zone is its side 1; upper face: side 0
+            side = lf == 4 ? 1 : 0;
+            f = (i64)c * (G.K + 1) + k + (lf - 4);
+        } else {
+            side = G.col_side[4 * c + lf];
+            f = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+        }
+        double *o = sbn + (i64)side * T::Q * G.NF + f;
+#pragma unroll 1
+        for (int q = 0; q < T::Q; q++) {
+            const R *fe = &s_fev[lf][q * T::NC];
+            R b0 = cf[0][0], b1 = cf[1][0], b2 = cf[2][0];
+#pragma unroll
+            for (int a = 0; a < T::NC; a++) {
+                const R w = fe[a];
+                b0 += cf[0][a + 1] * w;
+                b1 += cf[1][a + 1] * w;
+                b2 += cf[2][a + 1] * w;
+            }
+            const double *n = &s_nrm[lf][q * 3];
+            double bn = double(b0) * n[0];
+            bn += double(b1) * n[1];
+            bn += double(b2) * n[2];
+            o[(i64)q * G.NF] = bn;
+        }
     }
 }
 
-// MinMod of the two sides' normal components, mean restore, store
-template <int P, class R, class BQ>
-__device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__restrict__ Bf, R *__restrict__ bnod,
-                                              i64 f, const bool (&have)[2], const BQ &Bq, const double *nrm,
-                                              const double *fw)
+// Faces of the reconstructed shells: radial faces kf in [g-1, g+Nr+1] (their
+// outer sides beyond the reconstructed shells are missing), angular faces in
+// shells [g-1, g+Nr]; faces fastest along a column or an angular edge.
+template <int P, class R>
+__global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__restrict__ Bf,
+                                                     const double *__restrict__ sbn, R *__restrict__ bnod)
 {
     using T = Tr<P>;
+    const int nrad = G.Nr + 3, nang = G.Nr + 2;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const i64 nR = (i64)G.ncol * nrad;
+    if (t >= nR + (i64)G.nae * nang) return;
+    i64 f;
+    bool have[2];
+    const double *fw;
+    if (t < nR) {
+        const int c = (int)(t / nrad), kf = G.g - 1 + (int)(t % nrad);
+        f = (i64)c * (G.K + 1) + kf;
+        have[0] = kf - 1 >= G.g - 1;
+        have[1] = kf <= G.g + G.Nr;
+        fw = G.fwR + (i64)c * T::Q;
+    } else {
+        const i64 u = t - nR;
+        const int ae = (int)(u / nang), k = G.g - 1 + (int)(u % nang);
+        f = G.NRF + (i64)ae * G.K + k;
+        have[0] = have[1] = true;
+        fw = G.fwA + (i64)ae * T::Q;
+    }
     const double mean = Bf[f];
     double bn[T::Q];
 #pragma unroll
@@ -171,9 +251,7 @@ __device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__
         double d[2] = {0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < 2; s++)
-            if (have[s])
-                d[s] = double(Bq(s, 0, q)) * nrm[q * 3] + double(Bq(s, 1, q)) * nrm[q * 3 + 1] +
-                       double(Bq(s, 2, q)) * nrm[q * 3 + 2] - mean;
+            if (have[s]) d[s] = sbn[((i64)s * T::Q + q) * G.NF + f] - mean;
         if (!have[0]) d[0] = d[1];
         if (!have[1]) d[1] = d[0];
         bn[q] = mean + dev_minmod(d[0], d[1]);
@@ -183,84 +261,6 @@ __device__ __forceinline__ void bnodal_finish(const DevGeom &G, const double *__
     for (int q = 0; q < T::Q; q++) sum += fw[q] * bn[q];
 #pragma unroll
     for (int q = 0; q < T::Q; q++) bnod[(i64)q * G.NF + f] = R(bn[q] + (mean - sum));
-}
-
-// Geometry of a face: radial face kf of column owner, or the angular face of
-// angular edge owner in shell kf.
-template <int P, bool RADIAL, class R>
-struct FaceSides {
-    i64 f, z[2];
-    bool have[2];
-    const R *fev[2];
-    const double *nrm, *fw;
-    __device__ __forceinline__ FaceSides(const DevGeom &G, int owner, int kf)
-    {
-        using T = Tr<P>;
-        if (RADIAL) {
-            const R *fv = pick<R>(G.fevR, G.fevRF);
-            f = (i64)owner * (G.K + 1) + kf;
-            z[0] = (i64)owner * G.K + kf - 1;
-            z[1] = (i64)owner * G.K + kf;
-            have[0] = (kf - 1 >= G.g - 1) && (kf - 1 <= G.g + G.Nr);
-            have[1] = (kf >= G.g - 1) && (kf <= G.g + G.Nr);
-            fev[0] = fv + ((i64)owner * 2 + 0) * T::Q * T::NC;
-            fev[1] = fv + ((i64)owner * 2 + 1) * T::Q * T::NC;
-            nrm = G.fnR + (i64)owner * T::Q * 3;
-            fw = G.fwR + (i64)owner * T::Q;
-        } else {
-            const R *fv = pick<R>(G.fevA, G.fevAF);
-            f = G.NRF + (i64)owner * G.K + kf;
-            z[0] = (i64)G.ae_col[2 * owner] * G.K + kf;
-            z[1] = (i64)G.ae_col[2 * owner + 1] * G.K + kf;
-            have[0] = have[1] = true;
-            fev[0] = fv + ((i64)owner * 2 + 0) * T::Q * T::NC;
-            fev[1] = fv + ((i64)owner * 2 + 1) * T::Q * T::NC;
-            nrm = G.fnA + (i64)owner * T::Q * 3;
-            fw = G.fwA + (i64)owner * T::Q;
-        }
-    }
-};
-
-// One wavefront per run of up to 64 faces of one column (RADIAL) or of one
-// angular edge, so the face geometry is uniform across the wavefront.  A
-// short tail (nleft faces, at most 8) gets one more wavefront per owner whose
-// lanes take (face, side, component) triples and meet in LDS.
-template <int P, bool RADIAL, class R>
-__global__ __launch_bounds__(64) void face_bnodal_runs(DevGeom G, const double *__restrict__ U,
-                                                       const double *__restrict__ Bf, const R *__restrict__ wc,
-                                                       R *__restrict__ bnod, int nchunk, int nu, int nleft)
-{
-    using T = Tr<P>;
-    const int per = nchunk + (nleft > 0);
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const int owner = lb / per, ch = lb % per;
-    if (ch < nchunk) {
-        const int kk = ch * 64 + threadIdx.x;
-        if (kk >= nu) return;
-        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + kk);
-        R Bq[2][3][T::Q];
-#pragma unroll
-        for (int sd = 0; sd < 2; sd++)
-            if (fs.have[sd])
-#pragma unroll
-                for (int c3 = 0; c3 < 3; c3++) bnodal_side<P, R>(G, U, wc, fs.z[sd], fs.fev[sd], c3, Bq[sd][c3]);
-        bnodal_finish<P, R>(G, Bf, bnod, fs.f, fs.have, [&](int sd, int c3, int q) { return Bq[sd][c3][q]; },
-                            fs.nrm, fs.fw);
-        return;
-    }
-    __shared__ R s_bq[8][2][3][T::Q];
-    const int t = threadIdx.x, fi = t / 6, sd = (t % 6) / 3, c3 = t % 3;
-    if (fi < nleft) {
-        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + nu + fi);
-        const bool hv = sd ? fs.have[1] : fs.have[0];
-        if (hv) bnodal_side<P, R>(G, U, wc, sd ? fs.z[1] : fs.z[0], sd ? fs.fev[1] : fs.fev[0], c3, s_bq[fi][sd][c3]);
-    }
-    __syncthreads();
-    if (t < nleft) {
-        const FaceSides<P, RADIAL, R> fs(G, owner, G.g - 1 + nu + t);
-        bnodal_finish<P, R>(G, Bf, bnod, fs.f, fs.have, [&](int s2, int k3, int q) { return s_bq[t][s2][k3][q]; },
-                            fs.nrm, fs.fw);
-    }
 }
 
 // ---------------------------------------------------------------- predictor
@@ -1102,11 +1102,15 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
         R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft, g->whi);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
-    const RunSplit br = run_split(G.Nr + 3), ba = run_split(G.Nr + 2);
-    face_bnodal_runs<P, true, R><<<(unsigned)((i64)G.ncol * (br.nchunk + (br.nleft > 0))), 64, 0, st>>>(
-        G, Uo, Bo, wcoef, bnod, br.nchunk, br.nu, br.nleft);
-    face_bnodal_runs<P, false, R><<<(unsigned)((i64)G.nae * (ba.nchunk + (ba.nleft > 0))), 64, 0, st>>>(
-        G, Uo, Bo, wcoef, bnod, ba.nchunk, ba.nu, ba.nleft);
+    {
+        // the sides' normal B at the face points go through the face-trace
+        // buffer, which the predictor fills only later in the step
+        double *sbn = reinterpret_cast<double *>(ftr);
+        const int nch = (G.Nr + 2 + 63) / 64;
+        zone_face_bn<P, R><<<(unsigned)((i64)G.ncol * nch), 64, 0, st>>>(G, Uo, wcoef, sbn, nch);
+        face_bn_limit<P, R><<<nblocks((i64)G.ncol * (G.Nr + 3) + (i64)G.nae * (G.Nr + 2), 256), 256, 0, st>>>(
+            G, Bo, sbn, bnod);
+    }
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
