@@ -269,10 +269,16 @@ __global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__
 // new zone mean) is applied to the zone's inputs -- its WENO B, the limited
 // nodal normal B of its six faces and their face averages.  Per column this is
 // a dense product Out^T (NOUTB x zones) = Mb^T (NOUTB x NIN) In^T (NIN x zones),
-// done on the FP64 matrix cores: one wavefront owns 16 zones of a column and
-// all output rows, stepping through the inputs four at a time
+// done on the FP64 matrix cores: one wavefront owns bmap_tiles<R> tiles of
+// 16 zones of a column and all output rows, stepping through the inputs four
+// at a time; each A operand it loads serves all its tiles.  Three tiles
+// measured 6 % faster than one with FP64 inputs (two were slower: fewer
+// wavefronts in flight); with FP32 inputs the extra registers cost more
+// occupancy than the shared loads save, so that form keeps one
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
+template <class R>
+constexpr int bmap_tiles() { return sizeof(R) == sizeof(double) ? 3 : 1; }
 
 template <int P, class R>
 __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
@@ -280,38 +286,55 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
                                            R *__restrict__ bnode, double *__restrict__ zoneB)
 {
     using T = Tr<P>;
-    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16;
+    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16, NT = bmap_tiles<R>();
     constexpr int NA = 3 * (T::NC + 1), NQ = NA + 6 * T::Q;
     static_assert(NIN % 4 == 0, "input count must be a multiple of 4");
-    const int KR = G.Nr + 2, nt = (KR + 15) / 16;
+    const int KR = G.Nr + 2, nt = (KR + 16 * NT - 1) / (16 * NT);
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int c = lb / nt, tile = lb % nt;
     const int l = threadIdx.x, g = l >> 4, jz = l & 15;
-    const int kk = tile * 16 + jz;
-    const bool active = kk < KR;
-    const int k = G.g - 1 + (active ? kk : 0);
-    const i64 z = (i64)c * G.K + k;
-    const i64 fr = (i64)c * (G.K + 1) + k;
-    i64 fa[4];
+    int kk[NT];
+    bool active[NT];
+    i64 z[NT], fr[NT], fa[NT][4];
 #pragma unroll
-    for (int lf = 0; lf < 4; lf++) fa[lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    for (int t = 0; t < NT; t++) {
+        kk[t] = (tile * NT + t) * 16 + jz;
+        active[t] = kk[t] < KR;
+        const int k = G.g - 1 + (active[t] ? kk[t] : 0);
+        z[t] = (i64)c * G.K + k;
+        fr[t] = (i64)c * (G.K + 1) + k;
+#pragma unroll
+        for (int lf = 0; lf < 4; lf++) fa[t][lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+    }
     const double *Mb = G.Mb + (i64)c * NIN * NOUT;
-    dbl4 acc[MT];
+    dbl4 acc[NT][MT];
 #pragma unroll
-    for (int m = 0; m < MT; m++) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+        for (int m = 0; m < MT; m++) acc[t][m] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
     for (int s = 0; s < KT; s++) {
-        // B operand: input j = 4s + g of zone jz
+        // B operands: input j = 4s + g of zone jz of each tile
         const int j = 4 * s + g;
-        double b = 0.0;
-        if (active) {
-            if (j < NA) {
-                const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
-                b = a == 0 ? U[(i64)(5 + comp) * G.Z + z] : double(wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z]);
-            } else {
-                const int lf = j < NQ ? (j - NA) / T::Q : j - NQ;
-                const i64 idx = lf == 4 ? fr : lf == 5 ? fr + 1 : lf == 0 ? fa[0] : lf == 1 ? fa[1] : lf == 2 ? fa[2] : fa[3];
-                b = j < NQ ? double(bnod[(i64)((j - NA) % T::Q) * G.NF + idx]) : Bf[idx];
+        double b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            b[t] = 0.0;
+            if (active[t]) {
+                if (j < NA) {
+                    const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+                    b[t] = a == 0 ? U[(i64)(5 + comp) * G.Z + z[t]]
+                                  : double(wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z[t]]);
+                } else {
+                    const int lf = j < NQ ? (j - NA) / T::Q : j - NQ;
+                    const i64 idx = lf == 4   ? fr[t]
+                                    : lf == 5 ? fr[t] + 1
+                                    : lf == 0 ? fa[t][0]
+                                    : lf == 1 ? fa[t][1]
+                                    : lf == 2 ? fa[t][2]
+                                              : fa[t][3];
+                    b[t] = j < NQ ? double(bnod[(i64)((j - NA) % T::Q) * G.NF + idx]) : Bf[idx];
+                }
             }
         }
         const double *mrow = Mb + (i64)j * NOUT;
@@ -319,19 +342,23 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
         for (int m = 0; m < MT; m++) {
             const int r = m * 16 + jz;
             const double a = (m < MT - 1 || r < NOUT) ? mrow[r] : 0.0;
-            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t][m], 0, 0, 0);
         }
     }
-    if (!active) return;
-    const i64 zr = (i64)c * KR + kk;
 #pragma unroll
-    for (int m = 0; m < MT; m++)
+    for (int t = 0; t < NT; t++) {
+        if (!active[t]) continue;
+        const i64 zr = (i64)c * KR + kk[t];
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int r = m * 16 + g + 4 * v;
-            if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = R(acc[m][v]);
-            else if (r < NOUT) zoneB[(i64)(r - 3 * T::N) * G.Z + z] = acc[m][v];
-        }
+        for (int m = 0; m < MT; m++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = m * 16 + g + 4 * v;
+                if (r < 3 * T::N) bnode[zr * (3 * T::N) + r] = R(acc[t][m][v]);
+                else if (r < NOUT) zoneB[(i64)(r - 3 * T::N) * G.Z + z[t]] = acc[t][m][v];
+            }
+    }
 }
 
 // ADER-CG predictor (Section V.d).  One wavefront holds 64 / N zones, one lane
@@ -1114,7 +1141,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
-    const int ntile = (G.Nr + 2 + 15) / 16;
+    const int ntile = (G.Nr + 2 + 16 * bmap_tiles<R>() - 1) / (16 * bmap_tiles<R>());
     bmap<P, R><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, wcoef, bnod, bnode, g->zoneB);
     RG_LAUNCH_CHECK();
     sm.mark(4, st);
