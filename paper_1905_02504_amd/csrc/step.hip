@@ -141,15 +141,18 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
 // IV.b: both sides' WENO B at the face quadrature points, the MinMod of their
 // normal components' deviations from the face mean, then the mean restored.
 // A missing side takes the other side's value.
-// Two passes that read every zone's WENO B once.  zone_face_bn: one wavefront per run of up to 64 zones of a column,
-// whose six faces' evaluation tables and normals it stages in LDS (read
-// there at addresses uniform across the wavefront); each lane evaluates its
+// Two passes that read every zone's WENO B once.  zone_face_bn: one
+// wavefront per run of up to 64 zones of a column, which stages the column's
+// six faces' evaluation tables and normals in LDS; each lane evaluates its
 // zone's B at the quadrature points of its six faces and stores the normal
-// component in sbn[(side * Q + q) * NF + f].  face_bn_limit: one lane per
-// face, the MinMod of the two sides' deviations from the face mean and the
-// mean restore.  Each component sums its mean and then the coefficients in
-// order, and the normal component adds the three components' products in
-// order, as the adjoint's recomputation of this stage does.
+// component in sbn[(side * Q + q) * NF + f].  A short run (at most 10 zones,
+// such as the last one of a column) gives each lane one (zone, face) pair
+// instead, so that its wavefront is not as long as a full one.
+// face_bn_limit: one lane per face, the MinMod of the two sides' deviations
+// from the face mean and the mean restore.  Each component sums its mean and
+// then the coefficients in order, and the normal component adds the three
+// components' products in order, as the adjoint's recomputation of this
+// stage does.
 template <int P, class R>
 __global__ __launch_bounds__(64) void zone_face_bn(DevGeom G, const double *__restrict__ U,
                                                    const R *__restrict__ wc, double *__restrict__ sbn, int nchunk)
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(64) void zone_face_bn(DevGeom G, const double *__re
     __shared__ double s_nrm[6][T::Q * 3];
     const int KR = G.Nr + 2;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const int c = (int)(lb / (unsigned)nchunk), kk = (int)(lb % (unsigned)nchunk) * 64 + (int)threadIdx.x;
+    const int c = (int)(lb / (unsigned)nchunk), base = (int)(lb % (unsigned)nchunk) * 64;
     const R *fvR = pick<R>(G.fevR, G.fevRF), *fvA = pick<R>(G.fevA, G.fevAF);
     for (int j = threadIdx.x; j < 6 * QN; j += 64) {
         const int lf = j / QN, i = j % QN;
@@ -174,7 +177,19 @@ __global__ __launch_bounds__(64) void zone_face_bn(DevGeom G, const double *__re
         s_nrm[lf][i] = nrm[i];
     }
     __syncthreads();
-    if (kk >= KR) return;
+    const int nk = min(64, KR - base);
+    int kk, lf0, lf1;
+    if (nk <= 10) {   // short run: lane = (zone, face)
+        if ((int)threadIdx.x >= 6 * nk) return;
+        kk = base + (int)threadIdx.x / 6;
+        lf0 = (int)threadIdx.x % 6;
+        lf1 = lf0 + 1;
+    } else {
+        kk = base + (int)threadIdx.x;
+        if (kk >= KR) return;
+        lf0 = 0;
+        lf1 = 6;
+    }
     const int k = G.g - 1 + kk;
     const i64 z = (i64)c * G.K + k;
     R cf[3][T::NC + 1];
@@ -185,7 +200,7 @@ __global__ __launch_bounds__(64) void zone_face_bn(DevGeom G, const double *__re
         for (int a = 0; a < T::NC; a++) cf[c3][a + 1] = wc[((i64)(5 + c3) * T::NC + a) * G.Z + z];
     }
 #pragma unroll 1
-    for (int lf = 0; lf < 6; lf++) {
+    for (int lf = lf0; lf < lf1; lf++) {
         i64 f;
         int side;
         if (lf >= 4) {   // lower face: this zone is its side 1; upper face: side 0
