@@ -883,18 +883,23 @@ __global__ void adj_weno_gather(DevGeom G, const double *__restrict__ gdu, doubl
     const int c = (int)(z / G.K), k = (int)(z % G.K);
     const bool recon = k >= G.g - 1 && k <= G.g + G.Nr;
     const i64 zr = (i64)c * KR + (k - (G.g - 1));
+    // each entry read once for the eight variables; every variable still sums
+    // its entries in order
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = G.inv_ptr[c]; e < G.inv_ptr[c + 1]; e++) {
+        const int c2 = G.inv_ent[3 * e], j = G.inv_ent[3 * e + 1], dk = G.inv_ent[3 * e + 2];
+        const int k2 = k - dk;
+        if (k2 < G.g - 1 || k2 > G.g + G.Nr) continue;
+        const double *src = gdu + (i64)j * nzr + (i64)c2 * KR + (k2 - (G.g - 1));
+#pragma unroll
+        for (int v = 0; v < 8; v++) acc[v] += src[(i64)v * T::NS * nzr];
+    }
+#pragma unroll
     for (int v = 0; v < 8; v++) {
-        double acc = 0.0;
-        for (int e = G.inv_ptr[c]; e < G.inv_ptr[c + 1]; e++) {
-            const int c2 = G.inv_ent[3 * e], j = G.inv_ent[3 * e + 1], dk = G.inv_ent[3 * e + 2];
-            const int k2 = k - dk;
-            if (k2 < G.g - 1 || k2 > G.g + G.Nr) continue;
-            acc += gdu[((i64)v * T::NS + j) * nzr + (i64)c2 * KR + (k2 - (G.g - 1))];
-        }
         if (recon)
             for (int j = 0; j < T::NS; j++)
-                if (G.stm[(i64)c * T::NS + j] >= 0) acc -= gdu[((i64)v * T::NS + j) * nzr + zr];
-        gUo[(i64)v * G.Z + z] += acc;
+                if (G.stm[(i64)c * T::NS + j] >= 0) acc[v] -= gdu[((i64)v * T::NS + j) * nzr + zr];
+        gUo[(i64)v * G.Z + z] += acc[v];
     }
 }
 
