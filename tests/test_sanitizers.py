@@ -94,6 +94,10 @@ LIB_DRIVER = textwrap.dedent(r"""
         rg_geom_edge_data(g, em.data(), et.data());
         const double frame[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
         int rc = rg_init_alfven(g, frame, 1.0, 0.1, 1.0, 0.1, 1.0, 5.0 / 3.0, 0.0, nullptr, 0.0, U.data(), Bf.data());
+        const double tl[7] = {1.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0}, tr[7] = {0.125, 0.1, 0.0, 0.0, 0.0, 0.0, -1.0};
+        if (rc == RG_OK) rc = rg_init_tube(g, tl, tr, 0.75, 1.5, 1.5, 0.01, 2.0, U.data(), Bf.data());
+        const double tbad[7] = {1.0, 1.0, 0.0, 0.0, 0.0, 0.5, 1.0};
+        if (rc == RG_OK && rg_init_tube(g, tbad, tr, 0.75, 1.5, 1.5, 0.01, 2.0, U.data(), Bf.data()) != RG_EINVAL) rc = 4;
         // without device data the step entry points refuse
         rg_step_params p{5.0 / 3.0, 1e-3, 0.0, 0, 0, 0.0};
         if (rg_step(g, &p, U.data(), Bf.data(), U.data(), Bf.data(), nullptr) == RG_OK) rc = 3;
