@@ -32,6 +32,8 @@ ORACLE_DRIVER = textwrap.dedent(r"""
     void rgo_sizes(const rgo_mesh *, int64_t *);
     int rgo_step(const rgo_mesh *, double, double, int, int, double, const double *, const double *, double *,
                  double *, double *, double *, unsigned char *);
+    void rgo_init_tube(const rgo_mesh *, const double *, const double *, double, double, double, double, double,
+                       double *, double *);
     static int run(int order, int ghost) {
         rgo_mesh *m = rgo_create(2, 3, 1.0, 2.0, ghost, order - 1, order);
         if (!m) return 1;
@@ -51,6 +53,10 @@ ORACLE_DRIVER = textwrap.dedent(r"""
         int rc = rgo_step(m, 5.0 / 3.0, 5e-2, 0, 2, 1e-4, U, Bf, Uo, Bo, NULL, NULL, fz);
         free(fz);
         for (int64_t i = 0; i < 8 * nz; i++) if (Uo[i] != Uo[i]) rc = 2;
+        /* the spherical shock tube's initial state */
+        const double tl[7] = {1.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0}, tr[7] = {0.125, 0.1, 0.0, 0.0, 0.0, 0.0, -1.0};
+        rgo_init_tube(m, tl, tr, 0.75, 1.5, 1.5, 0.01, 2.0, U, Bf);
+        for (int64_t i = 0; i < 8 * nz; i++) if (U[i] != U[i]) rc = 3;
         free(U); free(Bf); free(Uo); free(Bo);
         rgo_destroy(m);
         return rc;
