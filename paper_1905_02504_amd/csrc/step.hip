@@ -644,11 +644,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 }
 
 // ---------------------------------------------------------------- face fluxes
-// HLL at every face quadrature point, one lane per point (each reads its
-// point's two adjacent side records), then the weighted sum over a face's
-// points in order.  256 / Q faces per block.
+// HLL at every face quadrature point, then the weighted sum over a face's
+// points in order.  A point's two side records are adjacent (2 x 16 values).
+// With FP64 records two lanes take a point: they load its records in
+// alternate 16-byte pieces, so that the lanes of a pair read neighbouring
+// bytes and each load instruction touches half as many cache lines, and a DPP
+// swap gives each lane the other's pieces; both evaluate the same HLL.  The
+// address unit was this kernel's limit with one lane per 256-byte point
+// (21.4 -> 17.3 ms, bit-identical).  FP32 records (128 bytes a point) keep one
+// lane per point, which measured faster for them.
 // MARKED: only faces with mark[f] set are solved and written (the re-solve of
 // the first-order fallback; *added counts the zones its round flagged).
+template <class R>
+constexpr int flux_lanes_per_point() { return sizeof(R) == sizeof(double) ? 2 : 1; }
+template <int P, class R>
+constexpr int flux_faces_per_block() { return 256 / (flux_lanes_per_point<R>() * Tr<P>::Q); }
+
 template <int P, class R, bool MARKED = false>
 __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R *__restrict__ ftr,
                                                  double *__restrict__ Phi, const unsigned char *__restrict__ mark = nullptr,
@@ -656,10 +667,10 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
 {
     using T = Tr<P>;
     if (MARKED && *added == 0) return;   // the round flagged no zone
-    constexpr int FPB = 256 / T::Q;
+    constexpr int LPP = flux_lanes_per_point<R>(), FPB = flux_faces_per_block<P, R>();
     __shared__ double s_q[FPB * T::Q][9];
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
-    const int tid = threadIdx.x, fl = tid / T::Q, q = tid % T::Q;
+    const int tid = threadIdx.x, pt = tid / LPP, half = tid % LPP, fl = pt / T::Q, q = pt % T::Q;
     const i64 t = (i64)blockIdx.x * FPB + fl;
     const double *nrm = nullptr, *fw = nullptr;
     i64 f = 0;
@@ -668,20 +679,56 @@ __global__ __launch_bounds__(256) void face_flux(DevGeom G, double gam, const R 
         f = flux_face<P>(G, t, nrm, fw);
         if (MARKED) live = mark[f] != 0;
     }
+    R vals[32];   // the point's side-0 record, then its side-1 record
+    if constexpr (LPP == 2) {
+        constexpr int NDW = 2 * 16 * (int)sizeof(R) / 4;   // dwords of the two records
+        constexpr int NPC = NDW / 4;                        // 16-byte pieces
+        uint32_t own[NPC / 2][4];   // this lane's pieces 2i + half
+#pragma unroll
+        for (int i = 0; i < NPC / 2; i++) own[i][0] = own[i][1] = own[i][2] = own[i][3] = 0u;
+        if (live) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(ftr + ftr_at<P>(f, q, 0));
+#pragma unroll
+            for (int i = 0; i < NPC / 2; i++) {
+                const uint4 w = src[2 * i + half];
+                own[i][0] = w.x;
+                own[i][1] = w.y;
+                own[i][2] = w.z;
+                own[i][3] = w.w;
+            }
+        }
+        uint32_t blk[NDW];
+#pragma unroll
+        for (int i = 0; i < NPC / 2; i++)
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                // lanes 2n and 2n + 1 swap (quad_perm 1, 0, 3, 2)
+                const uint32_t oth = (uint32_t)__builtin_amdgcn_mov_dpp((int)own[i][d], 0xB1, 0xF, 0xF, false);
+                blk[4 * (2 * i) + d] = half == 0 ? own[i][d] : oth;
+                blk[4 * (2 * i + 1) + d] = half == 0 ? oth : own[i][d];
+            }
+        __builtin_memcpy(vals, blk, sizeof(vals));
+    } else {
+        if (live) {
+            const R *a = ftr + ftr_at<P>(f, q, 0);
+#pragma unroll
+            for (int v = 0; v < 32; v++) vals[v] = a[v];
+        }
+    }
     if (live) {
-        const R *a = ftr + ftr_at<P>(f, q, 0), *b = a + 16;
         double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-            UL[v] = a[v];
-            FL[v] = a[8 + v];
-            UR[v] = b[v];
-            FR[v] = b[8 + v];
+            UL[v] = vals[v];
+            FL[v] = vals[8 + v];
+            UR[v] = vals[16 + v];
+            FR[v] = vals[24 + v];
         }
         dev_hll<double>(UL, UR, FL, FR, nrm + q * 3, gam, Fs);
         const double w = fw[q] * G.area[f];
+        if (half == 0)
 #pragma unroll
-        for (int v = 0; v < 8; v++) s_q[tid][v] = w * Fs[v];
+            for (int v = 0; v < 8; v++) s_q[pt][v] = w * Fs[v];
     }
     __syncthreads();
     // one thread per (face, variable), faces fastest
@@ -1165,7 +1212,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     if (front_only) return RG_OK;
     sm.mark(5, st);
     const i64 nff = (i64)G.ncol * (G.Nr + 1) + (i64)G.nae * G.Nr;
-    face_flux<P, R><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi);
+    face_flux<P, R><<<nblocks(nff, flux_faces_per_block<P, R>()), 256, 0, st>>>(G, gam, ftr, g->Phi);
     RG_LAUNCH_CHECK();
     sm.mark(6, st);
     const i64 nee = (i64)G.nv * G.Nr + (i64)G.nae * (G.Nr + 1);
@@ -1182,7 +1229,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
             fb_flag<<<nblocks(G.Z, 256), 256, 0, st>>>(G, dt, gam, round, g->Phi, g->zoneB, Uo, g->zfl, g->ffl,
                                                       g->efl, g->fbcnt);
             fb_traces<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, Uo, g->ffl, g->efl, ftr, etr, g->fbcnt + round);
-            face_flux<P, R, true><<<nblocks(nff, 256 / Tr<P>::Q), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl,
+            face_flux<P, R, true><<<nblocks(nff, flux_faces_per_block<P, R>()), 256, 0, st>>>(G, gam, ftr, g->Phi, g->ffl,
                                                                                  g->fbcnt + round);
             edge_emf<R, true><<<nblocks(nee, 64), 192, 0, st>>>(G, gam, etr, g->Gam, g->efl, g->fbcnt + round);
             RG_LAUNCH_CHECK();
