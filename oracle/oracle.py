@@ -4,6 +4,12 @@ The oracle is a plain FP64 CPU implementation of one ADER-WENO-AO
 divergence-free MHD step written from the paper (Sections II-VI).  Only the
 test-suite, the smoke check and the CPU-baseline leg of the benchmark may use
 it; the GPU library never imports or links it.
+
+Parity unpinned: the exact values of the WENO-AO nonlinear weights (their
+limits are pinned), the edge electric field in genuinely multidimensional
+data (its 1-D reduction is pinned) and the three-zone corner solver; every
+other part is pinned by the tests named in tests/test_oracle_pins.py,
+tests/test_oracle_fallback.py and tests/test_tube_init.py.
 """
 from __future__ import annotations
 

@@ -17,6 +17,12 @@
  *
  * Units are rationalised (magnetic pressure B^2/2), i.e. eq. (2.2) with 4 pi
  * absorbed into B.
+ *
+ * Parity unpinned (no value fixed by the paper or by mathematics checks
+ * them beyond the limits named): the exact values of the WENO-AO nonlinear
+ * weights (their limits, and their effect on the convergence order, are
+ * checked), the edge electric field in genuinely multidimensional data (its
+ * reduction to 1-D HLL is pinned), and the three-zone corner solver.
  */
 #include "oracle_internal.h"
 
