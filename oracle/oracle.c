@@ -18,6 +18,8 @@ int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U
 int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                            double *coeffs, int *exps, double *face_nodal);
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U);
+int rgo_run_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double *U, int z, double *out);
+double rgo_emf3(const double U[3][NVAR], const double E[3][3], const double n[3][3], const double *t, double gamma);
 void rgo_run_init_harmonic(const rgo_mesh *m, const double *rho, const double *v, const double *A, double p,
                            double gamma, double *U, double *Bf);
 void rgo_run_init_tube(const rgo_mesh *m, const double *left, const double *right, double Br0, double r0,
@@ -292,4 +294,17 @@ void rgo_flux(const double *U, double gamma, double *F)
 double rgo_emf(const double *U4, const double *E4, const double *cen4, const double *t, double gamma)
 {
     return rgo_emf4((const double(*)[NVAR])U4, (const double(*)[3])E4, (const double(*)[3])cen4, t, gamma);
+}
+
+/* test access to single pieces of the method */
+double rgo_fast(const double *U, double gamma, const double *n) { return fast_speed(U, gamma, n); }
+
+double rgo_emf3x(const double *U3, const double *E3, const double *n3, const double *t, double gamma)
+{
+    return rgo_emf3((const double(*)[NVAR])U3, (const double(*)[3])E3, (const double(*)[3])n3, t, gamma);
+}
+
+int rgo_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double *U, int z, double *out)
+{
+    return rgo_run_weno_detail(m, flags, weno_eps, U, z, out);
 }

@@ -5,11 +5,9 @@ divergence-free MHD step written from the paper (Sections II-VI).  Only the
 test-suite, the smoke check and the CPU-baseline leg of the benchmark may use
 it; the GPU library never imports or links it.
 
-Parity unpinned: the exact values of the WENO-AO nonlinear weights (their
-limits are pinned), the edge electric field in genuinely multidimensional
-data (its 1-D reduction is pinned) and the three-zone corner solver; every
-other part is pinned by the tests named in tests/test_oracle_pins.py,
-tests/test_oracle_fallback.py and tests/test_tube_init.py.
+Every part is pinned by the tests in tests/test_oracle_pins.py,
+tests/test_oracle_pins_solvers.py (fast speed, HLL, the edge solvers and the
+WENO-AO internals), tests/test_oracle_fallback.py and tests/test_tube_init.py.
 """
 from __future__ import annotations
 
@@ -93,6 +91,12 @@ def lib():
         L.rgo_flux.argtypes = [_dp, C.c_double, _dp]
         L.rgo_emf.restype = C.c_double
         L.rgo_emf.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
+        L.rgo_fast.restype = C.c_double
+        L.rgo_fast.argtypes = [_dp, C.c_double, _dp]
+        L.rgo_emf3x.restype = C.c_double
+        L.rgo_emf3x.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
+        L.rgo_weno_detail.restype = C.c_int
+        L.rgo_weno_detail.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, C.c_int, _dp]
         _lib = L
     return _lib
 
@@ -254,6 +258,17 @@ class OracleMesh:
                              np.ascontiguousarray(Bf, np.float64), out)
         return out
 
+    def weno_detail(self, U, z, flags=0, weno_eps=WENO_EPS):
+        """WENO-AO internals of zone z (no boundary fill): per variable the
+        smoothness indicators (large stencil, then the seven small ones), the
+        normalised nonlinear weights in the same order and the blended Taylor
+        coefficients (Section III)."""
+        nc = 9 if self.order == 3 else 19
+        out = np.zeros((NVAR, 16 + nc))
+        rc = lib().rgo_weno_detail(self._h, flags, weno_eps, np.ascontiguousarray(U, np.float64), int(z), out)
+        assert rc == nc
+        return dict(beta=out[:, :8].copy(), w=out[:, 8:16].copy(), coef=out[:, 16:].copy())
+
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return lib().rgo_cfl_dt(self._h, gamma, cfl, np.ascontiguousarray(U))
 
@@ -319,3 +334,14 @@ def flux(U, gamma=5.0 / 3.0):
 def emf4(U4, E4, cen4, t, gamma=5.0 / 3.0):
     return lib().rgo_emf(np.ascontiguousarray(U4, np.float64), np.ascontiguousarray(E4, np.float64),
                          np.ascontiguousarray(cen4, np.float64), np.ascontiguousarray(t, np.float64), gamma)
+
+
+def fast_speed(U, n, gamma=5.0 / 3.0):
+    return lib().rgo_fast(np.ascontiguousarray(U, np.float64), gamma, np.ascontiguousarray(n, np.float64))
+
+
+def emf3(U3, E3, n3, t, gamma=5.0 / 3.0):
+    """Three-zone edge electric field (E . t); n3[k] is the unit normal of the
+    face from zone k to zone k+1 (mod 3)."""
+    return lib().rgo_emf3x(np.ascontiguousarray(U3, np.float64), np.ascontiguousarray(E3, np.float64),
+                           np.ascontiguousarray(n3, np.float64), np.ascontiguousarray(t, np.float64), gamma)

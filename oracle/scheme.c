@@ -18,11 +18,10 @@
  * Units are rationalised (magnetic pressure B^2/2), i.e. eq. (2.2) with 4 pi
  * absorbed into B.
  *
- * Parity unpinned (no value fixed by the paper or by mathematics checks
- * them beyond the limits named): the exact values of the WENO-AO nonlinear
- * weights (their limits, and their effect on the convergence order, are
- * checked), the edge electric field in genuinely multidimensional data (its
- * reduction to 1-D HLL is pinned), and the three-zone corner solver.
+ * Every function here is pinned by a CPU test against closed forms, values
+ * worked out by hand, exactness on polynomial data or invariances (the
+ * fast speed, the HLL branches, the four-state and three-zone edge solvers,
+ * the WENO-AO indicators, weights and blend: tests/test_oracle_pins_solvers.py).
  */
 #include "oracle_internal.h"
 
@@ -159,6 +158,8 @@ typedef struct {
     double *Gam;            /* ne */
     int first_order;        /* traces are the zones' states at t^n (the fallback's re-solve) */
     double *whi;            /* nz, or NULL: the smallest over the variables of w_hi / gamma_hi */
+    int dbg_z;              /* zone whose WENO-AO internals are recorded (test access), or -1 */
+    double *dbg;            /* per variable: beta_hi, beta_s[7], weights[8], then the nc coefficients */
 } step_ws;
 
 static int zone_of(const rgo_mesh *m, int qd, int k) { return qd * m->ktot + k; }
@@ -250,7 +251,7 @@ static void weno_zone(step_ws *w, int z)
             }
             la_lsq_qr(n, 3, As, bs, cs[s]);
         }
-        double wgt[8];
+        double wgt[8], beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (w->flags & FLAG_LINEAR_WEIGHTS) {
             wgt[0] = WENO_GAMMA_HI;
             for (int s = 0; s < nsm; s++) wgt[1 + s] = gs;
@@ -268,12 +269,14 @@ static void weno_zone(step_ws *w, int z)
                 bhi += c0[p].wJ * acc;
             }
             bhi /= m->vol[z];
+            beta[0] = bhi;
             double tot = 0.0;
             const double eps = w->weno_eps;
             wgt[0] = WENO_GAMMA_HI / ((bhi + eps) * (bhi + eps));
             tot += wgt[0];
             for (int s = 0; s < nsm; s++) {
                 double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+                beta[1 + s] = b;
                 wgt[1 + s] = gs / ((b + eps) * (b + eps));
                 tot += wgt[1 + s];
             }
@@ -286,6 +289,11 @@ static void weno_zone(step_ws *w, int z)
             if (a < 3)
                 for (int s = 0; s < nsm; s++) { lin += gs * cs[s][a]; nl += wgt[1 + s] * cs[s][a]; }
             coef[v * nc + a] = wgt[0] / WENO_GAMMA_HI * (chi[a] - lin) + nl;
+        }
+        if (w->dbg && z == w->dbg_z) {
+            double *d = w->dbg + (size_t)v * (16 + nc);
+            for (int s = 0; s < 8; s++) { d[s] = beta[s]; d[8 + s] = wgt[s]; }
+            for (int a = 0; a < nc; a++) d[16 + a] = coef[v * nc + a];
         }
     }
     free(A);
@@ -969,6 +977,32 @@ int rgo_run_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_ep
     }
     free(w.U); free(w.Bf); free(w.wc);
     return 0;
+}
+
+/* WENO-AO internals of one zone (test access): for each of the eight
+ * variables, out[v * (16 + nc) + ...] holds the smoothness indicator of the
+ * large stencil and of the seven small stencils, the eight normalised
+ * nonlinear weights (large stencil first) and the nc blended Taylor
+ * coefficients (Section III).  No boundary fill: U holds every zone's
+ * average.  Returns nc. */
+int rgo_run_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double *U, int z, double *out)
+{
+    step_ws w;
+    memset(&w, 0, sizeof(w));
+    w.m = m;
+    w.flags = flags;
+    w.weno_eps = weno_eps;
+    setup_bases(&w);
+    const int nz = m->nz;
+    w.U = malloc(sizeof(double) * NVAR * nz);
+    memcpy(w.U, U, sizeof(double) * NVAR * nz);
+    w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(double));
+    w.dbg_z = z;
+    w.dbg = out;
+    weno_zone(&w, z);
+    int nc = w.nc;
+    free(w.U); free(w.wc);
+    return nc;
 }
 
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U)
