@@ -66,6 +66,29 @@ def measured_traffic(kernel):
     return None
 
 
+def host_cpu_model():
+    """The host CPU's model name and logical CPU count (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model, cpus = None, os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"model": model, "logical_cpus": cpus}
+
+
 def cpu_baseline(order, sample_n=16, sample_nr=16):
     """The oracle, as it stands, on a bounded sample of the same workload, on
     all the OpenMP threads it gets, and on one thread for a smaller sample."""
@@ -95,6 +118,7 @@ def cpu_baseline(order, sample_n=16, sample_nr=16):
     finally:
         gomp.omp_set_num_threads(threads)
     return {"value": zones / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "host_cpu": host_cpu_model(),
             "sample": f"one order-{order} step on 6x{sample_n}x{sample_n}x{sample_nr} zones "
                       f"(Alfven wave + noise), {el:.2f} s, geometry excluded",
             "single_thread": {"value": zones1 / el1, "sample": f"one order-{order} step on 6x4x4x8 zones, "

@@ -116,6 +116,20 @@ rg_status rg_geom_zone_data(const rg_geom *geom, double *centroid, double *volum
 rg_status rg_geom_face_data(const rg_geom *geom, double *center, double *normal, double *area);
 rg_status rg_geom_edge_data(const rg_geom *geom, double *midpoint, double *tangent);
 
+/* Conditioning of the per-column systems built by the precompute (Section
+ * III's least squares on eq. (3.4) rows, Section IV.b's KKT system), host
+ * copies of [n_columns] each; either pointer may be NULL.  cond_lsq: the
+ * 2-norm condition number sigma_max / sigma_min of the large-stencil
+ * least-squares matrix (rows: zone averages of the Taylor basis over the
+ * stencil members, scaled coordinates).  cond_kkt: the 1-norm condition
+ * number of the divergence-free KKT matrix (||K^-1||_1 by Hager's estimate).
+ * Rounding in the geometry is amplified by up to these factors in the
+ * reconstruction; thin zones (radial depth far below the angular width) and
+ * cube-corner stencils raise them.  The precompute returns RG_ESINGULAR when
+ * any column exceeds RG_COND_MAX. */
+#define RG_COND_MAX 1e13
+rg_status rg_geom_conditioning(const rg_geom *geom, double *cond_lsq, double *cond_kkt);
+
 typedef struct {
     double gamma;     /* ratio of specific heats                                   */
     double dt;        /* timestep; if <= 0 it is computed from cfl (host sync) and
@@ -143,13 +157,18 @@ typedef struct {
  * reconstruction's mean, so that its update is the first-order
  * finite-volume scheme on its own averages.  A re-solved face
  * can drive a neighbour negative, so the check is repeated with the new
- * fluxes and the newly flagged zones are re-solved too, for up to 4 rounds
- * (stopping when a round flags no new zone); the update and the constrained
- * transport then take the final values.  Conservation and the
- * discrete div B of the face field are kept; a flagged zone can still come
- * out non-positive (rg_diag reports the minima).  With no zone flagged the
- * result equals the plain step bit for bit; the extra passes cost a few
- * per cent of the step.  rg_step_adjoint refuses it (RG_ENOTSUP). */
+ * fluxes and the newly flagged zones are re-solved too, for up to
+ * RG_FALLBACK_ROUNDS rounds (stopping when a round flags no new zone); the
+ * update and the constrained transport then take the final values.
+ * Conservation and the discrete div B of the face field are kept; a flagged
+ * zone can still come out non-positive (rg_diag reports the minima).  The
+ * unflagged neighbours of zones flagged in the last round are not checked
+ * again: when rg_step_fallback_counts reports a non-zero count for the last
+ * round the rounds ran out, and such a neighbour can come out non-positive
+ * without a flag.  With no zone flagged the result equals the plain step bit
+ * for bit; the extra passes cost a few per cent of the step.
+ * rg_step_adjoint refuses it (RG_ENOTSUP). */
+#define RG_FALLBACK_ROUNDS 4
 
 /* One complete timestep (Section VI) on device buffers.
  * U, Bf: state at t (device, read only).  U_out, Bf_out: state at t + dt
@@ -206,6 +225,13 @@ rg_status rg_step_fluxes(const rg_geom *geom, double *Phi, double *Gam, void *st
  * 1 for every zone the first-order fallback took, 0 elsewhere (all 0 after a
  * step with the fallback off).  Asynchronous on `stream`. */
 rg_status rg_step_fallback_zones(const rg_geom *geom, uint8_t *flags, void *stream);
+
+/* Host copy of the last rg_step's fallback round counters,
+ * counts[RG_FALLBACK_ROUNDS]: the number of zones each round newly flagged
+ * (all 0 when the last step ran without the fallback).  A non-zero last
+ * entry means the rounds ran out (see the fallback above).  Synchronises
+ * `stream`. */
+rg_status rg_step_fallback_counts(const rg_geom *geom, int32_t *counts, void *stream);
 
 /* Device copy of the last rg_step's WENO-AO order indicator, whi[n_zones]
  * (float): for every zone of the reconstructed shells, the smallest over the

@@ -18,6 +18,7 @@ int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U
 int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                            double *coeffs, int *exps, double *face_nodal);
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U);
+int rgo_run_weno_rows(const rgo_mesh *m, int z, double *A);
 int rgo_run_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double *U, int z, double *out);
 double rgo_emf3(const double U[3][NVAR], const double E[3][3], const double n[3][3], const double *t, double gamma);
 void rgo_run_init_harmonic(const rgo_mesh *m, const double *rho, const double *v, const double *A, double p,
@@ -308,3 +309,5 @@ int rgo_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double 
 {
     return rgo_run_weno_detail(m, flags, weno_eps, U, z, out);
 }
+
+int rgo_weno_rows(const rgo_mesh *m, int z, double *A) { return rgo_run_weno_rows(m, z, A); }

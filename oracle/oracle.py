@@ -95,6 +95,8 @@ def lib():
         L.rgo_fast.argtypes = [_dp, C.c_double, _dp]
         L.rgo_emf3x.restype = C.c_double
         L.rgo_emf3x.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
+        L.rgo_weno_rows.restype = C.c_int
+        L.rgo_weno_rows.argtypes = [C.c_void_p, C.c_int, _dp]
         L.rgo_weno_detail.restype = C.c_int
         L.rgo_weno_detail.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, C.c_int, _dp]
         _lib = L
@@ -216,7 +218,9 @@ class OracleMesh:
     # the method -----------------------------------------------------------
     def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS, fallback=False):
         """One step.  With fallback=True the first-order fallback is on and the
-        per-zone flags (uint8, 1 = the zone fell back) are returned last."""
+        per-zone flags (uint8, 1 = the zone fell back) are returned last; the
+        round that flagged each zone (1-based, 0 = not flagged) is kept in
+        self.last_fallback_round."""
         U = np.ascontiguousarray(U, np.float64); Bf = np.ascontiguousarray(Bf, np.float64)
         Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
         phi = np.zeros((self.nf, NVAR)) if debug else None
@@ -230,6 +234,8 @@ class OracleMesh:
         if rc != 0:
             raise RuntimeError("oracle step failed")
         out = (Uo, Bo, phi, gam) if debug else (Uo, Bo)
+        self.last_fallback_round = fz.copy()
+        fz = (fz > 0).astype(np.uint8)
         return out + (fz,) if fallback else out
 
     def recon(self, U, Bf, z, pts, flags=0, weno_eps=WENO_EPS):
@@ -257,6 +263,13 @@ class OracleMesh:
         lib().rgo_weno_order(self._h, bc, flags, weno_eps, np.ascontiguousarray(U, np.float64),
                              np.ascontiguousarray(Bf, np.float64), out)
         return out
+
+    def weno_rows(self, z):
+        """Large-stencil least-squares matrix of zone z (members x Taylor coefficients)."""
+        nc = 9 if self.order == 3 else 19
+        A = np.zeros((40, nc))
+        ns = lib().rgo_weno_rows(self._h, int(z), A)
+        return A[:ns].copy()
 
     def weno_detail(self, U, z, flags=0, weno_eps=WENO_EPS):
         """WENO-AO internals of zone z (no boundary fill): per variable the

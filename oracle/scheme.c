@@ -201,14 +201,13 @@ static double minmod(double a, double b)
     return (a > 0 ? 1.0 : -1.0) * fmin(fabs(a), fabs(b));
 }
 
-static void weno_zone(step_ws *w, int z)
+/* large-stencil rows of zone z: volume average over each member zone j of
+ * zone z's Taylor basis (eq. 3.4); A is ns x nc, row-major */
+static void weno_rows(const step_ws *w, int z, double *A)
 {
     const rgo_mesh *m = w->m;
-    const int nc = w->nc, nz = m->nz;
-    const int ns = m->st_n[z];
+    const int nc = w->nc, ns = m->st_n[z];
     const int *st = &m->st_z[RGO_MAXST * z];
-    /* large-stencil rows: volume average over zone j of zone 0's Taylor basis (eq. 3.4) */
-    double *A = malloc(sizeof(double) * ns * nc);
     for (int j = 0; j < ns; j++) {
         int zj = st[j];
         const cub_pt *cp = &m->cub[(size_t)zj * m->ncub];
@@ -220,6 +219,16 @@ static void weno_zone(step_ws *w, int z)
         }
         for (int a = 0; a < nc; a++) A[j * nc + a] = A[j * nc + a] / m->vol[zj] - mom_of(m, z, w->te[a]);
     }
+}
+
+static void weno_zone(step_ws *w, int z)
+{
+    const rgo_mesh *m = w->m;
+    const int nc = w->nc, nz = m->nz;
+    const int ns = m->st_n[z];
+    const int *st = &m->st_z[RGO_MAXST * z];
+    double *A = malloc(sizeof(double) * ns * nc);
+    weno_rows(w, z, A);
     /* small stencils: central (all face neighbours) and one-sided (drop the
      * neighbour opposite direction d) with linear polynomials */
     int fnb[6];
@@ -818,7 +827,7 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
                 double u[NVAR];
                 update_zone(&w, z, 0, u);
                 if (u[IRHO] > 0.0 && pressure(u, gamma) > 0.0) continue;
-                bad[z] = 1;
+                bad[z] = (char)(round + 1);   /* the round that flagged it, 1-based */
                 added = 1;
                 for (int lf = 0; lf < 6; lf++) {
                     int f = m->zone_face[6 * z + lf];
@@ -1003,6 +1012,18 @@ int rgo_run_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const dou
     int nc = w.nc;
     free(w.U); free(w.wc);
     return nc;
+}
+
+/* the large-stencil least-squares matrix of zone z (test access): A[ns][nc]
+ * row-major in the stencil's member order; returns ns */
+int rgo_run_weno_rows(const rgo_mesh *m, int z, double *A)
+{
+    step_ws w;
+    memset(&w, 0, sizeof(w));
+    w.m = m;
+    setup_bases(&w);
+    weno_rows(&w, z, A);
+    return m->st_n[z];
 }
 
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U)

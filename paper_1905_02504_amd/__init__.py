@@ -86,6 +86,14 @@ class ShellMHD:
         N.rg_geom_edge_data(self._geom, _ptr(mid), _ptr(tan))
         return mid, tan
 
+    def conditioning(self):
+        """rg_geom_conditioning: per-column condition numbers of the large-stencil
+        least squares (2-norm) and of the divergence-free KKT matrix (1-norm)."""
+        ncol = self.info["n_columns"]
+        lsq = np.zeros(ncol); kkt = np.zeros(ncol)
+        N.rg_geom_conditioning(self._geom, _ptr(lsq), _ptr(kkt))
+        return lsq, kkt
+
     def shells(self):
         return np.tile(np.arange(self.K), self.nz // self.K)
 
@@ -202,6 +210,10 @@ class ShellMHD:
 
     def cfl_dt(self, U, cfl, gamma=5.0 / 3.0):
         return N.rg_cfl_dt(self._geom, U.data_ptr(), gamma, cfl, _stream())
+
+    def fallback_counts(self):
+        """rg_step_fallback_counts: zones newly flagged in each round of the last step's fallback."""
+        return N.rg_step_fallback_counts(self._geom, _stream())
 
     # per-stage timing ----------------------------------------------------------
     def diag(self, U, Bf, gamma=5.0 / 3.0):

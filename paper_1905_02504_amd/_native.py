@@ -77,6 +77,8 @@ def lib():
         L.rg_status_str.argtypes = [C.c_int]
         L.rg_status_str.restype = C.c_char_p
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
+        L.rg_geom_conditioning.argtypes = [_vp, _vp, _vp]
+        L.rg_step_fallback_counts.argtypes = [_vp, _vp, _vp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
         L.rg_init_tube.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -89,7 +91,8 @@ def lib():
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
                      "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
-                     "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag"):
+                     "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag",
+                     "rg_geom_conditioning", "rg_step_fallback_counts"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -189,6 +192,19 @@ def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
     out = C.c_double(0.0)
     check(lib().rg_cfl_dt(geom, _vp(U_ptr), gamma, cfl, _vp(stream), C.byref(out)), "rg_cfl_dt")
     return out.value
+
+
+def rg_geom_conditioning(geom, lsq_ptr, kkt_ptr):
+    check(lib().rg_geom_conditioning(geom, _vp(lsq_ptr), _vp(kkt_ptr)), "rg_geom_conditioning")
+
+
+RG_FALLBACK_ROUNDS = 4
+
+
+def rg_step_fallback_counts(geom, stream):
+    out = (C.c_int32 * RG_FALLBACK_ROUNDS)()
+    check(lib().rg_step_fallback_counts(geom, out, _vp(stream)), "rg_step_fallback_counts")
+    return list(out)
 
 
 def rg_init_tube(geom, left_ptr, right_ptr, Br0, r0, rm, delta, gamma, U_ptr, Bf_ptr):

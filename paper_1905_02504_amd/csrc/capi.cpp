@@ -185,6 +185,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         hg.fnR.assign((size_t)ncol * Q * 3, 0.0);
         hg.fwR.assign((size_t)ncol * Q, 0.0);
         hg.dins.assign(ncol, 0.0);
+        hg.cond_lsq.assign(ncol, 0.0);
+        hg.cond_kkt.assign(ncol, 0.0);
         hg.col_ae.assign((size_t)ncol * 4, 0);
         hg.col_side.assign((size_t)ncol * 4, 0);
         hg.col_perm.assign((size_t)ncol * 4 * Q, 0);
@@ -212,6 +214,16 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         for (int c = 0; c < ncol; c++)
             if (!column_pass2(m, r, cols, c, hg)) bad++;
         if (bad) { free_geom(g); return RG_ESINGULAR; }
+        for (int c = 0; c < ncol; c++)
+            if (!(hg.cond_lsq[c] <= RG_COND_MAX) || !(hg.cond_kkt[c] <= RG_COND_MAX)) {
+                set_error("column " + std::to_string(c) + ": least-squares condition " +
+                          std::to_string(hg.cond_lsq[c]) + ", KKT condition " + std::to_string(hg.cond_kkt[c]) +
+                          " above the limit " + std::to_string(RG_COND_MAX));
+                free_geom(g);
+                return RG_ESINGULAR;
+            }
+        g->cond_lsq = hg.cond_lsq;
+        g->cond_kkt = hg.cond_kkt;
 #pragma omp parallel for schedule(dynamic, 64)
         for (int ae = 0; ae < nae; ae++) angular_edge_pass(m, r, cols, ae, hg);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -437,6 +449,14 @@ extern "C" rg_status rg_geom_face_data(const rg_geom *g, double *center, double 
     return RG_OK;
 }
 
+extern "C" rg_status rg_geom_conditioning(const rg_geom *g, double *cond_lsq, double *cond_kkt)
+{
+    if (!g) { set_error("null geometry"); return RG_EINVAL; }
+    if (cond_lsq) std::memcpy(cond_lsq, g->cond_lsq.data(), g->cond_lsq.size() * sizeof(double));
+    if (cond_kkt) std::memcpy(cond_kkt, g->cond_kkt.data(), g->cond_kkt.size() * sizeof(double));
+    return RG_OK;
+}
+
 extern "C" rg_status rg_geom_edge_data(const rg_geom *g, double *midpoint, double *tangent)
 {
     if (!g) { set_error("null geometry"); return RG_EINVAL; }
@@ -579,6 +599,23 @@ extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, 
 {
     if (!g || !g->d.vol || !U || !dt || !(cfl > 0) || !(gamma > 1)) { set_error("invalid argument"); return RG_EINVAL; }
     return launch_cfl(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
+}
+
+extern "C" rg_status rg_step_fallback_counts(const rg_geom *g, int32_t *counts, void *stream)
+{
+    if (!g || !g->d.vol || !counts) { set_error("invalid argument"); return RG_EINVAL; }
+    if (!g->fb_last) {
+        for (int r = 0; r < RG_FALLBACK_ROUNDS; r++) counts[r] = 0;
+        return RG_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(counts, g->fbcnt, sizeof(int32_t) * RG_FALLBACK_ROUNDS, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("copy of the fallback counters failed");
+        return RG_EDEVICE;
+    }
+    return RG_OK;
 }
 
 extern "C" rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters, void *stream)

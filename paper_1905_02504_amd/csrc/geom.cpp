@@ -337,6 +337,85 @@ static bool pinv(int n, int m, const std::vector<double> &A, std::vector<double>
     return true;
 }
 
+// 2-norm condition number sigma_max / sigma_min of an n x m matrix (n >= m,
+// row-major) by one-sided Jacobi rotations of its columns (Hestenes): the
+// columns converge to mutually orthogonal vectors whose norms are the
+// singular values, accurately also for the smallest ones.
+static double cond2(int n, int m, const std::vector<double> &A)
+{
+    std::vector<double> W(A);
+    for (int sweep = 0; sweep < 40; sweep++) {
+        double off = 0.0;
+        for (int j = 0; j < m - 1; j++)
+            for (int k = j + 1; k < m; k++) {
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = 0; i < n; i++) {
+                    const double x = W[(size_t)i * m + j], y = W[(size_t)i * m + k];
+                    a += x * x;
+                    b += y * y;
+                    g += x * y;
+                }
+                if (g == 0.0 || std::abs(g) <= 1e-15 * std::sqrt(a * b)) continue;
+                off = std::max(off, std::abs(g) / std::sqrt(a * b));
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < n; i++) {
+                    const double x = W[(size_t)i * m + j], y = W[(size_t)i * m + k];
+                    W[(size_t)i * m + j] = cs * x - sn * y;
+                    W[(size_t)i * m + k] = sn * x + cs * y;
+                }
+            }
+        if (off < 1e-15) break;
+    }
+    double smax = 0.0, smin = 1e300;
+    for (int j = 0; j < m; j++) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s += W[(size_t)i * m + j] * W[(size_t)i * m + j];
+        s = std::sqrt(s);
+        smax = std::max(smax, s);
+        smin = std::min(smin, s);
+    }
+    return smin > 0.0 ? smax / smin : INFINITY;
+}
+
+// 1-norm condition number ||K||_1 ||K^-1||_1 of a symmetric matrix from its
+// LU factors, with ||K^-1||_1 estimated by Hager's method (a few solves with
+// K and, K being symmetric, with K^T = K; the estimate is a lower bound that
+// is exact in most cases).
+static double cond1_symmetric(int n, const std::vector<double> &K, const std::vector<double> &LU,
+                              const std::vector<int> &piv)
+{
+    double knorm = 0.0;
+    for (int j = 0; j < n; j++) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s += std::abs(K[(size_t)i * n + j]);
+        knorm = std::max(knorm, s);
+    }
+    std::vector<double> x(n, 1.0 / n), y(n), z(n);
+    double est = 0.0;
+    for (int it = 0; it < 5; it++) {
+        y = x;
+        lu_solve(n, LU, piv, y.data());
+        double ny = 0.0;
+        for (double v : y) ny += std::abs(v);
+        if (it > 0 && ny <= est) break;
+        est = ny;
+        for (int i = 0; i < n; i++) z[i] = y[i] >= 0 ? 1.0 : -1.0;
+        lu_solve(n, LU, piv, z.data());
+        int jmax = 0;
+        double zx = 0.0;
+        for (int i = 0; i < n; i++) {
+            zx += z[i] * x[i];
+            if (std::abs(z[i]) > std::abs(z[jmax])) jmax = i;
+        }
+        if (std::abs(z[jmax]) <= zx) break;
+        std::fill(x.begin(), x.end(), 0.0);
+        x[jmax] = 1.0;
+    }
+    return knorm * est;
+}
+
 // ---------------------------------------------------------------- pass 2
 bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &cols, int c, HostGeom &hg)
 {
@@ -411,6 +490,7 @@ bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &col
     }
     std::vector<double> P;
     if (!pinv(ns, NC, A, P)) { set_error("singular large-stencil least squares"); return false; }
+    hg.cond_lsq[c] = cond2(ns, NC, A);
     double *Pl = &hg.Pl[(size_t)c * NC * NS];
     for (int a = 0; a < NC; a++)
         for (int j = 0; j < NS; j++) Pl[a * NS + j] = (j < ns) ? P[(size_t)a * ns + j] : 0.0;
@@ -569,7 +649,9 @@ bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &col
     for (int i = 0; i < ncon; i++)
         for (int j = 0; j < NIN; j++) rhs[(size_t)(nu + i) * NIN + j] = Sd[(size_t)i * NIN + j];
     std::vector<int> piv;
+    const std::vector<double> Kfull(K);
     if (!lu_factor(nk, K, piv)) { set_error("singular divergence-free KKT system"); return false; }
+    hg.cond_kkt[c] = cond1_symmetric(nk, Kfull, K, piv);
     std::vector<double> G((size_t)nu * NIN), col(nk);
     for (int j = 0; j < NIN; j++) {
         for (int i = 0; i < nk; i++) col[i] = rhs[(size_t)i * NIN + j];

@@ -23,6 +23,9 @@ struct ColData {
 struct HostGeom {
     std::vector<int> stm, stn;
     std::vector<double> Pl, Ps, Qs, Ev, Mb, nJ, nM, fevR, fnR, fwR, dins;
+    // per column: 2-norm condition number of the large-stencil least-squares
+    // matrix, 1-norm condition number of the divergence-free KKT matrix
+    std::vector<double> cond_lsq, cond_kkt;
     std::vector<int> col_ae, col_side, col_perm, col_v, col_slot, col_rev, col_sgn;
     std::vector<double> fevA, fnA, fwA, aeF, aeW;
     std::vector<int> ae_rs;

@@ -176,10 +176,12 @@ struct rg_geom {
     float *whi = nullptr;
     unsigned char *zfl = nullptr, *ffl = nullptr, *efl = nullptr;
     bool fb_dirty = false;
+    bool fb_last = false;   // the last rg_step ran the fallback (its round counters are valid)
     rg::AdjBuffers adj;
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes
     std::vector<int> ae_rs_host; // +1 if side 1 of an angular edge is right of its direction
+    std::vector<double> cond_lsq, cond_kkt;   // per-column condition numbers (precompute)
     // optional per-stage timing: one set of RG_NSTAGE+1 events per recorded step
     bool prof_on = false;
     std::vector<void *> prof_events;
@@ -188,3 +190,4 @@ struct rg_geom {
 #define RG_NSTAGE RG_NSTAGES
 // bytes reserved for the fallback's round counters (ahead of its marks)
 #define RG_FB_COUNTER_BYTES 64
+constexpr int FALLBACK_ROUNDS = RG_FALLBACK_ROUNDS;

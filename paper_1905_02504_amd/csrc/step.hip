@@ -851,7 +851,7 @@ __global__ __launch_bounds__(256) void zone_update(DevGeom G, double dt, const d
 // ---------------------------------------------------------------- first-order fallback
 // Section I leaves positivity under strong fields to ruggedised schemes from
 // other work; the step's fallback is an a-posteriori per-zone order drop.
-constexpr int FALLBACK_ROUNDS = 4;
+static_assert(FALLBACK_ROUNDS == RG_FALLBACK_ROUNDS, "round count matches the C-ABI");
 static_assert(FALLBACK_ROUNDS * sizeof(int) <= RG_FB_COUNTER_BYTES, "round counters fit their slot");
 
 // zero n bytes (16 per lane; m 16-byte aligned)
@@ -1235,11 +1235,13 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
             RG_LAUNCH_CHECK();
         }
         g->fb_dirty = true;
+        g->fb_last = true;
     } else if (g->fb_dirty) {
         fb_clear<<<nblocks((G.Z + 15) / 16, 256), 256, 0, st>>>(g->zfl, G.Z);
         RG_LAUNCH_CHECK();
         g->fb_dirty = false;
     }
+    if (!prm.fallback) g->fb_last = false;
     zone_update<<<nblocks((i64)G.ncol * G.Nr, 256), 256, 0, st>>>(G, dt, g->Phi, g->zoneB, Uo,
                                                                   prm.fallback ? g->zfl : nullptr);
     face_ct<<<nblocks(nff, 256), 256, 0, st>>>(G, dt, g->Gam, Bo);
@@ -1303,26 +1305,37 @@ rg_status launch_stokes(rg_geom *g, const double *circ, double *Bf, void *stream
     return RG_OK;
 }
 
-rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
+// The CFL reduction: cfl_partial leaves one minimum per block of 256
+// interior zones in red[0 .. nb-1], cfl_final the global one in red[65535],
+// which is copied to the host.  red holds CFL_RED_DOUBLES doubles.
+constexpr int CFL_RED_DOUBLES = 65536;
+
+static rg_status cfl_reduce(const DevGeom &G, const double *U, double gamma, double cfl, hipStream_t st, double *red,
+                            double *dt)
 {
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const DevGeom &G = g->d;
-    i64 n = (i64)G.ncol * G.Nr;
-    unsigned nb = nblocks(n, 256);
-    if (nb > 65535) {
-        set_error("mesh too large for the CFL reduction");
+    const i64 n = (i64)G.ncol * G.Nr;
+    const unsigned nb = nblocks(n, 256);
+    if (nb > CFL_RED_DOUBLES - 1) {
+        set_error("mesh too large for the CFL reduction: " + std::to_string(n) + " interior zones, at most " +
+                  std::to_string((long long)(CFL_RED_DOUBLES - 1) * 256));
         return RG_ENOTSUP;
     }
-    cfl_partial<<<nb, 256, 0, st>>>(G, gamma, cfl, U, g->red);
-    cfl_final<<<1, 256, 0, st>>>((int)nb, g->red);
+    cfl_partial<<<nb, 256, 0, st>>>(G, gamma, cfl, U, red);
+    cfl_final<<<1, 256, 0, st>>>((int)nb, red);
     RG_LAUNCH_CHECK();
-    if (hipMemcpyAsync(dt, g->red + 65535, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(dt, red + CFL_RED_DOUBLES - 1, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         set_error("CFL reduction copy failed");
         return RG_EDEVICE;
     }
     return RG_OK;
 }
+
+rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
+{
+    return cfl_reduce(g->d, U, gamma, cfl, static_cast<hipStream_t>(stream), g->red, dt);
+}
+
 
 }  // namespace rg
 

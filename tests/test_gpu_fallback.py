@@ -73,8 +73,15 @@ def test_fallback_parity_blast(order, presteps):
             say(f"[fallback] flagged zones: GPU {int(flags.sum())}, oracle {int(fz.sum())}")
             assert fz.sum() > 0
             np.testing.assert_array_equal(flags, fz)
+            # zones newly flagged per round (rg_step_fallback_counts) against
+            # the round in which the oracle flagged each zone
+            counts = lib.fallback_counts()
+            want = np.bincount(om.last_fallback_round, minlength=5)[1:5].tolist()
+            say(f"[fallback] per-round counts: GPU {counts}, oracle {want}")
+            assert counts == want
         else:
             assert flags.sum() == 0
+            assert lib.fallback_counts() == [0, 0, 0, 0]
 
 
 def test_adjoint_refuses_the_fallback():
