@@ -245,6 +245,17 @@ rg_status rg_step_weno_order(const rg_geom *geom, float *whi, void *stream);
  * (Section VIII) for device state U; blocks until the result is on the host. */
 rg_status rg_cfl_dt(const rg_geom *geom, const double *U, double gamma, double cfl, void *stream, double *dt);
 
+/* rg_cfl_dt for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, but the block minima go
+ * through a file-scope device array of 65,536 doubles (512 KiB, held by each
+ * device the library runs on until the process ends) instead of the
+ * geometry's buffer, and the call allocates nothing.  Meshes with more than
+ * 65,535 x 256 = 16,776,960 interior zones are refused (RG_ENOTSUP).  The
+ * array is shared by every call on a device: calls that overlap on one
+ * device race.  Runs on the current device; blocks until dt is on the host. */
+rg_status rg_cfl_dt_noalloc(const rg_geom *geom, const double *U, double gamma, double cfl, void *stream, double *dt);
+
 /* Initial data on the host (caller-owned host arrays U[8][n_zones],
  * Bf[n_faces]) for a circularly polarised Alfven wave with axis frame
  * (e1, e2, a) = frame[0..8]: B = B0 a + dB (cos phi e1 + sin phi e2),

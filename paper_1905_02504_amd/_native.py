@@ -77,6 +77,7 @@ def lib():
         L.rg_status_str.argtypes = [C.c_int]
         L.rg_status_str.restype = C.c_char_p
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
+        L.rg_cfl_dt_noalloc.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_geom_conditioning.argtypes = [_vp, _vp, _vp]
         L.rg_step_fallback_counts.argtypes = [_vp, _vp, _vp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -92,7 +93,7 @@ def lib():
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
                      "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
                      "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag",
-                     "rg_geom_conditioning", "rg_step_fallback_counts"):
+                     "rg_cfl_dt_noalloc", "rg_geom_conditioning", "rg_step_fallback_counts"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -191,6 +192,12 @@ def rg_fma_probe(sink_ptr, n_threads, iters, stream):
 def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):
     out = C.c_double(0.0)
     check(lib().rg_cfl_dt(geom, _vp(U_ptr), gamma, cfl, _vp(stream), C.byref(out)), "rg_cfl_dt")
+    return out.value
+
+
+def rg_cfl_dt_noalloc(geom, U_ptr, gamma, cfl, stream):
+    out = C.c_double(0.0)
+    check(lib().rg_cfl_dt_noalloc(geom, _vp(U_ptr), gamma, cfl, _vp(stream), C.byref(out)), "rg_cfl_dt_noalloc")
     return out.value
 
 

@@ -601,6 +601,13 @@ extern "C" rg_status rg_cfl_dt(const rg_geom *g, const double *U, double gamma, 
     return launch_cfl(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
 }
 
+extern "C" rg_status rg_cfl_dt_noalloc(const rg_geom *g, const double *U, double gamma, double cfl, void *stream,
+                                       double *dt)
+{
+    if (!g || !g->d.vol || !U || !dt || !(cfl > 0) || !(gamma > 1)) { set_error("invalid argument"); return RG_EINVAL; }
+    return launch_cfl_noalloc(const_cast<rg_geom *>(g), U, gamma, cfl, stream, dt);
+}
+
 extern "C" rg_status rg_step_fallback_counts(const rg_geom *g, int32_t *counts, void *stream)
 {
     if (!g || !g->d.vol || !counts) { set_error("invalid argument"); return RG_EINVAL; }

@@ -48,6 +48,8 @@ rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, cons
                       double *Bo, void *stream);
 rg_status profile_end(rg_geom *g, double *ms, int *nsteps);
 rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt);
+// the same reduction through a file-scope device array (no allocation)
+rg_status launch_cfl_noalloc(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt);
 // stages 0-4 of the step only (boundary fill into Uo / Bo, reconstruction,
 // divergence-free B, predictor and traces), FP64
 rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,

@@ -15,6 +15,8 @@
 //   edge_emf           : multidimensional HLL electric field at edge Simpson points
 //   zone_update        : finite-volume update of the eight zone averages
 //   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
+#include <mutex>
+
 #include "mhd_device.hpp"
 
 namespace rg {
@@ -1336,6 +1338,43 @@ rg_status launch_cfl(rg_geom *g, const double *U, double gamma, double cfl, void
     return cfl_reduce(g->d, U, gamma, cfl, static_cast<hipStream_t>(stream), g->red, dt);
 }
 
+// ---------------------------------------------------------------- allocation-free CFL
+// rg_cfl_dt_noalloc reduces through this file-scope array instead of the
+// geometry's buffer.  Each device holds its own copy (512 KiB) for the life
+// of the process; every call on a device shares it, so calls that overlap on
+// one device race.  Its device address is taken once per device with
+// hipGetSymbolAddress (the array's name is not a device address in host code).
+__device__ __align__(256) double scratch[CFL_RED_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+rg_status launch_cfl_noalloc(rg_geom *g, const double *U, double gamma, double cfl, void *stream, double *dt)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        set_error("hipGetDevice failed or device index out of range");
+        return RG_EDEVICE;
+    }
+    double *red = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                set_error(std::string("hipGetSymbolAddress of the CFL scratch failed: ") + hipGetErrorString(e));
+                return RG_EDEVICE;
+            }
+            g_scratch_ptr[dev] = static_cast<double *>(p);
+        }
+        red = g_scratch_ptr[dev];
+    }
+    return cfl_reduce(g->d, U, gamma, cfl, static_cast<hipStream_t>(stream), red, dt);
+}
 
 }  // namespace rg
 
