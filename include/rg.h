@@ -54,10 +54,13 @@ typedef enum {
 } rg_status;
 
 /* Geodesic shell mesh, Section II.a (cube-based, recursive great-circle
- * bisection, N = 2^k zones per cube edge) with radial extrusion into shells
- * of geometrically growing thickness (self-similar zones, Section V.b). */
+ * bisection, N = 2^k zones per cube edge; for N = 3 * 2^k each cube face is
+ * first split 3 x 3, its edges at their thirds by arc length and the interior
+ * points where the great circles joining opposite edges' thirds meet) with
+ * radial extrusion into shells of geometrically growing thickness
+ * (self-similar zones, Section V.b). */
 typedef struct {
-    int32_t n_ang;      /* zones per cube edge, a power of two (>= 2)            */
+    int32_t n_ang;      /* zones per cube edge: 2^k (k >= 1) or 3 * 2^k (k >= 0) */
     int32_t n_rad;      /* physical radial shells                               */
     double r_in, r_out; /* inner / outer radius, 0 < r_in < r_out               */
     int32_t radial;     /* 0 = geometric shells r_k = r_in (r_out/r_in)^(k/n_rad) */
@@ -77,8 +80,8 @@ typedef struct rg_mesh rg_mesh;
 typedef struct rg_geom rg_geom;
 
 /* Builds the mesh topology on the host.  Deterministic.  *out receives a
- * handle owned by the caller (rg_mesh_free).  RG_ENOTSUP if n_ang is not a
- * power of two, RG_EINVAL for other bad fields. */
+ * handle owned by the caller (rg_mesh_free).  RG_ENOTSUP if n_ang is neither
+ * 2^k nor 3 * 2^k, RG_EINVAL for other bad fields. */
 rg_status rg_mesh_build(const rg_mesh_desc *desc, rg_mesh **out);
 rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info);
 void rg_mesh_free(rg_mesh *mesh);
@@ -286,6 +289,18 @@ rg_status rg_init_alfven(const rg_geom *geom, const double *frame, double rho, d
  * radial potential cannot produce it). */
 rg_status rg_init_tube(const rg_geom *geom, const double *left, const double *right, double Br0, double r0,
                        double rm, double delta, double gamma, double *U, double *Bf);
+
+/* Initial data on the host (caller-owned host arrays U[8][n_zones],
+ * Bf[n_faces]) for the magnetised blast of Section VIII.b: density rho, gas
+ * at rest, pressure p_in inside the ball |x - centre| < radius and p outside,
+ * uniform field B = B0 axis (axis: unit vector, double[3]; centre double[3]).
+ * Zone averages by Gauss cubature of the pressure step (12 x 12 x 12 points
+ * in zones the ball's surface may cut, 4 x 4 x 3 elsewhere); Bf from the
+ * circulations of A = (B0/2) axis x r, divergence-free to round-off.  Works on
+ * a host-only geometry.  RG_EINVAL unless radius, rho, p_in, p > 0 and
+ * gamma > 1. */
+rg_status rg_init_blast(const rg_geom *geom, const double *axis, const double *centre, double radius, double rho,
+                        double p_in, double p, double B0, double gamma, double *U, double *Bf);
 
 /* Diagnostics of a state on the device (for checks after a step; not part of
  * the scheme): over the interior zones, the largest relative divergence

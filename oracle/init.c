@@ -69,6 +69,8 @@ typedef struct {
     double frame[9], rho0, p0, B0, dB, kw, t;
     /* spherical shock tube: states (rho, p, v_r, v_theta, v_phi, B_theta, B_phi) */
     double sL[7], sR[7], Br0, r0, rm, delta;
+    /* blast: p_in inside the ball |x - centre| < radius, uniform B along frame[6..8] */
+    double centre[3], radius, p_in;
 } field_ctx;
 
 static void fields(const field_ctx *c, const double *x, double *rho, double *v, double *p, double *B, double *A)
@@ -82,6 +84,18 @@ static void fields(const field_ctx *c, const double *x, double *rho, double *v, 
         B[0] = g[2][1] - g[1][2];
         B[1] = g[0][2] - g[2][0];
         B[2] = g[1][0] - g[0][1];
+    } else if (c->kind == 3) {
+        const double *a = &c->frame[6];
+        double d2 = 0.0;
+        for (int i = 0; i < 3; i++) d2 += (x[i] - c->centre[i]) * (x[i] - c->centre[i]);
+        *rho = c->rho0;
+        *p = d2 < c->radius * c->radius ? c->p_in : c->p0;
+        double ax[3] = {a[1] * x[2] - a[2] * x[1], a[2] * x[0] - a[0] * x[2], a[0] * x[1] - a[1] * x[0]};
+        for (int i = 0; i < 3; i++) {
+            v[i] = 0.0;
+            B[i] = c->B0 * a[i];
+            A[i] = 0.5 * c->B0 * ax[i];
+        }
     } else if (c->kind == 2) {
         double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]), s = sqrt(x[0] * x[0] + x[1] * x[1]);
         double st = s / r, ct = x[2] / r;
@@ -245,6 +259,26 @@ void rgo_run_init_tube(const rgo_mesh *m, const double *left, const double *righ
     c.r0 = r0;
     c.rm = rm;
     c.delta = delta;
+    c.gamma = gamma;
+    init_state(m, &c, U, Bf);
+}
+
+/* magnetised blast (Section VIII.b): rho, v = 0, pressure p_in inside the
+ * ball |x - centre| < radius and p outside (zone averages by the zone
+ * cubature of this step function), uniform B = B0 a (A = (B0/2) a x r) */
+void rgo_run_init_blast(const rgo_mesh *m, const double *axis, const double *centre, double radius, double rho,
+                        double p_in, double p, double B0, double gamma, double *U, double *Bf)
+{
+    field_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.kind = 3;
+    memcpy(&c.frame[6], axis, sizeof(double) * 3);
+    memcpy(c.centre, centre, sizeof(double) * 3);
+    c.radius = radius;
+    c.rho0 = rho;
+    c.p_in = p_in;
+    c.p0 = p;
+    c.B0 = B0;
     c.gamma = gamma;
     init_state(m, &c, U, Bf);
 }

@@ -6,6 +6,8 @@
  * great-circle midpoints on the edges and the great-circle intersection of
  * the two mid-lines at the centre (the geodesic-mesh construction of Section
  * II.a transposed from icosahedral triangles to the cube's quadrilaterals).
+ * For 3 * 2^k zones per cube edge the face is first split 3 x 3 at the
+ * thirds of its edges (by arc length).
  * The surface mesh is extruded radially into shells with geometrically
  * growing radii (self-similar, "logarithmically ratioed" zones, Section V.b).
  *
@@ -173,11 +175,68 @@ static const double CUBE[6][3][3] = {
     {{0, 0, -1}, {0, 1, 0}, {1, 0, 0}},
 };
 
+/* the point k/3 (k = 1, 2) of the way along the great-circle arc from a to
+ * b: a rotated about the arc's axis by k/3 of the arc's angle (Rodrigues).
+ * Always computed from the lexicographically smaller endpoint, so that the
+ * two cube faces sharing an edge produce the same bits for its points. */
+static int lex_less(const double *a, const double *b)
+{
+    for (int i = 0; i < 3; i++)
+        if (a[i] != b[i]) return a[i] < b[i];
+    return 0;
+}
+
+static void arc_third(const double *a, const double *b, int k, double *out)
+{
+    if (!lex_less(a, b)) {
+        const double *t = a;
+        a = b;
+        b = t;
+        k = 3 - k;
+    }
+    double ax[3], w[3];
+    cross3(a, b, ax);
+    double s = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double phi = atan2(s, c) * k / 3.0;
+    for (int i = 0; i < 3; i++) ax[i] /= s;
+    cross3(ax, a, w);   /* in-plane direction perpendicular to a, toward b */
+    for (int i = 0; i < 3; i++) out[i] = cos(phi) * a[i] + sin(phi) * w[i];
+    normalize3(out);
+}
+
+/* a cube face (corners a, b, cc, d counter-clockwise) split 3 x 3: its edges
+ * at their thirds, the interior points where the great circles joining the
+ * thirds of opposite edges meet; each part then subdivided depth times */
+static void split3(subdiv_ctx *c, const double *a, const double *b, const double *cc, const double *d, int depth)
+{
+    double P[4][4][3];   /* P[j][i]: i along a -> b, j along a -> d */
+    memcpy(P[0][0], a, 24);
+    memcpy(P[0][3], b, 24);
+    memcpy(P[3][3], cc, 24);
+    memcpy(P[3][0], d, 24);
+    for (int k = 1; k <= 2; k++) {
+        arc_third(a, b, k, P[0][k]);
+        arc_third(d, cc, k, P[3][k]);
+        arc_third(a, d, k, P[k][0]);
+        arc_third(b, cc, k, P[k][3]);
+    }
+    double hint[3];
+    for (int i = 0; i < 3; i++) hint[i] = a[i] + b[i] + cc[i] + d[i];
+    for (int j = 1; j <= 2; j++)
+        for (int i = 1; i <= 2; i++) rgo_gc_intersect(P[0][i], P[3][i], P[j][0], P[j][3], hint, P[j][i]);
+    for (int j = 0; j < 3; j++)
+        for (int i = 0; i < 3; i++) subdivide(c, P[j][i], P[j][i + 1], P[j + 1][i + 1], P[j + 1][i], depth);
+}
+
 static int build_sphere(rgo_mesh *m)
 {
     int N = m->n_ang, depth = 0;
-    while ((1 << depth) < N) depth++;
-    if ((1 << depth) != N) return -1;
+    /* N = 2^depth, or 3 * 2^depth after a first split into 3 x 3 */
+    const int three = (N % 3 == 0);
+    const int base = three ? 3 : 1;
+    while ((base << depth) < N) depth++;
+    if ((base << depth) != N || N < 2) return -1;
     subdiv_ctx c;
     c.nv = 0;
     c.nq = 0;
@@ -193,7 +252,8 @@ static int build_sphere(rgo_mesh *m)
             for (int d = 0; d < 3; d++)
                 cr[k][d] = s * (CUBE[f][0][d] + (2 * ij[k][0] - 1) * CUBE[f][1][d] +
                                 (2 * ij[k][1] - 1) * CUBE[f][2][d]);
-        subdivide(&c, cr[0], cr[1], cr[2], cr[3], depth);
+        if (three) split3(&c, cr[0], cr[1], cr[2], cr[3], depth);
+        else subdivide(&c, cr[0], cr[1], cr[2], cr[3], depth);
     }
     hm_free(&c.vmap);
     if (c.nv != 6 * N * N + 2) return -1;

@@ -18,6 +18,8 @@ int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U
 int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
                            double *coeffs, int *exps, double *face_nodal);
 double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U);
+void rgo_run_init_blast(const rgo_mesh *m, const double *axis, const double *centre, double radius, double rho,
+                        double p_in, double p, double B0, double gamma, double *U, double *Bf);
 int rgo_run_weno_rows(const rgo_mesh *m, int z, double *A);
 int rgo_run_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double *U, int z, double *out);
 double rgo_emf3(const double U[3][NVAR], const double E[3][3], const double n[3][3], const double *t, double gamma);
@@ -311,3 +313,9 @@ int rgo_weno_detail(const rgo_mesh *m, int flags, double weno_eps, const double 
 }
 
 int rgo_weno_rows(const rgo_mesh *m, int z, double *A) { return rgo_run_weno_rows(m, z, A); }
+
+void rgo_init_blast(const rgo_mesh *m, const double *axis, const double *centre, double radius, double rho,
+                    double p_in, double p, double B0, double gamma, double *U, double *Bf)
+{
+    rgo_run_init_blast(m, axis, centre, radius, rho, p_in, p, B0, gamma, U, Bf);
+}

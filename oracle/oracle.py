@@ -95,6 +95,8 @@ def lib():
         L.rgo_fast.argtypes = [_dp, C.c_double, _dp]
         L.rgo_emf3x.restype = C.c_double
         L.rgo_emf3x.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
+        L.rgo_init_blast.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, _dp, _dp]
         L.rgo_weno_rows.restype = C.c_int
         L.rgo_weno_rows.argtypes = [C.c_void_p, C.c_int, _dp]
         L.rgo_weno_detail.restype = C.c_int
@@ -213,6 +215,16 @@ class OracleMesh:
         assert L.shape == (7,) and R.shape == (7,) and L[5] == 0.0 and R[5] == 0.0
         lib().rgo_init_tube(self._h, L, R, float(prob["Br0"]), float(prob["r0"]), float(prob["rm"]),
                             float(prob["delta"]), float(prob["gamma"]), U, Bf)
+        return U, Bf
+
+    def init_blast(self, prob):
+        """Magnetised blast: prob from rg_inputs.blast_problem; zone averages of the
+        pressure step by the zone cubature."""
+        U = np.zeros((NVAR, self.nz)); Bf = np.zeros(self.nf)
+        lib().rgo_init_blast(self._h, np.ascontiguousarray(prob["axis"], np.float64),
+                             np.ascontiguousarray(prob["centre"], np.float64), float(prob["radius"]),
+                             float(prob["rho"]), float(prob["p_in"]), float(prob["p"]), float(prob["B0"]),
+                             float(prob["gamma"]), U, Bf)
         return U, Bf
 
     # the method -----------------------------------------------------------

@@ -110,6 +110,17 @@ class ShellMHD:
                          prob["wavelength"], prob["gamma"], float(t), _ptr(nz), float(noise_amp), _ptr(U), _ptr(Bf))
         return U, Bf
 
+    def init_blast(self, prob):
+        """rg_init_blast: host (U, Bf) of the magnetised blast; prob from
+        rg_inputs.blast_problem (axis, centre, radius, rho, p_in, p, B0, gamma)."""
+        U = np.zeros((8, self.nz)); Bf = np.zeros(self.nf)
+        a = np.ascontiguousarray(prob["axis"], np.float64)
+        c = np.ascontiguousarray(prob["centre"], np.float64)
+        N.rg_init_blast(self._geom, _ptr(a), _ptr(c), float(prob["radius"]), float(prob["rho"]),
+                        float(prob["p_in"]), float(prob["p"]), float(prob["B0"]), float(prob["gamma"]),
+                        _ptr(U), _ptr(Bf))
+        return U, Bf
+
     def init_tube(self, prob):
         """rg_init_tube: host (U, Bf) of a spherical shock tube; prob holds 'left' and
         'right' (rho, p, v_r, v_theta, v_phi, B_theta, B_phi), 'Br0', 'r0', 'rm',

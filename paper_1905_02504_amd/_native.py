@@ -79,6 +79,8 @@ def lib():
         L.rg_cfl_dt.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_cfl_dt_noalloc.argtypes = [_vp, _vp, C.c_double, C.c_double, _vp, _dp]
         L.rg_geom_conditioning.argtypes = [_vp, _vp, _vp]
+        L.rg_init_blast.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, _vp, _vp]
         L.rg_step_fallback_counts.argtypes = [_vp, _vp, _vp]
         L.rg_init_alfven.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, C.c_double, _vp, _vp]
@@ -93,7 +95,7 @@ def lib():
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
                      "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
                      "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag",
-                     "rg_cfl_dt_noalloc", "rg_geom_conditioning", "rg_step_fallback_counts"):
+                     "rg_cfl_dt_noalloc", "rg_geom_conditioning", "rg_init_blast", "rg_step_fallback_counts"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +214,11 @@ def rg_step_fallback_counts(geom, stream):
     out = (C.c_int32 * RG_FALLBACK_ROUNDS)()
     check(lib().rg_step_fallback_counts(geom, out, _vp(stream)), "rg_step_fallback_counts")
     return list(out)
+
+
+def rg_init_blast(geom, axis_ptr, centre_ptr, radius, rho, p_in, p, B0, gamma, U_ptr, Bf_ptr):
+    check(lib().rg_init_blast(geom, _vp(axis_ptr), _vp(centre_ptr), radius, rho, p_in, p, B0, gamma, _vp(U_ptr),
+                              _vp(Bf_ptr)), "rg_init_blast")
 
 
 def rg_init_tube(geom, left_ptr, right_ptr, Br0, r0, rm, delta, gamma, U_ptr, Bf_ptr):

@@ -68,24 +68,47 @@ struct Tube {
     }
 };
 
+// Magnetised blast (Section VIII.b): density rho, gas at rest, pressure pin
+// inside the ball |x - c| < R and p outside, uniform B = B0 a with
+// A = (B0/2) a x r.
+struct Blast {
+    double a[3], c[3], R, rho, pin, p, B0;
+    void eval(const double *x, double &rh, double *v, double &pp, double *B, double *A) const
+    {
+        const double d0 = x[0] - c[0], d1 = x[1] - c[1], d2 = x[2] - c[2];
+        rh = rho;
+        pp = d0 * d0 + d1 * d1 + d2 * d2 < R * R ? pin : p;
+        const double axr[3] = {a[1] * x[2] - a[2] * x[1], a[2] * x[0] - a[0] * x[2], a[0] * x[1] - a[1] * x[0]};
+        for (int i = 0; i < 3; i++) {
+            v[i] = 0.0;
+            B[i] = B0 * a[i];
+            A[i] = 0.5 * B0 * axr[i];
+        }
+    }
+};
+
 const int LF_EDGE[4] = {4, 5, 0, 1};
 const int LF_FROMTO[4][2] = {{0, 3}, {1, 2}, {0, 1}, {3, 2}};
 
-// Zone averages of the conserved variables (4 x 4 x 3 Gauss points per zone)
+// Zone averages of the conserved variables (na x na x nr Gauss points per
+// zone; 4 x 4 x 3 unless given).  With only(c, k) set, only the zones it
+// accepts are written.
 template <class F>
-void zone_averages(const rg_geom *g, const F &fld, double gamma, const double *noise, double noise_amp, double *U)
+void zone_averages(const rg_geom *g, const F &fld, double gamma, const double *noise, double noise_amp, double *U,
+                   int na = 4, int nr = 3, bool (*only)(const rg_geom *, const void *, int, int) = nullptr,
+                   const void *only_arg = nullptr)
 {
     const Mesh &m = g->mesh->m;
     const int K = m.K, mo = m.map_order;
     const int64_t Z = m.nzones;
-    const int na = 4, nr = 3;
-    double ax[8], aw[8], rx[8], rw[8];
+    double ax[16], aw[16], rx[16], rw[16];
     gauss_legendre01(na, ax, aw);
     gauss_legendre01(nr, rx, rw);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(dynamic, 16)
     for (int c = 0; c < m.ncol; c++) {
         const double *sn = &g->snode[(size_t)c * 48];
         for (int k = 0; k < K; k++) {
+            if (only && !only(g, only_arg, c, k)) continue;
             int64_t z = (int64_t)c * K + k;
             double acc[8] = {0}, vol = 0.0;
             for (int kk = 0; kk < nr; kk++)
@@ -256,5 +279,45 @@ extern "C" rg_status rg_init_tube(const rg_geom *g, const double *left, const do
     zone_averages(g, tb, gamma, nullptr, 0.0, U);
     stokes_faces_host(g, tb, 4, Bf);
     radial_flux(g, tb, Bf);
+    return RG_OK;
+}
+
+namespace {
+// zones that the ball's surface may cut: the centroid is within the ball's
+// radius plus the zone's largest centroid-to-corner distance of its centre
+bool blast_cut(const rg_geom *g, const void *arg, int c, int k)
+{
+    const Blast &b = *static_cast<const Blast *>(arg);
+    const Mesh &m = g->mesh->m;
+    const int64_t z = (int64_t)c * m.K + k;
+    const double *cen = &g->zcen[(size_t)z * 3];
+    double reach = 0.0;
+    for (int corner = 0; corner < 8; corner++) {
+        double xi[3] = {(corner & 1) ? 0.5 : -0.5, (corner & 2) ? 0.5 : -0.5, (corner & 4) ? 0.5 : -0.5}, x[3], jac[9];
+        zone_map(m.map_order, &g->snode[(size_t)c * 48], m.radius[k], m.radius[k + 1], xi, x, jac);
+        reach = std::max(reach, std::sqrt((x[0] - cen[0]) * (x[0] - cen[0]) + (x[1] - cen[1]) * (x[1] - cen[1]) +
+                                          (x[2] - cen[2]) * (x[2] - cen[2])));
+    }
+    const double d = std::sqrt((cen[0] - b.c[0]) * (cen[0] - b.c[0]) + (cen[1] - b.c[1]) * (cen[1] - b.c[1]) +
+                               (cen[2] - b.c[2]) * (cen[2] - b.c[2]));
+    return d < b.R + 1.01 * reach;
+}
+}  // namespace
+
+extern "C" rg_status rg_init_blast(const rg_geom *g, const double *axis, const double *centre, double radius,
+                                   double rho, double p_in, double p, double B0, double gamma, double *U, double *Bf)
+{
+    if (!g || !axis || !centre || !U || !Bf || !(radius > 0) || !(rho > 0) || !(p_in > 0) || !(p > 0) ||
+        !(gamma > 1)) {
+        set_error("invalid argument");
+        return RG_EINVAL;
+    }
+    Blast b;
+    for (int i = 0; i < 3; i++) { b.a[i] = axis[i]; b.c[i] = centre[i]; }
+    b.R = radius; b.rho = rho; b.pin = p_in; b.p = p; b.B0 = B0;
+    // the step function's average: 4 x 4 x 3 points where it is constant, 12 x 12 x 12 where the sphere may cut
+    zone_averages(g, b, gamma, nullptr, 0.0, U);
+    zone_averages(g, b, gamma, nullptr, 0.0, U, 12, 12, blast_cut, &b);
+    stokes_faces_host(g, b, 1, Bf);
     return RG_OK;
 }

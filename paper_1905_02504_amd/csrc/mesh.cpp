@@ -54,13 +54,27 @@ struct BitsHash {
 
 }  // namespace
 
+// point a fraction k/3 (k = 1, 2) of the great-circle arc from a to b, by
+// spherical interpolation; third_point(b, a, 3 - k) gives the same bits, so
+// patches that share a cube edge share its vertices exactly
+V3 third_point(V3 a, V3 b, int k)
+{
+    const V3 c = crs(a, b);
+    const double th = std::atan2(std::sqrt(dt3(c, c)), dt3(a, b)), st = std::sin(th);
+    const double wa = std::sin((3 - k) * th / 3.0) / st, wb = std::sin(k * th / 3.0) / st;
+    return unit({wa * a.x + wb * b.x, wa * a.y + wb * b.y, wa * a.z + wb * b.z});
+}
+
 bool build_mesh(const rg_mesh_desc &d, Mesh &m)
 {
     int N = d.n_ang;
-    int levels = 0;
-    while ((1 << levels) < N) levels++;
-    if (N < 2 || (1 << levels) != N) {
-        set_error("n_ang must be a power of two >= 2");
+    // N = 2^levels (first grid: the patch corners) or 3 * 2^levels (first
+    // grid: the patch split 3 x 3 by great circles through the thirds of its
+    // edges), then levels bisections
+    int base = N % 3 == 0 ? 3 : 1, levels = 0;
+    while ((base << levels) < N) levels++;
+    if (N < 2 || (base << levels) != N) {
+        set_error("n_ang must be 2^k (k >= 1) or 3 * 2^k (k >= 0)");
         return false;
     }
     m.N = N;
@@ -90,6 +104,29 @@ bool build_mesh(const rg_mesh_desc &d, Mesh &m)
                 c.z = s * (FACE[p][0][2] + (2 * i - 1) * FACE[p][1][2] + (2 * j - 1) * FACE[p][2][2]);
                 cur[j * 2 + i] = c;
             }
+        if (base == 3) {
+            // edges split at their thirds, interior points where the great
+            // circles joining opposite edges' thirds meet
+            std::vector<V3> g3(16);
+            auto G = [&](int i, int j) -> V3 & { return g3[j * 4 + i]; };
+            G(0, 0) = cur[0];
+            G(3, 0) = cur[1];
+            G(0, 3) = cur[2];
+            G(3, 3) = cur[3];
+            for (int k = 1; k <= 2; k++) {
+                G(k, 0) = third_point(G(0, 0), G(3, 0), k);
+                G(k, 3) = third_point(G(0, 3), G(3, 3), k);
+                G(0, k) = third_point(G(0, 0), G(0, 3), k);
+                G(3, k) = third_point(G(3, 0), G(3, 3), k);
+            }
+            for (int j = 1; j <= 2; j++)
+                for (int i = 1; i <= 2; i++) {
+                    V3 hint = add(add(G(0, 0), G(3, 0)), add(G(0, 3), G(3, 3)));
+                    G(i, j) = gc_cross(G(i, 0), G(i, 3), G(0, j), G(3, j), hint);
+                }
+            cur.swap(g3);
+            n = 3;
+        }
         for (int lev = 0; lev < levels; lev++) {
             int n2 = 2 * n;
             nxt.assign((n2 + 1) * (n2 + 1), V3{0, 0, 0});

@@ -162,7 +162,8 @@ def blast_problem(p_in: float = 1000.0, radius: float = 0.1) -> dict:
     radius centred at 1.5 a."""
     frame = wave_frame()
     return {"frame": frame, "rho": 1.0, "p": 0.1, "B0": 10.0 / math.sqrt(4.0 * math.pi), "dB": 0.0,
-            "wavelength": 1.0, "gamma": 1.4, "p_in": p_in, "radius": radius, "centre": 1.5 * frame[2]}
+            "wavelength": 1.0, "gamma": 1.4, "p_in": p_in, "radius": radius, "centre": 1.5 * frame[2],
+            "axis": frame[2].copy()}
 
 
 def blast_pressure(prob: dict, centroids: np.ndarray) -> np.ndarray:

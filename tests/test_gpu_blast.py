@@ -25,10 +25,8 @@ CFL = 0.15
 
 
 def blast(lib, prob):
-    U, Bf = lib.init_alfven(prob)
-    cen, _ = lib.zone_data()
-    p = RI.blast_pressure(prob, cen)
-    U[4] = p / (prob["gamma"] - 1.0) + 0.5 * (U[1:4] ** 2).sum(0) / U[0] + 0.5 * (U[5:8] ** 2).sum(0)
+    """rg_init_blast: zone averages by cubature of the pressure step"""
+    U, Bf = lib.init_blast(prob)
     return torch.from_numpy(U).cuda(), torch.from_numpy(Bf).cuda()
 
 
@@ -83,16 +81,19 @@ def test_blast_with_fallback_stays_positive_6x16cubed(order):
     assert abs(d["sums"][0] - d["expected_sums"][0]) < 1e-12 * d0["sums"][0]
 
 
-def test_blast_6x128x128x54_fourth_order_50_steps():
-    """The blast workload at 5,308,416 zones (6 x 128^2 angular x 54 radial:
-    96 zones per patch edge are not reachable by recursive bisection, and
-    this split keeps the zone count with nearly cubic zones), fourth order,
-    50 steps, p = 1000 in a ball of radius 0.1, with the fallback."""
+@pytest.mark.parametrize("mode", ["fp64", "fp32"])
+def test_blast_6x96cubed_fourth_order_50_steps(mode):
+    """The blast workload at 6 x 96^2 angular x 96 radial = 5,308,416 zones
+    (96 = 3 x 2^5 zones per cube edge: a 3 x 3 first split, then five
+    bisections), fourth order, 50 steps, p = 1000 in a ball of radius 0.1
+    (zone averages by cubature of the step), with the fallback, in the FP64
+    scheme and in the FP32 form."""
     import paper_1905_02504_amd as R
-    print("[blast] order 4, 6x128^2x54, radius 0.1, 50 steps", flush=True)
-    lib = R.ShellMHD(128, 54, 4, n_ghost=3)
+    from paper_1905_02504_amd import _native as N
+    print(f"[blast] order 4, 6x96^3, radius 0.1, 50 steps, {mode}", flush=True)
+    lib = R.ShellMHD(96, 96, 4, n_ghost=3, mode=N.RG_MODE_FP32 if mode == "fp32" else N.RG_MODE_FP64)
     prob = RI.blast_problem(p_in=1000.0, radius=0.1)
-    U, Bf, d0, d, flagged, worst = run(lib, prob, 50, True, "6x128^2x54 o4")
+    U, Bf, d0, d, flagged, worst = run(lib, prob, 50, True, f"6x96^3 o4 {mode}")
     assert flagged > 0
     assert torch.isfinite(U).all() and torch.isfinite(Bf).all()
     assert worst[0] > 0.0 and worst[1] > 0.0

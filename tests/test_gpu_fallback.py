@@ -84,6 +84,35 @@ def test_fallback_parity_blast(order, presteps):
             assert lib.fallback_counts() == [0, 0, 0, 0]
 
 
+@pytest.mark.parametrize("order", [3, 4])
+def test_fallback_parity_blast_three_way_split_mesh(order):
+    """The blast on 6 x 6^2 x 6 zones (6 = 3 x 2: a 3 x 3 first split and one
+    bisection per cube face), its initial state by the oracle's cubature of
+    the pressure step (radius 0.35 at 1.5 a), one step with the fallback
+    against the oracle."""
+    import paper_1905_02504_amd as R
+    say(f"[fallback] order {order}, 6x6^3 blast")
+    om = O.OracleMesh(6, 6, order=order, n_ghost=3)
+    lib = R.ShellMHD(6, 6, order, n_ghost=3, device=True)
+    mp = Mapping(lib, om)
+    prob = RI.blast_problem(p_in=1000.0, radius=0.35)
+    gam = prob["gamma"]
+    U0, B0 = om.init_blast(prob)
+    dt = om.cfl_dt(U0, 0.15, gam)
+    ref = om.step(U0, B0, dt, gamma=gam, fallback=True)
+    dt_lib = lib.cfl_dt(torch.from_numpy(mp.U(U0)).cuda(), 0.15, gam)
+    Ug, Bg, _ = lib.step(torch.from_numpy(mp.U(U0)).cuda(), torch.from_numpy(mp.Bf(B0)).cuda(), dt, gamma=gam,
+                         fallback=True)
+    flags = lib.fallback_zones().cpu().numpy()
+    inter = lib.interior()
+    eU = rel_err(Ug.cpu().numpy()[:, inter], mp.U(ref[0])[:, inter]).max()
+    eB = rel_err(Bg.cpu().numpy(), mp.Bf(ref[1])).max()
+    say(f"[fallback] errors U {eU:.2e} Bf {eB:.2e} dt {abs(dt_lib - dt) / dt:.2e}, flagged GPU {int(flags.sum())} "
+        f"oracle {int(ref[2].sum())}")
+    assert eU < TOL and eB < TOL and abs(dt_lib - dt) < 1e-12 * dt
+    np.testing.assert_array_equal(flags, ref[2][mp.z])
+
+
 def test_adjoint_refuses_the_fallback():
     import paper_1905_02504_amd as R
     from paper_1905_02504_amd import _native as N

@@ -30,8 +30,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_argument_errors_are_reported():
     from paper_1905_02504_amd import _native as N
-    with pytest.raises(N.RGError):
-        N.rg_mesh_build(12, 4)          # not a power of two
+    for bad in (5, 10, 20):             # neither 2^k nor 3 * 2^k
+        with pytest.raises(N.RGError):
+            N.rg_mesh_build(bad, 4)
     with pytest.raises(N.RGError):
         N.rg_mesh_build(4, 4, r_in=2.0, r_out=1.0)
     m = N.rg_mesh_build(4, 2, n_ghost=2)
@@ -58,21 +59,22 @@ def test_status_strings():
     assert N.rg_status_str(99) == "unknown rg_status"
 
 
-def test_mesh_counts_match_formulas():
+@pytest.mark.parametrize("N", [8, 6, 3])
+def test_mesh_counts_match_formulas(N):
     import paper_1905_02504_amd as R
-    s = R.ShellMHD(8, 5, 3, n_ghost=2, device=False)
-    N, K = 8, s.K
+    s = R.ShellMHD(N, 5, 3, n_ghost=2, device=False)
+    K = s.K
     assert s.info["n_vertices"] == 6 * N * N + 2
     assert s.nz == 6 * N * N * K
     assert s.nf == 6 * N * N * (K + 1) + 12 * N * N * K
     assert s.ne == (6 * N * N + 2) * K + 12 * N * N * (K + 1)
 
 
-@pytest.mark.parametrize("order", [3, 4])
-def test_host_geometry_matches_oracle(order):
+@pytest.mark.parametrize("order,N", [(3, 4), (4, 4), (3, 6), (4, 6), (4, 3)])
+def test_host_geometry_matches_oracle(order, N):
     import paper_1905_02504_amd as R
-    s = R.ShellMHD(4, 3, order, n_ghost=order - 1, device=False)
-    m = O.OracleMesh(4, 3, order=order, n_ghost=order - 1)
+    s = R.ShellMHD(N, 3, order, n_ghost=order - 1, device=False)
+    m = O.OracleMesh(N, 3, order=order, n_ghost=order - 1)
     pc, pv = s.zone_data()
     oc, ov, _, _ = m.zones()
     zi = match(pc, oc)

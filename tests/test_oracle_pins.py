@@ -121,6 +121,34 @@ def test_mesh_counts(mesh3):
     assert m.ne == (6 * N * N + 2) * K + 12 * N * N * (K + 1)
 
 
+@pytest.mark.parametrize("N", [3, 6, 12])
+def test_mesh_with_three_way_first_split(N):
+    """N = 3 * 2^k: Euler's counts hold, every cube edge is cut into N arcs
+    of equal angle (the thirds of the first split, then bisections), each of
+    arccos(1/3) / N (a cube edge subtends arccos(1/3) at the centre), and the
+    shell volume converges to the closed form."""
+    m = O.OracleMesh(N, 2, order=3, n_ghost=2)
+    K = m.ktot
+    assert m.nv == 6 * N * N + 2 and m.nz == 6 * N * N * K
+    assert m.nf == 6 * N * N * (K + 1) + 12 * N * N * K
+    mid, tan, nzs = m.edges()
+    # radial edges at the cube corners have three zones around them
+    assert (nzs == 3).sum() == 8 * K
+    # unit vertex directions from the radial edges' tangents
+    rad = np.abs(np.linalg.norm(np.cross(mid, tan), axis=1)) < 1e-12
+    _, first = np.unique(np.round(tan[rad], 12), axis=0, return_index=True)
+    dirs = tan[rad][first]
+    assert len(dirs) == 6 * N * N + 2
+    cube_edge = np.sum(np.abs(dirs) >= np.abs(dirs).max(1, keepdims=True) - 1e-12, axis=1) >= 2
+    on_edge = dirs[cube_edge]   # vertices on the cube's edges (two equal largest |components|)
+    assert len(on_edge) == 12 * (N - 1) + 8
+    ang = np.arccos(np.clip(on_edge @ on_edge.T, -1, 1))
+    np.fill_diagonal(ang, 10.0)
+    want = np.arccos(1.0 / 3.0) / N
+    nearest = ang.min(1)
+    assert np.abs(nearest - want).max() < 1e-12
+
+
 def test_stencil_sizes(mesh3, mesh4):
     for m, full, corner in [(mesh3, 26, 23), (mesh4, 32, 29)]:
         cen, vol, shell, stn = m.zones()
