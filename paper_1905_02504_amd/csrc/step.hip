@@ -15,6 +15,7 @@
 //   edge_emf           : multidimensional HLL electric field at edge Simpson points
 //   zone_update        : finite-volume update of the eight zone averages
 //   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
+#include <climits>
 #include <mutex>
 
 #include "mhd_device.hpp"
@@ -135,6 +136,242 @@ __global__ __launch_bounds__(64) void weno_cols(DevGeom G, const double *__restr
             whi[(i64)c * G.K + G.g - 1 + kk] = wmin;
         }
     }
+}
+
+// WENO-AO on the FP64 matrix cores.  The per-column contractions are small
+// dense products shared by the zones of a column (Section III, eq. 3.4):
+//   chi  = Pl (NC x NS) . dU (NS x zones)        large-stencil least squares
+//   cs   = Ps (21 x 6)  . dU[0:6]                 the seven linear small stencils
+//   S    = Qs (NC x NC) . chi                     smoothness form, beta = chi . S
+// One wavefront takes 16 zones of a column and the eight variables in turn;
+// the column's matrices are the A operands and stay in registers for the
+// whole wavefront, the stencil differences are loaded straight into the B
+// operands, and chi leaves the first product in the layout the second one
+// takes as its B operand.  No LDS: the VALU form of this stage spent its
+// time on LDS broadcasts of the matrices (each element served one FMA).
+// v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16 (i % 4), element i / 4.  Here j is the zone, so
+// lane group g (lanes 16g .. 16g + 15) holds rows 4e + g of every tile.
+// Fourth order (NC = 19): chi takes two M tiles; the second holds chi's rows
+// 16-18 (element 0, groups 0-2) and small stencils 0-3 (stencil g in group
+// g, component i in element i + 1), a separate tile small stencils 4-6
+// (stencil 4 + g in group g, component i in element i); S is formed for
+// rows 0-15 only, with Qs's columns 16-18 doubled, and the rest of beta,
+// the 3 x 3 form of chi's rows 16-18, on the VALU.  Third order (NC = 9):
+// one chi tile; small stencil s, component i in row 16 (x / 4) + 4 (x % 4)
+// + s % 4, x = i + 3 (s / 4), of two tiles.
+template <int P>
+struct WenoMfma {
+    using T = Tr<P>;
+    static constexpr int MT = (T::NC + 15) / 16;   // M tiles of chi
+    static constexpr int KL = (T::NS + 3) / 4;     // K steps of the least squares
+    static constexpr int KQ = (T::NC + 3) / 4;     // K steps of the smoothness form
+    static constexpr int MS = P == 4 ? 1 : 2;      // M tiles of the separate small-stencil product
+};
+
+// sum of x over the four lane groups (lanes j, j + 16, j + 32, j + 48), the
+// same bits in every lane: rows of 16 lanes are exchanged with
+// v_permlane16_swap, then halves with v_permlane32_swap (VALU, no LDS)
+__device__ __forceinline__ double sum_lane_groups(double x)
+{
+    unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    x = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    lo = (unsigned)__double2loint(x);
+    hi = (unsigned)__double2hiint(x);
+    a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// x of lane groups 0, 1, 2 (the same lane offset) in every lane
+__device__ __forceinline__ void gather_groups3(double x, double &x0, double &x1, double &x2)
+{
+    const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+    // groups (0, 1) in rows 0-1, (2, 3) in rows 2-3
+    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    // the lower half's pair to every lane, and the upper half's
+    auto c = __builtin_amdgcn_permlane32_swap(a[0], a[0], false, false);
+    auto d = __builtin_amdgcn_permlane32_swap(b[0], b[0], false, false);
+    auto e = __builtin_amdgcn_permlane32_swap(a[1], a[1], false, false);
+    auto f = __builtin_amdgcn_permlane32_swap(b[1], b[1], false, false);
+    x0 = __hiloint2double((int)d[0], (int)c[0]);
+    x2 = __hiloint2double((int)d[1], (int)c[1]);
+    x1 = __hiloint2double((int)f[0], (int)e[0]);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void weno_mfma(
+    DevGeom G, const double *__restrict__ U, double *__restrict__ wc, const double *__restrict__ PlA,
+    const double *__restrict__ PsA, const double *__restrict__ QsA, double eps, int nrun, float *__restrict__ whi)
+{
+    using T = Tr<P>;
+    using W = WenoMfma<P>;
+    constexpr int MT = W::MT, KL = W::KL, KQ = W::KQ, MS = W::MS, NC = T::NC, NS = T::NS;
+    const double ghi = WENO_GAMMA_HI, gs = (1.0 - WENO_GAMMA_HI) / 7.0;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = (int)(lb / (unsigned)nrun), run = (int)(lb % (unsigned)nrun);
+    const int lane = threadIdx.x, g = lane >> 4, jz = lane & 15;
+    const int KR = G.Nr + 2, kk = run * 16 + jz;
+    const bool active = kk < KR;
+    const i64 z = (i64)c * G.K + G.g - 1 + (active ? kk : 0);
+    const double *Pl = PlA + (i64)c * NC * NS;
+    const double *Ps = PsA + (i64)c * 7 * 18;
+    const double *Qs = QsA + (i64)c * NC * NC;
+    // A operands: row jz of each M tile, column 4s + g of each K step.  Every
+    // load is unconditional (a lane without an entry reads entry 0 and masks
+    // it), so that the loads issue without branches.
+    double aL[MT][KL], aQ[KQ], aS[MS][2];
+#pragma unroll
+    for (int m = 0; m < MT; m++) {
+        const int row = 16 * m + jz;
+#pragma unroll
+        for (int s = 0; s < KL; s++) {
+            const int col = 4 * s + g;
+            // at fourth order rows 20-31 of tile 1 hold small stencil jz % 4,
+            // component jz / 4 - 1
+            const bool sm = P == 4 && m == 1 && jz >= 4;
+            const bool ok = sm ? col < 6 : (row < NC && col < NS);
+            const int idx = !ok ? 0 : sm ? (jz % 4) * 18 + (jz / 4 - 1) * 6 + col : row * NS + col;
+            const double a = (sm ? Ps : Pl)[idx];
+            aL[m][s] = ok ? a : 0.0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < KQ; s++) {
+        const int col = 4 * s + g;
+        // rows 0-15; at fourth order the columns of chi's rows 16-18 count twice
+        const bool ok = jz < NC && col < NC;
+        const double a = Qs[ok ? jz * NC + col : 0];
+        aQ[s] = ok ? (col >= 16 ? 2.0 : 1.0) * a : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < MS; m++)
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const int col = 4 * s + g;
+            bool ok;
+            int idx;
+            if (P == 4) {   // stencil 4 + jz % 4, component jz / 4
+                ok = jz % 4 < 3 && jz / 4 < 3 && col < 6;
+                idx = (4 + jz % 4) * 18 + (jz / 4) * 6 + col;
+            } else {
+                const int x = 4 * m + jz / 4, st = jz % 4 + 4 * (x / 3), comp = x % 3;
+                ok = x < 6 && st < 7 && col < 6;
+                idx = st * 18 + comp * 6 + col;
+            }
+            const double a = Ps[ok ? idx : 0];
+            aS[m][s] = ok ? a : 0.0;
+        }
+    // the 3 x 3 block of Qs for chi's rows 16-18 (fourth order)
+    double qbb[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b2 = 0; b2 < 3; b2++) qbb[a][b2] = P == 4 ? Qs[(16 + a) * NC + 16 + b2] : 0.0;
+    // stencil members of the K rows this lane feeds (offsets fit 32 bits);
+    // a lane without a member (missing corner member, padding, or a zone
+    // beyond the column) loads its own zone and masks the value, so that
+    // every load is unconditional
+    int dz[KL];
+    unsigned vmask = 0;
+#pragma unroll
+    for (int s = 0; s < KL; s++) {
+        const int t = 4 * s + g;
+        const int mem = t < NS ? G.stm[(i64)c * NS + t] : -1;
+        const bool ok = active && mem >= 0;
+        dz[s] = ok ? (int)(((i64)(mem >> 3) - c) * G.K + (mem & 7) - 3) : 0;
+        vmask |= ok ? 1u << s : 0u;
+    }
+    float wmin = 1e30f;
+    // the stencil values of the next variable are loaded while the current
+    // one is reduced (a software pipeline that also overlapped the products
+    // of the next variable with this reduction needed 175 VGPRs, two
+    // wavefronts per SIMD instead of three, and was slower: 12.4 against
+    // 10.5 ms at 6 x 128^2 x 128)
+    double raw[KL], u0 = U[z];
+#pragma unroll
+    for (int s = 0; s < KL; s++) raw[s] = U[z + dz[s]];
+#pragma unroll 1
+    for (int v = 0; v < 8; v++) {
+        double b[KL];
+#pragma unroll
+        for (int s = 0; s < KL; s++) b[s] = (vmask >> s) & 1u ? raw[s] - u0 : 0.0;
+        if (v < 7) {
+            const double *Un = U + (i64)(v + 1) * G.Z;
+            u0 = Un[z];
+#pragma unroll
+            for (int s = 0; s < KL; s++) raw[s] = Un[z + dz[s]];
+        }
+        dbl4 chi[MT], cs[MS], sq = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < MT; m++) chi[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < MS; m++) cs[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KL; s++)
+#pragma unroll
+            for (int m = 0; m < MT; m++) chi[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(aL[m][s], b[s], chi[m], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int m = 0; m < MS; m++) cs[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS[m][s], b[s], cs[m], 0, 0, 0);
+        // chi's element e of tile m is the B operand of K step 4m + e (at
+        // fourth order K step 4 takes tile 1's element 0: rows 16-19)
+#pragma unroll
+        for (int s = 0; s < KQ; s++) sq = __builtin_amdgcn_mfma_f64_16x16x4f64(aQ[s], chi[s / 4][s % 4], sq, 0, 0, 0);
+        // beta of the large stencil
+        double bhi = chi[0][0] * sq[0] + chi[0][1] * sq[1] + chi[0][2] * sq[2] + chi[0][3] * sq[3];
+        bhi = sum_lane_groups(bhi);
+        if constexpr (P == 4) {
+            double c16, c17, c18;
+            gather_groups3(chi[1][0], c16, c17, c18);
+            const double t0 = qbb[0][0] * c16 + qbb[0][1] * c17 + qbb[0][2] * c18;
+            const double t1 = qbb[1][0] * c16 + qbb[1][1] * c17 + qbb[1][2] * c18;
+            const double t2 = qbb[2][0] * c16 + qbb[2][1] * c17 + qbb[2][2] * c18;
+            bhi += c16 * t0 + c17 * t1 + c18 * t2;
+        }
+        // small stencils g and g + 4 of this lane group: components of each
+        double s0[3], s1[3];
+        if constexpr (P == 4) {
+            s0[0] = chi[1][1]; s0[1] = chi[1][2]; s0[2] = chi[1][3];
+            s1[0] = cs[0][0]; s1[1] = cs[0][1]; s1[2] = cs[0][2];
+        } else {
+            s0[0] = cs[0][0]; s0[1] = cs[0][1]; s0[2] = cs[0][2];
+            s1[0] = cs[0][3]; s1[1] = cs[MS - 1][0]; s1[2] = cs[MS - 1][1];
+        }
+        const double b0 = s0[0] * s0[0] + s0[1] * s0[1] + s0[2] * s0[2];
+        const double b1 = s1[0] * s1[0] + s1[1] * s1[1] + s1[2] * s1[2];
+        const double w0 = ghi / ((bhi + eps) * (bhi + eps));
+        const double ws0 = gs / ((b0 + eps) * (b0 + eps));
+        const double ws1 = g < 3 ? gs / ((b1 + eps) * (b1 + eps)) : 0.0;
+        const double tot = sum_lane_groups(ws0 + ws1) + w0;
+        const double itot = 1.0 / tot, w0n = w0 * itot;
+        wmin = fminf(wmin, float(w0n / ghi));
+        // first-order coefficients: (w0n / ghi)(chi_a - gs sum_s cs_sa) + sum_s (w_s / tot) cs_sa
+        const double k0 = ws0 * itot - w0n * gs / ghi, k1 = ws1 * itot - w0n * gs / ghi;
+        const double p0 = sum_lane_groups(k0 * s0[0] + k1 * s1[0]);
+        const double p1 = sum_lane_groups(k0 * s0[1] + k1 * s1[1]);
+        const double p2 = sum_lane_groups(k0 * s0[2] + k1 * s1[2]);
+        const double sc = w0n / ghi;
+        const double pg = g == 0 ? p0 : g == 1 ? p1 : p2;
+        if (active) {
+            double *out = wc + (i64)v * NC * G.Z + z;
+#pragma unroll
+            for (int m = 0; m < MT; m++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int a = 16 * m + 4 * e + g;
+                    if (P == 4 && m == 1 && e > 0) continue;   // small-stencil rows
+                    double o = sc * chi[m][e];
+                    if (a < 3) o += pg;
+                    if (a < NC) out[(i64)a * G.Z] = o;
+                }
+        }
+    }
+    if (active && g == 0) whi[z] = wmin;
 }
 
 // ---------------------------------------------------------------- face nodal B
@@ -1187,10 +1424,16 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(1, st);
     const i64 nzr = (i64)G.ncol * (G.Nr + 2);
-    const RunSplit wr = run_split(G.Nr + 2);
-    weno_cols<P, R><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
-        G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF),
-        R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft, g->whi);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        const int nrun = (G.Nr + 2 + 15) / 16;
+        weno_mfma<P><<<(unsigned)((i64)G.ncol * nrun), 64, 0, st>>>(G, Uo, reinterpret_cast<double *>(wcoef), G.Pl, G.Ps,
+                                                                    G.Qs, weno_eps(prm), nrun, g->whi);
+    } else {
+        const RunSplit wr = run_split(G.Nr + 2);
+        weno_cols<P, R><<<(unsigned)((i64)G.ncol * (wr.nchunk + (wr.nleft > 0))), 64, 0, st>>>(
+            G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF),
+            R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft, g->whi);
+    }
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
     {
