@@ -145,7 +145,21 @@ typedef struct {
                          gamma_s / (beta_s + eps)^2 (Section III; beta in units of
                          the squared zone data); 0 selects 1e-4                   */
     int32_t fallback; /* 0: off; 1: first-order fallback for positivity (below)  */
+    double flattener; /* 0: off; > 0: the flattener (below) with this threshold kappa */
 } rg_step_params;
+
+/* Flattener (params->flattener = kappa > 0).  Section VII.a applies a
+ * flattener on its coarse meshes and leaves its definition to other work;
+ * this step's reading: for every reconstructed zone, with
+ * D = (1/V) sum_faces s_f S_f . (v + v_neighbour) / 2 the discrete divergence
+ * of the zone averages' velocity (S_f the face's vector area, s_f = +1 on
+ * outward faces), l0 = V^(1/3) and c the smallest sqrt(gamma p / rho +
+ * B^2 / rho) over the zone and its six face neighbours,
+ * eta = min(1, max(0, -(l0 D + kappa c) / (kappa c))), and every WENO-AO
+ * coefficient of the zone (Section III; all eight variables) is scaled by
+ * 1 - eta before the rest of the step uses it: a zone compressing faster than
+ * kappa c / l0 drops toward first order, one compressing at 2 kappa c / l0 or
+ * faster is first order.  rg_step_adjoint refuses it (RG_ENOTSUP). */
 
 /* First-order fallback (params->fallback = 1).  Section I leaves positive
  * pressures under strong magnetic fields to ruggedised WENO schemes from

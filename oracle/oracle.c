@@ -9,8 +9,8 @@
 #include <string.h>
 
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
-                 unsigned char *fallback_zones);
+                 double flat_kappa, const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi,
+                 double *dbgGam, unsigned char *fallback_zones, double *eta_out);
 int rgo_run_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_eps, const double *U, const double *Bf,
                        double *whi);
 int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
@@ -172,11 +172,12 @@ double rgo_sphericity(const rgo_mesh *m, int samples)
 
 /* flags: 1 linear WENO weights (checks), 2 first-order fallback; fallback_zones
  * (may be NULL) receives 1 for every zone the fallback took */
-int rgo_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+int rgo_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps, double flat_kappa,
              const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
-             unsigned char *fallback_zones)
+             unsigned char *fallback_zones, double *eta)
 {
-    return rgo_run_step(m, gamma, dt, bc_kind, flags, weno_eps, U, Bf, Uout, Bfout, dbgPhi, dbgGam, fallback_zones);
+    return rgo_run_step(m, gamma, dt, bc_kind, flags, weno_eps, flat_kappa, U, Bf, Uout, Bfout, dbgPhi, dbgGam,
+                        fallback_zones, eta);
 }
 
 int rgo_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z, int npts,

@@ -62,8 +62,8 @@ def lib():
         L.rgo_sphericity.restype = C.c_double
         L.rgo_sphericity.argtypes = [C.c_void_p, C.c_int]
         L.rgo_step.restype = C.c_int
-        L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp,
-                               _dp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rgo_step.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double, _dp,
+                               _dp, _dp, _dp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rgo_recon.restype = C.c_int
         L.rgo_recon.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]
         L.rgo_divfree.restype = C.c_int
@@ -228,11 +228,13 @@ class OracleMesh:
         return U, Bf
 
     # the method -----------------------------------------------------------
-    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS, fallback=False):
+    def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, debug=False, weno_eps=WENO_EPS, fallback=False,
+             flattener=0.0):
         """One step.  With fallback=True the first-order fallback is on and the
         per-zone flags (uint8, 1 = the zone fell back) are returned last; the
         round that flagged each zone (1-based, 0 = not flagged) is kept in
-        self.last_fallback_round."""
+        self.last_fallback_round.  flattener > 0 turns the flattener on with
+        that threshold kappa; its per-zone values are kept in self.last_eta."""
         U = np.ascontiguousarray(U, np.float64); Bf = np.ascontiguousarray(Bf, np.float64)
         Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
         phi = np.zeros((self.nf, NVAR)) if debug else None
@@ -240,9 +242,11 @@ class OracleMesh:
         fz = np.zeros(self.nz, np.uint8)
         if fallback:
             flags |= FLAG_FALLBACK
-        rc = lib().rgo_step(self._h, gamma, dt, bc, flags, weno_eps, U, Bf, Uo, Bo,
+        eta = np.zeros(self.nz)
+        rc = lib().rgo_step(self._h, gamma, dt, bc, flags, weno_eps, float(flattener), U, Bf, Uo, Bo,
                             phi.ctypes.data if debug else None, gam.ctypes.data if debug else None,
-                            fz.ctypes.data)
+                            fz.ctypes.data, eta.ctypes.data)
+        self.last_eta = eta
         if rc != 0:
             raise RuntimeError("oracle step failed")
         out = (Uo, Bo, phi, gam) if debug else (Uo, Bo)

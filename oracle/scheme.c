@@ -158,6 +158,8 @@ typedef struct {
     double *Gam;            /* ne */
     int first_order;        /* traces are the zones' states at t^n (the fallback's re-solve) */
     double *whi;            /* nz, or NULL: the smallest over the variables of w_hi / gamma_hi */
+    double flat_kappa;      /* flattener threshold (0: off) */
+    double *eta;            /* nz flattener values, or NULL */
     int dbg_z;              /* zone whose WENO-AO internals are recorded (test access), or -1 */
     double *dbg;            /* per variable: beta_hi, beta_s[7], weights[8], then the nc coefficients */
 } step_ws;
@@ -199,6 +201,46 @@ static double minmod(double a, double b)
 {
     if (!(a * b > 0.0)) return 0.0;
     return (a > 0 ? 1.0 : -1.0) * fmin(fabs(a), fabs(b));
+}
+
+/* ---- flattener (Section VII.a applies one to its coarse meshes and
+ * defers its definition to other work).  The reading here: a zone is
+ * flattened where the flow compresses faster than a fraction kappa of the
+ * slowest signal speed around it.  With the discrete divergence of the zone
+ * averages' velocity over the zone,
+ *   D = (1/V) sum_faces s_f (sum_q dA_q n_q) . (v_zone + v_neighbour) / 2
+ * (s_f = +1 on outward faces), the length l0 = V^(1/3) and c the smallest
+ * fast speed sqrt(gamma p / rho + B^2 / rho) over the zone and its six face
+ * neighbours, eta = min(1, max(0, -(l0 D + kappa c) / (kappa c))): zero
+ * unless l0 D < -kappa c, one where l0 D <= -2 kappa c.  Every
+ * reconstruction coefficient of the zone (all eight variables) is then
+ * scaled by 1 - eta, so a fully flattened zone is first order. */
+static double zone_fast_max(const step_ws *w, int z)
+{
+    double u[NVAR];
+    for (int v = 0; v < NVAR; v++) u[v] = w->U[(size_t)v * w->m->nz + z];
+    double a2 = w->gamma * pressure(u, w->gamma) / u[IRHO], b2 = dot3(&u[IBX], &u[IBX]) / u[IRHO];
+    return sqrt(fmax(a2, 0.0) + b2);
+}
+
+static double flattener_eta(const step_ws *w, int z)
+{
+    const rgo_mesh *m = w->m;
+    const int nz = m->nz, Q = m->nq_face * m->nq_face;
+    double vz[3], div = 0.0, c = zone_fast_max(w, z);
+    for (int i = 0; i < 3; i++) vz[i] = w->U[(size_t)(IMX + i) * nz + z] / w->U[(size_t)IRHO * nz + z];
+    for (int lf = 0; lf < 6; lf++) {
+        int f = m->zone_face[6 * z + lf], zn = m->zone_nbr[6 * z + lf];
+        double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0, va[3] = {0, 0, 0}, vn[3] = {0, 0, 0};
+        for (int q = 0; q < Q; q++)
+            for (int i = 0; i < 3; i++) va[i] += m->fdA[f * RGO_MAXQ + q] * m->fn[(f * RGO_MAXQ + q) * 3 + i];
+        for (int i = 0; i < 3; i++) vn[i] = w->U[(size_t)(IMX + i) * nz + zn] / w->U[(size_t)IRHO * nz + zn];
+        for (int i = 0; i < 3; i++) div += sg * va[i] * 0.5 * (vz[i] + vn[i]);
+        c = fmin(c, zone_fast_max(w, zn));
+    }
+    div /= m->vol[z];
+    const double kc = w->flat_kappa * c;
+    return fmin(1.0, fmax(0.0, -(m->len[z] * div + kc) / kc));
 }
 
 /* large-stencil rows of zone z: volume average over each member zone j of
@@ -299,6 +341,8 @@ static void weno_zone(step_ws *w, int z)
                 for (int s = 0; s < nsm; s++) { lin += gs * cs[s][a]; nl += wgt[1 + s] * cs[s][a]; }
             coef[v * nc + a] = wgt[0] / WENO_GAMMA_HI * (chi[a] - lin) + nl;
         }
+        if (w->eta)   /* the flattener (above) */
+            for (int a = 0; a < nc; a++) coef[v * nc + a] *= 1.0 - w->eta[z];
         if (w->dbg && z == w->dbg_z) {
             double *d = w->dbg + (size_t)v * (16 + nc);
             for (int s = 0; s < 8; s++) { d[s] = beta[s]; d[8 + s] = wgt[s]; }
@@ -736,8 +780,8 @@ static void setup_bases(step_ws *w)
 }
 
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-                 const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi, double *dbgGam,
-                 unsigned char *fallback_zones)
+                 double flat_kappa, const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi,
+                 double *dbgGam, unsigned char *fallback_zones, double *eta_out)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
@@ -758,6 +802,14 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     for (int z = 0; z < nz; z++) {
         int k = m->zone_shell[z];
         w.recon[z] = (k >= g - 1 && k <= g + Nr);
+    }
+    if (flat_kappa > 0.0) {
+        w.flat_kappa = flat_kappa;
+        w.eta = calloc(nz, sizeof(double));
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; z++)
+            if (w.recon[z]) w.eta[z] = flattener_eta(&w, z);
+        if (eta_out) memcpy(eta_out, w.eta, sizeof(double) * nz);
     }
     w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(double));
     w.bface = calloc((size_t)nf * RGO_MAXQ, sizeof(double));
@@ -871,7 +923,7 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     if (dbgGam) memcpy(dbgGam, w.Gam, sizeof(double) * ne);
 
     free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc);
-    free(w.avgU); free(w.avgF); free(w.Phi); free(w.Gam);
+    free(w.avgU); free(w.avgF); free(w.Phi); free(w.Gam); free(w.eta);
     free(fneed); free(upd); free(fupd); free(eupd);
     return fail ? -1 : 0;
 }

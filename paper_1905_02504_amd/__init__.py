@@ -135,10 +135,11 @@ class ShellMHD:
 
     # the step ------------------------------------------------------------------
     def step(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, U_out=None, Bf_out=None, cfl=0.0, n_picard=0, weno_eps=0.0,
-             fallback=False):
+             fallback=False, flattener=0.0):
         """One timestep on torch.cuda float64 tensors; returns (U_out, Bf_out, dt).
         fallback=True turns on the first-order fallback for zones the high-order
-        update would leave with non-positive density or pressure."""
+        update would leave with non-positive density or pressure; flattener > 0
+        turns on the flattener with that threshold."""
         import torch
         assert U.is_cuda and U.dtype == torch.float64 and U.is_contiguous() and U.shape == (8, self.nz)
         assert Bf.is_cuda and Bf.dtype == torch.float64 and Bf.is_contiguous() and Bf.shape == (self.nf,)
@@ -146,7 +147,7 @@ class ShellMHD:
             U_out = torch.empty_like(U)
         if Bf_out is None:
             Bf_out = torch.empty_like(Bf)
-        p = rg_step_params(gamma, dt, cfl, bc, n_picard, weno_eps, int(bool(fallback)))
+        p = rg_step_params(gamma, dt, cfl, bc, n_picard, weno_eps, int(bool(fallback)), float(flattener))
         N.rg_step(self._geom, p, U.data_ptr(), Bf.data_ptr(), U_out.data_ptr(), Bf_out.data_ptr(), _stream())
         return U_out, Bf_out, p.dt
 

@@ -29,7 +29,8 @@ class rg_mesh_info(C.Structure):
 
 class rg_step_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("dt", C.c_double), ("cfl", C.c_double), ("bc_kind", C.c_int32),
-                ("n_picard", C.c_int32), ("weno_eps", C.c_double), ("fallback", C.c_int32)]
+                ("n_picard", C.c_int32), ("weno_eps", C.c_double), ("fallback", C.c_int32),
+                ("flattener", C.c_double)]
 
 
 class rg_diag_out(C.Structure):

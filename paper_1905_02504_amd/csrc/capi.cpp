@@ -470,7 +470,7 @@ extern "C" rg_status rg_step(const rg_geom *geom, rg_step_params *params, const 
 {
     if (!geom || !params || !U || !Bf || !U_out || !Bf_out) { set_error("null argument"); return RG_EINVAL; }
     if (!(params->gamma > 1.0) || params->bc_kind < 0 || params->bc_kind > 1 || params->n_picard < 0 ||
-        !(params->weno_eps >= 0.0) || params->fallback < 0 || params->fallback > 1) {
+        !(params->weno_eps >= 0.0) || params->fallback < 0 || params->fallback > 1 || !(params->flattener >= 0.0)) {
         set_error("invalid step parameters");
         return RG_EINVAL;
     }
@@ -524,6 +524,10 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
     if (!g->d.vol) { set_error("geometry was built without device data"); return RG_EINVAL; }
     if (params->fallback != 0) {
         set_error("the first-order fallback has no adjoint (run the adjoint with fallback = 0)");
+        return RG_ENOTSUP;
+    }
+    if (params->flattener != 0.0) {
+        set_error("the flattener has no adjoint (run the adjoint with flattener = 0)");
         return RG_ENOTSUP;
     }
     if ((const void *)gU_n == (const void *)gU_np1 || (const void *)gBf_n == (const void *)gBf_np1) {

@@ -374,6 +374,75 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void we
     if (active && g == 0) whi[z] = wmin;
 }
 
+// ---------------------------------------------------------------- flattener
+// Section VII.a applies a flattener on its coarse meshes and defers its
+// definition to other work.  Read here: a zone is flattened where the flow
+// compresses faster than a fraction kappa of the slowest signal speed around
+// it.  D = (1/V) sum_faces s_f (area-weighted face normal) . (v_zone +
+// v_neighbour) / 2 is the discrete divergence of the zone averages'
+// velocity, l0 = V^(1/3), c the smallest sqrt(gamma p / rho + B^2 / rho)
+// over the zone and its six face neighbours, and
+// eta = min(1, max(0, -(l0 D + kappa c) / (kappa c))).  Every WENO-AO
+// coefficient of the zone (all eight variables) is scaled by 1 - eta.  One
+// lane per reconstructed zone.
+__device__ __forceinline__ double zone_fast_max(const DevGeom &G, const double *__restrict__ U, i64 z, double gam,
+                                                double v[3])
+{
+    double u[8];
+    for (int k = 0; k < 8; k++) u[k] = U[k * G.Z + z];
+    const double ir = 1.0 / u[0];
+    v[0] = u[1] * ir;
+    v[1] = u[2] * ir;
+    v[2] = u[3] * ir;
+    const double a2 = gam * dev_pressure<double>(u, gam) * ir, b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+    return sqrt(fmax(a2, 0.0) + b2);
+}
+
+template <int P, class R>
+__global__ __launch_bounds__(256) void flatten_wc(DevGeom G, double gam, double kappa, const double *__restrict__ U,
+                                                  R *__restrict__ wc)
+{
+    using T = Tr<P>;
+    const int KR = G.Nr + 2;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)G.ncol * KR) return;
+    const int c = (int)(t / KR), k = G.g - 1 + (int)(t % KR);
+    const i64 z = (i64)c * G.K + k;
+    double vz[3], vn[3];
+    double cmin = zone_fast_max(G, U, z, gam, vz), div = 0.0;
+    for (int lf = 0; lf < 6; lf++) {
+        i64 f, zn;
+        double sg;
+        const double *nrm, *fw;
+        if (lf >= 4) {   // lower (outward -r) and upper radial faces
+            f = (i64)c * (G.K + 1) + k + (lf - 4);
+            zn = z + (lf == 4 ? -1 : 1);
+            sg = lf == 4 ? -1.0 : 1.0;
+            nrm = G.fnR + (i64)c * T::Q * 3;
+            fw = G.fwR + (i64)c * T::Q;
+        } else {
+            const int ae = G.col_ae[4 * c + lf], side = G.col_side[4 * c + lf];
+            f = G.NRF + (i64)ae * G.K + k;
+            zn = (i64)G.ae_col[2 * ae + 1 - side] * G.K + k;
+            sg = side == 0 ? 1.0 : -1.0;
+            nrm = G.fnA + (i64)ae * T::Q * 3;
+            fw = G.fwA + (i64)ae * T::Q;
+        }
+        double sa[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < T::Q; q++)
+            for (int i = 0; i < 3; i++) sa[i] += fw[q] * nrm[q * 3 + i];
+        cmin = fmin(cmin, zone_fast_max(G, U, zn, gam, vn));
+        const double A = G.area[f];
+        for (int i = 0; i < 3; i++) div += sg * A * sa[i] * 0.5 * (vz[i] + vn[i]);
+    }
+    div /= G.vol[z];
+    const double kc = kappa * cmin;
+    const double eta = fmin(1.0, fmax(0.0, -(cbrt(G.vol[z]) * div + kc) / kc));
+    if (eta == 0.0) return;
+    const R keep = R(1.0 - eta);
+    for (int j = 0; j < 8 * T::NC; j++) wc[(i64)j * G.Z + z] *= keep;
+}
+
 // ---------------------------------------------------------------- face nodal B
 // Limited nodal normal B on every face of the reconstructed shells (radial
 // faces kf in [g-1, g+Nr+1], angular faces in shells [g-1, g+Nr]), Section
@@ -1434,6 +1503,8 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
             G, Uo, wcoef, pick_host<R>(G.Pl, G.PlF), pick_host<R>(G.Ps, G.PsF), pick_host<R>(G.Qs, G.QsF),
             R(weno_eps(prm)), wr.nchunk, wr.nu, wr.nleft, g->whi);
     }
+    if (prm.flattener > 0.0)
+        flatten_wc<P, R><<<nblocks(nzr, 256), 256, 0, st>>>(G, gam, prm.flattener, Uo, wcoef);
     RG_LAUNCH_CHECK();
     sm.mark(2, st);
     {

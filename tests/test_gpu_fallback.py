@@ -113,6 +113,51 @@ def test_fallback_parity_blast_three_way_split_mesh(order):
     np.testing.assert_array_equal(flags, ref[2][mp.z])
 
 
+@pytest.mark.parametrize("order", [3, 4])
+def test_flattener_parity_blast(order):
+    """The flattener (kappa 0.1) on the 6 x 8^3 blast after three oracle steps
+    (the blast front compresses): one step with the flattener and the
+    fallback against the oracle."""
+    import paper_1905_02504_amd as R
+    say(f"[flattener] order {order}, 6x8^3 blast")
+    om = O.OracleMesh(8, 8, order=order, n_ghost=3)
+    lib = R.ShellMHD(8, 8, order, n_ghost=3, device=True)
+    mp = Mapping(lib, om)
+    prob = RI.blast_problem(p_in=1000.0, radius=0.3)
+    gam = prob["gamma"]
+    U1, B1 = blast_state(om, prob)
+    for _ in range(3):
+        U1, B1, _ = om.step(U1, B1, om.cfl_dt(U1, 0.15, gam), gamma=gam, fallback=True)
+    dt = om.cfl_dt(U1, 0.15, gam)
+    ref = om.step(U1, B1, dt, gamma=gam, fallback=True, flattener=0.1)
+    eta = om.last_eta
+    Ug, Bg, _ = lib.step(torch.from_numpy(mp.U(U1)).cuda(), torch.from_numpy(mp.Bf(B1)).cuda(), dt, gamma=gam,
+                         fallback=True, flattener=0.1)
+    flags = lib.fallback_zones().cpu().numpy()
+    inter = lib.interior()
+    eU = rel_err(Ug.cpu().numpy()[:, inter], mp.U(ref[0])[:, inter]).max()
+    eB = rel_err(Bg.cpu().numpy(), mp.Bf(ref[1])).max()
+    say(f"[flattener] zones flattened {(eta > 0).sum()} (fully {(eta == 1).sum()}); errors U {eU:.2e} Bf {eB:.2e}; "
+        f"fallback GPU {int(flags.sum())} oracle {int(ref[2].sum())}")
+    assert (eta > 0).sum() > 5
+    assert eU < TOL and eB < TOL
+    np.testing.assert_array_equal(flags, ref[2][mp.z])
+
+
+def test_adjoint_refuses_the_flattener():
+    import paper_1905_02504_amd as R
+    from paper_1905_02504_amd import _native as N
+    lib = R.ShellMHD(4, 3, 3, n_ghost=2, device=True)
+    U, Bf = lib.init_alfven(RI.alfven_problem())
+    U = torch.from_numpy(U).cuda()
+    Bf = torch.from_numpy(Bf).cuda()
+    gU, gB = torch.zeros_like(U), torch.zeros_like(Bf)
+    p = N.rg_step_params(5.0 / 3.0, 1e-3, 0.0, 0, 0, 0.0, 0, 0.1)
+    with pytest.raises(N.RGError, match="flattener"):
+        N.rg_step_adjoint(lib._geom, p, U.data_ptr(), Bf.data_ptr(), U.data_ptr(), Bf.data_ptr(),
+                          gU.data_ptr(), gB.data_ptr(), 0)
+
+
 def test_adjoint_refuses_the_fallback():
     import paper_1905_02504_amd as R
     from paper_1905_02504_amd import _native as N
