@@ -11,6 +11,12 @@
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
                  double flat_kappa, const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi,
                  double *dbgGam, unsigned char *fallback_zones, double *eta_out);
+/* the same step with complex state (scheme_cx.c): state arrays are
+ * interleaved (real, imaginary) pairs, i.e. C99 double complex */
+int rgo_run_step_cx(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+                    double flat_kappa, const double _Complex *U, const double _Complex *Bf, double _Complex *Uout,
+                    double _Complex *Bfout, double _Complex *dbgPhi, double _Complex *dbgGam,
+                    unsigned char *fallback_zones, double *eta_out);
 int rgo_run_weno_order(const rgo_mesh *m, int bc_kind, int flags, double weno_eps, const double *U, const double *Bf,
                        double *whi);
 int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
@@ -319,4 +325,13 @@ void rgo_init_blast(const rgo_mesh *m, const double *axis, const double *centre,
                     double p_in, double p, double B0, double gamma, double *U, double *Bf)
 {
     rgo_run_init_blast(m, axis, centre, radius, rho, p_in, p, B0, gamma, U, Bf);
+}
+
+/* one step with complex state (complex-step derivatives; see sreal.h) */
+int rgo_step_cx(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
+                double flat_kappa, const double _Complex *U, const double _Complex *Bf, double _Complex *Uout,
+                double _Complex *Bfout)
+{
+    return rgo_run_step_cx(m, gamma, dt, bc_kind, flags, weno_eps, flat_kappa, U, Bf, Uout, Bfout, NULL, NULL, NULL,
+                           NULL);
 }

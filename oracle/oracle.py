@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "init.c", "oracle.c"]
+_SOURCES = ["la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "scheme_cx.c", "init.c", "oracle.c"]
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -97,6 +97,10 @@ def lib():
         L.rgo_emf3x.argtypes = [_dp, _dp, _dp, _dp, C.c_double]
         L.rgo_init_blast.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _dp, _dp]
+        _cp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+        L.rgo_step_cx.restype = C.c_int
+        L.rgo_step_cx.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                  _cp, _cp, _cp, _cp]
         L.rgo_weno_rows.restype = C.c_int
         L.rgo_weno_rows.argtypes = [C.c_void_p, C.c_int, _dp]
         L.rgo_weno_detail.restype = C.c_int
@@ -253,6 +257,21 @@ class OracleMesh:
         self.last_fallback_round = fz.copy()
         fz = (fz > 0).astype(np.uint8)
         return out + (fz,) if fallback else out
+
+    def step_complex(self, U, Bf, dt, gamma=5.0 / 3.0, bc=0, flags=0, weno_eps=WENO_EPS, fallback=False,
+                     flattener=0.0):
+        """One step with complex state (complex128 arrays); the branches of the
+        step decide on real parts.  With U = U0 + i h dU, Bf = Bf0 + i h dB
+        (h about 1e-30) the imaginary parts of the outputs divided by h are the
+        step's directional derivative along (dU, dB)."""
+        U = np.ascontiguousarray(U, np.complex128); Bf = np.ascontiguousarray(Bf, np.complex128)
+        Uo = np.zeros_like(U); Bo = np.zeros_like(Bf)
+        if fallback:
+            flags |= FLAG_FALLBACK
+        rc = lib().rgo_step_cx(self._h, gamma, dt, bc, flags, weno_eps, float(flattener), U, Bf, Uo, Bo)
+        if rc != 0:
+            raise RuntimeError("oracle complex step failed")
+        return Uo, Bo
 
     def recon(self, U, Bf, z, pts, flags=0, weno_eps=WENO_EPS):
         pts = np.ascontiguousarray(pts, np.float64)

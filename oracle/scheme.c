@@ -29,12 +29,27 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include "sreal.h"
+
+#ifdef RGO_COMPLEX
+/* the complex build's own names for the functions other files call */
+#define phys_flux phys_flux_cx
+#define fast_speed fast_speed_cx
+#define hll_flux hll_flux_cx
+#define rgo_predict_element rgo_predict_element_cx
+#define rgo_emf4 rgo_emf4_cx
+#define rgo_emf3 rgo_emf3_cx
+#define rgo_run_step rgo_run_step_cx
+#endif
+
 #define WENO_GAMMA_HI 0.85
 #define FLAG_LINEAR_WEIGHTS 1
 #define FLAG_FALLBACK 2
 #define FALLBACK_ROUNDS 4
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static sreal dot3s(const sreal *a, const sreal *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static sreal dot3m(const sreal *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 static void cross3(const double *a, const double *b, double *c)
 {
@@ -43,22 +58,29 @@ static void cross3(const double *a, const double *b, double *c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-/* ---------------- ideal MHD (eq. 2.2, rationalised units) ---------------- */
-static double pressure(const double *U, double gamma)
+static void cross3m(const double *a, const sreal *b, sreal *c)
 {
-    double rho = U[IRHO];
-    double m2 = U[IMX] * U[IMX] + U[IMY] * U[IMY] + U[IMZ] * U[IMZ];
-    double B2 = U[IBX] * U[IBX] + U[IBY] * U[IBY] + U[IBZ] * U[IBZ];
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* ---------------- ideal MHD (eq. 2.2, rationalised units) ---------------- */
+static sreal pressure(const sreal *U, double gamma)
+{
+    sreal rho = U[IRHO];
+    sreal m2 = U[IMX] * U[IMX] + U[IMY] * U[IMY] + U[IMZ] * U[IMZ];
+    sreal B2 = U[IBX] * U[IBX] + U[IBY] * U[IBY] + U[IBZ] * U[IBZ];
     return (gamma - 1.0) * (U[IEN] - 0.5 * m2 / rho - 0.5 * B2);
 }
 
-void phys_flux(const double *U, double gamma, double F[3][NVAR])
+void phys_flux(const sreal *U, double gamma, sreal F[3][NVAR])
 {
-    double rho = U[IRHO];
-    double v[3] = {U[IMX] / rho, U[IMY] / rho, U[IMZ] / rho};
-    const double *B = &U[IBX];
-    double p = pressure(U, gamma);
-    double pt = p + 0.5 * dot3(B, B), vB = dot3(v, B);
+    sreal rho = U[IRHO];
+    sreal v[3] = {U[IMX] / rho, U[IMY] / rho, U[IMZ] / rho};
+    const sreal *B = &U[IBX];
+    sreal p = pressure(U, gamma);
+    sreal pt = p + 0.5 * dot3s(B, B), vB = dot3s(v, B);
     for (int d = 0; d < 3; d++) {
         F[d][IRHO] = U[IMX + d];
         for (int i = 0; i < 3; i++)
@@ -68,30 +90,30 @@ void phys_flux(const double *U, double gamma, double F[3][NVAR])
     }
 }
 
-double fast_speed(const double *U, double gamma, const double *n)
+sreal fast_speed(const sreal *U, double gamma, const double *n)
 {
-    double rho = U[IRHO];
-    const double *B = &U[IBX];
-    double a2 = gamma * pressure(U, gamma) / rho;
-    double b2 = dot3(B, B) / rho;
-    double bn = dot3(B, n);
-    double bn2 = bn * bn / rho;
-    double s = a2 + b2;
-    double disc = s * s - 4.0 * a2 * bn2;
-    if (disc < 0.0) disc = 0.0;
-    return sqrt(0.5 * (s + sqrt(disc)));
+    sreal rho = U[IRHO];
+    const sreal *B = &U[IBX];
+    sreal a2 = gamma * pressure(U, gamma) / rho;
+    sreal b2 = dot3s(B, B) / rho;
+    sreal bn = dot3m(B, n);
+    sreal bn2 = bn * bn / rho;
+    sreal s = a2 + b2;
+    sreal disc = s * s - 4.0 * a2 * bn2;
+    if (SRE(disc) < 0.0) disc = 0.0;
+    return s_sqrt(0.5 * (s + s_sqrt(disc)));
 }
 
 /* HLL flux along unit normal n (pointing from L to R) with Davis speeds */
-void hll_flux(const double *UL, const double *UR, const double *FnL, const double *FnR,
-              const double *n, double gamma, double *Fs)
+void hll_flux(const sreal *UL, const sreal *UR, const sreal *FnL, const sreal *FnR,
+              const double *n, double gamma, sreal *Fs)
 {
-    double vL = dot3(&UL[IMX], n) / UL[IRHO], vR = dot3(&UR[IMX], n) / UR[IRHO];
-    double cL = fast_speed(UL, gamma, n), cR = fast_speed(UR, gamma, n);
-    double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
-    if (SL >= 0.0) {
+    sreal vL = dot3m(&UL[IMX], n) / UL[IRHO], vR = dot3m(&UR[IMX], n) / UR[IRHO];
+    sreal cL = fast_speed(UL, gamma, n), cR = fast_speed(UR, gamma, n);
+    sreal SL = s_min(vL - cL, vR - cR), SR = s_max(vL + cL, vR + cR);
+    if (SRE(SL) >= 0.0) {
         for (int v = 0; v < NVAR; v++) Fs[v] = FnL[v];
-    } else if (SR <= 0.0) {
+    } else if (SRE(SR) <= 0.0) {
         for (int v = 0; v < NVAR; v++) Fs[v] = FnR[v];
     } else {
         for (int v = 0; v < NVAR; v++)
@@ -147,19 +169,19 @@ typedef struct {
     int deg, nc, nbx;       /* reconstruction degree p-1, # Taylor coeffs, # B coeffs per component */
     int te[40][3];          /* Taylor multi-indices 1..deg */
     int be[3][40][3];       /* divergence-free basis per component */
-    double *U;              /* state after the boundary fill, [8][nz] */
-    double *Bf;             /* [nf] */
+    sreal *U;               /* state after the boundary fill, [8][nz] */
+    sreal *Bf;              /* [nf] */
     char *recon;            /* zone is reconstructed */
-    double *wc;             /* nz * 8 * nc  WENO coefficients */
-    double *bface;          /* nf * Q  limited nodal normal B (eqs. 4.11-4.12), owner order */
-    double *bc;             /* nz * 3 * nbx divergence-free coefficients */
-    double *avgU, *avgF;    /* nz * N * 8, nz * N * 24 */
-    double *Phi;            /* nf * 8 */
-    double *Gam;            /* ne */
+    sreal *wc;              /* nz * 8 * nc  WENO coefficients */
+    sreal *bface;           /* nf * Q  limited nodal normal B (eqs. 4.11-4.12), owner order */
+    sreal *bc;              /* nz * 3 * nbx divergence-free coefficients */
+    sreal *avgU, *avgF;     /* nz * N * 8, nz * N * 24 */
+    sreal *Phi;             /* nf * 8 */
+    sreal *Gam;             /* ne */
     int first_order;        /* traces are the zones' states at t^n (the fallback's re-solve) */
     double *whi;            /* nz, or NULL: the smallest over the variables of w_hi / gamma_hi */
     double flat_kappa;      /* flattener threshold (0: off) */
-    double *eta;            /* nz flattener values, or NULL */
+    sreal *eta;             /* nz flattener values, or NULL */
     int dbg_z;              /* zone whose WENO-AO internals are recorded (test access), or -1 */
     double *dbg;            /* per variable: beta_hi, beta_s[7], weights[8], then the nc coefficients */
 } step_ws;
@@ -197,10 +219,10 @@ static void boundary_fill(step_ws *w)
 }
 
 /* ---- WENO-AO reconstruction of one zone (Section III) ---- */
-static double minmod(double a, double b)
+static sreal minmod(sreal a, sreal b)
 {
-    if (!(a * b > 0.0)) return 0.0;
-    return (a > 0 ? 1.0 : -1.0) * fmin(fabs(a), fabs(b));
+    if (!(SRE(a) * SRE(b) > 0.0)) return 0.0;
+    return (SRE(a) > 0 ? 1.0 : -1.0) * s_min(s_abs(a), s_abs(b));
 }
 
 /* ---- flattener (Section VII.a applies one to its coarse meshes and
@@ -215,32 +237,62 @@ static double minmod(double a, double b)
  * unless l0 D < -kappa c, one where l0 D <= -2 kappa c.  Every
  * reconstruction coefficient of the zone (all eight variables) is then
  * scaled by 1 - eta, so a fully flattened zone is first order. */
-static double zone_fast_max(const step_ws *w, int z)
+static sreal zone_fast_max(const step_ws *w, int z)
 {
-    double u[NVAR];
+    sreal u[NVAR];
     for (int v = 0; v < NVAR; v++) u[v] = w->U[(size_t)v * w->m->nz + z];
-    double a2 = w->gamma * pressure(u, w->gamma) / u[IRHO], b2 = dot3(&u[IBX], &u[IBX]) / u[IRHO];
-    return sqrt(fmax(a2, 0.0) + b2);
+    sreal a2 = w->gamma * pressure(u, w->gamma) / u[IRHO], b2 = dot3s(&u[IBX], &u[IBX]) / u[IRHO];
+    return s_sqrt(s_max(a2, 0.0) + b2);
 }
 
-static double flattener_eta(const step_ws *w, int z)
+static sreal flattener_eta(const step_ws *w, int z)
 {
     const rgo_mesh *m = w->m;
     const int nz = m->nz, Q = m->nq_face * m->nq_face;
-    double vz[3], div = 0.0, c = zone_fast_max(w, z);
+    sreal vz[3], div = 0.0, c = zone_fast_max(w, z);
     for (int i = 0; i < 3; i++) vz[i] = w->U[(size_t)(IMX + i) * nz + z] / w->U[(size_t)IRHO * nz + z];
     for (int lf = 0; lf < 6; lf++) {
         int f = m->zone_face[6 * z + lf], zn = m->zone_nbr[6 * z + lf];
-        double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0, va[3] = {0, 0, 0}, vn[3] = {0, 0, 0};
+        double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0, va[3] = {0, 0, 0};
+        sreal vn[3] = {0, 0, 0};
         for (int q = 0; q < Q; q++)
             for (int i = 0; i < 3; i++) va[i] += m->fdA[f * RGO_MAXQ + q] * m->fn[(f * RGO_MAXQ + q) * 3 + i];
         for (int i = 0; i < 3; i++) vn[i] = w->U[(size_t)(IMX + i) * nz + zn] / w->U[(size_t)IRHO * nz + zn];
         for (int i = 0; i < 3; i++) div += sg * va[i] * 0.5 * (vz[i] + vn[i]);
-        c = fmin(c, zone_fast_max(w, zn));
+        c = s_min(c, zone_fast_max(w, zn));
     }
     div /= m->vol[z];
-    const double kc = w->flat_kappa * c;
-    return fmin(1.0, fmax(0.0, -(m->len[z] * div + kc) / kc));
+    const sreal kc = w->flat_kappa * c;
+    return s_min(1.0, s_max(0.0, -(m->len[z] * div + kc) / kc));
+}
+
+/* least squares and LU solves with a real matrix and a state right-hand
+ * side: the complex build solves the real and imaginary parts in turn */
+static int s_lsq_qr(int m, int n, const double *A, const sreal *b, sreal *x)
+{
+#ifdef RGO_COMPLEX
+    double br[RGO_MAXST], bi[RGO_MAXST], xr[RGO_MAXST], xi[RGO_MAXST];
+    for (int i = 0; i < m; i++) { br[i] = creal(b[i]); bi[i] = cimag(b[i]); }
+    int rc = la_lsq_qr(m, n, A, br, xr) | la_lsq_qr(m, n, A, bi, xi);
+    for (int i = 0; i < n; i++) x[i] = xr[i] + I * xi[i];
+    return rc;
+#else
+    return la_lsq_qr(m, n, A, b, x);
+#endif
+}
+
+static int s_lu_solve(int n, const double *A, const sreal *b, sreal *x)
+{
+#ifdef RGO_COMPLEX
+    double *br = malloc(sizeof(double) * 4 * n), *bi = br + n, *xr = br + 2 * n, *xi = br + 3 * n;
+    for (int i = 0; i < n; i++) { br[i] = creal(b[i]); bi[i] = cimag(b[i]); }
+    int rc = la_lu_solve(n, A, br, xr) | la_lu_solve(n, A, bi, xi);
+    for (int i = 0; i < n; i++) x[i] = xr[i] + I * xi[i];
+    free(br);
+    return rc;
+#else
+    return la_lu_solve(n, A, b, x);
+#endif
 }
 
 /* large-stencil rows of zone z: volume average over each member zone j of
@@ -280,19 +332,20 @@ static void weno_zone(step_ws *w, int z)
 
     const int nsm = 7;
     const double gs = (1.0 - WENO_GAMMA_HI) / nsm;
-    double *coef = &w->wc[(size_t)z * NVAR * nc];
-    double *rhs = malloc(sizeof(double) * ns);
-    double chi[40], cs[7][3];
+    sreal *coef = &w->wc[(size_t)z * NVAR * nc];
+    sreal *rhs = malloc(sizeof(sreal) * ns);
+    sreal chi[40], cs[7][3];
     const cub_pt *c0 = &m->cub[(size_t)z * m->ncub];
     /* derivative multi-indices for the smoothness indicator */
     int de[40][3];
     int nde = taylor_list(w->deg, de);
     for (int v = 0; v < NVAR; v++) {
-        double u0 = w->U[(size_t)v * nz + z];
+        sreal u0 = w->U[(size_t)v * nz + z];
         for (int j = 0; j < ns; j++) rhs[j] = w->U[(size_t)v * nz + st[j]] - u0;
-        la_lsq_qr(ns, nc, A, rhs, chi);
+        s_lsq_qr(ns, nc, A, rhs, chi);
         for (int s = 0; s < nsm; s++) {
-            double As[6 * 3], bs[6];
+            double As[6 * 3];
+            sreal bs[6];
             int n = 0;
             for (int lf = 0; lf < 6; lf++) {
                 if (s > 0 && lf == ((s - 1) ^ 1)) continue;
@@ -300,20 +353,21 @@ static void weno_zone(step_ws *w, int z)
                 bs[n] = w->U[(size_t)v * nz + fnb[lf]] - u0;
                 n++;
             }
-            la_lsq_qr(n, 3, As, bs, cs[s]);
+            s_lsq_qr(n, 3, As, bs, cs[s]);
         }
-        double wgt[8], beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        sreal wgt[8], beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (w->flags & FLAG_LINEAR_WEIGHTS) {
             wgt[0] = WENO_GAMMA_HI;
             for (int s = 0; s < nsm; s++) wgt[1 + s] = gs;
         } else {
             /* smoothness: volume average over zone 0 of all squared derivatives */
-            double bhi = 0.0;
+            sreal bhi = 0.0;
             for (int p = 0; p < m->ncub; p++) {
-                double X[3], acc = 0.0;
+                double X[3];
+                sreal acc = 0.0;
                 to_X(m, z, c0[p].x, X);
                 for (int b = 0; b < nde; b++) {
-                    double dv = 0.0;
+                    sreal dv = 0.0;
                     for (int a = 0; a < nc; a++) dv += chi[a] * dmono_multi(w->te[a], de[b], X);
                     acc += dv * dv;
                 }
@@ -321,22 +375,22 @@ static void weno_zone(step_ws *w, int z)
             }
             bhi /= m->vol[z];
             beta[0] = bhi;
-            double tot = 0.0;
+            sreal tot = 0.0;
             const double eps = w->weno_eps;
             wgt[0] = WENO_GAMMA_HI / ((bhi + eps) * (bhi + eps));
             tot += wgt[0];
             for (int s = 0; s < nsm; s++) {
-                double b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
+                sreal b = cs[s][0] * cs[s][0] + cs[s][1] * cs[s][1] + cs[s][2] * cs[s][2];
                 beta[1 + s] = b;
                 wgt[1 + s] = gs / ((b + eps) * (b + eps));
                 tot += wgt[1 + s];
             }
             for (int s = 0; s <= nsm; s++) wgt[s] /= tot;
         }
-        if (w->whi && (v == 0 || wgt[0] / WENO_GAMMA_HI < w->whi[z])) w->whi[z] = wgt[0] / WENO_GAMMA_HI;
+        if (w->whi && (v == 0 || SRE(wgt[0]) / WENO_GAMMA_HI < w->whi[z])) w->whi[z] = SRE(wgt[0]) / WENO_GAMMA_HI;
         /* adaptive-order blend: (w_hi/g_hi)(P_hi - sum g_s P_s) + sum w_s P_s */
         for (int a = 0; a < nc; a++) {
-            double lin = 0.0, nl = 0.0;
+            sreal lin = 0.0, nl = 0.0;
             if (a < 3)
                 for (int s = 0; s < nsm; s++) { lin += gs * cs[s][a]; nl += wgt[1 + s] * cs[s][a]; }
             coef[v * nc + a] = wgt[0] / WENO_GAMMA_HI * (chi[a] - lin) + nl;
@@ -345,8 +399,8 @@ static void weno_zone(step_ws *w, int z)
             for (int a = 0; a < nc; a++) coef[v * nc + a] *= 1.0 - w->eta[z];
         if (w->dbg && z == w->dbg_z) {
             double *d = w->dbg + (size_t)v * (16 + nc);
-            for (int s = 0; s < 8; s++) { d[s] = beta[s]; d[8 + s] = wgt[s]; }
-            for (int a = 0; a < nc; a++) d[16 + a] = coef[v * nc + a];
+            for (int s = 0; s < 8; s++) { d[s] = SRE(beta[s]); d[8 + s] = SRE(wgt[s]); }
+            for (int a = 0; a < nc; a++) d[16 + a] = SRE(coef[v * nc + a]);
         }
     }
     free(A);
@@ -354,13 +408,13 @@ static void weno_zone(step_ws *w, int z)
 }
 
 /* WENO polynomial of zone z, variable v, at physical point x */
-static double weno_eval(const step_ws *w, int z, int v, const double *x)
+static sreal weno_eval(const step_ws *w, int z, int v, const double *x)
 {
     const rgo_mesh *m = w->m;
     double X[3];
     to_X(m, z, x, X);
-    double s = w->U[(size_t)v * m->nz + z];
-    const double *c = &w->wc[((size_t)z * NVAR + v) * w->nc];
+    sreal s = w->U[(size_t)v * m->nz + z];
+    const sreal *c = &w->wc[((size_t)z * NVAR + v) * w->nc];
     for (int a = 0; a < w->nc; a++) s += c[a] * (mono3(w->te[a], X) - mom_of(m, z, w->te[a]));
     return s;
 }
@@ -371,25 +425,25 @@ static void face_nodal_b(step_ws *w, int f)
     const rgo_mesh *m = w->m;
     const int Q = m->nq_face * m->nq_face;
     int zs[2] = {m->face_zone[2 * f], m->face_zone[2 * f + 1]};
-    double mean = w->Bf[f];
-    double *bn = &w->bface[(size_t)f * RGO_MAXQ];
+    sreal mean = w->Bf[f];
+    sreal *bn = &w->bface[(size_t)f * RGO_MAXQ];
     for (int q = 0; q < Q; q++) {
         const double *x = &m->fx[(f * RGO_MAXQ + q) * 3], *n = &m->fn[(f * RGO_MAXQ + q) * 3];
-        double d[2];
+        sreal d[2];
         int have[2];
         for (int s = 0; s < 2; s++) {
             have[s] = (zs[s] >= 0 && w->recon[zs[s]]);
             if (!have[s]) { d[s] = 0.0; continue; }
-            double B[3];
+            sreal B[3];
             for (int c = 0; c < 3; c++) B[c] = weno_eval(w, zs[s], IBX + c, x);
-            d[s] = dot3(B, n) - mean;
+            d[s] = dot3m(B, n) - mean;
         }
         /* a face with only one reconstructed neighbour takes that side's value */
         if (!have[0]) d[0] = d[1];
         if (!have[1]) d[1] = d[0];
         bn[q] = mean + minmod(d[0], d[1]);
     }
-    double s = 0.0;
+    sreal s = 0.0;
     for (int q = 0; q < Q; q++) s += m->fdA[f * RGO_MAXQ + q] / m->farea[f] * bn[q];
     for (int q = 0; q < Q; q++) bn[q] += mean - s;
 }
@@ -408,8 +462,10 @@ static int divfree_zone(step_ws *w, int z)
     int ndiv = w->nc;                     /* multi-indices 1 <= |mu| <= p-1 */
     int ncon = ndiv + 6;
     int nrow = nu + 6 * Q;
-    double *A = calloc((size_t)nrow * nu, sizeof(double)), *b = calloc(nrow, sizeof(double));
-    double *C = calloc((size_t)ncon * nu, sizeof(double)), *dcon = calloc(ncon, sizeof(double));
+    double *A = calloc((size_t)nrow * nu, sizeof(double));
+    sreal *b = calloc(nrow, sizeof(sreal));
+    double *C = calloc((size_t)ncon * nu, sizeof(double));
+    sreal *dcon = calloc(ncon, sizeof(sreal));
     /* closeness to the WENO-AO coefficients (eqs. 4.3, 4.6, 4.9) */
     for (int c = 0; c < 3; c++)
         for (int k = 0; k < nb; k++) {
@@ -457,14 +513,15 @@ static int divfree_zone(step_ws *w, int z)
         }
     /* KKT system [2 A^T A, C^T; C, 0] */
     int n = nu + ncon;
-    double *K = calloc((size_t)n * n, sizeof(double)), *rhs = calloc(n, sizeof(double)), *sol = malloc(sizeof(double) * n);
+    double *K = calloc((size_t)n * n, sizeof(double));
+    sreal *rhs = calloc(n, sizeof(sreal)), *sol = malloc(sizeof(sreal) * n);
     for (int i = 0; i < nu; i++) {
         for (int j = 0; j < nu; j++) {
             double s = 0.0;
             for (int r = 0; r < nrow; r++) s += A[(size_t)r * nu + i] * A[(size_t)r * nu + j];
             K[(size_t)i * n + j] = 2.0 * s;
         }
-        double s = 0.0;
+        sreal s = 0.0;
         for (int r = 0; r < nrow; r++) s += A[(size_t)r * nu + i] * b[r];
         rhs[i] = 2.0 * s;
     }
@@ -475,19 +532,19 @@ static int divfree_zone(step_ws *w, int z)
         }
         rhs[nu + i] = dcon[i];
     }
-    int rc = la_lu_solve(n, K, rhs, sol);
-    memcpy(&w->bc[(size_t)z * nu], sol, sizeof(double) * nu);
+    int rc = s_lu_solve(n, K, rhs, sol);
+    memcpy(&w->bc[(size_t)z * nu], sol, sizeof(sreal) * nu);
     free(A); free(b); free(C); free(dcon); free(K); free(rhs); free(sol);
     return rc;
 }
 
-static void divfree_eval(const step_ws *w, int z, const double *x, double *B)
+static void divfree_eval(const step_ws *w, int z, const double *x, sreal *B)
 {
     double X[3];
     to_X(w->m, z, x, X);
-    const double *c = &w->bc[(size_t)z * 3 * w->nbx];
+    const sreal *c = &w->bc[(size_t)z * 3 * w->nbx];
     for (int i = 0; i < 3; i++) {
-        double s = 0.0;
+        sreal s = 0.0;
         for (int k = 0; k < w->nbx; k++) s += c[i * w->nbx + k] * bbasis(w, z, w->be[i][k], X);
         B[i] = s;
     }
@@ -495,13 +552,13 @@ static void divfree_eval(const step_ws *w, int z, const double *x, double *B)
 
 /* ---- ADER-CG predictor on one element, eqs. (5.22)-(5.29) ---- */
 int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const double *J, const double *met,
-                        const double *Ua, double *Ulev, double *avgU, double *avgF)
+                        const sreal *Ua, sreal *Ulev, sreal *avgU, sreal *avgF)
 {
     const int N = r->N, M = r->M, E = (M - 1) * N;
-    double *U0 = malloc(sizeof(double) * N * NVAR), *U1 = malloc(sizeof(double) * E * NVAR);
-    double *F0 = malloc(sizeof(double) * 3 * N * NVAR), *F1 = malloc(sizeof(double) * 3 * E * NVAR);
-    double *Un = malloc(sizeof(double) * E * NVAR);
-    double Fp[3][NVAR], u[NVAR];
+    sreal *U0 = malloc(sizeof(sreal) * N * NVAR), *U1 = malloc(sizeof(sreal) * E * NVAR);
+    sreal *F0 = malloc(sizeof(sreal) * 3 * N * NVAR), *F1 = malloc(sizeof(sreal) * 3 * E * NVAR);
+    sreal *Un = malloc(sizeof(sreal) * E * NVAR);
+    sreal Fp[3][NVAR], u[NVAR];
     for (int i = 0; i < N; i++)
         for (int v = 0; v < NVAR; v++) U0[i * NVAR + v] = J[i] * Ua[i * NVAR + v];
     /* nodal fluxes in mapped form, eq. (5.23) with the zone's own metrics */
@@ -512,7 +569,7 @@ int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const doubl
         phys_flux(u, gamma, Fp);                                                              \
         for (int d = 0; d < 3; d++)                                                           \
             for (int v = 0; v < NVAR; v++) {                                                  \
-                double s = 0.0;                                                               \
+                sreal s = 0.0;                                                                \
                 for (int nn = 0; nn < 3; nn++) s += met[ii * 9 + d * 3 + nn] * Fp[nn][v];     \
                 (Fout)[((size_t)d * (stride) + (i)) * NVAR + v] = dt * s;                     \
             }                                                                                 \
@@ -525,7 +582,7 @@ int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const doubl
         for (int i = 0; i < E; i++) NODAL_FLUX(U1, i, F1, E);
         for (int i = 0; i < E; i++)
             for (int v = 0; v < NVAR; v++) {
-                double s = 0.0;
+                sreal s = 0.0;
                 for (int j = 0; j < N; j++) {
                     s += r->Kt0[i * N + j] * U0[j * NVAR + v];
                     for (int d = 0; d < 3; d++) s -= r->Kd0[d][i * N + j] * F0[((size_t)d * N + j) * NVAR + v];
@@ -534,11 +591,11 @@ int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const doubl
                     for (int d = 0; d < 3; d++) s -= r->Kd[d][i * E + j] * F1[((size_t)d * E + j) * NVAR + v];
                 Un[i * NVAR + v] = s;
             }
-        memcpy(U1, Un, sizeof(double) * E * NVAR);
+        memcpy(U1, Un, sizeof(sreal) * E * NVAR);
     }
     if (Ulev) {
-        memcpy(Ulev, U0, sizeof(double) * N * NVAR);
-        memcpy(Ulev + N * NVAR, U1, sizeof(double) * E * NVAR);
+        memcpy(Ulev, U0, sizeof(sreal) * N * NVAR);
+        memcpy(Ulev + N * NVAR, U1, sizeof(sreal) * E * NVAR);
     }
     /* time averages over the Gauss levels (step 10 of Section V.d) */
     for (int i = 0; i < N; i++) {
@@ -561,7 +618,7 @@ static void predictor_zone(step_ws *w, int z)
 {
     const rgo_mesh *m = w->m;
     const int N = m->ref.N;
-    double *Ua = malloc(sizeof(double) * N * NVAR);
+    sreal *Ua = malloc(sizeof(sreal) * N * NVAR);
     for (int i = 0; i < N; i++) {
         const double *x = &m->nodex[((size_t)z * N + i) * 3];
         for (int v = 0; v < IBX; v++) Ua[i * NVAR + v] = weno_eval(w, z, v, x);
@@ -574,7 +631,7 @@ static void predictor_zone(step_ws *w, int z)
 
 /* Conserved state of zone z at t^n: its eight averages after the boundary
  * fill (zone B as carried, consistent with the total energy) */
-static void zone_state(const step_ws *w, int z, double *U)
+static void zone_state(const step_ws *w, int z, sreal *U)
 {
     const int nz = w->m->nz;
     for (int v = 0; v < NVAR; v++) U[v] = w->U[(size_t)v * nz + z];
@@ -583,7 +640,7 @@ static void zone_state(const step_ws *w, int z, double *U)
 /* time-averaged state and flux of zone z at reference point xi; in the
  * re-solve of the first-order fallback, the zone's conserved state at t^n
  * and the physical flux of that state instead */
-static void trace(const step_ws *w, int z, const double *xi, double *U, double F[3][NVAR])
+static void trace(const step_ws *w, int z, const double *xi, sreal *U, sreal F[3][NVAR])
 {
     const rgo_mesh *m = w->m;
     const int N = m->ref.N;
@@ -596,7 +653,7 @@ static void trace(const step_ws *w, int z, const double *xi, double *U, double F
     for (int l = 0; l < N; l++) {
         double p = refel_psi(&m->ref, l, xi);
         if (p == 0.0) continue;
-        const double *au = &w->avgU[((size_t)z * N + l) * NVAR], *af = &w->avgF[((size_t)z * N + l) * 3 * NVAR];
+        const sreal *au = &w->avgU[((size_t)z * N + l) * NVAR], *af = &w->avgF[((size_t)z * N + l) * 3 * NVAR];
         for (int v = 0; v < NVAR; v++) U[v] += p * au[v];
         for (int d = 0; d < 3; d++)
             for (int v = 0; v < NVAR; v++) F[d][v] += p * af[d * NVAR + v];
@@ -610,11 +667,12 @@ static void face_flux(step_ws *w, int f)
     const int Q = m->nq_face * m->nq_face;
     int zL = m->face_zone[2 * f], zR = m->face_zone[2 * f + 1];
     int lL = m->face_lf[2 * f], lR = m->face_lf[2 * f + 1];
-    double *Phi = &w->Phi[(size_t)f * NVAR];
+    sreal *Phi = &w->Phi[(size_t)f * NVAR];
     for (int v = 0; v < NVAR; v++) Phi[v] = 0.0;
     for (int q = 0; q < Q; q++) {
         const double *n = &m->fn[(f * RGO_MAXQ + q) * 3];
-        double xi[3], UL[NVAR], UR[NVAR], FL[3][NVAR], FR[3][NVAR], FnL[NVAR], FnR[NVAR], Fs[NVAR];
+        double xi[3];
+        sreal UL[NVAR], UR[NVAR], FL[3][NVAR], FR[3][NVAR], FnL[NVAR], FnR[NVAR], Fs[NVAR];
         face_ref_point(m, lL, q, xi);
         trace(w, zL, xi, UL, FL);
         face_ref_point(m, lR, m->face_perm[f * RGO_MAXQ + q], xi);
@@ -630,8 +688,8 @@ static void face_flux(step_ws *w, int f)
 
 /* ---- multidimensional HLL electric field at one edge point ---- */
 /* states in counter-clockwise order about t (SW, SE, NE, NW); E[s] = time-averaged E vector */
-double rgo_emf4(const double U[4][NVAR], const double E[4][3], const double cen[4][3], const double *t,
-                double gamma)
+sreal rgo_emf4(const sreal U[4][NVAR], const sreal E[4][3], const double cen[4][3], const double *t,
+               double gamma)
 {
     /* frame: directions from the zone centroids, orthonormalised symmetrically */
     double u[3], v[3];
@@ -649,36 +707,37 @@ double rgo_emf4(const double U[4][NVAR], const double E[4][3], const double cen[
     cross3(t, b, bp);
     const double h = sqrt(0.5);
     for (int i = 0; i < 3; i++) { e1[i] = h * (b[i] - bp[i]); e2[i] = h * (b[i] + bp[i]); }
-    double ap1 = 0.0, am1 = 0.0, ap2 = 0.0, am2 = 0.0, Et[4], B1[4], B2[4];
+    sreal ap1 = 0.0, am1 = 0.0, ap2 = 0.0, am2 = 0.0, Et[4], B1[4], B2[4];
     for (int s = 0; s < 4; s++) {
-        double v1 = dot3(&U[s][IMX], e1) / U[s][IRHO], v2 = dot3(&U[s][IMX], e2) / U[s][IRHO];
-        double c1 = fast_speed(U[s], gamma, e1), c2 = fast_speed(U[s], gamma, e2);
-        ap1 = fmax(ap1, v1 + c1); am1 = fmax(am1, -(v1 - c1));
-        ap2 = fmax(ap2, v2 + c2); am2 = fmax(am2, -(v2 - c2));
-        Et[s] = dot3(E[s], t);
-        B1[s] = dot3(&U[s][IBX], e1);
-        B2[s] = dot3(&U[s][IBX], e2);
+        sreal v1 = dot3m(&U[s][IMX], e1) / U[s][IRHO], v2 = dot3m(&U[s][IMX], e2) / U[s][IRHO];
+        sreal c1 = fast_speed(U[s], gamma, e1), c2 = fast_speed(U[s], gamma, e2);
+        ap1 = s_max(ap1, v1 + c1); am1 = s_max(am1, -(v1 - c1));
+        ap2 = s_max(ap2, v2 + c2); am2 = s_max(am2, -(v2 - c2));
+        Et[s] = dot3m(E[s], t);
+        B1[s] = dot3m(&U[s][IBX], e1);
+        B2[s] = dot3m(&U[s][IBX], e2);
     }
     /* SW=0, SE=1, NE=2, NW=3 */
-    double den = (ap1 + am1) * (ap2 + am2);
-    double Es = (ap1 * ap2 * Et[0] + ap1 * am2 * Et[3] + am1 * ap2 * Et[1] + am1 * am2 * Et[2]) / den;
+    sreal den = (ap1 + am1) * (ap2 + am2);
+    sreal Es = (ap1 * ap2 * Et[0] + ap1 * am2 * Et[3] + am1 * ap2 * Et[1] + am1 * am2 * Et[2]) / den;
     Es += ap1 * am1 * (0.5 * (B2[1] + B2[2]) - 0.5 * (B2[0] + B2[3])) / (ap1 + am1);
     Es -= ap2 * am2 * (0.5 * (B1[2] + B1[3]) - 0.5 * (B1[0] + B1[1])) / (ap2 + am2);
     return Es;
 }
 
 /* three zones about an edge: mean of the 1-D HLL induction fluxes of the three faces */
-double rgo_emf3(const double U[3][NVAR], const double E[3][3], const double n[3][3], const double *t,
-                double gamma)
+sreal rgo_emf3(const sreal U[3][NVAR], const sreal E[3][3], const double n[3][3], const double *t,
+               double gamma)
 {
-    double acc = 0.0;
+    sreal acc = 0.0;
     for (int s = 0; s < 3; s++) {
         int s2 = (s + 1) % 3;
         const double *nn = n[s];
-        double FL[NVAR] = {0}, FR[NVAR] = {0}, Fs[NVAR], tn[3];
+        sreal FL[NVAR] = {0}, FR[NVAR] = {0}, Fs[NVAR];
+        double tn[3];
         /* induction flux n x E for B, zero for the fluid rows (they do not enter) */
-        cross3(nn, E[s], &FL[IBX]);
-        cross3(nn, E[s2], &FR[IBX]);
+        cross3m(nn, E[s], &FL[IBX]);
+        cross3m(nn, E[s2], &FR[IBX]);
         hll_flux(U[s], U[s2], FL, FR, nn, gamma, Fs);
         cross3(t, nn, tn);
         acc += -(Fs[IBX] * tn[0] + Fs[IBY] * tn[1] + Fs[IBZ] * tn[2]);
@@ -691,9 +750,10 @@ static void edge_emf(step_ws *w, int e)
     const rgo_mesh *m = w->m;
     const double simpson[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
     int nze = m->edge_nz[e];
-    double G = 0.0;
+    sreal G = 0.0;
     for (int p = 0; p < 3; p++) {
-        double s = 0.5 * p, U[4][NVAR], E[4][3], cen[4][3], F[3][NVAR];
+        double s = 0.5 * p, cen[4][3];
+        sreal U[4][NVAR], E[4][3], F[3][NVAR];
         const double *t = &m->et[e * 9 + p * 3];
         for (int k = 0; k < nze; k++) {
             int z = m->edge_zone[4 * e + k], le = m->edge_le[4 * e + k], rev = m->edge_rev[4 * e + k];
@@ -706,7 +766,7 @@ static void edge_emf(step_ws *w, int e)
             E[k][2] = F[1][IBX];
             memcpy(cen[k], &m->cen[3 * z], 24);
         }
-        double Es;
+        sreal Es;
         if (nze == 4) {
             Es = rgo_emf4(U, E, cen, t, w->gamma);
         } else {
@@ -729,7 +789,7 @@ static void edge_emf(step_ws *w, int e)
                 double sg = dot3(nrm[k], d) > 0 ? 1.0 : -1.0, nn = sqrt(dot3(nrm[k], nrm[k]));
                 for (int i = 0; i < 3; i++) nrm[k][i] *= sg / nn;
             }
-            Es = rgo_emf3((const double(*)[NVAR])U, (const double(*)[3])E, (const double(*)[3])nrm, t, w->gamma);
+            Es = rgo_emf3((const sreal(*)[NVAR])U, (const sreal(*)[3])E, (const double(*)[3])nrm, t, w->gamma);
         }
         G += simpson[p] * Es * m->edl[e * 3 + p];
     }
@@ -741,19 +801,19 @@ static void edge_emf(step_ws *w, int e)
  * (step 10 of Section IV.b), or, for a zone of the first-order fallback
  * (own != 0), from its own conserved B, so that its update is the
  * first-order finite-volume scheme on its eight averages */
-static void update_zone(const step_ws *w, int z, int own, double *u)
+static void update_zone(const step_ws *w, int z, int own, sreal *u)
 {
     const rgo_mesh *m = w->m;
     const int nz = m->nz;
-    double acc[NVAR] = {0};
+    sreal acc[NVAR] = {0};
     for (int lf = 0; lf < 6; lf++) {
         int f = m->zone_face[6 * z + lf];
         double sg = (m->face_zone[2 * f] == z) ? 1.0 : -1.0;
         for (int v = 0; v < NVAR; v++) acc[v] += sg * w->Phi[(size_t)f * NVAR + v];
     }
-    const double *bcz = &w->bc[(size_t)z * 3 * w->nbx];
+    const sreal *bcz = &w->bc[(size_t)z * 3 * w->nbx];
     for (int v = 0; v < NVAR; v++) {
-        double base = (v >= IBX && !own) ? bcz[(v - IBX) * w->nbx] : w->U[(size_t)v * nz + z];
+        sreal base = (v >= IBX && !own) ? bcz[(v - IBX) * w->nbx] : w->U[(size_t)v * nz + z];
         u[v] = base - w->dt / m->vol[z] * acc[v];
     }
 }
@@ -780,8 +840,8 @@ static void setup_bases(step_ws *w)
 }
 
 int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int flags, double weno_eps,
-                 double flat_kappa, const double *U, const double *Bf, double *Uout, double *Bfout, double *dbgPhi,
-                 double *dbgGam, unsigned char *fallback_zones, double *eta_out)
+                 double flat_kappa, const sreal *U, const sreal *Bf, sreal *Uout, sreal *Bfout, sreal *dbgPhi,
+                 sreal *dbgGam, unsigned char *fallback_zones, double *eta_out)
 {
     step_ws w;
     memset(&w, 0, sizeof(w));
@@ -792,10 +852,10 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     w.weno_eps = weno_eps;
     setup_bases(&w);
     const int nz = m->nz, nf = m->nf, ne = m->ne, N = m->ref.N, g = m->n_ghost, Nr = m->n_rad;
-    w.U = malloc(sizeof(double) * NVAR * nz);
-    w.Bf = malloc(sizeof(double) * nf);
-    memcpy(w.U, U, sizeof(double) * NVAR * nz);
-    memcpy(w.Bf, Bf, sizeof(double) * nf);
+    w.U = malloc(sizeof(sreal) * NVAR * nz);
+    w.Bf = malloc(sizeof(sreal) * nf);
+    memcpy(w.U, U, sizeof(sreal) * NVAR * nz);
+    memcpy(w.Bf, Bf, sizeof(sreal) * nf);
     if (bc_kind == 0) boundary_fill(&w);
 
     w.recon = calloc(nz, 1);
@@ -805,19 +865,20 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
     }
     if (flat_kappa > 0.0) {
         w.flat_kappa = flat_kappa;
-        w.eta = calloc(nz, sizeof(double));
+        w.eta = calloc(nz, sizeof(sreal));
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; z++)
             if (w.recon[z]) w.eta[z] = flattener_eta(&w, z);
-        if (eta_out) memcpy(eta_out, w.eta, sizeof(double) * nz);
+        if (eta_out)
+            for (int z = 0; z < nz; z++) eta_out[z] = SRE(w.eta[z]);
     }
-    w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(double));
-    w.bface = calloc((size_t)nf * RGO_MAXQ, sizeof(double));
-    w.bc = calloc((size_t)nz * 3 * w.nbx, sizeof(double));
-    w.avgU = calloc((size_t)nz * N * NVAR, sizeof(double));
-    w.avgF = calloc((size_t)nz * N * 3 * NVAR, sizeof(double));
-    w.Phi = calloc((size_t)nf * NVAR, sizeof(double));
-    w.Gam = calloc(ne, sizeof(double));
+    w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(sreal));
+    w.bface = calloc((size_t)nf * RGO_MAXQ, sizeof(sreal));
+    w.bc = calloc((size_t)nz * 3 * w.nbx, sizeof(sreal));
+    w.avgU = calloc((size_t)nz * N * NVAR, sizeof(sreal));
+    w.avgF = calloc((size_t)nz * N * 3 * NVAR, sizeof(sreal));
+    w.Phi = calloc((size_t)nf * NVAR, sizeof(sreal));
+    w.Gam = calloc(ne, sizeof(sreal));
 
 #pragma omp parallel for schedule(dynamic, 8)
     for (int z = 0; z < nz; z++)
@@ -876,9 +937,9 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
             int added = 0;
             for (int z = 0; z < nz; z++) {
                 if (!upd[z] || bad[z]) continue;
-                double u[NVAR];
+                sreal u[NVAR];
                 update_zone(&w, z, 0, u);
-                if (u[IRHO] > 0.0 && pressure(u, gamma) > 0.0) continue;
+                if (SRE(u[IRHO]) > 0.0 && SRE(pressure(u, gamma)) > 0.0) continue;
                 bad[z] = (char)(round + 1);   /* the round that flagged it, 1-based */
                 added = 1;
                 for (int lf = 0; lf < 6; lf++) {
@@ -903,30 +964,33 @@ int rgo_run_step(const rgo_mesh *m, double gamma, double dt, int bc_kind, int fl
 
     /* finite-volume update of the eight zone averages, zone B taken from the
      * divergence-free reconstruction (step 10 of Section IV.b) */
-    memcpy(Uout, w.U, sizeof(double) * NVAR * nz);
+    memcpy(Uout, w.U, sizeof(sreal) * NVAR * nz);
     for (int z = 0; z < nz; z++) {
         if (!upd[z]) continue;
-        double u[NVAR];
+        sreal u[NVAR];
         update_zone(&w, z, bad[z], u);
         for (int v = 0; v < NVAR; v++) Uout[(size_t)v * nz + z] = u[v];
     }
     free(bad);
     /* constrained transport: Faraday's law on each face (eqs. 2.5-2.6) */
-    memcpy(Bfout, w.Bf, sizeof(double) * nf);
+    memcpy(Bfout, w.Bf, sizeof(sreal) * nf);
     for (int f = 0; f < nf; f++) {
         if (!fupd[f]) continue;
-        double s = 0.0;
+        sreal s = 0.0;
         for (int k = 0; k < 4; k++) s += m->face_esign[4 * f + k] * w.Gam[m->face_edges[4 * f + k]];
         Bfout[f] = w.Bf[f] - dt / m->farea[f] * s;
     }
-    if (dbgPhi) memcpy(dbgPhi, w.Phi, sizeof(double) * nf * NVAR);
-    if (dbgGam) memcpy(dbgGam, w.Gam, sizeof(double) * ne);
+    if (dbgPhi) memcpy(dbgPhi, w.Phi, sizeof(sreal) * nf * NVAR);
+    if (dbgGam) memcpy(dbgGam, w.Gam, sizeof(sreal) * ne);
 
     free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc);
     free(w.avgU); free(w.avgF); free(w.Phi); free(w.Gam); free(w.eta);
     free(fneed); free(upd); free(fupd); free(eupd);
     return fail ? -1 : 0;
 }
+
+#ifndef RGO_COMPLEX
+/* test access to single parts of the step (the real oracle only) */
 
 /* reconstructed fields of one zone at arbitrary points (test access) */
 int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U, const double *Bf, int z,
@@ -948,10 +1012,19 @@ int rgo_run_recon(const rgo_mesh *m, int flags, double weno_eps, const double *U
     w.wc = calloc((size_t)nz * NVAR * w.nc, sizeof(double));
     w.bface = calloc((size_t)nf * RGO_MAXQ, sizeof(double));
     w.bc = calloc((size_t)nz * 3 * w.nbx, sizeof(double));
-    /* the zone and its face neighbours */
+    /* the zone and its face neighbours (each must have a full stencil) */
     int list[7];
     list[0] = z;
     for (int lf = 0; lf < 6; lf++) list[1 + lf] = m->zone_nbr[6 * z + lf];
+    int edge = 0;
+    for (int i = 0; i < 7 && !edge; i++) {
+        edge = list[i] < 0;
+        for (int lf = 0; lf < 6 && !edge; lf++) edge = m->zone_nbr[6 * list[i] + lf] < 0;
+    }
+    if (edge) {
+        free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc);
+        return -1;
+    }
     for (int i = 0; i < 7; i++) {
         w.recon[list[i]] = 1;
         weno_zone(&w, list[i]);
@@ -989,6 +1062,14 @@ int rgo_run_divfree_coeffs(const rgo_mesh *m, int flags, double weno_eps, const 
     int list[7];
     list[0] = z;
     for (int lf = 0; lf < 6; lf++) list[1 + lf] = m->zone_nbr[6 * z + lf];
+    for (int i = 0; i < 7; i++)
+        if (list[i] < 0) { free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc); return -1; }
+    for (int i = 0; i < 7; i++)
+        for (int lf = 0; lf < 6; lf++)
+            if (m->zone_nbr[6 * list[i] + lf] < 0) {
+                free(w.U); free(w.Bf); free(w.recon); free(w.wc); free(w.bface); free(w.bc);
+                return -1;
+            }
     for (int i = 0; i < 7; i++) {
         w.recon[list[i]] = 1;
         weno_zone(&w, list[i]);
@@ -1105,3 +1186,5 @@ double rgo_run_cfl(const rgo_mesh *m, double gamma, double cfl, const double *U)
     }
     return dtmin;
 }
+
+#endif /* RGO_COMPLEX */

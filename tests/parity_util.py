@@ -48,3 +48,24 @@ def rel_err(x, ref):
     scale = np.maximum(np.abs(ref), rms)
     scale = np.where(scale == 0, 1.0, scale)
     return np.abs(x - ref) / scale
+
+
+def roughen(U_h, Bf_h, gam, amp=0.2, seed=4242):
+    """per-zone noise of relative size amp in rho, p and of size amp in v and B
+    (primitive variables; total energy rebuilt), and amp x rms noise in face B"""
+    rng = np.random.default_rng(seed)
+    U = U_h.copy()
+    rho = U[0]
+    v = U[1:4] / rho
+    B = U[5:8]
+    p = (gam - 1) * (U[4] - 0.5 * rho * (v * v).sum(0) - 0.5 * (B * B).sum(0))
+    rho = rho * (1 + amp * rng.uniform(-1, 1, rho.shape))
+    p = p * (1 + amp * rng.uniform(-1, 1, p.shape))
+    v = v + amp * rng.uniform(-1, 1, v.shape)
+    B = B + amp * rng.uniform(-1, 1, B.shape)
+    U[0] = rho
+    U[1:4] = rho * v
+    U[5:8] = B
+    U[4] = p / (gam - 1) + 0.5 * rho * (v * v).sum(0) + 0.5 * (B * B).sum(0)
+    Bf = Bf_h + amp * np.sqrt((Bf_h ** 2).mean()) * rng.uniform(-1, 1, Bf_h.shape)
+    return U, Bf

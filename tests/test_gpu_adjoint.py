@@ -26,6 +26,7 @@ import numpy as np
 import pytest
 
 import rg_inputs as RI
+from tests.parity_util import roughen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -37,30 +38,6 @@ TOL = 1e-6
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
-
-
-ROUGH = 0.2
-
-
-def roughen(U_h, Bf_h, gam, amp=ROUGH, seed=4242):
-    """per-zone noise of relative size amp in rho, p and of size amp in v and B
-    (primitive variables; total energy rebuilt), and amp x rms noise in face B"""
-    rng = np.random.default_rng(seed)
-    U = U_h.copy()
-    rho = U[0]
-    v = U[1:4] / rho
-    B = U[5:8]
-    p = (gam - 1) * (U[4] - 0.5 * rho * (v * v).sum(0) - 0.5 * (B * B).sum(0))
-    rho = rho * (1 + amp * rng.uniform(-1, 1, rho.shape))
-    p = p * (1 + amp * rng.uniform(-1, 1, p.shape))
-    v = v + amp * rng.uniform(-1, 1, v.shape)
-    B = B + amp * rng.uniform(-1, 1, B.shape)
-    U[0] = rho
-    U[1:4] = rho * v
-    U[5:8] = B
-    U[4] = p / (gam - 1) + 0.5 * rho * (v * v).sum(0) + 0.5 * (B * B).sum(0)
-    Bf = Bf_h + amp * np.sqrt((Bf_h ** 2).mean()) * rng.uniform(-1, 1, Bf_h.shape)
-    return U, Bf
 
 
 def make_state(lib, order, problem, om=None):
@@ -196,6 +173,107 @@ def test_adjoint_against_oracle_differences():
         err = fd_check(a, oracle_fd)
         say(f"[adjoint] direction {d}: adjoint {a:.12e}, relative difference from the oracle's quotient {err:.2e}")
         assert err < TOL
+
+
+def _oracle_twin(n_ang, n_rad, order):
+    """library and oracle on the same mesh, a rough state in both numberings"""
+    import paper_1905_02504_amd as R
+    from oracle import oracle as O
+    from tests.parity_util import Mapping
+    om = O.OracleMesh(n_ang, n_rad, order=order, n_ghost=order - 1)
+    lib = R.ShellMHD(n_ang, n_rad, order, n_ghost=order - 1)
+    mp = Mapping(lib, om)
+    U_l, Bf_l, gam = make_state(lib, order, "rough")
+    U_l = U_l.cpu().numpy()
+    Bf_l = Bf_l.cpu().numpy()
+    Uo = np.zeros_like(U_l)
+    Uo[:, mp.z] = U_l
+    Bfo = np.zeros_like(Bf_l)
+    Bfo[mp.f] = mp.fs * Bf_l
+    return om, lib, mp, Uo, Bfo, gam
+
+
+CS_H = 1e-30       # complex-step size
+CS_TOL = 1e-9      # adjoint against the oracle's exact directional derivative
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_adjoint_against_oracle_complex_step(order):
+    """<gU, dU> + <gBf, dBf> from the library's adjoint against the oracle's
+    own derivative of its step: the complex step (C99 complex state through
+    the whole oracle step, branches on real parts; oracle/sreal.h), which
+    is exact to rounding, so the bar is 1e-9 relative, for 32 seeded global
+    directions on 6 x 8^3 zones."""
+    say(f"[adjoint] oracle complex step, order {order}, 6x8x8x8, 32 directions")
+    om, lib, mp, Uo, Bfo, gam = _oracle_twin(8, 8, order)
+    dt = om.cfl_dt(Uo, 0.4, gam)
+    U = torch.from_numpy(mp.U(Uo)).cuda()
+    Bf = torch.from_numpy(mp.Bf(Bfo)).cuda()
+    rng = np.random.default_rng(15)
+    gU1_h = rng.uniform(-1, 1, size=(8, lib.nz))
+    gB1_h = rng.uniform(-1, 1, size=lib.nf)
+    gU, gB = lib.step_adjoint(U, Bf, torch.from_numpy(gU1_h).cuda(), torch.from_numpy(gB1_h).cuda(), dt, gamma=gam)
+    gU = gU.cpu().numpy()
+    gB = gB.cpu().numpy()
+    worst = 0.0
+    for d in range(32):
+        r = np.random.default_rng(900 + d)
+        dUo = r.uniform(-1, 1, size=Uo.shape) * np.sqrt((Uo ** 2).mean(1, keepdims=True))
+        dBo = r.uniform(-1, 1, size=Bfo.shape) * np.sqrt((Bfo ** 2).mean())
+        Uc, Bc = om.step_complex(Uo + 1j * CS_H * dUo, Bfo + 1j * CS_H * dBo, dt, gamma=gam)
+        b = float((mp.U(Uc.imag / CS_H) * gU1_h).sum() + (mp.Bf(Bc.imag / CS_H) * gB1_h).sum())
+        a = float((gU * mp.U(dUo)).sum() + (gB * mp.Bf(dBo)).sum())
+        err = rel(a, b)
+        worst = max(worst, err)
+        if d % 8 == 0 or err > CS_TOL:
+            say(f"[adjoint] direction {d}: adjoint {a:.15e}, oracle complex step {b:.15e}, relative {err:.2e}")
+    say(f"[adjoint] worst relative difference over 32 directions {worst:.2e}")
+    assert worst < CS_TOL
+
+
+def test_rollout_gradient_against_oracle_complex_step():
+    """The differentiation workload's loss (the outer four shells' |V|
+    [(rho - rho*)^2 + (|B|^2 - b*)^2] after 4 third-order steps, dt fixed)
+    on 6 x 8^3 zones: the library's autograd gradient (one checkpoint per
+    step, rg_step_adjoint in backward) against the oracle's complex-step
+    derivative of the same 4-step loss, along 8 seeded global directions in
+    the initial conserved variables and face B; bar 1e-9 of sum |g d|."""
+    say("[adjoint] rollout against the oracle's complex step, order 3, 6x8x8x8, 4 steps")
+    om, lib, mp, Uo, Bfo, gam = _oracle_twin(8, 8, 3)
+    dt = om.cfl_dt(Uo, 0.4, gam)
+    rho_t_l, b_t_l = RI.loss_targets(lib.nz)
+    _, vol_l = lib.zone_data()
+    k = lib.shells()
+    outer_l = (k >= lib.g + lib.n_rad - 4) & (k < lib.g + lib.n_rad)
+    U = torch.from_numpy(mp.U(Uo)).cuda().requires_grad_(True)
+    Bf = torch.from_numpy(mp.Bf(Bfo)).cuda().requires_grad_(True)
+    U4, _ = lib.rollout(U, Bf, dt, 4, gamma=gam)
+    lo = tuple(torch.from_numpy(x).cuda() for x in (rho_t_l, b_t_l, np.abs(vol_l))) + \
+        (torch.from_numpy(outer_l).cuda(),)
+    loss_outer_shells(U4, *lo).backward()
+    gU, gB = U.grad.cpu().numpy(), Bf.grad.cpu().numpy()
+    # the loss on the oracle's numbering
+    rho_t, b_t, vol = (np.zeros(om.nz) for _ in range(3))
+    rho_t[mp.z], b_t[mp.z], vol[mp.z] = rho_t_l, b_t_l, np.abs(vol_l)
+    outer = np.zeros(om.nz, bool)
+    outer[mp.z] = outer_l
+    worst = 0.0
+    for d in range(8):
+        r = np.random.default_rng(950 + d)
+        dUo = r.uniform(-1, 1, size=Uo.shape) * np.sqrt((Uo ** 2).mean(1, keepdims=True))
+        dBo = r.uniform(-1, 1, size=Bfo.shape) * np.sqrt((Bfo ** 2).mean())
+        Uc, Bc = Uo + 1j * CS_H * dUo, Bfo + 1j * CS_H * dBo
+        for _ in range(4):
+            Uc, Bc = om.step_complex(Uc, Bc, dt, gamma=gam)
+        Lc = (vol[outer] * ((Uc[0, outer] - rho_t[outer]) ** 2 + ((Uc[5:8, outer] ** 2).sum(0) - b_t[outer]) ** 2)).sum()
+        b = Lc.imag / CS_H
+        terms = np.abs(gU * mp.U(dUo)).sum() + np.abs(gB * mp.Bf(dBo)).sum()
+        a = float((gU * mp.U(dUo)).sum() + (gB * mp.Bf(dBo)).sum())
+        err = abs(a - b) / terms
+        worst = max(worst, err)
+        say(f"[adjoint] rollout direction {d}: autograd {a:.15e}, oracle complex step {b:.15e}, "
+            f"difference / sum |terms| {err:.2e}")
+    assert worst < CS_TOL
 
 
 def loss_outer_shells(U, rho_t, b_t, vol, outer):

@@ -55,7 +55,7 @@ def test_vector_potential_gradient_through_a_step():
     """dL/dA for a loss after one step: stokes_T applied to the step adjoint's
     face-B gradient, against central differences in the edge values."""
     import paper_1905_02504_amd as R
-    from tests.test_gpu_adjoint import roughen
+    from tests.parity_util import roughen
     import rg_inputs as RI
     lib = R.ShellMHD(4, 5, 3, n_ghost=2)
     prob = RI.alfven_problem()
