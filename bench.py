@@ -388,28 +388,34 @@ def main():
         from paper_1905_02504_amd import _native as NV
         inter = torch.from_numpy(shell.interior()).cuda()
         shell.close()   # its work buffers and those of the FP32 geometry do not both fit in HBM
-        t0 = time.perf_counter()
-        shell32 = R.ShellMHD(args.n_ang, args.n_rad, args.order, n_ghost=max(3, args.order - 1),
-                             mode=NV.RG_MODE_FP32)
-        log(f"[bench] FP32-form geometry {time.perf_counter() - t0:.1f}s")
-        U32, Bf32, total32, stage32, nrec32 = run(shell32)
-        ms32 = total32 / args.steps
-        log(f"[bench] FP32 form: {ms32:.2f} ms/step, stages (ms/step): " +
-            ", ".join(f"{k} {v / nrec32:.2f}" for k, v in stage32.items()))
         names = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
-        a64, a32 = U[:, inter], U32[:, inter]
-        l1 = ((a32 - a64).abs().sum(1) / a64.abs().sum(1)).cpu().numpy()
-        l1b = float((Bf32 - Bf).abs().sum() / Bf.abs().sum())
-        diag32 = shell32.diag(U32, Bf32, gam)
-        mixed = {"mode": "fp32 (reconstruction, predictor and traces; geometry, div-free map, Riemann solvers, "
-                         "update and CT in fp64)",
-                 "value": interior * args.steps / (total32 * 1e-3), "ms_per_step": ms32,
-                 "speedup_vs_fp64": ms_step / ms32,
-                 "rel_l1_vs_fp64_after_steps": args.warmup + args.steps,
-                 "rel_l1_vs_fp64": {k: float(v) for k, v in zip(names, l1)}, "rel_l1_face_B": l1b,
-                 "div_b_rel_max": diag32["div_rel_max"],
-                 "stage_ms_per_step": {k: round(v / nrec32, 4) for k, v in stage32.items()}}
-        shell32.close()
+        mixed = {}
+        for tag, mode, what in (
+                ("fp32", NV.RG_MODE_FP32, "fp32 (reconstruction, predictor and traces; geometry, div-free map, "
+                                          "Riemann solvers, update and CT in fp64)"),
+                ("bf16", NV.RG_MODE_BF16, "the fp32 form with the predictor's flux derivatives on the BF16 matrix "
+                                          "cores (each fp32 value split exactly into three bf16 parts, fp32 "
+                                          "accumulation)")):
+            t0 = time.perf_counter()
+            shell32 = R.ShellMHD(args.n_ang, args.n_rad, args.order, n_ghost=max(3, args.order - 1), mode=mode)
+            log(f"[bench] {tag}-form geometry {time.perf_counter() - t0:.1f}s")
+            U32, Bf32, total32, stage32, nrec32 = run(shell32)
+            ms32 = total32 / args.steps
+            log(f"[bench] {tag} form: {ms32:.2f} ms/step, stages (ms/step): " +
+                ", ".join(f"{k} {v / nrec32:.2f}" for k, v in stage32.items()))
+            a64, a32 = U[:, inter], U32[:, inter]
+            l1 = ((a32 - a64).abs().sum(1) / a64.abs().sum(1)).cpu().numpy()
+            l1b = float((Bf32 - Bf).abs().sum() / Bf.abs().sum())
+            diag32 = shell32.diag(U32, Bf32, gam)
+            mixed[tag] = {"mode": what,
+                          "value": interior * args.steps / (total32 * 1e-3), "ms_per_step": ms32,
+                          "speedup_vs_fp64": ms_step / ms32,
+                          "rel_l1_vs_fp64_after_steps": args.warmup + args.steps,
+                          "rel_l1_vs_fp64": {k: float(v) for k, v in zip(names, l1)}, "rel_l1_face_B": l1b,
+                          "div_b_rel_max": diag32["div_rel_max"],
+                          "stage_ms_per_step": {k: round(v / nrec32, 4) for k, v in stage32.items()}}
+            del U32, Bf32
+            shell32.close()
     adjoint = None
     if not args.no_adjoint:
         if args.no_mixed:

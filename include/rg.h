@@ -95,7 +95,15 @@ void rg_mesh_free(rg_mesh *mesh);
  * U and Bf, the divergence-free map (FP64 matrix cores), the Riemann solvers,
  * the conservative update and constrained transport stay FP64, so div B
  * stays at round-off in either mode. */
-typedef enum { RG_MODE_FP64 = 0, RG_MODE_FP32 = 1 } rg_mode;
+typedef enum { RG_MODE_FP64 = 0, RG_MODE_FP32 = 1, RG_MODE_BF16 = 2 } rg_mode;
+/* RG_MODE_BF16 is RG_MODE_FP32 with the predictor's flux derivatives (the
+ * contraction sum_d D_d F_d of eqs. 5.24-5.29 applied at every Picard level,
+ * Section V.d) on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) with FP32
+ * accumulation: the derivative matrices' entries are multiples of 1/2 and
+ * exact in BF16, each FP32 flux value is split exactly into three BF16 parts
+ * (x = hi + mid + lo, by truncation), and the three products are summed in
+ * FP32, so the derivative keeps FP32 accuracy.  Everything else is as in
+ * RG_MODE_FP32.  rg_step_adjoint refuses it (RG_ENOTSUP). */
 
 /* Geometry precompute (Section VI step 1): FP64 on the host, one radial column
  * at a time (zones of a column are self-similar, Section V.b), then one upload

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librg.so")
 
 RG_OK, RG_EINVAL, RG_ENOMEM, RG_ESINGULAR, RG_ENOTSUP, RG_EDEVICE = range(6)
-RG_MODE_FP64, RG_MODE_FP32 = 0, 1
+RG_MODE_FP64, RG_MODE_FP32, RG_MODE_BF16 = 0, 1, 2
 
 
 class rg_mesh_desc(C.Structure):

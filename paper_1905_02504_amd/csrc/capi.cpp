@@ -113,6 +113,47 @@ bool check_dtab(const RefEl &r)
 }
 
 
+// A operands of the BF16 flux-derivative product (RG_MODE_BF16): lane l
+// (r = l % 16, q = l / 16) holds, for each direction d and M tile m, the
+// eight entries A_d[16 m + r][8 q + e] (e = 0..7) as packed bf16 pairs, with
+// A_d[i][p] = D_0[S_d(i)][p]: the predictor stores each direction's fluxes at
+// the swapped node positions S_d, so that A_d times that row is the
+// d-derivative at node i (D_d = S_d D_0 S_d).  Rows or columns beyond N are
+// zero.  Fails if an entry is not exact in BF16.
+template <int P>
+bool bf16_operands_order(const RefEl &r, std::vector<unsigned> &out)
+{
+    using D = DTab<P>;
+    const int N = r.N;
+    out.assign(64 * 3 * 2 * 4, 0u);
+    for (int l = 0; l < 64; l++) {
+        const int rr = l % 16, q = l / 16;
+        for (int d = 0; d < 3; d++)
+            for (int m = 0; m < 2; m++)
+                for (int e = 0; e < 8; e++) {
+                    const int i = 16 * m + rr, p = 8 * q + e;
+                    double v = 0.0;
+                    if (i < N && p < N) {
+                        const int si = d == 0 ? i : d == 1 ? D::SWAP1[i] : D::SWAP2[i];
+                        v = r.D[(size_t)si * N + p];   // the xi block of D: D_0
+                    }
+                    const float f = (float)v;
+                    unsigned bits;
+                    std::memcpy(&bits, &f, 4);
+                    if ((double)f != v || (bits & 0xFFFFu) != 0u) return false;
+                    out[((size_t)l * 6 + d * 2 + m) * 4 + e / 2] |= (bits >> 16) << (16 * (e % 2));
+                }
+    }
+    return true;
+}
+
+bool bf16_derivative_operands(const RefEl &r, std::vector<unsigned> &out)
+{
+    if (r.order == 3) return bf16_operands_order<3>(r, out);
+    if (r.order == 4) return bf16_operands_order<4>(r, out);
+    return false;
+}
+
 template <typename T>
 bool upload(rg_geom *g, const std::vector<T> &h, const T **dst)
 {
@@ -156,7 +197,10 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
     if (!mesh || !out) { set_error("null argument"); return RG_EINVAL; }
     *out = nullptr;
     if (order != 3 && order != 4) { set_error("order must be 3 or 4"); return RG_ENOTSUP; }
-    if (mode != RG_MODE_FP64 && mode != RG_MODE_FP32) { set_error("unknown precision mode"); return RG_ENOTSUP; }
+    if (mode != RG_MODE_FP64 && mode != RG_MODE_FP32 && mode != RG_MODE_BF16) {
+        set_error("unknown precision mode");
+        return RG_ENOTSUP;
+    }
     const Mesh &m = mesh->m;
     if (m.g < order - 1) { set_error("n_ghost must be at least order - 1"); return RG_EINVAL; }
     rg_geom *g = new (std::nothrow) rg_geom;
@@ -380,7 +424,16 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
                   upload(g, vol, &d.vol) && upload(g, area, &d.area) && upload(g, r.D, &d.Dfull) &&
                   upload(g, aelf, &d.ae_lf) && upload(g, vae, &d.v_ae) && upload(g, invp, &d.inv_ptr) &&
                   upload(g, inve, &d.inv_ent);
-        if (ok && mode == RG_MODE_FP32)
+        if (ok && mode == RG_MODE_BF16) {
+            std::vector<unsigned> dmf;
+            if (!bf16_derivative_operands(r, dmf)) {
+                set_error("derivative matrices are not exact in BF16");
+                free_geom(g);
+                return RG_EINVAL;
+            }
+            ok = upload(g, dmf, &d.DmfA);
+        }
+        if (ok && (mode == RG_MODE_FP32 || mode == RG_MODE_BF16))
             ok = upload_f32(g, hg.Pl, &d.PlF) && upload_f32(g, hg.Ps, &d.PsF) && upload_f32(g, hg.Qs, &d.QsF) &&
                  upload_f32(g, EvT, &d.EvF) && upload_f32(g, hg.nJ, &d.nJF) && upload_f32(g, nMT, &d.nMF) &&
                  upload_f32(g, hg.fevR, &d.fevRF) && upload_f32(g, hg.fevA, &d.fevAF) &&
@@ -528,6 +581,10 @@ extern "C" rg_status rg_step_adjoint(const rg_geom *geom, const rg_step_params *
     }
     if (params->flattener != 0.0) {
         set_error("the flattener has no adjoint (run the adjoint with flattener = 0)");
+        return RG_ENOTSUP;
+    }
+    if (g->mode == RG_MODE_BF16) {
+        set_error("the BF16 form has no adjoint (use RG_MODE_FP32 or RG_MODE_FP64)");
         return RG_ENOTSUP;
     }
     if ((const void *)gU_n == (const void *)gU_np1 || (const void *)gBf_n == (const void *)gBf_np1) {

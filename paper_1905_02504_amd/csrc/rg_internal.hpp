@@ -130,6 +130,10 @@ struct DevGeom {
     // FP32 copies of the tables read by the reconstruction and predictor
     // contractions (precision mode RG_MODE_FP32 only; null otherwise)
     const float *PlF, *PsF, *QsF, *EvF, *nJF, *nMF, *fevRF, *fevAF, *fintcF, *eintcF;
+    // RG_MODE_BF16: the A operands of the predictor's flux-derivative product
+    // on the BF16 matrix cores, per lane [64][direction 3][M tile 2][4 dwords
+    // of packed bf16 pairs]
+    const unsigned *DmfA;
     // tables used only by the adjoint of the step
     const double *Dfull;    // 3 x N x N  d psi_l / d xi_d at node i, [d][i][l]
     const int *ae_lf;       // nae x 2    local face of the angular edge in each column

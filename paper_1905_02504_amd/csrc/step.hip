@@ -684,23 +684,136 @@ __global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__
     }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Exact split of eight FP32 values into three BF16 parts each, x = hi + mid +
+// lo: hi is x truncated to BF16, the remainder x - hi (exact, at most 16
+// significant bits) is truncated again, and what is left has at most eight
+// significant bits.  The parts are returned packed in pairs (element 2k in the
+// low half of dword k), the layout of a BF16 matrix-core operand.
+__device__ __forceinline__ void split_bf16x3(const float (&x)[8], u32x4 &hi, u32x4 &mid, u32x4 &lo)
+{
+    unsigned h[8], m[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        h[e] = __float_as_uint(x[e]);
+        const float r1 = x[e] - __uint_as_float(h[e] & 0xFFFF0000u);
+        m[e] = __float_as_uint(r1);
+        l[e] = __float_as_uint(r1 - __uint_as_float(m[e] & 0xFFFF0000u));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        // high halves of both words: bytes 2, 3 of the second operand, then
+        // bytes 2, 3 of the first
+        hi[k] = __builtin_amdgcn_perm(h[2 * k + 1], h[2 * k], 0x07060302u);
+        mid[k] = __builtin_amdgcn_perm(m[2 * k + 1], m[2 * k], 0x07060302u);
+        lo[k] = __builtin_amdgcn_perm(l[2 * k + 1], l[2 * k], 0x07060302u);
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(const u32x4 &a, const u32x4 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
+
+// Flux derivatives of the FP32 predictor on the BF16 matrix cores.  The slab
+// rows (d, v) hold each direction's flux at the swapped node positions (see
+// put_flux), so the sum over directions of the derivatives at node i is
+// sum_d sum_p A_d[i][p] x_{d,v}[p] with A_d[i][p] = D_0[S_d(i)][p]: one
+// product with K = 3 x 32 (one 16x16x32 step per direction), M = the nodes
+// (two tiles of 16) and one column per (zone, variable).  The entries of A
+// (multiples of 1/2) are exact in BF16; each flux value enters as its three
+// exact BF16 parts, the small parts first, with FP32 accumulation.
+// v_mfma_f32_16x16x32_bf16: A[i][k] in lane i + 16 (k / 8), element k % 8;
+// B[k][j] in lane j + 16 (k / 8), element k % 8; D[i][j] in lane
+// j + 16 (i / 4), element i % 4.  The result overwrites the direction-0 rows
+// of the zone's slab: slot i of row v then holds the derivative sum of
+// variable v at node i.  A block is one wavefront, whose LDS accesses take
+// effect in program order, so each column's reads precede its writes.
+template <int N, int SN, int ZS, int ZPW>
+__device__ __forceinline__ void deriv_mfma(float *s_f, const u32x4 (&Am)[3][2], int lane)
+{
+    constexpr int NT = (ZPW * 8 + 15) / 16;
+    const int j = lane % 16, q = lane / 16;
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const int jj = 16 * nt + j, zl = jj / 8, v = jj % 8;
+        const bool zok = zl < ZPW;
+        float *row0 = s_f + (zok ? zl : 0) * ZS + v * SN;
+        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = c0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float *r = row0 + 8 * d * SN + 8 * q;
+            float x[8];
+            if constexpr (N % 16 == 0) {
+                const float4 a = *reinterpret_cast<const float4 *>(r);
+                const float4 b = *reinterpret_cast<const float4 *>(r + 4);
+                x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+                x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+            } else {
+                // the rows end at N; slots 8q + e >= N (and zones past the
+                // wavefront's) enter as zeros
+#pragma unroll
+                for (int e = 0; e < 8; e++) x[e] = 0.f;
+                if (8 * q < N) {
+                    const float4 a = *reinterpret_cast<const float4 *>(r);
+                    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+                    if (8 * q + 4 < N) {
+                        const float4 b = *reinterpret_cast<const float4 *>(r + 4);
+                        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; e++) x[e] = zok ? x[e] : 0.f;
+            }
+            u32x4 bh, bm, bl;
+            split_bf16x3(x, bh, bm, bl);
+            c0 = mfma_bf16(Am[d][0], bl, c0);
+            c1 = mfma_bf16(Am[d][1], bl, c1);
+            c0 = mfma_bf16(Am[d][0], bm, c0);
+            c1 = mfma_bf16(Am[d][1], bm, c1);
+            c0 = mfma_bf16(Am[d][0], bh, c0);
+            c1 = mfma_bf16(Am[d][1], bh, c1);
+        }
+        if (zok && 4 * q < N) *reinterpret_cast<f32x4 *>(row0 + 4 * q) = c0;
+        if (zok && 16 + 4 * q < N) *reinterpret_cast<f32x4 *>(row0 + 16 + 4 * q) = c1;
+    }
+}
+
 // ADER-CG predictor (Section V.d).  One wavefront holds 64 / N zones, one lane
 // per serendipity node.  Each time level's nodal fluxes pass through LDS
 // (node fastest) and the derivative matrices are applied level by level, so a
-// lane keeps only its own node's state in registers.
-template <int P, class R>
+// lane keeps only its own node's state in registers.  With MF (FP32 only) the
+// derivatives run on the BF16 matrix cores (deriv_mfma).
+template <int P, class R, bool MF = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void predictor(
     DevGeom G, double dt, double gamma, int npic, const double *__restrict__ U, const R *__restrict__ wc,
     const R *__restrict__ bnode, R *__restrict__ ftr, R *__restrict__ etr)
 {
     using T = Tr<P>;
+    static_assert(!MF || sizeof(R) == sizeof(float), "the matrix-core derivative is an FP32 form");
     // slab rows are N + 1 long so that lanes reading one node's different
-    // variables fall into different LDS banks
+    // variables fall into different LDS banks; the matrix-core form reads
+    // eight consecutive slots per lane and keeps rows 16-byte aligned instead
     // zone slabs are padded by eight elements so that the zones' rows fall
     // into different LDS banks (eight measured 1 % faster than four)
-    constexpr int N = T::N, SN = N + 1, ZS = 32 * SN + 8, ZPW = 64 / N, E = T::M - 1, NCF = T::NC + 1;
+    constexpr int N = T::N, SN = MF ? N + 4 : N + 1, ZS = 32 * SN + 8, ZPW = 64 / N, E = T::M - 1,
+                  NCF = T::NC + 1;
     __shared__ R s_c[ZPW][5 * NCF];
-    __shared__ R s_f[ZPW * ZS];
+    // 16-byte aligned for the matrix-core form's vector reads and writes
+    __shared__ __align__(16) R s_f[ZPW * ZS];
+    u32x4 Am[3][2];
+    if constexpr (MF) {
+        const u32x4 *a = reinterpret_cast<const u32x4 *>(G.DmfA) + threadIdx.x * 6;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            Am[d][0] = a[2 * d];
+            Am[d][1] = a[2 * d + 1];
+        }
+    }
     const R gam = R(gamma);
     const int lane = threadIdx.x, zl = lane / N, i = lane % N;
     const int KR = G.Nr + 2;
@@ -753,10 +866,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
         put_flux<SN, R>(sf, i, i1, i2, F);
     }
     __syncthreads();
-    deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
+    if constexpr (MF) deriv_mfma<N, SN, ZS, ZPW>(s_f, Am, lane);
+    else deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
     __syncthreads();
     if (active) {
-        get_deriv<SN, R>(sf, i, i1, i2, dFa);
+        if constexpr (MF) {
+#pragma unroll
+            for (int v = 0; v < 8; v++) dFa[v] = sf[v * SN + i];
+        } else {
+            get_deriv<SN, R>(sf, i, i1, i2, dFa);
+        }
         // The first sweep starts from the same state at every level, so each
         // level's flux derivative equals the one at tau = 0: it needs no flux
         // evaluations and gives the same numbers as the general sweep below.
@@ -784,12 +903,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
                 put_flux<SN, R>(sf, i, i1, i2, F);
             }
             __syncthreads();
-            deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
-            __syncthreads();
+            if constexpr (MF) {
+                deriv_mfma<N, SN, ZS, ZPW>(s_f, Am, lane);
+                __syncthreads();
 #pragma unroll
-            for (int v = 0; v < 8; v++) A[s][v] = R(0);
-            if (active) get_deriv<SN, R>(sf, i, i1, i2, A[s]);
-            __syncthreads();
+                for (int v = 0; v < 8; v++) A[s][v] = active ? sf[v * SN + i] : R(0);
+                __syncthreads();
+            } else {
+                deriv_rows<P, SN, ZS, ZPW, R>(s_f, lane);
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < 8; v++) A[s][v] = R(0);
+                if (active) get_deriv<SN, R>(sf, i, i1, i2, A[s]);
+                __syncthreads();
+            }
         }
 #pragma unroll
         for (int t = 0; t < E; t++) {
@@ -1468,7 +1595,7 @@ struct StageMarks {
     }
 };
 
-template <int P, class R>
+template <int P, class R, bool MF = false>
 static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double *U, const double *Bf, double *Uo,
                             double *Bo, hipStream_t st, bool front_only = false)
 {
@@ -1523,7 +1650,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     bmap<P, R><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, wcoef, bnod, bnode, g->zoneB);
     RG_LAUNCH_CHECK();
     sm.mark(4, st);
-    predictor<P, R><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, wcoef, bnode, ftr, etr);
+    predictor<P, R, MF><<<(unsigned)((nzr + ZPW - 1) / ZPW), 64, 0, st>>>(G, dt, gam, npic, Uo, wcoef, bnode, ftr, etr);
     RG_LAUNCH_CHECK();
     if (front_only) return RG_OK;
     sm.mark(5, st);
@@ -1588,13 +1715,25 @@ rg_status profile_end(rg_geom *g, double *ms, int *nsteps)
     return st;
 }
 
+template <int P>
+static rg_status step_mode(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo,
+                           double *Bo, hipStream_t st, bool front_only)
+{
+    switch (g->mode) {
+    case RG_MODE_FP64: return step_order<P, double>(g, p, U, Bf, Uo, Bo, st, front_only);
+    case RG_MODE_FP32: return step_order<P, float>(g, p, U, Bf, Uo, Bo, st, front_only);
+    case RG_MODE_BF16: return step_order<P, float, true>(g, p, U, Bf, Uo, Bo, st, front_only);
+    }
+    set_error("unknown precision mode");
+    return RG_ENOTSUP;
+}
+
 rg_status launch_step(rg_geom *g, const rg_step_params &p, const double *U, const double *Bf, double *Uo, double *Bo,
                       void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool f32 = g->mode == RG_MODE_FP32;
-    if (g->d.order == 3) return f32 ? step_order<3, float>(g, p, U, Bf, Uo, Bo, st) : step_order<3, double>(g, p, U, Bf, Uo, Bo, st);
-    if (g->d.order == 4) return f32 ? step_order<4, float>(g, p, U, Bf, Uo, Bo, st) : step_order<4, double>(g, p, U, Bf, Uo, Bo, st);
+    if (g->d.order == 3) return step_mode<3>(g, p, U, Bf, Uo, Bo, st, false);
+    if (g->d.order == 4) return step_mode<4>(g, p, U, Bf, Uo, Bo, st, false);
     set_error("unsupported order");
     return RG_ENOTSUP;
 }
@@ -1603,11 +1742,8 @@ rg_status launch_step_front(rg_geom *g, const rg_step_params &p, const double *U
                             double *Bo, void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool f32 = g->mode == RG_MODE_FP32;
-    if (g->d.order == 3)
-        return f32 ? step_order<3, float>(g, p, U, Bf, Uo, Bo, st, true) : step_order<3, double>(g, p, U, Bf, Uo, Bo, st, true);
-    if (g->d.order == 4)
-        return f32 ? step_order<4, float>(g, p, U, Bf, Uo, Bo, st, true) : step_order<4, double>(g, p, U, Bf, Uo, Bo, st, true);
+    if (g->d.order == 3) return step_mode<3>(g, p, U, Bf, Uo, Bo, st, true);
+    if (g->d.order == 4) return step_mode<4>(g, p, U, Bf, Uo, Bo, st, true);
     set_error("unsupported order");
     return RG_ENOTSUP;
 }
