@@ -992,9 +992,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
             perm = G.col_perm + ((i64)cq * 4 + lf) * T::Q;
         }
         R *o = ftr + ftr_at<P>(fid, 0, side);   // point q at o + 32 q
+        // every point's normal is loaded before the interpolation, so that the
+        // loads (behind the point permutation) are in flight together: the
+        // FP64 predictor at 6 x 128^3 measured 115.5 -> 109.6 ms
+        int qcs[T::Q];
+        R nn[T::Q][3];
+#pragma unroll
+        for (int q = 0; q < T::Q; q++) qcs[q] = perm ? perm[q] : q;
+#pragma unroll
+        for (int q = 0; q < T::Q; q++) {
+            nn[q][0] = R(nrm[qcs[q] * 3]);
+            nn[q][1] = R(nrm[qcs[q] * 3 + 1]);
+            nn[q][2] = R(nrm[qcs[q] * 3 + 2]);
+        }
         // one row of quadrature points at a time: its weights are uniform
         // across the wavefront and stay in scalar registers
-#pragma unroll 1
+#pragma unroll
         for (int b = 0; b < T::Q1; b++) {
             R aq[T::Q1][4];
 #pragma unroll
@@ -1011,10 +1024,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pr
 #pragma unroll
             for (int a = 0; a < T::Q1; a++) {
                 const int q = a + T::Q1 * b;
-                const int qc = perm ? perm[q] : q;
-                const double *n = nrm + qc * 3;
+                const int qc = qcs[q];
                 o[qc * 32 + v] = aq[a][0];
-                o[qc * 32 + 8 + v] = R(n[0]) * aq[a][1] + R(n[1]) * aq[a][2] + R(n[2]) * aq[a][3];
+                o[qc * 32 + 8 + v] = nn[q][0] * aq[a][1] + nn[q][1] * aq[a][2] + nn[q][2] * aq[a][3];
             }
         }
     }
