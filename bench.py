@@ -30,7 +30,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_cols<{p}, double>",
+STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_mfma<{p}>",
                 "face_bnodal": "zone_face_bn<{p}, double>", "bmap": "bmap<{p}, double>",
                 "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double, false>",
                 "edge_emf": "edge_emf<double, false>", "update_ct": "zone_update"}

@@ -77,6 +77,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_step(rg_geom *, const rg_step_params &, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
     rg_status profile_end(rg_geom *, double *, int *) { return RG_ENOTSUP; }
     rg_status launch_cfl(rg_geom *, const double *, double, double, void *, double *) { return RG_ENOTSUP; }
+    rg_status launch_cfl_noalloc(rg_geom *, const double *, double, double, void *, double *) { return RG_ENOTSUP; }
     rg_status launch_step_front(rg_geom *, const rg_step_params &, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_adjoint(rg_geom *, const rg_step_params &, const double *, const double *, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_stokes(rg_geom *, const double *, double *, void *) { return RG_ENOTSUP; }
@@ -104,6 +105,11 @@ LIB_DRIVER = textwrap.dedent(r"""
         if (rc == RG_OK) rc = rg_init_tube(g, tl, tr, 0.75, 1.5, 1.5, 0.01, 2.0, U.data(), Bf.data());
         const double tbad[7] = {1.0, 1.0, 0.0, 0.0, 0.0, 0.5, 1.0};
         if (rc == RG_OK && rg_init_tube(g, tbad, tr, 0.75, 1.5, 1.5, 0.01, 2.0, U.data(), Bf.data()) != RG_EINVAL) rc = 4;
+        const double axis[3] = {0.0, 0.0, 1.0}, centre[3] = {0.0, 0.0, 1.5};
+        if (rc == RG_OK)
+            rc = rg_init_blast(g, axis, centre, 0.3, 1.0, 1000.0, 0.1, 1.0, 5.0 / 3.0, U.data(), Bf.data());
+        std::vector<double> cl(info.n_columns), ck(info.n_columns);
+        if (rc == RG_OK) rc = rg_geom_conditioning(g, cl.data(), ck.data());
         // without device data the step entry points refuse
         rg_step_params p{5.0 / 3.0, 1e-3, 0.0, 0, 0, 0.0};
         if (rg_step(g, &p, U.data(), Bf.data(), U.data(), Bf.data(), nullptr) == RG_OK) rc = 3;
@@ -115,7 +121,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     }
     int main() {
         rg_mesh *m = nullptr;
-        rg_mesh_desc bad{12, 3, 1.0, 2.0, 0, 2, 3};
+        rg_mesh_desc bad{10, 3, 1.0, 2.0, 0, 2, 3};   // neither 2^k nor 3 x 2^k
         int rc = rg_mesh_build(&bad, &m) == RG_OK;
         rc |= run(3) | run(4);
         std::printf("library host driver rc=%d\n", rc);
@@ -133,7 +139,8 @@ def test_oracle_under_sanitizers(tmp_path):
     _need("gcc")
     drv = tmp_path / "oracle_driver.c"
     drv.write_text(ORACLE_DRIVER)
-    srcs = [os.path.join(ODIR, s) for s in ("la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "init.c", "oracle.c")]
+    from oracle import oracle as O
+    srcs = [os.path.join(ODIR, s) for s in O._SOURCES]
     exe = tmp_path / "oracle_driver"
     subprocess.run(["gcc", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", *SAN, str(drv), *srcs, "-o", str(exe), "-lm"],
                    check=True, capture_output=True)
