@@ -87,7 +87,8 @@ rg_status rg_mesh_get_info(const rg_mesh *mesh, rg_mesh_info *info);
 void rg_mesh_free(rg_mesh *mesh);
 
 /* Precision of the reconstruction and predictor contractions (the paper's
- * scheme is FP64 throughout; RG_MODE_FP32 is the reduced-precision form).
+ * scheme is FP64 throughout; RG_MODE_FP32 and RG_MODE_BF16 are the
+ * reduced-precision forms).
  * In RG_MODE_FP32 the WENO-AO contractions and weights, the face nodal B
  * contractions, the ADER-CG predictor (fluxes, derivatives, Picard updates,
  * time averages) and the face / edge traces are computed and stored in FP32,

@@ -592,24 +592,25 @@ __global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__
 // new zone mean) is applied to the zone's inputs -- its WENO B, the limited
 // nodal normal B of its six faces and their face averages.  Per column this is
 // a dense product Out^T (NOUTB x zones) = Mb^T (NOUTB x NIN) In^T (NIN x zones),
-// done on the FP64 matrix cores: one wavefront owns bmap_tiles<R> tiles of
+// done on the FP64 matrix cores: one wavefront owns BMAP_TILES tiles of
 // 16 zones of a column and all output rows, stepping through the inputs four
 // at a time; each A operand it loads serves all its tiles.  Three tiles
 // measured 6 % faster than one with FP64 inputs (two were slower: fewer
-// wavefronts in flight); with FP32 inputs the extra registers cost more
-// occupancy than the shared loads save, so that form keeps one
+// wavefronts in flight).  With FP32 inputs the compiler's own schedule for
+// three tiles took 218 VGPRs beside the accumulators (one wavefront per SIMD,
+// 23.3 ms at 6 x 128^3 against 16.3 ms for one tile); the occupancy hint of
+// two wavefronts per SIMD holds both forms to 242 registers (FP32: 14.5 ms)
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
-template <class R>
-constexpr int bmap_tiles() { return sizeof(R) == sizeof(double) ? 3 : 1; }
+constexpr int BMAP_TILES = 3;
 
 template <int P, class R>
-__global__ __launch_bounds__(64) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void bmap(DevGeom G, const double *__restrict__ U, const double *__restrict__ Bf,
                                            const R *__restrict__ wc, const R *__restrict__ bnod,
                                            R *__restrict__ bnode, double *__restrict__ zoneB)
 {
     using T = Tr<P>;
-    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16, NT = bmap_tiles<R>();
+    constexpr int NIN = T::NIN, NOUT = T::NOUTB, KT = NIN / 4, MT = (NOUT + 15) / 16, NT = BMAP_TILES;
     constexpr int NA = 3 * (T::NC + 1), NQ = NA + 6 * T::Q;
     static_assert(NIN % 4 == 0, "input count must be a multiple of 4");
     const int KR = G.Nr + 2, nt = (KR + 16 * NT - 1) / (16 * NT);
@@ -1658,7 +1659,7 @@ static rg_status step_order(rg_geom *g, const rg_step_params &prm, const double 
     RG_LAUNCH_CHECK();
     sm.mark(3, st);
     constexpr int ZPW = 64 / Tr<P>::N;
-    const int ntile = (G.Nr + 2 + 16 * bmap_tiles<R>() - 1) / (16 * bmap_tiles<R>());
+    const int ntile = (G.Nr + 2 + 16 * BMAP_TILES - 1) / (16 * BMAP_TILES);
     bmap<P, R><<<(unsigned)((i64)G.ncol * ntile), 64, 0, st>>>(G, Uo, Bo, wcoef, bnod, bnode, g->zoneB);
     RG_LAUNCH_CHECK();
     sm.mark(4, st);
