@@ -32,7 +32,7 @@ def log(msg):
 
 STAGE_KERNEL = {"bc_fill": "bc_zones", "weno": "weno_mfma<{p}>",
                 "face_bnodal": "zone_face_bn<{p}, double>", "bmap": "bmap<{p}, double>",
-                "predictor": "predictor<{p}, double>", "face_flux": "face_flux<{p}, double, false>",
+                "predictor": "predictor<{p}, double, false>", "face_flux": "face_flux<{p}, double, false>",
                 "edge_emf": "edge_emf<double, false>", "update_ct": "zone_update"}
 
 
