@@ -128,6 +128,19 @@ rg_status rg_geom_zone_data(const rg_geom *geom, double *centroid, double *volum
 rg_status rg_geom_face_data(const rg_geom *geom, double *center, double *normal, double *area);
 rg_status rg_geom_edge_data(const rg_geom *geom, double *midpoint, double *tangent);
 
+/* Orientation tables of the Yee layout (Section II.c, eqs. 2.5-2.6), host
+ * copies; any pointer may be NULL.  zone_face[n_zones][6]: a zone's faces in
+ * the local order xi-, xi+, eta-, eta+ (angular), r-, r+ (radial), and
+ * zone_face_sign[n_zones][6]: +1 where the face's canonical normal (as
+ * reported by rg_geom_face_data) points out of the zone, -1 where it points
+ * in.  face_edge[n_faces][4]: a face's four edges, and face_edge_sign
+ * [n_faces][4]: +1 where the edge's canonical direction (rg_geom_edge_data)
+ * runs with the circulation about the face's canonical normal (right-hand
+ * rule), -1 where it runs against it; the CT update of eqs. (2.5)-(2.6) is
+ * Bf[f] -= dt / area[f] * sum_j face_edge_sign[f][j] * E[face_edge[f][j]]. */
+rg_status rg_geom_incidence(const rg_geom *geom, int64_t *zone_face, int8_t *zone_face_sign, int64_t *face_edge,
+                            int8_t *face_edge_sign);
+
 /* Conditioning of the per-column systems built by the precompute (Section
  * III's least squares on eq. (3.4) rows, Section IV.b's KKT system), host
  * copies of [n_columns] each; either pointer may be NULL.  cond_lsq: the

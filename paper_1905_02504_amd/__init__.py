@@ -86,6 +86,13 @@ class ShellMHD:
         N.rg_geom_edge_data(self._geom, _ptr(mid), _ptr(tan))
         return mid, tan
 
+    def incidence(self):
+        """rg_geom_incidence: (zone_face [nz, 6], zone_face_sign, face_edge [nf, 4], face_edge_sign)"""
+        zf = np.zeros((self.nz, 6), np.int64); zs = np.zeros((self.nz, 6), np.int8)
+        fe = np.zeros((self.nf, 4), np.int64); fs = np.zeros((self.nf, 4), np.int8)
+        N.rg_geom_incidence(self._geom, _ptr(zf), _ptr(zs), _ptr(fe), _ptr(fs))
+        return zf, zs, fe, fs
+
     def conditioning(self):
         """rg_geom_conditioning: per-column condition numbers of the large-stencil
         least squares (2-norm) and of the divergence-free KKT matrix (1-norm)."""

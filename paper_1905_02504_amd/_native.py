@@ -67,6 +67,7 @@ def lib():
         L.rg_geom_zone_data.argtypes = [_vp, _vp, _vp]
         L.rg_geom_face_data.argtypes = [_vp, _vp, _vp, _vp]
         L.rg_geom_edge_data.argtypes = [_vp, _vp, _vp]
+        L.rg_geom_incidence.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.rg_step.argtypes = [_vp, C.POINTER(rg_step_params), _vp, _vp, _vp, _vp, _vp]
         L.rg_step_fluxes.argtypes = [_vp, _vp, _vp, _vp]
         L.rg_step_fallback_zones.argtypes = [_vp, _vp, _vp]
@@ -93,7 +94,8 @@ def lib():
         L.rg_profile_begin.argtypes = [_vp]
         L.rg_profile_end.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
-                     "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_step", "rg_step_fluxes",
+                     "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_geom_incidence", "rg_step",
+                     "rg_step_fluxes",
                      "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
                      "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag",
                      "rg_cfl_dt_noalloc", "rg_geom_conditioning", "rg_init_blast", "rg_step_fallback_counts"):
@@ -151,6 +153,10 @@ def rg_geom_face_data(geom, center_ptr, normal_ptr, area_ptr):
 
 def rg_geom_edge_data(geom, mid_ptr, tan_ptr):
     check(lib().rg_geom_edge_data(geom, _vp(mid_ptr), _vp(tan_ptr)), "rg_geom_edge_data")
+
+
+def rg_geom_incidence(geom, zf_ptr, zfs_ptr, fe_ptr, fes_ptr):
+    check(lib().rg_geom_incidence(geom, _vp(zf_ptr), _vp(zfs_ptr), _vp(fe_ptr), _vp(fes_ptr)), "rg_geom_incidence")
 
 
 def rg_step(geom, params: rg_step_params, U_ptr, Bf_ptr, Uo_ptr, Bfo_ptr, stream):

@@ -290,6 +290,8 @@ static rg_status precompute(const rg_mesh *mesh, int32_t order, int32_t mode, bo
         g->etan.assign(NE * 3, 0.0);
         g->snode.assign((size_t)ncol * 48, 0.0);
         g->ae_rs_host = hg.ae_rs;
+        g->col_side_host = hg.col_side;
+        g->col_sgn_host = hg.col_sgn;
 #pragma omp parallel for schedule(static)
         for (int c = 0; c < ncol; c++) {
             const ColData &cd = cols[c];
@@ -515,6 +517,61 @@ extern "C" rg_status rg_geom_edge_data(const rg_geom *g, double *midpoint, doubl
     if (!g) { set_error("null geometry"); return RG_EINVAL; }
     if (midpoint) std::memcpy(midpoint, g->emid.data(), g->emid.size() * sizeof(double));
     if (tangent) std::memcpy(tangent, g->etan.data(), g->etan.size() * sizeof(double));
+    return RG_OK;
+}
+
+extern "C" rg_status rg_geom_incidence(const rg_geom *g, int64_t *zone_face, int8_t *zone_face_sign,
+                                       int64_t *face_edge, int8_t *face_edge_sign)
+{
+    if (!g || !g->mesh) { set_error("null geometry"); return RG_EINVAL; }
+    const rg::Mesh &m = g->mesh->m;
+    const int K = m.K;
+    const int64_t NRF = m.nrf, NRE = m.nre;
+    if (zone_face || zone_face_sign) {
+        for (int c = 0; c < m.ncol; c++)
+            for (int k = 0; k < K; k++) {
+                const int64_t z = (int64_t)c * K + k;
+                for (int lf = 0; lf < 6; lf++) {
+                    int64_t f;
+                    int sg;
+                    if (lf < 4) {
+                        // the canonical normal runs from side 0 to side 1 of the angular edge
+                        f = NRF + (int64_t)m.col_ae[4 * c + lf] * K + k;
+                        sg = g->col_side_host[4 * c + lf] == 0 ? 1 : -1;
+                    } else {
+                        f = (int64_t)c * (K + 1) + k + (lf - 4);   // normal +r
+                        sg = lf == 5 ? 1 : -1;
+                    }
+                    if (zone_face) zone_face[z * 6 + lf] = f;
+                    if (zone_face_sign) zone_face_sign[z * 6 + lf] = (int8_t)sg;
+                }
+            }
+    }
+    if (face_edge || face_edge_sign) {
+        // radial face (c, kf): the four angular edges at interface kf
+        for (int c = 0; c < m.ncol; c++)
+            for (int kf = 0; kf <= K; kf++) {
+                const int64_t f = (int64_t)c * (K + 1) + kf;
+                for (int lf = 0; lf < 4; lf++) {
+                    if (face_edge) face_edge[f * 4 + lf] = NRE + (int64_t)m.col_ae[4 * c + lf] * (K + 1) + kf;
+                    if (face_edge_sign) face_edge_sign[f * 4 + lf] = (int8_t)g->col_sgn_host[4 * c + lf];
+                }
+            }
+        // angular face (ae, k): its lower and upper angular edges and the
+        // radial edges at the edge's two vertices
+        for (int ae = 0; ae < m.nae; ae++) {
+            const int rs = g->ae_rs_host[ae];
+            for (int k = 0; k < K; k++) {
+                const int64_t f = NRF + (int64_t)ae * K + k, ea = NRE + (int64_t)ae * (K + 1) + k;
+                const int64_t e[4] = {ea, (int64_t)m.ae_v[2 * ae + 1] * K + k, ea + 1, (int64_t)m.ae_v[2 * ae] * K + k};
+                const int sg[4] = {rs, rs, -rs, -rs};
+                for (int j = 0; j < 4; j++) {
+                    if (face_edge) face_edge[f * 4 + j] = e[j];
+                    if (face_edge_sign) face_edge_sign[f * 4 + j] = (int8_t)sg[j];
+                }
+            }
+        }
+    }
     return RG_OK;
 }
 

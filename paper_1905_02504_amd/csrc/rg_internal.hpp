@@ -185,6 +185,7 @@ struct rg_geom {
     // per-column host data kept for initial conditions
     std::vector<double> snode;   // ncol x 16 x 3 surface map nodes
     std::vector<int> ae_rs_host; // +1 if side 1 of an angular edge is right of its direction
+    std::vector<int> col_side_host, col_sgn_host;   // per column-local angular face: side, circulation sign
     std::vector<double> cond_lsq, cond_kkt;   // per-column condition numbers (precompute)
     // optional per-stage timing: one set of RG_NSTAGE+1 events per recorded step
     bool prof_on = false;

@@ -110,3 +110,58 @@ def test_library_initial_alfven_state_is_divergence_free():
     # and the oracle's own initial state agrees with it to the accuracy of the zone cubature
     Uo, Bfo = m.init_alfven(RI.alfven_problem())
     np.testing.assert_allclose(Bf, sg * Bfo[fi], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("n_ang", [4, 6])
+def test_incidence_tables_are_consistent_and_match_the_oracle(n_ang):
+    """rg_geom_incidence (the orientation tables of the Yee layout, eqs.
+    2.5-2.6).  Checked without the library's own orientation logic:
+    * each zone face's sign says whether the face's canonical normal points
+      out of the zone (the normal against the face-centre minus zone-centre
+      offset), and each face is held by at most two zones, with opposite signs;
+    * the boundary of a zone's boundary is empty: the signed edges of its six
+      signed faces cancel, for every zone;
+    * each face's edge sign says whether the edge's canonical direction runs
+      about the face's canonical normal counter-clockwise (the tangent against
+      normal x (edge midpoint - face centre));
+    * the signed face-edge incidence equals the oracle's, mapped by
+      coordinates with each side's own canonical orientations."""
+    import paper_1905_02504_amd as R
+    from tests.parity_util import Mapping
+    s = R.ShellMHD(n_ang, 4, 3, n_ghost=2, device=False)
+    zf, zs, fe, fes = s.incidence()
+    zc, _ = s.zone_data()
+    fc, fn, fa = s.face_data()
+    em, et = s.edge_data()
+    assert zf.min() >= 0 and zf.max() < s.nf and fe.min() >= 0 and fe.max() < s.ne
+    assert set(np.unique(zs)) <= {-1, 1} and set(np.unique(fes)) <= {-1, 1}
+    # signs against the geometry
+    out = np.einsum("zfc,zfc->zf", fn[zf], fc[zf] - zc[:, None, :])
+    assert (np.sign(out) == zs).all()
+    # two holders with opposite signs
+    cnt = np.bincount(zf.ravel(), minlength=s.nf)
+    tot = np.bincount(zf.ravel(), weights=zs.ravel().astype(float), minlength=s.nf)
+    assert cnt.max() <= 2 and (cnt > 0).all()
+    assert (tot[cnt == 2] == 0).all()
+    # boundary of the boundary: per zone, signed edge counts cancel
+    ze = fe[zf]                                  # [nz, 6, 4]
+    zes = zs[:, :, None] * fes[zf]               # [nz, 6, 4]
+    for z in range(0, s.nz, 7):
+        acc = {}
+        for e, g in zip(ze[z].ravel(), zes[z].ravel()):
+            acc[e] = acc.get(e, 0) + int(g)
+        assert all(v == 0 for v in acc.values())
+    # edge signs against the geometry: right-hand circulation about the normal
+    circ = np.einsum("fjc,fjc->fj", et[fe], np.cross(fn[:, None, :], em[fe] - fc[:, None, :]))
+    assert (np.sign(circ) == fes).all()
+    # the oracle's incidence under the coordinate mapping
+    from oracle import oracle as O
+    om = O.OracleMesh(n_ang, 4, order=3, n_ghost=2)
+    mp = Mapping(s, om)
+    oe, osg = om.face_edges()
+    inv_e = np.empty(s.ne, np.int64); inv_e[mp.e] = np.arange(s.ne)
+    for f in range(s.nf):
+        fo = mp.f[f]
+        mine = {int(e): int(g) for e, g in zip(fe[f], fes[f])}
+        theirs = {int(inv_e[e]): int(g) * int(mp.fs[f]) * int(mp.es[inv_e[e]]) for e, g in zip(oe[fo], osg[fo])}
+        assert mine == theirs, (f, mine, theirs)

@@ -110,6 +110,9 @@ LIB_DRIVER = textwrap.dedent(r"""
             rc = rg_init_blast(g, axis, centre, 0.3, 1.0, 1000.0, 0.1, 1.0, 5.0 / 3.0, U.data(), Bf.data());
         std::vector<double> cl(info.n_columns), ck(info.n_columns);
         if (rc == RG_OK) rc = rg_geom_conditioning(g, cl.data(), ck.data());
+        std::vector<int64_t> zf(6 * info.n_zones), fe(4 * info.n_faces);
+        std::vector<int8_t> zs(6 * info.n_zones), fs(4 * info.n_faces);
+        if (rc == RG_OK) rc = rg_geom_incidence(g, zf.data(), zs.data(), fe.data(), fs.data());
         // without device data the step entry points refuse
         rg_step_params p{5.0 / 3.0, 1e-3, 0.0, 0, 0, 0.0};
         if (rg_step(g, &p, U.data(), Bf.data(), U.data(), Bf.data(), nullptr) == RG_OK) rc = 3;
