@@ -1,18 +1,24 @@
-// Device step of the rg library for gfx950 (FP64).  One launch per stage,
-// all on the caller's stream:
+// Device step of the rg library for gfx950: the FP64 scheme and its FP32 and
+// BF16 forms.  One launch per stage, all on the caller's stream:
 //   bc_zones / bc_faces : continuative ghost fill (Section VII) into the output state
-//   weno_cols          : WENO-AO in the Taylor basis (Section III), one wavefront
-//                        per run of shells of one column
+//   weno_mfma          : WENO-AO in the Taylor basis (Section III) on the FP64
+//                        matrix cores, 16 shells of one column per wavefront;
+//                        weno_cols, its VALU form, serves the FP32 forms
+//   flatten_wc         : the flattener (when on): each zone's coefficients
+//                        scaled toward first order by a compression detector
 //   zone_face_bn /     : limited nodal normal B on every face, eqs. (4.11)-(4.12):
 //   face_bn_limit        each zone's normal B at its faces' points, then per face
 //                        the MinMod and the mean restore
 //   bmap               : divergence-free B (Section IV.b) as one dense per-column
 //                        map on the FP64 matrix cores, evaluated at the ADER nodes
 //   predictor          : ADER-CG Picard iteration (Section V.d), one lane per
-//                        serendipity node, then time-averaged traces at face and
-//                        edge points
+//                        serendipity node (the BF16 form's flux derivatives on
+//                        the BF16 matrix cores), then time-averaged traces at
+//                        face and edge points
 //   face_flux          : HLL at face quadrature points -> face flux integrals
 //   edge_emf           : multidimensional HLL electric field at edge Simpson points
+//   fb_*               : the first-order fallback (when on): flag, constant
+//                        traces, and the two Riemann kernels on marked faces/edges
 //   zone_update        : finite-volume update of the eight zone averages
 //   face_ct            : constrained transport of face-averaged normal B (eqs. 2.5-2.6)
 #include <climits>
@@ -85,6 +91,7 @@ __device__ __forceinline__ R weno_var(const DevGeom &G, const double *__restrict
     return whi;
 }
 
+// The FP32 forms' WENO-AO on the VALU (the FP64 scheme uses weno_mfma below).
 // One wavefront per run of up to 64 shells of one column, the eight
 // variables in turn.  With a short tail (nleft shells, at most 8) each column
 // gets one more wavefront whose lanes take (tail shell, variable) pairs.
