@@ -108,13 +108,38 @@ def cpu_baseline(order, sample_n=16, sample_nr=16):
         m.step(U, Bf, dt, gamma=prob["gamma"])
         return time.perf_counter() - t0, 6 * n * n * nr
 
+    def c1_step(n):
+        """one third-order step of the multi-harmonic state on 6 x n^3 zones"""
+        m = O.OracleMesh(n, n, order=3, n_ghost=2)
+        hp = RI.harmonic_problem()
+        U, Bf = m.init_harmonic(hp)
+        dt = m.cfl_dt(U, 0.4, hp["gamma"])
+        t0 = time.perf_counter()
+        m.step(U, Bf, dt, gamma=hp["gamma"])
+        return time.perf_counter() - t0, 6 * n ** 3
+
+    def c4_gradient():
+        """one directional derivative of a third-order step on 6 x 8^3 zones by
+        the oracle's complex step (the oracle gradient of the adjoint checks)"""
+        m = O.OracleMesh(8, 8, order=3, n_ghost=2)
+        U, Bf = m.init_alfven(prob)
+        dt = m.cfl_dt(U, 0.3, prob["gamma"])
+        d = np.random.default_rng(5).uniform(-1, 1, U.shape)
+        t0 = time.perf_counter()
+        m.step_complex(U + 1e-30j * d, Bf.astype(np.complex128), dt, gamma=prob["gamma"])
+        return time.perf_counter() - t0, 6 * 8 ** 3
+
     O.lib()   # the oracle's OpenMP runtime is the process's libgomp
     gomp = ctypes.CDLL("libgomp.so.1")
     threads = gomp.omp_get_max_threads()
     el, zones = one_step(sample_n, sample_nr)
+    elc1, zc1 = c1_step(16)
+    elg, zg = c4_gradient()
     gomp.omp_set_num_threads(1)
     try:
         el1, zones1 = one_step(4, 8)
+        elc1_1, zc1_1 = c1_step(8)
+        elg1, _ = c4_gradient()
     finally:
         gomp.omp_set_num_threads(threads)
     return {"value": zones / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
@@ -122,7 +147,12 @@ def cpu_baseline(order, sample_n=16, sample_nr=16):
             "sample": f"one order-{order} step on 6x{sample_n}x{sample_n}x{sample_nr} zones "
                       f"(Alfven wave + noise), {el:.2f} s, geometry excluded",
             "single_thread": {"value": zones1 / el1, "sample": f"one order-{order} step on 6x4x4x8 zones, "
-                                                                f"{el1:.2f} s"}}
+                                                                f"{el1:.2f} s"},
+            "order3": {"all_threads": zc1 / elc1, "single_thread": zc1_1 / elc1_1, "unit": "zone-updates/s",
+                       "sample": "one third-order step of the multi-harmonic state, 6x16^3 zones on all threads, "
+                                 "6x8^3 on one"},
+            "gradient_6x8cubed": {"all_threads": zg / elg, "single_thread": zg / elg1, "unit": "zone-updates/s",
+                                  "sample": "one directional derivative of a third-order step by complex step"}}
 
 
 def time_adjoint(reps=5):
@@ -181,8 +211,10 @@ def time_adjoint(reps=5):
 
 def measured_peaks(reps=5):
     """Attainable rates on this GPU, beside the datasheet peaks: the FP64
-    vector FMA rate of rg_fma_probe (16 independent chains per lane) and the
-    bandwidth of a 2 GiB device-to-device copy (bytes read + written)."""
+    vector FMA rate of rg_fma_probe (16 independent chains per lane), the FP64
+    and BF16 matrix-core rates of rg_mfma_probe (8 independent products per
+    wavefront) and the bandwidth of a 2 GiB device-to-device copy (bytes read +
+    written)."""
     import torch
     from paper_1905_02504_amd import _native as NV
     stream = torch.cuda.current_stream()
@@ -202,13 +234,19 @@ def measured_peaks(reps=5):
     sink = torch.empty(n, dtype=torch.float64, device="cuda")
     t = timed(lambda: NV.rg_fma_probe(sink.data_ptr(), n, iters, stream.cuda_stream))
     fp64 = 2.0 * 16 * iters * n / t / 1e12
+    # matrix cores: eight independent products per wavefront and iteration
+    nm, im = 256 * 4096, 256
+    t = timed(lambda: NV.rg_mfma_probe(sink.data_ptr(), nm, im, 0, stream.cuda_stream))
+    mfma64 = 2048.0 * 8 * im * (nm // 64) / t / 1e12
+    t = timed(lambda: NV.rg_mfma_probe(sink.data_ptr(), nm, 4 * im, 1, stream.cuda_stream))
+    mfma_bf16 = 16384.0 * 8 * 4 * im * (nm // 64) / t / 1e12
     del sink
     a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     t = timed(lambda: b.copy_(a))
     gbs = 2.0 * a.numel() * 8 / t / 1e9
     del a, b
-    return {"fp64_valu_tflops": fp64, "hbm_copy_gbs": gbs}
+    return {"fp64_valu_tflops": fp64, "fp64_mfma_tflops": mfma64, "bf16_mfma_tflops": mfma_bf16, "hbm_copy_gbs": gbs}
 
 
 def weno_order_stats(sh):
@@ -264,8 +302,8 @@ def time_blast(n_steps=50, mode=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-ang", type=int, default=128)
     ap.add_argument("--n-rad", type=int, default=128)
     ap.add_argument("--order", type=int, default=4)
@@ -380,7 +418,18 @@ def main():
     peaks = measured_peaks()
     roof["measured_peak"] = peaks["fp64_valu_tflops"] if roof["unit"] == "TFLOP/s" else peaks["hbm_copy_gbs"]
     roof["frac_of_measured_peak"] = roof["achieved"] / roof["measured_peak"]
-    log(f"[bench] measured peaks: FP64 FMA {peaks['fp64_valu_tflops']:.1f} TFLOP/s, device copy "
+    if traffic is not None:
+        roof["traffic_gbs"] = traffic / dom_s / 1e9   # measured HBM bytes over the kernel's time
+    # the matrix-core stages: algorithmic flops over their time, against the
+    # datasheet and the measured FP64 matrix-core rates
+    mfma_stages = {}
+    for st in ("weno", "bmap"):
+        tf = flops[st] / (stage_ms[st] / nrec * 1e-3) / 1e12
+        mfma_stages[st] = {"kernel": STAGE_KERNEL[st].format(p=args.order), "ms": stage_ms[st] / nrec,
+                           "tflops": tf, "frac_of_peak": tf / PEAK_FP64_TFLOPS,
+                           "frac_of_measured_mfma_peak": tf / peaks["fp64_mfma_tflops"]}
+    log(f"[bench] measured peaks: FP64 FMA {peaks['fp64_valu_tflops']:.1f} TFLOP/s, FP64 MFMA "
+        f"{peaks['fp64_mfma_tflops']:.1f} TFLOP/s, BF16 MFMA {peaks['bf16_mfma_tflops']:.0f} TFLOP/s, device copy "
         f"{peaks['hbm_copy_gbs']:.0f} GB/s; dominant kernel at {100 * roof['frac_of_measured_peak']:.1f} % of the "
         f"measured peak")
     mixed = None
@@ -454,6 +503,7 @@ def main():
                    "setup_s": {"geometry": round(t_geom, 2), "initial_data": round(t_init, 2)},
                    "stage_ms_per_step": {k: round(v / nrec, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
+        "mfma_stages": mfma_stages,
         "measured_peaks": peaks,
         "div_b_rel_max": diag64["div_rel_max"],
         "weno_order_last_step": weno_order,

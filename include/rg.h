@@ -382,6 +382,15 @@ rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
  * Asynchronous on `stream`. */
 rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters, void *stream);
 
+/* Benchmark helper (not part of the scheme): launches n_threads (a multiple
+ * of 256) lanes whose wavefronts each run iters x 8 independent matrix-core
+ * products and write one double per lane to sink[n_threads] (device).  kind 0:
+ * v_mfma_f64_16x16x4 (2048 flops per product), kind 1:
+ * v_mfma_f32_16x16x32_bf16 (16384 flops).  Timed by the caller, it gives the
+ * attainable matrix-core rate (flops x 8 x iters x n_threads / 64).  RG_EINVAL
+ * for other kinds or sizes.  Asynchronous on `stream`. */
+rg_status rg_mfma_probe(double *sink, int64_t n_threads, int32_t iters, int32_t kind, void *stream);
+
 const char *rg_last_error(void);
 
 /* Name and one-line meaning of a status code (static string). */

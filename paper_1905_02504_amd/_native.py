@@ -73,6 +73,7 @@ def lib():
         L.rg_step_fallback_zones.argtypes = [_vp, _vp, _vp]
         L.rg_step_weno_order.argtypes = [_vp, _vp, _vp]
         L.rg_fma_probe.argtypes = [_vp, C.c_int64, C.c_int32, _vp]
+        L.rg_mfma_probe.argtypes = [_vp, C.c_int64, C.c_int32, C.c_int32, _vp]
         L.rg_step_adjoint.argtypes = [_vp, C.POINTER(rg_step_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.rg_stokes.argtypes = [_vp, _vp, _vp, _vp]
         L.rg_stokes_T.argtypes = [_vp, _vp, _vp, _vp]
@@ -96,7 +97,7 @@ def lib():
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_geom_incidence", "rg_step",
                      "rg_step_fluxes",
-                     "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe",
+                     "rg_step_fallback_zones", "rg_step_weno_order", "rg_fma_probe", "rg_mfma_probe",
                      "rg_step_adjoint", "rg_stokes", "rg_stokes_T", "rg_cfl_dt", "rg_init_alfven", "rg_init_tube", "rg_diag",
                      "rg_cfl_dt_noalloc", "rg_geom_conditioning", "rg_init_blast", "rg_step_fallback_counts"):
             getattr(L, name).restype = C.c_int
@@ -196,6 +197,10 @@ def rg_step_weno_order(geom, whi_ptr, stream):
 
 def rg_fma_probe(sink_ptr, n_threads, iters, stream):
     check(lib().rg_fma_probe(_vp(sink_ptr), int(n_threads), int(iters), _vp(stream)), "rg_fma_probe")
+
+
+def rg_mfma_probe(sink_ptr, n_threads, iters, kind, stream):
+    check(lib().rg_mfma_probe(_vp(sink_ptr), int(n_threads), int(iters), int(kind), _vp(stream)), "rg_mfma_probe")
 
 
 def rg_cfl_dt(geom, U_ptr, gamma, cfl, stream):

@@ -749,6 +749,12 @@ extern "C" rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters
     return launch_fma_probe(sink, (long long)n_threads, (int)iters, stream);
 }
 
+extern "C" rg_status rg_mfma_probe(double *sink, int64_t n_threads, int32_t iters, int32_t kind, void *stream)
+{
+    if (!sink) { set_error("null argument"); return RG_EINVAL; }
+    return launch_mfma_probe(sink, (long long)n_threads, (int)iters, (int)kind, stream);
+}
+
 extern "C" rg_status rg_profile_begin(rg_geom *g)
 {
     if (!g || !g->d.vol) { set_error("null geometry or geometry without device data"); return RG_EINVAL; }

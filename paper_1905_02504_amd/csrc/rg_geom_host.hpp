@@ -59,6 +59,7 @@ rg_status launch_adjoint(rg_geom *g, const rg_step_params &p, const double *U, c
 rg_status launch_stokes(rg_geom *g, const double *circ, double *Bf, void *stream);
 rg_status launch_stokes_T(rg_geom *g, const double *gBf, double *gcirc, void *stream);
 rg_status launch_fma_probe(double *sink, long long n_threads, int iters, void *stream);
+rg_status launch_mfma_probe(double *sink, long long n_threads, int iters, int kind, void *stream);
 rg_status launch_diag(rg_geom *g, const double *U, const double *Bf, double gamma, void *stream, rg_diag_out *out);
 
 }  // namespace rg
