@@ -84,6 +84,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_stokes_T(rg_geom *, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_diag(rg_geom *, const double *, const double *, double, void *, rg_diag_out *) { return RG_ENOTSUP; }
     rg_status launch_fma_probe(double *, long long, int, void *) { return RG_ENOTSUP; }
+    rg_status launch_mfma_probe(double *, long long, int, int, void *) { return RG_ENOTSUP; }
     }
     static int run(int order) {
         rg_mesh_desc d{4, 3, 1.0, 2.0, 0, order - 1, 3};
