@@ -41,50 +41,75 @@ inline void normalize(double *a)
     a[0] /= n; a[1] /= n; a[2] /= n;
 }
 
-void slerp(const double *a, const double *b, double t, double *o)
+// point at fraction t of the great-circle arc from unit vector a to unit
+// vector b: a rotated by t times the arc's angle within the plane of a and b
+void arc_point(const double *a, const double *b, double t, double *o)
 {
-    double c[3];
-    cross(a, b, c);
-    double th = std::atan2(std::sqrt(dot(c, c)), dot(a, b));
-    double sa = std::sin((1 - t) * th) / std::sin(th), sb = std::sin(t * th) / std::sin(th);
-    for (int i = 0; i < 3; i++) o[i] = sa * a[i] + sb * b[i];
+    double u[3];
+    const double ab = dot(a, b);
+    for (int i = 0; i < 3; i++) u[i] = b[i] - ab * a[i];   // the in-plane direction orthogonal to a
+    const double un = std::sqrt(dot(u, u));
+    const double th = std::atan2(un, ab);
+    const double ca = std::cos(t * th), sa = std::sin(t * th) / un;
+    for (int i = 0; i < 3; i++) o[i] = ca * a[i] + sa * u[i];
 }
 
-void gc_meet(const double *p1, const double *p2, const double *q1, const double *q2, const double *hint, double *o)
+// where the great circle through p1, p2 meets the great circle through q1, q2:
+// the unit vector in the plane of p1, p2 orthogonal to the second circle's
+// normal, on the side of hint
+void circles_meet(const double *p1, const double *p2, const double *q1, const double *q2, const double *hint,
+                  double *o)
 {
-    double n1[3], n2[3];
-    cross(p1, p2, n1);
+    double n2[3];
     cross(q1, q2, n2);
-    cross(n1, n2, o);
+    const double s1 = dot(p1, n2), s2 = dot(p2, n2);
+    for (int i = 0; i < 3; i++) o[i] = s2 * p1[i] - s1 * p2[i];
     normalize(o);
     if (dot(o, hint) < 0) { o[0] = -o[0]; o[1] = -o[1]; o[2] = -o[2]; }
 }
 
-double lag(int mo, int a, double x)
-{
-    double v = 1.0, ta = -0.5 + double(a) / mo;
-    for (int b = 0; b <= mo; b++)
-        if (b != a) {
-            double tb = -0.5 + double(b) / mo;
-            v *= (x - tb) / (ta - tb);
-        }
-    return v;
-}
-
-double dlag(int mo, int a, double x)
-{
-    double s = 0.0, ta = -0.5 + double(a) / mo;
-    for (int b = 0; b <= mo; b++) {
-        if (b == a) continue;
-        double tb = -0.5 + double(b) / mo, v = 1.0 / (ta - tb);
-        for (int c = 0; c <= mo; c++)
-            if (c != a && c != b) {
-                double tc = -0.5 + double(c) / mo;
-                v *= (x - tc) / (ta - tc);
+// monomial coefficients of the 1-D Lagrange basis on mo + 1 equidistant nodes
+// of [-1/2, 1/2]: basis a is sum_k coef[a][k] x^k, expanded from its product
+// form once per order
+struct LagrangePoly {
+    double coef[4][4] = {};
+    explicit LagrangePoly(int mo)
+    {
+        for (int a = 0; a <= mo; a++) {
+            const double ta = -0.5 + double(a) / mo;
+            double pc[4] = {1.0, 0.0, 0.0, 0.0};   // running product, degree 0
+            int deg = 0;
+            for (int b = 0; b <= mo; b++) {
+                if (b == a) continue;
+                const double tb = -0.5 + double(b) / mo, den = ta - tb;
+                // multiply by (x - tb) / den
+                double nx[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int k = 0; k <= deg; k++) {
+                    nx[k + 1] += pc[k] / den;
+                    nx[k] -= tb * pc[k] / den;
+                }
+                deg++;
+                for (int k = 0; k <= deg; k++) pc[k] = nx[k];
             }
-        s += v;
+            for (int k = 0; k <= mo; k++) coef[a][k] = pc[k];
+        }
     }
-    return s;
+    // value and derivative of basis a at x (Horner)
+    void eval(int mo, int a, double x, double &v, double &d) const
+    {
+        v = coef[a][mo];
+        d = 0.0;
+        for (int k = mo - 1; k >= 0; k--) {
+            d = d * x + v;
+            v = v * x + coef[a][k];
+        }
+    }
+};
+
+const LagrangePoly &lagrange(int mo)
+{
+    static const LagrangePoly q2(2), q3(3);
+    return mo == 2 ? q2 : q3;
 }
 
 double det3(const double *j)
@@ -108,61 +133,64 @@ double falling(int a, int b)
 
 }  // namespace
 
-// surface nodes of column c: corners, slerp points on the edges, great-circle
-// intersections inside; node (a, b) at index a + (mo+1) b
+// surface nodes of column c (node (a, b) at index a + (mo + 1) b): the four
+// corners, points at equal arc fractions along the four edges, and inside
+// the meeting points of the great circles joining opposite edges' points
 void column_surface_nodes(const Mesh &m, int c, double *sn)
 {
     const int mo = m.map_order, n1 = mo + 1;
-    const double *v[4];
-    for (int k = 0; k < 4; k++) v[k] = &m.vpos[3 * m.col_v[4 * c + k]];
-    double bot[4][3], top[4][3], lef[4][3], rig[4][3], hint[3];
-    for (int a = 0; a <= mo; a++) {
-        double t = double(a) / mo;
-        if (a == 0) {
-            std::memcpy(bot[a], v[0], 24); std::memcpy(top[a], v[3], 24);
-            std::memcpy(lef[a], v[0], 24); std::memcpy(rig[a], v[1], 24);
-        } else if (a == mo) {
-            std::memcpy(bot[a], v[1], 24); std::memcpy(top[a], v[2], 24);
-            std::memcpy(lef[a], v[3], 24); std::memcpy(rig[a], v[2], 24);
-        } else {
-            slerp(v[0], v[1], t, bot[a]);
-            slerp(v[3], v[2], t, top[a]);
-            slerp(v[0], v[3], t, lef[a]);
-            slerp(v[1], v[2], t, rig[a]);
+    const double *v0 = &m.vpos[3 * m.col_v[4 * c]], *v1 = &m.vpos[3 * m.col_v[4 * c + 1]];
+    const double *v2 = &m.vpos[3 * m.col_v[4 * c + 2]], *v3 = &m.vpos[3 * m.col_v[4 * c + 3]];
+    auto node = [&](int a, int b) { return &sn[3 * (a + n1 * b)]; };
+    // the boundary: edges v0 -> v1 (b = 0), v3 -> v2 (b = mo), v0 -> v3
+    // (a = 0), v1 -> v2 (a = mo), corners included
+    for (int j = 0; j <= mo; j++) {
+        const double t = double(j) / mo;
+        arc_point(v0, v1, t, node(j, 0));
+        arc_point(v3, v2, t, node(j, mo));
+        if (j > 0 && j < mo) {
+            arc_point(v0, v3, t, node(0, j));
+            arc_point(v1, v2, t, node(mo, j));
         }
     }
-    for (int i = 0; i < 3; i++) hint[i] = v[0][i] + v[1][i] + v[2][i] + v[3][i];
-    for (int b = 0; b <= mo; b++)
-        for (int a = 0; a <= mo; a++) {
-            double *p = &sn[3 * (a + n1 * b)];
-            if (b == 0) std::memcpy(p, bot[a], 24);
-            else if (b == mo) std::memcpy(p, top[a], 24);
-            else if (a == 0) std::memcpy(p, lef[b], 24);
-            else if (a == mo) std::memcpy(p, rig[b], 24);
-            else gc_meet(bot[a], top[a], lef[b], rig[b], hint, p);
-        }
+    for (int i = 0; i < 3; i++) {   // the end points exactly
+        node(0, 0)[i] = v0[i]; node(mo, 0)[i] = v1[i]; node(mo, mo)[i] = v2[i]; node(0, mo)[i] = v3[i];
+    }
+    double hint[3];
+    for (int i = 0; i < 3; i++) hint[i] = v0[i] + v1[i] + v2[i] + v3[i];
+    for (int b = 1; b < mo; b++)
+        for (int a = 1; a < mo; a++) circles_meet(node(a, 0), node(a, mo), node(0, b), node(mo, b), hint, node(a, b));
 }
 
-// map of a zone with surface nodes sn between radii r0 < r1; jac[n*3+d] = dx_n/dxi_d
+// map of a zone with surface nodes sn between radii r0 < r1, x = R(xi_2)
+// S(xi_0, xi_1) with S the tensor Lagrange interpolant of the surface nodes
+// and R linear in xi_2; jac[n*3+d] = dx_n/dxi_d.  S is evaluated curve by
+// curve: first along xi_0 through each row b of nodes, then along xi_1
+// through the rows' values.
 void zone_map(int mo, const double *sn, double r0, double r1, const double *xi, double *x, double *jac)
 {
     const int n1 = mo + 1;
-    double La[4], Lb[4], dLa[4], dLb[4];
+    const LagrangePoly &L = lagrange(mo);
+    double la[4], dla[4], lb[4], dlb[4];
     for (int a = 0; a <= mo; a++) {
-        La[a] = lag(mo, a, xi[0]); Lb[a] = lag(mo, a, xi[1]);
-        dLa[a] = dlag(mo, a, xi[0]); dLb[a] = dlag(mo, a, xi[1]);
+        L.eval(mo, a, xi[0], la[a], dla[a]);
+        L.eval(mo, a, xi[1], lb[a], dlb[a]);
     }
     double S[3] = {0, 0, 0}, Sa[3] = {0, 0, 0}, Sb[3] = {0, 0, 0};
-    for (int b = 0; b <= mo; b++)
-        for (int a = 0; a <= mo; a++) {
-            const double *p = &sn[3 * (a + n1 * b)];
+    for (int b = 0; b <= mo; b++) {
+        double row[3] = {0, 0, 0}, drow[3] = {0, 0, 0};   // the row curve at xi_0 and its xi_0 derivative
+        for (int a = 0; a <= mo; a++)
             for (int i = 0; i < 3; i++) {
-                S[i] += La[a] * Lb[b] * p[i];
-                Sa[i] += dLa[a] * Lb[b] * p[i];
-                Sb[i] += La[a] * dLb[b] * p[i];
+                row[i] += la[a] * sn[3 * (a + n1 * b) + i];
+                drow[i] += dla[a] * sn[3 * (a + n1 * b) + i];
             }
+        for (int i = 0; i < 3; i++) {
+            S[i] += lb[b] * row[i];
+            Sa[i] += lb[b] * drow[i];
+            Sb[i] += dlb[b] * row[i];
         }
-    double R = (0.5 - xi[2]) * r0 + (0.5 + xi[2]) * r1, dR = r1 - r0;
+    }
+    const double h = 0.5 + xi[2], R = r0 + h * (r1 - r0), dR = r1 - r0;
     for (int i = 0; i < 3; i++) {
         x[i] = R * S[i];
         if (jac) {
