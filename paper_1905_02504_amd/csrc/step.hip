@@ -606,7 +606,10 @@ __global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__
 // wavefronts in flight).  With FP32 inputs the compiler's own schedule for
 // three tiles took 218 VGPRs beside the accumulators (one wavefront per SIMD,
 // 23.3 ms at 6 x 128^3 against 16.3 ms for one tile); the occupancy hint of
-// two wavefronts per SIMD holds both forms to 242 registers (FP32: 14.5 ms)
+// two wavefronts per SIMD holds both forms under 256 registers.  Face ids come
+// from a per-column table in LDS, so the per-lane choice of face costs no
+// branches: with a six-way select in registers the FP32 form took 14.4 ms,
+// with the table 10.9 ms (FP64 12.0 -> 11.8 ms)
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
 constexpr int BMAP_TILES = 3;
@@ -624,18 +627,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void bm
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int c = lb / nt, tile = lb % nt;
     const int l = threadIdx.x, g = l >> 4, jz = l & 15;
-    int kk[NT];
+    // face id of a zone's local face lf (0..3 angular, 4, 5 radial) is
+    // s_fbase[lf] + its shell index: a table, so that lanes choosing different
+    // faces in one K step read it without branching
+    __shared__ i64 s_fbase[6];
+    if (l < 6)
+        s_fbase[l] = l >= 4 ? (i64)c * (G.K + 1) + (l - 4) : G.NRF + (i64)G.col_ae[4 * c + l] * G.K;
+    __syncthreads();
+    int kk[NT], ks[NT];
     bool active[NT];
-    i64 z[NT], fr[NT], fa[NT][4];
+    i64 z[NT];
 #pragma unroll
     for (int t = 0; t < NT; t++) {
         kk[t] = (tile * NT + t) * 16 + jz;
         active[t] = kk[t] < KR;
-        const int k = G.g - 1 + (active[t] ? kk[t] : 0);
-        z[t] = (i64)c * G.K + k;
-        fr[t] = (i64)c * (G.K + 1) + k;
-#pragma unroll
-        for (int lf = 0; lf < 4; lf++) fa[t][lf] = G.NRF + (i64)G.col_ae[4 * c + lf] * G.K + k;
+        ks[t] = G.g - 1 + (active[t] ? kk[t] : 0);
+        z[t] = (i64)c * G.K + ks[t];
     }
     const double *Mb = G.Mb + (i64)c * NIN * NOUT;
     dbl4 acc[NT][MT];
@@ -643,29 +650,55 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void bm
     for (int t = 0; t < NT; t++)
 #pragma unroll
         for (int m = 0; m < MT; m++) acc[t][m] = dbl4{0.0, 0.0, 0.0, 0.0};
+    auto face_of = [&](int t, int lf) -> i64 { return s_fbase[lf] + ks[t]; };
 #pragma unroll 2
     for (int s = 0; s < KT; s++) {
-        // B operands: input j = 4s + g of zone jz of each tile
+        // B operands: input j = 4s + g of zone jz of each tile.  The inputs
+        // are the zone's WENO B coefficients (j < NA; the zone mean, a = 0,
+        // comes from U), the faces' limited nodal normal B (j < NQ) and the
+        // face averages.  s is uniform, so the kind of a K step is decided
+        // by scalar branches; only the steps that straddle two kinds take the
+        // per-lane choice.  Inactive zones (past the column's top) read a
+        // valid zone and enter as zeros.
         const int j = 4 * s + g;
         double b[NT];
+        if (4 * s + 3 < NA) {
+            const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
+            // does any lane group of this step take a zone mean from U?
+            const bool any_mean = (4 * s) / (T::NC + 1) != (4 * s + 3) / (T::NC + 1) || (4 * s) % (T::NC + 1) == 0;
 #pragma unroll
-        for (int t = 0; t < NT; t++) {
-            b[t] = 0.0;
-            if (active[t]) {
-                if (j < NA) {
-                    const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
-                    b[t] = a == 0 ? U[(i64)(5 + comp) * G.Z + z[t]]
-                                  : double(wc[((i64)(5 + comp) * T::NC + a - 1) * G.Z + z[t]]);
-                } else {
-                    const int lf = j < NQ ? (j - NA) / T::Q : j - NQ;
-                    const i64 idx = lf == 4   ? fr[t]
-                                    : lf == 5 ? fr[t] + 1
-                                    : lf == 0 ? fa[t][0]
-                                    : lf == 1 ? fa[t][1]
-                                    : lf == 2 ? fa[t][2]
-                                              : fa[t][3];
-                    b[t] = j < NQ ? double(bnod[(i64)((j - NA) % T::Q) * G.NF + idx]) : Bf[idx];
-                }
+            for (int t = 0; t < NT; t++) {
+                const double w = double(wc[((i64)(5 + comp) * T::NC + (a > 0 ? a - 1 : 0)) * G.Z + z[t]]);
+                const double u = any_mean ? U[(i64)(5 + comp) * G.Z + z[t]] : 0.0;
+                b[t] = active[t] ? (a == 0 ? u : w) : 0.0;
+            }
+        } else if (4 * s >= NA && 4 * s + 3 < NQ) {
+            const int q = (j - NA) % T::Q, lf = (j - NA) / T::Q;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const double v = double(bnod[(i64)q * G.NF + face_of(t, lf)]);
+                b[t] = active[t] ? v : 0.0;
+            }
+        } else if (4 * s >= NQ) {
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const double v = Bf[face_of(t, j - NQ)];
+                b[t] = active[t] ? v : 0.0;
+            }
+        } else {
+            // every lane reads one valid element of each source and keeps
+            // the one its input index names
+            const int jw = j < NA ? j : NA - 1, jq = j < NA ? 0 : j < NQ ? j - NA : 6 * T::Q - 1;
+            const int comp = jw / (T::NC + 1), a = jw % (T::NC + 1);
+            const int lfq = jq / T::Q, lff = j < NQ ? 0 : j - NQ;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const double u = U[(i64)(5 + comp) * G.Z + z[t]];
+                const double w = double(wc[((i64)(5 + comp) * T::NC + (a > 0 ? a - 1 : 0)) * G.Z + z[t]]);
+                const double q = double(bnod[(i64)(jq % T::Q) * G.NF + face_of(t, lfq)]);
+                const double f = Bf[face_of(t, lff)];
+                const double v = j < NA ? (a == 0 ? u : w) : j < NQ ? q : f;
+                b[t] = active[t] ? v : 0.0;
             }
         }
         const double *mrow = Mb + (i64)j * NOUT;
