@@ -7,7 +7,9 @@ it; the GPU library never imports or links it.
 
 Every part is pinned by the tests in tests/test_oracle_pins.py,
 tests/test_oracle_pins_solvers.py (fast speed, HLL, the edge solvers and the
-WENO-AO internals), tests/test_oracle_fallback.py and tests/test_tube_init.py.
+WENO-AO internals), tests/test_oracle_fallback.py, tests/test_tube_init.py
+and, for the triangular-prism element on the icosahedral mesh (prism.c,
+prism.py), tests/test_oracle_prism.py.
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "scheme_cx.c", "init.c", "oracle.c"]
+_SOURCES = ["la.c", "refel.c", "mesh.c", "geom.c", "scheme.c", "scheme_cx.c", "init.c", "oracle.c", "prism.c"]
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")

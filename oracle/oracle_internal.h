@@ -42,6 +42,7 @@ typedef struct {
 } rgo_refel;
 
 int refel_init(rgo_refel *r, int order);
+int refel_spacetime(rgo_refel *r, int M, int nq, const double *xq, const double *wq);
 void refel_free(rgo_refel *r);
 double refel_psi(const rgo_refel *r, int l, const double *xi);
 double refel_dpsi(const rgo_refel *r, int l, int d, const double *xi);

@@ -1,0 +1,348 @@
+/*
+ * Triangular-prism element of the oracle (TEST INFRASTRUCTURE ONLY: only the
+ * test-suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it; it shares no code with the GPU library).
+ *
+ * - The reference element is the equilateral prism with unit edges and its
+ *   centroid at the origin (Appendices B-D): triangle vertices
+ *   (-1/2, -1/(2 sqrt 3)), (1/2, -1/(2 sqrt 3)), (0, 1/sqrt 3), zeta in
+ *   [-1/2, 1/2].  Nodes (Fig. 7): the six vertices; at third order the
+ *   vertical-edge midpoints and the triangle-edge midpoints; at fourth order
+ *   the vertical-edge thirds, the triangle-edge thirds and the two triangle
+ *   centroids, numbered as in eqs. (C.2)-(C.16) and (D.2)-(D.27).
+ *   Appendix B prints the second-order nodes with a vertex at the origin,
+ *   but its bases (B.10)-(B.15) are those of the centred prism; the centred
+ *   prism is used at every order.
+ * - Monomials of eqs. (5.12)-(5.14); nodal Lagrange basis by eq. (5.3).
+ * - Space-time Galerkin system of eqs. (5.24)-(5.29) integrated over the
+ *   prism: a collapsed (Duffy) Gauss rule on the triangle times Gauss points
+ *   in zeta, exact for the integrands' degrees.
+ * - Geometry of a zone of the icosahedral geodesic mesh (Sections II.a-II.b):
+ *   the zone's spherical triangle (vertices a, b, c on the unit sphere,
+ *   counter-clockwise seen from outside) is interpolated by a triangle
+ *   Lagrange map of degree order-1 through nodes on the sphere -- vertices,
+ *   equidistant points along the great-circle edges and, for the cubic map,
+ *   the spherical centroid (a + b + c)/|a + b + c|, where the three
+ *   great-circle medians meet -- and the radial direction is linear:
+ *   x = [(1/2 - zeta) r0 + (1/2 + zeta) r1] S(xi, eta).
+ *   At the element nodes: position, Jacobian, and the flux metrics of
+ *   eq. (5.11) in the conservative curl form (their discrete divergence
+ *   vanishes, so a uniform state stays uniform).
+ */
+#include "oracle_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+int rgo_predict_element(const rgo_refel *r, double gamma, double dt, const double *J, const double *met,
+                        const double *Ua, double *Ulev, double *avgU, double *avgF);
+
+static const double S3 = 1.7320508075688772935;
+
+/* triangle vertices of the reference prism */
+static void tri_vertex(int k, double *v)
+{
+    static const double vx[3] = {-0.5, 0.5, 0.0};
+    v[0] = vx[k];
+    v[1] = (k == 2) ? 1.0 / S3 : -0.5 / S3;
+}
+
+static int add_node(rgo_refel *r, int n, double x, double y, double z)
+{
+    r->node[n][0] = x;
+    r->node[n][1] = y;
+    r->node[n][2] = z;
+    return n + 1;
+}
+
+/* point at fraction t along the triangle edge from vertex k to vertex k+1 */
+static void tri_edge_point(int k, double t, double *p)
+{
+    double a[2], b[2];
+    tri_vertex(k, a);
+    tri_vertex((k + 1) % 3, b);
+    p[0] = a[0] + t * (b[0] - a[0]);
+    p[1] = a[1] + t * (b[1] - a[1]);
+}
+
+/* nodes of Fig. 7 in the numbering of Appendices B-D */
+static int prism_nodes(rgo_refel *r, int order)
+{
+    int n = 0;
+    double v[2], p[2];
+    for (int s = 0; s < 2; s++)            /* vertices: top (zeta = 1/2), then bottom */
+        for (int k = 0; k < 3; k++) { tri_vertex(k, v); n = add_node(r, n, v[0], v[1], s ? -0.5 : 0.5); }
+    if (order == 3) {
+        for (int k = 0; k < 3; k++) { tri_vertex(k, v); n = add_node(r, n, v[0], v[1], 0.0); }
+        for (int s = 0; s < 2; s++)
+            for (int k = 0; k < 3; k++) { tri_edge_point(k, 0.5, p); n = add_node(r, n, p[0], p[1], s ? -0.5 : 0.5); }
+    } else if (order == 4) {
+        for (int s = 0; s < 2; s++)
+            for (int k = 0; k < 3; k++) { tri_vertex(k, v); n = add_node(r, n, v[0], v[1], s ? -1.0 / 6.0 : 1.0 / 6.0); }
+        for (int s = 0; s < 2; s++)
+            for (int k = 0; k < 3; k++)
+                for (int t = 1; t <= 2; t++) {
+                    tri_edge_point(k, t / 3.0, p);
+                    n = add_node(r, n, p[0], p[1], s ? -0.5 : 0.5);
+                }
+        n = add_node(r, n, 0.0, 0.0, 0.5);
+        n = add_node(r, n, 0.0, 0.0, -0.5);
+    }
+    return n;
+}
+
+/* monomial exponents (a, b, c) of xi^a eta^b zeta^c, eqs. (5.12)-(5.14) */
+static const int MONO2[6][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {0, 1, 1}};
+static const int MONO3[15][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0},
+                                 {1, 0, 1}, {0, 1, 1}, {1, 1, 1}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}};
+static const int MONO4[26][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2},
+                                 {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {3, 0, 0}, {0, 3, 0}, {0, 0, 3}, {2, 1, 0},
+                                 {2, 0, 1}, {1, 2, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}, {1, 1, 1}, {1, 0, 3},
+                                 {0, 1, 3}, {3, 0, 1}, {0, 3, 1}, {2, 1, 1}, {1, 2, 1}};
+
+/* nodes, monomials and the nodal basis only */
+static int prism_basis_init(rgo_refel *r, int order)
+{
+    memset(r, 0, sizeof(*r));
+    if (order < 2 || order > 4) return -1;
+    r->order = order;
+    r->N = prism_nodes(r, order);
+    const int(*mono)[3] = order == 2 ? MONO2 : order == 3 ? MONO3 : MONO4;
+    for (int k = 0; k < r->N; k++) memcpy(r->exps[k], mono[k], sizeof(int) * 3);
+    return lagrange3(r->N, &r->node[0][0], &r->exps[0][0], r->coef);
+}
+
+int prism_refel_init(rgo_refel *r, int order)
+{
+    if (prism_basis_init(r, order)) return -1;
+
+    /* prism quadrature: on the triangle x = V1 + s (V2 - V1) + t (V3 - V1),
+     * t = (1 - s) w, dA = 2 |T| (1 - s) ds dw with |T| = sqrt(3)/4; six
+     * Gauss points in s, w and zeta integrate degree 11, above the degree 9
+     * of psi_i dpsi_l psi_j */
+    const int ng = 6;
+    double gx[8], gw[8], v1[2], v2[2], v3[2];
+    gauss01(ng, gx, gw);
+    tri_vertex(0, v1);
+    tri_vertex(1, v2);
+    tri_vertex(2, v3);
+    const int nq = ng * ng * ng;
+    double *xq = malloc(sizeof(double) * 3 * nq), *wq = malloc(sizeof(double) * nq);
+    int n = 0;
+    for (int i = 0; i < ng; i++)
+        for (int j = 0; j < ng; j++)
+            for (int k = 0; k < ng; k++) {
+                double s = gx[i], t = (1.0 - s) * gx[j];
+                xq[3 * n] = v1[0] + s * (v2[0] - v1[0]) + t * (v3[0] - v1[0]);
+                xq[3 * n + 1] = v1[1] + s * (v2[1] - v1[1]) + t * (v3[1] - v1[1]);
+                xq[3 * n + 2] = gx[k] - 0.5;
+                wq[n++] = 2.0 * (S3 / 4.0) * (1.0 - s) * gw[i] * gw[j] * gw[k];
+            }
+    int rc = refel_spacetime(r, order, nq, xq, wq);
+    free(xq);
+    free(wq);
+    return rc;
+}
+
+/* ---------------------------------------------------------------- geometry */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void unit3(double *a)
+{
+    double n = sqrt(dot3(a, a));
+    for (int i = 0; i < 3; i++) a[i] /= n;
+}
+
+/* point at fraction t of the central angle along the great circle from a to b */
+static void great_circle_point(const double *a, const double *b, double t, double *p)
+{
+    double om = acos(fmax(-1.0, fmin(1.0, dot3(a, b)))), s = sin(om);
+    double wa = sin((1.0 - t) * om) / s, wb = sin(t * om) / s;
+    for (int i = 0; i < 3; i++) p[i] = wa * a[i] + wb * b[i];
+}
+
+typedef struct {
+    int mo, nm;
+    double node[10][3];     /* reference-triangle lattice nodes (zeta = 0) */
+    int exps[10][3];
+    double coef[100];
+    double sph[10][3];      /* the matching points on the unit sphere */
+} tri_map;
+
+/* lattice nodes (i, j, k)/mo in barycentric coordinates and their points on
+ * the sphere for the spherical triangle (a, b, c) */
+static int tri_map_init(tri_map *t, int mo, const double *a, const double *b, const double *c)
+{
+    const double *P[3] = {a, b, c};
+    double V[3][2];
+    for (int k = 0; k < 3; k++) tri_vertex(k, V[k]);
+    t->mo = mo;
+    int n = 0;
+    for (int i = mo; i >= 0; i--)
+        for (int j = mo - i; j >= 0; j--) {
+            int k = mo - i - j;
+            double l[3] = {(double)i / mo, (double)j / mo, (double)k / mo};
+            t->node[n][0] = l[0] * V[0][0] + l[1] * V[1][0] + l[2] * V[2][0];
+            t->node[n][1] = l[0] * V[0][1] + l[1] * V[1][1] + l[2] * V[2][1];
+            t->node[n][2] = 0.0;
+            int nzero = (i == 0) + (j == 0) + (k == 0);
+            if (nzero == 2) {
+                const double *v = i ? a : j ? b : c;
+                memcpy(t->sph[n], v, sizeof(double) * 3);
+            } else if (nzero == 1) {
+                /* on the edge between the two vertices with nonzero weight */
+                int p = i == 0 ? 1 : 0, q = k == 0 ? 1 : 2;
+                great_circle_point(P[p], P[q], l[q] / (l[p] + l[q]), t->sph[n]);
+            } else {
+                for (int d = 0; d < 3; d++) t->sph[n][d] = a[d] + b[d] + c[d];
+                unit3(t->sph[n]);
+            }
+            n++;
+        }
+    t->nm = n;
+    n = 0;
+    for (int e = 0; e <= mo; e++)
+        for (int f = 0; e + f <= mo; f++) {
+            t->exps[n][0] = e;
+            t->exps[n][1] = f;
+            t->exps[n][2] = 0;
+            n++;
+        }
+    return lagrange3(t->nm, &t->node[0][0], &t->exps[0][0], t->coef);
+}
+
+/* x(xi) and jac[i][j] = d x_i / d xi_j */
+static void prism_map(const tri_map *t, double r0, double r1, const double *xi, double *x, double *jac)
+{
+    double S[3] = {0, 0, 0}, Sx[3] = {0, 0, 0}, Sy[3] = {0, 0, 0};
+    for (int l = 0; l < t->nm; l++) {
+        double p = 0.0, px = 0.0, py = 0.0;
+        for (int k = 0; k < t->nm; k++) {
+            double ck = t->coef[k * t->nm + l];
+            p += ck * mono3(t->exps[k], xi);
+            px += ck * dmono3(t->exps[k], 0, xi);
+            py += ck * dmono3(t->exps[k], 1, xi);
+        }
+        for (int d = 0; d < 3; d++) {
+            S[d] += p * t->sph[l][d];
+            Sx[d] += px * t->sph[l][d];
+            Sy[d] += py * t->sph[l][d];
+        }
+    }
+    double R = (0.5 - xi[2]) * r0 + (0.5 + xi[2]) * r1, dR = r1 - r0;
+    for (int d = 0; d < 3; d++) {
+        x[d] = R * S[d];
+        jac[d * 3 + 0] = R * Sx[d];
+        jac[d * 3 + 1] = R * Sy[d];
+        jac[d * 3 + 2] = dR * S[d];
+    }
+}
+
+static double det3(const double *j)
+{
+    return j[0] * (j[4] * j[8] - j[5] * j[7]) - j[1] * (j[3] * j[8] - j[5] * j[6]) + j[2] * (j[3] * j[7] - j[4] * j[6]);
+}
+
+/* node positions x[N][3], Jacobians J[N] and curl-form metrics
+ * met[N][d][n] = J d xi_d / d x_n of one zone */
+static int zone_geometry(const rgo_refel *r, const double *a, const double *b, const double *c, double r0,
+                         double r1, double *x, double *J, double *met)
+{
+    tri_map t;
+    if (tri_map_init(&t, r->order - 1, a, b, c)) return -1;
+    const int N = r->N;
+    double *jac = malloc(sizeof(double) * N * 9), cen[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++) {
+        prism_map(&t, r0, r1, r->node[i], &x[3 * i], &jac[9 * i]);
+        J[i] = det3(&jac[9 * i]);
+        for (int d = 0; d < 3; d++) cen[d] += x[3 * i + d] / N;
+    }
+    /* V[i][n][j] = (x_l - c_l) d x_m / d xi_j with (n, m, l) cyclic;
+     * (J a^d)_n = -(curl_xi of the interpolated V_n)_d */
+    double *V = malloc(sizeof(double) * N * 9);
+    for (int i = 0; i < N; i++)
+        for (int nn = 0; nn < 3; nn++) {
+            int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+            for (int j = 0; j < 3; j++) V[i * 9 + nn * 3 + j] = (x[3 * i + ll] - cen[ll]) * jac[9 * i + mm * 3 + j];
+        }
+    for (int i = 0; i < N; i++)
+        for (int nn = 0; nn < 3; nn++) {
+            double dV[3][3] = {{0}};
+            for (int l = 0; l < N; l++)
+                for (int d = 0; d < 3; d++) {
+                    double dp = refel_dpsi(r, l, d, r->node[i]);
+                    for (int j = 0; j < 3; j++) dV[j][d] += V[l * 9 + nn * 3 + j] * dp;
+                }
+            met[i * 9 + 0 * 3 + nn] = -(dV[2][1] - dV[1][2]);
+            met[i * 9 + 1 * 3 + nn] = -(dV[0][2] - dV[2][0]);
+            met[i * 9 + 2 * 3 + nn] = -(dV[1][0] - dV[0][1]);
+        }
+    free(V);
+    free(jac);
+    return 0;
+}
+
+/* geometry of nz zones: abc[z] = the triangle's vertices a, b, c (9
+ * doubles), r01[z] = inner and outer radius; x[z][N][3], J[z][N],
+ * met[z][N][9] */
+int rgo_prism_geometry(int order, int nz, const double *abc, const double *r01, double *x, double *J, double *met)
+{
+    rgo_refel r;
+    if (prism_basis_init(&r, order)) return -1;
+    const int N = r.N;
+    int rc = 0;
+    for (int z = 0; z < nz && !rc; z++)
+        rc = zone_geometry(&r, &abc[9 * z], &abc[9 * z + 3], &abc[9 * z + 6], r01[2 * z], r01[2 * z + 1],
+                           &x[(size_t)z * N * 3], &J[(size_t)z * N], &met[(size_t)z * N * 9]);
+    return rc;
+}
+
+/* reference-element matrices (as rgo_refel_query, for the prism) */
+int rgo_prism_refel_query(int order, int *NM, double *tau, double *wt, double *nodes, int *exps, double *coef,
+                          double *D, double *Kd, double *Kd0, double *Kt0)
+{
+    rgo_refel r;
+    if (prism_refel_init(&r, order)) return -1;
+    int N = r.N, M = r.M, E = (M - 1) * N;
+    NM[0] = N;
+    NM[1] = M;
+    if (tau) memcpy(tau, r.tau, sizeof(double) * M);
+    if (wt) memcpy(wt, r.wt, sizeof(double) * M);
+    if (nodes) memcpy(nodes, r.node, sizeof(double) * 3 * N);
+    if (exps) memcpy(exps, r.exps, sizeof(int) * 3 * N);
+    if (coef)
+        for (int k = 0; k < N; k++)
+            for (int l = 0; l < N; l++) coef[k * N + l] = r.coef[k * N + l];
+    if (D)
+        for (int d = 0; d < 3; d++)
+            for (int i = 0; i < N; i++)
+                for (int l = 0; l < N; l++) D[(d * N + i) * N + l] = refel_dpsi(&r, l, d, r.node[i]);
+    for (int d = 0; d < 3; d++) {
+        if (Kd) memcpy(&Kd[(size_t)d * E * E], r.Kd[d], sizeof(double) * E * E);
+        if (Kd0) memcpy(&Kd0[(size_t)d * E * N], r.Kd0[d], sizeof(double) * E * N);
+    }
+    if (Kt0) memcpy(Kt0, r.Kt0, sizeof(double) * E * N);
+    refel_free(&r);
+    return 0;
+}
+
+/* the ADER-CG predictor (Section V.d) of nz prism zones, one after another:
+ * J[z][N], met[z][N][9], Ua[z][N][8] node-major as in rgo_predict_element;
+ * Ulev[z][M][N][8] (J times the state at every time level; may be NULL),
+ * avgU[z][N][8], avgF[z][N][3][8] */
+int rgo_prism_predict(int order, int nz, double gamma, double dt, const double *J, const double *met,
+                      const double *Ua, double *Ulev, double *avgU, double *avgF)
+{
+    rgo_refel r;
+    if (prism_refel_init(&r, order)) return -1;
+    const int N = r.N;
+    int rc = 0;
+    for (int z = 0; z < nz && !rc; z++)
+        rc = rgo_predict_element(&r, gamma, dt, &J[(size_t)z * N], &met[(size_t)z * N * 9],
+                                 &Ua[(size_t)z * N * NVAR], Ulev ? &Ulev[(size_t)z * r.M * N * NVAR] : NULL,
+                                 &avgU[(size_t)z * N * NVAR],
+                                 &avgF[(size_t)z * N * 3 * NVAR]);
+    refel_free(&r);
+    return rc;
+}

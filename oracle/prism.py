@@ -1,0 +1,159 @@
+"""Triangular-prism element on the icosahedral geodesic mesh, oracle side
+(TEST INFRASTRUCTURE ONLY: only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may use it; the GPU library never imports
+or links it).
+
+- Mesh (Section II.a, Fig. 1): the icosahedron projected to the unit sphere
+  gives 20 spherical triangles (level 0); each level splits every triangle
+  into four by the great-circle midpoints of its edges, (a + b)/|a + b|, so
+  level L has 20 4^L triangles.  The radial direction is cut into n_rad
+  shells with logarithmically spaced radii (Section VII), and each
+  (triangle, shell) pair is a curved prism zone (Fig. 2).
+- Numbering: vertices 0 (north pole), 1-5 (upper ring at z = 1/sqrt 5,
+  longitudes 72 k degrees), 6-10 (lower ring, longitudes 36 + 72 k), 11
+  (south pole); the 20 level-0 faces are, for k = 0..4 (k1 = k + 1 mod 5),
+  (0, 1+k, 1+k1), (1+k, 6+k, 1+k1), (1+k1, 6+k, 6+k1), (11, 6+k1, 6+k), each
+  turned counter-clockwise as seen from outside; the children of triangle t
+  (a, b, c) with midpoints m_ab, m_bc, m_ca are 4t + (0: a m_ab m_ca,
+  1: m_ab b m_bc, 2: m_ca m_bc c, 3: m_ab m_bc m_ca).  Zone z = t n_rad + k.
+- Zone geometry and the element predictor are in prism.c.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import oracle as O
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+NODES = {2: 6, 3: 15, 4: 26}
+
+
+def _lib():
+    L = O.lib()
+    if not getattr(L, "_prism_ready", False):
+        L.rgo_prism_refel_query.restype = C.c_int
+        L.rgo_prism_refel_query.argtypes = [C.c_int, _ip] + [C.c_void_p] * 9
+        L.rgo_prism_geometry.restype = C.c_int
+        L.rgo_prism_geometry.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.rgo_prism_predict.restype = C.c_int
+        L.rgo_prism_predict.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp, C.c_void_p,
+                                        _dp, _dp]
+        L._prism_ready = True
+    return L
+
+
+def refel(order):
+    """Prism reference element: nodes, monomials, basis coefficients
+    (psi_l = sum_k coef[k, l] m_k), nodal derivative matrices D[d, i, l] =
+    d psi_l / d xi_d at node i, and the full-Galerkin matrices of eq. (5.29)."""
+    N, M = NODES[order], order
+    E = (M - 1) * N
+    NM = np.zeros(2, np.int32)
+    tau, wt = np.zeros(M), np.zeros(M)
+    nodes, exps, coef = np.zeros((N, 3)), np.zeros((N, 3), np.int32), np.zeros((N, N))
+    D, Kd, Kd0, Kt0 = np.zeros((3, N, N)), np.zeros((3, E, E)), np.zeros((3, E, N)), np.zeros((E, N))
+    rc = _lib().rgo_prism_refel_query(order, NM, tau.ctypes, wt.ctypes, nodes.ctypes, exps.ctypes, coef.ctypes,
+                                      D.ctypes, Kd.ctypes, Kd0.ctypes, Kt0.ctypes)
+    if rc:
+        raise ValueError("prism reference element failed")
+    return dict(N=N, M=M, tau=tau, wt=wt, nodes=nodes, exps=exps, coef=coef, D=D, Kd=Kd, Kd0=Kd0, Kt0=Kt0)
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def icosahedron():
+    """The 12 vertices and 20 outward counter-clockwise faces of level 0."""
+    h, rho = 1 / np.sqrt(5), 2 / np.sqrt(5)
+    V = [np.array([0.0, 0.0, 1.0])]
+    for k in range(5):
+        a = 2 * np.pi * k / 5
+        V.append(np.array([rho * np.cos(a), rho * np.sin(a), h]))
+    for k in range(5):
+        a = 2 * np.pi * (k + 0.5) / 5
+        V.append(np.array([rho * np.cos(a), rho * np.sin(a), -h]))
+    V.append(np.array([0.0, 0.0, -1.0]))
+    F = []
+    for k in range(5):
+        k1 = (k + 1) % 5
+        F += [(0, 1 + k, 1 + k1), (1 + k, 6 + k, 1 + k1), (1 + k1, 6 + k, 6 + k1), (11, 6 + k1, 6 + k)]
+    out = []
+    for a, b, c in F:
+        if np.cross(V[b] - V[a], V[c] - V[a]) @ (V[a] + V[b] + V[c]) < 0:
+            b, c = c, b
+        out.append((a, b, c))
+    return np.array(V), np.array(out, np.int64)
+
+
+def subdivide(V, T):
+    """One level of great-circle bisection: vertices shared through an edge
+    table, children in the order documented above."""
+    V = list(V)
+    mid = {}
+
+    def m(i, j):
+        key = (min(i, j), max(i, j))
+        if key not in mid:
+            mid[key] = len(V)
+            V.append(_unit(V[i] + V[j]))
+        return mid[key]
+
+    out = np.empty((4 * len(T), 3), np.int64)
+    for t, (a, b, c) in enumerate(T):
+        ab, bc, ca = m(a, b), m(b, c), m(c, a)
+        out[4 * t:4 * t + 4] = [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+    return np.array(V), out
+
+
+class OraclePrismMesh:
+    """Icosahedral geodesic prism mesh with per-zone geometry on demand."""
+
+    def __init__(self, level, n_rad, r_in=1.0, r_out=2.0, order=4):
+        V, T = icosahedron()
+        for _ in range(level):
+            V, T = subdivide(V, T)
+        self.level, self.n_rad, self.order = level, n_rad, order
+        self.vert, self.tri = V, T
+        self.ntri = len(T)
+        self.nz = self.ntri * n_rad
+        self.N = NODES[order]
+        self.radius = r_in * (r_out / r_in) ** (np.arange(n_rad + 1) / n_rad)
+
+    def zone_tri_shell(self, zones):
+        zones = np.asarray(zones, np.int64)
+        return zones // self.n_rad, zones % self.n_rad
+
+    def geometry(self, zones):
+        """x[z][N][3], J[z][N], met[z][N][d][n] of the given zones."""
+        t, k = self.zone_tri_shell(zones)
+        nz = len(t)
+        abc = np.ascontiguousarray(self.vert[self.tri[t]].reshape(nz, 9))
+        r01 = np.ascontiguousarray(np.stack([self.radius[k], self.radius[k + 1]], 1))
+        x, J, met = np.zeros((nz, self.N, 3)), np.zeros((nz, self.N)), np.zeros((nz, self.N, 3, 3))
+        if _lib().rgo_prism_geometry(self.order, nz, abc, r01, x, J, met):
+            raise ValueError("prism geometry failed")
+        return x, J, met
+
+    def predict(self, zones, Ua, dt, gamma=5.0 / 3.0):
+        """Element predictor of the given zones from nodal states Ua[z][N][8]:
+        time-averaged nodal state avgU[z][N][8] and flux avgF[z][N][3][8]."""
+        _, J, met = self.geometry(zones)
+        return predict(self.order, J, met, Ua, dt, gamma)
+
+
+def predict(order, J, met, Ua, dt, gamma=5.0 / 3.0, levels=False):
+    """avgU[z][N][8], avgF[z][N][3][8] (and with levels=True also
+    Ulev[z][M][N][8], J times the state at each time level)."""
+    nz, N = J.shape
+    Ua = np.ascontiguousarray(Ua, dtype=np.float64)
+    aU, aF = np.zeros((nz, N, 8)), np.zeros((nz, N, 3, 8))
+    Ul = np.zeros((nz, order, N, 8)) if levels else None
+    if _lib().rgo_prism_predict(order, nz, gamma, dt, np.ascontiguousarray(J), np.ascontiguousarray(met), Ua,
+                                Ul.ctypes if levels else None, aU, aF):
+        raise ValueError("prism predictor failed")
+    return (aU, aF, Ul) if levels else (aU, aF)

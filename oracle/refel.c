@@ -161,64 +161,56 @@ static double dlag1(int M, const double *t, int j, double x)
     return s;
 }
 
-int refel_init(rgo_refel *r, int order)
+/* Time levels tau = 0 plus the M-1 Gauss points (eqs. 5.15-5.17) and the
+ * full space-time Galerkin system of eqs. (5.24)-(5.27) for the element's
+ * nodal basis, integrated with the given spatial quadrature (points xq,
+ * weights wq) times M+1 Gauss points in time, split into the non-evolving and
+ * evolving blocks and reduced to the matrices of eq. (5.29).  The spatial
+ * rule must integrate the products psi_i dpsi_l exactly. */
+int refel_spacetime(rgo_refel *r, int M, int nq, const double *xq, const double *wq)
 {
-    memset(r, 0, sizeof(*r));
-    if (order < 3 || order > 4) return -1;
-    r->order = order;
-    r->N = serendipity_nodes(order, r->node, r->exps);
-    if (r->N <= 0) return -1;
-    if (lagrange3(r->N, &r->node[0][0], &r->exps[0][0], r->coef)) return -1;
-
-    /* time levels: tau = 0 and the M-1 Gauss points (eqs. 5.15-5.17) */
-    int M = order;
-    r->M = M;
     double gx[4], gw[4];
     gauss01(M - 1, gx, gw);
+    r->M = M;
     r->tau[0] = 0.0;
     r->wt[0] = 0.0;
     for (int j = 1; j < M; j++) { r->tau[j] = gx[j - 1]; r->wt[j] = gw[j - 1]; }
 
     int N = r->N, L = N * M, E = L - N;
     r->L = L;
-
-    /* space-time quadrature, exact for the products in eq. (5.26) */
-    const int ns = 4, nt = M + 1;
-    double sx[8], sw[8], tx[8], tw[8];
-    gauss01(ns, sx, sw);
+    const int nt = M + 1;
+    double tx[8], tw[8];
     gauss01(nt, tx, tw);
     double *Kt = calloc((size_t)L * L, sizeof(double));
     double *Kx[3];
     for (int d = 0; d < 3; d++) Kx[d] = calloc((size_t)L * L, sizeof(double));
     double *psi = malloc(sizeof(double) * N), *dpsi = malloc(sizeof(double) * N * 3);
     double phi[4], dphi[4];
-    for (int a = 0; a < ns; a++)
-        for (int b = 0; b < ns; b++)
-            for (int c = 0; c < ns; c++) {
-                double xi[3] = {sx[a] - 0.5, sx[b] - 0.5, sx[c] - 0.5};
-                double ws = sw[a] * sw[b] * sw[c];
-                for (int i = 0; i < N; i++) {
-                    psi[i] = refel_psi(r, i, xi);
-                    for (int d = 0; d < 3; d++) dpsi[i * 3 + d] = refel_dpsi(r, i, d, xi);
-                }
-                for (int t = 0; t < nt; t++) {
-                    for (int j = 0; j < M; j++) {
-                        phi[j] = lag1(M, r->tau, j, tx[t]);
-                        dphi[j] = dlag1(M, r->tau, j, tx[t]);
-                    }
-                    double w = ws * tw[t];
-                    /* theta_{i + j N} = psi_i phi_j   (eq. 5.19) */
-                    for (int jj = 0; jj < L; jj++) {
-                        double th = psi[jj % N] * phi[jj / N];
-                        for (int ll = 0; ll < L; ll++) {
-                            int i = ll % N, j = ll / N;
-                            Kt[jj * L + ll] += w * th * psi[i] * dphi[j];
-                            for (int d = 0; d < 3; d++)
-                                Kx[d][jj * L + ll] += w * th * dpsi[i * 3 + d] * phi[j];
-                        }
-                    }
+    for (int p = 0; p < nq; p++) {
+        const double *xi = &xq[3 * p];
+        double ws = wq[p];
+        for (int i = 0; i < N; i++) {
+            psi[i] = refel_psi(r, i, xi);
+            for (int d = 0; d < 3; d++) dpsi[i * 3 + d] = refel_dpsi(r, i, d, xi);
+        }
+        for (int t = 0; t < nt; t++) {
+            for (int j = 0; j < M; j++) {
+                phi[j] = lag1(M, r->tau, j, tx[t]);
+                dphi[j] = dlag1(M, r->tau, j, tx[t]);
+            }
+            double w = ws * tw[t];
+            /* theta_{i + j N} = psi_i phi_j   (eq. 5.19) */
+            for (int jj = 0; jj < L; jj++) {
+                double th = psi[jj % N] * phi[jj / N];
+                for (int ll = 0; ll < L; ll++) {
+                    int i = ll % N, j = ll / N;
+                    Kt[jj * L + ll] += w * th * psi[i] * dphi[j];
+                    for (int d = 0; d < 3; d++)
+                        Kx[d][jj * L + ll] += w * th * dpsi[i * 3 + d] * phi[j];
                 }
             }
+        }
+    }
     /* split into blocks (eq. 5.27) and form eq. (5.29) */
     double *K11 = malloc(sizeof(double) * E * E), *K11i = malloc(sizeof(double) * E * E);
     for (int i = 0; i < E; i++)
@@ -251,6 +243,32 @@ int refel_init(rgo_refel *r, int order)
     for (int d = 0; d < 3; d++) free(Kx[d]);
     free(psi); free(dpsi); free(K11); free(K11i);
     return 0;
+}
+
+int refel_init(rgo_refel *r, int order)
+{
+    memset(r, 0, sizeof(*r));
+    if (order < 3 || order > 4) return -1;
+    r->order = order;
+    r->N = serendipity_nodes(order, r->node, r->exps);
+    if (r->N <= 0) return -1;
+    if (lagrange3(r->N, &r->node[0][0], &r->exps[0][0], r->coef)) return -1;
+
+    /* spatial quadrature: 4^3 Gauss points on the cube, exact for the
+     * products in eq. (5.26) */
+    const int ns = 4;
+    double sx[8], sw[8], xq[64 * 3], wq[64];
+    gauss01(ns, sx, sw);
+    int n = 0;
+    for (int a = 0; a < ns; a++)
+        for (int b = 0; b < ns; b++)
+            for (int c = 0; c < ns; c++) {
+                xq[3 * n] = sx[a] - 0.5;
+                xq[3 * n + 1] = sx[b] - 0.5;
+                xq[3 * n + 2] = sx[c] - 0.5;
+                wq[n++] = sw[a] * sw[b] * sw[c];
+            }
+    return refel_spacetime(r, order, n, xq, wq);
 }
 
 void refel_free(rgo_refel *r)

@@ -72,3 +72,27 @@ def square_rules():
         else:
             out[cur].append([num(x) for x in ln.split(";")])
     return out
+
+
+def prism_order2_update():
+    """rows of D_xi, D_eta, D_zeta at the six second-order nodes"""
+    out = []
+    for ln in lines("prism_order2_update.txt"):
+        out.append([[num(x) for x in part.split(";")] for part in ln.split("|")])
+    return out
+
+
+def prism_order4_nodes():
+    sec, nodes, monos = None, [], []
+    for ln in lines("prism_order4_nodes.txt"):
+        if ln in ("nodes", "monomials"):
+            sec = ln; continue
+        if sec == "nodes":
+            nodes.append([num(x) for x in ln.split(";")])
+        else:
+            monos = [tuple(int(v) for v in t.split()) for t in ln.split(";")]
+    return nodes, monos
+
+
+def icosahedral_angles():
+    return [(int(a), num(b), int(c)) for a, b, c in (ln.split(";") for ln in lines("icosahedral_angles.txt"))]

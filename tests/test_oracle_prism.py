@@ -1,0 +1,256 @@
+"""Pins of the oracle's triangular-prism element and icosahedral mesh against
+what the paper prints and what the mathematics fixes (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import tests.golden_io as G
+from oracle import prism as P
+
+S3 = math.sqrt(3.0)
+
+
+def _galerkin_is_R_kron_D(r, R):
+    """The reduced full-Galerkin matrices of eq. (5.29) factor into the
+    printed time matrix R and the nodal derivative matrices (the spaces are
+    closed under differentiation), as eqs. (C.35)-(C.36) and (D.30)-(D.32)
+    state: Kd0 = R[1:, :1] (x) D, Kd = R[1:, 1:] (x) D, Kt0 = 1 (x) I."""
+    N, M = r["N"], r["M"]
+    R = np.asarray(R)
+    # rounding of the basis (Vandermonde condition number up to 323 at fourth
+    # order) and of the quadrature sums, relative to the largest entry of D
+    tol = 1e-13 * np.abs(r["D"]).max() * N
+    for d in range(3):
+        np.testing.assert_allclose(r["Kd0"][d], np.kron(R[1:, :1], r["D"][d]), rtol=0, atol=tol)
+        np.testing.assert_allclose(r["Kd"][d], np.kron(R[1:, 1:], r["D"][d]), rtol=0, atol=tol)
+    np.testing.assert_allclose(r["Kt0"], np.kron(np.ones((M - 1, 1)), np.eye(N)), rtol=0, atol=1e-12)
+
+
+def test_second_order_update_matches_appendix_B():
+    r = P.refel(2)
+    rows = G.prism_order2_update()
+    for i, (f, g, h) in enumerate(rows):
+        np.testing.assert_allclose(r["D"][0][i], f, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(r["D"][1][i], g, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(r["D"][2][i], h, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["tau"], [0.0, 0.5], rtol=0, atol=1e-15)
+    _galerkin_is_R_kron_D(r, G.time_R()[2])
+
+
+def test_second_order_basis_matches_B10_to_B15():
+    """(B.10)-(B.15): psi_1 = 1/6 - xi/2 - eta/(2 sqrt 3) + zeta/3 - xi zeta - eta zeta/sqrt 3,
+    psi_3 = 1/6 + eta/sqrt 3 + zeta/3 + 2 eta zeta/sqrt 3, psi_6 = 1/6 + eta/sqrt 3 - zeta/3 - 2 eta zeta/sqrt 3
+    on the monomials (1, xi, eta, zeta, xi zeta, eta zeta) of eq. (5.12)."""
+    r = P.refel(2)
+    assert [tuple(e) for e in r["exps"]] == [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1)]
+    printed = {0: [1 / 6, -1 / 2, -1 / (2 * S3), 1 / 3, -1, -1 / S3],
+               1: [1 / 6, 1 / 2, -1 / (2 * S3), 1 / 3, 1, -1 / S3],
+               2: [1 / 6, 0, 1 / S3, 1 / 3, 0, 2 / S3],
+               3: [1 / 6, -1 / 2, -1 / (2 * S3), -1 / 3, 1, 1 / S3],
+               4: [1 / 6, 1 / 2, -1 / (2 * S3), -1 / 3, -1, 1 / S3],
+               5: [1 / 6, 0, 1 / S3, -1 / 3, 0, -2 / S3]}
+    for l, c in printed.items():
+        np.testing.assert_allclose(r["coef"][:, l], c, rtol=0, atol=1e-13)
+
+
+def test_third_order_element_matches_appendix_C():
+    """Nodes (C.2)-(C.16) and monomials (5.13) as printed; the printed bases
+    (C.19), (C.21), (C.25), (C.28), (C.29); the Galerkin system against the
+    printed R of (C.18)."""
+    r = P.refel(3)
+    nodes, monos, basis = G.prism_basis()
+    np.testing.assert_allclose(r["nodes"], nodes, rtol=0, atol=1e-15)
+    assert [tuple(e) for e in r["exps"]] == monos
+    for l1, coefs in basis.items():
+        c = dict(zip([tuple(e) for e in r["exps"]], r["coef"][:, l1 - 1]))
+        for e, v in c.items():
+            assert abs(v - coefs.get(e, 0.0)) < 1e-12, (l1, e, v, coefs.get(e, 0.0))
+    _galerkin_is_R_kron_D(r, G.time_R()[3])
+
+
+def test_fourth_order_element_matches_appendix_D():
+    r = P.refel(4)
+    nodes, monos = G.prism_order4_nodes()
+    np.testing.assert_allclose(r["nodes"], nodes, rtol=0, atol=1e-15)
+    assert [tuple(e) for e in r["exps"]] == monos
+    _galerkin_is_R_kron_D(r, G.time_R()[4])
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_derivative_matrices_differentiate_the_space_exactly(order):
+    """D_d applied to the nodal values of every monomial of eqs. (5.12)-(5.14)
+    gives the nodal values of its exact derivative, and psi_l(node_i) = delta_il
+    (eq. 5.3)."""
+    r = P.refel(order)
+    X = r["nodes"]
+    V = np.array([[np.prod(x ** np.array(e)) for e in r["exps"]] for x in X])
+    np.testing.assert_allclose(V @ r["coef"], np.eye(r["N"]), rtol=0, atol=1e-12)
+    for k, e in enumerate(r["exps"]):
+        m = V[:, k]
+        for d in range(3):
+            if e[d] == 0:
+                exact = np.zeros(len(X))
+            else:
+                ee = np.array(e); ee[d] -= 1
+                exact = e[d] * np.prod(X ** ee, axis=1)
+            np.testing.assert_allclose(r["D"][d] @ m, exact, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_predictor_exact_for_advected_polynomial_on_affine_prism(order):
+    """On an affine prism a density polynomial of total degree <= p-1 (inside
+    the space of eqs. 5.12-5.14) advected by uniform v with uniform p and B is
+    reproduced exactly at every space-time node after p Picard iterations
+    (ADER-CG, eqs. 5.20-5.29)."""
+    r = P.refel(order)
+    N, X0 = r["N"], r["nodes"]
+    rng = np.random.default_rng(11)
+    A = np.eye(3) * 0.1 + 0.02 * rng.normal(size=(3, 3))
+    x0 = np.array([1.1, -0.2, 0.6])
+    X = X0 @ A.T + x0
+    J = np.full((1, N), np.linalg.det(A))
+    h = [A[:, 0], A[:, 1], A[:, 2]]
+    met = np.zeros((1, N, 3, 3))
+    met[0, :, 0] = np.cross(h[1], h[2]); met[0, :, 1] = np.cross(h[2], h[0]); met[0, :, 2] = np.cross(h[0], h[1])
+    v = np.array([0.6, -0.4, 0.3]); B = np.array([0.3, -0.1, 0.2]); p = 0.9; gam = 5 / 3
+    exps = [(a, b, c) for a in range(order) for b in range(order - a) for c in range(order - a - b)]
+    cf = 0.05 * rng.normal(size=len(exps)); cf[0] = 1.0
+
+    def state(x):
+        y = (x - x0) / 0.1
+        rh = sum(c * y[:, 0] ** a * y[:, 1] ** b * y[:, 2] ** cc for c, (a, b, cc) in zip(cf, exps))
+        U = np.zeros((len(x), 8))
+        U[:, 0] = rh; U[:, 1:4] = rh[:, None] * v
+        U[:, 4] = p / (gam - 1) + 0.5 * rh * (v @ v) + 0.5 * (B @ B)
+        U[:, 5:8] = B
+        return U
+
+    dt = 0.02
+    aU, aF, Ul = P.predict(order, J, met, state(X)[None], dt, gam, levels=True)
+    for t in range(order):
+        np.testing.assert_allclose(Ul[0, t] / J[0][:, None], state(X - v * r["tau"][t] * dt), rtol=0, atol=1e-11)
+    # the time average of the state is the Gauss-weighted average of the levels
+    ref = sum(r["wt"][t] * state(X - v * r["tau"][t] * dt) for t in range(1, order))
+    np.testing.assert_allclose(aU[0], ref, rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------------- mesh
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_icosahedral_mesh_topology(level):
+    """20 4^L triangles, 10 4^L + 2 vertices on the unit sphere, every edge
+    shared by exactly two triangles with opposite orientation (a closed
+    oriented surface, V - E + F = 2), all triangles counter-clockwise seen
+    from outside."""
+    m = P.OraclePrismMesh(level, 1, order=2)
+    V, T = m.vert, m.tri
+    assert len(T) == 20 * 4 ** level and len(V) == 10 * 4 ** level + 2
+    np.testing.assert_allclose(np.linalg.norm(V, axis=1), 1.0, rtol=0, atol=1e-15)
+    directed = {}
+    for a, b, c in T:
+        for e in ((a, b), (b, c), (c, a)):
+            assert e not in directed
+            directed[e] = 1
+    for (a, b) in directed:
+        assert (b, a) in directed
+    nE = len(directed) // 2
+    assert len(V) - nE + len(T) == 2
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    assert np.all(np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c) > 0)
+
+
+def test_icosahedral_edge_angles_match_section_IIa():
+    """Mean central angle of an edge at levels 0, 1 and 4, as printed."""
+    for level, deg, digits in G.icosahedral_angles():
+        m = P.OraclePrismMesh(level, 1, order=2)
+        V, T = m.vert, m.tri
+        ang = []
+        for i, j in ((0, 1), (1, 2), (2, 0)):
+            ang.append(np.degrees(np.arccos(np.clip(np.einsum("ij,ij->i", V[T[:, i]], V[T[:, j]]), -1, 1))))
+        assert round(float(np.mean(ang)), digits) == pytest.approx(deg, abs=1e-9), (level, np.mean(ang))
+    np.testing.assert_allclose(G.icosahedral_angles()[0][1], 63.4)
+    m = P.OraclePrismMesh(0, 1, order=2)
+    V, T = m.vert, m.tri
+    ang0 = np.degrees(np.arccos(V[T[0, 0]] @ V[T[0, 1]]))
+    np.testing.assert_allclose(ang0, 90 - np.degrees(np.arctan(0.5)), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- geometry
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_zone_geometry_sphericity_and_radial_lines(order):
+    """The map interpolates the sphere at its lattice nodes, which are the
+    prism's nodes on the inner and outer faces, and is linear in radius
+    along the vertical edges (Section II.b, Fig. 3)."""
+    m = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.6, order=order)
+    r = P.refel(order)
+    zones = np.arange(m.nz)
+    x, J, met = m.geometry(zones)
+    t, k = m.zone_tri_shell(zones)
+    r0, r1 = m.radius[k], m.radius[k + 1]
+    zeta = r["nodes"][:, 2]
+    rad = np.linalg.norm(x, axis=2)
+    for i in range(r["N"]):
+        expect = (0.5 - zeta[i]) * r0 + (0.5 + zeta[i]) * r1
+        if abs(zeta[i]) == 0.5:
+            np.testing.assert_allclose(rad[:, i], expect, rtol=1e-14, atol=0)
+    # vertical-edge nodes lie on the radial line through the vertex
+    vert_nodes = [i for i in range(r["N"]) if np.min(np.linalg.norm(r["nodes"][i, :2] - r["nodes"][:3, :2], axis=1)) < 1e-12]
+    for i in vert_nodes:
+        kv = int(np.argmin(np.linalg.norm(r["nodes"][i, :2] - r["nodes"][:3, :2], axis=1)))
+        vdir = m.vert[m.tri[t, kv]]
+        expect = ((0.5 - zeta[i]) * r0 + (0.5 + zeta[i]) * r1)[:, None] * vdir
+        np.testing.assert_allclose(x[:, i], expect, rtol=0, atol=1e-14)
+    assert np.all(J > 0)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_curl_metrics_have_zero_discrete_divergence(order):
+    """sum_d D_d (J a^d)_n = 0 at every node (free-stream preservation of
+    eq. 5.11 in curl form), and the metrics approach J times the inverse
+    Jacobian as the zones shrink."""
+    r = P.refel(order)
+    m = P.OraclePrismMesh(2, 2, order=order)
+    zones = np.arange(0, m.nz, 7)
+    x, J, met = m.geometry(zones)
+    for z in range(len(zones)):
+        div = sum(r["D"][d] @ met[z, :, d, :] for d in range(3))
+        assert np.abs(div).max() < 1e-13 * np.abs(met[z]).max()
+    # against the cofactor of the map's Jacobian: halving the zones in every
+    # direction shrinks the gap by 2^(p-1) (the interpolation error of the
+    # curl form's vector potential), up to a margin
+    gaps = []
+    for level, n_rad in ((2, 4), (3, 8)):
+        mm = P.OraclePrismMesh(level, n_rad, order=order)
+        zz = np.arange(0, mm.nz, 97)
+        xx, JJ, mt = mm.geometry(zz)
+        gaps.append(_metric_gap(r, xx, JJ, mt))
+    assert gaps[1] / gaps[0] < 1.25 * 0.5 ** (order - 1), gaps
+
+
+def _metric_gap(r, x, J, met):
+    """max relative difference between the curl-form metrics and J d xi/dx
+    from the nodal interpolant of x (differentiated with D)"""
+    worst = 0.0
+    for z in range(len(x)):
+        jac = np.stack([r["D"][d] @ x[z] for d in range(3)], axis=2)  # [i][n][d] = d x_n / d xi_d
+        for i in range(r["N"]):
+            cof = np.linalg.det(jac[i]) * np.linalg.inv(jac[i])           # [d][n] = J d xi_d / d x_n
+            worst = max(worst, np.abs(cof - met[z, i]).max() / np.abs(cof).max())
+    return worst
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_predictor_keeps_a_uniform_state_on_curved_zones(order):
+    """Free stream: a uniform state stays uniform through the predictor on the
+    curved zones, and the averaged flux is the physical flux of that state."""
+    from oracle import oracle as O
+    m = P.OraclePrismMesh(1, 2, order=order)
+    zones = np.arange(0, m.nz, 5)
+    U = np.array([1.1, 0.3, -0.2, 0.4, 2.5, 0.2, 0.1, -0.3])
+    Ua = np.tile(U, (len(zones), m.N, 1))
+    aU, aF = m.predict(zones, Ua, 0.05)
+    # round-off of the metric sums only (a wrong metric term moves the state
+    # by dt times the flux, about 1e-2 here)
+    np.testing.assert_allclose(aU, Ua, rtol=0, atol=1e-12)
+    F = O.flux(U)
+    np.testing.assert_allclose(aF, np.broadcast_to(F, aF.shape), rtol=0, atol=1e-12)
