@@ -382,6 +382,76 @@ rg_status rg_geom_work(const rg_geom *geom, double *flops, double *bytes);
  * Asynchronous on `stream`. */
 rg_status rg_fma_probe(double *sink, int64_t n_threads, int32_t iters, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Triangular-prism element on the icosahedral geodesic mesh: the paper's own
+ * zone (Sections II.a-II.b, V.b; Fig. 7; Appendices B-D) with its
+ * element-local ADER-CG predictor (Section V.d).
+ *
+ * Mesh: the icosahedron projected to the unit sphere (vertex 0 the north
+ * pole, 1-5 an upper ring at z = 1/sqrt 5 at longitudes 72 k degrees, 6-10 a
+ * lower ring at z = -1/sqrt 5 at longitudes 36 + 72 k, 11 the south pole;
+ * faces, for k = 0..4 and k1 = k + 1 mod 5, (0, 1+k, 1+k1), (1+k, 6+k, 1+k1),
+ * (1+k1, 6+k, 6+k1), (11, 6+k1, 6+k), each turned counter-clockwise seen
+ * from outside) is split `level` times: triangle t = (a, b, c) becomes
+ * 4t + 0: (a, m_ab, m_ca), 4t + 1: (m_ab, b, m_bc), 4t + 2: (m_ca, m_bc, c),
+ * 4t + 3: (m_ab, m_bc, m_ca), with the great-circle midpoints
+ * m_uv = (u + v) / |u + v|: 20 * 4^level triangles.  Shells have radii
+ * r_k = r_in (r_out / r_in)^(k / n_rad), k = 0..n_rad; zone z = t * n_rad + k.
+ *
+ * Element: the prism with unit edges and its centroid at the origin,
+ * triangle vertices (-1/2, -1/(2 sqrt 3)), (1/2, -1/(2 sqrt 3)),
+ * (0, 1/sqrt 3), zeta in [-1/2, 1/2] (zeta = -1/2 on the inner sphere); its
+ * 6 / 15 / 26 nodes at orders 2 / 3 / 4 numbered as in Appendices B-D; the
+ * map to a zone interpolates the sphere through the triangle lattice of
+ * degree order-1 (vertices, equidistant great-circle edge points, and at
+ * order 4 the spherical centroid) and is linear in radius.
+ * ------------------------------------------------------------------------ */
+typedef struct rg_prism rg_prism;
+
+typedef struct {
+    int64_t n_zones;   /* 20 * 4^level * n_rad                 */
+    int64_t n_tri;     /* 20 * 4^level columns                  */
+    int32_t n_nodes;   /* nodes per zone: 6, 15, 26             */
+    int32_t n_levels;  /* time levels: order                    */
+    int32_t order, level, n_rad;
+} rg_prism_info;
+
+/* Builds the mesh and, on the current device, the geometry of every column
+ * (Jacobians and curl-form flux metrics of eq. (5.11) at the nodes, for a
+ * unit shell, 104 bytes per node).  *out is a library-owned handle
+ * (rg_prism_free).  RG_ENOTSUP for order outside 2..4, level outside 0..8 or
+ * more than 2^31 zone nodes; RG_EINVAL unless n_rad >= 1 and
+ * 0 < r_in < r_out; RG_ESINGULAR if the element or a Jacobian degenerates;
+ * RG_ENOMEM if a device allocation fails. */
+rg_status rg_prism_build(int32_t level, int32_t n_rad, double r_in, double r_out, int32_t order, rg_prism **out);
+/* The same mesh and host geometry without device uploads (queries only;
+ * rg_prism_predict returns RG_EINVAL on it). */
+rg_status rg_prism_build_host(int32_t level, int32_t n_rad, double r_in, double r_out, int32_t order,
+                              rg_prism **out);
+void rg_prism_free(rg_prism *prism);
+rg_status rg_prism_get_info(const rg_prism *prism, rg_prism_info *info);
+
+/* Host copy of the triangles' vertices: abc[n_tri][3][3] (a, b, c). */
+rg_status rg_prism_triangles(const rg_prism *prism, double *abc);
+
+/* Host copies for zones [z0, z0 + nz): node positions x[nz][N][3],
+ * Jacobians J[nz][N] and metrics met[nz][N][3][3] (row d, column n:
+ * J d xi_d / d x_n); any output may be NULL.  RG_EINVAL outside the mesh. */
+rg_status rg_prism_geometry(const rg_prism *prism, int64_t z0, int64_t nz, double *x, double *J, double *met);
+
+/* The ADER-CG predictor of every zone (Section V.d, eqs. (5.20)-(5.29), in
+ * the R (x) D form of eqs. (C.34)-(C.36) and (D.29)-(D.32)): from the nodal
+ * conserved state Ua at t^n it runs n_picard Picard sweeps over the
+ * order - 1 Gauss time levels (the scheme uses n_picard = order; 0 keeps
+ * every level at the initial state) and returns the time averages over the
+ * levels of the nodal state, avgU, and of the physical flux, avgF -- the
+ * inputs of the corrector's face and edge quadratures.  Device arrays,
+ * caller-owned: Ua and avgU double[8][n_zones][N], avgF double[3][8][n_zones][N]
+ * (direction, variable, zone, node).  Asynchronous on stream.  RG_EINVAL for
+ * null pointers, gamma <= 1, dt < 0 or n_picard outside 0..16. */
+rg_status rg_prism_predict(const rg_prism *prism, double gamma, double dt, int32_t n_picard, const double *Ua,
+                           double *avgU, double *avgF, void *stream);
+
 /* Benchmark helper (not part of the scheme): launches n_threads (a multiple
  * of 256) lanes whose wavefronts each run iters x 8 independent matrix-core
  * products and write one double per lane to sink[n_threads] (device).  kind 0:

@@ -13,7 +13,7 @@ import numpy as np
 from . import _native as N
 from ._native import RGError, rg_step_params  # noqa: F401
 
-__all__ = ["ShellMHD", "RGError", "rg_step_params"]
+__all__ = ["ShellMHD", "PrismMesh", "RGError", "rg_step_params"]
 
 
 def _ptr(a):
@@ -249,6 +249,55 @@ class ShellMHD:
     def work(self):
         """-> ({stage: flops per step}, {stage: algorithmic HBM bytes per step})"""
         return N.rg_geom_work(self._geom)
+
+
+class PrismMesh:
+    """Icosahedral geodesic prism mesh of `level` (20 * 4^level triangles) and
+    n_rad shells with the order-`order` prism element's geometry on the
+    device (rg_prism_build).  Zone z = triangle * n_rad + shell."""
+
+    def __init__(self, level, n_rad, order, r_in=1.0, r_out=2.0, device=True):
+        build = N.rg_prism_build if device else N.rg_prism_build_host
+        self._h = build(level, n_rad, r_in, r_out, order)
+        info = N.rg_prism_get_info(self._h)
+        self.nz, self.ntri, self.N = info["n_zones"], info["n_tri"], info["n_nodes"]
+        self.level, self.n_rad, self.order = level, n_rad, order
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.rg_prism_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def triangles(self):
+        abc = np.zeros((self.ntri, 3, 3))
+        N.rg_prism_triangles(self._h, _ptr(abc))
+        return abc
+
+    def geometry(self, z0, nz):
+        """host x[nz][N][3], J[nz][N], met[nz][N][3][3] of zones z0 .. z0 + nz - 1"""
+        x, J, met = np.zeros((nz, self.N, 3)), np.zeros((nz, self.N)), np.zeros((nz, self.N, 3, 3))
+        N.rg_prism_geometry(self._h, z0, nz, _ptr(x), _ptr(J), _ptr(met))
+        return x, J, met
+
+    def predict(self, Ua, dt, gamma=5.0 / 3.0, n_picard=None, aU=None, aF=None):
+        """ADER-CG predictor of every zone: Ua, aU [8][nz][N], aF [3][8][nz][N]
+        float64 CUDA tensors (aU, aF allocated when not given)."""
+        import torch
+        assert Ua.dtype == torch.float64 and Ua.is_cuda and Ua.is_contiguous()
+        assert tuple(Ua.shape) == (8, self.nz, self.N)
+        if aU is None:
+            aU = torch.empty_like(Ua)
+        if aF is None:
+            aF = torch.empty((3, 8, self.nz, self.N), dtype=torch.float64, device=Ua.device)
+        N.rg_prism_predict(self._h, gamma, dt, self.order if n_picard is None else n_picard, _ptr(Ua), _ptr(aU),
+                           _ptr(aF), _stream())
+        return aU, aF
 
 
 _STEP_FN = None

@@ -38,6 +38,11 @@ class rg_diag_out(C.Structure):
                 ("p_min", C.c_double)]
 
 
+class rg_prism_info(C.Structure):
+    _fields_ = [("n_zones", C.c_int64), ("n_tri", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
+                ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32)]
+
+
 class RGError(RuntimeError):
     pass
 
@@ -94,6 +99,17 @@ def lib():
         L.rg_geom_work.restype = C.c_int
         L.rg_profile_begin.argtypes = [_vp]
         L.rg_profile_end.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
+        L.rg_prism_build.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(_vp)]
+        L.rg_prism_build_host.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(_vp)]
+        L.rg_prism_free.argtypes = [_vp]
+        L.rg_prism_free.restype = None
+        L.rg_prism_get_info.argtypes = [_vp, C.POINTER(rg_prism_info)]
+        L.rg_prism_triangles.argtypes = [_vp, _vp]
+        L.rg_prism_geometry.argtypes = [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]
+        L.rg_prism_predict.argtypes = [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp, _vp, _vp]
+        for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_triangles", "rg_prism_geometry",
+                     "rg_prism_predict"):
+            getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
                      "rg_geom_zone_data", "rg_geom_face_data", "rg_geom_edge_data", "rg_geom_incidence", "rg_step",
                      "rg_step_fluxes",
@@ -269,3 +285,39 @@ def rg_geom_work(geom):
     b = (C.c_double * RG_NSTAGES)()
     check(lib().rg_geom_work(geom, f, b), "rg_geom_work")
     return dict(zip(STAGES, list(f))), dict(zip(STAGES, list(b)))
+
+
+# ------------------------------------------------------------------ prism element
+def rg_prism_build(level, n_rad, r_in, r_out, order):
+    h = _vp()
+    check(lib().rg_prism_build(level, n_rad, r_in, r_out, order, C.byref(h)), "rg_prism_build")
+    return h
+
+
+def rg_prism_build_host(level, n_rad, r_in, r_out, order):
+    h = _vp()
+    check(lib().rg_prism_build_host(level, n_rad, r_in, r_out, order, C.byref(h)), "rg_prism_build_host")
+    return h
+
+
+def rg_prism_free(prism):
+    lib().rg_prism_free(prism)
+
+
+def rg_prism_get_info(prism):
+    info = rg_prism_info()
+    check(lib().rg_prism_get_info(prism, C.byref(info)), "rg_prism_get_info")
+    return {n: getattr(info, n) for n, _ in rg_prism_info._fields_}
+
+
+def rg_prism_triangles(prism, abc_ptr):
+    check(lib().rg_prism_triangles(prism, _vp(abc_ptr)), "rg_prism_triangles")
+
+
+def rg_prism_geometry(prism, z0, nz, x_ptr, J_ptr, met_ptr):
+    check(lib().rg_prism_geometry(prism, z0, nz, _vp(x_ptr), _vp(J_ptr), _vp(met_ptr)), "rg_prism_geometry")
+
+
+def rg_prism_predict(prism, gamma, dt, n_picard, Ua_ptr, aU_ptr, aF_ptr, stream):
+    check(lib().rg_prism_predict(prism, gamma, dt, n_picard, _vp(Ua_ptr), _vp(aU_ptr), _vp(aF_ptr), _vp(stream)),
+          "rg_prism_predict")

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librg.so")
-SOURCES = ["mesh.cpp", "refel.cpp", "geom.cpp", "capi.cpp", "init.cpp", "step.hip", "adjoint.hip", "probe.hip"]
+SOURCES = ["mesh.cpp", "refel.cpp", "geom.cpp", "capi.cpp", "init.cpp", "prism_ref.cpp", "prism.cpp", "step.hip",
+           "adjoint.hip", "probe.hip", "prism.hip"]
 ARCH = "gfx950"
 
 

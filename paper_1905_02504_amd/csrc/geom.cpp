@@ -41,6 +41,8 @@ inline void normalize(double *a)
     a[0] /= n; a[1] /= n; a[2] /= n;
 }
 
+}  // namespace
+
 // point at fraction t of the great-circle arc from unit vector a to unit
 // vector b: a rotated by t times the arc's angle within the plane of a and b
 void arc_point(const double *a, const double *b, double t, double *o)
@@ -53,6 +55,8 @@ void arc_point(const double *a, const double *b, double t, double *o)
     const double ca = std::cos(t * th), sa = std::sin(t * th) / un;
     for (int i = 0; i < 3; i++) o[i] = ca * a[i] + sa * u[i];
 }
+
+namespace {
 
 // where the great circle through p1, p2 meets the great circle through q1, q2:
 // the unit vector in the plane of p1, p2 orthogonal to the second circle's

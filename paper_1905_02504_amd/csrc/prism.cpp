@@ -1,0 +1,333 @@
+// Icosahedral geodesic prism mesh of the library (host, FP64) and the C-ABI
+// of the prism element:
+//  - mesh of Section II.a: the projected icosahedron split level times at
+//    great-circle edge midpoints;
+//  - per column (triangle), the curved-prism map of Section II.b for a unit
+//    shell with radii 1 and q = (r_out / r_in)^(1 / n_rad): a triangle
+//    Lagrange interpolant of degree p-1 through sphere points (vertices,
+//    equidistant great-circle points on the edges, the spherical centroid
+//    where the medians meet) times a linear radial factor.  Shell k is that
+//    shell scaled by r_k, so J scales by r_k^3 and the metrics by r_k^2.
+//    Metrics J d xi_d / d x_n at the nodes in the conservative curl form.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "prism.hpp"
+#include "prism_dtab.hpp"
+#include "rg_geom_host.hpp"
+#include "rg_internal.hpp"
+
+namespace rg {
+
+// compiled-in sparse tables of the kernels against the computed matrices
+static bool prism_tables_match(const PrismRef &r)
+{
+    const int N = r.N;
+    std::vector<double> T((size_t)3 * N * N, 0.0);
+    auto fill = [&](int d, int nnz, const short (*e)[2], const double *v) {
+        for (int k = 0; k < nnz; k++) T[((size_t)d * N + e[k][0]) * N + e[k][1]] = v[k];
+    };
+    if (r.order == 2) {
+        fill(0, PrismD<2>::NZ0, PrismD<2>::E0, PrismD<2>::V0);
+        fill(1, PrismD<2>::NZ1, PrismD<2>::E1, PrismD<2>::V1);
+        fill(2, PrismD<2>::NZ2, PrismD<2>::E2, PrismD<2>::V2);
+    } else if (r.order == 3) {
+        fill(0, PrismD<3>::NZ0, PrismD<3>::E0, PrismD<3>::V0);
+        fill(1, PrismD<3>::NZ1, PrismD<3>::E1, PrismD<3>::V1);
+        fill(2, PrismD<3>::NZ2, PrismD<3>::E2, PrismD<3>::V2);
+    } else {
+        fill(0, PrismD<4>::NZ0, PrismD<4>::E0, PrismD<4>::V0);
+        fill(1, PrismD<4>::NZ1, PrismD<4>::E1, PrismD<4>::V1);
+        fill(2, PrismD<4>::NZ2, PrismD<4>::E2, PrismD<4>::V2);
+    }
+    for (size_t k = 0; k < T.size(); k++)
+        if (std::fabs(T[k] - r.D[k]) > 1e-13) return false;
+    return true;
+}
+
+}  // namespace rg
+
+using namespace rg;
+
+struct rg_prism {
+    int level = 0, n_rad = 0, order = 0;
+    double r_in = 0, r_out = 0, q = 0;
+    int64_t ntri = 0, nz = 0;
+    PrismRef ref;
+    std::vector<double> tri;       // ntri x 9: vertices a, b, c of each triangle
+    std::vector<double> radius;    // n_rad + 1
+    std::vector<double> hx, hJ, hM;  // unit-shell nodes ntri x N x 3, J ntri x N, metrics ntri x 9 x N
+    std::vector<void *> allocations;
+    bool device = false;
+    DevPrism dev{};
+};
+
+namespace {
+
+void free_prism(rg_prism *p)
+{
+    if (!p) return;
+    for (void *a : p->allocations) (void)hipFree(a);
+    delete p;
+}
+
+bool upload(rg_prism *p, const std::vector<double> &h, const double **dst)
+{
+    void *d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(8, h.size() * sizeof(double))) != hipSuccess) return false;
+    p->allocations.push_back(d);
+    if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    *dst = static_cast<const double *>(d);
+    return true;
+}
+
+void unit(double *v)
+{
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n; v[1] /= n; v[2] /= n;
+}
+
+// the 20 level-0 triangles, each counter-clockwise seen from outside
+void icosahedron(std::vector<double> &tri)
+{
+    double V[12][3];
+    const double h = 1.0 / std::sqrt(5.0), rho = 2.0 / std::sqrt(5.0);
+    V[0][0] = 0; V[0][1] = 0; V[0][2] = 1;
+    V[11][0] = 0; V[11][1] = 0; V[11][2] = -1;
+    for (int k = 0; k < 5; k++) {
+        const double up = 2 * M_PI * k / 5, lo = 2 * M_PI * (k + 0.5) / 5;
+        V[1 + k][0] = rho * std::cos(up); V[1 + k][1] = rho * std::sin(up); V[1 + k][2] = h;
+        V[6 + k][0] = rho * std::cos(lo); V[6 + k][1] = rho * std::sin(lo); V[6 + k][2] = -h;
+    }
+    tri.clear();
+    for (int k = 0; k < 5; k++) {
+        const int k1 = (k + 1) % 5;
+        const int F[4][3] = {{0, 1 + k, 1 + k1}, {1 + k, 6 + k, 1 + k1}, {1 + k1, 6 + k, 6 + k1}, {11, 6 + k1, 6 + k}};
+        for (auto &f : F) {
+            const double *a = V[f[0]], *b = V[f[1]], *c = V[f[2]];
+            double u[3], w[3], n[3];
+            for (int i = 0; i < 3; i++) { u[i] = b[i] - a[i]; w[i] = c[i] - a[i]; }
+            n[0] = u[1] * w[2] - u[2] * w[1];
+            n[1] = u[2] * w[0] - u[0] * w[2];
+            n[2] = u[0] * w[1] - u[1] * w[0];
+            const double o = n[0] * (a[0] + b[0] + c[0]) + n[1] * (a[1] + b[1] + c[1]) + n[2] * (a[2] + b[2] + c[2]);
+            const double *s1 = o < 0 ? c : b, *s2 = o < 0 ? b : c;
+            tri.insert(tri.end(), a, a + 3);
+            tri.insert(tri.end(), s1, s1 + 3);
+            tri.insert(tri.end(), s2, s2 + 3);
+        }
+    }
+}
+
+// children of every triangle: (a, m_ab, m_ca), (m_ab, b, m_bc),
+// (m_ca, m_bc, c), (m_ab, m_bc, m_ca) with m = (u + v) / |u + v|
+void split(std::vector<double> &tri)
+{
+    const size_t nt = tri.size() / 9;
+    std::vector<double> out(nt * 36);
+    for (size_t t = 0; t < nt; t++) {
+        const double *a = &tri[9 * t], *b = a + 3, *c = a + 6;
+        double ab[3], bc[3], ca[3];
+        for (int i = 0; i < 3; i++) { ab[i] = a[i] + b[i]; bc[i] = b[i] + c[i]; ca[i] = c[i] + a[i]; }
+        unit(ab); unit(bc); unit(ca);
+        const double *ch[4][3] = {{a, ab, ca}, {ab, b, bc}, {ca, bc, c}, {ab, bc, ca}};
+        for (int k = 0; k < 4; k++)
+            for (int v = 0; v < 3; v++) std::memcpy(&out[36 * t + 9 * k + 3 * v], ch[k][v], 24);
+    }
+    tri.swap(out);
+}
+
+// unit-shell geometry of one column: nodes x[N][3], J[N], metrics M[9][N]
+void column_geometry(const PrismRef &r, const double *abc, double q, double *x, double *J, double *M)
+{
+    const int N = r.N, mo = r.order - 1;
+    std::vector<std::array<int, 3>> bary;
+    std::vector<std::array<double, 3>> lx;
+    lattice(mo, bary, lx);
+    const int nl = (int)lx.size();
+    // sphere point of every lattice node
+    std::vector<double> sp((size_t)nl * 3);
+    const double *P[3] = {abc, abc + 3, abc + 6};
+    for (int a = 0; a < nl; a++) {
+        double *o = &sp[3 * a];
+        const auto &bc = bary[a];
+        const int nz = (bc[0] == 0) + (bc[1] == 0) + (bc[2] == 0);
+        if (nz == 2) {
+            std::memcpy(o, P[bc[0] ? 0 : bc[1] ? 1 : 2], 24);
+        } else if (nz == 1) {
+            const int u = bc[0] ? 0 : 1, w = bc[2] ? 2 : 1;
+            arc_point(P[u], P[w], double(bc[w]) / (bc[u] + bc[w]), o);
+        } else {
+            for (int i = 0; i < 3; i++) o[i] = P[0][i] + P[1][i] + P[2][i];
+            unit(o);
+        }
+    }
+    // derivatives of the triangle interpolant at the lattice nodes
+    std::vector<std::array<int, 3>> tmo;
+    for (int deg = 0; deg <= mo; deg++)
+        for (int a = deg; a >= 0; a--) tmo.push_back({a, deg - a, 0});
+    std::vector<double> C, TD;
+    lagrange_coefficients(lx, tmo, C);
+    derivative_matrices(lx, tmo, C, TD);   // TD[d][a][b], d = 0, 1 used
+    std::vector<double> jac((size_t)N * 9);
+    double cen[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++) {
+        const int a = r.lat[i];
+        const double z = r.node[i][2], Rz = (0.5 - z) + (0.5 + z) * q, dR = q - 1.0;
+        double Sx[3] = {0, 0, 0}, Sy[3] = {0, 0, 0};
+        for (int b = 0; b < nl; b++) {
+            const double gx = TD[((size_t)0 * nl + a) * nl + b], gy = TD[((size_t)1 * nl + a) * nl + b];
+            for (int k = 0; k < 3; k++) { Sx[k] += gx * sp[3 * b + k]; Sy[k] += gy * sp[3 * b + k]; }
+        }
+        for (int k = 0; k < 3; k++) {
+            x[3 * i + k] = Rz * sp[3 * a + k];
+            jac[9 * i + 3 * k + 0] = Rz * Sx[k];
+            jac[9 * i + 3 * k + 1] = Rz * Sy[k];
+            jac[9 * i + 3 * k + 2] = dR * sp[3 * a + k];
+            cen[k] += x[3 * i + k] / N;
+        }
+        const double *j = &jac[9 * i];
+        J[i] = j[0] * (j[4] * j[8] - j[5] * j[7]) - j[1] * (j[3] * j[8] - j[5] * j[6]) + j[2] * (j[3] * j[7] - j[4] * j[6]);
+    }
+    // curl form: with W_n[j] = (x_{n+2} - c) d x_{n+1} / d xi_j interpolated
+    // in the element's basis, J d xi_d / d x_n = -(curl_xi W_n)_d
+    for (int n = 0; n < 3; n++) {
+        const int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
+        std::vector<double> W((size_t)N * 3);
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < 3; j++) W[3 * i + j] = (x[3 * i + m2] - cen[m2]) * jac[9 * i + 3 * m1 + j];
+        for (int i = 0; i < N; i++) {
+            double g[3][3] = {{0}};   // g[j][d] = d W_j / d xi_d at node i
+            for (int l = 0; l < N; l++)
+                for (int d = 0; d < 3; d++) {
+                    const double w = r.D[((size_t)d * N + i) * N + l];
+                    if (w == 0.0) continue;
+                    for (int j = 0; j < 3; j++) g[j][d] += w * W[3 * l + j];
+                }
+            M[(0 * 3 + n) * N + i] = -(g[2][1] - g[1][2]);
+            M[(1 * 3 + n) * N + i] = -(g[0][2] - g[2][0]);
+            M[(2 * 3 + n) * N + i] = -(g[1][0] - g[0][1]);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r_out, int32_t order, bool device,
+                             rg_prism **out)
+{
+    if (!out) { set_error("null argument"); return RG_EINVAL; }
+    *out = nullptr;
+    if (order < 2 || order > 4) { set_error("prism order must be 2, 3 or 4"); return RG_ENOTSUP; }
+    if (level < 0 || level > 8) { set_error("icosahedral level must be 0..8"); return RG_ENOTSUP; }
+    if (n_rad < 1 || !(r_in > 0.0) || !(r_out > r_in)) { set_error("need n_rad >= 1 and 0 < r_in < r_out"); return RG_EINVAL; }
+    rg_prism *p = new (std::nothrow) rg_prism;
+    if (!p) { set_error("out of host memory"); return RG_ENOMEM; }
+    p->level = level; p->n_rad = n_rad; p->order = order; p->r_in = r_in; p->r_out = r_out;
+    if (!build_prism_ref(order, p->ref)) { set_error("prism reference element construction failed"); free_prism(p); return RG_ESINGULAR; }
+    if (!prism_tables_match(p->ref)) { set_error("prism derivative matrices differ from the compiled-in tables"); free_prism(p); return RG_ESINGULAR; }
+    icosahedron(p->tri);
+    for (int l = 0; l < level; l++) split(p->tri);
+    p->ntri = (int64_t)(p->tri.size() / 9);
+    p->nz = p->ntri * n_rad;
+    if (p->nz * p->ref.N >= ((int64_t)1 << 31)) { set_error("zone-node count exceeds 2^31"); free_prism(p); return RG_ENOTSUP; }
+    p->q = std::pow(r_out / r_in, 1.0 / n_rad);
+    p->radius.resize(n_rad + 1);
+    for (int k = 0; k <= n_rad; k++) p->radius[k] = r_in * std::pow(r_out / r_in, double(k) / n_rad);
+    const int N = p->ref.N;
+    p->hx.assign((size_t)p->ntri * N * 3, 0.0);
+    p->hJ.assign((size_t)p->ntri * N, 0.0);
+    p->hM.assign((size_t)p->ntri * 9 * N, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < p->ntri; t++)
+        column_geometry(p->ref, &p->tri[9 * t], p->q, &p->hx[(size_t)t * N * 3], &p->hJ[(size_t)t * N],
+                        &p->hM[(size_t)t * 9 * N]);
+    for (int64_t t = 0; t < p->ntri * N; t++)
+        if (!(p->hJ[t] > 0.0)) { set_error("non-positive Jacobian"); free_prism(p); return RG_ESINGULAR; }
+    p->device = device;
+    if (!device) { *out = p; return RG_OK; }
+    std::vector<double> rinv(n_rad);
+    for (int k = 0; k < n_rad; k++) rinv[k] = 1.0 / p->radius[k];
+    DevPrism &G = p->dev;
+    G.order = order; G.N = N; G.n_rad = n_rad; G.ntri = p->ntri; G.nz = p->nz;
+    if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
+        !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt)) {
+        set_error("device allocation or upload of the prism geometry failed");
+        free_prism(p);
+        return RG_ENOMEM;
+    }
+    *out = p;
+    return RG_OK;
+}
+
+rg_status rg_prism_build(int32_t level, int32_t n_rad, double r_in, double r_out, int32_t order, rg_prism **out)
+{
+    return prism_build(level, n_rad, r_in, r_out, order, true, out);
+}
+
+rg_status rg_prism_build_host(int32_t level, int32_t n_rad, double r_in, double r_out, int32_t order, rg_prism **out)
+{
+    return prism_build(level, n_rad, r_in, r_out, order, false, out);
+}
+
+void rg_prism_free(rg_prism *p) { free_prism(p); }
+
+rg_status rg_prism_get_info(const rg_prism *p, rg_prism_info *info)
+{
+    if (!p || !info) { set_error("null argument"); return RG_EINVAL; }
+    info->n_zones = p->nz;
+    info->n_tri = p->ntri;
+    info->n_nodes = p->ref.N;
+    info->n_levels = p->ref.M;
+    info->order = p->order;
+    info->level = p->level;
+    info->n_rad = p->n_rad;
+    return RG_OK;
+}
+
+rg_status rg_prism_triangles(const rg_prism *p, double *abc)
+{
+    if (!p || !abc) { set_error("null argument"); return RG_EINVAL; }
+    std::memcpy(abc, p->tri.data(), p->tri.size() * sizeof(double));
+    return RG_OK;
+}
+
+rg_status rg_prism_geometry(const rg_prism *p, int64_t z0, int64_t nz, double *x, double *J, double *met)
+{
+    if (!p) { set_error("null argument"); return RG_EINVAL; }
+    if (z0 < 0 || nz < 0 || z0 + nz > p->nz) { set_error("zone range outside the mesh"); return RG_EINVAL; }
+    const int N = p->ref.N;
+    for (int64_t zz = 0; zz < nz; zz++) {
+        const int64_t z = z0 + zz, t = z / p->n_rad;
+        const double s = p->radius[z % p->n_rad];
+        for (int i = 0; i < N; i++) {
+            if (x)
+                for (int k = 0; k < 3; k++) x[(zz * N + i) * 3 + k] = s * p->hx[((size_t)t * N + i) * 3 + k];
+            if (J) J[zz * N + i] = s * s * s * p->hJ[(size_t)t * N + i];
+            if (met)
+                for (int m = 0; m < 9; m++) met[(zz * N + i) * 9 + m] = s * s * p->hM[((size_t)t * 9 + m) * N + i];
+        }
+    }
+    return RG_OK;
+}
+
+rg_status rg_prism_predict(const rg_prism *p, double gamma, double dt, int32_t n_picard, const double *Ua,
+                           double *avgU, double *avgF, void *stream)
+{
+    if (!p || !Ua || !avgU || !avgF) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    if (!(gamma > 1.0) || !(dt >= 0.0) || n_picard < 0 || n_picard > 16) {
+        set_error("need gamma > 1, dt >= 0 and 0 <= n_picard <= 16");
+        return RG_EINVAL;
+    }
+    return launch_prism_predict(p->dev, dt, gamma, n_picard, Ua, avgU, avgF, stream);
+}
+
+}  // extern "C"

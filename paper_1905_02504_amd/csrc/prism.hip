@@ -1,0 +1,248 @@
+// ADER-CG predictor on the triangular-prism element (Section V.d, eqs.
+// (5.20)-(5.29); Appendices B-D) for every zone of the icosahedral geodesic
+// mesh.
+//
+// The space-time Galerkin system factors into the 1-D time matrix R and the
+// nodal derivative matrices D_d (the prism spaces of eqs. (5.12)-(5.14) are
+// closed under differentiation), so each Picard sweep is, per time level,
+// mapped fluxes at the nodes followed by sum_d D_d F_d (eqs. C.34-C.36,
+// D.29-D.32).  Layout of a 256-lane workgroup (ZPB zones):
+//  - node phase: lane (zone, node) holds the node's eight conserved values at
+//    every time level and computes its mapped flux (eq. 5.23), written to the
+//    zone's LDS slab as 24 rows (direction, variable) of N values;
+//  - derivative phase: lane (direction, zone, variable) loads one row into
+//    registers and applies that direction's sparse D (compile-time tables) in
+//    place.  ZPB * 8 rows per direction is a multiple of 64, so every
+//    wavefront works on one direction and no lane diverges.
+// The first sweep starts from the tau = 0 state at every level, so it needs
+// only the tau = 0 flux.  Geometry is per column for a unit shell; shell k
+// scales it by r_k, which enters as dt / r_k on the metrics.
+#include <hip/hip_runtime.h>
+
+#include "mhd_device.hpp"
+#include "prism.hpp"
+#include "prism_dtab.hpp"
+
+namespace rg {
+
+template <int P>
+struct PrismLayout {
+    static constexpr int N = PrismD<P>::N;
+    static constexpr int ZPB = P == 2 ? 32 : P == 3 ? 16 : 8;   // zones per workgroup
+    static constexpr int SN = N + 1;                             // slab row stride
+    static constexpr int ZS = 24 * SN;                           // slab of one zone
+    static_assert(ZPB * N <= 256 && (ZPB * 8) % 64 == 0, "workgroup layout");
+};
+
+template <int P, int DIR>
+constexpr int pd_nz()
+{
+    if constexpr (DIR == 0) return PrismD<P>::NZ0;
+    else if constexpr (DIR == 1) return PrismD<P>::NZ1;
+    else return PrismD<P>::NZ2;
+}
+
+template <int P, int DIR>
+constexpr int pd_ent(int e, int k)
+{
+    if constexpr (DIR == 0) return PrismD<P>::E0[e][k];
+    else if constexpr (DIR == 1) return PrismD<P>::E1[e][k];
+    else return PrismD<P>::E2[e][k];
+}
+
+template <int P, int DIR>
+constexpr double pd_val(int e)
+{
+    if constexpr (DIR == 0) return PrismD<P>::V0[e];
+    else if constexpr (DIR == 1) return PrismD<P>::V1[e];
+    else return PrismD<P>::V2[e];
+}
+
+// the in-place row update below writes each output row once, so every row
+// must have an entry and the entries must be grouped by row
+template <int P, int DIR>
+constexpr bool rows_complete()
+{
+    int e = 0;
+    for (int i = 0; i < PrismD<P>::N; i++) {
+        if (e >= pd_nz<P, DIR>() || pd_ent<P, DIR>(e, 0) != i) return false;
+        while (e < pd_nz<P, DIR>() && pd_ent<P, DIR>(e, 0) == i) e++;
+    }
+    return e == pd_nz<P, DIR>();
+}
+static_assert(rows_complete<2, 0>() && rows_complete<2, 1>() && rows_complete<2, 2>(), "order-2 tables");
+static_assert(rows_complete<3, 0>() && rows_complete<3, 1>() && rows_complete<3, 2>(), "order-3 tables");
+static_assert(rows_complete<4, 0>() && rows_complete<4, 1>() && rows_complete<4, 2>(), "order-4 tables");
+
+// row <- D_DIR row (the row holds one variable's DIR-flux at the N nodes)
+template <int P, int DIR>
+__device__ __forceinline__ void prism_row(double *row)
+{
+    constexpr int N = PrismD<P>::N, NZ = pd_nz<P, DIR>();
+    double x[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) x[j] = row[j];
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < NZ; e++) {
+        acc += pd_val<P, DIR>(e) * x[pd_ent<P, DIR>(e, 1)];
+        if (e == NZ - 1 || pd_ent<P, DIR>(e + 1, 0) != pd_ent<P, DIR>(e, 0)) {
+            row[pd_ent<P, DIR>(e, 0)] = acc;
+            acc = 0.0;
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void prism_derivs(double *s_f, int tid)
+{
+    using L = PrismLayout<P>;
+    constexpr int NROW = 3 * L::ZPB * 8;
+#pragma unroll 1
+    for (int rr = tid; rr < NROW; rr += 256) {
+        const int d = rr / (L::ZPB * 8), rem = rr % (L::ZPB * 8);
+        double *row = s_f + (rem / 8) * L::ZS + (d * 8 + rem % 8) * L::SN;
+        if (d == 0) prism_row<P, 0>(row);
+        else if (d == 1) prism_row<P, 1>(row);
+        else prism_row<P, 2>(row);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void prism_predictor(DevPrism G, double dt, double gamma, int npic,
+                                                       const double *__restrict__ Ua, double *__restrict__ aU,
+                                                       double *__restrict__ aF)
+{
+    using L = PrismLayout<P>;
+    constexpr int N = L::N, SN = L::SN, E = P - 1;
+    __shared__ double s_f[L::ZPB * L::ZS];
+    const int tid = threadIdx.x, zl = tid / N, i = tid % N;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const i64 z = (i64)lb * L::ZPB + zl;
+    const bool active = zl < L::ZPB && z < G.nz;
+    double *sf = s_f + (zl < L::ZPB ? zl : 0) * L::ZS;
+    const double gam = gamma;
+
+    double U0[8], met[9], iJ = 1.0, dFa[8], Ut[E][8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) U0[v] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; m++) met[m] = 0.0;
+    if (active) {
+        const i64 t = z / G.n_rad;
+        const int k = (int)(z - t * G.n_rad);
+        const double J = G.J[t * N + i];
+        iJ = 1.0 / J;
+        const double fac = dt * G.rinv[k];
+#pragma unroll
+        for (int m = 0; m < 9; m++) met[m] = fac * G.met[(t * 9 + m) * N + i];
+#pragma unroll
+        for (int v = 0; v < 8; v++) U0[v] = J * Ua[((i64)v * G.nz + z) * N + i];
+        double F[3][8];
+        mapped_flux<double>(U0, iJ, met, gam, F);
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
+    }
+    __syncthreads();
+    prism_derivs<P>(s_f, tid);
+    __syncthreads();
+    const double on = npic > 0 ? 1.0 : 0.0;
+#pragma unroll
+    for (int v = 0; v < 8; v++) dFa[v] = active ? sf[v * SN + i] + sf[(8 + v) * SN + i] + sf[(16 + v) * SN + i] : 0.0;
+#pragma unroll
+    for (int t = 0; t < E; t++) {
+        double rs = G.R[t * P];
+#pragma unroll
+        for (int s = 0; s < E; s++) rs += G.R[t * P + s + 1];
+#pragma unroll
+        for (int v = 0; v < 8; v++) Ut[t][v] = U0[v] - on * rs * dFa[v];
+    }
+    __syncthreads();
+    for (int it = 1; it < npic; it++) {
+        double A[E][8];
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+            if (active) {
+                double F[3][8];
+                mapped_flux<double>(Ut[s], iJ, met, gam, F);
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+#pragma unroll
+                    for (int v = 0; v < 8; v++) sf[(d * 8 + v) * SN + i] = F[d][v];
+            }
+            __syncthreads();
+            prism_derivs<P>(s_f, tid);
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 8; v++)
+                A[s][v] = active ? sf[v * SN + i] + sf[(8 + v) * SN + i] + sf[(16 + v) * SN + i] : 0.0;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < E; t++) {
+            const double r0 = G.R[t * P];
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                double u = U0[v] - r0 * dFa[v];
+#pragma unroll
+                for (int s = 0; s < E; s++) u -= G.R[t * P + s + 1] * A[s][v];
+                Ut[t][v] = u;
+            }
+        }
+    }
+    if (!active) return;
+    // time averages of the state and of the physical flux over the Gauss levels
+    double sU[8], sF[3][8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) { sU[v] = 0.0; sF[0][v] = sF[1][v] = sF[2][v] = 0.0; }
+#pragma unroll
+    for (int t = 0; t < E; t++) {
+        const double wt = G.wt[t + 1];
+        double w[8], F[3][8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) w[v] = Ut[t][v] * iJ;
+        dev_flux<double>(w, gam, F);
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            sU[v] += wt * w[v];
+            sF[0][v] += wt * F[0][v];
+            sF[1][v] += wt * F[1][v];
+            sF[2][v] += wt * F[2][v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) aU[((i64)v * G.nz + z) * N + i] = sU[v];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int v = 0; v < 8; v++) aF[((i64)(d * 8 + v) * G.nz + z) * N + i] = sF[d][v];
+}
+
+template <int P>
+static rg_status launch_order(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
+                              double *aF, hipStream_t st)
+{
+    using L = PrismLayout<P>;
+    const i64 nb = (G.nz + L::ZPB - 1) / L::ZPB;
+    if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (nb == 0) return RG_OK;
+    prism_predictor<P><<<(unsigned)nb, 256, 0, st>>>(G, dt, gamma, npic, Ua, aU, aF);
+    if (hipGetLastError() != hipSuccess) { set_error("prism predictor launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
+rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
+                               double *aF, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (G.order) {
+    case 2: return launch_order<2>(G, dt, gamma, npic, Ua, aU, aF, st);
+    case 3: return launch_order<3>(G, dt, gamma, npic, Ua, aU, aF, st);
+    case 4: return launch_order<4>(G, dt, gamma, npic, Ua, aU, aF, st);
+    default: set_error("prism order must be 2, 3 or 4"); return RG_ENOTSUP;
+    }
+}
+
+}  // namespace rg

@@ -132,6 +132,56 @@ void edge_ref_point(int le, double s, double *xi)
     xi[a2] = (c & 2) ? 0.5 : -0.5;
 }
 
+// time levels tau = 0 plus M-1 Gauss points (eqs. 5.15-5.17), their Gauss
+// weights (wt[0] = 0) and the 1-D time Galerkin matrix R = (K_tau^11)^-1 M^1
+// ((M-1) x M; printed as B.9, C.18, D.28)
+bool time_galerkin(int M, std::vector<double> &tau, std::vector<double> &wt, std::vector<double> &R)
+{
+    const int p = M;
+    tau.assign(p, 0.0);
+    wt.assign(p, 0.0);
+    gauss_legendre01(p - 1, &tau[1], &wt[1]);
+    {
+        const int nq = 8;
+        double tx[8], tw[8];
+        gauss_legendre01(nq, tx, tw);
+        auto phi = [&](int j, double t) {
+            double v = 1.0;
+            for (int k = 0; k < M; k++)
+                if (k != j) v *= (t - tau[k]) / (tau[j] - tau[k]);
+            return v;
+        };
+        auto dphi = [&](int j, double t) {
+            double s = 0.0;
+            for (int k = 0; k < M; k++) {
+                if (k == j) continue;
+                double v = 1.0 / (tau[j] - tau[k]);
+                for (int m = 0; m < M; m++)
+                    if (m != j && m != k) v *= (t - tau[m]) / (tau[j] - tau[m]);
+                s += v;
+            }
+            return s;
+        };
+        int E = M - 1;
+        std::vector<double> K11((size_t)E * E, 0.0), M1((size_t)E * M, 0.0);
+        for (int a = 0; a < nq; a++)
+            for (int j = 1; j < M; j++) {
+                for (int l = 1; l < M; l++) K11[(j - 1) * E + (l - 1)] += tw[a] * phi(j, tx[a]) * dphi(l, tx[a]);
+                for (int l = 0; l < M; l++) M1[(j - 1) * M + l] += tw[a] * phi(j, tx[a]) * phi(l, tx[a]);
+            }
+        std::vector<int> pv;
+        if (!lu_factor(E, K11, pv)) return false;
+        R.assign((size_t)E * M, 0.0);
+        for (int l = 0; l < M; l++) {
+            std::vector<double> col(E);
+            for (int j = 0; j < E; j++) col[j] = M1[j * M + l];
+            lu_solve(E, K11, pv, col.data());
+            for (int j = 0; j < E; j++) R[j * M + l] = col[j];
+        }
+    }
+    return true;
+}
+
 bool build_refel(int order, RefEl &r)
 {
     if (order != 3 && order != 4) return false;
@@ -187,47 +237,7 @@ bool build_refel(int order, RefEl &r)
 
     // time levels and the 1-D time Galerkin matrix
     r.M = p;
-    r.tau.assign(p, 0.0);
-    r.wt.assign(p, 0.0);
-    gauss_legendre01(p - 1, &r.tau[1], &r.wt[1]);
-    {
-        const int M = p, nq = 8;
-        double tx[8], tw[8];
-        gauss_legendre01(nq, tx, tw);
-        auto phi = [&](int j, double t) {
-            double v = 1.0;
-            for (int k = 0; k < M; k++)
-                if (k != j) v *= (t - r.tau[k]) / (r.tau[j] - r.tau[k]);
-            return v;
-        };
-        auto dphi = [&](int j, double t) {
-            double s = 0.0;
-            for (int k = 0; k < M; k++) {
-                if (k == j) continue;
-                double v = 1.0 / (r.tau[j] - r.tau[k]);
-                for (int m = 0; m < M; m++)
-                    if (m != j && m != k) v *= (t - r.tau[m]) / (r.tau[j] - r.tau[m]);
-                s += v;
-            }
-            return s;
-        };
-        int E = M - 1;
-        std::vector<double> K11((size_t)E * E, 0.0), M1((size_t)E * M, 0.0);
-        for (int a = 0; a < nq; a++)
-            for (int j = 1; j < M; j++) {
-                for (int l = 1; l < M; l++) K11[(j - 1) * E + (l - 1)] += tw[a] * phi(j, tx[a]) * dphi(l, tx[a]);
-                for (int l = 0; l < M; l++) M1[(j - 1) * M + l] += tw[a] * phi(j, tx[a]) * phi(l, tx[a]);
-            }
-        std::vector<int> pv;
-        if (!lu_factor(E, K11, pv)) return false;
-        r.R.assign((size_t)E * M, 0.0);
-        for (int l = 0; l < M; l++) {
-            std::vector<double> col(E);
-            for (int j = 0; j < E; j++) col[j] = M1[j * M + l];
-            lu_solve(E, K11, pv, col.data());
-            for (int j = 0; j < E; j++) r.R[j * M + l] = col[j];
-        }
-    }
+    if (!time_galerkin(p, r.tau, r.wt, r.R)) return false;
 
     // Taylor basis multi-indices of degree 1..p-1
     r.tex.clear();

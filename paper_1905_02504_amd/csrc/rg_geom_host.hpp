@@ -35,6 +35,8 @@ struct HostGeom {
 };
 
 void column_surface_nodes(const Mesh &m, int c, double *sn);
+// point at fraction t of the great-circle arc from unit vector a to b
+void arc_point(const double *a, const double *b, double t, double *o);
 void zone_map(int mo, const double *sn, double r0, double r1, const double *xi, double *x, double *jac);
 int moment_index(int a, int b, int c);
 void column_pass1(const Mesh &m, const RefEl &r, int c, ColData &cd);

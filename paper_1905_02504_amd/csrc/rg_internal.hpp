@@ -66,6 +66,7 @@ struct RefEl {
 };
 
 bool build_refel(int order, RefEl &r);
+bool time_galerkin(int M, std::vector<double> &tau, std::vector<double> &wt, std::vector<double> &R);
 void face_ref_point(const RefEl &r, int lf, int q, double *xi);
 void edge_ref_point(int le, double s, double *xi);
 void gauss_legendre01(int n, double *x, double *w);

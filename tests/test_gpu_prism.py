@@ -1,0 +1,135 @@
+"""Parity of the library's prism-element predictor (rg_prism_predict) with the
+oracle's full space-time Galerkin predictor on the same inputs, zone by zone:
+small icosahedral meshes at orders 2-4 (every zone, ragged last workgroups),
+the fourth-order benchmark mesh (level 6, 128 shells) on sampled zones, a
+uniform state at full size, and the argument errors."""
+import numpy as np
+import pytest
+
+from oracle import prism as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GAMMA = 5.0 / 3.0
+TOL = 1e-12
+
+
+def smooth_state(x, rng, noise=0.01):
+    """conserved MHD state [.., 8] from a smooth field at positions x plus
+    seeded multiplicative noise"""
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    rho = 1.0 + 0.2 * np.sin(3 * X) * np.sin(2 * Y + Z)
+    v = np.stack([0.3 * np.sin(Y), 0.3 * np.cos(Z), 0.3 * np.sin(X)], -1)
+    p = 1.0 + 0.1 * np.cos(X + Y)
+    B = np.stack([0.4 + 0.1 * np.sin(Z), 0.2 * np.cos(X), 0.3 * np.sin(Y)], -1)
+    rho = rho * (1 + noise * rng.uniform(-1, 1, rho.shape))
+    p = p * (1 + noise * rng.uniform(-1, 1, p.shape))
+    U = np.empty(x.shape[:-1] + (8,))
+    U[..., 0] = rho
+    U[..., 1:4] = rho[..., None] * v
+    U[..., 4] = p / (GAMMA - 1) + 0.5 * rho * (v * v).sum(-1) + 0.5 * (B * B).sum(-1)
+    U[..., 5:8] = B
+    return U
+
+
+def rel_by_var(a, b, axis):
+    """max |a - b| / max |b| for each variable (variables on `axis`); a
+    variable that vanishes identically (the flux of B_d along d) is measured
+    against the largest variable's scale"""
+    a = np.moveaxis(a, axis, 0).reshape(a.shape[axis], -1)
+    b = np.moveaxis(b, axis, 0).reshape(b.shape[axis], -1)
+    scale = np.abs(b).max(1)
+    return np.abs(a - b).max(1) / np.maximum(scale, 1e-3 * scale.max())
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("level,n_rad,dt", [(0, 5, 0.05), (1, 3, 0.02)])
+def test_prism_predictor_matches_oracle(order, level, n_rad, dt):
+    import paper_1905_02504_amd as R
+    print(f"[prism] order {order}, level {level} x {n_rad} shells, dt {dt}", flush=True)
+    lib = R.PrismMesh(level, n_rad, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(level, n_rad, r_in=1.0, r_out=1.5, order=order)
+    zones = np.arange(om.nz)
+    x, J, met = om.geometry(zones)
+    Ua = smooth_state(x, np.random.default_rng(100 * order + level))
+    aU_o, aF_o = P.predict(order, J, met, Ua, dt, GAMMA)
+    Ua_d = torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda()
+    aU, aF = lib.predict(Ua_d, dt, GAMMA)
+    torch.cuda.synchronize()
+    eU = rel_by_var(aU.cpu().numpy(), aU_o.transpose(2, 0, 1), 0)
+    eF = rel_by_var(aF.cpu().numpy().reshape(24, om.nz, om.N), aF_o.reshape(om.nz, om.N, 24).transpose(2, 0, 1), 0)
+    print(f"[prism] max rel error per variable: avgU {eU.max():.2e}, avgF {eF.max():.2e}", flush=True)
+    assert eU.max() < TOL and eF.max() < TOL
+
+
+def test_prism_predictor_without_sweeps_returns_the_initial_state():
+    """n_picard = 0 keeps every level at the initial state: the averages are
+    the state itself and its physical flux (the Gauss weights sum to one)."""
+    import paper_1905_02504_amd as R
+    from oracle import oracle as O
+    print("[prism] n_picard = 0, order 4, level 0 x 2", flush=True)
+    lib = R.PrismMesh(0, 2, 4)
+    om = P.OraclePrismMesh(0, 2, order=4)
+    x, _, _ = om.geometry(np.arange(om.nz))
+    Ua = smooth_state(x, np.random.default_rng(3))
+    aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), 0.05, GAMMA,
+                         n_picard=0)
+    aU = aU.cpu().numpy().transpose(1, 2, 0)
+    aF = aF.cpu().numpy().transpose(2, 3, 0, 1)
+    np.testing.assert_allclose(aU, Ua, rtol=1e-14, atol=0)
+    F = np.array([[O.flux(u) for u in zu] for zu in Ua])
+    np.testing.assert_allclose(aF, F, rtol=0, atol=1e-13 * np.abs(F).max())
+
+
+def _fullsize():
+    import paper_1905_02504_amd as R
+    return R.PrismMesh(6, 128, 4, r_in=1.0, r_out=2.0)
+
+
+def test_prism_predictor_fullsize_sampled_zones():
+    """The benchmark's launch: order 4 on level 6 (81,920 triangles) x 128
+    shells, 10.5 M zones; uniform state with 5 % seeded noise; sampled zones
+    (first, last, spread in between) against the oracle."""
+    print("[prism] full size: order 4, level 6 x 128 shells, sampled zones", flush=True)
+    lib = _fullsize()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    base = torch.tensor([1.0, 0.3, -0.2, 0.1, 2.0, 0.4, 0.2, -0.3], dtype=torch.float64, device="cuda")
+    Ua = base[:, None, None] * (1 + 0.05 * (2 * torch.rand((8, lib.nz, lib.N), generator=gen, device="cuda",
+                                                             dtype=torch.float64) - 1))
+    dt = 2e-3
+    aU, aF = lib.predict(Ua, dt, GAMMA)
+    torch.cuda.synchronize()
+    assert torch.isfinite(aU).all() and torch.isfinite(aF).all()
+    om = P.OraclePrismMesh(6, 128, r_in=1.0, r_out=2.0, order=4)
+    zones = np.unique(np.concatenate([[0, 1, 127, 128, lib.nz - 1, lib.nz - 2],
+                                      np.random.default_rng(9).integers(0, lib.nz, 18)]))
+    zt = torch.from_numpy(zones).cuda()
+    Us = Ua[:, zt].cpu().numpy().transpose(1, 2, 0)
+    _, J, met = om.geometry(zones)
+    aU_o, aF_o = P.predict(4, J, met, np.ascontiguousarray(Us), dt, GAMMA)
+    eU = rel_by_var(aU[:, zt].cpu().numpy(), aU_o.transpose(2, 0, 1), 0)
+    eF = rel_by_var(aF[:, :, zt].cpu().numpy().reshape(24, len(zones), 26),
+                    aF_o.reshape(len(zones), 26, 24).transpose(2, 0, 1), 0)
+    print(f"[prism] {len(zones)} sampled zones: avgU {eU.max():.2e}, avgF {eF.max():.2e}", flush=True)
+    assert eU.max() < TOL and eF.max() < TOL
+    # free stream at full size: a uniform state stays uniform in every zone
+    Ua.copy_(base[:, None, None].expand_as(Ua))
+    aU, aF = lib.predict(Ua, dt, GAMMA, aU=aU, aF=aF)
+    dev = float((aU - Ua).abs().max() / base.abs().max())
+    print(f"[prism] uniform state: max relative change {dev:.2e}", flush=True)
+    assert dev < 1e-12
+    lib.close()
+
+
+def test_prism_predictor_argument_errors():
+    import paper_1905_02504_amd as R
+    from paper_1905_02504_amd import _native as N
+    print("[prism] argument errors", flush=True)
+    lib = R.PrismMesh(0, 1, 3)
+    U = torch.zeros((8, lib.nz, lib.N), dtype=torch.float64, device="cuda")
+    for g, dt, npic in [(1.0, 0.1, 3), (5 / 3, -1.0, 3), (5 / 3, 0.1, -1), (5 / 3, 0.1, 17)]:
+        with pytest.raises(N.RGError, match="RG_EINVAL"):
+            N.rg_prism_predict(lib._h, g, dt, npic, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_predict(lib._h, 5 / 3, 0.1, 3, 0, U.data_ptr(), U.data_ptr(), 0)
