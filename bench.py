@@ -209,6 +209,49 @@ def time_adjoint(reps=5):
                                                 "face_B": float((gB32 - gB).norm() / gB.norm())}}}
 
 
+def time_prism(level=6, n_rad=128, order=4, reps=5):
+    """The prism element's ADER-CG predictor (rg_prism_predict) on the
+    icosahedral geodesic mesh: fourth order, level 6 (81,920 spherical
+    triangles, mean edge 1.08 degrees: a quarter of the sphere of the paper's
+    finest 0.54-degree, 128-shell mesh, one GPU's share) x 128 logarithmic
+    shells, 10.5 M zones; uniform state with 5 % seeded noise, dt 2e-3.  HIP
+    events on the stream the library runs on."""
+    import torch
+    import paper_1905_02504_amd as R
+    lib = R.PrismMesh(level, n_rad, order, r_in=1.0, r_out=2.0)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    base = torch.tensor([1.0, 0.3, -0.2, 0.1, 2.0, 0.4, 0.2, -0.3], dtype=torch.float64, device="cuda")
+    Ua = base[:, None, None] * (1 + 0.05 * (2 * torch.rand((8, lib.nz, lib.N), generator=gen, device="cuda",
+                                                             dtype=torch.float64) - 1))
+    aU = torch.empty_like(Ua)
+    aF = torch.empty((3, 8, lib.nz, lib.N), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        lib.predict(Ua, 2e-3, aU=aU, aF=aF)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lib.predict(Ua, 2e-3, aU=aU, aF=aF)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    if not (torch.isfinite(aU).all() and torch.isfinite(aF).all()):
+        raise RuntimeError("non-finite prism predictor output")
+    flops, nbytes = lib.work()
+    nz = lib.nz
+    del Ua, aU, aF
+    lib.close()
+    torch.cuda.empty_cache()
+    tf = flops * nz / (ms * 1e-3) / 1e12
+    return {"workload": f"prism ADER-CG predictor, order {order}, icosahedral level {level} "
+                        f"({20 * 4 ** level} triangles) x {n_rad} shells = {nz} zones, uniform state + 5% noise",
+            "zones": nz, "ms_per_predictor": ms, "zone_updates_per_s": nz / (ms * 1e-3),
+            "flops_per_zone": flops, "bytes_per_zone": nbytes,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
+
+
 def measured_peaks(reps=5):
     """Attainable rates on this GPU, beside the datasheet peaks: the FP64
     vector FMA rate of rg_fma_probe (16 independent chains per lane), the FP64
@@ -313,6 +356,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-blast", action="store_true", help="skip the magnetised-blast run")
     ap.add_argument("--no-fallback", action="store_true", help="skip the timing with the fallback on")
+    ap.add_argument("--no-prism", action="store_true", help="skip the prism-element predictor timing")
     ap.add_argument("--calib", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -484,6 +528,13 @@ def main():
         log(f"[bench] blast (order 4, 6x96^3, FP32 form): {blast['fp32']['ms_per_step']:.2f} ms/step, "
             f"{blast['fp32']['fallback_zone_steps']} fallback zone-steps, min rho {blast['fp32']['rho_min']:.4f}, "
             f"min p {blast['fp32']['p_min']:.3e}")
+    prism = None
+    if not args.no_prism:
+        shell.close()   # the prism arrays (about 90 GB) need the HBM the step's buffers hold
+        prism = time_prism()
+        log(f"[bench] prism predictor (order 4, icosahedral level 6 x 128 = {prism['zones']} zones): "
+            f"{prism['ms_per_predictor']:.2f} ms, {prism['zone_updates_per_s'] / 1e6:.1f} M zone-updates/s, "
+            f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,
@@ -511,6 +562,7 @@ def main():
         "adjoint": adjoint,
         "fallback": fallback,
         "blast": blast,
+        "prism": prism,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle sample)")

@@ -439,6 +439,13 @@ rg_status rg_prism_triangles(const rg_prism *prism, double *abc);
  * J d xi_d / d x_n); any output may be NULL.  RG_EINVAL outside the mesh. */
 rg_status rg_prism_geometry(const rg_prism *prism, int64_t z0, int64_t nz, double *x, double *J, double *met);
 
+/* Algorithmic work of rg_prism_predict per zone with n_picard sweeps:
+ * floating-point operations (mapped fluxes 149 per node, the sparse
+ * derivative products, the level updates and the time averages) and HBM
+ * bytes (Ua read, avgU and avgF written, per-column geometry shared by the
+ * column's shells).  Host only. */
+rg_status rg_prism_work(const rg_prism *prism, int32_t n_picard, double *flops_per_zone, double *bytes_per_zone);
+
 /* The ADER-CG predictor of every zone (Section V.d, eqs. (5.20)-(5.29), in
  * the R (x) D form of eqs. (C.34)-(C.36) and (D.29)-(D.32)): from the nodal
  * conserved state Ua at t^n it runs n_picard Picard sweeps over the

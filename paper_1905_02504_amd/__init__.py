@@ -285,6 +285,10 @@ class PrismMesh:
         N.rg_prism_geometry(self._h, z0, nz, _ptr(x), _ptr(J), _ptr(met))
         return x, J, met
 
+    def work(self, n_picard=None):
+        """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""
+        return N.rg_prism_work(self._h, self.order if n_picard is None else n_picard)
+
     def predict(self, Ua, dt, gamma=5.0 / 3.0, n_picard=None, aU=None, aF=None):
         """ADER-CG predictor of every zone: Ua, aU [8][nz][N], aF [3][8][nz][N]
         float64 CUDA tensors (aU, aF allocated when not given)."""

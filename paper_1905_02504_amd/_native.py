@@ -107,7 +107,8 @@ def lib():
         L.rg_prism_triangles.argtypes = [_vp, _vp]
         L.rg_prism_geometry.argtypes = [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]
         L.rg_prism_predict.argtypes = [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp, _vp, _vp]
-        for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_triangles", "rg_prism_geometry",
+        L.rg_prism_work.argtypes = [_vp, C.c_int32, _dp, _dp]
+        for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -321,3 +322,9 @@ def rg_prism_geometry(prism, z0, nz, x_ptr, J_ptr, met_ptr):
 def rg_prism_predict(prism, gamma, dt, n_picard, Ua_ptr, aU_ptr, aF_ptr, stream):
     check(lib().rg_prism_predict(prism, gamma, dt, n_picard, _vp(Ua_ptr), _vp(aU_ptr), _vp(aF_ptr), _vp(stream)),
           "rg_prism_predict")
+
+
+def rg_prism_work(prism, n_picard):
+    f, b = C.c_double(0), C.c_double(0)
+    check(lib().rg_prism_work(prism, n_picard, C.byref(f), C.byref(b)), "rg_prism_work")
+    return f.value, b.value

@@ -318,6 +318,26 @@ rg_status rg_prism_geometry(const rg_prism *p, int64_t z0, int64_t nz, double *x
     return RG_OK;
 }
 
+rg_status rg_prism_work(const rg_prism *p, int32_t n_picard, double *flops_per_zone, double *bytes_per_zone)
+{
+    if (!p || !flops_per_zone || !bytes_per_zone) { set_error("null argument"); return RG_EINVAL; }
+    if (n_picard < 0 || n_picard > 16) { set_error("n_picard outside 0..16"); return RG_EINVAL; }
+    const double N = p->ref.N, E = p->ref.M - 1;
+    int nnz = 0;
+    for (double v : p->ref.D) nnz += std::fabs(v) > 1e-14;
+    // sweeps: the tau = 0 flux, then every level in each further iteration
+    const double sweeps = n_picard > 0 ? 1.0 + (n_picard - 1) * E : 1.0;
+    const double MAPPED_FLUX = 149.0, PHYS_FLUX = 94.0;
+    double f = sweeps * (MAPPED_FLUX * N + 2.0 * 8 * nnz + 2.0 * 8 * N);       // fluxes, sum_d D_d F_d
+    if (n_picard > 0) f += 2.0 * 8 * N * E + (n_picard - 1) * 8 * N * E * (2.0 + 2.0 * E);  // level updates
+    f += 18.0 * N;                                                              // J U, scaled metrics
+    f += (8.0 + PHYS_FLUX + 64.0) * N * E;                                      // time averages
+    *flops_per_zone = f;
+    // Ua read, avgU and avgF written, the column's geometry shared by its shells
+    *bytes_per_zone = 8.0 * (8 * N + 8 * N + 24 * N) + 8.0 * 10 * N / p->n_rad;
+    return RG_OK;
+}
+
 rg_status rg_prism_predict(const rg_prism *p, double gamma, double dt, int32_t n_picard, const double *Ua,
                            double *avgU, double *avgF, void *stream)
 {
