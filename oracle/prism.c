@@ -346,3 +346,114 @@ int rgo_prism_predict(int order, int nz, double gamma, double dt, const double *
     refel_free(&r);
     return rc;
 }
+
+/* ---------------------------------------------------------------- face traces
+ * Face quadrature of Appendix A.  The rules are printed for the triangle
+ * with vertices (0, 0), (1, 0), (1/2, sqrt 3 / 2) and the unit square; the
+ * triangle points are moved to the centred reference triangle.  Triangle
+ * faces: (A.1), (A.3), (A.5) at orders 2, 3, 4; the three quadrilateral side
+ * faces: (A.2), (A.4), (A.6), with x along the triangle edge from vertex k to
+ * vertex k+1 and y along zeta from -1/2 to 1/2.  Points are listed face by
+ * face: zeta = +1/2, zeta = -1/2, then side faces k = 0, 1, 2.  Weights are
+ * fractions of the face's reference area (they sum to one per face). */
+static int tri_rule(int order, double (*p)[2], double *w)
+{
+    const double r3 = S3;
+    if (order == 2) {
+        const double P[3][3] = {{0.25, 0.25 / r3, 1.0 / 3}, {0.75, 0.25 / r3, 1.0 / 3}, {0.5, 1.0 / r3, 1.0 / 3}};
+        for (int i = 0; i < 3; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+        return 3;
+    }
+    if (order == 3) {
+        const double P[6][3] = {{0.125, 0.125 / r3, 0.125}, {0.875, 0.125 / r3, 0.125}, {0.5, 1.25 / r3, 0.125},
+                                {0.375, r3 / 8, 5.0 / 24}, {0.625, r3 / 8, 5.0 / 24}, {0.5, r3 / 4, 5.0 / 24}};
+        for (int i = 0; i < 6; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+        return 6;
+    }
+    const double a = 32.0 / 405, b = 14.0 / 135, c = 19.0 / 135;
+    const double P[10][3] = {{0.125, r3 / 24, a},       {0.875, r3 / 24, a},       {0.5, 5 * r3 / 12, a},
+                             {0.375, r3 / 24, b},       {0.625, r3 / 24, b},       {0.75, r3 / 6, b},
+                             {0.625, 7 * r3 / 24, b},   {0.375, 7 * r3 / 24, b},   {0.25, r3 / 6, b},
+                             {0.5, r3 / 6, c}};
+    for (int i = 0; i < 10; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+    return 10;
+}
+
+static int square_rule(int order, double (*p)[2], double *w)
+{
+    const double g = 0.5 / S3, h = 0.5 * sqrt(3.0 / 5.0);
+    if (order == 2) {
+        const double P[3][3] = {{0.5 - g, 0.5 + g, 0.25}, {0.5 + g, 0.5 + g, 0.25}, {0.5, 0.5 - g, 0.5}};
+        for (int i = 0; i < 3; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+        return 3;
+    }
+    if (order == 3) {
+        const double P[4][3] = {{0.5 - g, 0.5 - g, 0.25}, {0.5 + g, 0.5 - g, 0.25}, {0.5 - g, 0.5 + g, 0.25},
+                                {0.5 + g, 0.5 + g, 0.25}};
+        for (int i = 0; i < 4; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+        return 4;
+    }
+    const double P[6][3] = {{0.5 - g, 0.5 - h, 5.0 / 36}, {0.5 + g, 0.5 - h, 5.0 / 36}, {0.5 - g, 0.5 + h, 5.0 / 36},
+                            {0.5 + g, 0.5 + h, 5.0 / 36}, {0.5 - g, 0.5, 2.0 / 9},      {0.5 + g, 0.5, 2.0 / 9}};
+    for (int i = 0; i < 6; i++) { p[i][0] = P[i][0]; p[i][1] = P[i][1]; w[i] = P[i][2]; }
+    return 6;
+}
+
+/* reference points xi[q][3] and weights w[q] of all five faces; returns the
+ * number of points (nt per triangle face in *nt, ns per side face in *ns) */
+int rgo_prism_face_points(int order, double *xi, double *w, int *nt, int *ns)
+{
+    if (order < 2 || order > 4) return -1;
+    double tp[10][2], tw[10], sp[6][2], sw[6], V[3][2];
+    const int t = tri_rule(order, tp, tw), s = square_rule(order, sp, sw);
+    for (int k = 0; k < 3; k++) tri_vertex(k, V[k]);
+    /* the printed triangle has its first vertex at the origin: shift by the
+     * centred triangle's first vertex */
+    int q = 0;
+    for (int f = 0; f < 2; f++)
+        for (int i = 0; i < t; i++, q++) {
+            xi[3 * q] = tp[i][0] + V[0][0];
+            xi[3 * q + 1] = tp[i][1] + V[0][1];
+            xi[3 * q + 2] = f == 0 ? 0.5 : -0.5;
+            w[q] = tw[i];
+        }
+    for (int k = 0; k < 3; k++)
+        for (int i = 0; i < s; i++, q++) {
+            const double *a = V[k], *b = V[(k + 1) % 3];
+            xi[3 * q] = a[0] + sp[i][0] * (b[0] - a[0]);
+            xi[3 * q + 1] = a[1] + sp[i][0] * (b[1] - a[1]);
+            xi[3 * q + 2] = sp[i][1] - 0.5;
+            w[q] = sw[i];
+        }
+    *nt = t;
+    *ns = s;
+    return q;
+}
+
+/* traces of the time-averaged state and flux at the face points:
+ * tr[z][q][0..8) = sum_l psi_l(xi_q) avgU[z][l], tr[z][q][8 + 8 d + v] the
+ * same of avgF[z][l][d][v] */
+int rgo_prism_traces(int order, int nz, const double *avgU, const double *avgF, double *tr)
+{
+    rgo_refel r;
+    if (prism_basis_init(&r, order)) return -1;
+    double xi[38 * 3], w[38];
+    int nt, ns;
+    const int Q = rgo_prism_face_points(order, xi, w, &nt, &ns), N = r.N;
+    double *psi = malloc(sizeof(double) * Q * N);
+    for (int q = 0; q < Q; q++)
+        for (int l = 0; l < N; l++) psi[q * N + l] = refel_psi(&r, l, &xi[3 * q]);
+    for (int z = 0; z < nz; z++)
+        for (int q = 0; q < Q; q++) {
+            double *o = &tr[((size_t)z * Q + q) * 32];
+            for (int k = 0; k < 32; k++) o[k] = 0.0;
+            for (int l = 0; l < N; l++) {
+                const double p = psi[q * N + l];
+                const double *u = &avgU[((size_t)z * N + l) * 8], *f = &avgF[((size_t)z * N + l) * 24];
+                for (int v = 0; v < 8; v++) o[v] += p * u[v];
+                for (int k = 0; k < 24; k++) o[8 + k] += p * f[k];
+            }
+        }
+    free(psi);
+    return 0;
+}

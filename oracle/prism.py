@@ -42,6 +42,10 @@ def _lib():
         L.rgo_prism_predict.restype = C.c_int
         L.rgo_prism_predict.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp, C.c_void_p,
                                         _dp, _dp]
+        L.rgo_prism_face_points.restype = C.c_int
+        L.rgo_prism_face_points.argtypes = [C.c_int, _dp, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.rgo_prism_traces.restype = C.c_int
+        L.rgo_prism_traces.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
         L._prism_ready = True
     return L
 
@@ -157,3 +161,25 @@ def predict(order, J, met, Ua, dt, gamma=5.0 / 3.0, levels=False):
                                 Ul.ctypes if levels else None, aU, aF):
         raise ValueError("prism predictor failed")
     return (aU, aF, Ul) if levels else (aU, aF)
+
+
+def face_points(order):
+    """reference points [Q][3], weights [Q] (fractions of each face's area),
+    points per triangle face and per side face: faces zeta = +1/2, -1/2, then
+    the side faces on triangle edges 0-1, 1-2, 2-0 (Appendix A)"""
+    xi, w = np.zeros(38 * 3), np.zeros(38)
+    nt, ns = C.c_int(0), C.c_int(0)
+    Q = _lib().rgo_prism_face_points(order, xi, w, C.byref(nt), C.byref(ns))
+    if Q < 0:
+        raise ValueError("order must be 2, 3 or 4")
+    return xi[:3 * Q].reshape(Q, 3), w[:Q], nt.value, ns.value
+
+
+def traces(order, aU, aF):
+    """tr[z][q][32]: time-averaged state (8) and flux (3 x 8) at the face points"""
+    nz = aU.shape[0]
+    Q = len(face_points(order)[1])
+    tr = np.zeros((nz, Q, 32))
+    if _lib().rgo_prism_traces(order, nz, np.ascontiguousarray(aU), np.ascontiguousarray(aF), tr):
+        raise ValueError("prism traces failed")
+    return tr

@@ -96,3 +96,13 @@ def prism_order4_nodes():
 
 def icosahedral_angles():
     return [(int(a), num(b), int(c)) for a, b, c in (ln.split(";") for ln in lines("icosahedral_angles.txt"))]
+
+
+def triangle_rules():
+    out, cur = {}, None
+    for ln in lines("triangle_quadrature.txt"):
+        if ln.startswith("rule"):
+            cur = ln.split()[1]; out[cur] = []
+        else:
+            out[cur].append([num(x) for x in ln.split(";")])
+    return out

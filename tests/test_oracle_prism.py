@@ -254,3 +254,88 @@ def test_predictor_keeps_a_uniform_state_on_curved_zones(order):
     np.testing.assert_allclose(aU, Ua, rtol=0, atol=1e-12)
     F = O.flux(U)
     np.testing.assert_allclose(aF, np.broadcast_to(F, aF.shape), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- face rules and traces
+def _tri_exact(f, n=8):
+    """(1/|T|) integral of f over the printed triangle (0,0), (1,0), (1/2, sqrt 3/2)
+    by a collapsed Gauss-Legendre rule of numpy's (exact for polynomials of
+    degree < 2n - 1)"""
+    g, gw = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1); gw = 0.5 * gw
+    A, B, Cc = np.array([0.0, 0.0]), np.array([1.0, 0.0]), np.array([0.5, S3 / 2])
+    tot = 0.0
+    for s, ws in zip(g, gw):
+        for t, wt in zip(g, gw):
+            x = A + s * (B - A) + (1 - s) * t * (Cc - A)
+            tot += ws * wt * (1 - s) * f(x[0], x[1])
+    return 2 * tot
+
+
+@pytest.mark.parametrize("rule,degree", [("A1", 2), ("A3", 2), ("A5", 3)])
+def test_triangle_rules_of_appendix_A_are_exact(rule, degree):
+    """The printed triangle rules integrate every monomial up to the degree
+    their scheme's order needs (p - 1: second-order rule at least 1, third 2,
+    fourth 3) exactly, with weights summing to one and points inside."""
+    R = np.array(G.triangle_rules()[rule])
+    x, y, w = R[:, 0], R[:, 1], R[:, 2]
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.all(y > 0) and np.all(y < S3 * x) and np.all(y < S3 * (1 - x))
+    for a in range(degree + 1):
+        for b in range(degree + 1 - a):
+            exact = _tri_exact(lambda u, v: u ** a * v ** b)
+            assert abs((w * x ** a * y ** b).sum() - exact) < 1e-14, (rule, a, b)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_face_points_are_the_printed_rules_on_the_prism_faces(order):
+    """The oracle's face points: the printed triangle rule on both triangle
+    faces (shifted to the centred triangle) and the printed square rule on the
+    three side faces (x along the edge, y along zeta)."""
+    xi, w, nt, ns = P.face_points(order)
+    tri = np.array(G.triangle_rules()[{2: "A1", 3: "A3", 4: "A5"}[order]])
+    sq = np.array(G.square_rules()[{2: "A2", 3: "A4", 4: "A6"}[order]])
+    assert (nt, ns) == (len(tri), len(sq)) and len(w) == 2 * nt + 3 * ns
+    v1 = np.array([-0.5, -0.5 / S3])
+    for f, zeta in ((0, 0.5), (1, -0.5)):
+        blk = slice(f * nt, (f + 1) * nt)
+        np.testing.assert_allclose(xi[blk, :2], tri[:, :2] + v1, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(xi[blk, 2], zeta, rtol=0, atol=0)
+        np.testing.assert_allclose(w[blk], tri[:, 2], rtol=0, atol=1e-16)
+    V = np.array([[-0.5, -0.5 / S3], [0.5, -0.5 / S3], [0.0, 1 / S3]])
+    for k in range(3):
+        blk = slice(2 * nt + k * ns, 2 * nt + (k + 1) * ns)
+        along = V[k] + sq[:, :1] * (V[(k + 1) % 3] - V[k])
+        np.testing.assert_allclose(xi[blk, :2], along, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(xi[blk, 2], sq[:, 1] - 0.5, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(w[blk], sq[:, 2], rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_traces_reproduce_polynomials_of_the_space(order):
+    """Nodal values of a monomial of the element's space, traced to the face
+    points, give the monomial's values there (the nodal interpolant is exact)."""
+    r = P.refel(order)
+    xi, w, nt, ns = P.face_points(order)
+    X = r["nodes"]
+    rng = np.random.default_rng(order)
+    aU = np.zeros((1, r["N"], 8)); aF = np.zeros((1, r["N"], 3, 8))
+    want = np.zeros((len(w), 32))
+    for k in range(32):
+        e = r["exps"][rng.integers(len(r["exps"]))]
+        c = rng.normal()
+        vals = c * np.prod(X ** e, axis=1)
+        (aU[0, :, k] if k < 8 else aF[0, :, (k - 8) // 8, (k - 8) % 8])[...] = vals
+        want[:, k] = c * np.prod(xi ** e, axis=1)
+    tr = P.traces(order, aU, aF)
+    np.testing.assert_allclose(tr[0], want, rtol=0, atol=1e-12 * max(1, np.abs(want).max()))
+
+
+def test_square_rule_A2_integrates_bilinear_functions():
+    """(A.2), the second-order side-face rule, integrates 1, x, y and x y over
+    the unit square exactly (all a second-order trace needs)."""
+    R = np.array(G.square_rules()["A2"])
+    x, y, w = R[:, 0], R[:, 1], R[:, 2]
+    for f, exact in ((lambda a, b: 1 + 0 * a, 1.0), (lambda a, b: a, 0.5), (lambda a, b: b, 0.5),
+                     (lambda a, b: a * b, 0.25)):
+        assert abs((w * f(x, y)).sum() - exact) < 1e-15
