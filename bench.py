@@ -238,9 +238,22 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     ms = e0.elapsed_time(e1) / reps
     if not (torch.isfinite(aU).all() and torch.isfinite(aF).all()):
         raise RuntimeError("non-finite prism predictor output")
+    # face traces at the rules of Appendix A (HBM-bound: 32 N values read and
+    # 32 Q written per zone)
+    del Ua
+    tr = torch.empty((32, lib.nz, lib.Q), dtype=torch.float64, device="cuda")
+    lib.traces(aU, aF, tr)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        lib.traces(aU, aF, tr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_tr = e0.elapsed_time(e1) / reps
+    tr_bytes = 8.0 * 32 * (lib.N + lib.Q)
     flops, nbytes = lib.work()
-    nz = lib.nz
-    del Ua, aU, aF
+    nz, lib_q = lib.nz, lib.Q
+    del aU, aF, tr
     lib.close()
     torch.cuda.empty_cache()
     tf = flops * nz / (ms * 1e-3) / 1e12
@@ -248,6 +261,8 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
                         f"({20 * 4 ** level} triangles) x {n_rad} shells = {nz} zones, uniform state + 5% noise",
             "zones": nz, "ms_per_predictor": ms, "zone_updates_per_s": nz / (ms * 1e-3),
             "flops_per_zone": flops, "bytes_per_zone": nbytes,
+            "traces": {"ms": ms_tr, "face_points_per_zone": lib_q, "bytes_per_zone": tr_bytes,
+                       "hbm_gbs": tr_bytes * nz / (ms_tr * 1e-3) / 1e9},
             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
 
@@ -534,7 +549,8 @@ def main():
         prism = time_prism()
         log(f"[bench] prism predictor (order 4, icosahedral level 6 x 128 = {prism['zones']} zones): "
             f"{prism['ms_per_predictor']:.2f} ms, {prism['zone_updates_per_s'] / 1e6:.1f} M zone-updates/s, "
-            f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak)")
+            f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak); "
+            f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,

@@ -414,6 +414,7 @@ typedef struct {
     int32_t n_nodes;   /* nodes per zone: 6, 15, 26             */
     int32_t n_levels;  /* time levels: order                    */
     int32_t order, level, n_rad;
+    int32_t n_face_points;  /* face points per zone: 15, 24, 38      */
 } rg_prism_info;
 
 /* Builds the mesh and, on the current device, the geometry of every column
@@ -438,6 +439,26 @@ rg_status rg_prism_triangles(const rg_prism *prism, double *abc);
  * Jacobians J[nz][N] and metrics met[nz][N][3][3] (row d, column n:
  * J d xi_d / d x_n); any output may be NULL.  RG_EINVAL outside the mesh. */
 rg_status rg_prism_geometry(const rg_prism *prism, int64_t z0, int64_t nz, double *x, double *J, double *met);
+
+/* Face points of Appendix A in reference coordinates, xi[Q][3], and their
+ * weights w[Q] (fractions of each face's reference area): the triangle rule
+ * (A.1), (A.3) or (A.5) on the face zeta = +1/2, then on zeta = -1/2, then the
+ * square rule (A.2), (A.4) or (A.6) on the side faces over the triangle edges
+ * from vertex k to k + 1 (k = 0, 1, 2; x along the edge, y along zeta).  The
+ * triangle rules are printed for a triangle with a vertex at the origin and
+ * are moved to the centred one; within a face the points are in the
+ * library's order.  Q = 2 n_tri_points + 3 n_side_points; any output may be
+ * NULL.  Host only. */
+rg_status rg_prism_face_points(const rg_prism *prism, double *xi, double *w, int32_t *n_tri_points,
+                               int32_t *n_side_points);
+
+/* Traces of the predictor's time averages at the face points, the corrector's
+ * quadrature inputs (Section VI): tr[k][z][q] = sum_l psi_l(xi_q) a_k[z][l]
+ * for the 32 values a = (avgU[0..8), avgF[0][0..8), avgF[1][0..8),
+ * avgF[2][0..8)).  Device arrays as written by rg_prism_predict; tr is
+ * double[32][n_zones][Q], caller-owned.  Asynchronous on stream.  RG_EINVAL
+ * for null pointers or a host-only mesh. */
+rg_status rg_prism_traces(const rg_prism *prism, const double *avgU, const double *avgF, double *tr, void *stream);
 
 /* Algorithmic work of rg_prism_predict per zone with n_picard sweeps:
  * floating-point operations (mapped fluxes 149 per node, the sparse

@@ -261,6 +261,7 @@ class PrismMesh:
         self._h = build(level, n_rad, r_in, r_out, order)
         info = N.rg_prism_get_info(self._h)
         self.nz, self.ntri, self.N = info["n_zones"], info["n_tri"], info["n_nodes"]
+        self.Q = info["n_face_points"]
         self.level, self.n_rad, self.order = level, n_rad, order
 
     def close(self):
@@ -284,6 +285,21 @@ class PrismMesh:
         x, J, met = np.zeros((nz, self.N, 3)), np.zeros((nz, self.N)), np.zeros((nz, self.N, 3, 3))
         N.rg_prism_geometry(self._h, z0, nz, _ptr(x), _ptr(J), _ptr(met))
         return x, J, met
+
+    def face_points(self):
+        """reference face points [Q][3], weights [Q], points per triangle face, per side face"""
+        xi, w = np.zeros((self.Q, 3)), np.zeros(self.Q)
+        nt, ns = N.rg_prism_face_points(self._h, _ptr(xi), _ptr(w))
+        return xi, w, nt, ns
+
+    def traces(self, aU, aF, tr=None):
+        """face-point traces [32][nz][Q] of predict()'s averages (float64 CUDA tensors)"""
+        import torch
+        assert aU.is_contiguous() and aF.is_contiguous()
+        if tr is None:
+            tr = torch.empty((32, self.nz, self.Q), dtype=torch.float64, device=aU.device)
+        N.rg_prism_traces(self._h, _ptr(aU), _ptr(aF), _ptr(tr), _stream())
+        return tr
 
     def work(self, n_picard=None):
         """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""

@@ -40,7 +40,7 @@ class rg_diag_out(C.Structure):
 
 class rg_prism_info(C.Structure):
     _fields_ = [("n_zones", C.c_int64), ("n_tri", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
-                ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32)]
+                ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32), ("n_face_points", C.c_int32)]
 
 
 class RGError(RuntimeError):
@@ -108,7 +108,10 @@ def lib():
         L.rg_prism_geometry.argtypes = [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]
         L.rg_prism_predict.argtypes = [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp, _vp, _vp]
         L.rg_prism_work.argtypes = [_vp, C.c_int32, _dp, _dp]
-        for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work", "rg_prism_triangles", "rg_prism_geometry",
+        L.rg_prism_face_points.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.rg_prism_traces.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work",
+                     "rg_prism_face_points", "rg_prism_traces", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -328,3 +331,14 @@ def rg_prism_work(prism, n_picard):
     f, b = C.c_double(0), C.c_double(0)
     check(lib().rg_prism_work(prism, n_picard, C.byref(f), C.byref(b)), "rg_prism_work")
     return f.value, b.value
+
+
+def rg_prism_face_points(prism, xi_ptr, w_ptr):
+    nt, ns = C.c_int32(0), C.c_int32(0)
+    check(lib().rg_prism_face_points(prism, _vp(xi_ptr), _vp(w_ptr), C.byref(nt), C.byref(ns)),
+          "rg_prism_face_points")
+    return nt.value, ns.value
+
+
+def rg_prism_traces(prism, aU_ptr, aF_ptr, tr_ptr, stream):
+    check(lib().rg_prism_traces(prism, _vp(aU_ptr), _vp(aF_ptr), _vp(tr_ptr), _vp(stream)), "rg_prism_traces")

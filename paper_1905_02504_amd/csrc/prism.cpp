@@ -75,14 +75,15 @@ void free_prism(rg_prism *p)
     delete p;
 }
 
-bool upload(rg_prism *p, const std::vector<double> &h, const double **dst)
+template <class T>
+bool upload(rg_prism *p, const std::vector<T> &h, const T **dst)
 {
     void *d = nullptr;
-    if (hipMalloc(&d, std::max<size_t>(8, h.size() * sizeof(double))) != hipSuccess) return false;
+    if (hipMalloc(&d, std::max<size_t>(8, h.size() * sizeof(T))) != hipSuccess) return false;
     p->allocations.push_back(d);
-    if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
         return false;
-    *dst = static_cast<const double *>(d);
+    *dst = static_cast<const T *>(d);
     return true;
 }
 
@@ -257,8 +258,10 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     for (int k = 0; k < n_rad; k++) rinv[k] = 1.0 / p->radius[k];
     DevPrism &G = p->dev;
     G.order = order; G.N = N; G.n_rad = n_rad; G.ntri = p->ntri; G.nz = p->nz;
+    G.Q = p->ref.Q;
     if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
-        !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt)) {
+        !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt) || !upload(p, p->ref.fidx, &G.fidx) ||
+        !upload(p, p->ref.fval, &G.fval)) {
         set_error("device allocation or upload of the prism geometry failed");
         free_prism(p);
         return RG_ENOMEM;
@@ -289,7 +292,28 @@ rg_status rg_prism_get_info(const rg_prism *p, rg_prism_info *info)
     info->order = p->order;
     info->level = p->level;
     info->n_rad = p->n_rad;
+    info->n_face_points = p->ref.Q;
     return RG_OK;
+}
+
+rg_status rg_prism_face_points(const rg_prism *p, double *xi, double *w, int32_t *n_tri_points, int32_t *n_side_points)
+{
+    if (!p) { set_error("null argument"); return RG_EINVAL; }
+    for (int q = 0; q < p->ref.Q; q++) {
+        if (xi)
+            for (int k = 0; k < 3; k++) xi[3 * q + k] = p->ref.fpt[q][k];
+        if (w) w[q] = p->ref.fw[q];
+    }
+    if (n_tri_points) *n_tri_points = p->ref.QT;
+    if (n_side_points) *n_side_points = p->ref.QS;
+    return RG_OK;
+}
+
+rg_status rg_prism_traces(const rg_prism *p, const double *avgU, const double *avgF, double *tr, void *stream)
+{
+    if (!p || !avgU || !avgF || !tr) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    return launch_prism_traces(p->dev, avgU, avgF, tr, stream);
 }
 
 rg_status rg_prism_triangles(const rg_prism *p, double *abc)

@@ -276,6 +276,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         for (int v = 0; v < 8; v++) aF[((i64)(d * 8 + v) * G.nz + z) * N + i] = sF[d][v];
 }
 
+// Face traces: a 256-lane workgroup stages the 32 nodal averages of ZB zones
+// in LDS (coalesced: for each value the ZB zones' nodes are contiguous), then
+// lane (zone, face point) sums the at most TRACE_TERMS basis values of the
+// nodes on its face.  Bound by HBM: 32 N values read and 32 Q written per zone.
+template <int P>
+struct TraceLayout {
+    static constexpr int N = PrismD<P>::N;
+    static constexpr int Q = P == 2 ? 15 : P == 3 ? 24 : 38;
+    static constexpr int ZB = 256 / Q;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void prism_traces(DevPrism G, const double *__restrict__ aU,
+                                                    const double *__restrict__ aF, double *__restrict__ tr)
+{
+    using L = TraceLayout<P>;
+    constexpr int N = L::N, Q = L::Q, ZB = L::ZB;
+    __shared__ double s_v[ZB * 32 * N];
+    const int tid = threadIdx.x;
+    const i64 z0 = (i64)xcd_block(blockIdx.x, gridDim.x) * ZB;
+    const int nzb = (int)(G.nz - z0 < ZB ? G.nz - z0 : ZB);
+    for (int e = tid; e < 32 * ZB * N; e += 256) {
+        const int k = e / (ZB * N), rem = e - k * (ZB * N);
+        if (rem < nzb * N) {
+            const double *src = k < 8 ? aU + (i64)k * G.nz * N : aF + (i64)(k - 8) * G.nz * N;
+            s_v[k * ZB * N + rem] = src[z0 * N + rem];
+        }
+    }
+    __syncthreads();
+    const int zl = tid / Q, q = tid - zl * Q;
+    if (zl >= nzb) return;
+    int idx[TRACE_TERMS];
+    double w[TRACE_TERMS];
+#pragma unroll
+    for (int t = 0; t < TRACE_TERMS; t++) {
+        idx[t] = G.fidx[q * TRACE_TERMS + t];
+        w[t] = G.fval[q * TRACE_TERMS + t];
+    }
+    const i64 z = z0 + zl;
+#pragma unroll 4
+    for (int k = 0; k < 32; k++) {
+        const double *sv = s_v + k * ZB * N + zl * N;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < TRACE_TERMS; t++) acc += w[t] * sv[idx[t]];
+        tr[((i64)k * G.nz + z) * Q + q] = acc;
+    }
+}
+
+template <int P>
+static rg_status launch_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, hipStream_t st)
+{
+    using L = TraceLayout<P>;
+    if (G.Q != L::Q) { set_error("face point count differs from the kernel's"); return RG_EINVAL; }
+    const i64 nb = (G.nz + L::ZB - 1) / L::ZB;
+    if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (nb == 0) return RG_OK;
+    prism_traces<P><<<(unsigned)nb, 256, 0, st>>>(G, aU, aF, tr);
+    if (hipGetLastError() != hipSuccess) { set_error("prism trace launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
+rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (G.order) {
+    case 2: return launch_traces<2>(G, aU, aF, tr, st);
+    case 3: return launch_traces<3>(G, aU, aF, tr, st);
+    case 4: return launch_traces<4>(G, aU, aF, tr, st);
+    default: set_error("prism order must be 2, 3 or 4"); return RG_ENOTSUP;
+    }
+}
+
 template <int P>
 static rg_status launch_order(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                               double *aF, hipStream_t st)

@@ -19,7 +19,20 @@ struct PrismRef {
     std::vector<double> D;          // 3 x N x N: d psi_l / d xi_d at node i
     std::vector<double> tau, wt, R; // time levels, Gauss weights, (M-1) x M time matrix
     std::vector<int> lat;           // N: index of the node's (xi, eta) in the map's triangle lattice
+    std::vector<double> coef;       // N x N: psi_l = sum_k coef[k * N + l] m_k
+    // face points of Appendix A: faces zeta = +1/2, -1/2, then the side faces
+    // on triangle edges 0-1, 1-2, 2-0; weights as fractions of the face
+    int QT = 0, QS = 0, Q = 0;
+    std::vector<std::array<double, 3>> fpt;
+    std::vector<double> fw;
+    // the nodes whose basis functions are non-zero at each face point, and
+    // their values there (Q x TRACE_TERMS, padded with weight 0)
+    std::vector<int> fidx;
+    std::vector<double> fval;
+    double psi(int l, const double *xi) const;
 };
+
+constexpr int TRACE_TERMS = 12;   // at most 12 nodes on a face (fourth-order side faces)
 
 bool build_prism_ref(int order, PrismRef &r);
 
@@ -43,8 +56,12 @@ struct DevPrism {
     const double *rinv;   // n_rad: 1 / r_k
     const double *R;      // (M-1) x M
     const double *wt;     // M
+    int Q;                // face points per zone
+    const int *fidx;      // Q x TRACE_TERMS
+    const double *fval;   // Q x TRACE_TERMS
 };
 
+rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream);
 rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                                double *aF, void *stream);
 

@@ -1,5 +1,6 @@
-"""Parity of the library's prism-element predictor (rg_prism_predict) with the
-oracle's full space-time Galerkin predictor on the same inputs, zone by zone:
+"""Parity of the library's prism-element predictor (rg_prism_predict) and its
+face traces (rg_prism_traces) with the oracle's full space-time Galerkin
+predictor and traces on the same inputs, zone by zone:
 small icosahedral meshes at orders 2-4 (every zone, ragged last workgroups),
 the fourth-order benchmark mesh (level 6, 128 shells) on sampled zones, a
 uniform state at full size, and the argument errors."""
@@ -63,6 +64,39 @@ def test_prism_predictor_matches_oracle(order, level, n_rad, dt):
     assert eU.max() < TOL and eF.max() < TOL
 
 
+def _point_map(lib, order):
+    """library face point q -> the oracle's point at the same coordinates"""
+    xl, wl, nt, ns = lib.face_points()
+    xo, wo, nto, nso = P.face_points(order)
+    assert (nt, ns) == (nto, nso)
+    d = np.linalg.norm(xl[:, None, :] - xo[None, :, :], axis=2)
+    j = d.argmin(1)
+    assert d.min(1).max() < 1e-14 and len(set(j.tolist())) == len(j)
+    np.testing.assert_allclose(wl, wo[j], rtol=0, atol=1e-15)
+    return j
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_traces_match_oracle(order):
+    """Face-point traces (rg_prism_traces) of the library's averages against the
+    oracle's traces of its own averages, level 1 x 3 shells (ragged last
+    workgroup at every order)."""
+    import paper_1905_02504_amd as R
+    print(f"[prism] traces, order {order}, level 1 x 3 shells", flush=True)
+    lib = R.PrismMesh(1, 3, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.5, order=order)
+    x, J, met = om.geometry(np.arange(om.nz))
+    Ua = smooth_state(x, np.random.default_rng(7 + order))
+    aU_o, aF_o = P.predict(order, J, met, Ua, 0.02, GAMMA)
+    tr_o = P.traces(order, aU_o, aF_o)                           # [z][q][32]
+    aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), 0.02, GAMMA)
+    tr = lib.traces(aU, aF).cpu().numpy()                        # [32][z][q]
+    j = _point_map(lib, order)
+    e = rel_by_var(tr, tr_o[:, j, :].transpose(2, 0, 1), 0)
+    print(f"[prism] traces: max rel error per value {e.max():.2e}", flush=True)
+    assert e.max() < TOL
+
+
 def test_prism_predictor_without_sweeps_returns_the_initial_state():
     """n_picard = 0 keeps every level at the initial state: the averages are
     the state itself and its physical flux (the Gauss weights sum to one)."""
@@ -113,6 +147,14 @@ def test_prism_predictor_fullsize_sampled_zones():
                     aF_o.reshape(len(zones), 26, 24).transpose(2, 0, 1), 0)
     print(f"[prism] {len(zones)} sampled zones: avgU {eU.max():.2e}, avgF {eF.max():.2e}", flush=True)
     assert eU.max() < TOL and eF.max() < TOL
+    # face traces of the whole mesh, sampled zones against the oracle's
+    tr = lib.traces(aU, aF)
+    tr_o = P.traces(4, aU_o, aF_o)
+    j = _point_map(lib, 4)
+    eT = rel_by_var(tr[:, zt].cpu().numpy(), tr_o[:, j, :].transpose(2, 0, 1), 0)
+    print(f"[prism] sampled traces: {eT.max():.2e}", flush=True)
+    assert eT.max() < TOL
+    del tr
     # free stream at full size: a uniform state stays uniform in every zone
     Ua.copy_(base[:, None, None].expand_as(Ua))
     aU, aF = lib.predict(Ua, dt, GAMMA, aU=aU, aF=aF)
@@ -133,3 +175,5 @@ def test_prism_predictor_argument_errors():
             N.rg_prism_predict(lib._h, g, dt, npic, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_predict(lib._h, 5 / 3, 0.1, 3, 0, U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_traces(lib._h, U.data_ptr(), 0, U.data_ptr(), 0)
