@@ -3,8 +3,8 @@
 Two small drivers are compiled with -fsanitize=address,undefined and run:
 the oracle (one third- and one fourth-order step on tiny meshes), and the
 library's host side (mesh build, geometry precompute without a device, the
-host initialiser, argument errors) with the device launchers replaced by
-stubs that refuse.  A sanitizer report makes the run exit non-zero.
+host initialiser, argument errors, the prism element's mesh, geometry and
+face points) with the device launchers replaced by stubs that refuse.  A sanitizer report makes the run exit non-zero.
 """
 import os
 import shutil
@@ -72,6 +72,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     #include <cstdio>
     #include <vector>
     #include "rg_geom_host.hpp"
+    #include "prism.hpp"
     namespace rg {
     // the device side is not linked: every launcher refuses
     rg_status launch_step(rg_geom *, const rg_step_params &, const double *, const double *, double *, double *, void *) { return RG_ENOTSUP; }
@@ -85,6 +86,28 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_diag(rg_geom *, const double *, const double *, double, void *, rg_diag_out *) { return RG_ENOTSUP; }
     rg_status launch_fma_probe(double *, long long, int, void *) { return RG_ENOTSUP; }
     rg_status launch_mfma_probe(double *, long long, int, int, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_predict(const DevPrism &, double, double, int, const double *, double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_traces(const DevPrism &, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
+    }
+    // the prism element's host side: mesh, geometry and face-point queries
+    static int run_prism(int order) {
+        rg_prism *p = nullptr;
+        if (rg_prism_build_host(2, 3, 1.0, 1.6, order, &p) != RG_OK) { std::printf("%s\n", rg_last_error()); return 10; }
+        rg_prism_info info;
+        rg_prism_get_info(p, &info);
+        std::vector<double> abc(9 * info.n_tri), x(3 * 5 * info.n_nodes), J(5 * info.n_nodes), met(45 * info.n_nodes);
+        std::vector<double> xi(3 * info.n_face_points), w(info.n_face_points);
+        int rc = rg_prism_triangles(p, abc.data());
+        if (rc == RG_OK) rc = rg_prism_geometry(p, info.n_zones - 5, 5, x.data(), J.data(), met.data());
+        int32_t nt = 0, ns = 0;
+        if (rc == RG_OK) rc = rg_prism_face_points(p, xi.data(), w.data(), &nt, &ns);
+        double f = 0, b = 0;
+        if (rc == RG_OK) rc = rg_prism_work(p, order, &f, &b);
+        if (rg_prism_geometry(p, info.n_zones - 4, 5, x.data(), J.data(), met.data()) != RG_EINVAL) rc = 11;
+        if (rg_prism_predict(p, 5.0 / 3.0, 1e-3, order, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 12;
+        rg_prism_free(p);
+        if (rg_prism_build_host(9, 3, 1.0, 1.6, order, &p) != RG_ENOTSUP) rc = 13;
+        return rc;
     }
     static int run(int order) {
         rg_mesh_desc d{4, 3, 1.0, 2.0, 0, order - 1, 3};
@@ -128,6 +151,7 @@ LIB_DRIVER = textwrap.dedent(r"""
         rg_mesh_desc bad{10, 3, 1.0, 2.0, 0, 2, 3};   // neither 2^k nor 3 x 2^k
         int rc = rg_mesh_build(&bad, &m) == RG_OK;
         rc |= run(3) | run(4);
+        rc |= run_prism(2) | run_prism(3) | run_prism(4);
         std::printf("library host driver rc=%d\n", rc);
         return rc;
     }
@@ -159,7 +183,8 @@ def test_library_host_side_under_sanitizers(tmp_path):
         pytest.skip("HIP headers not available")
     drv = tmp_path / "lib_driver.cpp"
     drv.write_text(LIB_DRIVER)
-    srcs = [os.path.join(CSRC, s) for s in ("mesh.cpp", "refel.cpp", "geom.cpp", "init.cpp", "capi.cpp")]
+    srcs = [os.path.join(CSRC, s) for s in ("mesh.cpp", "refel.cpp", "geom.cpp", "init.cpp", "capi.cpp",
+                                            "prism_ref.cpp", "prism.cpp")]
     exe = tmp_path / "lib_driver"
     cmd = ["g++", "-std=c++17", "-fopenmp", *SAN, "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include",
            f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", str(drv), *srcs, "-o", str(exe),
