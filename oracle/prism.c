@@ -457,3 +457,61 @@ int rgo_prism_traces(int order, int nz, const double *avgU, const double *avgF, 
     free(psi);
     return 0;
 }
+
+/* ---------------------------------------------------------------- face fluxes
+ * Geometry of the face points of nz zones: positions xq[z][Q][3] and the
+ * outward area vectors dAw[z][Q][3], each the rule's weight times the face's
+ * reference area (sqrt 3 / 4 for the triangles, 1 for the side faces) times
+ * the cross product of the map's tangents: d x / d xi x d x / d eta on the
+ * triangle faces (sign + on zeta = 1/2, - on zeta = -1/2), and on side face k
+ * (d x / d s) x (d x / d zeta) with s along the edge from vertex k to k + 1,
+ * which points out of a counter-clockwise triangle. */
+int rgo_prism_face_geometry(int order, int nz, const double *abc, const double *r01, double *xq, double *dAw)
+{
+    rgo_refel r;
+    if (prism_basis_init(&r, order)) return -1;
+    double xi[38 * 3], w[38], V[3][2];
+    int nt, ns;
+    const int Q = rgo_prism_face_points(order, xi, w, &nt, &ns);
+    for (int k = 0; k < 3; k++) tri_vertex(k, V[k]);
+    for (int z = 0; z < nz; z++) {
+        tri_map t;
+        if (tri_map_init(&t, order - 1, &abc[9 * z], &abc[9 * z + 3], &abc[9 * z + 6])) return -1;
+        for (int q = 0; q < Q; q++) {
+            double jac[9], a[3], b[3], c[3];
+            prism_map(&t, r01[2 * z], r01[2 * z + 1], &xi[3 * q], &xq[((size_t)z * Q + q) * 3], jac);
+            double scale;
+            if (q < 2 * nt) {
+                for (int i = 0; i < 3; i++) { a[i] = jac[3 * i]; b[i] = jac[3 * i + 1]; }
+                scale = (q < nt ? 1.0 : -1.0) * (S3 / 4.0) * w[q];
+            } else {
+                const int k = (q - 2 * nt) / ns;
+                const double ex = V[(k + 1) % 3][0] - V[k][0], ey = V[(k + 1) % 3][1] - V[k][1];
+                for (int i = 0; i < 3; i++) { a[i] = jac[3 * i] * ex + jac[3 * i + 1] * ey; b[i] = jac[3 * i + 2]; }
+                scale = w[q];
+            }
+            c[0] = a[1] * b[2] - a[2] * b[1];
+            c[1] = a[2] * b[0] - a[0] * b[2];
+            c[2] = a[0] * b[1] - a[1] * b[0];
+            for (int i = 0; i < 3; i++) dAw[((size_t)z * Q + q) * 3 + i] = scale * c[i];
+        }
+    }
+    return 0;
+}
+
+/* HLL (Section II.c, as for the hexahedra) at np points: left and right
+ * states U[np][8] and Cartesian fluxes F[np][3][8] (the traces of the
+ * time averages), unit normals n[np][3] from left to right; Fs[np][8] */
+void rgo_prism_hll(int np, const double *UL, const double *UR, const double *FL, const double *FR, const double *n,
+                   double gamma, double *Fs)
+{
+    for (int p = 0; p < np; p++) {
+        double FnL[NVAR], FnR[NVAR];
+        const double *nn = &n[3 * p];
+        for (int v = 0; v < NVAR; v++) {
+            FnL[v] = nn[0] * FL[p * 24 + v] + nn[1] * FL[p * 24 + 8 + v] + nn[2] * FL[p * 24 + 16 + v];
+            FnR[v] = nn[0] * FR[p * 24 + v] + nn[1] * FR[p * 24 + 8 + v] + nn[2] * FR[p * 24 + 16 + v];
+        }
+        hll_flux(&UL[p * NVAR], &UR[p * NVAR], FnL, FnR, nn, gamma, &Fs[p * NVAR]);
+    }
+}

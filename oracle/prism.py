@@ -46,6 +46,10 @@ def _lib():
         L.rgo_prism_face_points.argtypes = [C.c_int, _dp, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.rgo_prism_traces.restype = C.c_int
         L.rgo_prism_traces.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+        L.rgo_prism_face_geometry.restype = C.c_int
+        L.rgo_prism_face_geometry.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.rgo_prism_hll.restype = None
+        L.rgo_prism_hll.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
         L._prism_ready = True
     return L
 
@@ -142,6 +146,82 @@ class OraclePrismMesh:
         if _lib().rgo_prism_geometry(self.order, nz, abc, r01, x, J, met):
             raise ValueError("prism geometry failed")
         return x, J, met
+
+    def face_geometry(self, zones):
+        """face-point positions xq[z][Q][3] and weighted outward area vectors
+        dAw[z][Q][3] of the given zones"""
+        t, k = self.zone_tri_shell(zones)
+        nz = len(t)
+        Q = len(face_points(self.order)[1])
+        abc = np.ascontiguousarray(self.vert[self.tri[t]].reshape(nz, 9))
+        r01 = np.ascontiguousarray(np.stack([self.radius[k], self.radius[k + 1]], 1))
+        xq, dA = np.zeros((nz, Q, 3)), np.zeros((nz, Q, 3))
+        if _lib().rgo_prism_face_geometry(self.order, nz, abc, r01, xq, dA):
+            raise ValueError("prism face geometry failed")
+        return xq, dA
+
+    def edges(self):
+        """mesh edges in first-encounter order over (triangle, local edge
+        0: a-b, 1: b-c, 2: c-a): [n_edges][4] = (t, local edge, t', local edge'),
+        t < t'"""
+        where = {}
+        for t, (a, b, c) in enumerate(self.tri):
+            for e, (u, v) in enumerate(((a, b), (b, c), (c, a))):
+                where[(u, v)] = (t, e)
+        out = []
+        for t, (a, b, c) in enumerate(self.tri):
+            for e, (u, v) in enumerate(((a, b), (b, c), (c, a))):
+                t2, e2 = where[(v, u)]
+                if t < t2:
+                    out.append((t, e, t2, e2))
+        return np.array(out, np.int64)
+
+    def face_fluxes(self, tr, gamma=5.0 / 3.0):
+        """HLL flux integrals over every face from the traces tr[z][Q][32] of
+        the predictor's averages (Section VI): radial faces first,
+        f = t (n_rad + 1) + kf, along +r (boundary faces take the one zone's
+        trace on both sides); then side faces n_radial + e n_rad + k, along the
+        outward normal of edge e's first triangle t.  -> Phi[n_faces][8]"""
+        order, nr = self.order, self.n_rad
+        xi, w, nt, ns = face_points(order)
+        Q = len(w)
+        zones = np.arange(self.nz)
+        xq, dA = self.face_geometry(zones)
+        E = self.edges()
+        nrf = self.ntri * (nr + 1)
+        Phi = np.zeros((nrf + len(E) * nr, 8))
+        # radial faces: the zone below (top face, points 0..nt) or, at the
+        # inner boundary, the zone above (bottom face, points nt..2nt, turned)
+        for t in range(self.ntri):
+            for kf in range(nr + 1):
+                below, above = (t * nr + kf - 1 if kf > 0 else None), (t * nr + kf if kf < nr else None)
+                if below is not None:
+                    qs = np.arange(nt); zl, A = below, dA[below, :nt]
+                else:
+                    qs = np.arange(nt, 2 * nt); zl, A = above, -dA[above, nt:2 * nt]
+                zr = above if above is not None else below
+                qr = np.arange(nt, 2 * nt) if above is not None else np.arange(nt)
+                Phi[t * (nr + 1) + kf] = self._integrate(tr[zl, qs], tr[zr, qr], A, gamma)
+        # side faces: the neighbour's point at the same height, mirrored along the edge
+        xs = xi[2 * nt:2 * nt + ns]
+        sx = xs[:, 0] + 0.5                                     # position along edge 0 (xi from -1/2 to 1/2)
+        mirror = [int(np.argmin(np.abs(sx - (1 - sx[i])) + np.abs(xs[:, 2] - xs[i, 2]))) for i in range(ns)]
+        for e, (t1, e1, t2, e2) in enumerate(E):
+            for k in range(nr):
+                z1, z2 = t1 * nr + k, t2 * nr + k
+                q1 = 2 * nt + e1 * ns + np.arange(ns)
+                q2 = 2 * nt + e2 * ns + np.array(mirror)
+                Phi[nrf + e * nr + k] = self._integrate(tr[z1, q1], tr[z2, q2], dA[z1, q1 - 0], gamma)
+        return Phi
+
+    @staticmethod
+    def _integrate(tl, tr_, A, gamma):
+        a = np.linalg.norm(A, axis=1)
+        n = np.ascontiguousarray(A / a[:, None])
+        Fs = np.zeros((len(a), 8))
+        _lib().rgo_prism_hll(len(a), np.ascontiguousarray(tl[:, :8]), np.ascontiguousarray(tr_[:, :8]),
+                             np.ascontiguousarray(tl[:, 8:]), np.ascontiguousarray(tr_[:, 8:]), n, gamma, Fs)
+        return (a[:, None] * Fs).sum(0)
 
     def predict(self, zones, Ua, dt, gamma=5.0 / 3.0):
         """Element predictor of the given zones from nodal states Ua[z][N][8]:

@@ -339,3 +339,77 @@ def test_square_rule_A2_integrates_bilinear_functions():
     for f, exact in ((lambda a, b: 1 + 0 * a, 1.0), (lambda a, b: a, 0.5), (lambda a, b: b, 0.5),
                      (lambda a, b: a * b, 0.25)):
         assert abs((w * f(x, y)).sum() - exact) < 1e-15
+
+
+# ---------------------------------------------------------------- face fluxes
+def _zone_faces(m):
+    """for every zone its five faces with the sign of the zone's outward normal:
+    [(face, sign)] x 5 per zone"""
+    nr, nrf = m.n_rad, m.ntri * (m.n_rad + 1)
+    faces = [[] for _ in range(m.nz)]
+    for t in range(m.ntri):
+        for k in range(nr):
+            z = t * nr + k
+            faces[z].append((t * (nr + 1) + k + 1, +1))    # top: +r is outward
+            faces[z].append((t * (nr + 1) + k, -1))        # bottom
+    for e, (t1, e1, t2, e2) in enumerate(m.edges()):
+        for k in range(nr):
+            faces[t1 * nr + k].append((nrf + e * nr + k, +1))
+            faces[t2 * nr + k].append((nrf + e * nr + k, -1))
+    return faces
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_face_points_of_neighbours_coincide(order):
+    """The two sides of every face see the same physical points: a radial
+    face's triangle points from the zone below and above, a side face's points
+    from the first triangle and the mirrored points of its neighbour."""
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    xi, w, nt, ns = P.face_points(order)
+    xq, dA = m.face_geometry(np.arange(m.nz))
+    nr = m.n_rad
+    for t in range(m.ntri):
+        np.testing.assert_allclose(xq[t * nr, :nt], xq[t * nr + 1, nt:2 * nt], rtol=0, atol=1e-14)
+    xs = xi[2 * nt:2 * nt + ns]
+    sx = xs[:, 0] + 0.5                                     # position along edge 0 (xi from -1/2 to 1/2)
+    mirror = [int(np.argmin(np.abs(sx - (1 - sx[i])) + np.abs(xs[:, 2] - xs[i, 2]))) for i in range(ns)]
+    for t1, e1, t2, e2 in m.edges():
+        for k in range(nr):
+            a = xq[t1 * nr + k, 2 * nt + e1 * ns + np.arange(ns)]
+            b = xq[t2 * nr + k, 2 * nt + e2 * ns + np.array(mirror)]
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_face_area_vectors_close_each_zone(order):
+    """The rule-weighted outward area vectors of a zone's five faces sum to
+    zero: exactly where the face rules integrate the map's area vectors
+    (orders 2, 3), and at fourth order (cubic map, (A.5) exact to degree 3)
+    with a gap that shrinks with the zones."""
+    gaps = []
+    for level in (1, 2):
+        m = P.OraclePrismMesh(level, 2, r_in=1.0, r_out=1.5, order=order)
+        _, dA = m.face_geometry(np.arange(m.nz))
+        gaps.append(np.abs(dA.sum(1)).max() / np.abs(dA).sum(1).max())
+    if order < 4:
+        assert max(gaps) < 1e-14
+    else:
+        assert gaps[1] < gaps[0] / 8 and gaps[1] < 1e-5, gaps
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_face_fluxes_of_a_uniform_state_cancel(order):
+    """A uniform state's face fluxes are F(U) . A_f, so every zone's net
+    outward flux vanishes where the faces close exactly (free stream of the
+    corrector)."""
+    from oracle import oracle as O
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    U = np.array([1.1, 0.3, -0.2, 0.4, 2.5, 0.2, 0.1, -0.3])
+    F = O.flux(U)
+    Q = len(P.face_points(order)[1])
+    tr = np.zeros((m.nz, Q, 32)); tr[:, :, :8] = U; tr[:, :, 8:] = F.reshape(24)
+    Phi = m.face_fluxes(tr)
+    scale = np.abs(Phi).max()
+    for faces in _zone_faces(m):
+        net = sum(s * Phi[f] for f, s in faces)
+        assert np.abs(net).max() < 1e-13 * scale
