@@ -251,9 +251,24 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     torch.cuda.synchronize()
     ms_tr = e0.elapsed_time(e1) / reps
     tr_bytes = 8.0 * 32 * (lib.N + lib.Q)
+    # HLL face fluxes of every radial and side face from the traces
+    del aF
+    Phi = torch.empty((lib.n_faces, 8), dtype=torch.float64, device="cuda")
+    lib.face_fluxes(tr, Phi=Phi)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        lib.face_fluxes(tr, Phi=Phi)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_ff = e0.elapsed_time(e1) / reps
+    if not torch.isfinite(Phi).all():
+        raise RuntimeError("non-finite prism face fluxes")
+    n_faces = lib.n_faces
+    ff_bytes = 8.0 * (32 * lib.Q * lib.nz + 8 * n_faces)
     flops, nbytes = lib.work()
     nz, lib_q = lib.nz, lib.Q
-    del aU, aF, tr
+    del aU, tr, Phi
     lib.close()
     torch.cuda.empty_cache()
     tf = flops * nz / (ms * 1e-3) / 1e12
@@ -263,6 +278,8 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
             "flops_per_zone": flops, "bytes_per_zone": nbytes,
             "traces": {"ms": ms_tr, "face_points_per_zone": lib_q, "bytes_per_zone": tr_bytes,
                        "hbm_gbs": tr_bytes * nz / (ms_tr * 1e-3) / 1e9},
+            "face_fluxes": {"ms": ms_ff, "faces": n_faces, "face_updates_per_s": n_faces / (ms_ff * 1e-3),
+                            "hbm_gbs": ff_bytes / (ms_ff * 1e-3) / 1e9},
             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
 
@@ -550,7 +567,8 @@ def main():
         log(f"[bench] prism predictor (order 4, icosahedral level 6 x 128 = {prism['zones']} zones): "
             f"{prism['ms_per_predictor']:.2f} ms, {prism['zone_updates_per_s'] / 1e6:.1f} M zone-updates/s, "
             f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak); "
-            f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s)")
+            f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s), "
+            f"face fluxes {prism['face_fluxes']['ms']:.2f} ms ({prism['face_fluxes']['hbm_gbs']:.0f} GB/s)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,

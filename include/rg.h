@@ -415,6 +415,8 @@ typedef struct {
     int32_t n_levels;  /* time levels: order                    */
     int32_t order, level, n_rad;
     int32_t n_face_points;  /* face points per zone: 15, 24, 38      */
+    int64_t n_edges;        /* mesh edges: 30 * 4^level              */
+    int64_t n_faces;        /* n_tri (n_rad + 1) + n_edges n_rad     */
 } rg_prism_info;
 
 /* Builds the mesh and, on the current device, the geometry of every column
@@ -459,6 +461,23 @@ rg_status rg_prism_face_points(const rg_prism *prism, double *xi, double *w, int
  * double[32][n_zones][Q], caller-owned.  Asynchronous on stream.  RG_EINVAL
  * for null pointers or a host-only mesh. */
 rg_status rg_prism_traces(const rg_prism *prism, const double *avgU, const double *avgF, double *tr, void *stream);
+
+/* Mesh edges, edges[n_edges][4] = (t, k, t', k'): triangle t's local edge k
+ * (0: a-b, 1: b-c, 2: c-a) is triangle t''s local edge k', t < t'; listed in
+ * the order met going through the triangles and their local edges.  Host. */
+rg_status rg_prism_edges(const rg_prism *prism, int32_t *edges);
+
+/* The corrector's face fluxes (Sections II.c and VI) on the prism faces:
+ * for every face the integral over its points (rg_prism_face_points) of the
+ * HLL flux of the two sides' traces (tr of rg_prism_traces: time-averaged
+ * state and Cartesian flux), along the face's area vector, weighted by the
+ * rule.  Faces: radial faces f = t (n_rad + 1) + kf at radius r_kf, along +r,
+ * then side faces n_tri (n_rad + 1) + e n_rad + k over edge e in shell k,
+ * along the outward normal of the edge's first triangle t; at r_in and r_out
+ * the one zone's trace is taken on both sides.  Phi double[n_faces][8],
+ * device, caller-owned.  Asynchronous on stream.  RG_EINVAL for null
+ * pointers, gamma <= 1 or a host-only mesh. */
+rg_status rg_prism_face_fluxes(const rg_prism *prism, double gamma, const double *tr, double *Phi, void *stream);
 
 /* Algorithmic work of rg_prism_predict per zone with n_picard sweeps:
  * floating-point operations (mapped fluxes 149 per node, the sparse

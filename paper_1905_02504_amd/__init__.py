@@ -262,6 +262,7 @@ class PrismMesh:
         info = N.rg_prism_get_info(self._h)
         self.nz, self.ntri, self.N = info["n_zones"], info["n_tri"], info["n_nodes"]
         self.Q = info["n_face_points"]
+        self.n_edges, self.n_faces = info["n_edges"], info["n_faces"]
         self.level, self.n_rad, self.order = level, n_rad, order
 
     def close(self):
@@ -300,6 +301,21 @@ class PrismMesh:
             tr = torch.empty((32, self.nz, self.Q), dtype=torch.float64, device=aU.device)
         N.rg_prism_traces(self._h, _ptr(aU), _ptr(aF), _ptr(tr), _stream())
         return tr
+
+    def edges(self):
+        """[n_edges][4]: (t, local edge, t', local edge'), t < t'"""
+        e = np.zeros((self.n_edges, 4), np.int32)
+        N.rg_prism_edges(self._h, _ptr(e))
+        return e
+
+    def face_fluxes(self, tr, gamma=5.0 / 3.0, Phi=None):
+        """HLL flux integrals [n_faces][8] of every face from traces() (CUDA tensors)"""
+        import torch
+        assert tr.is_contiguous()
+        if Phi is None:
+            Phi = torch.empty((self.n_faces, 8), dtype=torch.float64, device=tr.device)
+        N.rg_prism_face_fluxes(self._h, gamma, _ptr(tr), _ptr(Phi), _stream())
+        return Phi
 
     def work(self, n_picard=None):
         """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""

@@ -40,7 +40,8 @@ class rg_diag_out(C.Structure):
 
 class rg_prism_info(C.Structure):
     _fields_ = [("n_zones", C.c_int64), ("n_tri", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
-                ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32), ("n_face_points", C.c_int32)]
+                ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32), ("n_face_points", C.c_int32),
+                ("n_edges", C.c_int64), ("n_faces", C.c_int64)]
 
 
 class RGError(RuntimeError):
@@ -110,8 +111,10 @@ def lib():
         L.rg_prism_work.argtypes = [_vp, C.c_int32, _dp, _dp]
         L.rg_prism_face_points.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.rg_prism_traces.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.rg_prism_edges.argtypes = [_vp, _vp]
+        L.rg_prism_face_fluxes.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
         for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work",
-                     "rg_prism_face_points", "rg_prism_traces", "rg_prism_triangles", "rg_prism_geometry",
+                     "rg_prism_face_points", "rg_prism_traces", "rg_prism_edges", "rg_prism_face_fluxes", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -342,3 +345,11 @@ def rg_prism_face_points(prism, xi_ptr, w_ptr):
 
 def rg_prism_traces(prism, aU_ptr, aF_ptr, tr_ptr, stream):
     check(lib().rg_prism_traces(prism, _vp(aU_ptr), _vp(aF_ptr), _vp(tr_ptr), _vp(stream)), "rg_prism_traces")
+
+
+def rg_prism_edges(prism, edges_ptr):
+    check(lib().rg_prism_edges(prism, _vp(edges_ptr)), "rg_prism_edges")
+
+
+def rg_prism_face_fluxes(prism, gamma, tr_ptr, Phi_ptr, stream):
+    check(lib().rg_prism_face_fluxes(prism, gamma, _vp(tr_ptr), _vp(Phi_ptr), _vp(stream)), "rg_prism_face_fluxes")

@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 
@@ -61,6 +62,8 @@ struct rg_prism {
     std::vector<double> tri;       // ntri x 9: vertices a, b, c of each triangle
     std::vector<double> radius;    // n_rad + 1
     std::vector<double> hx, hJ, hM;  // unit-shell nodes ntri x N x 3, J ntri x N, metrics ntri x 9 x N
+    std::vector<int> edges, mirror;   // nedges x 4; QS
+    std::vector<double> tfA, sfA;     // ntri x QT x 3; ntri x 3 x QS x 3
     std::vector<void *> allocations;
     bool device = false;
     DevPrism dev{};
@@ -217,6 +220,129 @@ void column_geometry(const PrismRef &r, const double *abc, double q, double *x, 
     }
 }
 
+// Face geometry of one column for the unit shell: the triangle-face area
+// vectors at radius 1, (sqrt 3 / 4) w_q (S_xi x S_eta), which point along +r
+// for a counter-clockwise triangle, and the side faces' outward area vectors
+// w_q R(zeta) (q - 1) (S_s x S) with s along the edge from vertex k to k + 1;
+// S is the triangle's sphere interpolant (reading of the map as in
+// column_geometry).
+void column_face_geometry(const PrismRef &r, const double *abc, double q, double *tfA, double *sfA)
+{
+    const int mo = r.order - 1;
+    std::vector<std::array<int, 3>> bary;
+    std::vector<std::array<double, 3>> lx;
+    lattice(mo, bary, lx);
+    const int nl = (int)lx.size();
+    std::vector<double> sp((size_t)nl * 3);
+    const double *P[3] = {abc, abc + 3, abc + 6};
+    for (int a = 0; a < nl; a++) {
+        double *o = &sp[3 * a];
+        const auto &bc = bary[a];
+        const int nz = (bc[0] == 0) + (bc[1] == 0) + (bc[2] == 0);
+        if (nz == 2) {
+            std::memcpy(o, P[bc[0] ? 0 : bc[1] ? 1 : 2], 24);
+        } else if (nz == 1) {
+            const int u = bc[0] ? 0 : 1, w = bc[2] ? 2 : 1;
+            arc_point(P[u], P[w], double(bc[w]) / (bc[u] + bc[w]), o);
+        } else {
+            for (int i = 0; i < 3; i++) o[i] = P[0][i] + P[1][i] + P[2][i];
+            unit(o);
+        }
+    }
+    std::vector<std::array<int, 3>> tmo;
+    for (int deg = 0; deg <= mo; deg++)
+        for (int a = deg; a >= 0; a--) tmo.push_back({a, deg - a, 0});
+    std::vector<double> C;
+    lagrange_coefficients(lx, tmo, C);
+    // S and its (xi, eta) derivatives at a reference point
+    auto surf = [&](const double *xi, double *S, double *Sx, double *Sy) {
+        for (int k = 0; k < 3; k++) S[k] = Sx[k] = Sy[k] = 0.0;
+        for (int b = 0; b < nl; b++) {
+            double L = 0.0, Lx = 0.0, Ly = 0.0;
+            for (int m = 0; m < nl; m++) {
+                const double c = C[(size_t)m * nl + b];
+                if (c == 0.0) continue;
+                const int ex = tmo[m][0], ey = tmo[m][1];
+                double px = 1.0, py = 1.0;
+                for (int i = 0; i < ex; i++) px *= xi[0];
+                for (int i = 0; i < ey; i++) py *= xi[1];
+                L += c * px * py;
+                if (ex > 0) { double d = ex; for (int i = 0; i < ex - 1; i++) d *= xi[0]; Lx += c * d * py; }
+                if (ey > 0) { double d = ey; for (int i = 0; i < ey - 1; i++) d *= xi[1]; Ly += c * px * d; }
+            }
+            for (int k = 0; k < 3; k++) {
+                S[k] += L * sp[3 * b + k];
+                Sx[k] += Lx * sp[3 * b + k];
+                Sy[k] += Ly * sp[3 * b + k];
+            }
+        }
+    };
+    auto cross = [](const double *a, const double *b, double *c) {
+        c[0] = a[1] * b[2] - a[2] * b[1];
+        c[1] = a[2] * b[0] - a[0] * b[2];
+        c[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    const double tri_area = std::sqrt(3.0) / 4.0;
+    for (int i = 0; i < r.QT; i++) {
+        double S[3], Sx[3], Sy[3], c[3];
+        surf(r.fpt[i].data(), S, Sx, Sy);
+        cross(Sx, Sy, c);
+        for (int k = 0; k < 3; k++) tfA[3 * i + k] = tri_area * r.fw[i] * c[k];
+    }
+    double V[3][2];
+    for (int k = 0; k < 3; k++) {
+        V[k][0] = k == 0 ? -0.5 : k == 1 ? 0.5 : 0.0;
+        V[k][1] = k == 2 ? 1.0 / std::sqrt(3.0) : -0.5 / std::sqrt(3.0);
+    }
+    for (int e = 0; e < 3; e++)
+        for (int i = 0; i < r.QS; i++) {
+            const int qi = 2 * r.QT + e * r.QS + i;
+            const double *xi = r.fpt[qi].data();
+            double S[3], Sx[3], Sy[3], Ss[3], c[3];
+            surf(xi, S, Sx, Sy);
+            const double ex = V[(e + 1) % 3][0] - V[e][0], ey = V[(e + 1) % 3][1] - V[e][1];
+            for (int k = 0; k < 3; k++) Ss[k] = ex * Sx[k] + ey * Sy[k];
+            cross(Ss, S, c);
+            const double R = (0.5 - xi[2]) + (0.5 + xi[2]) * q;
+            for (int k = 0; k < 3; k++) sfA[(e * r.QS + i) * 3 + k] = r.fw[qi] * R * (q - 1.0) * c[k];
+        }
+}
+
+// mesh edges in first-encounter order over (triangle, local edge a-b, b-c,
+// c-a), kept where the triangle precedes its neighbour; endpoints are
+// compared bit for bit (shared vertices come out of the same sums)
+bool mesh_edges(const std::vector<double> &tri, std::vector<int> &edges)
+{
+    const int64_t nt = (int64_t)(tri.size() / 9);
+    struct Key {
+        double v[6];
+        bool operator<(const Key &o) const { return std::memcmp(v, o.v, sizeof(v)) < 0; }
+    };
+    std::map<Key, std::pair<int, int>> where;
+    auto key = [&](int64_t t, int e, bool rev) {
+        Key k;
+        const double *a = &tri[9 * t + 3 * e], *b = &tri[9 * t + 3 * ((e + 1) % 3)];
+        std::memcpy(k.v, rev ? b : a, 24);
+        std::memcpy(k.v + 3, rev ? a : b, 24);
+        return k;
+    };
+    for (int64_t t = 0; t < nt; t++)
+        for (int e = 0; e < 3; e++) where[key(t, e, false)] = {(int)t, e};
+    edges.clear();
+    for (int64_t t = 0; t < nt; t++)
+        for (int e = 0; e < 3; e++) {
+            auto it = where.find(key(t, e, true));
+            if (it == where.end()) return false;
+            if (t < it->second.first) {
+                edges.push_back((int)t);
+                edges.push_back(e);
+                edges.push_back(it->second.first);
+                edges.push_back(it->second.second);
+            }
+        }
+    return (int64_t)edges.size() / 4 == 3 * nt / 2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -252,6 +378,25 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
                         &p->hM[(size_t)t * 9 * N]);
     for (int64_t t = 0; t < p->ntri * N; t++)
         if (!(p->hJ[t] > 0.0)) { set_error("non-positive Jacobian"); free_prism(p); return RG_ESINGULAR; }
+    const int QT = p->ref.QT, QS = p->ref.QS;
+    p->tfA.assign((size_t)p->ntri * QT * 3, 0.0);
+    p->sfA.assign((size_t)p->ntri * 3 * QS * 3, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < p->ntri; t++)
+        column_face_geometry(p->ref, &p->tri[9 * t], p->q, &p->tfA[(size_t)t * QT * 3], &p->sfA[(size_t)t * 3 * QS * 3]);
+    if (!mesh_edges(p->tri, p->edges)) { set_error("the triangles do not close into a sphere"); free_prism(p); return RG_ESINGULAR; }
+    // side point at the same height, mirrored along the edge (the neighbour
+    // runs the shared edge the other way)
+    p->mirror.assign(QS, -1);
+    for (int i = 0; i < QS; i++) {
+        const auto &a = p->ref.fpt[2 * QT + i];
+        for (int j = 0; j < QS; j++) {
+            const auto &b = p->ref.fpt[2 * QT + j];
+            // on edge 0 (eta fixed), mirroring along the edge maps xi to -xi
+            if (std::fabs(b[0] + a[0]) < 1e-12 && std::fabs(b[2] - a[2]) < 1e-12) p->mirror[i] = j;
+        }
+        if (p->mirror[i] < 0) { set_error("side-face rule is not symmetric along the edge"); free_prism(p); return RG_ESINGULAR; }
+    }
     p->device = device;
     if (!device) { *out = p; return RG_OK; }
     std::vector<double> rinv(n_rad);
@@ -259,9 +404,14 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     DevPrism &G = p->dev;
     G.order = order; G.N = N; G.n_rad = n_rad; G.ntri = p->ntri; G.nz = p->nz;
     G.Q = p->ref.Q;
+    G.QT = QT;
+    G.QS = QS;
+    G.nedges = (int64_t)p->edges.size() / 4;
+    G.nfaces = p->ntri * (n_rad + 1) + G.nedges * n_rad;
     if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
         !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt) || !upload(p, p->ref.fidx, &G.fidx) ||
-        !upload(p, p->ref.fval, &G.fval)) {
+        !upload(p, p->ref.fval, &G.fval) || !upload(p, p->edges, &G.edges) || !upload(p, p->mirror, &G.mirror) ||
+        !upload(p, p->tfA, &G.tfA) || !upload(p, p->sfA, &G.sfA) || !upload(p, p->radius, &G.radius)) {
         set_error("device allocation or upload of the prism geometry failed");
         free_prism(p);
         return RG_ENOMEM;
@@ -293,7 +443,24 @@ rg_status rg_prism_get_info(const rg_prism *p, rg_prism_info *info)
     info->level = p->level;
     info->n_rad = p->n_rad;
     info->n_face_points = p->ref.Q;
+    info->n_edges = (int64_t)p->edges.size() / 4;
+    info->n_faces = p->ntri * (p->n_rad + 1) + info->n_edges * p->n_rad;
     return RG_OK;
+}
+
+rg_status rg_prism_edges(const rg_prism *p, int32_t *edges)
+{
+    if (!p || !edges) { set_error("null argument"); return RG_EINVAL; }
+    std::memcpy(edges, p->edges.data(), p->edges.size() * sizeof(int));
+    return RG_OK;
+}
+
+rg_status rg_prism_face_fluxes(const rg_prism *p, double gamma, const double *tr, double *Phi, void *stream)
+{
+    if (!p || !tr || !Phi) { set_error("null argument"); return RG_EINVAL; }
+    if (!(gamma > 1.0)) { set_error("need gamma > 1"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    return launch_prism_face_flux(p->dev, gamma, tr, Phi, stream);
 }
 
 rg_status rg_prism_face_points(const rg_prism *p, double *xi, double *w, int32_t *n_tri_points, int32_t *n_side_points)

@@ -349,6 +349,103 @@ rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double 
     }
 }
 
+// Face fluxes: lane (face, point) reads both sides' traces at its point
+// (for one value, the lanes of a face and of neighbouring faces read adjacent
+// doubles), forms the normal fluxes along the point's area vector and the HLL
+// flux times |dA|; the face's points are then summed through LDS.  Radial
+// faces (NPT = triangle points) take the zone below (top face) and above
+// (bottom face) at the same (xi, eta); side faces (NPT = side points) pair
+// point i of the first triangle with the mirrored point of its neighbour,
+// which runs the edge the other way.  One launch per kind of face.
+template <int NPT, bool SIDE>
+__global__ __launch_bounds__(256) void prism_face_flux(DevPrism G, double gam, const double *__restrict__ tr,
+                                                       double *__restrict__ Phi)
+{
+    constexpr int FPB = 256 / NPT;
+    __shared__ double s_acc[256 * 8];   // every lane writes its slot, active or not
+    const int tid = threadIdx.x, fl = tid / NPT, i = tid - fl * NPT;
+    const int nr = G.n_rad, Q = G.Q, QT = G.QT;
+    const i64 nrf = G.ntri * (nr + 1), ZQ = G.nz * (i64)Q;
+    const i64 nf = SIDE ? G.nedges * nr : nrf;
+    const i64 f = (i64)xcd_block(blockIdx.x, gridDim.x) * FPB + fl;
+    const bool active = fl < FPB && f < nf;
+    double Fs[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) Fs[v] = 0.0;
+    if (active) {
+        i64 pl, pr;
+        const double *A;
+        double scale;
+        if (!SIDE) {
+            const i64 t = f / (nr + 1);
+            const int kf = (int)(f - t * (nr + 1));
+            const i64 zl = t * nr + (kf > 0 ? kf - 1 : 0), zr = t * nr + (kf < nr ? kf : nr - 1);
+            pl = zl * Q + (kf > 0 ? 0 : QT) + i;        // top face of the zone below, else the bottom face
+            pr = zr * Q + (kf < nr ? QT : 0) + i;       // bottom face of the zone above, else the top face
+            scale = G.radius[kf] * G.radius[kf];
+            A = G.tfA + (t * NPT + i) * 3;
+        } else {
+            const i64 e = f / nr;
+            const int k = (int)(f - e * nr);
+            const int t1 = G.edges[4 * e], e1 = G.edges[4 * e + 1], t2 = G.edges[4 * e + 2], e2 = G.edges[4 * e + 3];
+            pl = ((i64)t1 * nr + k) * Q + 2 * QT + e1 * NPT + i;
+            pr = ((i64)t2 * nr + k) * Q + 2 * QT + e2 * NPT + G.mirror[i];
+            scale = G.radius[k] * G.radius[k];
+            A = G.sfA + (((i64)t1 * 3 + e1) * NPT + i) * 3;
+        }
+        double n[3] = {scale * A[0], scale * A[1], scale * A[2]};
+        const double a = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]), ia = 1.0 / a;
+        n[0] *= ia; n[1] *= ia; n[2] *= ia;
+        double UL[8], UR[8], FL[8], FR[8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            UL[v] = tr[v * ZQ + pl];
+            UR[v] = tr[v * ZQ + pr];
+            FL[v] = n[0] * tr[(8 + v) * ZQ + pl] + n[1] * tr[(16 + v) * ZQ + pl] + n[2] * tr[(24 + v) * ZQ + pl];
+            FR[v] = n[0] * tr[(8 + v) * ZQ + pr] + n[1] * tr[(16 + v) * ZQ + pr] + n[2] * tr[(24 + v) * ZQ + pr];
+        }
+        dev_hll<double>(UL, UR, FL, FR, n, gam, Fs);
+#pragma unroll
+        for (int v = 0; v < 8; v++) Fs[v] *= a;
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) s_acc[tid * 8 + v] = Fs[v];
+    __syncthreads();
+    if (active && i == 0) {
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            double sum = 0.0;
+#pragma unroll
+            for (int j = 0; j < NPT; j++) sum += s_acc[(tid + j) * 8 + v];
+            Phi[((SIDE ? nrf : 0) + f) * 8 + v] = sum;
+        }
+    }
+}
+
+template <int QT, int QS>
+static rg_status launch_fluxes(const DevPrism &G, double gamma, const double *tr, double *Phi, hipStream_t st)
+{
+    if (G.QT != QT || G.QS != QS) { set_error("face point counts differ from the kernel's"); return RG_EINVAL; }
+    const i64 nrf = G.ntri * (G.n_rad + 1), nsf = G.nedges * G.n_rad;
+    const i64 br = (nrf + 256 / QT - 1) / (256 / QT), bs = (nsf + 256 / QS - 1) / (256 / QS);
+    if (br >= ((i64)1 << 31) || bs >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (br > 0) prism_face_flux<QT, false><<<(unsigned)br, 256, 0, st>>>(G, gamma, tr, Phi);
+    if (bs > 0) prism_face_flux<QS, true><<<(unsigned)bs, 256, 0, st>>>(G, gamma, tr, Phi);
+    if (hipGetLastError() != hipSuccess) { set_error("prism face flux launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
+rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *tr, double *Phi, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (G.order) {
+    case 2: return launch_fluxes<3, 3>(G, gamma, tr, Phi, st);
+    case 3: return launch_fluxes<6, 4>(G, gamma, tr, Phi, st);
+    case 4: return launch_fluxes<10, 6>(G, gamma, tr, Phi, st);
+    default: set_error("prism order must be 2, 3 or 4"); return RG_ENOTSUP;
+    }
+}
+
 template <int P>
 static rg_status launch_order(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                               double *aF, hipStream_t st)

@@ -59,9 +59,18 @@ struct DevPrism {
     int Q;                // face points per zone
     const int *fidx;      // Q x TRACE_TERMS
     const double *fval;   // Q x TRACE_TERMS
+    // face fluxes
+    int QT, QS;           // points per triangle face, per side face
+    int64_t nedges, nfaces;
+    const int *edges;     // nedges x 4: t, local edge, t', local edge' (t < t')
+    const int *mirror;    // QS: the side point at the same height, mirrored along the edge
+    const double *tfA;    // ntri x QT x 3: weighted area vectors of the triangle faces at radius 1 (+r)
+    const double *sfA;    // ntri x 3 x QS x 3: weighted outward area vectors of the side faces, unit shell
+    const double *radius; // n_rad + 1
 };
 
 rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream);
+rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *tr, double *Phi, void *stream);
 rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                                double *aF, void *stream);
 

@@ -97,6 +97,27 @@ def test_prism_traces_match_oracle(order):
     assert e.max() < TOL
 
 
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_face_fluxes_match_oracle(order):
+    """HLL face-flux integrals (rg_prism_face_fluxes) over every radial and
+    side face of level 1 x 3 shells, from the library's own predictor and
+    traces, against the oracle's chain on the same inputs."""
+    import paper_1905_02504_amd as R
+    print(f"[prism] face fluxes, order {order}, level 1 x 3 shells", flush=True)
+    lib = R.PrismMesh(1, 3, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.5, order=order)
+    x, J, met = om.geometry(np.arange(om.nz))
+    Ua = smooth_state(x, np.random.default_rng(31 + order))
+    aU_o, aF_o = P.predict(order, J, met, Ua, 0.02, GAMMA)
+    Phi_o = om.face_fluxes(P.traces(order, aU_o, aF_o), GAMMA)
+    aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), 0.02, GAMMA)
+    Phi = lib.face_fluxes(lib.traces(aU, aF), GAMMA).cpu().numpy()
+    assert Phi.shape == Phi_o.shape == (lib.n_faces, 8)
+    e = rel_by_var(Phi, Phi_o, 1)
+    print(f"[prism] face fluxes ({lib.n_faces} faces): max rel error per variable {e.max():.2e}", flush=True)
+    assert e.max() < TOL
+
+
 def test_prism_predictor_without_sweeps_returns_the_initial_state():
     """n_picard = 0 keeps every level at the initial state: the averages are
     the state itself and its physical flux (the Gauss weights sum to one)."""
@@ -177,3 +198,5 @@ def test_prism_predictor_argument_errors():
         N.rg_prism_predict(lib._h, 5 / 3, 0.1, 3, 0, U.data_ptr(), U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_traces(lib._h, U.data_ptr(), 0, U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_face_fluxes(lib._h, 1.0, U.data_ptr(), U.data_ptr(), 0)

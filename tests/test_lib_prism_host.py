@@ -43,3 +43,12 @@ def test_prism_counts_and_errors():
         N.rg_prism_predict(m._h, 5 / 3, 0.01, 4, 8, 8, 8, 0)
     with pytest.raises(N.RGError, match="outside the mesh"):
         m.geometry(39, 2)
+
+
+def test_prism_edges_and_face_counts_match_oracle():
+    import paper_1905_02504_amd as R
+    for level in (0, 1, 2):
+        m = R.PrismMesh(level, 3, 3, device=False)
+        om = P.OraclePrismMesh(level, 3, order=3)
+        assert np.array_equal(m.edges(), om.edges())
+        assert m.n_edges == 30 * 4 ** level and m.n_faces == m.ntri * 4 + m.n_edges * 3
