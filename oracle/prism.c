@@ -515,3 +515,32 @@ void rgo_prism_hll(int np, const double *UL, const double *UR, const double *FL,
         hll_flux(&UL[p * NVAR], &UR[p * NVAR], FnL, FnR, nn, gamma, &Fs[p * NVAR]);
     }
 }
+
+/* zone volumes by a collapsed Gauss rule on the triangle times Gauss points
+ * in zeta (six each way), exact for the maps' Jacobians */
+int rgo_prism_volumes(int order, int nz, const double *abc, const double *r01, double *vol)
+{
+    const int ng = 6;
+    double gx[8], gw[8], v1[2], v2[2], v3[2];
+    gauss01(ng, gx, gw);
+    tri_vertex(0, v1);
+    tri_vertex(1, v2);
+    tri_vertex(2, v3);
+    for (int z = 0; z < nz; z++) {
+        tri_map t;
+        if (tri_map_init(&t, order - 1, &abc[9 * z], &abc[9 * z + 3], &abc[9 * z + 6])) return -1;
+        double V = 0.0;
+        for (int i = 0; i < ng; i++)
+            for (int j = 0; j < ng; j++)
+                for (int k = 0; k < ng; k++) {
+                    double s = gx[i], tt = (1.0 - s) * gx[j], xi[3], x[3], jac[9];
+                    xi[0] = v1[0] + s * (v2[0] - v1[0]) + tt * (v3[0] - v1[0]);
+                    xi[1] = v1[1] + s * (v2[1] - v1[1]) + tt * (v3[1] - v1[1]);
+                    xi[2] = gx[k] - 0.5;
+                    prism_map(&t, r01[2 * z], r01[2 * z + 1], xi, x, jac);
+                    V += 2.0 * (S3 / 4.0) * (1.0 - s) * gw[i] * gw[j] * gw[k] * det3(jac);
+                }
+        vol[z] = V;
+    }
+    return 0;
+}

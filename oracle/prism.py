@@ -50,6 +50,8 @@ def _lib():
         L.rgo_prism_face_geometry.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L.rgo_prism_hll.restype = None
         L.rgo_prism_hll.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
+        L.rgo_prism_volumes.restype = C.c_int
+        L.rgo_prism_volumes.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
         L._prism_ready = True
     return L
 
@@ -222,6 +224,43 @@ class OraclePrismMesh:
         _lib().rgo_prism_hll(len(a), np.ascontiguousarray(tl[:, :8]), np.ascontiguousarray(tr_[:, :8]),
                              np.ascontiguousarray(tl[:, 8:]), np.ascontiguousarray(tr_[:, 8:]), n, gamma, Fs)
         return (a[:, None] * Fs).sum(0)
+
+    def volumes(self, zones):
+        t, k = self.zone_tri_shell(zones)
+        nz = len(t)
+        abc = np.ascontiguousarray(self.vert[self.tri[t]].reshape(nz, 9))
+        r01 = np.ascontiguousarray(np.stack([self.radius[k], self.radius[k + 1]], 1))
+        vol = np.zeros(nz)
+        if _lib().rgo_prism_volumes(self.order, nz, abc, r01, vol):
+            raise ValueError("prism volumes failed")
+        return vol
+
+    def zone_faces(self):
+        """for every zone its five faces with the sign of the zone's outward
+        normal relative to the face's direction: [nz][5] faces, [nz][5] signs"""
+        nr, nrf = self.n_rad, self.ntri * (self.n_rad + 1)
+        F = np.zeros((self.nz, 5), np.int64); S = np.zeros((self.nz, 5))
+        cnt = np.zeros(self.nz, np.int64)
+        def put(z, f, s):
+            F[z, cnt[z]] = f; S[z, cnt[z]] = s; cnt[z] += 1
+        for t in range(self.ntri):
+            for k in range(nr):
+                put(t * nr + k, t * (nr + 1) + k + 1, 1.0)
+                put(t * nr + k, t * (nr + 1) + k, -1.0)
+        for e, (t1, e1, t2, e2) in enumerate(self.edges()):
+            for k in range(nr):
+                put(t1 * nr + k, nrf + e * nr + k, 1.0)
+                put(t2 * nr + k, nrf + e * nr + k, -1.0)
+        assert np.all(cnt == 5)
+        return F, S
+
+    def update(self, U, Phi, dt):
+        """finite-volume update of the zone averages U[nz][8] (Section VI):
+        U - dt / V sum over the zone's faces of the outward face flux"""
+        F, S = self.zone_faces()
+        vol = self.volumes(np.arange(self.nz))
+        net = (S[:, :, None] * Phi[F]).sum(1)
+        return U - dt / vol[:, None] * net
 
     def predict(self, zones, Ua, dt, gamma=5.0 / 3.0):
         """Element predictor of the given zones from nodal states Ua[z][N][8]:

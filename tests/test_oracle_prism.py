@@ -413,3 +413,39 @@ def test_face_fluxes_of_a_uniform_state_cancel(order):
     for faces in _zone_faces(m):
         net = sum(s * Phi[f] for f, s in faces)
         assert np.abs(net).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_volumes_fill_the_shell(order):
+    """The zones' volumes sum to the volume the maps enclose, which approaches
+    (4 pi / 3)(r_out^3 - r_in^3) at the rate of the map (flat facets at order 2,
+    Section II.b's sphericity at orders 3 and 4); zones of one column scale as
+    r_k^3 and a uniform state is left unchanged by the update."""
+    exact = 4 * np.pi / 3 * (1.5 ** 3 - 1.0)
+    errs = []
+    for level in (1, 2):
+        m = P.OraclePrismMesh(level, 3, r_in=1.0, r_out=1.5, order=order)
+        vol = m.volumes(np.arange(m.nz))
+        errs.append(abs(vol.sum() - exact) / exact)
+        q = (1.5) ** (1 / 3)
+        np.testing.assert_allclose(vol[1::3] / vol[0::3], q ** 3, rtol=1e-13)
+    # flat facets: h^2; the quadratic and cubic maps: h^4 (measured 15-16 per halving)
+    rate = {2: 3.5, 3: 12.0, 4: 12.0}[order]
+    assert errs[0] / errs[1] > rate and errs[1] < {2: 5e-2, 3: 2e-4, 4: 1e-5}[order], errs
+
+
+def test_prism_update_conserves_up_to_boundary_fluxes():
+    """With any face fluxes, sum_z V_z (U1 - U) = -dt (outer minus inner
+    boundary fluxes): interior faces cancel in pairs (Section VI)."""
+    m = P.OraclePrismMesh(1, 3, order=3)
+    rng = np.random.default_rng(2)
+    nf = m.ntri * (m.n_rad + 1) + len(m.edges()) * m.n_rad
+    Phi = rng.normal(size=(nf, 8))
+    U = rng.normal(size=(m.nz, 8))
+    dt = 0.01
+    U1 = m.update(U, Phi, dt)
+    vol = m.volumes(np.arange(m.nz))
+    nr = m.n_rad
+    outer = Phi[[t * (nr + 1) + nr for t in range(m.ntri)]].sum(0)
+    inner = Phi[[t * (nr + 1) for t in range(m.ntri)]].sum(0)
+    np.testing.assert_allclose((vol[:, None] * (U1 - U)).sum(0), -dt * (outer - inner), rtol=0, atol=1e-13)
