@@ -266,6 +266,20 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
         raise RuntimeError("non-finite prism face fluxes")
     n_faces = lib.n_faces
     ff_bytes = 8.0 * (32 * lib.Q * lib.nz + 8 * n_faces)
+    # finite-volume update of the zone averages from the face fluxes
+    U = base[:, None] * (1 + 0.05 * (2 * torch.rand((8, lib.nz), generator=gen, device="cuda",
+                                                     dtype=torch.float64) - 1))
+    U1 = torch.empty_like(U)
+    lib.update(U, Phi, 2e-3, U1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        lib.update(U, Phi, 2e-3, U1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_up = e0.elapsed_time(e1) / reps
+    up_bytes = 8.0 * (16 * lib.nz + 5 * 8 * lib.nz)
+    del U, U1
     flops, nbytes = lib.work()
     nz, lib_q = lib.nz, lib.Q
     del aU, tr, Phi
@@ -280,6 +294,7 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
                        "hbm_gbs": tr_bytes * nz / (ms_tr * 1e-3) / 1e9},
             "face_fluxes": {"ms": ms_ff, "faces": n_faces, "face_updates_per_s": n_faces / (ms_ff * 1e-3),
                             "hbm_gbs": ff_bytes / (ms_ff * 1e-3) / 1e9},
+            "update": {"ms": ms_up, "hbm_gbs": up_bytes / (ms_up * 1e-3) / 1e9},
             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
 
@@ -568,7 +583,8 @@ def main():
             f"{prism['ms_per_predictor']:.2f} ms, {prism['zone_updates_per_s'] / 1e6:.1f} M zone-updates/s, "
             f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak); "
             f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s), "
-            f"face fluxes {prism['face_fluxes']['ms']:.2f} ms ({prism['face_fluxes']['hbm_gbs']:.0f} GB/s)")
+            f"face fluxes {prism['face_fluxes']['ms']:.2f} ms ({prism['face_fluxes']['hbm_gbs']:.0f} GB/s), "
+            f"update {prism['update']['ms']:.2f} ms")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,

@@ -479,6 +479,21 @@ rg_status rg_prism_edges(const rg_prism *prism, int32_t *edges);
  * pointers, gamma <= 1 or a host-only mesh. */
 rg_status rg_prism_face_fluxes(const rg_prism *prism, double gamma, const double *tr, double *Phi, void *stream);
 
+/* Host copies of the volumes of zones [z0, z0 + nz) (the map's Jacobian
+ * integrated by cubature).  RG_EINVAL outside the mesh. */
+rg_status rg_prism_volumes(const rg_prism *prism, int64_t z0, int64_t nz, double *vol);
+
+/* Finite-volume update of the zone averages (Section VI): Uo = U - dt / V_z
+ * times the sum over the zone's five faces of the face flux (Phi of
+ * rg_prism_face_fluxes) taken along the zone's outward normal, for all eight
+ * variables.  (The scheme replaces the B averages by those of its
+ * divergence-free reconstruction after constrained transport, which is not
+ * built for prisms.)  U, Uo double[8][n_zones], device, caller-owned, may
+ * alias.  Asynchronous on stream.  RG_EINVAL for null pointers, dt < 0 or a
+ * host-only mesh. */
+rg_status rg_prism_update(const rg_prism *prism, double dt, const double *U, const double *Phi, double *Uo,
+                          void *stream);
+
 /* Algorithmic work of rg_prism_predict per zone with n_picard sweeps:
  * floating-point operations (mapped fluxes 149 per node, the sparse
  * derivative products, the level updates and the time averages) and HBM

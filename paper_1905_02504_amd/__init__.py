@@ -317,6 +317,21 @@ class PrismMesh:
         N.rg_prism_face_fluxes(self._h, gamma, _ptr(tr), _ptr(Phi), _stream())
         return Phi
 
+    def volumes(self, z0=0, nz=None):
+        nz = self.nz - z0 if nz is None else nz
+        vol = np.zeros(nz)
+        N.rg_prism_volumes(self._h, z0, nz, _ptr(vol))
+        return vol
+
+    def update(self, U, Phi, dt, Uo=None):
+        """finite-volume update of the zone averages U [8][nz] (CUDA tensors)"""
+        import torch
+        assert U.is_contiguous() and Phi.is_contiguous() and tuple(U.shape) == (8, self.nz)
+        if Uo is None:
+            Uo = torch.empty_like(U)
+        N.rg_prism_update(self._h, dt, _ptr(U), _ptr(Phi), _ptr(Uo), _stream())
+        return Uo
+
     def work(self, n_picard=None):
         """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""
         return N.rg_prism_work(self._h, self.order if n_picard is None else n_picard)

@@ -113,8 +113,11 @@ def lib():
         L.rg_prism_traces.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.rg_prism_edges.argtypes = [_vp, _vp]
         L.rg_prism_face_fluxes.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
+        L.rg_prism_volumes.argtypes = [_vp, C.c_int64, C.c_int64, _vp]
+        L.rg_prism_update.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp]
         for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work",
-                     "rg_prism_face_points", "rg_prism_traces", "rg_prism_edges", "rg_prism_face_fluxes", "rg_prism_triangles", "rg_prism_geometry",
+                     "rg_prism_face_points", "rg_prism_traces", "rg_prism_edges", "rg_prism_face_fluxes",
+                     "rg_prism_volumes", "rg_prism_update", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -353,3 +356,11 @@ def rg_prism_edges(prism, edges_ptr):
 
 def rg_prism_face_fluxes(prism, gamma, tr_ptr, Phi_ptr, stream):
     check(lib().rg_prism_face_fluxes(prism, gamma, _vp(tr_ptr), _vp(Phi_ptr), _vp(stream)), "rg_prism_face_fluxes")
+
+
+def rg_prism_volumes(prism, z0, nz, vol_ptr):
+    check(lib().rg_prism_volumes(prism, z0, nz, _vp(vol_ptr)), "rg_prism_volumes")
+
+
+def rg_prism_update(prism, dt, U_ptr, Phi_ptr, Uo_ptr, stream):
+    check(lib().rg_prism_update(prism, dt, _vp(U_ptr), _vp(Phi_ptr), _vp(Uo_ptr), _vp(stream)), "rg_prism_update")

@@ -63,6 +63,8 @@ struct rg_prism {
     std::vector<double> radius;    // n_rad + 1
     std::vector<double> hx, hJ, hM;  // unit-shell nodes ntri x N x 3, J ntri x N, metrics ntri x 9 x N
     std::vector<int> edges, mirror;   // nedges x 4; QS
+    std::vector<int> tedge;           // ntri x 3
+    std::vector<double> vol;          // ntri, unit shell
     std::vector<double> tfA, sfA;     // ntri x QT x 3; ntri x 3 x QS x 3
     std::vector<void *> allocations;
     bool device = false;
@@ -308,6 +310,72 @@ void column_face_geometry(const PrismRef &r, const double *abc, double q, double
         }
 }
 
+// volume of one column's zone in the unit shell: the Jacobian of the map
+// integrated by Gauss points in zeta times a rule on the triangle obtained by
+// collapsing the square onto it (Duffy), six points each way
+double column_volume(const PrismRef &r, const double *abc, double q)
+{
+    const int mo = r.order - 1, ng = 6;
+    std::vector<std::array<int, 3>> bary;
+    std::vector<std::array<double, 3>> lx;
+    lattice(mo, bary, lx);
+    const int nl = (int)lx.size();
+    std::vector<double> sp((size_t)nl * 3);
+    const double *P[3] = {abc, abc + 3, abc + 6};
+    for (int a = 0; a < nl; a++) {
+        double *o = &sp[3 * a];
+        const auto &bc = bary[a];
+        const int nz = (bc[0] == 0) + (bc[1] == 0) + (bc[2] == 0);
+        if (nz == 2) std::memcpy(o, P[bc[0] ? 0 : bc[1] ? 1 : 2], 24);
+        else if (nz == 1) {
+            const int u = bc[0] ? 0 : 1, w = bc[2] ? 2 : 1;
+            arc_point(P[u], P[w], double(bc[w]) / (bc[u] + bc[w]), o);
+        } else {
+            for (int i = 0; i < 3; i++) o[i] = P[0][i] + P[1][i] + P[2][i];
+            unit(o);
+        }
+    }
+    std::vector<std::array<int, 3>> tmo;
+    for (int deg = 0; deg <= mo; deg++)
+        for (int a = deg; a >= 0; a--) tmo.push_back({a, deg - a, 0});
+    std::vector<double> C;
+    lagrange_coefficients(lx, tmo, C);
+    double gx[8], gw[8];
+    gauss_legendre01(ng, gx, gw);
+    const double s3 = std::sqrt(3.0);
+    const double A[2] = {-0.5, -0.5 / s3}, B[2] = {0.5, -0.5 / s3}, Cc[2] = {0.0, 1.0 / s3};
+    double V = 0.0;
+    for (int i = 0; i < ng; i++)
+        for (int j = 0; j < ng; j++) {
+            // the square's (s, w) -> the triangle point A + s (B - A) + (1 - s) w (C - A)
+            const double sv = gx[i], tv = (1.0 - sv) * gx[j];
+            const double xi = A[0] + sv * (B[0] - A[0]) + tv * (Cc[0] - A[0]);
+            const double eta = A[1] + sv * (B[1] - A[1]) + tv * (Cc[1] - A[1]);
+            double S[3] = {0, 0, 0}, Sx[3] = {0, 0, 0}, Sy[3] = {0, 0, 0};
+            for (int b = 0; b < nl; b++) {
+                double L = 0.0, Lx = 0.0, Ly = 0.0;
+                for (int m = 0; m < nl; m++) {
+                    const double c = C[(size_t)m * nl + b];
+                    const int ex = tmo[m][0], ey = tmo[m][1];
+                    L += c * std::pow(xi, ex) * std::pow(eta, ey);
+                    if (ex) Lx += c * ex * std::pow(xi, ex - 1) * std::pow(eta, ey);
+                    if (ey) Ly += c * ey * std::pow(xi, ex) * std::pow(eta, ey - 1);
+                }
+                for (int k = 0; k < 3; k++) { S[k] += L * sp[3 * b + k]; Sx[k] += Lx * sp[3 * b + k]; Sy[k] += Ly * sp[3 * b + k]; }
+            }
+            // x = R(zeta) S: J = R^2 (q - 1) S . (S_xi x S_eta)
+            const double trip = S[0] * (Sx[1] * Sy[2] - Sx[2] * Sy[1]) + S[1] * (Sx[2] * Sy[0] - Sx[0] * Sy[2]) +
+                                S[2] * (Sx[0] * Sy[1] - Sx[1] * Sy[0]);
+            double rz = 0.0;
+            for (int k = 0; k < ng; k++) {
+                const double R = (1.0 - gx[k]) + gx[k] * q;   // zeta = gx - 1/2
+                rz += gw[k] * R * R;
+            }
+            V += 2.0 * (s3 / 4.0) * (1.0 - sv) * gw[i] * gw[j] * (q - 1.0) * trip * rz;
+        }
+    return V;
+}
+
 // mesh edges in first-encounter order over (triangle, local edge a-b, b-c,
 // c-a), kept where the triangle precedes its neighbour; endpoints are
 // compared bit for bit (shared vertices come out of the same sums)
@@ -385,6 +453,14 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     for (int64_t t = 0; t < p->ntri; t++)
         column_face_geometry(p->ref, &p->tri[9 * t], p->q, &p->tfA[(size_t)t * QT * 3], &p->sfA[(size_t)t * 3 * QS * 3]);
     if (!mesh_edges(p->tri, p->edges)) { set_error("the triangles do not close into a sphere"); free_prism(p); return RG_ESINGULAR; }
+    p->vol.assign(p->ntri, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < p->ntri; t++) p->vol[t] = column_volume(p->ref, &p->tri[9 * t], p->q);
+    p->tedge.assign((size_t)p->ntri * 3, 0);
+    for (size_t e = 0; e < p->edges.size() / 4; e++) {
+        p->tedge[3 * (size_t)p->edges[4 * e] + p->edges[4 * e + 1]] = (int)e;
+        p->tedge[3 * (size_t)p->edges[4 * e + 2] + p->edges[4 * e + 3]] = -(int)e - 1;
+    }
     // side point at the same height, mirrored along the edge (the neighbour
     // runs the shared edge the other way)
     p->mirror.assign(QS, -1);
@@ -411,7 +487,8 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
         !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt) || !upload(p, p->ref.fidx, &G.fidx) ||
         !upload(p, p->ref.fval, &G.fval) || !upload(p, p->edges, &G.edges) || !upload(p, p->mirror, &G.mirror) ||
-        !upload(p, p->tfA, &G.tfA) || !upload(p, p->sfA, &G.sfA) || !upload(p, p->radius, &G.radius)) {
+        !upload(p, p->tfA, &G.tfA) || !upload(p, p->sfA, &G.sfA) || !upload(p, p->radius, &G.radius) ||
+        !upload(p, p->vol, &G.vol) || !upload(p, p->tedge, &G.tedge)) {
         set_error("device allocation or upload of the prism geometry failed");
         free_prism(p);
         return RG_ENOMEM;
@@ -453,6 +530,26 @@ rg_status rg_prism_edges(const rg_prism *p, int32_t *edges)
     if (!p || !edges) { set_error("null argument"); return RG_EINVAL; }
     std::memcpy(edges, p->edges.data(), p->edges.size() * sizeof(int));
     return RG_OK;
+}
+
+rg_status rg_prism_volumes(const rg_prism *p, int64_t z0, int64_t nz, double *vol)
+{
+    if (!p || !vol) { set_error("null argument"); return RG_EINVAL; }
+    if (z0 < 0 || nz < 0 || z0 + nz > p->nz) { set_error("zone range outside the mesh"); return RG_EINVAL; }
+    for (int64_t i = 0; i < nz; i++) {
+        const int64_t z = z0 + i;
+        const double s = p->radius[z % p->n_rad];
+        vol[i] = s * s * s * p->vol[z / p->n_rad];
+    }
+    return RG_OK;
+}
+
+rg_status rg_prism_update(const rg_prism *p, double dt, const double *U, const double *Phi, double *Uo, void *stream)
+{
+    if (!p || !U || !Phi || !Uo) { set_error("null argument"); return RG_EINVAL; }
+    if (!(dt >= 0.0)) { set_error("need dt >= 0"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    return launch_prism_update(p->dev, dt, U, Phi, Uo, stream);
 }
 
 rg_status rg_prism_face_fluxes(const rg_prism *p, double gamma, const double *tr, double *Phi, void *stream)

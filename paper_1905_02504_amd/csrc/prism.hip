@@ -446,6 +446,50 @@ rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *
     }
 }
 
+// Finite-volume update of the zone averages (Section VI): U - dt / V times
+// the zone's net outward face flux; one lane per zone (U, Uo [8][nz],
+// Phi [nfaces][8]).
+__global__ __launch_bounds__(256) void prism_update(DevPrism G, double dt, const double *__restrict__ U,
+                                                    const double *__restrict__ Phi, double *__restrict__ Uo)
+{
+    const i64 z = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (z >= G.nz) return;
+    const int nr = G.n_rad;
+    const i64 t = z / nr, nrf = G.ntri * (nr + 1);
+    const int k = (int)(z - t * nr);
+    i64 f[5];
+    double sg[5];
+    f[0] = t * (nr + 1) + k + 1;   // top face, +r outward
+    sg[0] = 1.0;
+    f[1] = t * (nr + 1) + k;       // bottom face
+    sg[1] = -1.0;
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        const int id = G.tedge[t * 3 + e];
+        f[2 + e] = nrf + (i64)(id >= 0 ? id : -id - 1) * nr + k;
+        sg[2 + e] = id >= 0 ? 1.0 : -1.0;
+    }
+    const double r = G.radius[k], cfac = dt / (r * r * r * G.vol[t]);
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; j++) acc += sg[j] * Phi[f[j] * 8 + v];
+        Uo[(i64)v * G.nz + z] = U[(i64)v * G.nz + z] - cfac * acc;
+    }
+}
+
+rg_status launch_prism_update(const DevPrism &G, double dt, const double *U, const double *Phi, double *Uo, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const i64 nb = (G.nz + 255) / 256;
+    if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (nb == 0) return RG_OK;
+    prism_update<<<(unsigned)nb, 256, 0, st>>>(G, dt, U, Phi, Uo);
+    if (hipGetLastError() != hipSuccess) { set_error("prism update launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
 template <int P>
 static rg_status launch_order(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                               double *aF, hipStream_t st)

@@ -67,10 +67,14 @@ struct DevPrism {
     const double *tfA;    // ntri x QT x 3: weighted area vectors of the triangle faces at radius 1 (+r)
     const double *sfA;    // ntri x 3 x QS x 3: weighted outward area vectors of the side faces, unit shell
     const double *radius; // n_rad + 1
+    // update
+    const double *vol;    // ntri: volume of the unit shell's zone (shell k: r_k^3 times it)
+    const int *tedge;     // ntri x 3: edge id of each local edge, negated - 1 where t is the second triangle
 };
 
 rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream);
 rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *tr, double *Phi, void *stream);
+rg_status launch_prism_update(const DevPrism &G, double dt, const double *U, const double *Phi, double *Uo, void *stream);
 rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                                double *aF, void *stream);
 

@@ -118,6 +118,28 @@ def test_prism_face_fluxes_match_oracle(order):
     assert e.max() < TOL
 
 
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_update_matches_oracle(order):
+    """The finite-volume update (rg_prism_update) of zone averages from the
+    library's own face fluxes against the oracle's chain, level 1 x 3."""
+    import paper_1905_02504_amd as R
+    print(f"[prism] update, order {order}, level 1 x 3 shells", flush=True)
+    lib = R.PrismMesh(1, 3, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.5, order=order)
+    x, J, met = om.geometry(np.arange(om.nz))
+    Ua = smooth_state(x, np.random.default_rng(53 + order))
+    U = Ua.mean(1)                                  # zone averages [nz][8]
+    dt = 0.02
+    aU_o, aF_o = P.predict(order, J, met, Ua, dt, GAMMA)
+    U1_o = om.update(U, om.face_fluxes(P.traces(order, aU_o, aF_o), GAMMA), dt)
+    aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), dt, GAMMA)
+    Phi = lib.face_fluxes(lib.traces(aU, aF), GAMMA)
+    U1 = lib.update(torch.from_numpy(np.ascontiguousarray(U.T)).cuda(), Phi, dt).cpu().numpy()
+    e = rel_by_var(U1, U1_o.T, 0)
+    print(f"[prism] update: max rel error per variable {e.max():.2e}", flush=True)
+    assert e.max() < TOL
+
+
 def test_prism_predictor_without_sweeps_returns_the_initial_state():
     """n_picard = 0 keeps every level at the initial state: the averages are
     the state itself and its physical flux (the Gauss weights sum to one)."""
@@ -175,7 +197,23 @@ def test_prism_predictor_fullsize_sampled_zones():
     eT = rel_by_var(tr[:, zt].cpu().numpy(), tr_o[:, j, :].transpose(2, 0, 1), 0)
     print(f"[prism] sampled traces: {eT.max():.2e}", flush=True)
     assert eT.max() < TOL
+    # face fluxes and the update of the whole mesh: conservation up to the
+    # boundary fluxes, zone averages from the nodal states
+    Phi = lib.face_fluxes(tr, GAMMA)
     del tr
+    U = Ua.mean(2).contiguous()
+    U1 = lib.update(U, Phi, dt)
+    vol = torch.from_numpy(lib.volumes()).cuda()
+    nr = lib.n_rad
+    rad = torch.arange(lib.ntri, device="cuda") * (nr + 1)
+    outer, inner = Phi[rad + nr].sum(0), Phi[rad].sum(0)
+    lhs = (vol[None, :] * (U1 - U)).sum(1)
+    rhs = -dt * (outer - inner)
+    scale = float(dt * (Phi.abs() * 1.0).sum(0).max())
+    dev_c = float((lhs - rhs).abs().max()) / scale
+    print(f"[prism] update at full size: conservation defect {dev_c:.2e} of the summed face fluxes", flush=True)
+    assert dev_c < 1e-12 and torch.isfinite(U1).all()
+    del Phi, U, U1
     # free stream at full size: a uniform state stays uniform in every zone
     Ua.copy_(base[:, None, None].expand_as(Ua))
     aU, aF = lib.predict(Ua, dt, GAMMA, aU=aU, aF=aF)
@@ -200,3 +238,5 @@ def test_prism_predictor_argument_errors():
         N.rg_prism_traces(lib._h, U.data_ptr(), 0, U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_face_fluxes(lib._h, 1.0, U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_update(lib._h, -1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)

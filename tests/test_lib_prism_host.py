@@ -52,3 +52,11 @@ def test_prism_edges_and_face_counts_match_oracle():
         om = P.OraclePrismMesh(level, 3, order=3)
         assert np.array_equal(m.edges(), om.edges())
         assert m.n_edges == 30 * 4 ** level and m.n_faces == m.ntri * 4 + m.n_edges * 3
+
+
+def test_prism_volumes_match_oracle():
+    import paper_1905_02504_amd as R
+    for order in (2, 3, 4):
+        m = R.PrismMesh(2, 3, order, r_in=1.0, r_out=1.5, device=False)
+        om = P.OraclePrismMesh(2, 3, r_in=1.0, r_out=1.5, order=order)
+        np.testing.assert_allclose(m.volumes(), om.volumes(np.arange(om.nz)), rtol=1e-13)

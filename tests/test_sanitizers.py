@@ -89,6 +89,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_prism_predict(const DevPrism &, double, double, int, const double *, double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_traces(const DevPrism &, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_face_flux(const DevPrism &, double, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_update(const DevPrism &, double, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
     }
     // the prism element's host side: mesh, geometry and face-point queries
     static int run_prism(int order) {
@@ -107,6 +108,9 @@ LIB_DRIVER = textwrap.dedent(r"""
         std::vector<int32_t> edges(4 * info.n_edges);
         if (rc == RG_OK) rc = rg_prism_edges(p, edges.data());
         if (rg_prism_face_fluxes(p, 5.0 / 3.0, x.data(), x.data(), nullptr) != RG_EINVAL) rc = 14;
+        std::vector<double> vol(info.n_zones);
+        if (rc == RG_OK) rc = rg_prism_volumes(p, 0, info.n_zones, vol.data());
+        if (rg_prism_update(p, 1e-3, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 15;
         if (rg_prism_geometry(p, info.n_zones - 4, 5, x.data(), J.data(), met.data()) != RG_EINVAL) rc = 11;
         if (rg_prism_predict(p, 5.0 / 3.0, 1e-3, order, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 12;
         rg_prism_free(p);
