@@ -544,3 +544,244 @@ int rgo_prism_volumes(int order, int nz, const double *abc, const double *r01, d
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------- divergence-free B
+ * Section IV.b on the prism (five faces).  Per zone, in the zone's Taylor
+ * frame X = (x - centroid) / l0, l0 = V^(1/3): each component carries the
+ * monomials of degree <= p-1 and the degree-p monomials containing its own
+ * coordinate (eqs. 4.1, 4.4, 4.7 generalised), each non-constant one minus its
+ * zone mean.  Least squares: the coefficients of degree <= p-1 towards the
+ * WENO-AO ones (the extras towards zero) (eqs. 4.3, 4.6, 4.9), and the normal
+ * component at every face point towards the face's nodal normal B
+ * (eq. 4.15).  Constraints: the divergence identities of eq. (4.10) without
+ * its first member (the multi-indices 1 <= |mu| <= p-1) and the five face
+ * averages (eq. 4.14) by each face's rule.  Inputs per zone, NIN values:
+ * for each component its zone mean and its Taylor coefficients of degree
+ * 1..p-1 (degree by degree, x exponent descending, then y descending), then
+ * the normal B at the Q face points along the zone's outward normal (in the
+ * order of rgo_prism_face_points), then the five outward face averages (faces
+ * zeta = +1/2, -1/2, sides 0, 1, 2).  Outputs, 3N + 3 values: B at the N
+ * element nodes (x components, then y, then z), then the three zone means of
+ * the reconstruction. */
+static int taylor_multi(int deg, int e[][3])
+{
+    int n = 0;
+    for (int d = 1; d <= deg; d++)
+        for (int a = d; a >= 0; a--)
+            for (int b = d - a; b >= 0; b--) { e[n][0] = a; e[n][1] = b; e[n][2] = d - a - b; n++; }
+    return n;
+}
+
+int rgo_prism_divfree(int order, int nz, const double *abc, const double *r01, const double *Bin, double *Bout)
+{
+    rgo_refel r;
+    if (prism_basis_init(&r, order)) return -1;
+    const int p = order, N = r.N;
+    int te[40][3];
+    const int nc = taylor_multi(p - 1, te);
+    /* B basis of each component: constant, Taylor multi-indices, degree-p extras */
+    int be[3][64][3], nb = 0;
+    for (int c = 0; c < 3; c++) {
+        int k = 0;
+        be[c][k][0] = be[c][k][1] = be[c][k][2] = 0; k++;
+        for (int a = 0; a < nc; a++) { memcpy(be[c][k], te[a], sizeof(int) * 3); k++; }
+        for (int a = p; a >= 0; a--)
+            for (int b = p - a; b >= 0; b--) {
+                int e[3] = {a, b, p - a - b};
+                if (e[c] >= 1) { memcpy(be[c][k], e, sizeof(int) * 3); k++; }
+            }
+        nb = k;
+    }
+    double xi[38 * 3], wr[38];
+    int nt, ns;
+    const int Q = rgo_prism_face_points(order, xi, wr, &nt, &ns);
+    const int nu = 3 * nb, ndiv = nc, ncon = ndiv + 5, nrow = nu + Q, NIN = 3 * (nc + 1) + Q + 5, NOUT = 3 * N + 3;
+    const int ng = 6;
+    double gx[8], gw[8], v1[2], v2[2], v3[2];
+    gauss01(ng, gx, gw);
+    tri_vertex(0, v1);
+    tri_vertex(1, v2);
+    tri_vertex(2, v3);
+    double *A = malloc(sizeof(double) * nrow * nu), *C = malloc(sizeof(double) * ncon * nu);
+    double *K = malloc(sizeof(double) * (nu + ncon) * (nu + ncon)), *rhs = malloc(sizeof(double) * (nu + ncon));
+    double *sol = malloc(sizeof(double) * (nu + ncon)), *b = malloc(sizeof(double) * nrow), *d = malloc(sizeof(double) * ncon);
+    int rc = 0;
+    for (int z = 0; z < nz && !rc; z++) {
+        tri_map t;
+        if (tri_map_init(&t, order - 1, &abc[9 * z], &abc[9 * z + 3], &abc[9 * z + 6])) { rc = -1; break; }
+        const double r0 = r01[2 * z], r1 = r01[2 * z + 1];
+        /* cubature: volume, centroid, moments of the Taylor frame */
+        double V = 0.0, cen[3] = {0, 0, 0};
+        double *px = malloc(sizeof(double) * ng * ng * ng * 4);
+        int np = 0;
+        for (int i = 0; i < ng; i++)
+            for (int j = 0; j < ng; j++)
+                for (int k = 0; k < ng; k++) {
+                    double s = gx[i], tt = (1.0 - s) * gx[j], q3[3], x[3], jac[9];
+                    q3[0] = v1[0] + s * (v2[0] - v1[0]) + tt * (v3[0] - v1[0]);
+                    q3[1] = v1[1] + s * (v2[1] - v1[1]) + tt * (v3[1] - v1[1]);
+                    q3[2] = gx[k] - 0.5;
+                    prism_map(&t, r0, r1, q3, x, jac);
+                    double wJ = 2.0 * (S3 / 4.0) * (1.0 - s) * gw[i] * gw[j] * gw[k] * det3(jac);
+                    V += wJ;
+                    for (int c = 0; c < 3; c++) cen[c] += wJ * x[c];
+                    memcpy(&px[4 * np], x, 24);
+                    px[4 * np + 3] = wJ;
+                    np++;
+                }
+        for (int c = 0; c < 3; c++) cen[c] /= V;
+        const double l0 = cbrt(V);
+        double mom[6][6][6];
+        memset(mom, 0, sizeof(mom));
+        for (int q = 0; q < np; q++) {
+            double X[3];
+            for (int c = 0; c < 3; c++) X[c] = (px[4 * q + c] - cen[c]) / l0;
+            for (int a = 0; a <= p; a++)
+                for (int bb = 0; a + bb <= p; bb++)
+                    for (int cc = 0; a + bb + cc <= p; cc++) {
+                        int e[3] = {a, bb, cc};
+                        mom[a][bb][cc] += px[4 * q + 3] * mono3(e, X) / V;
+                    }
+        }
+        free(px);
+#define TB(e, X) (((e)[0] + (e)[1] + (e)[2]) == 0 ? 1.0 : mono3((e), (X)) - mom[(e)[0]][(e)[1]][(e)[2]])
+        const double *in = &Bin[(size_t)z * NIN];
+        memset(A, 0, sizeof(double) * nrow * nu);
+        memset(C, 0, sizeof(double) * ncon * nu);
+        memset(b, 0, sizeof(double) * nrow);
+        memset(d, 0, sizeof(double) * ncon);
+        /* closeness to the WENO-AO coefficients */
+        for (int c = 0; c < 3; c++)
+            for (int k = 0; k < nb; k++) {
+                A[(size_t)(c * nb + k) * nu + c * nb + k] = 1.0;
+                b[c * nb + k] = k <= nc ? in[c * (nc + 1) + k] : 0.0;
+            }
+        /* face points: positions, outward normals, weights within each face */
+        double area[5] = {0, 0, 0, 0, 0};
+        double fx[38][3], fn[38][3], fa[38];
+        for (int q = 0; q < Q; q++) {
+            double jac[9], a3[3], b3[3], c3[3], sc;
+            prism_map(&t, r0, r1, &xi[3 * q], fx[q], jac);
+            if (q < 2 * nt) {
+                for (int i = 0; i < 3; i++) { a3[i] = jac[3 * i]; b3[i] = jac[3 * i + 1]; }
+                sc = (q < nt ? 1.0 : -1.0) * (S3 / 4.0) * wr[q];
+            } else {
+                const int k = (q - 2 * nt) / ns;
+                double V0[2], V1[2];
+                tri_vertex(k, V0);
+                tri_vertex((k + 1) % 3, V1);
+                for (int i = 0; i < 3; i++) { a3[i] = jac[3 * i] * (V1[0] - V0[0]) + jac[3 * i + 1] * (V1[1] - V0[1]); b3[i] = jac[3 * i + 2]; }
+                sc = wr[q];
+            }
+            c3[0] = a3[1] * b3[2] - a3[2] * b3[1];
+            c3[1] = a3[2] * b3[0] - a3[0] * b3[2];
+            c3[2] = a3[0] * b3[1] - a3[1] * b3[0];
+            const double m = sqrt(dot3(c3, c3));
+            for (int i = 0; i < 3; i++) fn[q][i] = (sc > 0 ? 1.0 : -1.0) * c3[i] / m;
+            fa[q] = fabs(sc) * m;
+            const int f = q < nt ? 0 : q < 2 * nt ? 1 : 2 + (q - 2 * nt) / ns;
+            area[f] += fa[q];
+        }
+        for (int q = 0; q < Q; q++) {
+            const int f = q < nt ? 0 : q < 2 * nt ? 1 : 2 + (q - 2 * nt) / ns;
+            double X[3];
+            for (int c = 0; c < 3; c++) X[c] = (fx[q][c] - cen[c]) / l0;
+            for (int c = 0; c < 3; c++)
+                for (int k = 0; k < nb; k++) {
+                    const double val = fn[q][c] * TB(be[c][k], X);
+                    A[(size_t)(nu + q) * nu + c * nb + k] = val;
+                    C[(size_t)(ndiv + f) * nu + c * nb + k] += fa[q] / area[f] * val;
+                }
+            b[nu + q] = in[3 * (nc + 1) + q];
+        }
+        for (int f = 0; f < 5; f++) d[ndiv + f] = in[3 * (nc + 1) + Q + f];
+        /* divergence identities: coefficient of X^mu in div B vanishes, 1 <= |mu| <= p-1 */
+        for (int i = 0; i < ndiv; i++)
+            for (int c = 0; c < 3; c++) {
+                int tmu[3] = {te[i][0], te[i][1], te[i][2]};
+                tmu[c] += 1;
+                for (int k = 0; k < nb; k++)
+                    if (be[c][k][0] == tmu[0] && be[c][k][1] == tmu[1] && be[c][k][2] == tmu[2])
+                        C[(size_t)i * nu + c * nb + k] += (double)tmu[c];
+            }
+        /* KKT [2 A^T A, C^T; C, 0] */
+        const int n = nu + ncon;
+        for (int i = 0; i < nu; i++) {
+            for (int j = 0; j < nu; j++) {
+                double s = 0.0;
+                for (int k = 0; k < nrow; k++) s += A[(size_t)k * nu + i] * A[(size_t)k * nu + j];
+                K[(size_t)i * n + j] = 2.0 * s;
+            }
+            double s = 0.0;
+            for (int k = 0; k < nrow; k++) s += A[(size_t)k * nu + i] * b[k];
+            rhs[i] = 2.0 * s;
+        }
+        for (int i = 0; i < ncon; i++) {
+            for (int j = 0; j < nu; j++) {
+                K[(size_t)(nu + i) * n + j] = C[(size_t)i * nu + j];
+                K[(size_t)j * n + nu + i] = C[(size_t)i * nu + j];
+            }
+            for (int j = 0; j < ncon; j++) K[(size_t)(nu + i) * n + nu + j] = 0.0;
+            rhs[nu + i] = d[i];
+        }
+        if (la_lu_solve(n, K, rhs, sol)) { rc = -2; break; }
+        /* B at the element nodes and the zone means */
+        double *out = &Bout[(size_t)z * NOUT];
+        for (int i = 0; i < N; i++) {
+            double x[3], jac[9], X[3];
+            prism_map(&t, r0, r1, r.node[i], x, jac);
+            for (int c = 0; c < 3; c++) X[c] = (x[c] - cen[c]) / l0;
+            for (int c = 0; c < 3; c++) {
+                double s = 0.0;
+                for (int k = 0; k < nb; k++) s += sol[c * nb + k] * TB(be[c][k], X);
+                out[c * N + i] = s;
+            }
+        }
+        for (int c = 0; c < 3; c++) out[3 * N + c] = sol[c * nb];
+#undef TB
+    }
+    free(A); free(C); free(K); free(rhs); free(sol); free(b); free(d);
+    return rc;
+}
+
+/* sizes of the divergence-free map's input and output vectors */
+void rgo_prism_divfree_sizes(int order, int *nin, int *nout)
+{
+    int te[40][3];
+    const int nc = taylor_multi(order - 1, te);
+    const int Q = order == 2 ? 15 : order == 3 ? 24 : 38, N = order == 2 ? 6 : order == 3 ? 15 : 26;
+    *nin = 3 * (nc + 1) + Q + 5;
+    *nout = 3 * N + 3;
+}
+
+/* zone centroid cen[z][3] and Taylor length l0[z] = V^(1/3) by the cubature
+ * of rgo_prism_volumes */
+int rgo_prism_frames(int order, int nz, const double *abc, const double *r01, double *cen, double *l0)
+{
+    const int ng = 6;
+    double gx[8], gw[8], v1[2], v2[2], v3[2];
+    gauss01(ng, gx, gw);
+    tri_vertex(0, v1);
+    tri_vertex(1, v2);
+    tri_vertex(2, v3);
+    for (int z = 0; z < nz; z++) {
+        tri_map t;
+        if (tri_map_init(&t, order - 1, &abc[9 * z], &abc[9 * z + 3], &abc[9 * z + 6])) return -1;
+        double V = 0.0, c[3] = {0, 0, 0};
+        for (int i = 0; i < ng; i++)
+            for (int j = 0; j < ng; j++)
+                for (int k = 0; k < ng; k++) {
+                    double s = gx[i], tt = (1.0 - s) * gx[j], xi[3], x[3], jac[9];
+                    xi[0] = v1[0] + s * (v2[0] - v1[0]) + tt * (v3[0] - v1[0]);
+                    xi[1] = v1[1] + s * (v2[1] - v1[1]) + tt * (v3[1] - v1[1]);
+                    xi[2] = gx[k] - 0.5;
+                    prism_map(&t, r01[2 * z], r01[2 * z + 1], xi, x, jac);
+                    const double wJ = 2.0 * (S3 / 4.0) * (1.0 - s) * gw[i] * gw[j] * gw[k] * det3(jac);
+                    V += wJ;
+                    for (int d = 0; d < 3; d++) c[d] += wJ * x[d];
+                }
+        for (int d = 0; d < 3; d++) cen[3 * z + d] = c[d] / V;
+        l0[z] = cbrt(V);
+    }
+    return 0;
+}

@@ -52,6 +52,12 @@ def _lib():
         L.rgo_prism_hll.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
         L.rgo_prism_volumes.restype = C.c_int
         L.rgo_prism_volumes.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+        L.rgo_prism_divfree.restype = C.c_int
+        L.rgo_prism_divfree.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.rgo_prism_divfree_sizes.restype = None
+        L.rgo_prism_divfree_sizes.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.rgo_prism_frames.restype = C.c_int
+        L.rgo_prism_frames.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L._prism_ready = True
     return L
 
@@ -235,6 +241,31 @@ class OraclePrismMesh:
             raise ValueError("prism volumes failed")
         return vol
 
+    def _abc_r01(self, zones):
+        t, k = self.zone_tri_shell(zones)
+        nz = len(t)
+        abc = np.ascontiguousarray(self.vert[self.tri[t]].reshape(nz, 9))
+        r01 = np.ascontiguousarray(np.stack([self.radius[k], self.radius[k + 1]], 1))
+        return nz, abc, r01
+
+    def frames(self, zones):
+        """zone centroids [z][3] and Taylor lengths l0 = V^(1/3) [z]"""
+        nz, abc, r01 = self._abc_r01(zones)
+        cen, l0 = np.zeros((nz, 3)), np.zeros(nz)
+        if _lib().rgo_prism_frames(self.order, nz, abc, r01, cen, l0):
+            raise ValueError("prism frames failed")
+        return cen, l0
+
+    def divfree(self, zones, Bin):
+        """divergence-free reconstruction of B (Section IV.b, five faces) from
+        Bin[z][NIN] (see prism.c) -> [z][3N + 3]: B at the nodes, zone means"""
+        nz, abc, r01 = self._abc_r01(zones)
+        nin, nout = divfree_sizes(self.order)
+        out = np.zeros((nz, nout))
+        if _lib().rgo_prism_divfree(self.order, nz, abc, r01, np.ascontiguousarray(Bin, np.float64), out):
+            raise ValueError("prism divergence-free reconstruction failed")
+        return out
+
     def zone_faces(self):
         """for every zone its five faces with the sign of the zone's outward
         normal relative to the face's direction: [nz][5] faces, [nz][5] signs"""
@@ -302,3 +333,14 @@ def traces(order, aU, aF):
     if _lib().rgo_prism_traces(order, nz, np.ascontiguousarray(aU), np.ascontiguousarray(aF), tr):
         raise ValueError("prism traces failed")
     return tr
+
+
+def divfree_sizes(order):
+    a, b = C.c_int(0), C.c_int(0)
+    _lib().rgo_prism_divfree_sizes(order, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def taylor_indices(order):
+    """multi-indices of degree 1..p-1: degree by degree, x exponent descending, then y"""
+    return [(a, b, d - a - b) for d in range(1, order) for a in range(d, -1, -1) for b in range(d - a, -1, -1)]

@@ -449,3 +449,54 @@ def test_prism_update_conserves_up_to_boundary_fluxes():
     outer = Phi[[t * (nr + 1) + nr for t in range(m.ntri)]].sum(0)
     inner = Phi[[t * (nr + 1) for t in range(m.ntri)]].sum(0)
     np.testing.assert_allclose((vol[:, None] * (U1 - U)).sum(0), -dt * (outer - inner), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- divergence-free B
+def divfree_inputs_linear(m, zones, B0, G):
+    """the KKT inputs of the field B(x) = B0 + G x (G trace-free, so div B = 0):
+    zone means, Taylor coefficients (degree 1: l0 G; higher: 0), the outward
+    normal B at the face points and the face averages by each face's rule"""
+    order = m.order
+    nc = len(P.taylor_indices(order))
+    xi, w, nt, ns = P.face_points(order)
+    Q = len(w)
+    cen, l0 = m.frames(zones)
+    xq, dA = m.face_geometry(zones)
+    nin, nout = P.divfree_sizes(order)
+    Bin = np.zeros((len(zones), nin))
+    ti = P.taylor_indices(order)
+    for z in range(len(zones)):
+        for c in range(3):
+            Bin[z, c * (nc + 1)] = B0[c] + G[c] @ cen[z]
+            for a, e in enumerate(ti):
+                if sum(e) == 1:
+                    Bin[z, c * (nc + 1) + 1 + a] = l0[z] * G[c][int(np.argmax(e))]
+        Bx = B0[None] + xq[z] @ G.T
+        an = np.linalg.norm(dA[z], axis=1)
+        nrm = dA[z] / an[:, None]
+        bn = (Bx * nrm).sum(1)
+        Bin[z, 3 * (nc + 1):3 * (nc + 1) + Q] = bn
+        faces = [np.arange(nt), np.arange(nt, 2 * nt)] + [2 * nt + k * ns + np.arange(ns) for k in range(3)]
+        for f, q in enumerate(faces):
+            Bin[z, 3 * (nc + 1) + Q + f] = (an[q] * bn[q]).sum() / an[q].sum()
+    return Bin
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_divfree_reconstruction_reproduces_linear_divergence_free_fields(order):
+    """Consistent inputs of a divergence-free linear field (in the space at
+    every order) give that field back exactly at the nodes of curved zones
+    (Section IV.b: the constraints and the least squares are all met by it)."""
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    rng = np.random.default_rng(17)
+    G = rng.normal(size=(3, 3)); G -= np.eye(3) * np.trace(G) / 3
+    B0 = rng.normal(size=3)
+    zones = np.arange(0, m.nz, 7)
+    out = m.divfree(zones, divfree_inputs_linear(m, zones, B0, G))
+    x, _, _ = m.geometry(zones)
+    N = m.N
+    want = B0[None, None] + x @ G.T                 # [z][N][3]
+    got = out[:, :3 * N].reshape(len(zones), 3, N).transpose(0, 2, 1)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    cen, _ = m.frames(zones)
+    np.testing.assert_allclose(out[:, 3 * N:], B0[None] + cen @ G.T, rtol=0, atol=1e-12)
