@@ -280,6 +280,26 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     ms_up = e0.elapsed_time(e1) / reps
     up_bytes = 8.0 * (16 * lib.nz + 5 * 8 * lib.nz)
     del U, U1
+    # divergence-free reconstruction of B: one column map per column applied
+    # to every shell (the first call builds and uploads the maps, untimed)
+    nin, nout = lib.n_divfree_in, lib.n_divfree_out
+    Bin = torch.randn((nin, lib.nz), generator=gen, device="cuda", dtype=torch.float64)
+    Bout = torch.empty((nout, lib.nz), dtype=torch.float64, device="cuda")
+    t_maps = time.perf_counter()
+    lib.divfree(Bin, Bout)
+    torch.cuda.synchronize()
+    t_maps = time.perf_counter() - t_maps
+    e0.record(stream)
+    for _ in range(reps):
+        lib.divfree(Bin, Bout)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_df = e0.elapsed_time(e1) / reps
+    if not torch.isfinite(Bout).all():
+        raise RuntimeError("non-finite divergence-free reconstruction")
+    df_bytes = 8.0 * (nin + nout) + 8.0 * nin * nout / n_rad     # per zone: in, out, the column's map shared by its shells
+    df_flops = 2.0 * nin * nout
+    del Bin, Bout
     flops, nbytes = lib.work()
     nz, lib_q = lib.nz, lib.Q
     del aU, tr, Phi
@@ -295,6 +315,9 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
             "face_fluxes": {"ms": ms_ff, "faces": n_faces, "face_updates_per_s": n_faces / (ms_ff * 1e-3),
                             "hbm_gbs": ff_bytes / (ms_ff * 1e-3) / 1e9},
             "update": {"ms": ms_up, "hbm_gbs": up_bytes / (ms_up * 1e-3) / 1e9},
+            "divfree": {"ms": ms_df, "inputs": nin, "outputs": nout, "bytes_per_zone": df_bytes,
+                        "flops_per_zone": df_flops, "hbm_gbs": df_bytes * nz / (ms_df * 1e-3) / 1e9,
+                        "tflops": df_flops * nz / (ms_df * 1e-3) / 1e12, "map_build_s": t_maps},
             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
 
@@ -584,7 +607,9 @@ def main():
             f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak); "
             f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s), "
             f"face fluxes {prism['face_fluxes']['ms']:.2f} ms ({prism['face_fluxes']['hbm_gbs']:.0f} GB/s), "
-            f"update {prism['update']['ms']:.2f} ms")
+            f"update {prism['update']['ms']:.2f} ms, divergence-free B {prism['divfree']['ms']:.2f} ms "
+            f"({prism['divfree']['hbm_gbs']:.0f} GB/s, {prism['divfree']['tflops']:.1f} TFLOP/s; maps built in "
+            f"{prism['divfree']['map_build_s']:.1f} s)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,

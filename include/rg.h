@@ -417,6 +417,8 @@ typedef struct {
     int32_t n_face_points;  /* face points per zone: 15, 24, 38      */
     int64_t n_edges;        /* mesh edges: 30 * 4^level              */
     int64_t n_faces;        /* n_tri (n_rad + 1) + n_edges n_rad     */
+    int32_t n_divfree_in;   /* inputs of rg_prism_divfree per zone   */
+    int32_t n_divfree_out;  /* outputs: 3 n_nodes + 3                */
 } rg_prism_info;
 
 /* Builds the mesh and, on the current device, the geometry of every column
@@ -478,6 +480,29 @@ rg_status rg_prism_edges(const rg_prism *prism, int32_t *edges);
  * device, caller-owned.  Asynchronous on stream.  RG_EINVAL for null
  * pointers, gamma <= 1 or a host-only mesh. */
 rg_status rg_prism_face_fluxes(const rg_prism *prism, double gamma, const double *tr, double *Phi, void *stream);
+
+/* Divergence-free reconstruction of B (Section IV.b) on the prism's five
+ * faces: per zone the constrained least squares of eqs. (4.3), (4.6), (4.9)
+ * (closeness to the WENO-AO coefficients) and (4.15) (the normal B at every
+ * face point) under the divergence identities of eq. (4.10) without its first
+ * member and the five face averages of eq. (4.14), in the zone's Taylor frame
+ * (centroid, l0 = V^(1/3)); each component carries the monomials of degree
+ * <= p-1 and the degree-p ones containing its own coordinate.  The KKT system
+ * is solved once per column for all inputs (the shells of a column are
+ * scaled copies) and applied as a matrix: the first call builds and uploads
+ * the maps (8 n_out n_in bytes per column, 5.5 GB at level 6, fourth order).
+ * Bin double[n_divfree_in][n_zones]: per component its zone mean and Taylor
+ * coefficients of degree 1..p-1 (degree by degree, x exponent descending,
+ * then y), the outward normal B at the Q face points (rg_prism_face_points
+ * order), the five outward face averages (zeta = +1/2, -1/2, sides 0, 1, 2);
+ * Bout double[n_divfree_out][n_zones]: B at the nodes (x components, then y,
+ * then z), then the three zone means.  Device, caller-owned, asynchronous on
+ * stream.  RG_EINVAL for null pointers or a host-only mesh, RG_ESINGULAR if a
+ * KKT system is singular, RG_ENOMEM. */
+rg_status rg_prism_divfree(rg_prism *prism, const double *Bin, double *Bout, void *stream);
+/* The same map on the host for zones [z0, z0 + nz): Bin[nz][n_divfree_in],
+ * Bout[nz][n_divfree_out] (zone-major).  Works on host-only meshes. */
+rg_status rg_prism_divfree_host(rg_prism *prism, int64_t z0, int64_t nz, const double *Bin, double *Bout);
 
 /* Host copies of the volumes of zones [z0, z0 + nz) (the map's Jacobian
  * integrated by cubature).  RG_EINVAL outside the mesh. */

@@ -263,6 +263,7 @@ class PrismMesh:
         self.nz, self.ntri, self.N = info["n_zones"], info["n_tri"], info["n_nodes"]
         self.Q = info["n_face_points"]
         self.n_edges, self.n_faces = info["n_edges"], info["n_faces"]
+        self.n_divfree_in, self.n_divfree_out = info["n_divfree_in"], info["n_divfree_out"]
         self.level, self.n_rad, self.order = level, n_rad, order
 
     def close(self):
@@ -331,6 +332,22 @@ class PrismMesh:
             Uo = torch.empty_like(U)
         N.rg_prism_update(self._h, dt, _ptr(U), _ptr(Phi), _ptr(Uo), _stream())
         return Uo
+
+    def divfree(self, Bin, Bout=None):
+        """divergence-free B (Section IV.b): Bin [n_in][nz] -> Bout [n_out][nz] (CUDA tensors)"""
+        import torch
+        assert Bin.is_contiguous() and tuple(Bin.shape) == (self.n_divfree_in, self.nz)
+        if Bout is None:
+            Bout = torch.empty((self.n_divfree_out, self.nz), dtype=torch.float64, device=Bin.device)
+        N.rg_prism_divfree(self._h, _ptr(Bin), _ptr(Bout), _stream())
+        return Bout
+
+    def divfree_host(self, Bin, z0=0):
+        """the same map on the host: Bin [nz][n_in] -> [nz][n_out]"""
+        Bin = np.ascontiguousarray(Bin, np.float64)
+        out = np.zeros((len(Bin), self.n_divfree_out))
+        N.rg_prism_divfree_host(self._h, z0, len(Bin), _ptr(Bin), _ptr(out))
+        return out
 
     def work(self, n_picard=None):
         """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""

@@ -41,7 +41,8 @@ class rg_diag_out(C.Structure):
 class rg_prism_info(C.Structure):
     _fields_ = [("n_zones", C.c_int64), ("n_tri", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
                 ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32), ("n_face_points", C.c_int32),
-                ("n_edges", C.c_int64), ("n_faces", C.c_int64)]
+                ("n_edges", C.c_int64), ("n_faces", C.c_int64), ("n_divfree_in", C.c_int32),
+                ("n_divfree_out", C.c_int32)]
 
 
 class RGError(RuntimeError):
@@ -115,9 +116,11 @@ def lib():
         L.rg_prism_face_fluxes.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
         L.rg_prism_volumes.argtypes = [_vp, C.c_int64, C.c_int64, _vp]
         L.rg_prism_update.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp]
+        L.rg_prism_divfree.argtypes = [_vp, _vp, _vp, _vp]
+        L.rg_prism_divfree_host.argtypes = [_vp, C.c_int64, C.c_int64, _vp, _vp]
         for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work",
                      "rg_prism_face_points", "rg_prism_traces", "rg_prism_edges", "rg_prism_face_fluxes",
-                     "rg_prism_volumes", "rg_prism_update", "rg_prism_triangles", "rg_prism_geometry",
+                     "rg_prism_volumes", "rg_prism_update", "rg_prism_divfree", "rg_prism_divfree_host", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -364,3 +367,11 @@ def rg_prism_volumes(prism, z0, nz, vol_ptr):
 
 def rg_prism_update(prism, dt, U_ptr, Phi_ptr, Uo_ptr, stream):
     check(lib().rg_prism_update(prism, dt, _vp(U_ptr), _vp(Phi_ptr), _vp(Uo_ptr), _vp(stream)), "rg_prism_update")
+
+
+def rg_prism_divfree(prism, Bin_ptr, Bout_ptr, stream):
+    check(lib().rg_prism_divfree(prism, _vp(Bin_ptr), _vp(Bout_ptr), _vp(stream)), "rg_prism_divfree")
+
+
+def rg_prism_divfree_host(prism, z0, nz, Bin_ptr, Bout_ptr):
+    check(lib().rg_prism_divfree_host(prism, z0, nz, _vp(Bin_ptr), _vp(Bout_ptr)), "rg_prism_divfree_host")

@@ -65,6 +65,8 @@ struct rg_prism {
     std::vector<int> edges, mirror;   // nedges x 4; QS
     std::vector<int> tedge;           // ntri x 3
     std::vector<double> vol;          // ntri, unit shell
+    std::vector<double> Mb;           // ntri x nout x nin, built on first use
+    int nin = 0, nout = 0;
     std::vector<double> tfA, sfA;     // ntri x QT x 3; ntri x 3 x QS x 3
     std::vector<void *> allocations;
     bool device = false;
@@ -221,6 +223,61 @@ void column_geometry(const PrismRef &r, const double *abc, double q, double *x, 
         }
     }
 }
+
+// The sphere interpolant S(xi, eta) of one triangle: Lagrange through the
+// lattice of degree p-1 mapped to the sphere (vertices, great-circle edge
+// points, the spherical centroid), with its (xi, eta) derivatives.
+struct TriSurface {
+    int nl = 0;
+    std::vector<double> sp, C;
+    std::vector<std::array<int, 3>> tmo;
+    TriSurface(const PrismRef &r, const double *abc)
+    {
+        const int mo = r.order - 1;
+        std::vector<std::array<int, 3>> bary;
+        std::vector<std::array<double, 3>> lx;
+        lattice(mo, bary, lx);
+        nl = (int)lx.size();
+        sp.assign((size_t)nl * 3, 0.0);
+        const double *P[3] = {abc, abc + 3, abc + 6};
+        for (int a = 0; a < nl; a++) {
+            double *o = &sp[3 * a];
+            const auto &bc = bary[a];
+            const int nz = (bc[0] == 0) + (bc[1] == 0) + (bc[2] == 0);
+            if (nz == 2) std::memcpy(o, P[bc[0] ? 0 : bc[1] ? 1 : 2], 24);
+            else if (nz == 1) {
+                const int u = bc[0] ? 0 : 1, w = bc[2] ? 2 : 1;
+                arc_point(P[u], P[w], double(bc[w]) / (bc[u] + bc[w]), o);
+            } else {
+                for (int i = 0; i < 3; i++) o[i] = P[0][i] + P[1][i] + P[2][i];
+                unit(o);
+            }
+        }
+        for (int deg = 0; deg <= mo; deg++)
+            for (int a = deg; a >= 0; a--) tmo.push_back({a, deg - a, 0});
+        lagrange_coefficients(lx, tmo, C);
+    }
+    void eval(const double *xi, double *S, double *Sx, double *Sy) const
+    {
+        for (int k = 0; k < 3; k++) S[k] = Sx[k] = Sy[k] = 0.0;
+        for (int b = 0; b < nl; b++) {
+            double L = 0.0, Lx = 0.0, Ly = 0.0;
+            for (int m = 0; m < nl; m++) {
+                const double c = C[(size_t)m * nl + b];
+                if (c == 0.0) continue;
+                const int ex = tmo[m][0], ey = tmo[m][1];
+                L += c * std::pow(xi[0], ex) * std::pow(xi[1], ey);
+                if (ex) Lx += c * ex * std::pow(xi[0], ex - 1) * std::pow(xi[1], ey);
+                if (ey) Ly += c * ey * std::pow(xi[0], ex) * std::pow(xi[1], ey - 1);
+            }
+            for (int k = 0; k < 3; k++) {
+                S[k] += L * sp[3 * b + k];
+                Sx[k] += Lx * sp[3 * b + k];
+                Sy[k] += Ly * sp[3 * b + k];
+            }
+        }
+    }
+};
 
 // Face geometry of one column for the unit shell: the triangle-face area
 // vectors at radius 1, (sqrt 3 / 4) w_q (S_xi x S_eta), which point along +r
@@ -411,6 +468,190 @@ bool mesh_edges(const std::vector<double> &tri, std::vector<int> &edges)
     return (int64_t)edges.size() / 4 == 3 * nt / 2;
 }
 
+// Divergence-free reconstruction of B (Section IV.b with the prism's five
+// faces) as one linear map per column: the KKT system of the constrained
+// least squares is solved for every input at once, and the solution is
+// evaluated at the element nodes.  The Taylor frame (centroid, l0 = V^(1/3),
+// moments) makes the map the same for every shell of a column (each shell is
+// the unit shell scaled by r_k).  Inputs (NIN): per component its zone mean
+// and Taylor coefficients of degree 1..p-1 (degree by degree, x exponent
+// descending, then y), the outward normal B at the face points
+// (rg_prism_face_points order), the five outward face averages; outputs
+// (3N + 3): B at the nodes by component, then the three zone means.
+bool column_divfree_map(const PrismRef &r, const double *abc, double q, const double *nodex, double *Mb)
+{
+    const int p = r.order, N = r.N, Q = r.Q, QT = r.QT, QS = r.QS;
+    std::vector<std::array<int, 3>> te;
+    for (int d = 1; d <= p - 1; d++)
+        for (int a = d; a >= 0; a--)
+            for (int b = d - a; b >= 0; b--) te.push_back({a, b, d - a - b});
+    const int nc = (int)te.size();
+    std::vector<std::array<int, 3>> be[3];
+    for (int c = 0; c < 3; c++) {
+        be[c].push_back({0, 0, 0});
+        for (auto &e : te) be[c].push_back(e);
+        for (int a = p; a >= 0; a--)
+            for (int b = p - a; b >= 0; b--) {
+                std::array<int, 3> e = {a, b, p - a - b};
+                if (e[c] >= 1) be[c].push_back(e);
+            }
+    }
+    const int NB = (int)be[0].size(), nu = 3 * NB, ndiv = nc, ncon = ndiv + 5, nrow = nu + Q;
+    const int NIN = 3 * (nc + 1) + Q + 5, NOUT = 3 * N + 3;
+    const TriSurface ts(r, abc);
+    // zone cubature: Gauss in zeta times the collapsed rule on the triangle
+    const int ng = 6;
+    double gx[8], gw[8];
+    gauss_legendre01(ng, gx, gw);
+    const double s3 = std::sqrt(3.0);
+    const double VA[2] = {-0.5, -0.5 / s3}, VB[2] = {0.5, -0.5 / s3}, VC[2] = {0.0, 1.0 / s3};
+    std::vector<std::array<double, 4>> cub;
+    double V = 0.0, cen[3] = {0, 0, 0};
+    for (int i = 0; i < ng; i++)
+        for (int j = 0; j < ng; j++) {
+            const double sv = gx[i], tv = (1.0 - sv) * gx[j];
+            const double xe[2] = {VA[0] + sv * (VB[0] - VA[0]) + tv * (VC[0] - VA[0]),
+                                  VA[1] + sv * (VB[1] - VA[1]) + tv * (VC[1] - VA[1])};
+            double S[3], Sx[3], Sy[3];
+            ts.eval(xe, S, Sx, Sy);
+            const double trip = S[0] * (Sx[1] * Sy[2] - Sx[2] * Sy[1]) + S[1] * (Sx[2] * Sy[0] - Sx[0] * Sy[2]) +
+                                S[2] * (Sx[0] * Sy[1] - Sx[1] * Sy[0]);
+            for (int k = 0; k < ng; k++) {
+                const double R = (1.0 - gx[k]) + gx[k] * q;
+                const double wJ = 2.0 * (s3 / 4.0) * (1.0 - sv) * gw[i] * gw[j] * gw[k] * R * R * (q - 1.0) * trip;
+                cub.push_back({R * S[0], R * S[1], R * S[2], wJ});
+                V += wJ;
+                for (int d = 0; d < 3; d++) cen[d] += wJ * R * S[d];
+            }
+        }
+    for (int d = 0; d < 3; d++) cen[d] /= V;
+    const double l0 = std::cbrt(V);
+    auto mono = [](const std::array<int, 3> &e, const double *X) {
+        double v = 1.0;
+        for (int d = 0; d < 3; d++)
+            for (int k = 0; k < e[d]; k++) v *= X[d];
+        return v;
+    };
+    std::map<std::array<int, 3>, double> mom;
+    for (int a = 0; a <= p; a++)
+        for (int b = 0; a + b <= p; b++)
+            for (int c = 0; a + b + c <= p; c++) mom[{a, b, c}] = 0.0;
+    for (auto &pt : cub) {
+        double X[3];
+        for (int d = 0; d < 3; d++) X[d] = (pt[d] - cen[d]) / l0;
+        for (auto &kv : mom) kv.second += pt[3] * mono(kv.first, X) / V;
+    }
+    auto tb = [&](const std::array<int, 3> &e, const double *X) {
+        return e[0] + e[1] + e[2] == 0 ? 1.0 : mono(e, X) - mom.at(e);
+    };
+    // face points: positions, outward unit normals, weights within the face
+    std::vector<std::array<double, 3>> fx(Q), fn(Q);
+    std::vector<double> fa(Q);
+    double area[5] = {0, 0, 0, 0, 0};
+    double Vt[3][2] = {{VA[0], VA[1]}, {VB[0], VB[1]}, {VC[0], VC[1]}};
+    for (int qq = 0; qq < Q; qq++) {
+        const double *xi = r.fpt[qq].data();
+        double S[3], Sx[3], Sy[3], a3[3], b3[3];
+        ts.eval(xi, S, Sx, Sy);
+        const double R = (0.5 - xi[2]) + (0.5 + xi[2]) * q;
+        double sc;
+        int f;
+        if (qq < 2 * QT) {
+            for (int k = 0; k < 3; k++) { a3[k] = R * Sx[k]; b3[k] = R * Sy[k]; }
+            sc = (qq < QT ? 1.0 : -1.0) * (s3 / 4.0) * r.fw[qq];
+            f = qq < QT ? 0 : 1;
+        } else {
+            const int e = (qq - 2 * QT) / QS;
+            const double ex = Vt[(e + 1) % 3][0] - Vt[e][0], ey = Vt[(e + 1) % 3][1] - Vt[e][1];
+            for (int k = 0; k < 3; k++) { a3[k] = R * (ex * Sx[k] + ey * Sy[k]); b3[k] = (q - 1.0) * S[k]; }
+            sc = r.fw[qq];
+            f = 2 + e;
+        }
+        const double cx = a3[1] * b3[2] - a3[2] * b3[1], cy = a3[2] * b3[0] - a3[0] * b3[2], cz = a3[0] * b3[1] - a3[1] * b3[0];
+        const double m = std::sqrt(cx * cx + cy * cy + cz * cz), sg = sc > 0 ? 1.0 : -1.0;
+        fn[qq] = {sg * cx / m, sg * cy / m, sg * cz / m};
+        fa[qq] = std::fabs(sc) * m;
+        area[f] += fa[qq];
+        for (int k = 0; k < 3; k++) fx[qq][k] = R * S[k];
+    }
+    // least-squares rows and constraints, each as a map of the inputs
+    const int inF = 3 * (nc + 1), inM = inF + Q;
+    std::vector<double> Am((size_t)nrow * nu, 0.0), Sb((size_t)nrow * NIN, 0.0);
+    std::vector<double> Cm((size_t)ncon * nu, 0.0), Sd((size_t)ncon * NIN, 0.0);
+    for (int c = 0; c < 3; c++)
+        for (int k = 0; k < NB; k++) {
+            Am[(size_t)(c * NB + k) * nu + c * NB + k] = 1.0;
+            if (k <= nc) Sb[(size_t)(c * NB + k) * NIN + c * (nc + 1) + k] = 1.0;
+        }
+    for (int qq = 0; qq < Q; qq++) {
+        const int f = qq < QT ? 0 : qq < 2 * QT ? 1 : 2 + (qq - 2 * QT) / QS;
+        double X[3];
+        for (int d = 0; d < 3; d++) X[d] = (fx[qq][d] - cen[d]) / l0;
+        for (int c = 0; c < 3; c++)
+            for (int k = 0; k < NB; k++) {
+                const double val = fn[qq][c] * tb(be[c][k], X);
+                Am[(size_t)(nu + qq) * nu + c * NB + k] = val;
+                Cm[(size_t)(ndiv + f) * nu + c * NB + k] += fa[qq] / area[f] * val;
+            }
+        Sb[(size_t)(nu + qq) * NIN + inF + qq] = 1.0;
+    }
+    for (int f = 0; f < 5; f++) Sd[(size_t)(ndiv + f) * NIN + inM + f] = 1.0;
+    for (int i = 0; i < ndiv; i++)
+        for (int c = 0; c < 3; c++) {
+            std::array<int, 3> t = te[i];
+            t[c] += 1;
+            for (int k = 0; k < NB; k++)
+                if (be[c][k] == t) Cm[(size_t)i * nu + c * NB + k] += t[c];
+        }
+    // normal equations 2 A^T A u + C^T lambda = 2 A^T S b, C u = S_d b; the
+    // first nu rows of A are the identity and each face row of S one unit
+    const int nk = nu + ncon;
+    std::vector<double> K((size_t)nk * nk, 0.0), rhs((size_t)nk * NIN, 0.0);
+    for (int i = 0; i < nu; i++) {
+        K[(size_t)i * nk + i] = 2.0;
+        for (int j = 0; j < NIN; j++) rhs[(size_t)i * NIN + j] = 2.0 * Sb[(size_t)i * NIN + j];
+    }
+    for (int k = nu; k < nrow; k++) {
+        const double *a = &Am[(size_t)k * nu];
+        for (int i = 0; i < nu; i++) {
+            if (a[i] == 0.0) continue;
+            for (int j = 0; j < nu; j++) K[(size_t)i * nk + j] += 2.0 * a[i] * a[j];
+            rhs[(size_t)i * NIN + inF + (k - nu)] += 2.0 * a[i];
+        }
+    }
+    for (int i = 0; i < ncon; i++)
+        for (int j = 0; j < nu; j++) {
+            K[(size_t)(nu + i) * nk + j] = Cm[(size_t)i * nu + j];
+            K[(size_t)j * nk + nu + i] = Cm[(size_t)i * nu + j];
+        }
+    for (int i = 0; i < ncon; i++)
+        for (int j = 0; j < NIN; j++) rhs[(size_t)(nu + i) * NIN + j] = Sd[(size_t)i * NIN + j];
+    std::vector<int> piv;
+    if (!lu_factor(nk, K, piv)) return false;
+    std::vector<double> Gm((size_t)nu * NIN), col(nk);
+    for (int j = 0; j < NIN; j++) {
+        for (int i = 0; i < nk; i++) col[i] = rhs[(size_t)i * NIN + j];
+        lu_solve(nk, K, piv, col.data());
+        for (int i = 0; i < nu; i++) Gm[(size_t)i * NIN + j] = col[i];
+    }
+    for (int c = 0; c < 3; c++)
+        for (int i = 0; i < N; i++) {
+            double X[3];
+            for (int d = 0; d < 3; d++) X[d] = (nodex[3 * i + d] - cen[d]) / l0;
+            double *row = &Mb[(size_t)(c * N + i) * NIN];
+            for (int j = 0; j < NIN; j++) row[j] = 0.0;
+            for (int k = 0; k < NB; k++) {
+                const double bv = tb(be[c][k], X);
+                const double *g = &Gm[(size_t)(c * NB + k) * NIN];
+                for (int j = 0; j < NIN; j++) row[j] += bv * g[j];
+            }
+        }
+    for (int c = 0; c < 3; c++)
+        std::memcpy(&Mb[(size_t)(3 * N + c) * NIN], &Gm[(size_t)(c * NB) * NIN], sizeof(double) * NIN);
+    (void)NOUT;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -453,6 +694,12 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     for (int64_t t = 0; t < p->ntri; t++)
         column_face_geometry(p->ref, &p->tri[9 * t], p->q, &p->tfA[(size_t)t * QT * 3], &p->sfA[(size_t)t * 3 * QS * 3]);
     if (!mesh_edges(p->tri, p->edges)) { set_error("the triangles do not close into a sphere"); free_prism(p); return RG_ESINGULAR; }
+    {
+        int nc = 0;
+        for (int d = 1; d <= order - 1; d++) nc += (d + 1) * (d + 2) / 2;
+        p->nin = 3 * (nc + 1) + p->ref.Q + 5;
+        p->nout = 3 * N + 3;
+    }
     p->vol.assign(p->ntri, 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < p->ntri; t++) p->vol[t] = column_volume(p->ref, &p->tri[9 * t], p->q);
@@ -483,6 +730,9 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     G.QT = QT;
     G.QS = QS;
     G.nedges = (int64_t)p->edges.size() / 4;
+    G.nin = p->nin;
+    G.nout = p->nout;
+    G.Mb = nullptr;
     G.nfaces = p->ntri * (n_rad + 1) + G.nedges * n_rad;
     if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
         !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt) || !upload(p, p->ref.fidx, &G.fidx) ||
@@ -522,6 +772,8 @@ rg_status rg_prism_get_info(const rg_prism *p, rg_prism_info *info)
     info->n_face_points = p->ref.Q;
     info->n_edges = (int64_t)p->edges.size() / 4;
     info->n_faces = p->ntri * (p->n_rad + 1) + info->n_edges * p->n_rad;
+    info->n_divfree_in = p->nin;
+    info->n_divfree_out = p->nout;
     return RG_OK;
 }
 
@@ -542,6 +794,58 @@ rg_status rg_prism_volumes(const rg_prism *p, int64_t z0, int64_t nz, double *vo
         vol[i] = s * s * s * p->vol[z / p->n_rad];
     }
     return RG_OK;
+}
+
+static rg_status build_divfree_maps(rg_prism *p)
+{
+    if (!p->Mb.empty()) return RG_OK;
+    const int N = p->ref.N;
+    std::vector<double> Mb((size_t)p->ntri * p->nout * p->nin);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : bad)
+    for (int64_t t = 0; t < p->ntri; t++)
+        bad += !column_divfree_map(p->ref, &p->tri[9 * t], p->q, &p->hx[(size_t)t * N * 3],
+                                   &Mb[(size_t)t * p->nout * p->nin]);
+    if (bad) { set_error("singular divergence-free KKT system"); return RG_ESINGULAR; }
+    p->Mb.swap(Mb);
+    return RG_OK;
+}
+
+rg_status rg_prism_divfree_host(rg_prism *p, int64_t z0, int64_t nz, const double *Bin, double *Bout)
+{
+    if (!p || !Bin || !Bout) { set_error("null argument"); return RG_EINVAL; }
+    if (z0 < 0 || nz < 0 || z0 + nz > p->nz) { set_error("zone range outside the mesh"); return RG_EINVAL; }
+    rg_status st = build_divfree_maps(p);
+    if (st != RG_OK) return st;
+    for (int64_t i = 0; i < nz; i++) {
+        const double *M = &p->Mb[(size_t)((z0 + i) / p->n_rad) * p->nout * p->nin];
+        for (int o = 0; o < p->nout; o++) {
+            double acc = 0.0;
+            for (int j = 0; j < p->nin; j++) acc += M[(size_t)o * p->nin + j] * Bin[i * p->nin + j];
+            Bout[i * p->nout + o] = acc;
+        }
+    }
+    return RG_OK;
+}
+
+rg_status rg_prism_divfree(rg_prism *p, const double *Bin, double *Bout, void *stream)
+{
+    if (!p || !Bin || !Bout) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    if (!p->dev.Mb) {
+        rg_status st = build_divfree_maps(p);
+        if (st != RG_OK) return st;
+        // the device copy is transposed per column: [nin][nout]
+        std::vector<double> MT(p->Mb.size());
+        const size_t blk = (size_t)p->nout * p->nin;
+#pragma omp parallel for schedule(static)
+        for (int64_t t = 0; t < p->ntri; t++)
+            for (int o = 0; o < p->nout; o++)
+                for (int j = 0; j < p->nin; j++)
+                    MT[t * blk + (size_t)j * p->nout + o] = p->Mb[t * blk + (size_t)o * p->nin + j];
+        if (!upload(p, MT, &p->dev.Mb)) { set_error("device allocation of the divergence-free maps failed"); return RG_ENOMEM; }
+    }
+    return launch_prism_divfree(p->dev, Bin, Bout, stream);
 }
 
 rg_status rg_prism_update(const rg_prism *p, double dt, const double *U, const double *Phi, double *Uo, void *stream)

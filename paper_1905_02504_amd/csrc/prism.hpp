@@ -70,10 +70,14 @@ struct DevPrism {
     // update
     const double *vol;    // ntri: volume of the unit shell's zone (shell k: r_k^3 times it)
     const int *tedge;     // ntri x 3: edge id of each local edge, negated - 1 where t is the second triangle
+    // divergence-free B
+    int nin, nout;
+    const double *Mb;     // ntri x nin x nout: per column the transposed map (built on the first rg_prism_divfree call)
 };
 
 rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream);
 rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *tr, double *Phi, void *stream);
+rg_status launch_prism_divfree(const DevPrism &G, const double *Bin, double *Bout, void *stream);
 rg_status launch_prism_update(const DevPrism &G, double dt, const double *U, const double *Phi, double *Uo, void *stream);
 rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                                double *aF, void *stream);

@@ -1,6 +1,6 @@
-"""Parity of the library's prism-element predictor (rg_prism_predict) and its
-face traces (rg_prism_traces) with the oracle's full space-time Galerkin
-predictor and traces on the same inputs, zone by zone:
+"""Parity of the library's prism-element kernels (predictor, face traces, face
+fluxes, update and the divergence-free reconstruction of B) with the
+oracle's on the same inputs, zone by zone:
 small icosahedral meshes at orders 2-4 (every zone, ragged last workgroups),
 the fourth-order benchmark mesh (level 6, 128 shells) on sampled zones, a
 uniform state at full size, and the argument errors."""
@@ -193,6 +193,60 @@ def test_prism_predictor_without_sweeps_returns_the_initial_state():
     np.testing.assert_allclose(aF, F, rtol=0, atol=1e-13 * np.abs(F).max())
 
 
+def _to_lib_inputs(lib, order, Bin):
+    """oracle KKT inputs [z][nin] -> the library's [nin][z] (the face nodal
+    part in the library's face-point order)"""
+    j = _point_map(lib, order)
+    f0 = 3 * (len(P.taylor_indices(order)) + 1)
+    out = Bin.copy()
+    out[:, f0:f0 + len(j)] = Bin[:, f0 + j]
+    return np.ascontiguousarray(out.T)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("level,n_rad,cols", [(1, 3, None), (0, 70, [0, 7, 19])])
+def test_prism_divfree_matches_oracle(order, level, n_rad, cols):
+    """The divergence-free reconstruction of B (rg_prism_divfree, Section
+    IV.b on five faces) against the oracle's per-zone KKT solve on seeded
+    random inputs: every zone of level 1 x 3 shells (3 of 64 lanes live), and
+    every shell of three columns of level 0 x 70 (a full and a ragged run of
+    64 shells)."""
+    import paper_1905_02504_amd as R
+    print(f"[prism] divfree, order {order}, level {level} x {n_rad} shells", flush=True)
+    lib = R.PrismMesh(level, n_rad, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(level, n_rad, r_in=1.0, r_out=1.5, order=order)
+    Bin = np.random.default_rng(71 + order).normal(size=(lib.nz, lib.n_divfree_in))
+    out = lib.divfree(torch.from_numpy(_to_lib_inputs(lib, order, Bin)).cuda()).cpu().numpy()
+    zones = np.arange(lib.nz) if cols is None else np.concatenate([np.arange(c * n_rad, (c + 1) * n_rad) for c in cols])
+    want = om.divfree(zones, Bin[zones])
+    e = np.abs(out[:, zones].T - want).max() / np.abs(want).max()
+    print(f"[prism] divfree: {len(zones)} zones, max error {e:.2e} of the largest output", flush=True)
+    assert e < TOL
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_divfree_reproduces_linear_divergence_free_field(order):
+    """Inputs of a trace-free linear field B0 + G x (div B = 0, in the space
+    at every order) come back exactly at the nodes of every zone of level
+    1 x 3 shells, with the zone means at the centroids."""
+    import paper_1905_02504_amd as R
+    from tests.test_oracle_prism import divfree_inputs_linear
+    lib = R.PrismMesh(1, 3, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.5, order=order)
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(3, 3)); G -= np.eye(3) * np.trace(G) / 3
+    B0 = rng.normal(size=3)
+    zones = np.arange(lib.nz)
+    Bin = divfree_inputs_linear(om, zones, B0, G)
+    out = lib.divfree(torch.from_numpy(_to_lib_inputs(lib, order, Bin)).cuda()).cpu().numpy().T
+    x, _, _ = lib.geometry(0, lib.nz)
+    N = lib.N
+    got = out[:, :3 * N].reshape(lib.nz, 3, N).transpose(0, 2, 1)
+    np.testing.assert_allclose(got, B0[None, None] + x @ G.T, rtol=0, atol=1e-12)
+    cen, _ = om.frames(zones)
+    np.testing.assert_allclose(out[:, 3 * N:], B0[None] + cen @ G.T, rtol=0, atol=1e-12)
+
+
 def _fullsize():
     import paper_1905_02504_amd as R
     return R.PrismMesh(6, 128, 4, r_in=1.0, r_out=2.0)
@@ -269,6 +323,33 @@ def test_prism_predictor_fullsize_sampled_zones(release_device_memory):
     assert dev < 1e-12
 
 
+def test_prism_divfree_fullsize_sampled_zones(release_device_memory):
+    """The benchmark's launch of rg_prism_divfree: order 4, level 6 x 128
+    shells (10.5 M zones, 5.5 GB of column maps), seeded random inputs,
+    sampled zones against the oracle."""
+    print("[prism] full size divfree: order 4, level 6 x 128 shells, sampled zones", flush=True)
+    lib = _fullsize()
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    Bin = torch.randn((lib.n_divfree_in, lib.nz), generator=gen, device="cuda", dtype=torch.float64)
+    out = lib.divfree(Bin)
+    torch.cuda.synchronize()
+    om = P.OraclePrismMesh(6, 128, r_in=1.0, r_out=2.0, order=4)
+    zones = np.unique(np.concatenate([[0, 63, 64, 127, 128, lib.nz - 1],
+                                      np.random.default_rng(13).integers(0, lib.nz, 18)]))
+    zt = torch.from_numpy(zones).cuda()
+    Bl = Bin[:, zt].cpu().numpy()                    # library order [nin][z]
+    j = _point_map(lib, 4)
+    f0 = 3 * (len(P.taylor_indices(4)) + 1)
+    Bo = Bl.T.copy()
+    Bo[:, f0 + j] = Bl.T[:, f0:f0 + len(j)]          # back to the oracle's face-point order
+    want = om.divfree(zones, Bo)
+    e = np.abs(out[:, zt].cpu().numpy().T - want).max() / np.abs(want).max()
+    print(f"[prism] full size divfree: {len(zones)} sampled zones, max error {e:.2e}", flush=True)
+    del Bin, out
+    lib.close()
+    assert e < TOL
+
+
 def test_prism_predictor_argument_errors():
     import paper_1905_02504_amd as R
     from paper_1905_02504_amd import _native as N
@@ -286,3 +367,5 @@ def test_prism_predictor_argument_errors():
         N.rg_prism_face_fluxes(lib._h, 1.0, U.data_ptr(), U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_update(lib._h, -1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_divfree(lib._h, 0, U.data_ptr(), 0)

@@ -90,6 +90,7 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_prism_traces(const DevPrism &, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_face_flux(const DevPrism &, double, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_update(const DevPrism &, double, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_divfree(const DevPrism &, const double *, double *, void *) { return RG_ENOTSUP; }
     }
     // the prism element's host side: mesh, geometry and face-point queries
     static int run_prism(int order) {
@@ -111,6 +112,10 @@ LIB_DRIVER = textwrap.dedent(r"""
         std::vector<double> vol(info.n_zones);
         if (rc == RG_OK) rc = rg_prism_volumes(p, 0, info.n_zones, vol.data());
         if (rg_prism_update(p, 1e-3, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 15;
+        std::vector<double> bin(3 * info.n_divfree_in, 0.5), bout(3 * info.n_divfree_out);
+        if (rc == RG_OK) rc = rg_prism_divfree_host(p, info.n_zones - 3, 3, bin.data(), bout.data());
+        if (rg_prism_divfree_host(p, info.n_zones - 2, 3, bin.data(), bout.data()) != RG_EINVAL) rc = 16;
+        if (rg_prism_divfree(p, bin.data(), bout.data(), nullptr) != RG_EINVAL) rc = 17;
         if (rg_prism_geometry(p, info.n_zones - 4, 5, x.data(), J.data(), met.data()) != RG_EINVAL) rc = 11;
         if (rg_prism_predict(p, 5.0 / 3.0, 1e-3, order, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 12;
         rg_prism_free(p);
