@@ -609,7 +609,10 @@ __global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__
 // two wavefronts per SIMD holds both forms under 256 registers.  Face ids come
 // from a per-column table in LDS, so the per-lane choice of face costs no
 // branches: with a six-way select in registers the FP32 form took 14.4 ms,
-// with the table 10.9 ms (FP64 12.0 -> 11.8 ms)
+// with the table 10.9 ms (FP64 12.0 -> 11.8 ms).  The operands are loaded one
+// K step ahead with no load under a branch: FP64 11.8 -> 10.6 ms, FP32
+// 10.9 -> 9.9 ms (two tiles per wavefront with the same loads: 13.1 ms; at
+// fourth order three tiles hold 256 registers with a 24-byte spill)
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
 constexpr int BMAP_TILES = 3;
@@ -651,17 +654,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void bm
 #pragma unroll
         for (int m = 0; m < MT; m++) acc[t][m] = dbl4{0.0, 0.0, 0.0, 0.0};
     auto face_of = [&](int t, int lf) -> i64 { return s_fbase[lf] + ks[t]; };
-#pragma unroll 2
-    for (int s = 0; s < KT; s++) {
-        // B operands: input j = 4s + g of zone jz of each tile.  The inputs
-        // are the zone's WENO B coefficients (j < NA; the zone mean, a = 0,
-        // comes from U), the faces' limited nodal normal B (j < NQ) and the
-        // face averages.  s is uniform, so the kind of a K step is decided
-        // by scalar branches; only the steps that straddle two kinds take the
-        // per-lane choice.  Inactive zones (past the column's top) read a
-        // valid zone and enter as zeros.
+    // operands of K step s.  B: input j = 4s + g of zone jz of each tile.
+    // The inputs are the zone's WENO B coefficients (j < NA; the zone mean,
+    // a = 0, comes from U), the faces' limited nodal normal B (j < NQ) and
+    // the face averages.  s is uniform, so the kind of a K step is decided by
+    // scalar branches; only the steps that straddle two kinds take the
+    // per-lane choice.  Inactive zones (past the column's top) read a valid
+    // zone and enter as zeros.  A: rows of the map, the padding rows read in
+    // bounds and selected to zero, so that no load sits under a branch and
+    // the loads of the next step are in flight during this step's products.
+    auto load = [&](int s, double (&am)[MT], double (&b)[NT]) {
         const int j = 4 * s + g;
-        double b[NT];
         if (4 * s + 3 < NA) {
             const int comp = j / (T::NC + 1), a = j % (T::NC + 1);
             // does any lane group of this step take a zone mean from U?
@@ -705,10 +708,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void bm
 #pragma unroll
         for (int m = 0; m < MT; m++) {
             const int r = m * 16 + jz;
-            const double a = (m < MT - 1 || r < NOUT) ? mrow[r] : 0.0;
-#pragma unroll
-            for (int t = 0; t < NT; t++) acc[t][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t][m], 0, 0, 0);
+            const double v = mrow[r < NOUT ? r : NOUT - 1];
+            am[m] = r < NOUT ? v : 0.0;
         }
+    };
+    auto product = [&](const double (&am)[MT], const double (&b)[NT]) {
+#pragma unroll
+        for (int m = 0; m < MT; m++)
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[m], b[t], acc[t][m], 0, 0, 0);
+    };
+    double a0[MT], b0[NT], a1[MT], b1[NT];
+    load(0, a0, b0);
+#pragma unroll 1
+    for (int s = 0; s < KT; s += 2) {
+        if (s + 1 < KT) load(s + 1, a1, b1);
+        product(a0, b0);
+        if (s + 2 < KT) load(s + 2, a0, b0);
+        if (s + 1 < KT) product(a1, b1);
     }
 #pragma unroll
     for (int t = 0; t < NT; t++) {
