@@ -17,6 +17,19 @@ or links it).
   (a, b, c) with midpoints m_ab, m_bc, m_ca are 4t + (0: a m_ab m_ca,
   1: m_ab b m_bc, 2: m_ca m_bc c, 3: m_ab m_bc m_ca).  Zone z = t n_rad + k.
 - Zone geometry and the element predictor are in prism.c.
+- Constrained transport on the prisms (Section VI with the prism's edges):
+  the line integral of the electric field along every edge by Simpson's rule
+  (as on the hexahedra), from the four zones about an angular edge by the
+  four-state multidimensional HLL field of the hexahedral oracle (two zones
+  at the inner and outer radius: the 1-D HLL of their side face), and from
+  the five or six zones about a radial edge by the mean of the 1-D HLL
+  induction fluxes of the faces between consecutive zones (the three-zone
+  rule of the hexahedral oracle for any number of zones); the magnetic flux
+  through every face then changes by minus dt times the circulation of these
+  integrals around it (Stokes' theorem), so each zone's net outward flux is
+  unchanged.  Parity unpinned beyond what test_oracle_prism.py checks: the
+  identity for random circulations, exact Stokes for linear fields, the
+  uniform state, and the three-zone special case.
 """
 from __future__ import annotations
 
@@ -77,6 +90,62 @@ def refel(order):
     if rc:
         raise ValueError("prism reference element failed")
     return dict(N=N, M=M, tau=tau, wt=wt, nodes=nodes, exps=exps, coef=coef, D=D, Kd=Kd, Kd0=Kd0, Kt0=Kt0)
+
+
+_REFEL = {}
+
+S3 = np.sqrt(3.0)
+# reference triangle vertices (centred, unit edges), local vertex j <-> the
+# triangle's j-th mesh vertex
+TRI_V = np.array([[-0.5, -0.5 / S3], [0.5, -0.5 / S3], [0.0, 1.0 / S3]])
+# Simpson's rule on [0, 1]: the edge quadrature of the electric field
+SIMPSON_S = np.array([0.0, 0.5, 1.0])
+SIMPSON_W = np.array([1.0, 4.0, 1.0]) / 6.0
+IBX = 5
+
+
+def basis(order, pts):
+    """nodal basis values [P][N] and gradients [P][N][3] at reference points
+    pts[P][3] (psi_l = sum_k coef[k, l] xi^a eta^b zeta^c)"""
+    if order not in _REFEL:
+        _REFEL[order] = refel(order)
+    r = _REFEL[order]
+    e, coef = r["exps"], r["coef"]
+    pts = np.atleast_2d(pts)
+    def mono(p, d=None):
+        out = np.ones((len(pts), len(e)))
+        for k, ex in enumerate(e):
+            ex = list(ex)
+            fac = 1.0
+            if d is not None:
+                fac = ex[d]
+                ex[d] = max(ex[d] - 1, 0)
+            out[:, k] = fac * pts[:, 0] ** ex[0] * pts[:, 1] ** ex[1] * pts[:, 2] ** ex[2]
+        return out
+    val = mono(pts) @ coef
+    grad = np.stack([mono(pts, d) @ coef for d in range(3)], axis=2)
+    return val, grad
+
+
+def efield(F):
+    """electric field from the Cartesian fluxes F[..][3][8] of the induction
+    equation: E_x = F_z[B_y], E_y = F_x[B_z], E_z = F_y[B_x]"""
+    return np.stack([F[..., 2, IBX + 1], F[..., 0, IBX + 2], F[..., 1, IBX]], axis=-1)
+
+
+def emf_faces(U, F, n, t, gamma=5.0 / 3.0):
+    """edge field E . t from K zones about an edge: the mean over the faces
+    between consecutive zones (k -> k + 1 mod K, unit normals n[K][3] from
+    zone k toward zone k + 1) of -(t x n) . F_B, F_B the B rows of the 1-D HLL
+    flux of the two zones' states U[K][8] and Cartesian fluxes F[K][3][8]"""
+    K = len(U)
+    k2 = (np.arange(K) + 1) % K
+    Fs = np.zeros((K, 8))
+    _lib().rgo_prism_hll(K, np.ascontiguousarray(U), np.ascontiguousarray(U[k2]),
+                         np.ascontiguousarray(F.reshape(K, 24)), np.ascontiguousarray(F[k2].reshape(K, 24)),
+                         np.ascontiguousarray(n), gamma, Fs)
+    tn = np.cross(t[None, :], n)
+    return float(-(Fs[:, IBX:IBX + 3] * tn).sum(1).mean())
 
 
 def _unit(v):
@@ -284,6 +353,127 @@ class OraclePrismMesh:
                 put(t2 * nr + k, nrf + e * nr + k, -1.0)
         assert np.all(cnt == 5)
         return F, S
+
+    def vertex_rings(self):
+        """for every mesh vertex its (triangle, local vertex) pairs in
+        counter-clockwise order seen from outside, starting at its lowest
+        triangle (a triangle (v, a, b) is followed by the one with the
+        directed edge v -> b)"""
+        where, inc = {}, [[] for _ in range(len(self.vert))]
+        for t, tri in enumerate(self.tri):
+            for j in range(3):
+                where[(tri[j], tri[(j + 1) % 3])] = (t, j)
+                inc[tri[j]].append((t, j))
+        rings = []
+        for v in range(len(self.vert)):
+            ring = [min(inc[v])]
+            while True:
+                t, j = ring[-1]
+                nxt = where[(v, self.tri[t][(j + 2) % 3])]
+                if nxt == ring[0]:
+                    break
+                ring.append(nxt)
+            assert len(ring) == len(inc[v])
+            rings.append(ring)
+        return rings
+
+    def edge_emfs(self, aU, aF, gamma=5.0 / 3.0):
+        """line integrals of E along every edge from the predictor's time
+        averages aU[z][N][8], aF[z][N][3][8] (Section VI; see the module
+        notes).  Gam_ang[n_edges][n_rad + 1]: mesh edge e at radius r_kr, from
+        its first triangle's local vertex e1 to e1 + 1; Gam_rad[n_vert][n_rad]:
+        the radial edge at vertex v through shell k, outward."""
+        order, nr = self.order, self.n_rad
+        zones = np.arange(self.nz)
+        x, _, _ = self.geometry(zones)
+        cen, _ = self.frames(zones)
+        E = self.edges()
+
+        def at(z, xi):
+            """state, flux, position and d x / d xi of zone z at reference point xi"""
+            val, grad = basis(order, xi)
+            return (val[0] @ aU[z], np.einsum("l,ldv->dv", val[0], aF[z]), val[0] @ x[z],
+                    np.einsum("ld,lc->cd", grad[0], x[z]))
+
+        Gang = np.zeros((len(E), nr + 1))
+        for e, (t1, e1, t2, e2) in enumerate(E):
+            d1 = TRI_V[(e1 + 1) % 3] - TRI_V[e1]
+            d2 = TRI_V[(e2 + 1) % 3] - TRI_V[e2]
+            for kr in range(nr + 1):
+                G = 0.0
+                for s, w in zip(SIMPSON_S, SIMPSON_W):
+                    p1, p2 = TRI_V[e1] + s * d1, TRI_V[e2] + (1 - s) * d2
+                    # zones: below (zeta = +1/2) and above (zeta = -1/2) the radius
+                    side = []
+                    for k, zeta in ((kr - 1, 0.5), (kr, -0.5)):
+                        if 0 <= k < nr:
+                            side.append([at(t1 * nr + k, np.array([p1[0], p1[1], zeta])),
+                                         at(t2 * nr + k, np.array([p2[0], p2[1], zeta])), k])
+                    # position and tangent from the first triangle's zone
+                    (_, _, xp, jac), _, k0 = side[0][0], side[0][1], side[0][2]
+                    dx = jac[:, :2] @ d1
+                    dl = np.linalg.norm(dx)
+                    tt = dx / dl
+                    if len(side) == 2:
+                        (a_lo, b_lo, klo), (a_hi, b_hi, khi) = side
+                        # counter-clockwise about t: SW, SE, NE, NW with east = t1
+                        # (left of the edge seen from outside) and north = outward
+                        St = [b_lo, a_lo, a_hi, b_hi]
+                        zs = [t2 * nr + klo, t1 * nr + klo, t1 * nr + khi, t2 * nr + khi]
+                        Es = O.emf4(np.array([q[0] for q in St]), np.array([efield(q[1]) for q in St]),
+                                    cen[zs], tt, gamma)
+                    else:
+                        a, b, _ = side[0]
+                        rh = xp / np.linalg.norm(xp)
+                        n = np.cross(tt, rh)
+                        n /= np.linalg.norm(n)
+                        Es = emf_faces(np.array([a[0], b[0]]), np.array([a[1], b[1]]),
+                                       np.array([n, -n]), tt, gamma)
+                    G += w * dl * Es
+                Gang[e, kr] = G
+        Grad = np.zeros((len(self.vert), nr))
+        for v, ring in enumerate(self.vertex_rings()):
+            vhat = self.vert[v] / np.linalg.norm(self.vert[v])
+            n = []
+            for t, j in ring:
+                b = self.vert[self.tri[t][(j + 2) % 3]]
+                c = np.cross(vhat, b)
+                n.append(c / np.linalg.norm(c))
+            n = np.array(n)
+            for k in range(nr):
+                G = 0.0
+                for s, w in zip(SIMPSON_S, SIMPSON_W):
+                    St = [at(t * nr + k, np.array([TRI_V[j][0], TRI_V[j][1], s - 0.5])) for t, j in ring]
+                    jac = St[0][3]
+                    dl = np.linalg.norm(jac[:, 2])
+                    Es = emf_faces(np.array([q[0] for q in St]), np.array([q[1] for q in St]), n,
+                                   jac[:, 2] / dl, gamma)
+                    G += w * dl * Es
+                Grad[v, k] = G
+        return Gang, Grad
+
+    def ct_update(self, PhiB, Gang, Grad, dt):
+        """magnetic fluxes PhiB[n_faces] through the faces (numbered and
+        directed as in face_fluxes) after dt of constrained transport: minus dt
+        times the circulation of the edge integrals around each face, taken
+        counter-clockwise about the face's direction"""
+        nr, nrf = self.n_rad, self.ntri * (self.n_rad + 1)
+        E = self.edges()
+        tedge = {}
+        for e, (t1, e1, t2, e2) in enumerate(E):
+            tedge[(t1, e1)] = (e, 1.0)
+            tedge[(t2, e2)] = (e, -1.0)
+        out = np.array(PhiB, dtype=np.float64, copy=True)
+        for t in range(self.ntri):
+            for kf in range(nr + 1):
+                circ = sum(sg * Gang[e, kf] for e, sg in (tedge[(t, j)] for j in range(3)))
+                out[t * (nr + 1) + kf] -= dt * circ
+        for e, (t1, e1, t2, e2) in enumerate(E):
+            A, B = self.tri[t1][e1], self.tri[t1][(e1 + 1) % 3]
+            for k in range(nr):
+                circ = Gang[e, k] + Grad[B, k] - Gang[e, k + 1] - Grad[A, k]
+                out[nrf + e * nr + k] -= dt * circ
+        return out
 
     def update(self, U, Phi, dt):
         """finite-volume update of the zone averages U[nz][8] (Section VI):

@@ -6,7 +6,9 @@ import numpy as np
 import pytest
 
 import tests.golden_io as G
+from oracle import oracle as O
 from oracle import prism as P
+from oracle.prism import IBX
 
 S3 = math.sqrt(3.0)
 
@@ -500,3 +502,114 @@ def test_divfree_reconstruction_reproduces_linear_divergence_free_fields(order):
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
     cen, _ = m.frames(zones)
     np.testing.assert_allclose(out[:, 3 * N:], B0[None] + cen @ G.T, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- constrained transport on the prisms
+
+_EPS = np.zeros((3, 3, 3))
+_EPS[0, 1, 2] = _EPS[1, 2, 0] = _EPS[2, 0, 1] = 1.0
+_EPS[0, 2, 1] = _EPS[2, 1, 0] = _EPS[1, 0, 2] = -1.0
+_U0 = np.array([1.0, 0.3, -0.2, 0.1, 2.0, 0.4, 0.2, -0.3])
+
+
+def test_vertex_rings_are_counter_clockwise_cycles():
+    """Every vertex of level 2 has valence 5 (the 12 icosahedron vertices)
+    or 6, consecutive triangles of its ring share the edge to the next
+    vertex, and the ring turns counter-clockwise seen from outside."""
+    m = P.OraclePrismMesh(2, 1, order=2)
+    rings = m.vertex_rings()
+    val = np.array([len(r) for r in rings])
+    assert (val == 5).sum() == 12 and (val == 6).sum() == len(rings) - 12
+    for v, ring in enumerate(rings):
+        cen = [m.vert[m.tri[t]].mean(0) for t, _ in ring]
+        for i, (t, j) in enumerate(ring):
+            t2, j2 = ring[(i + 1) % len(ring)]
+            assert m.tri[t][j] == v and m.tri[t2][j2] == v
+            assert m.tri[t][(j + 2) % 3] == m.tri[t2][(j2 + 1) % 3]
+            assert np.cross(cen[i] - m.vert[v], cen[(i + 1) % len(ring)] - m.vert[v]) @ m.vert[v] > 0
+
+
+def test_ct_keeps_every_zones_net_flux_for_any_edge_integrals():
+    """The circulations of the edge integrals around a zone's five faces
+    cancel (each edge bounds two of them, run both ways), so the update
+    keeps each zone's net outward magnetic flux for arbitrary integrals."""
+    m = P.OraclePrismMesh(1, 3, order=3)
+    F, S = m.zone_faces()
+    rng = np.random.default_rng(2)
+    nf = m.ntri * (m.n_rad + 1) + len(m.edges()) * m.n_rad
+    Phi0 = rng.normal(size=nf)
+    Phi1 = m.ct_update(Phi0, rng.normal(size=(len(m.edges()), m.n_rad + 1)),
+                       rng.normal(size=(len(m.vert), m.n_rad)), 0.3)
+    assert np.abs((S * (Phi1 - Phi0)[F]).sum(1)).max() < 1e-14
+    assert np.abs(Phi1 - Phi0).max() > 0.1
+
+
+def _uniform(m):
+    Fl = O.flux(_U0)
+    return (np.broadcast_to(_U0, (m.nz, m.N, 8)).copy(), np.broadcast_to(Fl, (m.nz, m.N, 3, 8)).copy(),
+            P.efield(Fl))
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_edge_integrals_of_a_uniform_state_are_exact(order):
+    """A uniform state has E = -v x B everywhere: every edge integral is
+    E . (chord) (Simpson's rule is exact for the tangent of a curve of degree
+    p - 1 <= 3), and no face flux changes."""
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    aU, aF, E = _uniform(m)
+    Ga, Gr = m.edge_emfs(aU, aF)
+    for e, (t1, e1, _, _) in enumerate(m.edges()):
+        chord = m.vert[m.tri[t1][(e1 + 1) % 3]] - m.vert[m.tri[t1][e1]]
+        np.testing.assert_allclose(Ga[e], m.radius * (E @ chord), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Gr, (m.vert @ E)[:, None] * np.diff(m.radius)[None, :], rtol=0, atol=1e-15)
+    nf = m.ntri * (m.n_rad + 1) + len(m.edges()) * m.n_rad
+    assert np.abs(m.ct_update(np.zeros(nf), Ga, Gr, 1.0)).max() < 1e-15
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_ct_obeys_stokes_for_a_linear_electric_field(order):
+    """With a uniform state and the induction fluxes of E = G x (continuous,
+    so every edge solver returns E . t), each face's flux changes by
+    -dt (curl E) . A_f, A_f the face's vector area from the face rules (exact
+    at orders 2 and 3, as Simpson's rule is for E . dx/ds on these edges)."""
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    aU, aF, _ = _uniform(m)
+    G = np.random.default_rng(3).normal(size=(3, 3))
+    x, _, _ = m.geometry(np.arange(m.nz))
+    Ex = x @ G.T
+    for d in range(3):
+        for i in range(3):
+            aF[:, :, d, IBX + i] = -np.einsum("k,znk->zn", _EPS[d, i], Ex)
+    Ga, Gr = m.edge_emfs(aU, aF)
+    dt = 0.25
+    E = m.edges()
+    nr, nrf = m.n_rad, m.ntri * (m.n_rad + 1)
+    dPhi = m.ct_update(np.zeros(nrf + len(E) * nr), Ga, Gr, dt)
+    _, dA = m.face_geometry(np.arange(m.nz))
+    _, _, nt, ns = P.face_points(order)
+    A = np.zeros((len(dPhi), 3))
+    for t in range(m.ntri):
+        for kf in range(nr + 1):
+            A[t * (nr + 1) + kf] = dA[t * nr + kf - 1, :nt].sum(0) if kf > 0 else -dA[t * nr, nt:2 * nt].sum(0)
+    for e, (t1, e1, _, _) in enumerate(E):
+        for k in range(nr):
+            A[nrf + e * nr + k] = dA[t1 * nr + k, 2 * nt + e1 * ns:2 * nt + (e1 + 1) * ns].sum(0)
+    curl = np.einsum("ijk,kj->i", _EPS, G)
+    np.testing.assert_allclose(dPhi, -dt * (A @ curl), rtol=0, atol=1e-14)
+
+
+def test_k_face_edge_rule_with_three_zones_is_the_hexahedral_corner_rule():
+    """The mean of the faces' 1-D HLL induction fluxes over K zones (the
+    radial edges' rule) is, for K = 3, the hexahedral oracle's three-zone
+    corner rule, computed there from the electric fields alone."""
+    rng = np.random.default_rng(4)
+    t = np.array([0.0, 0.0, 1.0])
+    ang = np.array([0.3, 2.2, 4.1])
+    n = np.stack([-np.sin(ang + 1.05), np.cos(ang + 1.05), 0 * ang], 1)
+    for _ in range(5):
+        U = np.array([_U0 * (1 + 0.3 * rng.uniform(-1, 1, 8)) for _ in range(3)])
+        U[:, 4] += 1.0
+        F = np.array([O.flux(u) for u in U])
+        a = P.emf_faces(U, F, n, t)
+        b = O.emf3(U, P.efield(F), n, t)
+        assert abs(a - b) < 1e-14 * max(1.0, abs(b))
