@@ -252,7 +252,6 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     ms_tr = e0.elapsed_time(e1) / reps
     tr_bytes = 8.0 * 32 * (lib.N + lib.Q)
     # HLL face fluxes of every radial and side face from the traces
-    del aF
     Phi = torch.empty((lib.n_faces, 8), dtype=torch.float64, device="cuda")
     lib.face_fluxes(tr, Phi=Phi)
     torch.cuda.synchronize()
@@ -280,6 +279,35 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     ms_up = e0.elapsed_time(e1) / reps
     up_bytes = 8.0 * (16 * lib.nz + 5 * 8 * lib.nz)
     del U, U1
+    # constrained transport: the predictor's averages at the edge points,
+    # the edge integrals of E, then the face magnetic fluxes
+    er = lib.edge_traces(aU, aF)
+    Ga, Gr = lib.edge_emfs(er)
+    PhiB = torch.zeros(lib.n_faces, dtype=torch.float64, device="cuda")
+    PhiB1 = lib.ct(PhiB, Ga, Gr, 2e-3)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        lib.edge_traces(aU, aF, er)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_etr = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        lib.edge_emfs(er, Gang=Ga, Grad=Gr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_emf = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        lib.ct(PhiB, Ga, Gr, 2e-3, out=PhiB1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_ct = e0.elapsed_time(e1) / reps
+    if not (torch.isfinite(Ga).all() and torch.isfinite(Gr).all() and torch.isfinite(PhiB1).all()):
+        raise RuntimeError("non-finite prism edge fields")
+    n_aedges, n_redges = Ga.numel(), Gr.numel()
+    del er, Ga, Gr, PhiB, PhiB1
     # divergence-free reconstruction of B: one column map per column applied
     # to every shell (the first call builds and uploads the maps, untimed)
     nin, nout = lib.n_divfree_in, lib.n_divfree_out
@@ -301,8 +329,8 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     df_flops = 2.0 * nin * nout
     del Bin, Bout
     flops, nbytes = lib.work()
-    nz, lib_q = lib.nz, lib.Q
-    del aU, tr, Phi
+    nz, lib_q, lib_n = lib.nz, lib.Q, lib.N
+    del aU, aF, tr, Phi
     lib.close()
     torch.cuda.empty_cache()
     tf = flops * nz / (ms * 1e-3) / 1e12
@@ -315,6 +343,9 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
             "face_fluxes": {"ms": ms_ff, "faces": n_faces, "face_updates_per_s": n_faces / (ms_ff * 1e-3),
                             "hbm_gbs": ff_bytes / (ms_ff * 1e-3) / 1e9},
             "update": {"ms": ms_up, "hbm_gbs": up_bytes / (ms_up * 1e-3) / 1e9},
+            "edge_traces": {"ms": ms_etr, "hbm_gbs": 8.0 * 17 * (lib_n + 27) * nz / (ms_etr * 1e-3) / 1e9},
+            "edge_emfs": {"ms": ms_emf, "angular_edges": n_aedges, "radial_edges": n_redges},
+            "ct": {"ms": ms_ct},
             "divfree": {"ms": ms_df, "inputs": nin, "outputs": nout, "bytes_per_zone": df_bytes,
                         "flops_per_zone": df_flops, "hbm_gbs": df_bytes * nz / (ms_df * 1e-3) / 1e9,
                         "tflops": df_flops * nz / (ms_df * 1e-3) / 1e12, "map_build_s": t_maps},
@@ -607,7 +638,9 @@ def main():
             f"{prism['roofline']['achieved']:.1f} TFLOP/s ({100 * prism['roofline']['frac']:.1f} % of FP64 peak); "
             f"face traces {prism['traces']['ms']:.2f} ms ({prism['traces']['hbm_gbs']:.0f} GB/s), "
             f"face fluxes {prism['face_fluxes']['ms']:.2f} ms ({prism['face_fluxes']['hbm_gbs']:.0f} GB/s), "
-            f"update {prism['update']['ms']:.2f} ms, divergence-free B {prism['divfree']['ms']:.2f} ms "
+            f"update {prism['update']['ms']:.2f} ms, edge traces {prism['edge_traces']['ms']:.2f} ms, "
+            f"edge fields {prism['edge_emfs']['ms']:.2f} ms, "
+            f"CT {prism['ct']['ms']:.2f} ms, divergence-free B {prism['divfree']['ms']:.2f} ms "
             f"({prism['divfree']['hbm_gbs']:.0f} GB/s, {prism['divfree']['tflops']:.1f} TFLOP/s; maps built in "
             f"{prism['divfree']['map_build_s']:.1f} s)")
     out = {

@@ -419,6 +419,7 @@ typedef struct {
     int64_t n_faces;        /* n_tri (n_rad + 1) + n_edges n_rad     */
     int32_t n_divfree_in;   /* inputs of rg_prism_divfree per zone   */
     int32_t n_divfree_out;  /* outputs: 3 n_nodes + 3                */
+    int64_t n_vertices;     /* mesh vertices: n_tri / 2 + 2          */
 } rg_prism_info;
 
 /* Builds the mesh and, on the current device, the geometry of every column
@@ -480,6 +481,44 @@ rg_status rg_prism_edges(const rg_prism *prism, int32_t *edges);
  * device, caller-owned.  Asynchronous on stream.  RG_EINVAL for null
  * pointers, gamma <= 1 or a host-only mesh. */
 rg_status rg_prism_face_fluxes(const rg_prism *prism, double gamma, const double *tr, double *Phi, void *stream);
+
+/* Constrained transport on the prisms (Section VI with the prism's edges).
+ * rg_prism_edge_traces: the state (8 values) and the induction fluxes
+ * F_d[B_i] (9 values, d major) of every zone at the 27 Simpson points of its
+ * edges, from the predictor's time averages avgU double[8][n_zones][n_nodes]
+ * and avgF double[3][8][n_zones][n_nodes] (rg_prism_predict's outputs):
+ * er double[17][27][n_zones]; point (side * 3 + j) * 3 + p lies on the
+ * triangle's edge j (vertex j to j + 1) at zeta = +1/2 (side 0) or -1/2
+ * (side 1), point 18 + 3 j + p on the radial edge through vertex j, p = 0, 1,
+ * 2 at the start, middle and end.
+ * rg_prism_edge_emfs: the line integral of the electric field along every
+ * edge from those records, by Simpson's rule along the edge.  At a point of
+ * an angular edge (mesh edge e at radius r_k) the four zones about it give
+ * the four-state multidimensional HLL field (as on the hexahedra; east = the
+ * edge's first triangle, north = outward, frame from the zone centroids); at
+ * r_in and r_out the two zones give the 1-D HLL field of their side face.
+ * At a point of a radial edge (vertex v, shell k) the five or six zones
+ * about it give the mean over the side faces between consecutive zones of
+ * their 1-D HLL induction flux (the three-zone rule of the hexahedra for any
+ * number).  Gang double[n_edges][n_rad + 1] runs from the start to the end
+ * of edge e as its first triangle lists them (rg_prism_edges), Grad
+ * double[n_vertices][n_rad] outward (vertices as rg_prism_vertices lists
+ * them).
+ * rg_prism_ct: the magnetic fluxes PhiB double[n_faces] through the faces
+ * (numbered and directed as in rg_prism_face_fluxes) after dt: PhiBo = PhiB
+ * - dt times the circulation of the edge integrals around each face,
+ * counter-clockwise about its direction (Stokes' theorem), which keeps every
+ * zone's net outward flux.
+ * Device, caller-owned, asynchronous on stream; RG_EINVAL for null
+ * pointers, a host-only mesh, gamma <= 1 or dt < 0. */
+rg_status rg_prism_edge_traces(const rg_prism *prism, const double *avgU, const double *avgF, double *er, void *stream);
+rg_status rg_prism_edge_emfs(const rg_prism *prism, double gamma, const double *er, double *Gang, double *Grad,
+                             void *stream);
+rg_status rg_prism_ct(const rg_prism *prism, double dt, const double *Gang, const double *Grad, const double *PhiB,
+                      double *PhiBo, void *stream);
+/* Host copy of the unit-sphere mesh vertices, double[n_vertices][3], numbered
+ * in first encounter over (triangle, local vertex). */
+rg_status rg_prism_vertices(const rg_prism *prism, double *xyz);
 
 /* Divergence-free reconstruction of B (Section IV.b) on the prism's five
  * faces: per zone the constrained least squares of eqs. (4.3), (4.6), (4.9)

@@ -264,6 +264,7 @@ class PrismMesh:
         self.Q = info["n_face_points"]
         self.n_edges, self.n_faces = info["n_edges"], info["n_faces"]
         self.n_divfree_in, self.n_divfree_out = info["n_divfree_in"], info["n_divfree_out"]
+        self.n_vertices = info["n_vertices"]
         self.level, self.n_rad, self.order = level, n_rad, order
 
     def close(self):
@@ -348,6 +349,42 @@ class PrismMesh:
         out = np.zeros((len(Bin), self.n_divfree_out))
         N.rg_prism_divfree_host(self._h, z0, len(Bin), _ptr(Bin), _ptr(out))
         return out
+
+    def edge_traces(self, aU, aF, er=None):
+        """state and induction fluxes at the 27 edge points of every zone,
+        [17][27][nz], from predict()'s outputs"""
+        import torch
+        assert aU.is_contiguous() and aF.is_contiguous()
+        if er is None:
+            er = torch.empty((17, 27, self.nz), dtype=torch.float64, device=aU.device)
+        N.rg_prism_edge_traces(self._h, _ptr(aU), _ptr(aF), _ptr(er), _stream())
+        return er
+
+    def edge_emfs(self, er, gamma=5.0 / 3.0, Gang=None, Grad=None):
+        """line integrals of E along the angular edges [n_edges][n_rad + 1]
+        and the radial edges [n_vertices][n_rad] from edge_traces()"""
+        import torch
+        assert er.is_contiguous()
+        if Gang is None:
+            Gang = torch.empty((self.n_edges, self.n_rad + 1), dtype=torch.float64, device=er.device)
+        if Grad is None:
+            Grad = torch.empty((self.n_vertices, self.n_rad), dtype=torch.float64, device=er.device)
+        N.rg_prism_edge_emfs(self._h, gamma, _ptr(er), _ptr(Gang), _ptr(Grad), _stream())
+        return Gang, Grad
+
+    def ct(self, PhiB, Gang, Grad, dt, out=None):
+        """face magnetic fluxes [n_faces] after dt of constrained transport"""
+        import torch
+        if out is None:
+            out = torch.empty_like(PhiB)
+        N.rg_prism_ct(self._h, dt, _ptr(Gang), _ptr(Grad), _ptr(PhiB), _ptr(out), _stream())
+        return out
+
+    def vertices(self):
+        """unit-sphere mesh vertices [n_vertices][3] in the library's numbering"""
+        xyz = np.zeros((self.n_vertices, 3))
+        N.rg_prism_vertices(self._h, _ptr(xyz))
+        return xyz
 
     def work(self, n_picard=None):
         """-> (flops per zone, algorithmic HBM bytes per zone) of predict()"""

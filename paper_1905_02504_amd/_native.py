@@ -42,7 +42,7 @@ class rg_prism_info(C.Structure):
     _fields_ = [("n_zones", C.c_int64), ("n_tri", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
                 ("order", C.c_int32), ("level", C.c_int32), ("n_rad", C.c_int32), ("n_face_points", C.c_int32),
                 ("n_edges", C.c_int64), ("n_faces", C.c_int64), ("n_divfree_in", C.c_int32),
-                ("n_divfree_out", C.c_int32)]
+                ("n_divfree_out", C.c_int32), ("n_vertices", C.c_int64)]
 
 
 class RGError(RuntimeError):
@@ -118,9 +118,14 @@ def lib():
         L.rg_prism_update.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp]
         L.rg_prism_divfree.argtypes = [_vp, _vp, _vp, _vp]
         L.rg_prism_divfree_host.argtypes = [_vp, C.c_int64, C.c_int64, _vp, _vp]
+        L.rg_prism_edge_traces.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.rg_prism_edge_emfs.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp]
+        L.rg_prism_ct.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, _vp]
+        L.rg_prism_vertices.argtypes = [_vp, _vp]
         for name in ("rg_prism_build", "rg_prism_build_host", "rg_prism_get_info", "rg_prism_work",
                      "rg_prism_face_points", "rg_prism_traces", "rg_prism_edges", "rg_prism_face_fluxes",
-                     "rg_prism_volumes", "rg_prism_update", "rg_prism_divfree", "rg_prism_divfree_host", "rg_prism_triangles", "rg_prism_geometry",
+                     "rg_prism_volumes", "rg_prism_update", "rg_prism_divfree", "rg_prism_divfree_host",
+                     "rg_prism_edge_traces", "rg_prism_edge_emfs", "rg_prism_ct", "rg_prism_vertices", "rg_prism_triangles", "rg_prism_geometry",
                      "rg_prism_predict"):
             getattr(L, name).restype = C.c_int
         for name in ("rg_profile_begin", "rg_profile_end", "rg_mesh_build", "rg_mesh_get_info", "rg_geom_precompute", "rg_geom_precompute_host",
@@ -375,3 +380,21 @@ def rg_prism_divfree(prism, Bin_ptr, Bout_ptr, stream):
 
 def rg_prism_divfree_host(prism, z0, nz, Bin_ptr, Bout_ptr):
     check(lib().rg_prism_divfree_host(prism, z0, nz, _vp(Bin_ptr), _vp(Bout_ptr)), "rg_prism_divfree_host")
+
+
+def rg_prism_edge_traces(prism, aU_ptr, aF_ptr, er_ptr, stream):
+    check(lib().rg_prism_edge_traces(prism, _vp(aU_ptr), _vp(aF_ptr), _vp(er_ptr), _vp(stream)), "rg_prism_edge_traces")
+
+
+def rg_prism_edge_emfs(prism, gamma, er_ptr, Gang_ptr, Grad_ptr, stream):
+    check(lib().rg_prism_edge_emfs(prism, gamma, _vp(er_ptr), _vp(Gang_ptr), _vp(Grad_ptr), _vp(stream)),
+          "rg_prism_edge_emfs")
+
+
+def rg_prism_ct(prism, dt, Gang_ptr, Grad_ptr, PhiB_ptr, PhiBo_ptr, stream):
+    check(lib().rg_prism_ct(prism, dt, _vp(Gang_ptr), _vp(Grad_ptr), _vp(PhiB_ptr), _vp(PhiBo_ptr), _vp(stream)),
+          "rg_prism_ct")
+
+
+def rg_prism_vertices(prism, xyz_ptr):
+    check(lib().rg_prism_vertices(prism, _vp(xyz_ptr)), "rg_prism_vertices")

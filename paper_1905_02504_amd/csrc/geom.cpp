@@ -708,7 +708,7 @@ bool column_pass2(const Mesh &m, const RefEl &r, const std::vector<ColData> &col
 }
 
 // ---------------------------------------------------------------- pass 3: angular edges, vertices
-static void symmetric_frame(const double *u0, const double *w0, const double *t, double *e1, double *e2)
+void symmetric_frame(const double *u0, const double *w0, const double *t, double *e1, double *e2)
 {
     double u[3], w[3], b[3], bp[3];
     double pu = dot(u0, t), pw = dot(w0, t);

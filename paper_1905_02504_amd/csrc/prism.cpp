@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <string>
 
@@ -68,6 +69,9 @@ struct rg_prism {
     std::vector<double> Mb;           // ntri x nout x nin, built on first use
     int nin = 0, nout = 0;
     std::vector<double> tfA, sfA;     // ntri x QT x 3; ntri x 3 x QS x 3
+    // constrained transport
+    std::vector<int> tri_v, edge_ab, ring_off, ring_tj, eidx;
+    std::vector<double> vxyz, ring_n, aeg, eval;
     std::vector<void *> allocations;
     bool device = false;
     DevPrism dev{};
@@ -468,6 +472,179 @@ bool mesh_edges(const std::vector<double> &tri, std::vector<int> &edges)
     return (int64_t)edges.size() / 4 == 3 * nt / 2;
 }
 
+// Constrained-transport tables of the mesh.  Vertices are numbered in first
+// encounter over (triangle, local vertex), matched bit for bit (shared
+// vertices come out of the same sums); each vertex's ring lists its
+// triangles counter-clockwise seen from outside, starting at the lowest, a
+// triangle (v, a, b) followed by the one holding the directed edge v -> b,
+// with the unit normal v x b / |v x b| of the side face between them (it
+// points from the ring's triangle to the next).  Per mesh edge and Simpson
+// point on the unit shell: the unit tangent along the edge's first
+// triangle, the frame of the four-state field from the two columns'
+// centroids (east = the first triangle, north = outward: the directions of
+// east minus west and north minus south do not depend on the radius), the
+// normal t x r of the side face out of the first triangle, and |dx/ds|.
+void zone_cubature(const TriSurface &ts, double q, std::vector<std::array<double, 4>> &cub, double &V, double *cen);
+
+bool ct_tables(rg_prism *p)
+{
+    const int64_t nt = p->ntri;
+    std::map<std::array<double, 3>, int> vid;
+    p->tri_v.assign((size_t)nt * 3, -1);
+    p->vxyz.clear();
+    for (int64_t t = 0; t < nt; t++)
+        for (int j = 0; j < 3; j++) {
+            std::array<double, 3> a = {p->tri[9 * t + 3 * j], p->tri[9 * t + 3 * j + 1], p->tri[9 * t + 3 * j + 2]};
+            auto it = vid.find(a);
+            if (it == vid.end()) {
+                it = vid.emplace(a, (int)(p->vxyz.size() / 3)).first;
+                p->vxyz.insert(p->vxyz.end(), a.begin(), a.end());
+            }
+            p->tri_v[3 * t + j] = it->second;
+        }
+    const int64_t nv = (int64_t)p->vxyz.size() / 3;
+    if (nv != nt / 2 + 2) return false;     // Euler: V = F / 2 + 2 for a closed triangulated sphere
+    std::unordered_map<int64_t, int> directed;   // (u, w) -> 3 t + (local index of u)
+    std::vector<int> first(nv, -1), count(nv, 0);
+    for (int64_t t = 0; t < nt; t++)
+        for (int j = 0; j < 3; j++) {
+            const int u = p->tri_v[3 * t + j], w = p->tri_v[3 * t + (j + 1) % 3];
+            directed[(int64_t)u * nv + w] = (int)(3 * t + j);
+            if (first[u] < 0) first[u] = (int)(3 * t + j);
+            count[u]++;
+        }
+    p->ring_off.assign(nv + 1, 0);
+    for (int64_t v = 0; v < nv; v++) p->ring_off[v + 1] = p->ring_off[v] + count[v];
+    p->ring_tj.assign(p->ring_off[nv], 0);
+    p->ring_n.assign((size_t)p->ring_off[nv] * 3, 0.0);
+    for (int64_t v = 0; v < nv; v++) {
+        int cur = first[v];
+        const double *vp = &p->vxyz[3 * v];
+        for (int m = 0; m < count[v]; m++) {
+            const int t = cur / 3, j = cur % 3;
+            const int b = p->tri_v[3 * (size_t)t + (j + 2) % 3];
+            p->ring_tj[p->ring_off[v] + m] = cur;
+            const double *bp = &p->vxyz[3 * (size_t)b];
+            double n[3] = {vp[1] * bp[2] - vp[2] * bp[1], vp[2] * bp[0] - vp[0] * bp[2], vp[0] * bp[1] - vp[1] * bp[0]};
+            unit(n);
+            std::memcpy(&p->ring_n[3 * (size_t)(p->ring_off[v] + m)], n, 24);
+            auto it = directed.find((int64_t)v * nv + b);
+            if (it == directed.end()) return false;
+            cur = it->second;
+        }
+        if (cur != first[v]) return false;        // the ring must close after its count
+    }
+    const int64_t ne = (int64_t)p->edges.size() / 4;
+    p->edge_ab.assign((size_t)ne * 2, 0);
+    for (int64_t e = 0; e < ne; e++) {
+        const int t1 = p->edges[4 * e], e1 = p->edges[4 * e + 1];
+        p->edge_ab[2 * e] = p->tri_v[3 * (size_t)t1 + e1];
+        p->edge_ab[2 * e + 1] = p->tri_v[3 * (size_t)t1 + (e1 + 1) % 3];
+    }
+    // unit-shell centroids of the columns
+    std::vector<double> cen((size_t)nt * 3);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; t++) {
+        const TriSurface ts(p->ref, &p->tri[9 * t]);
+        std::vector<std::array<double, 4>> cub;
+        double V;
+        zone_cubature(ts, p->q, cub, V, &cen[3 * t]);
+    }
+    const double s3 = std::sqrt(3.0);
+    const double TV[3][2] = {{-0.5, -0.5 / s3}, {0.5, -0.5 / s3}, {0.0, 1.0 / s3}};
+    const double SS[3] = {0.0, 0.5, 1.0};
+    p->aeg.assign((size_t)ne * 3 * 16, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; e++) {
+        const int t1 = p->edges[4 * e], e1 = p->edges[4 * e + 1], t2 = p->edges[4 * e + 2];
+        const TriSurface ts(p->ref, &p->tri[9 * (size_t)t1]);
+        const double dx = TV[(e1 + 1) % 3][0] - TV[e1][0], dy = TV[(e1 + 1) % 3][1] - TV[e1][1];
+        double u[3], w[3];
+        for (int i = 0; i < 3; i++) {
+            u[i] = cen[3 * (size_t)t1 + i] - cen[3 * (size_t)t2 + i];
+            w[i] = cen[3 * (size_t)t1 + i] + cen[3 * (size_t)t2 + i];
+        }
+        for (int pp = 0; pp < 3; pp++) {
+            const double xi[2] = {TV[e1][0] + SS[pp] * dx, TV[e1][1] + SS[pp] * dy};
+            double S[3], Sx[3], Sy[3], tg[3], rh[3], nb[3];
+            ts.eval(xi, S, Sx, Sy);
+            for (int i = 0; i < 3; i++) tg[i] = Sx[i] * dx + Sy[i] * dy;
+            const double dl = std::sqrt(tg[0] * tg[0] + tg[1] * tg[1] + tg[2] * tg[2]);
+            for (int i = 0; i < 3; i++) { tg[i] /= dl; rh[i] = S[i]; }
+            unit(rh);
+            nb[0] = tg[1] * rh[2] - tg[2] * rh[1];
+            nb[1] = tg[2] * rh[0] - tg[0] * rh[2];
+            nb[2] = tg[0] * rh[1] - tg[1] * rh[0];
+            unit(nb);
+            double *g = &p->aeg[((size_t)e * 3 + pp) * 16];
+            std::memcpy(g, tg, 24);
+            symmetric_frame(u, w, tg, g + 3, g + 6);
+            std::memcpy(g + 9, nb, 24);
+            g[12] = dl;
+        }
+    }
+    // basis values at the edge points
+    p->eidx.assign((size_t)EDGE_POINTS * EDGE_TERMS, 0);
+    p->eval.assign((size_t)EDGE_POINTS * EDGE_TERMS, 0.0);
+    for (int pt = 0; pt < EDGE_POINTS; pt++) {
+        double xi[3];
+        if (pt < 18) {
+            const int side = pt / 9, j = (pt / 3) % 3, pp = pt % 3;
+            xi[0] = TV[j][0] + SS[pp] * (TV[(j + 1) % 3][0] - TV[j][0]);
+            xi[1] = TV[j][1] + SS[pp] * (TV[(j + 1) % 3][1] - TV[j][1]);
+            xi[2] = side == 0 ? 0.5 : -0.5;
+        } else {
+            const int j = (pt - 18) / 3, pp = (pt - 18) % 3;
+            xi[0] = TV[j][0];
+            xi[1] = TV[j][1];
+            xi[2] = SS[pp] - 0.5;
+        }
+        int n = 0;
+        for (int l = 0; l < p->ref.N; l++) {
+            const double v = p->ref.psi(l, xi);
+            if (std::fabs(v) < 1e-13) continue;
+            if (n == EDGE_TERMS) return false;
+            p->eidx[(size_t)pt * EDGE_TERMS + n] = l;
+            p->eval[(size_t)pt * EDGE_TERMS + n] = v;
+            n++;
+        }
+    }
+    return true;
+}
+
+// cubature of the unit shell's zone over the column's triangle: Gauss (6
+// points) in zeta times the collapsed 6 x 6 Gauss rule on the triangle;
+// points (x, weight J) and the zone's volume and centroid
+void zone_cubature(const TriSurface &ts, double q, std::vector<std::array<double, 4>> &cub, double &V, double *cen)
+{
+    const int ng = 6;
+    double gx[8], gw[8];
+    gauss_legendre01(ng, gx, gw);
+    const double s3 = std::sqrt(3.0);
+    const double VA[2] = {-0.5, -0.5 / s3}, VB[2] = {0.5, -0.5 / s3}, VC[2] = {0.0, 1.0 / s3};
+    cub.clear();
+    V = 0.0;
+    cen[0] = cen[1] = cen[2] = 0.0;
+    for (int i = 0; i < ng; i++)
+        for (int j = 0; j < ng; j++) {
+            const double sv = gx[i], tv = (1.0 - sv) * gx[j];
+            const double xe[2] = {VA[0] + sv * (VB[0] - VA[0]) + tv * (VC[0] - VA[0]),
+                                  VA[1] + sv * (VB[1] - VA[1]) + tv * (VC[1] - VA[1])};
+            double S[3], Sx[3], Sy[3];
+            ts.eval(xe, S, Sx, Sy);
+            const double trip = S[0] * (Sx[1] * Sy[2] - Sx[2] * Sy[1]) + S[1] * (Sx[2] * Sy[0] - Sx[0] * Sy[2]) +
+                                S[2] * (Sx[0] * Sy[1] - Sx[1] * Sy[0]);
+            for (int k = 0; k < ng; k++) {
+                const double R = (1.0 - gx[k]) + gx[k] * q;
+                const double wJ = 2.0 * (s3 / 4.0) * (1.0 - sv) * gw[i] * gw[j] * gw[k] * R * R * (q - 1.0) * trip;
+                cub.push_back({R * S[0], R * S[1], R * S[2], wJ});
+                V += wJ;
+                for (int d = 0; d < 3; d++) cen[d] += wJ * R * S[d];
+            }
+        }
+    for (int d = 0; d < 3; d++) cen[d] /= V;
+}
+
 // Divergence-free reconstruction of B (Section IV.b with the prism's five
 // faces) as one linear map per column: the KKT system of the constrained
 // least squares is solved for every input at once, and the solution is
@@ -499,32 +676,11 @@ bool column_divfree_map(const PrismRef &r, const double *abc, double q, const do
     const int NB = (int)be[0].size(), nu = 3 * NB, ndiv = nc, ncon = ndiv + 5, nrow = nu + Q;
     const int NIN = 3 * (nc + 1) + Q + 5, NOUT = 3 * N + 3;
     const TriSurface ts(r, abc);
-    // zone cubature: Gauss in zeta times the collapsed rule on the triangle
-    const int ng = 6;
-    double gx[8], gw[8];
-    gauss_legendre01(ng, gx, gw);
+    std::vector<std::array<double, 4>> cub;
+    double V = 0.0, cen[3];
+    zone_cubature(ts, q, cub, V, cen);
     const double s3 = std::sqrt(3.0);
     const double VA[2] = {-0.5, -0.5 / s3}, VB[2] = {0.5, -0.5 / s3}, VC[2] = {0.0, 1.0 / s3};
-    std::vector<std::array<double, 4>> cub;
-    double V = 0.0, cen[3] = {0, 0, 0};
-    for (int i = 0; i < ng; i++)
-        for (int j = 0; j < ng; j++) {
-            const double sv = gx[i], tv = (1.0 - sv) * gx[j];
-            const double xe[2] = {VA[0] + sv * (VB[0] - VA[0]) + tv * (VC[0] - VA[0]),
-                                  VA[1] + sv * (VB[1] - VA[1]) + tv * (VC[1] - VA[1])};
-            double S[3], Sx[3], Sy[3];
-            ts.eval(xe, S, Sx, Sy);
-            const double trip = S[0] * (Sx[1] * Sy[2] - Sx[2] * Sy[1]) + S[1] * (Sx[2] * Sy[0] - Sx[0] * Sy[2]) +
-                                S[2] * (Sx[0] * Sy[1] - Sx[1] * Sy[0]);
-            for (int k = 0; k < ng; k++) {
-                const double R = (1.0 - gx[k]) + gx[k] * q;
-                const double wJ = 2.0 * (s3 / 4.0) * (1.0 - sv) * gw[i] * gw[j] * gw[k] * R * R * (q - 1.0) * trip;
-                cub.push_back({R * S[0], R * S[1], R * S[2], wJ});
-                V += wJ;
-                for (int d = 0; d < 3; d++) cen[d] += wJ * R * S[d];
-            }
-        }
-    for (int d = 0; d < 3; d++) cen[d] /= V;
     const double l0 = std::cbrt(V);
     auto mono = [](const std::array<int, 3> &e, const double *X) {
         double v = 1.0;
@@ -720,6 +876,7 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
         }
         if (p->mirror[i] < 0) { set_error("side-face rule is not symmetric along the edge"); free_prism(p); return RG_ESINGULAR; }
     }
+    if (!ct_tables(p)) { set_error("edge and vertex tables of the prism mesh could not be built"); free_prism(p); return RG_ESINGULAR; }
     p->device = device;
     if (!device) { *out = p; return RG_OK; }
     std::vector<double> rinv(n_rad);
@@ -734,11 +891,15 @@ static rg_status prism_build(int32_t level, int32_t n_rad, double r_in, double r
     G.nout = p->nout;
     G.Mb = nullptr;
     G.nfaces = p->ntri * (n_rad + 1) + G.nedges * n_rad;
+    G.nvert = (int64_t)p->vxyz.size() / 3;
     if (!upload(p, p->hJ, &G.J) || !upload(p, p->hM, &G.met) || !upload(p, rinv, &G.rinv) ||
         !upload(p, p->ref.R, &G.R) || !upload(p, p->ref.wt, &G.wt) || !upload(p, p->ref.fidx, &G.fidx) ||
         !upload(p, p->ref.fval, &G.fval) || !upload(p, p->edges, &G.edges) || !upload(p, p->mirror, &G.mirror) ||
         !upload(p, p->tfA, &G.tfA) || !upload(p, p->sfA, &G.sfA) || !upload(p, p->radius, &G.radius) ||
-        !upload(p, p->vol, &G.vol) || !upload(p, p->tedge, &G.tedge)) {
+        !upload(p, p->vol, &G.vol) || !upload(p, p->tedge, &G.tedge) || !upload(p, p->eidx, &G.eidx) ||
+        !upload(p, p->eval, &G.eval) || !upload(p, p->aeg, &G.aeg) || !upload(p, p->edge_ab, &G.edge_ab) ||
+        !upload(p, p->vxyz, &G.vxyz) || !upload(p, p->ring_off, &G.ring_off) || !upload(p, p->ring_tj, &G.ring_tj) ||
+        !upload(p, p->ring_n, &G.ring_n)) {
         set_error("device allocation or upload of the prism geometry failed");
         free_prism(p);
         return RG_ENOMEM;
@@ -774,6 +935,7 @@ rg_status rg_prism_get_info(const rg_prism *p, rg_prism_info *info)
     info->n_faces = p->ntri * (p->n_rad + 1) + info->n_edges * p->n_rad;
     info->n_divfree_in = p->nin;
     info->n_divfree_out = p->nout;
+    info->n_vertices = (int64_t)p->vxyz.size() / 3;
     return RG_OK;
 }
 
@@ -782,6 +944,38 @@ rg_status rg_prism_edges(const rg_prism *p, int32_t *edges)
     if (!p || !edges) { set_error("null argument"); return RG_EINVAL; }
     std::memcpy(edges, p->edges.data(), p->edges.size() * sizeof(int));
     return RG_OK;
+}
+
+rg_status rg_prism_vertices(const rg_prism *p, double *xyz)
+{
+    if (!p || !xyz) { set_error("null argument"); return RG_EINVAL; }
+    std::memcpy(xyz, p->vxyz.data(), p->vxyz.size() * sizeof(double));
+    return RG_OK;
+}
+
+rg_status rg_prism_edge_traces(const rg_prism *p, const double *avgU, const double *avgF, double *er, void *stream)
+{
+    if (!p || !avgU || !avgF || !er) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    return launch_prism_edge_traces(p->dev, avgU, avgF, er, stream);
+}
+
+rg_status rg_prism_edge_emfs(const rg_prism *p, double gamma, const double *er, double *Gang, double *Grad,
+                             void *stream)
+{
+    if (!p || !er || !Gang || !Grad) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    if (!(gamma > 1.0)) { set_error("gamma must exceed 1"); return RG_EINVAL; }
+    return launch_prism_edge_emfs(p->dev, gamma, er, Gang, Grad, stream);
+}
+
+rg_status rg_prism_ct(const rg_prism *p, double dt, const double *Gang, const double *Grad, const double *PhiB,
+                      double *PhiBo, void *stream)
+{
+    if (!p || !Gang || !Grad || !PhiB || !PhiBo) { set_error("null argument"); return RG_EINVAL; }
+    if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    if (!(dt >= 0.0)) { set_error("dt must be non-negative"); return RG_EINVAL; }
+    return launch_prism_ct(p->dev, dt, Gang, Grad, PhiB, PhiBo, stream);
 }
 
 rg_status rg_prism_volumes(const rg_prism *p, int64_t z0, int64_t nz, double *vol)

@@ -605,6 +605,249 @@ rg_status launch_prism_divfree(const DevPrism &G, const double *Bin, double *Bou
     return RG_OK;
 }
 
+// ---------------------------------------------------------------- constrained transport
+// Edge traces: per zone the state and the induction fluxes F_d[B_i] at the
+// 27 edge points (EDGE_POINTS), er double[17][27][nz] (value, point, zone;
+// zones fastest, so that the edge kernels' lanes, consecutive shells, read
+// consecutive records).  One lane per zone: for each of the 17 values the
+// lane loads its zone's N nodal values (the wavefront's loads cover
+// contiguous memory) into its own LDS row, then sums the at most
+// EDGE_TERMS non-zero basis values of each point's nodes from there.
+constexpr int ETR_LANES = 128;
+constexpr int ETR_VALUES = 17;
+
+template <int P>
+__global__ __launch_bounds__(ETR_LANES) void prism_edge_traces(DevPrism G, const double *__restrict__ aU,
+                                                               const double *__restrict__ aF,
+                                                               double *__restrict__ er)
+{
+    constexpr int N = P == 2 ? 6 : P == 3 ? 15 : 26;
+    __shared__ double s_row[ETR_LANES * (N + 1)];
+    const i64 z = (i64)xcd_block(blockIdx.x, gridDim.x) * ETR_LANES + threadIdx.x;
+    if (z >= G.nz) return;
+    double *row = s_row + threadIdx.x * (N + 1);
+    const i64 nz = G.nz;
+    for (int v = 0; v < ETR_VALUES; v++) {
+        const int fv = v - 8;
+        const double *src = v < 8 ? aU + ((i64)v * nz + z) * N
+                                  : aF + ((i64)((fv / 3) * 8 + 5 + fv % 3) * nz + z) * N;
+#pragma unroll
+        for (int l = 0; l < N; l++) row[l] = src[l];
+        for (int pt = 0; pt < EDGE_POINTS; pt++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int n = 0; n < EDGE_TERMS; n++)
+                acc += G.eval[pt * EDGE_TERMS + n] * row[G.eidx[pt * EDGE_TERMS + n]];
+            er[((i64)v * EDGE_POINTS + pt) * nz + z] = acc;
+        }
+    }
+}
+
+// state and induction fluxes of zone z at edge point pt from the records
+__device__ __forceinline__ void edge_trace(const DevPrism &G, const double *__restrict__ er, i64 z, int pt,
+                                           double (&U)[8], double (&FB)[3][3])
+{
+    const i64 nz = G.nz;
+#pragma unroll
+    for (int v = 0; v < 8; v++) U[v] = er[((i64)v * EDGE_POINTS + pt) * nz + z];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) FB[d][i] = er[((i64)(8 + 3 * d + i) * EDGE_POINTS + pt) * nz + z];
+}
+
+// E . t with E_x = F_z[B_y], E_y = F_x[B_z], E_z = F_y[B_x]
+__device__ __forceinline__ double edge_field(const double (&FB)[3][3], const double *t)
+{
+    return FB[2][1] * t[0] + FB[0][2] * t[1] + FB[1][0] * t[2];
+}
+
+// -(t x n) . F_B of the 1-D HLL flux between two zones along unit n (from a
+// to b): the field along t that the face between them carries
+__device__ __forceinline__ double face_field(const double (&Ua)[8], const double (&Fa)[3][3], const double (&Ub)[8],
+                                             const double (&Fb)[3][3], const double *n, const double *t, double gam)
+{
+    double FL[8], FR[8], Fs[8];
+#pragma unroll
+    for (int v = 0; v < 5; v++) FL[v] = FR[v] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        FL[5 + i] = n[0] * Fa[0][i] + n[1] * Fa[1][i] + n[2] * Fa[2][i];
+        FR[5 + i] = n[0] * Fb[0][i] + n[1] * Fb[1][i] + n[2] * Fb[2][i];
+    }
+    dev_hll<double>(Ua, Ub, FL, FR, n, gam, Fs);
+    const double tn[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
+    return -(Fs[5] * tn[0] + Fs[6] * tn[1] + Fs[7] * tn[2]);
+}
+
+// angular edges: one lane per (mesh edge, radius level), the levels of an
+// edge in consecutive lanes
+__global__ __launch_bounds__(256) void prism_emf_ang(DevPrism G, double gam, const double *__restrict__ er,
+                                                     double *__restrict__ Gang)
+{
+    const i64 i = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int nr1 = G.n_rad + 1;
+    if (i >= G.nedges * nr1) return;
+    const i64 e = i / nr1;
+    const int kr = (int)(i % nr1);
+    const int t1 = G.edges[4 * e], e1 = G.edges[4 * e + 1], t2 = G.edges[4 * e + 2], e2 = G.edges[4 * e + 3];
+    const double r = G.radius[kr];
+    const double w3[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    double gam_sum = 0.0;
+    for (int pp = 0; pp < 3; pp++) {
+        const double *g = G.aeg + (e * 3 + pp) * 16;
+        double Es;
+        if (kr > 0 && kr < G.n_rad) {
+            // slots counter-clockwise about t: SW (t2 below), SE (t1 below),
+            // NE (t1 above), NW (t2 above); the zone below sees the edge on
+            // its top face (zeta = +1/2), the zone above on its bottom face;
+            // the second triangle runs the edge the other way
+            double U[4][8], Et[4], FB[3][3];
+            edge_trace(G, er, (i64)t2 * G.n_rad + kr - 1, (0 * 3 + e2) * 3 + 2 - pp, U[0], FB);
+            Et[0] = edge_field(FB, g);
+            edge_trace(G, er, (i64)t1 * G.n_rad + kr - 1, (0 * 3 + e1) * 3 + pp, U[1], FB);
+            Et[1] = edge_field(FB, g);
+            edge_trace(G, er, (i64)t1 * G.n_rad + kr, (1 * 3 + e1) * 3 + pp, U[2], FB);
+            Et[2] = edge_field(FB, g);
+            edge_trace(G, er, (i64)t2 * G.n_rad + kr, (1 * 3 + e2) * 3 + 2 - pp, U[3], FB);
+            Et[3] = edge_field(FB, g);
+            Es = emf4<double>(U, Et, g + 3, gam);
+        } else {
+            // the one shell at r_in or r_out: the side face's 1-D HLL field
+            const int k = kr > 0 ? kr - 1 : kr, side = kr > 0 ? 0 : 1;
+            double Ua[8], Ub[8], Fa[3][3], Fb[3][3];
+            edge_trace(G, er, (i64)t1 * G.n_rad + k, (side * 3 + e1) * 3 + pp, Ua, Fa);
+            edge_trace(G, er, (i64)t2 * G.n_rad + k, (side * 3 + e2) * 3 + 2 - pp, Ub, Fb);
+            Es = face_field(Ua, Fa, Ub, Fb, g + 9, g, gam);
+        }
+        gam_sum += w3[pp] * (g[12] * r) * Es;
+    }
+    Gang[i] = gam_sum;
+}
+
+// radial edges: one lane per (vertex, shell); the ring's zones are traced in
+// turn and each face between consecutive ones contributes its 1-D HLL field
+__global__ __launch_bounds__(256) void prism_emf_rad(DevPrism G, double gam, const double *__restrict__ er,
+                                                     double *__restrict__ Grad)
+{
+    const i64 i = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (i >= G.nvert * G.n_rad) return;
+    const i64 v = i / G.n_rad;
+    const int k = (int)(i % G.n_rad);
+    const int r0 = G.ring_off[v], K = G.ring_off[v + 1] - r0;
+    const double t[3] = {G.vxyz[3 * v], G.vxyz[3 * v + 1], G.vxyz[3 * v + 2]};
+    const double dl = G.radius[k + 1] - G.radius[k];
+    const double w3[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    double gam_sum = 0.0;
+    for (int pp = 0; pp < 3; pp++) {
+        double U0[8], F0[3][3], Up[8], Fp[3][3], Uc[8], Fc[3][3];
+        double acc = 0.0;
+        for (int m = 0; m <= K; m++) {
+            if (m < K) {
+                const int tj = G.ring_tj[r0 + m];
+                edge_trace(G, er, (i64)(tj / 3) * G.n_rad + k, 18 + 3 * (tj % 3) + pp, Uc, Fc);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; q++) Uc[q] = U0[q];
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+#pragma unroll
+                    for (int q = 0; q < 3; q++) Fc[d][q] = F0[d][q];
+            }
+            if (m == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) U0[q] = Uc[q];
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+#pragma unroll
+                    for (int q = 0; q < 3; q++) F0[d][q] = Fc[d][q];
+            } else {
+                acc += face_field(Up, Fp, Uc, Fc, G.ring_n + 3 * (i64)(r0 + m - 1), t, gam);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) Up[q] = Uc[q];
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+#pragma unroll
+                for (int q = 0; q < 3; q++) Fp[d][q] = Fc[d][q];
+        }
+        gam_sum += w3[pp] * dl * (acc / K);
+    }
+    Grad[i] = gam_sum;
+}
+
+// face magnetic fluxes: minus dt times the circulation of the edge integrals
+// counter-clockwise about each face's direction (radial faces along +r,
+// side faces out of the edge's first triangle)
+__global__ __launch_bounds__(256) void prism_ct(DevPrism G, double dt, const double *__restrict__ Gang,
+                                                const double *__restrict__ Grad, const double *__restrict__ PhiB,
+                                                double *__restrict__ PhiBo)
+{
+    const i64 f = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (f >= G.nfaces) return;
+    const int nr = G.n_rad, nr1 = nr + 1;
+    const i64 nrf = G.ntri * nr1;
+    double circ;
+    if (f < nrf) {
+        const i64 t = f / nr1;
+        const int kf = (int)(f % nr1);
+        circ = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int te = G.tedge[3 * t + j];
+            const i64 e = te >= 0 ? te : -te - 1;
+            const double g = Gang[e * nr1 + kf];
+            circ += te >= 0 ? g : -g;
+        }
+    } else {
+        const i64 s = f - nrf, e = s / nr;
+        const int k = (int)(s % nr);
+        const i64 A = G.edge_ab[2 * e], B = G.edge_ab[2 * e + 1];
+        circ = Gang[e * nr1 + k] + Grad[B * nr + k] - Gang[e * nr1 + k + 1] - Grad[A * nr + k];
+    }
+    PhiBo[f] = PhiB[f] - dt * circ;
+}
+
+rg_status launch_prism_edge_traces(const DevPrism &G, const double *aU, const double *aF, double *er, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const i64 nb = (G.nz + ETR_LANES - 1) / ETR_LANES;
+    if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (nb == 0) return RG_OK;
+    switch (G.order) {
+    case 2: prism_edge_traces<2><<<(unsigned)nb, ETR_LANES, 0, st>>>(G, aU, aF, er); break;
+    case 3: prism_edge_traces<3><<<(unsigned)nb, ETR_LANES, 0, st>>>(G, aU, aF, er); break;
+    case 4: prism_edge_traces<4><<<(unsigned)nb, ETR_LANES, 0, st>>>(G, aU, aF, er); break;
+    default: set_error("order must be 2, 3 or 4"); return RG_EINVAL;
+    }
+    if (hipGetLastError() != hipSuccess) { set_error("prism edge trace launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
+rg_status launch_prism_edge_emfs(const DevPrism &G, double gamma, const double *er, double *Gang, double *Grad,
+                                 void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const i64 na = G.nedges * (G.n_rad + 1), nv = G.nvert * G.n_rad;
+    const i64 ba = (na + 255) / 256, bv = (nv + 255) / 256;
+    if (ba >= ((i64)1 << 31) || bv >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (ba > 0) prism_emf_ang<<<(unsigned)ba, 256, 0, st>>>(G, gamma, er, Gang);
+    if (bv > 0) prism_emf_rad<<<(unsigned)bv, 256, 0, st>>>(G, gamma, er, Grad);
+    if (hipGetLastError() != hipSuccess) { set_error("prism edge field launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
+rg_status launch_prism_ct(const DevPrism &G, double dt, const double *Gang, const double *Grad, const double *PhiB,
+                          double *PhiBo, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const i64 nb = (G.nfaces + 255) / 256;
+    if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
+    if (nb > 0) prism_ct<<<(unsigned)nb, 256, 0, st>>>(G, dt, Gang, Grad, PhiB, PhiBo);
+    if (hipGetLastError() != hipSuccess) { set_error("prism constrained-transport launch failed"); return RG_EDEVICE; }
+    return RG_OK;
+}
+
 rg_status launch_prism_update(const DevPrism &G, double dt, const double *U, const double *Phi, double *Uo, void *stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -73,11 +73,32 @@ struct DevPrism {
     // divergence-free B
     int nin, nout;
     const double *Mb;     // ntri x nin x nout: per column the transposed map (built on the first rg_prism_divfree call)
+    // constrained transport: edges and vertices
+    int64_t nvert;
+    const int *eidx;      // EDGE_POINTS x EDGE_TERMS: nodes whose basis functions do not vanish at each edge point
+    const double *eval;   // EDGE_POINTS x EDGE_TERMS: their values (padding: weight 0)
+    const double *aeg;    // nedges x 3 x 16 (unit shell): tangent, frame e1, e2, boundary normal, |dx/ds|
+    const int *edge_ab;   // nedges x 2: vertices at the start and end of each edge (its first triangle's order)
+    const double *vxyz;   // nvert x 3: unit-sphere vertices
+    const int *ring_off;  // nvert + 1
+    const int *ring_tj;   // per ring entry 3 t + j: triangle t with vertex j at the ring's vertex, counter-clockwise
+    const double *ring_n; // per ring entry: unit normal of the side face to the next triangle of the ring
 };
+
+// edge points of the element (Simpson's rule along each edge): angular edges
+// (side 0: zeta = +1/2, side 1: zeta = -1/2) x local edge j x point p at
+// (side * 3 + j) * 3 + p; radial edges at triangle vertex j: 18 + 3 j + p
+constexpr int EDGE_POINTS = 27;
+constexpr int EDGE_TERMS = 4;      // at most p nodes on an edge
 
 rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double *aF, double *tr, void *stream);
 rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *tr, double *Phi, void *stream);
 rg_status launch_prism_divfree(const DevPrism &G, const double *Bin, double *Bout, void *stream);
+rg_status launch_prism_edge_traces(const DevPrism &G, const double *aU, const double *aF, double *er, void *stream);
+rg_status launch_prism_edge_emfs(const DevPrism &G, double gamma, const double *er, double *Gang, double *Grad,
+                                 void *stream);
+rg_status launch_prism_ct(const DevPrism &G, double dt, const double *Gang, const double *Grad, const double *PhiB,
+                          double *PhiBo, void *stream);
 rg_status launch_prism_update(const DevPrism &G, double dt, const double *U, const double *Phi, double *Uo, void *stream);
 rg_status launch_prism_predict(const DevPrism &G, double dt, double gamma, int npic, const double *Ua, double *aU,
                                double *aF, void *stream);

@@ -37,6 +37,10 @@ struct HostGeom {
 void column_surface_nodes(const Mesh &m, int c, double *sn);
 // point at fraction t of the great-circle arc from unit vector a to b
 void arc_point(const double *a, const double *b, double t, double *o);
+// frame of the four-state edge field: u and w (east minus west, north minus
+// south) projected off the unit tangent t and normalised, their bisector b
+// and t x b turned by 45 degrees into e1 = (b - t x b)/sqrt 2, e2 = (b + t x b)/sqrt 2
+void symmetric_frame(const double *u0, const double *w0, const double *t, double *e1, double *e2);
 void zone_map(int mo, const double *sn, double r0, double r1, const double *xi, double *x, double *jac);
 int moment_index(int a, int b, int c);
 void column_pass1(const Mesh &m, const RefEl &r, int c, ColData &cd);

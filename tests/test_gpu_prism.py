@@ -369,3 +369,95 @@ def test_prism_predictor_argument_errors():
         N.rg_prism_update(lib._h, -1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_divfree(lib._h, 0, U.data_ptr(), 0)
+
+
+def _vertex_map(lib, om):
+    """library vertex i -> the oracle's vertex at the same coordinates"""
+    V = lib.vertices()
+    d = np.linalg.norm(V[:, None, :] - om.vert[None, :, :], axis=2)
+    j = d.argmin(1)
+    assert d.min(1).max() == 0.0 and len(set(j.tolist())) == len(j)
+    return j
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_prism_edge_emfs_and_ct_match_oracle(order):
+    """Edge integrals of E (rg_prism_edge_emfs: four-state field at angular
+    edges, two-zone field at r_in and r_out, the K-face mean at the five- and
+    six-zone radial edges) from the library's predictor, and the face flux
+    update (rg_prism_ct), against the oracle's chain on the same nodal
+    states, level 1 x 3 shells; every zone's net outward flux kept."""
+    import paper_1905_02504_amd as R
+    print(f"[prism] edge fields and CT, order {order}, level 1 x 3 shells", flush=True)
+    lib = R.PrismMesh(1, 3, order, r_in=1.0, r_out=1.5)
+    om = P.OraclePrismMesh(1, 3, r_in=1.0, r_out=1.5, order=order)
+    x, J, met = om.geometry(np.arange(om.nz))
+    Ua = smooth_state(x, np.random.default_rng(91 + order))
+    dt = 0.02
+    aU_o, aF_o = P.predict(order, J, met, Ua, dt, GAMMA)
+    Ga_o, Gr_o = om.edge_emfs(aU_o, aF_o, GAMMA)
+    aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), dt, GAMMA)
+    Ga, Gr = lib.edge_emfs(lib.edge_traces(aU, aF), GAMMA)
+    Ga, Gr = Ga.cpu().numpy(), Gr.cpu().numpy()
+    vm = _vertex_map(lib, om)
+    scale = max(np.abs(Ga_o).max(), np.abs(Gr_o).max())
+    ea, er = np.abs(Ga - Ga_o).max() / scale, np.abs(Gr - Gr_o[vm]).max() / scale
+    print(f"[prism] edge integrals: angular {ea:.2e}, radial {er:.2e} of the largest", flush=True)
+    assert ea < TOL and er < TOL
+    # constrained transport from random face fluxes
+    nf = lib.n_faces
+    Phi0 = np.random.default_rng(5).normal(size=nf)
+    want = om.ct_update(Phi0, Ga_o, Gr_o, dt)
+    got = lib.ct(torch.from_numpy(Phi0).cuda(), torch.from_numpy(Ga).cuda(), torch.from_numpy(Gr).cuda(), dt)
+    got = got.cpu().numpy()
+    ect = np.abs(got - want).max() / np.abs(want).max()
+    # the change alone (from zero fluxes): each zone's net outward flux stays zero
+    d = lib.ct(torch.zeros(nf, dtype=torch.float64, device="cuda"), torch.from_numpy(Ga).cuda(),
+               torch.from_numpy(Gr).cuda(), dt).cpu().numpy()
+    F, S = om.zone_faces()
+    div = np.abs((S * d[F]).sum(1)).max() / np.abs(d).max()
+    print(f"[prism] CT: {ect:.2e} of the largest flux; zone net flux change {div:.2e} of the largest change",
+          flush=True)
+    assert ect < TOL and div < 1e-14
+
+
+def test_prism_ct_fullsize_keeps_zone_fluxes(release_device_memory):
+    """The benchmark mesh (order 4, level 6 x 128 shells): edge integrals
+    from the predictor of a noisy state and one CT update from zero face
+    fluxes; every zone's net outward flux stays zero to round-off, and a
+    uniform state changes no face flux."""
+    print("[prism] full size edge fields and CT", flush=True)
+    lib = _fullsize()
+    gen = torch.Generator(device="cuda").manual_seed(21)
+    base = torch.tensor([1.0, 0.3, -0.2, 0.1, 2.0, 0.4, 0.2, -0.3], dtype=torch.float64, device="cuda")
+    Ua = base[:, None, None] * (1 + 0.05 * (2 * torch.rand((8, lib.nz, lib.N), generator=gen, device="cuda",
+                                                             dtype=torch.float64) - 1))
+    dt = 2e-3
+    aU, aF = lib.predict(Ua, dt, GAMMA)
+    er = lib.edge_traces(aU, aF)
+    Ga, Gr = lib.edge_emfs(er, GAMMA)
+    zero = torch.zeros(lib.n_faces, dtype=torch.float64, device="cuda")
+    dPhi = lib.ct(zero, Ga, Gr, dt)
+    torch.cuda.synchronize()
+    assert torch.isfinite(Ga).all() and torch.isfinite(Gr).all()
+    nr, nt = lib.n_rad, lib.ntri
+    nrf = nt * (nr + 1)
+    t = torch.arange(nt, device="cuda")[:, None] * (nr + 1) + torch.arange(nr, device="cuda")[None, :]
+    net = (dPhi[t + 1] - dPhi[t]).reshape(-1)           # zone t nr + k: top minus bottom
+    E = torch.from_numpy(lib.edges().astype(np.int64)).cuda()
+    ks = torch.arange(nr, device="cuda")
+    side = dPhi[nrf:].reshape(-1, nr)
+    net.index_add_(0, (E[:, 0:1] * nr + ks[None, :]).reshape(-1), side.reshape(-1))
+    net.index_add_(0, (E[:, 2:3] * nr + ks[None, :]).reshape(-1), -side.reshape(-1))
+    rel = float(net.abs().max() / dPhi.abs().max())
+    print(f"[prism] full size CT: zone net flux change {rel:.2e} of the largest face change", flush=True)
+    assert rel < 1e-13
+    Ua.copy_(base[:, None, None].expand_as(Ua))
+    aU, aF = lib.predict(Ua, dt, GAMMA, aU=aU, aF=aF)
+    Ga, Gr = lib.edge_emfs(lib.edge_traces(aU, aF, er), GAMMA, Ga, Gr)
+    dPhi2 = lib.ct(zero, Ga, Gr, dt)
+    uni = float(dPhi2.abs().max() / dPhi.abs().max())
+    print(f"[prism] full size CT, uniform state: largest face change {uni:.2e} of the noisy one", flush=True)
+    del Ua, aU, aF, er, Ga, Gr, dPhi, dPhi2, zero, net, side
+    lib.close()
+    assert uni < 1e-9

@@ -91,6 +91,9 @@ LIB_DRIVER = textwrap.dedent(r"""
     rg_status launch_prism_face_flux(const DevPrism &, double, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_update(const DevPrism &, double, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
     rg_status launch_prism_divfree(const DevPrism &, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_edge_traces(const DevPrism &, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_edge_emfs(const DevPrism &, double, const double *, double *, double *, void *) { return RG_ENOTSUP; }
+    rg_status launch_prism_ct(const DevPrism &, double, const double *, const double *, const double *, double *, void *) { return RG_ENOTSUP; }
     }
     // the prism element's host side: mesh, geometry and face-point queries
     static int run_prism(int order) {
@@ -116,6 +119,11 @@ LIB_DRIVER = textwrap.dedent(r"""
         if (rc == RG_OK) rc = rg_prism_divfree_host(p, info.n_zones - 3, 3, bin.data(), bout.data());
         if (rg_prism_divfree_host(p, info.n_zones - 2, 3, bin.data(), bout.data()) != RG_EINVAL) rc = 16;
         if (rg_prism_divfree(p, bin.data(), bout.data(), nullptr) != RG_EINVAL) rc = 17;
+        std::vector<double> vxyz(3 * info.n_vertices);
+        if (rc == RG_OK) rc = rg_prism_vertices(p, vxyz.data());
+        if (rg_prism_edge_traces(p, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 18;
+        if (rg_prism_edge_emfs(p, 5.0 / 3.0, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 20;
+        if (rg_prism_ct(p, 1e-3, x.data(), x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 19;
         if (rg_prism_geometry(p, info.n_zones - 4, 5, x.data(), J.data(), met.data()) != RG_EINVAL) rc = 11;
         if (rg_prism_predict(p, 5.0 / 3.0, 1e-3, order, x.data(), x.data(), x.data(), nullptr) != RG_EINVAL) rc = 12;
         rg_prism_free(p);
