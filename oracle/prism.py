@@ -27,9 +27,12 @@ or links it).
   rule of the hexahedral oracle for any number of zones); the magnetic flux
   through every face then changes by minus dt times the circulation of these
   integrals around it (Stokes' theorem), so each zone's net outward flux is
-  unchanged.  Parity unpinned beyond what test_oracle_prism.py checks: the
-  identity for random circulations, exact Stokes for linear fields, the
-  uniform state, and the three-zone special case.
+  unchanged.  Pinned (tests/test_oracle_prism.py): the zone identity for
+  arbitrary edge integrals, exact integrals and no change for a uniform
+  state, Stokes' theorem for linear fields against the faces' vector areas,
+  the three-zone case against the hexahedral rule, upwinding of the K-zone
+  rule in supersonic flow and its invariance under relabelling and rotation;
+  the four-state field is the hexahedral oracle's, pinned there.
 """
 from __future__ import annotations
 

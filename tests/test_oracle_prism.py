@@ -613,3 +613,59 @@ def test_k_face_edge_rule_with_three_zones_is_the_hexahedral_corner_rule():
         a = P.emf_faces(U, F, n, t)
         b = O.emf3(U, P.efield(F), n, t)
         assert abs(a - b) < 1e-14 * max(1.0, abs(b))
+
+
+def _ring_frame(K):
+    """K zones about the z axis counter-clockwise; the face between zone k
+    and k + 1 lies at the angle between them, its unit normal pointing from
+    k to k + 1 (the rotation direction about z)"""
+    ang = 2 * np.pi * (np.arange(K) + 0.5) / K
+    return np.stack([-np.sin(ang), np.cos(ang), 0 * ang], 1), np.array([0.0, 0.0, 1.0])
+
+
+def _mhd_state(rho, v, p, B, gam=5.0 / 3.0):
+    v, B = np.asarray(v, float), np.asarray(B, float)
+    return np.array([rho, *(rho * v), p / (gam - 1) + 0.5 * rho * v @ v + 0.5 * B @ B, *B])
+
+
+@pytest.mark.parametrize("K", [5, 6])
+@pytest.mark.parametrize("phi", [0.0, 40.0, 100.0, 250.0])
+def test_k_face_edge_rule_takes_the_upwind_fields_in_supersonic_flow(K, phi):
+    """Flow faster than every fast speed across every face of a five- or
+    six-zone edge: each face's HLL flux is its upwind zone's, so the edge
+    field is the mean over the faces of the upwind zones' E . t."""
+    n, t = _ring_frame(K)
+    d = np.array([np.cos(np.deg2rad(phi)), np.sin(np.deg2rad(phi)), 0.0])
+    if min(abs(n @ d)) < 0.2:
+        d = np.array([np.cos(np.deg2rad(phi + 11)), np.sin(np.deg2rad(phi + 11)), 0.0])
+    gen = np.random.default_rng(K * 1000 + int(phi))
+    U = np.array([_mhd_state(gen.uniform(0.7, 1.3), 80.0 * d + 0.2 * gen.normal(size=3), gen.uniform(0.5, 1.5),
+                             0.5 * gen.normal(size=3)) for _ in range(K)])
+    F = np.array([O.flux(u) for u in U])
+    Et = P.efield(F) @ t
+    up = [k if n[k] @ d > 0 else (k + 1) % K for k in range(K)]
+    want = np.mean(Et[up])
+    assert abs(P.emf_faces(U, F, n, t) - want) < 1e-13 * np.abs(Et).max()
+
+
+@pytest.mark.parametrize("K", [5, 6])
+def test_k_face_edge_rule_is_invariant_under_relabelling_and_rotation(K):
+    """The K-face mean does not depend on which zone of the ring comes first,
+    and rotating the states, normals and tangent together leaves it alone."""
+    n, t = _ring_frame(K)
+    gen = np.random.default_rng(K)
+    U = np.array([_mhd_state(gen.uniform(0.7, 1.3), gen.normal(size=3), gen.uniform(0.5, 1.5), gen.normal(size=3))
+                  for _ in range(K)])
+    F = np.array([O.flux(u) for u in U])
+    a = P.emf_faces(U, F, n, t)
+    for r in range(1, K):
+        assert abs(P.emf_faces(np.roll(U, -r, 0), np.roll(F, -r, 0), np.roll(n, -r, 0), t) - a) < 1e-14 * max(1, abs(a))
+    q, rr = np.linalg.qr(gen.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(rr))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    Ur = U.copy()
+    Ur[:, 1:4] = U[:, 1:4] @ q.T
+    Ur[:, 5:8] = U[:, 5:8] @ q.T
+    Fr = np.array([O.flux(u) for u in Ur])
+    assert abs(P.emf_faces(Ur, Fr, n @ q.T, q @ t) - a) < 1e-13 * max(1, abs(a))
