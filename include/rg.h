@@ -529,7 +529,8 @@ rg_status rg_prism_vertices(const rg_prism *prism, double *xyz);
  * <= p-1 and the degree-p ones containing its own coordinate.  The KKT system
  * is solved once per column for all inputs (the shells of a column are
  * scaled copies) and applied as a matrix: the first call builds and uploads
- * the maps (8 n_out n_in bytes per column, 5.5 GB at level 6, fourth order).
+ * the maps (8 n_out n_in bytes per column, 5.5 GB at level 6, fourth order;
+ * a lock makes concurrent first calls on one mesh safe).
  * Bin double[n_divfree_in][n_zones]: per component its zone mean and Taylor
  * coefficients of degree 1..p-1 (degree by degree, x exponent descending,
  * then y), the outward normal B at the Q face points (rg_prism_face_points

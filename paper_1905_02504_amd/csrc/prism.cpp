@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <new>
 #include <string>
@@ -68,6 +69,7 @@ struct rg_prism {
     std::vector<double> vol;          // ntri, unit shell
     std::vector<double> Mb;           // ntri x nout x nin, built on first use
     int nin = 0, nout = 0;
+    std::mutex mb_mutex;              // the first divergence-free call builds (and uploads) the maps
     std::vector<double> tfA, sfA;     // ntri x QT x 3; ntri x 3 x QS x 3
     // constrained transport
     std::vector<int> tri_v, edge_ab, ring_off, ring_tj, eidx;
@@ -1009,8 +1011,11 @@ rg_status rg_prism_divfree_host(rg_prism *p, int64_t z0, int64_t nz, const doubl
 {
     if (!p || !Bin || !Bout) { set_error("null argument"); return RG_EINVAL; }
     if (z0 < 0 || nz < 0 || z0 + nz > p->nz) { set_error("zone range outside the mesh"); return RG_EINVAL; }
-    rg_status st = build_divfree_maps(p);
-    if (st != RG_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(p->mb_mutex);
+        rg_status st = build_divfree_maps(p);
+        if (st != RG_OK) return st;
+    }
     for (int64_t i = 0; i < nz; i++) {
         const double *M = &p->Mb[(size_t)((z0 + i) / p->n_rad) * p->nout * p->nin];
         for (int o = 0; o < p->nout; o++) {
@@ -1026,6 +1031,7 @@ rg_status rg_prism_divfree(rg_prism *p, const double *Bin, double *Bout, void *s
 {
     if (!p || !Bin || !Bout) { set_error("null argument"); return RG_EINVAL; }
     if (!p->device) { set_error("host-only prism mesh (rg_prism_build_host) has no device geometry"); return RG_EINVAL; }
+    std::lock_guard<std::mutex> lock(p->mb_mutex);
     if (!p->dev.Mb) {
         rg_status st = build_divfree_maps(p);
         if (st != RG_OK) return st;
