@@ -241,7 +241,7 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     # face traces at the rules of Appendix A (HBM-bound: 32 N values read and
     # 32 Q written per zone)
     del Ua
-    tr = torch.empty((32, lib.nz, lib.Q), dtype=torch.float64, device="cuda")
+    tr = torch.empty((32, lib.Q, lib.nz), dtype=torch.float64, device="cuda")
     lib.traces(aU, aF, tr)
     torch.cuda.synchronize()
     e0.record(stream)

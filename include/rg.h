@@ -458,11 +458,11 @@ rg_status rg_prism_face_points(const rg_prism *prism, double *xi, double *w, int
                                int32_t *n_side_points);
 
 /* Traces of the predictor's time averages at the face points, the corrector's
- * quadrature inputs (Section VI): tr[k][z][q] = sum_l psi_l(xi_q) a_k[z][l]
+ * quadrature inputs (Section VI): tr[k][q][z] = sum_l psi_l(xi_q) a_k[z][l]
  * for the 32 values a = (avgU[0..8), avgF[0][0..8), avgF[1][0..8),
  * avgF[2][0..8)).  Device arrays as written by rg_prism_predict; tr is
- * double[32][n_zones][Q], caller-owned.  Asynchronous on stream.  RG_EINVAL
- * for null pointers or a host-only mesh. */
+ * double[32][Q][n_zones] (zones fastest), caller-owned.  Asynchronous on
+ * stream.  RG_EINVAL for null pointers or a host-only mesh. */
 rg_status rg_prism_traces(const rg_prism *prism, const double *avgU, const double *avgF, double *tr, void *stream);
 
 /* Mesh edges, edges[n_edges][4] = (t, k, t', k'): triangle t's local edge k

@@ -296,11 +296,11 @@ class PrismMesh:
         return xi, w, nt, ns
 
     def traces(self, aU, aF, tr=None):
-        """face-point traces [32][nz][Q] of predict()'s averages (float64 CUDA tensors)"""
+        """face-point traces [32][Q][nz] of predict()'s averages (float64 CUDA tensors)"""
         import torch
         assert aU.is_contiguous() and aF.is_contiguous()
         if tr is None:
-            tr = torch.empty((32, self.nz, self.Q), dtype=torch.float64, device=aU.device)
+            tr = torch.empty((32, self.Q, self.nz), dtype=torch.float64, device=aU.device)
         N.rg_prism_traces(self._h, _ptr(aU), _ptr(aF), _ptr(tr), _stream())
         return tr
 

@@ -276,52 +276,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         for (int v = 0; v < 8; v++) aF[((i64)(d * 8 + v) * G.nz + z) * N + i] = sF[d][v];
 }
 
-// Face traces: a 256-lane workgroup stages the 32 nodal averages of ZB zones
-// in LDS (coalesced: for each value the ZB zones' nodes are contiguous), then
-// lane (zone, face point) sums the at most TRACE_TERMS basis values of the
-// nodes on its face.  Bound by HBM: 32 N values read and 32 Q written per zone.
+// Face traces: tr double[32][Q][nz] (value, face point, zone; zones fastest,
+// so that the face-flux kernels' lanes, consecutive shells, read consecutive
+// records).  One lane per zone: for each of the 32 values the lane copies its
+// zone's N nodal averages (the wavefront's loads cover contiguous memory)
+// into its own LDS row and sums the at most TRACE_TERMS non-zero basis values
+// of each face point's nodes from there.  Bound by HBM: 32 N values read and
+// 32 Q written per zone.  (A 256-lane form that staged the averages of 256/Q
+// zones and gave each lane one (zone, point) wrote [32][nz][Q]: 40.5 ms at
+// fourth order on the benchmark mesh, and the face fluxes that read it
+// 32.5 ms.)
 template <int P>
 struct TraceLayout {
     static constexpr int N = PrismD<P>::N;
-    static constexpr int Q = P == 2 ? 15 : P == 3 ? 24 : 38;
-    static constexpr int ZB = 256 / Q;
+    static constexpr int QT = P == 2 ? 3 : P == 3 ? 6 : 10;
+    static constexpr int QS = P == 2 ? 3 : P == 3 ? 4 : 6;
+    static constexpr int Q = 2 * QT + 3 * QS;
 };
+constexpr int TR_LANES = 128;
 
 template <int P>
-__global__ __launch_bounds__(256) void prism_traces(DevPrism G, const double *__restrict__ aU,
-                                                    const double *__restrict__ aF, double *__restrict__ tr)
+__global__ __launch_bounds__(TR_LANES) void prism_traces(DevPrism G, const double *__restrict__ aU,
+                                                         const double *__restrict__ aF, double *__restrict__ tr)
 {
     using L = TraceLayout<P>;
-    constexpr int N = L::N, Q = L::Q, ZB = L::ZB;
-    __shared__ double s_v[ZB * 32 * N];
-    const int tid = threadIdx.x;
-    const i64 z0 = (i64)xcd_block(blockIdx.x, gridDim.x) * ZB;
-    const int nzb = (int)(G.nz - z0 < ZB ? G.nz - z0 : ZB);
-    for (int e = tid; e < 32 * ZB * N; e += 256) {
-        const int k = e / (ZB * N), rem = e - k * (ZB * N);
-        if (rem < nzb * N) {
-            const double *src = k < 8 ? aU + (i64)k * G.nz * N : aF + (i64)(k - 8) * G.nz * N;
-            s_v[k * ZB * N + rem] = src[z0 * N + rem];
+    constexpr int N = L::N, Q = L::Q;
+    __shared__ double s_row[TR_LANES * (N + 1)];
+    const i64 z = (i64)xcd_block(blockIdx.x, gridDim.x) * TR_LANES + threadIdx.x;
+    if (z >= G.nz) return;
+    double *row = s_row + threadIdx.x * (N + 1);
+    const i64 nz = G.nz;
+    for (int v = 0; v < 32; v++) {
+        const double *src = v < 8 ? aU + ((i64)v * nz + z) * N : aF + ((i64)(v - 8) * nz + z) * N;
+#pragma unroll
+        for (int l = 0; l < N; l++) row[l] = src[l];
+        for (int q = 0; q < Q; q++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < TRACE_TERMS; t++)
+                acc += G.fval[q * TRACE_TERMS + t] * row[G.fidx[q * TRACE_TERMS + t]];
+            tr[((i64)v * Q + q) * nz + z] = acc;
         }
-    }
-    __syncthreads();
-    const int zl = tid / Q, q = tid - zl * Q;
-    if (zl >= nzb) return;
-    int idx[TRACE_TERMS];
-    double w[TRACE_TERMS];
-#pragma unroll
-    for (int t = 0; t < TRACE_TERMS; t++) {
-        idx[t] = G.fidx[q * TRACE_TERMS + t];
-        w[t] = G.fval[q * TRACE_TERMS + t];
-    }
-    const i64 z = z0 + zl;
-#pragma unroll 4
-    for (int k = 0; k < 32; k++) {
-        const double *sv = s_v + k * ZB * N + zl * N;
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < TRACE_TERMS; t++) acc += w[t] * sv[idx[t]];
-        tr[((i64)k * G.nz + z) * Q + q] = acc;
     }
 }
 
@@ -330,10 +325,10 @@ static rg_status launch_traces(const DevPrism &G, const double *aU, const double
 {
     using L = TraceLayout<P>;
     if (G.Q != L::Q) { set_error("face point count differs from the kernel's"); return RG_EINVAL; }
-    const i64 nb = (G.nz + L::ZB - 1) / L::ZB;
+    const i64 nb = (G.nz + TR_LANES - 1) / TR_LANES;
     if (nb >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
     if (nb == 0) return RG_OK;
-    prism_traces<P><<<(unsigned)nb, 256, 0, st>>>(G, aU, aF, tr);
+    prism_traces<P><<<(unsigned)nb, TR_LANES, 0, st>>>(G, aU, aF, tr);
     if (hipGetLastError() != hipSuccess) { set_error("prism trace launch failed"); return RG_EDEVICE; }
     return RG_OK;
 }
@@ -349,88 +344,100 @@ rg_status launch_prism_traces(const DevPrism &G, const double *aU, const double 
     }
 }
 
-// Face fluxes: lane (face, point) reads both sides' traces at its point
-// (for one value, the lanes of a face and of neighbouring faces read adjacent
-// doubles), forms the normal fluxes along the point's area vector and the HLL
-// flux times |dA|; the face's points are then summed through LDS.  Radial
-// faces (NPT = triangle points) take the zone below (top face) and above
-// (bottom face) at the same (xi, eta); side faces (NPT = side points) pair
-// point i of the first triangle with the mirrored point of its neighbour,
-// which runs the edge the other way.  One launch per kind of face.
-template <int NPT, bool SIDE>
-__global__ __launch_bounds__(256) void prism_face_flux(DevPrism G, double gam, const double *__restrict__ tr,
-                                                       double *__restrict__ Phi)
+// Face fluxes: one lane per face, the faces of a column (radial) or of an
+// edge (side) in consecutive lanes, so that for every value and point the
+// lanes read consecutive records of the traces.  The lane sums over its
+// face's points |dA| times the HLL flux of the two sides' traces along the
+// point's area vector.  Radial faces take the zone below (top face) and above
+// (bottom face) at the same (xi, eta); side faces pair point i of the first
+// triangle with the mirrored point of its neighbour, which runs the edge the
+// other way.  One launch per kind of face.  (The lane-per-point form on the
+// [32][nz][Q] traces, its face's points summed in LDS, took 15.4 + 17.1 ms on
+// the benchmark mesh.)
+template <int NPT>
+__device__ __forceinline__ void face_point_flux(const double *__restrict__ tr, i64 nz, int Q, int ql, i64 zl, int qr,
+                                                i64 zr, const double *A, double scale, double gam, double (&Fsum)[8])
 {
-    constexpr int FPB = 256 / NPT;
-    __shared__ double s_acc[256 * 8];   // every lane writes its slot, active or not
-    const int tid = threadIdx.x, fl = tid / NPT, i = tid - fl * NPT;
-    const int nr = G.n_rad, Q = G.Q, QT = G.QT;
-    const i64 nrf = G.ntri * (nr + 1), ZQ = G.nz * (i64)Q;
-    const i64 nf = SIDE ? G.nedges * nr : nrf;
-    const i64 f = (i64)xcd_block(blockIdx.x, gridDim.x) * FPB + fl;
-    const bool active = fl < FPB && f < nf;
-    double Fs[8];
+    double n[3] = {scale * A[0], scale * A[1], scale * A[2]};
+    const double a = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]), ia = 1.0 / a;
+    n[0] *= ia; n[1] *= ia; n[2] *= ia;
+    const i64 sl = (i64)Q * nz;
+    const double *pl = tr + (i64)ql * nz + zl, *pr = tr + (i64)qr * nz + zr;
+    double UL[8], UR[8], FL[8], FR[8], Fs[8];
 #pragma unroll
-    for (int v = 0; v < 8; v++) Fs[v] = 0.0;
-    if (active) {
-        i64 pl, pr;
-        const double *A;
-        double scale;
-        if (!SIDE) {
-            const i64 t = f / (nr + 1);
-            const int kf = (int)(f - t * (nr + 1));
-            const i64 zl = t * nr + (kf > 0 ? kf - 1 : 0), zr = t * nr + (kf < nr ? kf : nr - 1);
-            pl = zl * Q + (kf > 0 ? 0 : QT) + i;        // top face of the zone below, else the bottom face
-            pr = zr * Q + (kf < nr ? QT : 0) + i;       // bottom face of the zone above, else the top face
-            scale = G.radius[kf] * G.radius[kf];
-            A = G.tfA + (t * NPT + i) * 3;
-        } else {
-            const i64 e = f / nr;
-            const int k = (int)(f - e * nr);
-            const int t1 = G.edges[4 * e], e1 = G.edges[4 * e + 1], t2 = G.edges[4 * e + 2], e2 = G.edges[4 * e + 3];
-            pl = ((i64)t1 * nr + k) * Q + 2 * QT + e1 * NPT + i;
-            pr = ((i64)t2 * nr + k) * Q + 2 * QT + e2 * NPT + G.mirror[i];
-            scale = G.radius[k] * G.radius[k];
-            A = G.sfA + (((i64)t1 * 3 + e1) * NPT + i) * 3;
-        }
-        double n[3] = {scale * A[0], scale * A[1], scale * A[2]};
-        const double a = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]), ia = 1.0 / a;
-        n[0] *= ia; n[1] *= ia; n[2] *= ia;
-        double UL[8], UR[8], FL[8], FR[8];
-#pragma unroll
-        for (int v = 0; v < 8; v++) {
-            UL[v] = tr[v * ZQ + pl];
-            UR[v] = tr[v * ZQ + pr];
-            FL[v] = n[0] * tr[(8 + v) * ZQ + pl] + n[1] * tr[(16 + v) * ZQ + pl] + n[2] * tr[(24 + v) * ZQ + pl];
-            FR[v] = n[0] * tr[(8 + v) * ZQ + pr] + n[1] * tr[(16 + v) * ZQ + pr] + n[2] * tr[(24 + v) * ZQ + pr];
-        }
-        dev_hll<double>(UL, UR, FL, FR, n, gam, Fs);
-#pragma unroll
-        for (int v = 0; v < 8; v++) Fs[v] *= a;
+    for (int v = 0; v < 8; v++) {
+        UL[v] = pl[v * sl];
+        UR[v] = pr[v * sl];
+        FL[v] = n[0] * pl[(8 + v) * sl] + n[1] * pl[(16 + v) * sl] + n[2] * pl[(24 + v) * sl];
+        FR[v] = n[0] * pr[(8 + v) * sl] + n[1] * pr[(16 + v) * sl] + n[2] * pr[(24 + v) * sl];
     }
+    dev_hll<double>(UL, UR, FL, FR, n, gam, Fs);
 #pragma unroll
-    for (int v = 0; v < 8; v++) s_acc[tid * 8 + v] = Fs[v];
-    __syncthreads();
-    if (active && i == 0) {
-#pragma unroll
-        for (int v = 0; v < 8; v++) {
-            double sum = 0.0;
-#pragma unroll
-            for (int j = 0; j < NPT; j++) sum += s_acc[(tid + j) * 8 + v];
-            Phi[((SIDE ? nrf : 0) + f) * 8 + v] = sum;
-        }
-    }
+    for (int v = 0; v < 8; v++) Fsum[v] += Fs[v] * a;
 }
 
-template <int QT, int QS>
+template <int P>
+__global__ __launch_bounds__(256) void prism_face_flux_radial(DevPrism G, double gam, const double *__restrict__ tr,
+                                                              double *__restrict__ Phi)
+{
+    using L = TraceLayout<P>;
+    constexpr int QT = L::QT, Q = L::Q;
+    const i64 f = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int nr = G.n_rad;
+    if (f >= G.ntri * (nr + 1)) return;
+    const i64 t = f / (nr + 1);
+    const int kf = (int)(f - t * (nr + 1));
+    // top face of the zone below, else the bottom face; bottom face of the
+    // zone above, else the top face
+    const i64 zl = t * nr + (kf > 0 ? kf - 1 : 0), zr = t * nr + (kf < nr ? kf : nr - 1);
+    const int ql = kf > 0 ? 0 : QT, qr = kf < nr ? QT : 0;
+    const double scale = G.radius[kf] * G.radius[kf];
+    double Fsum[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) Fsum[v] = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < QT; i++)
+        face_point_flux<QT>(tr, G.nz, Q, ql + i, zl, qr + i, zr, G.tfA + (t * QT + i) * 3, scale, gam, Fsum);
+#pragma unroll
+    for (int v = 0; v < 8; v++) Phi[f * 8 + v] = Fsum[v];
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void prism_face_flux_side(DevPrism G, double gam, const double *__restrict__ tr,
+                                                            double *__restrict__ Phi)
+{
+    using L = TraceLayout<P>;
+    constexpr int QT = L::QT, QS = L::QS, Q = L::Q;
+    const i64 f = (i64)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int nr = G.n_rad;
+    if (f >= G.nedges * nr) return;
+    const i64 e = f / nr;
+    const int k = (int)(f - e * nr);
+    const int t1 = G.edges[4 * e], e1 = G.edges[4 * e + 1], t2 = G.edges[4 * e + 2], e2 = G.edges[4 * e + 3];
+    const i64 zl = (i64)t1 * nr + k, zr = (i64)t2 * nr + k;
+    const double scale = G.radius[k] * G.radius[k];
+    double Fsum[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) Fsum[v] = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < QS; i++)
+        face_point_flux<QS>(tr, G.nz, Q, 2 * QT + e1 * QS + i, zl, 2 * QT + e2 * QS + G.mirror[i], zr,
+                            G.sfA + (((i64)t1 * 3 + e1) * QS + i) * 3, scale, gam, Fsum);
+    const i64 nrf = G.ntri * (nr + 1);
+#pragma unroll
+    for (int v = 0; v < 8; v++) Phi[(nrf + f) * 8 + v] = Fsum[v];
+}
+
+template <int P>
 static rg_status launch_fluxes(const DevPrism &G, double gamma, const double *tr, double *Phi, hipStream_t st)
 {
-    if (G.QT != QT || G.QS != QS) { set_error("face point counts differ from the kernel's"); return RG_EINVAL; }
+    using L = TraceLayout<P>;
+    if (G.QT != L::QT || G.QS != L::QS) { set_error("face point counts differ from the kernel's"); return RG_EINVAL; }
     const i64 nrf = G.ntri * (G.n_rad + 1), nsf = G.nedges * G.n_rad;
-    const i64 br = (nrf + 256 / QT - 1) / (256 / QT), bs = (nsf + 256 / QS - 1) / (256 / QS);
+    const i64 br = (nrf + 255) / 256, bs = (nsf + 255) / 256;
     if (br >= ((i64)1 << 31) || bs >= ((i64)1 << 31)) { set_error("prism mesh too large for one launch"); return RG_ENOTSUP; }
-    if (br > 0) prism_face_flux<QT, false><<<(unsigned)br, 256, 0, st>>>(G, gamma, tr, Phi);
-    if (bs > 0) prism_face_flux<QS, true><<<(unsigned)bs, 256, 0, st>>>(G, gamma, tr, Phi);
+    if (br > 0) prism_face_flux_radial<P><<<(unsigned)br, 256, 0, st>>>(G, gamma, tr, Phi);
+    if (bs > 0) prism_face_flux_side<P><<<(unsigned)bs, 256, 0, st>>>(G, gamma, tr, Phi);
     if (hipGetLastError() != hipSuccess) { set_error("prism face flux launch failed"); return RG_EDEVICE; }
     return RG_OK;
 }
@@ -439,9 +446,9 @@ rg_status launch_prism_face_flux(const DevPrism &G, double gamma, const double *
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (G.order) {
-    case 2: return launch_fluxes<3, 3>(G, gamma, tr, Phi, st);
-    case 3: return launch_fluxes<6, 4>(G, gamma, tr, Phi, st);
-    case 4: return launch_fluxes<10, 6>(G, gamma, tr, Phi, st);
+    case 2: return launch_fluxes<2>(G, gamma, tr, Phi, st);
+    case 3: return launch_fluxes<3>(G, gamma, tr, Phi, st);
+    case 4: return launch_fluxes<4>(G, gamma, tr, Phi, st);
     default: set_error("prism order must be 2, 3 or 4"); return RG_ENOTSUP;
     }
 }

@@ -90,7 +90,7 @@ def test_prism_traces_match_oracle(order):
     aU_o, aF_o = P.predict(order, J, met, Ua, 0.02, GAMMA)
     tr_o = P.traces(order, aU_o, aF_o)                           # [z][q][32]
     aU, aF = lib.predict(torch.from_numpy(np.ascontiguousarray(Ua.transpose(2, 0, 1))).cuda(), 0.02, GAMMA)
-    tr = lib.traces(aU, aF).cpu().numpy()                        # [32][z][q]
+    tr = lib.traces(aU, aF).cpu().numpy().transpose(0, 2, 1)     # [32][q][z] -> [32][z][q]
     j = _point_map(lib, order)
     e = rel_by_var(tr, tr_o[:, j, :].transpose(2, 0, 1), 0)
     print(f"[prism] traces: max rel error per value {e.max():.2e}", flush=True)
@@ -293,7 +293,7 @@ def test_prism_predictor_fullsize_sampled_zones(release_device_memory):
     tr = lib.traces(aU, aF)
     tr_o = P.traces(4, aU_o, aF_o)
     j = _point_map(lib, 4)
-    eT = rel_by_var(tr[:, zt].cpu().numpy(), tr_o[:, j, :].transpose(2, 0, 1), 0)
+    eT = rel_by_var(tr[:, :, zt].cpu().numpy().transpose(0, 2, 1), tr_o[:, j, :].transpose(2, 0, 1), 0)
     print(f"[prism] sampled traces: {eT.max():.2e}", flush=True)
     assert eT.max() < TOL
     # face fluxes and the update of the whole mesh: conservation up to the
