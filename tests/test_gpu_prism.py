@@ -369,6 +369,16 @@ def test_prism_predictor_argument_errors():
         N.rg_prism_update(lib._h, -1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
     with pytest.raises(N.RGError, match="RG_EINVAL"):
         N.rg_prism_divfree(lib._h, 0, U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_edge_traces(lib._h, U.data_ptr(), 0, U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_edge_emfs(lib._h, 1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_edge_emfs(lib._h, 5 / 3, U.data_ptr(), 0, U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_ct(lib._h, -1.0, U.data_ptr(), U.data_ptr(), U.data_ptr(), U.data_ptr(), 0)
+    with pytest.raises(N.RGError, match="RG_EINVAL"):
+        N.rg_prism_ct(lib._h, 0.1, U.data_ptr(), U.data_ptr(), 0, U.data_ptr(), 0)
 
 
 def _vertex_map(lib, om):
