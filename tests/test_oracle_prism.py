@@ -669,3 +669,130 @@ def test_k_face_edge_rule_is_invariant_under_relabelling_and_rotation(K):
     Ur[:, 5:8] = U[:, 5:8] @ q.T
     Fr = np.array([O.flux(u) for u in Ur])
     assert abs(P.emf_faces(Ur, Fr, n @ q.T, q @ t) - a) < 1e-13 * max(1, abs(a))
+
+
+# ---- polynomial fields for the divergence-free pin (dict: exponent triple -> coefficient)
+
+def _pmul(p, q):
+    out = {}
+    for e1, c1 in p.items():
+        for e2, c2 in q.items():
+            e = (e1[0] + e2[0], e1[1] + e2[1], e1[2] + e2[2])
+            out[e] = out.get(e, 0.0) + c1 * c2
+    return out
+
+
+def _pderiv(p, d):
+    out = {}
+    for e, c in p.items():
+        if e[d] > 0:
+            f = list(e)
+            f[d] -= 1
+            out[tuple(f)] = out.get(tuple(f), 0.0) + c * e[d]
+    return out
+
+
+def _padd(p, q, s=1.0):
+    out = dict(p)
+    for e, c in q.items():
+        out[e] = out.get(e, 0.0) + s * c
+    return out
+
+
+def _peval(p, x):
+    return sum(c * x[..., 0] ** e[0] * x[..., 1] ** e[1] * x[..., 2] ** e[2] for e, c in p.items())
+
+
+def _pshift(p, c, l0):
+    """p(c + l0 X) as a polynomial in X"""
+    out = {}
+    for e, coef in p.items():
+        term = {(0, 0, 0): coef}
+        for d in range(3):
+            lin = {(0, 0, 0): c[d]}
+            unit = [0, 0, 0]
+            unit[d] = 1
+            lin[tuple(unit)] = l0
+            for _ in range(e[d]):
+                term = _pmul(term, lin)
+        out = _padd(out, term)
+    return out
+
+
+def _zone_quadrature(order, x_nodes, n=6):
+    """points [P][3] and weights J dxi [P] of one zone from its nodal map
+    (the map lies in the element space, so the nodal interpolant and its
+    gradient are exact): Gauss in zeta times a collapsed Gauss rule on the
+    reference triangle"""
+    g, gw = np.polynomial.legendre.leggauss(n)
+    s, sw = 0.5 * (g + 1), 0.5 * gw
+    A, B, Cv = P.TRI_V
+    pts, wts = [], []
+    for i in range(n):
+        for j in range(n):
+            u, v = s[i], (1 - s[i]) * s[j]
+            xy = A + u * (B - A) + v * (Cv - A)
+            for k in range(n):
+                pts.append([xy[0], xy[1], s[k] - 0.5])
+                wts.append(sw[i] * sw[j] * sw[k] * (1 - s[i]) * 2 * (S3 / 4))
+    pts, wts = np.array(pts), np.array(wts)
+    val, grad = P.basis(order, pts)
+    x = val @ x_nodes
+    jac = np.einsum("pld,lc->pcd", grad, x_nodes)
+    return x, wts * np.abs(np.linalg.det(jac))
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_divfree_reconstruction_reproduces_divergence_free_polynomials_of_degree_p_minus_1(order):
+    """B = curl A for a random vector potential A of degree p is a
+    divergence-free polynomial of degree p - 1, inside the reconstruction's
+    space: with its own zone means, Taylor coefficients about the centroid,
+    face-point normal components and face averages (by the faces' rules) as
+    inputs, the reconstruction returns it exactly at the nodes of curved zones
+    (Section IV.b: all constraints and least-squares rows are met by B).
+    The zone moments come from an independent quadrature of the nodal map."""
+    m = P.OraclePrismMesh(1, 2, r_in=1.0, r_out=1.5, order=order)
+    rng = np.random.default_rng(40 + order)
+    monos = [(a, b, c) for a in range(order + 1) for b in range(order + 1 - a) for c in range(order + 1 - a - b)]
+    Apot = [{e: rng.normal() for e in monos} for _ in range(3)]
+    Bpol = [_padd(_pderiv(Apot[2], 1), _pderiv(Apot[1], 2), -1.0),
+            _padd(_pderiv(Apot[0], 2), _pderiv(Apot[2], 0), -1.0),
+            _padd(_pderiv(Apot[1], 0), _pderiv(Apot[0], 1), -1.0)]
+    div = _padd(_padd(_pderiv(Bpol[0], 0), _pderiv(Bpol[1], 1)), _pderiv(Bpol[2], 2))
+    assert max(abs(c) for c in div.values()) < 1e-12
+    zones = np.array([0, 5, 17, 33, m.nz - 1])
+    cen, l0 = m.frames(zones)
+    x, _, _ = m.geometry(zones)
+    xq, dA = m.face_geometry(zones)
+    _, _, nt, ns = P.face_points(order)
+    te = P.taylor_indices(order)
+    nc = len(te)
+    nin, _ = P.divfree_sizes(order)
+    Q = dA.shape[1]
+    Bin = np.zeros((len(zones), nin))
+    for i in range(len(zones)):
+        xg, wg = _zone_quadrature(order, x[i])
+        X = (xg - cen[i]) / l0[i]
+        mom = {e: (wg * X[:, 0] ** e[0] * X[:, 1] ** e[1] * X[:, 2] ** e[2]).sum() / wg.sum() for e in te}
+        for comp in range(3):
+            bX = _pshift(Bpol[comp], cen[i], l0[i])
+            # B = b_0 + sum b_a X^a = (b_0 + sum b_a <X^a>) + sum b_a (X^a - <X^a>)
+            mean = bX.get((0, 0, 0), 0.0) + sum(bX.get(e, 0.0) * mom[e] for e in te)
+            Bin[i, comp * (nc + 1)] = mean
+            for a, e in enumerate(te):
+                Bin[i, comp * (nc + 1) + 1 + a] = bX.get(e, 0.0)
+        an = np.linalg.norm(dA[i], axis=1)
+        nrm = dA[i] / an[:, None]
+        Bq = np.stack([_peval(Bpol[c], xq[i]) for c in range(3)], 1)
+        bn = (Bq * nrm).sum(1)
+        Bin[i, 3 * (nc + 1):3 * (nc + 1) + Q] = bn
+        faces = [np.arange(nt), np.arange(nt, 2 * nt)] + [2 * nt + k * ns + np.arange(ns) for k in range(3)]
+        for f, q in enumerate(faces):
+            Bin[i, 3 * (nc + 1) + Q + f] = (an[q] * bn[q]).sum() / an[q].sum()
+    out = m.divfree(zones, Bin)
+    N = m.N
+    got = out[:, :3 * N].reshape(len(zones), 3, N).transpose(0, 2, 1)
+    want = np.stack([_peval(Bpol[c], x) for c in range(3)], 2)
+    scale = np.abs(want).max()
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(out[:, 3 * N:], Bin[:, [0, nc + 1, 2 * (nc + 1)]], rtol=0, atol=1e-11 * scale)
