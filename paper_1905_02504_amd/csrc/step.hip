@@ -612,9 +612,7 @@ __global__ __launch_bounds__(256) void face_bn_limit(DevGeom G, const double *__
 // with the table 10.9 ms (FP64 12.0 -> 11.8 ms).  The operands are loaded one
 // K step ahead with no load under a branch: FP64 11.8 -> 10.6 ms, FP32
 // 10.9 -> 9.9 ms (two tiles per wavefront with the same loads: 13.1 ms; at
-// fourth order three tiles hold 256 registers with a 24-byte spill; the
-// output rows split between two wavefronts per tile set, which load the same
-// B operands: 13.1 ms at three wavefronts per SIMD, 15.6 ms at two)
+// fourth order three tiles hold 256 registers with a 24-byte spill)
 // (v_mfma_f64_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in lane j + 16 (i % 4), element i / 4).
 constexpr int BMAP_TILES = 3;
