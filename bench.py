@@ -334,6 +334,7 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
     lib.close()
     torch.cuda.empty_cache()
     tf = flops * nz / (ms * 1e-3) / 1e12
+    chain_ms = ms + ms_tr + ms_ff + ms_up + ms_etr + ms_emf + ms_ct + ms_df
     return {"workload": f"prism ADER-CG predictor, order {order}, icosahedral level {level} "
                         f"({20 * 4 ** level} triangles) x {n_rad} shells = {nz} zones, uniform state + 5% noise",
             "zones": nz, "ms_per_predictor": ms, "zone_updates_per_s": nz / (ms * 1e-3),
@@ -350,7 +351,13 @@ def time_prism(level=6, n_rad=128, order=4, reps=5):
                         "flops_per_zone": df_flops, "hbm_gbs": df_bytes * nz / (ms_df * 1e-3) / 1e9,
                         "tflops": df_flops * nz / (ms_df * 1e-3) / 1e12, "map_build_s": t_maps},
             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9}}
+                         "frac": tf / PEAK_FP64_TFLOPS, "hbm_gbs": nbytes * nz / (ms * 1e-3) / 1e9},
+            # the built stages of one prism step in sequence (the WENO-AO
+            # reconstruction on triangle stencils, which would feed the
+            # predictor and the divergence-free map, is not built)
+            "chain_without_reconstruction": {
+                "ms": chain_ms, "zone_updates_per_s": nz / (chain_ms * 1e-3),
+                "stages": "predictor, face traces, face fluxes, update, edge traces, edge fields, CT, divergence-free B"}}
 
 
 def measured_peaks(reps=5):
@@ -642,7 +649,9 @@ def main():
             f"edge fields {prism['edge_emfs']['ms']:.2f} ms, "
             f"CT {prism['ct']['ms']:.2f} ms, divergence-free B {prism['divfree']['ms']:.2f} ms "
             f"({prism['divfree']['hbm_gbs']:.0f} GB/s, {prism['divfree']['tflops']:.1f} TFLOP/s; maps built in "
-            f"{prism['divfree']['map_build_s']:.1f} s)")
+            f"{prism['divfree']['map_build_s']:.1f} s); these stages in sequence "
+            f"{prism['chain_without_reconstruction']['ms']:.1f} ms = "
+            f"{prism['chain_without_reconstruction']['zone_updates_per_s'] / 1e6:.1f} M zone-updates/s (no reconstruction)")
     out = {
         "metric": "zone-updates/s per ADER step (4th order), FP64",
         "value": value,
